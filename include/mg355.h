@@ -1,0 +1,187 @@
+/*
+ * mg355.h -- C ABI of the MI355X (gfx950) geometric multigrid Poisson solver.
+ *
+ * Solves  nabla^2 phi = 4 pi G rho  (eq. poisson of Tomida & Stone, arXiv:2302.13903,
+ * Sec. 2.1) on a uniform cubic grid of n^3 cells with the 7-point cell-centred Laplacian
+ * (eq. discretized2), by full multigrid (Alg. 2) followed by V(npre, npost) correction-
+ * scheme cycles (Alg. 1) with the over-relaxed red-black Gauss-Seidel smoother
+ * (eqs. rbsor1-2), 8-cell restriction (eq. restriction), trilinear correction
+ * prolongation (eq. trilinear) and tricubic FMG prolongation (Sec. 2.3.1), the convergence
+ * test of Sec. 2.3.7 and the boundary conditions of Sec. 2.3.6 and Appendix A.
+ *
+ * Conventions shared by every entry point:
+ *   - Grid arrays are contiguous, x fastest: element (i, j, k) at ((k*n + j)*n + i);
+ *     cell (i, j, k) is centred at ((i+1/2) dx, (j+1/2) dx, (k+1/2) dx); the domain is
+ *     [0, n dx]^3.
+ *   - Face order: -x, +x, -y, +y, -z, +z.  A face array is indexed [t2][t1] over the face's
+ *     two transverse axes in increasing axis order (x faces: (y, z); y faces: (x, z);
+ *     z faces: (x, y)), t1 fastest.
+ *   - "Device" pointers are HIP device memory on the context's device; "host" pointers
+ *     are ordinary host memory.  Every device pointer is caller-owned: the library neither
+ *     frees nor retains it after the call returns.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on it; calls
+ *     that return host values (residual history, moments) synchronise that stream.
+ *   - Return value: MG_OK (0); a positive soft status (the output is valid, see below);
+ *     or a negative error (nothing valid was written; mg_last_error() explains).
+ *   - A context is not re-entrant: one host thread at a time per context.
+ */
+#ifndef MG355_H
+#define MG355_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------------------- */
+#define MG_OK 0
+#define MG_NOT_CONVERGED 1   /* max_cycles reached above tol; phi holds the last iterate */
+#define MG_STALLED 2         /* residual fell < 10 % per cycle twice in a row (round-off floor) */
+#define MG_ERR_INVALID_ARG -1
+#define MG_ERR_UNSUPPORTED -2
+#define MG_ERR_OOM -3
+#define MG_ERR_DEVICE -4
+#define MG_ERR_NONFINITE -5  /* NaN/Inf in rho or in fixed face values */
+
+/* ---- boundary kinds (Sec. 2.3.6, Appendix A) -------------------------------------- */
+#define MG_BC_PERIODIC 0       /* ghost = opposite active cell; must be set on both faces of an axis */
+#define MG_BC_ZERO_GRADIENT 1  /* ghost = adjacent active cell */
+#define MG_BC_FIXED 2          /* ghost = 2 b - adjacent cell: the value on the face equals b */
+#define MG_BC_MULTIPOLE 3      /* FIXED with b from the l <= lmax multipole expansion of rho */
+
+#define MG_MODE_FMG 0          /* full multigrid start (Alg. 2), then V-cycles */
+#define MG_MODE_MGI 1          /* V-cycles from the initial guess held in phi */
+
+#define MG_PREC_FP64 0         /* every operator in FP64 */
+#define MG_PREC_MIXED 1        /* FP32 smoothing / restriction / prolongation inside FP64
+                                  defect-correction (FP64 residual and phi update) */
+
+#define MG_LAYOUT_DENSE 0      /* one n^3 array per level */
+#define MG_LAYOUT_BLOCKS 1     /* MeshBlock decomposition: block_n^3 blocks + root grid */
+
+typedef struct mg_ctx mg_ctx;
+
+/* Solver parameters.  mg_default_params() fills the defaults given in brackets. */
+typedef struct {
+  int n;            /* cells per side: a power of two, 2 <= n <= 2048                   [-] */
+  double dx;        /* cell width, > 0                                                  [1/n] */
+  double four_pi_g; /* 4 pi G; the source is f = four_pi_g * rho                        [4 pi] */
+  int mode;         /* MG_MODE_FMG or MG_MODE_MGI                                       [FMG] */
+  int npre, npost;  /* smoothing sweeps before / after the coarse correction, 0..4     [2, 2] */
+  double omega;     /* over-relaxation factor of the smoother, 0 < omega < 2            [1.15] */
+  double tol;       /* stop when RMS(defect)/RMS(f) <= tol (finest level)               [1e-10] */
+  int max_cycles;   /* V-cycle cap after the FMG sweep, 0..1000                         [50] */
+  int fixed_cycles; /* > 0: run exactly this many V-cycles and ignore tol               [0] */
+  int precision;    /* MG_PREC_FP64 or MG_PREC_MIXED                                    [FP64] */
+  int layout;       /* MG_LAYOUT_DENSE or MG_LAYOUT_BLOCKS                              [DENSE] */
+  int block_n;      /* MeshBlock size for MG_LAYOUT_BLOCKS (power of two, < n)         [16] */
+} mg_params;
+
+/* Boundary description of a solve. */
+typedef struct {
+  int kind[6];               /* MG_BC_* per face */
+  const double *fixed_b[6];  /* device, n*n face-centre values per FIXED face; NULL = 0 */
+  int lmax;                  /* multipole order 0..4 (Appendix A)                        */
+  int use_origin;            /* 0: expansion about the centre of mass; 1: about origin[] */
+  double origin[3];
+} mg_bc;
+
+/* Boundary description of one level for the operator entry points: face kinds and
+ * extended face arrays of (nl+2)^2 values (device, indexed [t2+1][t1+1], t = -1..nl;
+ * the outer ring gives the values used for edge and corner ghosts); NULL = 0.
+ * MG_BC_MULTIPOLE faces are treated as MG_BC_FIXED with the given arrays. */
+typedef struct {
+  int kind[6];
+  const double *b[6];
+} mg_level_bc;
+
+void mg_default_params(mg_params *p);
+
+/* Create a context on HIP device `device` (workspace grows on demand and is reused). */
+int mg_ctx_create(mg_ctx **ctx, int device);
+void mg_ctx_destroy(mg_ctx *ctx);
+const char *mg_last_error(const mg_ctx *ctx);
+
+/* Device bytes a solve with these parameters keeps resident in its context (hierarchy,
+ * boundary arrays, reduction scratch); 0 for invalid parameters.  Used for admission. */
+size_t mg_footprint_bytes(const mg_params *p);
+
+/* Full solve (Sec. 2.3.7, Alg. 1, Alg. 2).
+ *   rho   device, n^3 FP64, read only.
+ *   phi   device, n^3 FP64; output (and the initial guess when mode = MG_MODE_MGI).
+ *         When no face is FIXED or MULTIPOLE the mean of f and of phi is removed.
+ *   hist  host, capacity max(max_cycles, fixed_cycles) + 1: the relative residual after
+ *         the FMG sweep (or of the initial guess) and after each V-cycle.
+ *   n_hist host: number of entries written.
+ * Synchronises `stream` once per cycle (the stopping test runs on the host). */
+int mg_solve(mg_ctx *ctx, const mg_params *p, const mg_bc *bc, const double *rho, double *phi,
+             double *hist, int *n_hist, void *stream);
+
+/* Timing of the last mg_solve on this context, from HIP events on its stream:
+ * *fmg_ms = set-up + FMG sweep; cycle_ms[c] = wall time of V-cycle c (including its
+ * residual norm); *n = number of cycles (up to cap). */
+int mg_last_timing(const mg_ctx *ctx, double *setup_ms, double *fmg_ms, double *cycle_ms,
+                   int cap, int *n);
+
+/* Kernel-level timing of the finest-level smoothing kernels during the last mg_solve:
+ * number of launches and their summed duration (HIP events around each launch).
+ * Enabled by mg_set_kernel_timing(ctx, 1); off by default. */
+int mg_set_kernel_timing(mg_ctx *ctx, int on);
+int mg_kernel_timing(const mg_ctx *ctx, int *launches, double *total_ms, double *bytes_per_launch,
+                     char *name, int name_cap);
+
+/* Multipole set-up (Appendix A): centre of mass (unless use_origin) and the 25 moments
+ * Q_lm, l <= lmax, of rho (device, n^3) with cell volume dx^3.  origin_out (host, 3) and
+ * q_out (host, 25, index l*l + l + m) receive the results. */
+int mg_multipole_moments(mg_ctx *ctx, int n, double dx, const double *rho, int lmax, int use_origin,
+                         const double *origin, double *origin_out, double *q_out, void *stream);
+
+/* ---- operator entry points (each operator alone, for parity checks) ---------------- */
+
+/* One colour (0 = red, (i+j+k) even; 1 = black) of the RB-SOR smoother, eqs. rbsor1-2:
+ * u <- u + omega ((sum of 6 neighbours - h^2 f)/6 - u) on cells of that colour, with
+ * ghosts from `bc` evaluated from u before the colour.  u, f: device, n^3 FP64. */
+int mg_op_half_sweep(mg_ctx *ctx, int n, double h, double omega, int colour, const mg_level_bc *bc,
+                     double *u, const double *f, void *stream);
+
+/* `sweeps` full red-then-black smoothing sweeps in the bandwidth-optimised fused kernel
+ * used by the solver on large levels; identical in result to 2*sweeps half-sweeps. */
+int mg_op_smooth(mg_ctx *ctx, int n, double h, double omega, int sweeps, const mg_level_bc *bc,
+                 double *u, const double *f, void *stream);
+
+/* d = f - L_h u (eq. defect).  u, f, d: device, n^3 FP64. */
+int mg_op_defect(mg_ctx *ctx, int n, double h, const mg_level_bc *bc, const double *u,
+                 const double *f, double *d, void *stream);
+
+/* uc = 8-cell mean of uf (eq. restriction).  uf: device (2nc)^3, uc: device nc^3. */
+int mg_op_restrict(mg_ctx *ctx, int nc, const double *uf, double *uc, void *stream);
+
+/* uf += trilinear prolongation of uc (eq. trilinear; Alg. 1 steps 5-6), ghosts of uc from bc. */
+int mg_op_prolong_add(mg_ctx *ctx, int nc, const mg_level_bc *bc, const double *uc, double *uf,
+                      void *stream);
+
+/* uf = tricubic FMG prolongation of uc (Sec. 2.3.1; Alg. 2 step 3), ghosts of uc from bc. */
+int mg_op_prolong_fmg(mg_ctx *ctx, int nc, const mg_level_bc *bc, const double *uc, double *uf,
+                      void *stream);
+
+/* Single-cell coarsest solve (Sec. 2.3.2): u (device, 1) from f (device, 1), cell width h. */
+int mg_op_coarsest(mg_ctx *ctx, double h, const mg_level_bc *bc, double *u, const double *f,
+                   void *stream);
+
+/* Fused down step of a V-cycle level (Alg. 1 steps 1-3): `npre` smoothing sweeps of u,
+ * then fc = restriction of the defect f - L u; uc = 0.  u, f: device n^3; fc, uc: (n/2)^3. */
+int mg_op_down(mg_ctx *ctx, int n, double h, double omega, int npre, const mg_level_bc *bc,
+               double *u, const double *f, double *fc, double *uc, void *stream);
+
+/* Fused up step of a V-cycle level (Alg. 1 steps 5-7): u += trilinear(uc) with uc's ghosts
+ * from bc_coarse, then `npost` smoothing sweeps with bc. */
+int mg_op_up(mg_ctx *ctx, int n, double h, double omega, int npost, const mg_level_bc *bc,
+             const mg_level_bc *bc_coarse, double *u, const double *f, const double *uc,
+             void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MG355_H */

@@ -1,0 +1,260 @@
+"""MI355X-native geometric multigrid Poisson solver (Tomida & Stone, arXiv:2302.13903).
+
+Thin Python binding of the C ABI in ``include/mg355.h``: every step of a solve runs in the
+HIP kernels of ``libmg355.so``; this module only marshals torch device tensors (memory and
+streams) into the C calls, under the same names.  There is no CPU fallback: without the
+built library every entry point raises.
+
+Quick use::
+
+    import torch, paper_2302_13903_amd as mg
+    phi, hist, status = mg.solve(rho_cuda_f64, dx=1/256, bc="periodic", tol=1e-10)
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+from . import _abi
+from ._abi import (MG_BC_FIXED, MG_BC_MULTIPOLE, MG_BC_PERIODIC, MG_BC_ZERO_GRADIENT, MG_LAYOUT_BLOCKS,
+                   MG_LAYOUT_DENSE, MG_MODE_FMG, MG_MODE_MGI, MG_PREC_FP64, MG_PREC_MIXED, MG_NOT_CONVERGED,
+                   MG_OK, MG_STALLED, MgError, STATUS_NAMES)
+
+__all__ = ["Context", "solve", "mg_solve", "mg_footprint_bytes", "params", "boundary", "level_bc",
+           "mg_op_half_sweep", "mg_op_smooth", "mg_op_defect", "mg_op_restrict", "mg_op_prolong_add",
+           "mg_op_prolong_fmg", "mg_op_coarsest", "mg_op_down", "mg_op_up", "mg_multipole_moments",
+           "MgError", "KINDS"]
+
+KINDS = {"periodic": MG_BC_PERIODIC, "zero_gradient": MG_BC_ZERO_GRADIENT, "fixed": MG_BC_FIXED,
+         "multipole": MG_BC_MULTIPOLE}
+
+
+def _kinds(k) -> list:
+    if isinstance(k, (str, int)):
+        k = [k] * 6
+    out = [KINDS[x] if isinstance(x, str) else int(x) for x in k]
+    if len(out) != 6:
+        raise ValueError("six face kinds expected (-x,+x,-y,+y,-z,+z)")
+    return out
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("device tensors must be contiguous CUDA/HIP tensors")
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+class Context:
+    """Owns an ``mg_ctx`` (pooled device workspace, reused across solves)."""
+
+    def __init__(self, device: int = 0):
+        self._lib = _abi.lib()
+        h = ctypes.c_void_p()
+        st = self._lib.mg_ctx_create(ctypes.byref(h), int(device))
+        if st != MG_OK:
+            raise MgError(f"mg_ctx_create failed: {STATUS_NAMES.get(st, st)}")
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.mg_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self) -> str:
+        return self._lib.mg_last_error(self.handle).decode()
+
+    def check(self, st: int, what: str) -> int:
+        if st < 0:
+            raise MgError(f"{what}: {STATUS_NAMES.get(st, st)}: {self.last_error()}")
+        return st
+
+    def last_timing(self, cap: int = 1024):
+        setup, fmg = ctypes.c_double(), ctypes.c_double()
+        cyc = (ctypes.c_double * cap)()
+        n = ctypes.c_int()
+        self._lib.mg_last_timing(self.handle, ctypes.byref(setup), ctypes.byref(fmg), cyc, cap, ctypes.byref(n))
+        return setup.value, fmg.value, [cyc[i] for i in range(min(n.value, cap))]
+
+    def set_kernel_timing(self, on: bool):
+        self._lib.mg_set_kernel_timing(self.handle, 1 if on else 0)
+
+    def kernel_timing(self):
+        n, ms, by = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
+        name = ctypes.create_string_buffer(128)
+        self._lib.mg_kernel_timing(self.handle, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by), name, 128)
+        return {"launches": n.value, "total_ms": ms.value, "bytes_per_launch": by.value, "name": name.value.decode()}
+
+
+_default_ctx = {}
+
+
+def default_context(device: int = 0) -> Context:
+    if device not in _default_ctx:
+        _default_ctx[device] = Context(device)
+    return _default_ctx[device]
+
+
+def params(n: int, dx: float, **kw) -> _abi.MgParams:
+    p = _abi.MgParams()
+    _abi.lib().mg_default_params(ctypes.byref(p))
+    p.n = int(n)
+    p.dx = float(dx)
+    for k, v in kw.items():
+        if k == "mode" and isinstance(v, str):
+            v = {"fmg": MG_MODE_FMG, "mgi": MG_MODE_MGI}[v]
+        if k == "precision" and isinstance(v, str):
+            v = {"fp64": MG_PREC_FP64, "mixed": MG_PREC_MIXED}[v]
+        if k == "layout" and isinstance(v, str):
+            v = {"dense": MG_LAYOUT_DENSE, "blocks": MG_LAYOUT_BLOCKS}[v]
+        setattr(p, k, v)
+    return p
+
+
+def boundary(kinds, fixed_b: Optional[Sequence] = None, lmax: int = 4, origin=None) -> _abi.MgBC:
+    b = _abi.MgBC()
+    for f, k in enumerate(_kinds(kinds)):
+        b.kind[f] = k
+        b.fixed_b[f] = _ptr(fixed_b[f]) if fixed_b is not None and fixed_b[f] is not None else None
+    b.lmax = int(lmax)
+    b.use_origin = 0 if origin is None else 1
+    if origin is not None:
+        for a in range(3):
+            b.origin[a] = float(origin[a])
+    return b
+
+
+def level_bc(kinds, bext: Optional[Sequence] = None) -> _abi.MgLevelBC:
+    b = _abi.MgLevelBC()
+    for f, k in enumerate(_kinds(kinds)):
+        b.kind[f] = k
+        b.b[f] = _ptr(bext[f]) if bext is not None and bext[f] is not None else None
+    return b
+
+
+def mg_footprint_bytes(p: _abi.MgParams) -> int:
+    return int(_abi.lib().mg_footprint_bytes(ctypes.byref(p)))
+
+
+def mg_solve(ctx: Context, p: _abi.MgParams, bc: _abi.MgBC, rho, phi, stream=None):
+    """Raw ``mg_solve``: returns (status, hist list)."""
+    cap = max(p.max_cycles, p.fixed_cycles) + 1
+    hist = (ctypes.c_double * cap)()
+    nh = ctypes.c_int(0)
+    st = ctx._lib.mg_solve(ctx.handle, ctypes.byref(p), ctypes.byref(bc), _ptr(rho), _ptr(phi), hist,
+                           ctypes.byref(nh), _stream(stream))
+    ctx.check(st, "mg_solve")
+    return st, [hist[i] for i in range(nh.value)]
+
+
+def solve(rho, dx: float, bc="periodic", fixed_b=None, lmax: int = 4, origin=None, tol: float = 1e-10,
+          max_cycles: int = 50, fixed_cycles: int = 0, npre: int = 2, npost: int = 2, omega: float = 1.15,
+          mode: str = "fmg", precision: str = "fp64", layout: str = "dense", block_n: int = 16, phi=None,
+          four_pi_g: float = 4.0 * math.pi, ctx: Optional[Context] = None, stream=None):
+    """Solve nabla^2 phi = 4 pi G rho on the device.  ``rho``: contiguous float64 (n, n, n) tensor
+    on the GPU.  Returns ``(phi, hist, status)``."""
+    import torch
+    if rho.dtype != torch.float64 or rho.dim() != 3:
+        raise ValueError("rho must be a float64 (n, n, n) tensor")
+    n = rho.shape[0]
+    ctx = ctx or default_context(rho.device.index or 0)
+    p = params(n, dx, tol=tol, max_cycles=max_cycles, fixed_cycles=fixed_cycles, npre=npre, npost=npost,
+               omega=omega, mode=mode, precision=precision, layout=layout, block_n=block_n, four_pi_g=four_pi_g)
+    b = boundary(bc, fixed_b, lmax, origin)
+    if phi is None:
+        phi = torch.zeros_like(rho)
+    st, hist = mg_solve(ctx, p, b, rho, phi, stream)
+    return phi, hist, st
+
+
+# ------------------------------------------------------------------ operator entry points
+
+def _ctx(ctx):
+    return ctx or default_context()
+
+
+def mg_op_half_sweep(u, f, h, omega, colour, kinds, bext=None, ctx=None, stream=None):
+    c = _ctx(ctx)
+    return c.check(c._lib.mg_op_half_sweep(c.handle, u.shape[0], float(h), float(omega), int(colour),
+                                           ctypes.byref(level_bc(kinds, bext)), _ptr(u), _ptr(f), _stream(stream)),
+                   "mg_op_half_sweep")
+
+
+def mg_op_smooth(u, f, h, omega, sweeps, kinds, bext=None, ctx=None, stream=None):
+    c = _ctx(ctx)
+    return c.check(c._lib.mg_op_smooth(c.handle, u.shape[0], float(h), float(omega), int(sweeps),
+                                       ctypes.byref(level_bc(kinds, bext)), _ptr(u), _ptr(f), _stream(stream)),
+                   "mg_op_smooth")
+
+
+def mg_op_defect(u, f, d, h, kinds, bext=None, ctx=None, stream=None):
+    c = _ctx(ctx)
+    return c.check(c._lib.mg_op_defect(c.handle, u.shape[0], float(h), ctypes.byref(level_bc(kinds, bext)),
+                                       _ptr(u), _ptr(f), _ptr(d), _stream(stream)), "mg_op_defect")
+
+
+def mg_op_restrict(uf, uc, ctx=None, stream=None):
+    c = _ctx(ctx)
+    return c.check(c._lib.mg_op_restrict(c.handle, uc.shape[0], _ptr(uf), _ptr(uc), _stream(stream)),
+                   "mg_op_restrict")
+
+
+def mg_op_prolong_add(uc, uf, kinds, bext=None, ctx=None, stream=None):
+    c = _ctx(ctx)
+    return c.check(c._lib.mg_op_prolong_add(c.handle, uc.shape[0], ctypes.byref(level_bc(kinds, bext)), _ptr(uc),
+                                            _ptr(uf), _stream(stream)), "mg_op_prolong_add")
+
+
+def mg_op_prolong_fmg(uc, uf, kinds, bext=None, ctx=None, stream=None):
+    c = _ctx(ctx)
+    return c.check(c._lib.mg_op_prolong_fmg(c.handle, uc.shape[0], ctypes.byref(level_bc(kinds, bext)), _ptr(uc),
+                                            _ptr(uf), _stream(stream)), "mg_op_prolong_fmg")
+
+
+def mg_op_coarsest(u, f, h, kinds, bext=None, ctx=None, stream=None):
+    c = _ctx(ctx)
+    return c.check(c._lib.mg_op_coarsest(c.handle, float(h), ctypes.byref(level_bc(kinds, bext)), _ptr(u), _ptr(f),
+                                         _stream(stream)), "mg_op_coarsest")
+
+
+def mg_op_down(u, f, fc, uc, h, omega, npre, kinds, bext=None, ctx=None, stream=None):
+    c = _ctx(ctx)
+    return c.check(c._lib.mg_op_down(c.handle, u.shape[0], float(h), float(omega), int(npre),
+                                     ctypes.byref(level_bc(kinds, bext)), _ptr(u), _ptr(f), _ptr(fc), _ptr(uc),
+                                     _stream(stream)), "mg_op_down")
+
+
+def mg_op_up(u, f, uc, h, omega, npost, kinds, bext=None, kinds_coarse=None, ctx=None, stream=None):
+    c = _ctx(ctx)
+    kc = kinds_coarse if kinds_coarse is not None else kinds
+    return c.check(c._lib.mg_op_up(c.handle, u.shape[0], float(h), float(omega), int(npost),
+                                   ctypes.byref(level_bc(kinds, bext)), ctypes.byref(level_bc(kc, None)), _ptr(u),
+                                   _ptr(f), _ptr(uc), _stream(stream)), "mg_op_up")
+
+
+def mg_multipole_moments(rho, dx, lmax=4, origin=None, ctx=None, stream=None):
+    c = _ctx(ctx)
+    o_in = (ctypes.c_double * 3)(*(origin if origin is not None else (0.0, 0.0, 0.0)))
+    o_out = (ctypes.c_double * 3)()
+    q = (ctypes.c_double * 25)()
+    c.check(c._lib.mg_multipole_moments(c.handle, rho.shape[0], float(dx), _ptr(rho), int(lmax),
+                                        0 if origin is None else 1, o_in, o_out, q, _stream(stream)),
+            "mg_multipole_moments")
+    return list(o_out), list(q)

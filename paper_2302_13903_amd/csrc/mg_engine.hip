@@ -1,0 +1,704 @@
+// mg_engine.hip -- host-side engine and C ABI of the multigrid solver (see include/mg355.h).
+//
+// A context owns one pooled device workspace (grown on demand, reused across solves) holding
+// the level hierarchy, the per-level boundary face arrays and the reduction scratch.  A solve
+// enqueues everything on the caller's stream; the host reads one scalar per cycle for the
+// stopping test of Sec. 2.3.7.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mg355.h"
+#include "mg_fused.h"
+#include "mg_launch.h"
+
+using namespace mg;
+
+struct mg_ctx {
+  int device = 0;
+  std::string err;
+  size_t lds_per_block = 65536;
+  int tail64_top = 3;          // highest FP64 level held by the LDS coarse tail
+  char* ws = nullptr;
+  size_t ws_cap = 0;
+  double* part = nullptr;      // reduction partials
+  double* scal = nullptr;      // device scalars: [0] sum rho, [1] sum f^2, [2] defect^2, [3] sum phi,
+                               // [8..13] sum b^2 per face, [16..47] multipole scratch
+  double* hscal = nullptr;     // pinned host mirror of scal
+  // timing of the last solve
+  hipEvent_t ev0 = nullptr, ev_setup = nullptr, ev_fmg = nullptr;
+  std::vector<hipEvent_t> ev_cycle;
+  double setup_ms = 0, fmg_ms = 0;
+  std::vector<double> cycle_ms;
+  // kernel timing of the finest-level smoothing kernel
+  int ktiming = 0;
+  std::vector<hipEvent_t> kev;
+  int klaunches = 0;
+  double kms = 0, kbytes = 0;
+  std::string kname;
+};
+
+namespace {
+
+constexpr int kScal = 64;
+constexpr int kMpoleOff = 16;
+
+int fail(mg_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIP_CHECK(ctx, call)                                                                     \
+  do {                                                                                           \
+    hipError_t e_ = (call);                                                                      \
+    if (e_ != hipSuccess)                                                                        \
+      return fail((ctx), MG_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));       \
+  } while (0)
+
+bool is_pow2(long long n) { return n >= 1 && (n & (n - 1)) == 0; }
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t cells(int l) { return (size_t)1 << (3 * l); }
+size_t face_sz(int l) { return (size_t)((1 << l) + 2) * (size_t)((1 << l) + 2); }
+
+// Layout of the workspace for one (n, precision).
+struct Layout {
+  int L = 0;
+  bool mixed = false;
+  size_t f64L = 0;             // FP64 finest source
+  size_t u64[16], f64[16];     // FP64 levels 0..L-1 (FP64 mode)
+  size_t u32[16], f32[16];     // FP32 levels 0..L (mixed mode)
+  size_t faces[16];            // 6 extended face arrays per level
+  size_t total = 0;
+};
+
+Layout make_layout(int n, int precision) {
+  Layout y;
+  y.L = ilog2(n);
+  y.mixed = precision == MG_PREC_MIXED;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  y.f64L = take(cells(y.L) * 8);
+  for (int l = 0; l <= y.L; ++l) {
+    y.u64[l] = y.f64[l] = y.u32[l] = y.f32[l] = 0;
+    if (!y.mixed && l < y.L) {
+      y.u64[l] = take(cells(l) * 8);
+      y.f64[l] = take(cells(l) * 8);
+    }
+    if (y.mixed) {
+      y.u32[l] = take(cells(l) * 4);
+      y.f32[l] = take(cells(l) * 4);
+    }
+    y.faces[l] = take(6 * face_sz(l) * 8);
+  }
+  y.total = off;
+  return y;
+}
+
+int validate(mg_ctx* c, const mg_params* p, const mg_bc* bc) {
+  if (!p || !bc) return fail(c, MG_ERR_INVALID_ARG, "null params or bc");
+  if (!is_pow2(p->n) || p->n < 2 || p->n > 2048) return fail(c, MG_ERR_INVALID_ARG, "n must be a power of two in [2, 2048]");
+  if (!(p->dx > 0) || !std::isfinite(p->dx)) return fail(c, MG_ERR_INVALID_ARG, "dx must be positive");
+  if (p->npre < 0 || p->npre > 4 || p->npost < 0 || p->npost > 4) return fail(c, MG_ERR_INVALID_ARG, "npre/npost in 0..4");
+  if (!(p->omega > 0 && p->omega < 2)) return fail(c, MG_ERR_INVALID_ARG, "omega in (0, 2)");
+  if (p->max_cycles < 0 || p->max_cycles > 1000 || p->fixed_cycles < 0 || p->fixed_cycles > 1000)
+    return fail(c, MG_ERR_INVALID_ARG, "cycle counts in 0..1000");
+  if (p->mode != MG_MODE_FMG && p->mode != MG_MODE_MGI) return fail(c, MG_ERR_INVALID_ARG, "bad mode");
+  if (p->precision != MG_PREC_FP64 && p->precision != MG_PREC_MIXED) return fail(c, MG_ERR_INVALID_ARG, "bad precision");
+  if (p->layout != MG_LAYOUT_DENSE && p->layout != MG_LAYOUT_BLOCKS) return fail(c, MG_ERR_INVALID_ARG, "bad layout");
+  if (p->layout == MG_LAYOUT_BLOCKS && (!is_pow2(p->block_n) || p->block_n < 2 || p->block_n >= p->n))
+    return fail(c, MG_ERR_INVALID_ARG, "block_n must be a power of two below n");
+  for (int f = 0; f < 6; ++f)
+    if (bc->kind[f] < MG_BC_PERIODIC || bc->kind[f] > MG_BC_MULTIPOLE) return fail(c, MG_ERR_INVALID_ARG, "bad face kind");
+  for (int a = 0; a < 3; ++a)
+    if ((bc->kind[2 * a] == MG_BC_PERIODIC) != (bc->kind[2 * a + 1] == MG_BC_PERIODIC))
+      return fail(c, MG_ERR_INVALID_ARG, "periodic faces must be paired per axis");
+  if (bc->lmax < 0 || bc->lmax > 4) return fail(c, MG_ERR_INVALID_ARG, "lmax in 0..4");
+  return MG_OK;
+}
+
+LevelBC to_level_bc(const mg_level_bc* b) {
+  LevelBC r;
+  for (int f = 0; f < 6; ++f) {
+    r.kind[f] = b ? (b->kind[f] == MG_BC_MULTIPOLE ? MG_BC_FIXED : b->kind[f]) : MG_BC_PERIODIC;
+    r.b[f] = b ? b->b[f] : nullptr;
+  }
+  return r;
+}
+
+int ensure_ws(mg_ctx* c, size_t bytes) {
+  if (bytes <= c->ws_cap) return MG_OK;
+  if (c->ws) {
+    HIP_CHECK(c, hipDeviceSynchronize());
+    HIP_CHECK(c, hipFree(c->ws));
+    c->ws = nullptr;
+    c->ws_cap = 0;
+  }
+  hipError_t e = hipMalloc((void**)&c->ws, bytes);
+  if (e != hipSuccess) {
+    c->ws = nullptr;
+    (void)hipGetLastError();
+    return fail(c, MG_ERR_OOM, "workspace allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  c->ws_cap = bytes;
+  return MG_OK;
+}
+
+// Per-solve plan: typed level pointers and boundary descriptions.
+template <typename T>
+struct Hier {
+  int L = 0, T_top = 0;
+  T* u[16];
+  T* f[16];
+  double h[16];
+  LevelBC phys[16];
+  LevelBC hom;
+  int npre = 2, npost = 2;
+  double omega = 1.15;
+};
+
+struct Solver {
+  mg_ctx* c;
+  hipStream_t s;
+  int fused_ok = 1;
+
+  // smoothing sweeps on one level; the finest FP64 level may use the fused kernel
+  template <typename T>
+  void smooth(Hier<T>& H, int l, int sweeps, const LevelBC& bc, bool timed) {
+    if (sweeps <= 0) return;
+    const int n = 1 << l;
+    if (fused_ok && fused_supported<T>(n)) {
+      if (timed && c->ktiming) kernel_begin();
+      launch_fused_smooth<T>(H.u[l], H.f[l], n, H.h[l], H.omega, sweeps, bc, s);
+      if (timed && c->ktiming) kernel_end(fused_smooth_name<T>(n, sweeps), fused_smooth_bytes<T>(n, sweeps));
+      return;
+    }
+    for (int it = 0; it < sweeps; ++it)
+      for (int colour = 0; colour < 2; ++colour) {
+        if (timed && c->ktiming) kernel_begin();
+        launch_half_sweep<T>(H.u[l], H.f[l], n, H.h[l], H.omega, colour, bc, s);
+        // algorithmic bytes: all of u read, f read and u written on one colour
+        if (timed && c->ktiming) kernel_end("k_half_sweep", (double)cells(l) * 2.0 * sizeof(T));
+      }
+  }
+
+  void kernel_begin() {
+    hipEvent_t e;
+    (void)hipEventCreate(&e);
+    (void)hipEventRecord(e, s);
+    c->kev.push_back(e);
+  }
+  void kernel_end(const std::string& name, double bytes) {
+    hipEvent_t e;
+    (void)hipEventCreate(&e);
+    (void)hipEventRecord(e, s);
+    c->kev.push_back(e);
+    c->kname = name;
+    c->kbytes = bytes;
+  }
+
+  template <typename T>
+  void tail(Hier<T>& H, int mode, const LevelBC& bc_top) {
+    TailArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.top = H.T_top;
+    a.mode = mode;
+    a.npre = H.npre;
+    a.npost = H.npost;
+    a.omega = H.omega;
+    for (int l = 0; l <= H.T_top; ++l) {
+      a.h[l] = H.h[l];
+      a.phys[l] = H.phys[l];
+      a.fg[l] = H.f[l];
+    }
+    a.bc_top = bc_top;
+    a.hom = H.hom;
+    a.ug = H.u[H.T_top];
+    launch_tail<T>(a, s);
+  }
+
+  // Alg. 1 on level l (l >= T_top).  At the tail level the whole remaining recursion runs in
+  // one LDS-resident workgroup.
+  template <typename T>
+  void vcycle(Hier<T>& H, int l, const LevelBC& bc, bool top_call) {
+    if (l == H.T_top) {
+      tail(H, top_call ? TAIL_LOAD_U : 0, bc);
+      return;
+    }
+    const int n = 1 << l;
+    const bool timed = top_call && l == H.L;
+    smooth(H, l, H.npre, bc, timed);
+    launch_defect_restrict<T>(H.u[l], H.f[l], H.f[l - 1], H.u[l - 1], n, H.h[l], bc, s);
+    vcycle(H, l - 1, H.hom, false);
+    launch_prolong<T>(H.u[l - 1], H.u[l], n / 2, H.hom, 0, s);
+    smooth(H, l, H.npost, bc, timed);
+  }
+
+  // Alg. 2: FMG over all levels with each level's physical description.
+  template <typename T>
+  void fmg(Hier<T>& H) {
+    tail(H, TAIL_FMG, H.phys[H.T_top]);
+    for (int l = H.T_top + 1; l <= H.L; ++l) {
+      launch_prolong<T>(H.u[l - 1], H.u[l], 1 << (l - 1), H.phys[l - 1], 1, s);
+      vcycle(H, l, H.phys[l], false);
+    }
+  }
+};
+
+double elapsed(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0;
+  return ms;
+}
+
+}  // namespace
+
+// ===================================================================================== ABI
+
+extern "C" {
+
+void mg_default_params(mg_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->n = 0;
+  p->dx = 0;
+  p->four_pi_g = 4.0 * M_PI;
+  p->mode = MG_MODE_FMG;
+  p->npre = 2;
+  p->npost = 2;
+  p->omega = 1.15;
+  p->tol = 1e-10;
+  p->max_cycles = 50;
+  p->fixed_cycles = 0;
+  p->precision = MG_PREC_FP64;
+  p->layout = MG_LAYOUT_DENSE;
+  p->block_n = 16;
+}
+
+int mg_ctx_create(mg_ctx** out, int device) {
+  if (!out) return MG_ERR_INVALID_ARG;
+  *out = nullptr;
+  mg_ctx* c = new mg_ctx();
+  c->device = device;
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) {
+    delete c;
+    return MG_ERR_DEVICE;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->lds_per_block = prop.sharedMemPerBlock;
+  if (hipMalloc((void**)&c->part, sizeof(double) * kMaxPartials * 32) != hipSuccess ||
+      hipMalloc((void**)&c->scal, sizeof(double) * kScal) != hipSuccess ||
+      hipHostMalloc((void**)&c->hscal, sizeof(double) * kScal, hipHostMallocDefault) != hipSuccess ||
+      hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev_setup) != hipSuccess ||
+      hipEventCreate(&c->ev_fmg) != hipSuccess) {
+    mg_ctx_destroy(c);
+    return MG_ERR_DEVICE;
+  }
+  // the FP64 coarse tail keeps levels <= 16^3 in LDS when the device allows it per block
+  c->tail64_top = tail_prepare(c->lds_per_block);
+  *out = c;
+  return MG_OK;
+}
+
+void mg_ctx_destroy(mg_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  if (c->ws) (void)hipFree(c->ws);
+  if (c->part) (void)hipFree(c->part);
+  if (c->scal) (void)hipFree(c->scal);
+  if (c->hscal) (void)hipHostFree(c->hscal);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev_setup) (void)hipEventDestroy(c->ev_setup);
+  if (c->ev_fmg) (void)hipEventDestroy(c->ev_fmg);
+  for (auto e : c->ev_cycle) (void)hipEventDestroy(e);
+  for (auto e : c->kev) (void)hipEventDestroy(e);
+  delete c;
+}
+
+const char* mg_last_error(const mg_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+size_t mg_footprint_bytes(const mg_params* p) {
+  if (!p || !is_pow2(p->n) || p->n < 2 || p->n > 2048) return 0;
+  return make_layout(p->n, p->precision).total + sizeof(double) * (kMaxPartials * 32 + kScal);
+}
+
+int mg_set_kernel_timing(mg_ctx* c, int on) {
+  if (!c) return MG_ERR_INVALID_ARG;
+  c->ktiming = on ? 1 : 0;
+  return MG_OK;
+}
+
+int mg_kernel_timing(const mg_ctx* c, int* launches, double* total_ms, double* bytes_per_launch, char* name,
+                     int name_cap) {
+  if (!c) return MG_ERR_INVALID_ARG;
+  if (launches) *launches = c->klaunches;
+  if (total_ms) *total_ms = c->kms;
+  if (bytes_per_launch) *bytes_per_launch = c->kbytes;
+  if (name && name_cap > 0) {
+    std::strncpy(name, c->kname.c_str(), name_cap - 1);
+    name[name_cap - 1] = 0;
+  }
+  return MG_OK;
+}
+
+int mg_last_timing(const mg_ctx* c, double* setup_ms, double* fmg_ms, double* cycle_ms, int cap, int* n) {
+  if (!c) return MG_ERR_INVALID_ARG;
+  if (setup_ms) *setup_ms = c->setup_ms;
+  if (fmg_ms) *fmg_ms = c->fmg_ms;
+  int m = (int)c->cycle_ms.size();
+  if (cycle_ms)
+    for (int i = 0; i < std::min(m, cap); ++i) cycle_ms[i] = c->cycle_ms[i];
+  if (n) *n = m;
+  return MG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Build the per-level physical boundary descriptions in the workspace (Sec. 2.3.6, App. A).
+int setup_faces(mg_ctx* c, const Layout& y, const mg_params* p, const mg_bc* bc, const double* rho, hipStream_t s,
+                LevelBC* phys, LevelBC* hom) {
+  const int L = y.L;
+  bool any_mp = false;
+  for (int f = 0; f < 6; ++f) any_mp |= bc->kind[f] == MG_BC_MULTIPOLE;
+  double* mps = c->scal + kMpoleOff;
+  if (any_mp) launch_multipole_moments(rho, p->n, p->dx, bc->lmax, bc->use_origin, bc->origin, c->part, mps, s);
+  const double G = p->four_pi_g / (4.0 * M_PI);
+  for (int l = L; l >= 0; --l) {
+    double* fb = reinterpret_cast<double*>(c->ws + y.faces[l]);
+    double* mp_out[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    for (int f = 0; f < 6; ++f) {
+      const int k = bc->kind[f];
+      double* e = fb + (size_t)f * face_sz(l);
+      phys[l].kind[f] = k == MG_BC_MULTIPOLE ? MG_BC_FIXED : k;
+      phys[l].b[f] = nullptr;
+      if (k == MG_BC_FIXED) {
+        if (l == L) launch_face_extend(bc->fixed_b[f], e, 1 << l, s);
+        else launch_face_restrict(reinterpret_cast<double*>(c->ws + y.faces[l + 1]) + (size_t)f * face_sz(l + 1), e,
+                                  1 << l, s);
+        phys[l].b[f] = e;
+      } else if (k == MG_BC_MULTIPOLE) {
+        mp_out[f] = e;
+        phys[l].b[f] = e;
+      }
+    }
+    if (any_mp) launch_multipole_faces(mps, bc->lmax, G, 1 << l, p->dx * (double)(1 << (L - l)), p->n * p->dx, mp_out, s);
+  }
+  for (int f = 0; f < 6; ++f) {
+    const int k = bc->kind[f];
+    hom->kind[f] = (k == MG_BC_PERIODIC || k == MG_BC_ZERO_GRADIENT) ? k : MG_BC_FIXED;
+    hom->b[f] = nullptr;
+  }
+  // non-finite fixed values are reported with the rho check
+  for (int f = 0; f < 6; ++f) {
+    if (bc->kind[f] == MG_BC_FIXED && bc->fixed_b[f])
+      launch_sum(bc->fixed_b[f], (size_t)p->n * p->n, 2, c->part, c->scal + 8 + f, s);
+  }
+  return MG_OK;
+}
+
+}  // namespace
+
+extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const double* rho, double* phi, double* hist,
+                        int* n_hist, void* stream) {
+  if (!c) return MG_ERR_INVALID_ARG;
+  if (n_hist) *n_hist = 0;
+  int st = validate(c, p, bc);
+  if (st != MG_OK) return st;
+  if (!rho || !phi || !hist || !n_hist) return fail(c, MG_ERR_INVALID_ARG, "null rho/phi/hist/n_hist");
+  if (p->layout == MG_LAYOUT_BLOCKS) return fail(c, MG_ERR_UNSUPPORTED, "block layout is not available in this build");
+  HIP_CHECK(c, hipSetDevice(c->device));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const Layout y = make_layout(p->n, p->precision);
+  st = ensure_ws(c, y.total);
+  if (st != MG_OK) return st;
+  for (auto e : c->kev) (void)hipEventDestroy(e);
+  c->kev.clear();
+  c->klaunches = 0;
+  c->kms = 0;
+
+  const int L = y.L;
+  const size_t n3 = cells(L);
+  bool gauge_free = true;
+  for (int f = 0; f < 6; ++f)
+    if (bc->kind[f] == MG_BC_FIXED || bc->kind[f] == MG_BC_MULTIPOLE) gauge_free = false;
+  const bool mixed = y.mixed;
+  const int tail_max = mixed ? 4 : c->tail64_top;
+
+  HIP_CHECK(c, hipEventRecord(c->ev0, s));
+  HIP_CHECK(c, hipMemsetAsync(c->scal, 0, sizeof(double) * kScal, s));
+
+  // ---- source (eq. poisson, f = 4 pi G rho; mean removed when gauge-free, Sec. 2.3.6)
+  double* f64L = reinterpret_cast<double*>(c->ws + y.f64L);
+  float* f32L = mixed ? reinterpret_cast<float*>(c->ws + y.f32[L]) : nullptr;
+  double shift = 0.0;
+  launch_sum(rho, n3, 0, c->part, c->scal + 0, s);
+  if (gauge_free) {
+    // the shift needs the mean on the host; this is the one extra synchronisation of set-up
+    HIP_CHECK(c, hipMemcpyAsync(c->hscal, c->scal, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(c, hipStreamSynchronize(s));
+    shift = -p->four_pi_g * (c->hscal[0] / (double)n3);
+  }
+  launch_source(rho, f64L, f32L, n3, p->four_pi_g, shift, s);
+  launch_sum(f64L, n3, 1, c->part, c->scal + 1, s);
+
+  LevelBC phys[16], hom;
+  setup_faces(c, y, p, bc, rho, s, phys, &hom);
+
+  Solver S{c, s};
+  Hier<double> H64;
+  Hier<float> H32;
+  auto fill_common = [&](auto& H, int tail_top) {
+    H.L = L;
+    H.T_top = std::min(L, tail_top);
+    H.npre = p->npre;
+    H.npost = p->npost;
+    H.omega = p->omega;
+    H.hom = hom;
+    for (int l = 0; l <= L; ++l) {
+      H.h[l] = p->dx * (double)(1LL << (L - l));
+      H.phys[l] = phys[l];
+    }
+  };
+  if (!mixed) {
+    fill_common(H64, tail_max);
+    for (int l = 0; l < L; ++l) {
+      H64.u[l] = reinterpret_cast<double*>(c->ws + y.u64[l]);
+      H64.f[l] = reinterpret_cast<double*>(c->ws + y.f64[l]);
+    }
+    H64.u[L] = phi;
+    H64.f[L] = f64L;
+    for (int l = L; l >= 1; --l) launch_restrict<double, double>(H64.f[l], H64.f[l - 1], 1 << (l - 1), s);
+  } else {
+    fill_common(H32, tail_max);
+    for (int l = 0; l <= L; ++l) {
+      H32.u[l] = reinterpret_cast<float*>(c->ws + y.u32[l]);
+      H32.f[l] = reinterpret_cast<float*>(c->ws + y.f32[l]);
+    }
+    for (int l = L; l >= 1; --l) launch_restrict<float, float>(H32.f[l], H32.f[l - 1], 1 << (l - 1), s);
+  }
+  HIP_CHECK(c, hipEventRecord(c->ev_setup, s));
+
+  // ---- FMG sweep (Alg. 2) or the caller's initial guess
+  if (p->mode == MG_MODE_FMG) {
+    if (!mixed) {
+      S.fmg(H64);
+    } else {
+      S.fmg(H32);
+      launch_f32_to_f64(H32.u[L], phi, n3, s);
+    }
+  }
+  // ---- residual of the start (Sec. 2.3.7); mixed: also its FP32 copy as the inner RHS
+  launch_defect_norm(phi, f64L, mixed ? H32.f[L] : nullptr, p->n, p->dx, phys[L], c->part, c->scal + 2, s);
+  HIP_CHECK(c, hipEventRecord(c->ev_fmg, s));
+  HIP_CHECK(c, hipMemcpyAsync(c->hscal, c->scal, sizeof(double) * 16, hipMemcpyDeviceToHost, s));
+  HIP_CHECK(c, hipStreamSynchronize(s));
+  bool finite = std::isfinite(c->hscal[0]) && std::isfinite(c->hscal[1]);
+  for (int f = 0; f < 6; ++f) finite = finite && c->hscal[8 + f] == 0.0;
+  if (!finite) return fail(c, MG_ERR_NONFINITE, "non-finite values in rho or fixed boundary values");
+  const double rms_f = std::sqrt(c->hscal[1] / (double)n3);
+  auto rel = [&](double sumsq) {
+    const double rd = std::sqrt(sumsq / (double)n3);
+    return rms_f > 0 ? rd / rms_f : rd;
+  };
+  double r = rel(c->hscal[2]);
+  int nh = 0;
+  hist[nh++] = r;
+
+  // ---- V-cycles until the stopping test (Sec. 2.3.7)
+  const int ncyc = p->fixed_cycles > 0 ? p->fixed_cycles : p->max_cycles;
+  while ((int)c->ev_cycle.size() < ncyc) {
+    hipEvent_t e;
+    HIP_CHECK(c, hipEventCreate(&e));
+    c->ev_cycle.push_back(e);
+  }
+  int status = p->fixed_cycles > 0 ? MG_OK : MG_NOT_CONVERGED;
+  int slow = 0, done_cycles = 0;
+  if (p->fixed_cycles > 0 || r > p->tol) {
+    for (int cyc = 0; cyc < ncyc; ++cyc) {
+      if (!mixed) {
+        S.vcycle(H64, L, phys[L], true);
+        launch_defect_norm(phi, f64L, nullptr, p->n, p->dx, phys[L], c->part, c->scal + 2, s);
+      } else {
+        // defect correction: e32 solves L e = r32 from zero with homogeneous conditions
+        if (L == H32.T_top) {
+          S.tail(H32, 0, hom);
+        } else {
+          HIP_CHECK(c, hipMemsetAsync(H32.u[L], 0, n3 * sizeof(float), s));
+          S.vcycle(H32, L, hom, true);
+        }
+        launch_add_f32(phi, H32.u[L], n3, s);
+        launch_defect_norm(phi, f64L, H32.f[L], p->n, p->dx, phys[L], c->part, c->scal + 2, s);
+      }
+      HIP_CHECK(c, hipEventRecord(c->ev_cycle[cyc], s));
+      HIP_CHECK(c, hipMemcpyAsync(c->hscal + 2, c->scal + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_CHECK(c, hipStreamSynchronize(s));
+      const double rn = rel(c->hscal[2]);
+      hist[nh++] = rn;
+      ++done_cycles;
+      if (p->fixed_cycles > 0) { r = rn; continue; }
+      slow = rn > 0.9 * r ? slow + 1 : 0;
+      r = rn;
+      if (r <= p->tol) { status = MG_OK; break; }
+      if (slow >= 2) { status = MG_STALLED; break; }
+    }
+  } else {
+    status = MG_OK;
+  }
+  *n_hist = nh;
+
+  // ---- gauge (Sec. 2.3.6): zero mean potential when no face fixes the zero point
+  if (gauge_free) {
+    launch_sum(phi, n3, 0, c->part, c->scal + 3, s);
+    launch_sub_mean(phi, n3, c->scal + 3, s);
+  }
+  HIP_CHECK(c, hipStreamSynchronize(s));
+  HIP_CHECK(c, hipGetLastError());
+
+  // ---- timing
+  c->setup_ms = elapsed(c->ev0, c->ev_setup);
+  c->fmg_ms = elapsed(c->ev_setup, c->ev_fmg);
+  c->cycle_ms.clear();
+  hipEvent_t prev = c->ev_fmg;
+  for (int cyc = 0; cyc < done_cycles; ++cyc) {
+    c->cycle_ms.push_back(elapsed(prev, c->ev_cycle[cyc]));
+    prev = c->ev_cycle[cyc];
+  }
+  if (c->ktiming) {
+    for (size_t q = 0; q + 1 < c->kev.size(); q += 2) c->kms += elapsed(c->kev[q], c->kev[q + 1]);
+    c->klaunches = (int)(c->kev.size() / 2);
+  }
+  return status;
+}
+
+// ============================================================== operator entry points
+
+namespace {
+int op_prologue(mg_ctx* c, int n) {
+  if (!c) return MG_ERR_INVALID_ARG;
+  if (!is_pow2(n) || n > 2048) return fail(c, MG_ERR_INVALID_ARG, "n must be a power of two <= 2048");
+  HIP_CHECK(c, hipSetDevice(c->device));
+  return MG_OK;
+}
+int op_epilogue(mg_ctx* c) {
+  HIP_CHECK(c, hipGetLastError());
+  return MG_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int mg_op_half_sweep(mg_ctx* c, int n, double h, double omega, int colour, const mg_level_bc* bc, double* u,
+                     const double* f, void* stream) {
+  int st = op_prologue(c, n);
+  if (st) return st;
+  if (n < 2 || (colour != 0 && colour != 1)) return fail(c, MG_ERR_INVALID_ARG, "n >= 2, colour 0 or 1");
+  launch_half_sweep<double>(u, f, n, h, omega, colour, to_level_bc(bc), reinterpret_cast<hipStream_t>(stream));
+  return op_epilogue(c);
+}
+
+int mg_op_smooth(mg_ctx* c, int n, double h, double omega, int sweeps, const mg_level_bc* bc, double* u,
+                 const double* f, void* stream) {
+  int st = op_prologue(c, n);
+  if (st) return st;
+  if (n < 2 || sweeps < 0 || sweeps > 4) return fail(c, MG_ERR_INVALID_ARG, "n >= 2, sweeps 0..4");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const LevelBC b = to_level_bc(bc);
+  if (fused_supported<double>(n)) {
+    launch_fused_smooth<double>(u, f, n, h, omega, sweeps, b, s);
+  } else {
+    for (int it = 0; it < sweeps; ++it)
+      for (int colour = 0; colour < 2; ++colour) launch_half_sweep<double>(u, f, n, h, omega, colour, b, s);
+  }
+  return op_epilogue(c);
+}
+
+int mg_op_defect(mg_ctx* c, int n, double h, const mg_level_bc* bc, const double* u, const double* f, double* d,
+                 void* stream) {
+  int st = op_prologue(c, n);
+  if (st) return st;
+  launch_defect<double>(u, f, d, n, h, to_level_bc(bc), reinterpret_cast<hipStream_t>(stream));
+  return op_epilogue(c);
+}
+
+int mg_op_restrict(mg_ctx* c, int nc, const double* uf, double* uc, void* stream) {
+  int st = op_prologue(c, nc);
+  if (st) return st;
+  launch_restrict<double, double>(uf, uc, nc, reinterpret_cast<hipStream_t>(stream));
+  return op_epilogue(c);
+}
+
+int mg_op_prolong_add(mg_ctx* c, int nc, const mg_level_bc* bc, const double* uc, double* uf, void* stream) {
+  int st = op_prologue(c, nc);
+  if (st) return st;
+  launch_prolong<double>(uc, uf, nc, to_level_bc(bc), 0, reinterpret_cast<hipStream_t>(stream));
+  return op_epilogue(c);
+}
+
+int mg_op_prolong_fmg(mg_ctx* c, int nc, const mg_level_bc* bc, const double* uc, double* uf, void* stream) {
+  int st = op_prologue(c, nc);
+  if (st) return st;
+  launch_prolong<double>(uc, uf, nc, to_level_bc(bc), 1, reinterpret_cast<hipStream_t>(stream));
+  return op_epilogue(c);
+}
+
+int mg_op_coarsest(mg_ctx* c, double h, const mg_level_bc* bc, double* u, const double* f, void* stream) {
+  int st = op_prologue(c, 1);
+  if (st) return st;
+  launch_coarsest<double>(u, f, h, to_level_bc(bc), reinterpret_cast<hipStream_t>(stream));
+  return op_epilogue(c);
+}
+
+int mg_op_down(mg_ctx* c, int n, double h, double omega, int npre, const mg_level_bc* bc, double* u, const double* f,
+               double* fc, double* uc, void* stream) {
+  int st = op_prologue(c, n);
+  if (st) return st;
+  if (n < 2 || npre < 0 || npre > 4) return fail(c, MG_ERR_INVALID_ARG, "n >= 2, npre 0..4");
+  st = mg_op_smooth(c, n, h, omega, npre, bc, u, f, stream);
+  if (st) return st;
+  launch_defect_restrict<double>(u, f, fc, uc, n, h, to_level_bc(bc), reinterpret_cast<hipStream_t>(stream));
+  return op_epilogue(c);
+}
+
+int mg_op_up(mg_ctx* c, int n, double h, double omega, int npost, const mg_level_bc* bc, const mg_level_bc* bc_coarse,
+             double* u, const double* f, const double* uc, void* stream) {
+  int st = op_prologue(c, n);
+  if (st) return st;
+  if (n < 2 || npost < 0 || npost > 4) return fail(c, MG_ERR_INVALID_ARG, "n >= 2, npost 0..4");
+  launch_prolong<double>(uc, u, n / 2, to_level_bc(bc_coarse), 0, reinterpret_cast<hipStream_t>(stream));
+  return mg_op_smooth(c, n, h, omega, npost, bc, u, f, stream);
+}
+
+int mg_multipole_moments(mg_ctx* c, int n, double dx, const double* rho, int lmax, int use_origin, const double* origin,
+                         double* origin_out, double* q_out, void* stream) {
+  int st = op_prologue(c, n);
+  if (st) return st;
+  if (lmax < 0 || lmax > 4) return fail(c, MG_ERR_INVALID_ARG, "lmax in 0..4");
+  if (use_origin && !origin) return fail(c, MG_ERR_INVALID_ARG, "origin required");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  double* mps = c->scal + kMpoleOff;
+  HIP_CHECK(c, hipMemsetAsync(c->scal, 0, sizeof(double) * kScal, s));
+  launch_multipole_moments(rho, n, dx, lmax, use_origin, origin, c->part, mps, s);
+  HIP_CHECK(c, hipMemcpyAsync(c->hscal, c->scal, sizeof(double) * kScal, hipMemcpyDeviceToHost, s));
+  HIP_CHECK(c, hipStreamSynchronize(s));
+  if (origin_out)
+    for (int a = 0; a < 3; ++a) origin_out[a] = c->hscal[kMpoleOff + 4 + a];
+  if (q_out)
+    for (int q = 0; q < 25; ++q) q_out[q] = c->hscal[kMpoleOff + 7 + q];
+  return op_epilogue(c);
+}
+
+}  // extern "C"

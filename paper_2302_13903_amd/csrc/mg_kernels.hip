@@ -1,0 +1,565 @@
+// mg_kernels.hip -- per-operator HIP kernels (gfx950) of the multigrid solver, in FP64 and FP32.
+//
+// These are the plain one-operator-per-launch kernels used on every level below the fused
+// large-level kernels, by the operator entry points, and as the building blocks of the
+// FP32 inner cycle of the mixed-precision path.  Each kernel is a streaming loop with
+// 64-bit indices and on-the-fly boundary ghosts (see mg_common.h).
+#include "mg_common.h"
+#include "mg_launch.h"
+
+namespace mg {
+
+constexpr int kBlock = 256;
+
+static inline unsigned grid_for(size_t work, int per_thread = 1) {
+  size_t threads = (work + per_thread - 1) / per_thread;
+  size_t g = (threads + kBlock - 1) / kBlock;
+  return (unsigned)(g == 0 ? 1 : g);
+}
+
+// ------------------------------------------------------------------ smoothing (eqs. rbsor1-2)
+
+// One colour of the over-relaxed red-black Gauss-Seidel update.  Work item t covers the
+// x-pair (2p, 2p+1) of row (j, k); exactly one of the two has the requested colour.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_half_sweep(T* __restrict__ u, const T* __restrict__ f, int n,
+                                                        int L, T h2, T omega, int colour, LevelBC bc) {
+  const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  const size_t pairs = (size_t)1 << (3 * L - 1);
+  if (t >= pairs) return;
+  const int p = (int)(t & (size_t)((n >> 1) - 1));
+  const int j = (int)((t >> (L - 1)) & (size_t)(n - 1));
+  const int k = (int)(t >> (2 * L - 1));
+  const int i = 2 * p + ((j + k + colour) & 1);
+  const size_t c = cidx(L, i, j, k);
+  const T uc = u[c];
+  const T nb = neighbour_sum(u, n, L, i, j, k, c, uc, bc);
+  u[c] = uc + omega * ((nb - h2 * f[c]) / (T)6 - uc);
+}
+
+template <typename T>
+void launch_half_sweep(T* u, const T* f, int n, double h, double omega, int colour, const LevelBC& bc,
+                       hipStream_t s) {
+  const int L = ilog2(n);
+  const size_t pairs = (size_t)1 << (3 * L - 1);
+  hipLaunchKernelGGL(k_half_sweep<T>, dim3(grid_for(pairs)), dim3(kBlock), 0, s, u, f, n, L, (T)(h * h),
+                     (T)omega, colour, bc);
+}
+
+// ------------------------------------------------------------------ defect (eq. defect)
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_defect(const T* __restrict__ u, const T* __restrict__ f,
+                                                    T* __restrict__ d, int n, int L, T ih2, LevelBC bc) {
+  const size_t c = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= ((size_t)1 << (3 * L))) return;
+  const int i = (int)(c & (size_t)(n - 1));
+  const int j = (int)((c >> L) & (size_t)(n - 1));
+  const int k = (int)(c >> (2 * L));
+  const T uc = u[c];
+  const T nb = neighbour_sum(u, n, L, i, j, k, c, uc, bc);
+  d[c] = f[c] - (nb - (T)6 * uc) * ih2;
+}
+
+template <typename T>
+void launch_defect(const T* u, const T* f, T* d, int n, double h, const LevelBC& bc, hipStream_t s) {
+  const int L = ilog2(n);
+  hipLaunchKernelGGL(k_defect<T>, dim3(grid_for((size_t)1 << (3 * L))), dim3(kBlock), 0, s, u, f, d, n, L,
+                     (T)(1.0 / (h * h)), bc);
+}
+
+// Defect on the fine level restricted straight to the coarse level (Alg. 1 steps 2-3): one
+// work item per coarse cell computes its 8 children's defects and their mean; it also clears
+// the coarse correction (the recursion starts from zero, Alg. 1 step 4).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_defect_restrict(const T* __restrict__ u, const T* __restrict__ f,
+                                                             T* __restrict__ fc, T* __restrict__ uc0, int n,
+                                                             int L, T ih2, LevelBC bc) {
+  const int nc = n >> 1, Lc = L - 1;
+  const size_t C = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (C >= ((size_t)1 << (3 * Lc))) return;
+  const int I = (int)(C & (size_t)(nc - 1));
+  const int J = (int)((C >> Lc) & (size_t)(nc - 1));
+  const int K = (int)(C >> (2 * Lc));
+  T s = (T)0;
+#pragma unroll
+  for (int c3 = 0; c3 < 2; ++c3)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int i = 2 * I + a, j = 2 * J + b, k = 2 * K + c3;
+        const size_t c = cidx(L, i, j, k);
+        const T ucv = u[c];
+        const T nb = neighbour_sum(u, n, L, i, j, k, c, ucv, bc);
+        s += f[c] - (nb - (T)6 * ucv) * ih2;
+      }
+  fc[C] = s * (T)0.125;
+  if (uc0) uc0[C] = (T)0;
+}
+
+template <typename T>
+void launch_defect_restrict(const T* u, const T* f, T* fc, T* uc0, int n, double h, const LevelBC& bc,
+                            hipStream_t s) {
+  const int L = ilog2(n);
+  hipLaunchKernelGGL(k_defect_restrict<T>, dim3(grid_for((size_t)1 << (3 * (L - 1)))), dim3(kBlock), 0, s, u,
+                     f, fc, uc0, n, L, (T)(1.0 / (h * h)), bc);
+}
+
+// ------------------------------------------------------------------ restriction (eq. restriction)
+
+template <typename Tin, typename Tout>
+__global__ void __launch_bounds__(kBlock) k_restrict(const Tin* __restrict__ uf, Tout* __restrict__ uc, int Lc) {
+  const int nc = 1 << Lc, L = Lc + 1;
+  const size_t C = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (C >= ((size_t)1 << (3 * Lc))) return;
+  const int I = (int)(C & (size_t)(nc - 1));
+  const int J = (int)((C >> Lc) & (size_t)(nc - 1));
+  const int K = (int)(C >> (2 * Lc));
+  Tin s = (Tin)0;
+#pragma unroll
+  for (int c3 = 0; c3 < 2; ++c3)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) s += uf[cidx(L, 2 * I + a, 2 * J + b, 2 * K + c3)];
+  uc[C] = (Tout)(s * (Tin)0.125);
+}
+
+template <typename Tin, typename Tout>
+void launch_restrict(const Tin* uf, Tout* uc, int nc, hipStream_t s) {
+  const int Lc = ilog2(nc);
+  hipLaunchKernelGGL((k_restrict<Tin, Tout>), dim3(grid_for((size_t)1 << (3 * Lc))), dim3(kBlock), 0, s, uf,
+                     uc, Lc);
+}
+
+// ------------------------------------------------------------------ prolongation (Sec. 2.3.1)
+
+// cubic = 0: uf += trilinear(uc) (eq. trilinear, Alg. 1 steps 5-6);
+// cubic = 1: uf  = tricubic(uc)  (FMG prolongation, Alg. 2 step 3).
+// One work item per fine cell; the 3x3x3 coarse neighbourhood uses ghost_any() near faces.
+template <typename T, int CUBIC>
+__global__ void __launch_bounds__(kBlock) k_prolong(const T* __restrict__ uc, T* __restrict__ uf, int Lc,
+                                                     LevelBC bcc) {
+  const int nc = 1 << Lc, L = Lc + 1, n = 2 * nc;
+  const size_t c = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= ((size_t)1 << (3 * L))) return;
+  const int i = (int)(c & (size_t)(n - 1));
+  const int j = (int)((c >> L) & (size_t)(n - 1));
+  const int k = (int)(c >> (2 * L));
+  const int I = i >> 1, J = j >> 1, K = k >> 1;
+  T wx[3], wy[3], wz[3];
+  if (CUBIC) { cub_w(i & 1, wx); cub_w(j & 1, wy); cub_w(k & 1, wz); }
+  else { lin_w(i & 1, wx); lin_w(j & 1, wy); lin_w(k & 1, wz); }
+  const bool inner = I > 0 && I < nc - 1 && J > 0 && J < nc - 1 && K > 0 && K < nc - 1;
+  T s = (T)0;
+#pragma unroll
+  for (int cz = -1; cz <= 1; ++cz) {
+    if (!CUBIC && wz[cz + 1] == (T)0) continue;
+#pragma unroll
+    for (int by = -1; by <= 1; ++by) {
+      if (!CUBIC && wy[by + 1] == (T)0) continue;
+#pragma unroll
+      for (int ax = -1; ax <= 1; ++ax) {
+        if (!CUBIC && wx[ax + 1] == (T)0) continue;
+        const T w = wx[ax + 1] * wy[by + 1] * wz[cz + 1];
+        const T v = inner ? uc[cidx(Lc, I + ax, J + by, K + cz)] : ghost_any(uc, nc, Lc, I + ax, J + by, K + cz, bcc);
+        s += w * v;
+      }
+    }
+  }
+  if (CUBIC) uf[c] = s;
+  else uf[c] += s;
+}
+
+template <typename T>
+void launch_prolong(const T* uc, T* uf, int nc, const LevelBC& bcc, int cubic, hipStream_t s) {
+  const int Lc = ilog2(nc);
+  const dim3 g(grid_for((size_t)1 << (3 * (Lc + 1))));
+  if (cubic) hipLaunchKernelGGL((k_prolong<T, 1>), g, dim3(kBlock), 0, s, uc, uf, Lc, bcc);
+  else hipLaunchKernelGGL((k_prolong<T, 0>), g, dim3(kBlock), 0, s, uc, uf, Lc, bcc);
+}
+
+// ------------------------------------------------------------------ coarsest (Sec. 2.3.2)
+
+// Single-cell solve: every ghost is alpha*u + beta (periodic / zero-gradient: alpha = 1,
+// fixed: alpha = -1, beta = 2b), so u = (sum beta - h^2 f) / (6 - sum alpha); 0 if sum alpha = 6.
+template <typename T>
+__device__ __forceinline__ T coarsest_value(T f, T h2, const LevelBC& bc) {
+  T sa = (T)0, sb = (T)0;
+#pragma unroll
+  for (int face = 0; face < 6; ++face) {
+    if (bc_has_value(bc.kind[face])) { sa -= (T)1; sb += (T)(2.0 * face_b(bc, face, 1, 0, 0)); }
+    else sa += (T)1;
+  }
+  return sa == (T)6 ? (T)0 : (sb - h2 * f) / ((T)6 - sa);
+}
+
+template <typename T>
+__global__ void k_coarsest(T* u, const T* f, T h2, LevelBC bc) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) u[0] = coarsest_value(f[0], h2, bc);
+}
+
+template <typename T>
+void launch_coarsest(T* u, const T* f, double h, const LevelBC& bc, hipStream_t s) {
+  hipLaunchKernelGGL(k_coarsest<T>, dim3(1), dim3(64), 0, s, u, f, (T)(h * h), bc);
+}
+
+// ------------------------------------------------------------------ coarse tail (levels <= 2^TL)
+
+// All levels 0..T (T <= 4, at most 16^3 cells) of one hierarchy in LDS, one workgroup.
+// mode bits: TAIL_FMG runs Alg. 2 on levels 0..T with the physical description of each level
+// and writes u_T; otherwise one V-cycle (Alg. 1) at level T with bc_top (u_T loaded from
+// global when TAIL_LOAD_U, else started from zero) and homogeneous descriptions below.
+constexpr int kTailThreads = 512;
+
+template <typename T>
+struct TailLDS {
+  T* u[5];
+  T* f[5];
+};
+
+template <typename T>
+__device__ __forceinline__ T lds_nb(const T* u, int n, int L, int i, int j, int k, T uc, const LevelBC& bc) {
+  const size_t c = cidx(L, i, j, k);
+  return neighbour_sum(u, n, L, i, j, k, c, uc, bc);
+}
+
+template <typename T>
+__device__ void tail_smooth(T* u, const T* f, int L, T h2, T omega, const LevelBC& bc) {
+  const int n = 1 << L, n3 = 1 << (3 * L);
+  for (int colour = 0; colour < 2; ++colour) {
+    for (int c = threadIdx.x; c < n3; c += blockDim.x) {
+      const int i = c & (n - 1), j = (c >> L) & (n - 1), k = c >> (2 * L);
+      if (((i + j + k) & 1) != colour) continue;
+      const T uc = u[c];
+      const T nb = lds_nb(u, n, L, i, j, k, uc, bc);
+      u[c] = uc + omega * ((nb - h2 * f[c]) / (T)6 - uc);
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__device__ void tail_defect_restrict(const T* u, const T* f, T* fc, T* uc0, int L, T ih2, const LevelBC& bc) {
+  const int n = 1 << L, Lc = L - 1, nc = n >> 1, nc3 = 1 << (3 * Lc);
+  for (int C = threadIdx.x; C < nc3; C += blockDim.x) {
+    const int I = C & (nc - 1), J = (C >> Lc) & (nc - 1), K = C >> (2 * Lc);
+    T s = (T)0;
+    for (int c3 = 0; c3 < 2; ++c3)
+      for (int b = 0; b < 2; ++b)
+        for (int a = 0; a < 2; ++a) {
+          const int i = 2 * I + a, j = 2 * J + b, k = 2 * K + c3;
+          const int c = (int)cidx(L, i, j, k);
+          const T ucv = u[c];
+          s += f[c] - (lds_nb(u, n, L, i, j, k, ucv, bc) - (T)6 * ucv) * ih2;
+        }
+    fc[C] = s * (T)0.125;
+    uc0[C] = (T)0;
+  }
+  __syncthreads();
+}
+
+template <typename T, int CUBIC>
+__device__ void tail_prolong(const T* uc, T* uf, int L, const LevelBC& bcc) {
+  const int n = 1 << L, n3 = 1 << (3 * L), Lc = L - 1, nc = n >> 1;
+  for (int c = threadIdx.x; c < n3; c += blockDim.x) {
+    const int i = c & (n - 1), j = (c >> L) & (n - 1), k = c >> (2 * L);
+    const int I = i >> 1, J = j >> 1, K = k >> 1;
+    T wx[3], wy[3], wz[3];
+    if (CUBIC) { cub_w(i & 1, wx); cub_w(j & 1, wy); cub_w(k & 1, wz); }
+    else { lin_w(i & 1, wx); lin_w(j & 1, wy); lin_w(k & 1, wz); }
+    T s = (T)0;
+    for (int cz = -1; cz <= 1; ++cz)
+      for (int by = -1; by <= 1; ++by)
+        for (int ax = -1; ax <= 1; ++ax) {
+          const T w = wx[ax + 1] * wy[by + 1] * wz[cz + 1];
+          if (w == (T)0) continue;
+          s += w * ghost_any(uc, nc, Lc, I + ax, J + by, K + cz, bcc);
+        }
+    if (CUBIC) uf[c] = s;
+    else uf[c] += s;
+  }
+  __syncthreads();
+}
+
+// V-cycle from level top down to 0 and back, with bc_top on level `top` and `hom` below.
+template <typename T>
+__device__ void tail_vcycle(TailLDS<T>& s, int top, const TailArgs& a, const LevelBC& bc_top) {
+  const T omega = (T)a.omega;
+  for (int l = top; l >= 1; --l) {
+    const LevelBC& bc = l == top ? bc_top : a.hom;
+    const T h2 = (T)(a.h[l] * a.h[l]);
+    for (int it = 0; it < a.npre; ++it) tail_smooth(s.u[l], s.f[l], l, h2, omega, bc);
+    tail_defect_restrict(s.u[l], s.f[l], s.f[l - 1], s.u[l - 1], l, (T)(1.0 / (a.h[l] * a.h[l])), bc);
+  }
+  if (threadIdx.x == 0) s.u[0][0] = coarsest_value(s.f[0][0], (T)(a.h[0] * a.h[0]), top == 0 ? bc_top : a.hom);
+  __syncthreads();
+  for (int l = 1; l <= top; ++l) {
+    const LevelBC& bc = l == top ? bc_top : a.hom;
+    const T h2 = (T)(a.h[l] * a.h[l]);
+    tail_prolong<T, 0>(s.u[l - 1], s.u[l], l, a.hom);
+    for (int it = 0; it < a.npost; ++it) tail_smooth(s.u[l], s.f[l], l, h2, omega, bc);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kTailThreads) k_tail(TailArgs a) {
+  const T* const* fg = reinterpret_cast<const T* const*>(a.fg);
+  T* ug = reinterpret_cast<T*>(a.ug);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* base = reinterpret_cast<T*>(smem_raw);
+  TailLDS<T> s;
+  int off = 0;
+  for (int l = 0; l <= a.top; ++l) {
+    const int n3 = 1 << (3 * l);
+    s.u[l] = base + off;
+    s.f[l] = base + off + a.total;
+    off += n3;
+  }
+  const int top = a.top;
+  const int ntop = 1 << (3 * top);
+  if (a.mode & TAIL_FMG) {
+    for (int l = 0; l <= top; ++l) {
+      const int n3 = 1 << (3 * l);
+      for (int c = threadIdx.x; c < n3; c += blockDim.x) s.f[l][c] = fg[l][c];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) s.u[0][0] = coarsest_value(s.f[0][0], (T)(a.h[0] * a.h[0]), a.phys[0]);
+    __syncthreads();
+    for (int l = 1; l <= top; ++l) {
+      tail_prolong<T, 1>(s.u[l - 1], s.u[l], l, a.phys[l - 1]);
+      // The V-cycle on level l overwrites the source of level l-1 and below with restricted
+      // defects; FMG has finished with them (it proceeds upwards).
+      tail_vcycle(s, l, a, a.phys[l]);
+    }
+  } else {
+    for (int c = threadIdx.x; c < ntop; c += blockDim.x) {
+      s.f[top][c] = fg[top][c];
+      s.u[top][c] = (a.mode & TAIL_LOAD_U) ? ug[c] : (T)0;
+    }
+    __syncthreads();
+    tail_vcycle(s, top, a, a.bc_top);
+  }
+  for (int c = threadIdx.x; c < ntop; c += blockDim.x) ug[c] = s.u[top][c];
+}
+
+template <typename T>
+void launch_tail(const TailArgs& a, hipStream_t s) {
+  size_t total = 0;
+  for (int l = 0; l <= a.top; ++l) total += (size_t)1 << (3 * l);
+  TailArgs b = a;
+  b.total = (int)total;
+  const size_t lds = 2 * total * sizeof(T);
+  hipLaunchKernelGGL(k_tail<T>, dim3(1), dim3(kTailThreads), lds, s, b);
+}
+
+int tail_prepare(size_t lds_per_block) {
+  const size_t need64 = tail_lds_bytes(4, sizeof(double));
+  const size_t need32 = tail_lds_bytes(4, sizeof(float));
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tail<float>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)need32);
+  if (lds_per_block < need64) return 3;
+  if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tail<double>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)need64) != hipSuccess) {
+    (void)hipGetLastError();
+    return 3;
+  }
+  return 4;
+}
+
+size_t tail_lds_bytes(int top, size_t elem) {
+  size_t total = 0;
+  for (int l = 0; l <= top; ++l) total += (size_t)1 << (3 * l);
+  return 2 * total * elem;
+}
+
+// ------------------------------------------------------------------ elementwise / set-up
+
+// f = a * rho + c (the source 4 pi G rho, mean-shifted when gauge-free), in FP64, plus the
+// FP32 copy when f32 != nullptr.
+__global__ void __launch_bounds__(kBlock) k_source(const double* __restrict__ rho, double* __restrict__ f,
+                                                    float* __restrict__ f32, size_t n3, double a, double c) {
+  const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n3) return;
+  const double v = a * rho[t] + c;
+  f[t] = v;
+  if (f32) f32[t] = (float)v;
+}
+
+void launch_source(const double* rho, double* f, float* f32, size_t n3, double a, double c, hipStream_t s) {
+  hipLaunchKernelGGL(k_source, dim3(grid_for(n3)), dim3(kBlock), 0, s, rho, f, f32, n3, a, c);
+}
+
+// u += shift (gauge fix, Sec. 2.3.6)
+__global__ void __launch_bounds__(kBlock) k_shift(double* __restrict__ u, size_t n3, const double* __restrict__ sum,
+                                                   double scale) {
+  const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n3) return;
+  u[t] -= sum[0] * scale;
+}
+
+void launch_sub_mean(double* u, size_t n3, const double* sum_dev, hipStream_t s) {
+  hipLaunchKernelGGL(k_shift, dim3(grid_for(n3)), dim3(kBlock), 0, s, u, n3, sum_dev, 1.0 / (double)n3);
+}
+
+template <typename Ta, typename Tb>
+__global__ void __launch_bounds__(kBlock) k_copy_convert(const Ta* __restrict__ a, Tb* __restrict__ b, size_t n3) {
+  const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t < n3) b[t] = (Tb)a[t];
+}
+
+void launch_f32_to_f64(const float* a, double* b, size_t n3, hipStream_t s) {
+  hipLaunchKernelGGL((k_copy_convert<float, double>), dim3(grid_for(n3)), dim3(kBlock), 0, s, a, b, n3);
+}
+
+// phi64 += e32 (mixed precision correction, defect equation eq. defecteq)
+__global__ void __launch_bounds__(kBlock) k_add_f32(double* __restrict__ phi, const float* __restrict__ e, size_t n3) {
+  const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t < n3) phi[t] += (double)e[t];
+}
+
+void launch_add_f32(double* phi, const float* e, size_t n3, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_f32, dim3(grid_for(n3)), dim3(kBlock), 0, s, phi, e, n3);
+}
+
+// ------------------------------------------------------------------ reductions
+
+// Deterministic two-stage sums: stage 1 writes one partial per block (grid-stride loop, fixed
+// grid, fixed tree); stage 2 sums the partials in index order in one block.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+    for (int q = 0; q < kBlock / 64; ++q) r += red[q];
+  }
+  __syncthreads();
+  return r;
+}
+
+// what: 0 = sum x, 1 = sum x^2, 2 = sum of squared non-finite flags (count of NaN/Inf)
+__global__ void __launch_bounds__(kBlock) k_sum_partials(const double* __restrict__ x, size_t n3, int what,
+                                                          double* __restrict__ part) {
+  __shared__ double red[kBlock / 64];
+  double acc = 0.0;
+  for (size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x; t < n3; t += (size_t)gridDim.x * kBlock) {
+    const double v = x[t];
+    acc += what == 0 ? v : (what == 1 ? v * v : (isfinite(v) ? 0.0 : 1.0));
+  }
+  const double r = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+__global__ void __launch_bounds__(kBlock) k_sum_final(const double* __restrict__ part, int np, int stride,
+                                                       double* __restrict__ out, int nvals) {
+  // out[v] = sum_{b < np} part[b*stride + v] in index order, v < nvals
+  __shared__ double red[kBlock / 64];
+  for (int v = 0; v < nvals; ++v) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < np; b += kBlock) acc += part[(size_t)b * stride + v];
+    const double r = block_sum(acc, red);
+    if (threadIdx.x == 0) out[v] = r;
+  }
+}
+
+int reduce_blocks(size_t n3) {
+  size_t b = (n3 + (size_t)kBlock * 8 - 1) / ((size_t)kBlock * 8);
+  if (b > (size_t)kMaxPartials) b = kMaxPartials;
+  return (int)(b < 1 ? 1 : b);
+}
+
+void launch_sum(const double* x, size_t n3, int what, double* part, double* out, hipStream_t s) {
+  const int nb = reduce_blocks(n3);
+  hipLaunchKernelGGL(k_sum_partials, dim3(nb), dim3(kBlock), 0, s, x, n3, what, part);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBlock), 0, s, part, nb, 1, out, 1);
+}
+
+// Defect of the finest level and its sum of squares (Sec. 2.3.7, eq. threshold); optionally
+// the defect itself in FP32 (mixed precision: right-hand side of the inner correction cycle).
+__global__ void __launch_bounds__(kBlock) k_defect_norm(const double* __restrict__ u, const double* __restrict__ f,
+                                                         float* __restrict__ r32, int n, int L, double ih2, LevelBC bc,
+                                                         double* __restrict__ part) {
+  __shared__ double red[kBlock / 64];
+  const size_t n3 = (size_t)1 << (3 * L);
+  double acc = 0.0;
+  for (size_t c = (size_t)blockIdx.x * kBlock + threadIdx.x; c < n3; c += (size_t)gridDim.x * kBlock) {
+    const int i = (int)(c & (size_t)(n - 1));
+    const int j = (int)((c >> L) & (size_t)(n - 1));
+    const int k = (int)(c >> (2 * L));
+    const double uc = u[c];
+    const double nb = neighbour_sum(u, n, L, i, j, k, c, uc, bc);
+    const double d = f[c] - (nb - 6.0 * uc) * ih2;
+    acc += d * d;
+    if (r32) r32[c] = (float)d;
+  }
+  const double r = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+void launch_defect_norm(const double* u, const double* f, float* r32, int n, double h, const LevelBC& bc,
+                        double* part, double* out, hipStream_t s) {
+  const int L = ilog2(n);
+  const size_t n3 = (size_t)1 << (3 * L);
+  const int nb = reduce_blocks(n3);
+  hipLaunchKernelGGL(k_defect_norm, dim3(nb), dim3(kBlock), 0, s, u, f, r32, n, L, 1.0 / (h * h), bc, part);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBlock), 0, s, part, nb, 1, out, 1);
+}
+
+// ------------------------------------------------------------------ boundary face arrays
+
+// Finest-level FIXED face: extend the caller's n^2 face-centre array to (n+2)^2, the ring
+// taking the nearest face value.
+__global__ void __launch_bounds__(kBlock) k_face_extend(const double* __restrict__ b, double* __restrict__ e, int n) {
+  const int m = n + 2;
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= m * m) return;
+  const int t1 = t % m - 1, t2 = t / m - 1;
+  const int c1 = t1 < 0 ? 0 : (t1 >= n ? n - 1 : t1);
+  const int c2 = t2 < 0 ? 0 : (t2 >= n ? n - 1 : t2);
+  e[t] = b ? b[(size_t)c2 * n + c1] : 0.0;
+}
+
+// Coarser FIXED face: 2x2 area mean of the finer face values, then the extension ring.
+__global__ void __launch_bounds__(kBlock) k_face_restrict(const double* __restrict__ ef, double* __restrict__ ec, int nc) {
+  const int m = nc + 2, nf = 2 * nc, mf = nf + 2;
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= m * m) return;
+  int t1 = t % m - 1, t2 = t / m - 1;
+  t1 = t1 < 0 ? 0 : (t1 >= nc ? nc - 1 : t1);
+  t2 = t2 < 0 ? 0 : (t2 >= nc ? nc - 1 : t2);
+  const double* r0 = ef + (size_t)(2 * t2 + 1) * mf + 1;
+  const double* r1 = ef + (size_t)(2 * t2 + 2) * mf + 1;
+  ec[t] = (r0[2 * t1] + r0[2 * t1 + 1] + r1[2 * t1] + r1[2 * t1 + 1]) / 4.0;
+}
+
+void launch_face_extend(const double* b, double* e, int n, hipStream_t s) {
+  const int m = n + 2;
+  hipLaunchKernelGGL(k_face_extend, dim3((m * m + kBlock - 1) / kBlock), dim3(kBlock), 0, s, b, e, n);
+}
+
+void launch_face_restrict(const double* ef, double* ec, int nc, hipStream_t s) {
+  const int m = nc + 2;
+  hipLaunchKernelGGL(k_face_restrict, dim3((m * m + kBlock - 1) / kBlock), dim3(kBlock), 0, s, ef, ec, nc);
+}
+
+// ------------------------------------------------------------------ explicit instantiations
+
+#define MG_INST(T)                                                                                   \
+  template void launch_half_sweep<T>(T*, const T*, int, double, double, int, const LevelBC&, hipStream_t); \
+  template void launch_defect<T>(const T*, const T*, T*, int, double, const LevelBC&, hipStream_t);        \
+  template void launch_defect_restrict<T>(const T*, const T*, T*, T*, int, double, const LevelBC&,         \
+                                          hipStream_t);                                                    \
+  template void launch_prolong<T>(const T*, T*, int, const LevelBC&, int, hipStream_t);                    \
+  template void launch_coarsest<T>(T*, const T*, double, const LevelBC&, hipStream_t);                     \
+  template void launch_tail<T>(const TailArgs&, hipStream_t);
+
+MG_INST(double)
+MG_INST(float)
+template void launch_restrict<double, double>(const double*, double*, int, hipStream_t);
+template void launch_restrict<float, float>(const float*, float*, int, hipStream_t);
+template void launch_restrict<double, float>(const double*, float*, int, hipStream_t);
+
+}  // namespace mg

@@ -1,0 +1,78 @@
+// mg_launch.h -- host-side declarations of the kernel launchers (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+#include "mg_common.h"
+
+namespace mg {
+
+constexpr int kMaxPartials = 2048;   // per-block partial sums of the two-stage reductions
+
+inline int ilog2(long long n) {
+  int l = 0;
+  while ((1LL << l) < n) ++l;
+  return l;
+}
+
+enum : int { TAIL_FMG = 1, TAIL_LOAD_U = 2 };
+
+// Arguments of the coarse-tail kernel (all levels <= 16^3 of one hierarchy in LDS).
+struct TailArgs {
+  int top;            // highest level held (level 0 is one cell)
+  int total;          // cells over levels 0..top (set by the launcher)
+  int mode;           // TAIL_FMG / TAIL_LOAD_U bits
+  int npre, npost;
+  double omega;
+  double h[5];        // cell width per level
+  LevelBC bc_top;     // description of level `top` in V-cycle mode
+  LevelBC hom;        // homogeneous description (coarse corrections)
+  LevelBC phys[5];    // physical description per level (FMG mode)
+  const void* fg[5];  // device source per level (FMG mode: all levels; V-cycle mode: top only)
+  void* ug;           // device solution / correction of level `top` (in and out)
+};
+
+template <typename T>
+void launch_half_sweep(T* u, const T* f, int n, double h, double omega, int colour, const LevelBC& bc,
+                       hipStream_t s);
+template <typename T>
+void launch_defect(const T* u, const T* f, T* d, int n, double h, const LevelBC& bc, hipStream_t s);
+template <typename T>
+void launch_defect_restrict(const T* u, const T* f, T* fc, T* uc0, int n, double h, const LevelBC& bc,
+                            hipStream_t s);
+template <typename Tin, typename Tout>
+void launch_restrict(const Tin* uf, Tout* uc, int nc, hipStream_t s);
+template <typename T>
+void launch_prolong(const T* uc, T* uf, int nc, const LevelBC& bcc, int cubic, hipStream_t s);
+template <typename T>
+void launch_coarsest(T* u, const T* f, double h, const LevelBC& bc, hipStream_t s);
+template <typename T>
+void launch_tail(const TailArgs& a, hipStream_t s);
+size_t tail_lds_bytes(int top, size_t elem);
+// Allows the FP64 tail its dynamic LDS; returns the highest level it can hold (3 or 4).
+int tail_prepare(size_t lds_per_block);
+
+void launch_source(const double* rho, double* f, float* f32, size_t n3, double a, double c, hipStream_t s);
+void launch_sub_mean(double* u, size_t n3, const double* sum_dev, hipStream_t s);
+void launch_f32_to_f64(const float* a, double* b, size_t n3, hipStream_t s);
+void launch_add_f32(double* phi, const float* e, size_t n3, hipStream_t s);
+
+int reduce_blocks(size_t n3);
+// what: 0 = sum x, 1 = sum x^2, 2 = count of non-finite values; result in out[0] (device)
+void launch_sum(const double* x, size_t n3, int what, double* part, double* out, hipStream_t s);
+void launch_defect_norm(const double* u, const double* f, float* r32, int n, double h, const LevelBC& bc,
+                        double* part, double* out, hipStream_t s);
+
+void launch_face_extend(const double* b, double* e, int n, hipStream_t s);
+void launch_face_restrict(const double* ef, double* ec, int nc, hipStream_t s);
+
+// multipole (mg_multipole.hip)
+// moments[0..3] = (M, Mx, My, Mz) sums; origin[3]; q[25]
+void launch_multipole_moments(const double* rho, int n, double dx, int lmax, int use_origin, const double* origin_host,
+                              double* part, double* scratch, hipStream_t s);
+void launch_multipole_faces(const double* scratch, int lmax, double G, int nl, double hl, double length,
+                            double* faces[6], hipStream_t s);
+
+}  // namespace mg

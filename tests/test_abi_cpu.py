@@ -1,0 +1,54 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every function
+the header declares, and its pure host entry points behave."""
+import ctypes
+
+import pytest
+
+from paper_2302_13903_amd import _abi
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _abi.lib()
+    declared = _abi.declared_functions()
+    assert len(declared) >= 18
+    missing = [name for name in declared if not hasattr(lib, name)]
+    assert not missing, missing
+
+
+def test_default_params():
+    p = _abi.MgParams()
+    _abi.lib().mg_default_params(ctypes.byref(p))
+    assert (p.npre, p.npost, p.omega, p.tol, p.max_cycles) == (2, 2, 1.15, 1e-10, 50)
+    assert abs(p.four_pi_g - 12.566370614359172) < 1e-15
+    assert p.precision == _abi.MG_PREC_FP64 and p.layout == _abi.MG_LAYOUT_DENSE
+
+
+def test_footprint_model():
+    lib = _abi.lib()
+    p = _abi.MgParams()
+    lib.mg_default_params(ctypes.byref(p))
+    for bad in (0, 3, 6, 4096):
+        p.n = bad
+        assert lib.mg_footprint_bytes(ctypes.byref(p)) == 0
+    p.n = 512
+    fp64 = lib.mg_footprint_bytes(ctypes.byref(p))
+    # finest source + (u, f) on coarser levels: about 8 + 16/7 bytes per finest cell
+    assert 10.0 < fp64 / 512 ** 3 < 10.6
+    p.precision = _abi.MG_PREC_MIXED
+    mixed = lib.mg_footprint_bytes(ctypes.byref(p))
+    # FP64 source + FP32 (e, r) on all levels: about 8 + 8 * 8/7 bytes per finest cell
+    assert 17.0 < mixed / 512 ** 3 < 17.4
+
+
+def test_binding_has_the_abi_names():
+    import paper_2302_13903_amd as mg
+    for name in _abi.declared_functions():
+        if name.startswith("mg_op_") or name in ("mg_solve", "mg_footprint_bytes", "mg_multipole_moments"):
+            assert hasattr(mg, name), name
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    monkeypatch.setattr(_abi, "_lib", None)
+    monkeypatch.setattr(_abi, "LIB_PATH", "/nonexistent/libmg355.so")
+    with pytest.raises(_abi.MgError):
+        _abi.lib()
