@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Benchmark of the multigrid hot path on one MI355X.
+
+Workload (default): the 512^3 periodic Gaussian-clump problem (64 clumps, widths 0.01-0.05,
+lognormal amplitudes, mean removed), FMG + V(2,2) cycles to a relative residual of 1e-10,
+FP64 and FP32/FP64 mixed precision.  One step = one whole solve with rho already resident
+in HBM.  The JSON line reports:
+
+  value         GDoF/s per V-cycle (FP64) = n^3 / median V-cycle time, V-cycles timed with
+                HIP events inside the library during the timed steps;
+  ms_per_step   wall time of one FP64 solve (set-up + FMG + cycles to tolerance);
+  roofline      the dominant kernel (finest-level smoothing): algorithmic bytes per launch /
+                its mean launch time (HIP events on the solve stream) against 8 TB/s;
+  cpu_baseline  the CPU oracle timed on a bounded sample of the same workload;
+  mixed         the same numbers for the mixed-precision solve; p50/p99 solve latency.
+
+python bench.py [--steps K] [--warmup W] [--n N] [--no-cpu-baseline] [--no-mixed]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def pct(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q
+    lo, hi = math.floor(k), math.ceil(k)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2302_13903_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, n: int):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None
+    when there is none or the kernel sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != kernel_source_hash():
+        return None
+    entry = t.get("kernels", {}).get(f"{kernel}@{n}")
+    return None if entry is None else entry.get("bytes_per_launch")
+
+
+def run_solves(mg, ctx, rho, n, precision, steps, warmup, tol):
+    import torch
+    phi = torch.zeros_like(rho)
+    lat, cyc, hists, kt = [], [], [], []
+    for it in range(warmup + steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        phi, hist, st = mg.solve(rho, 1.0 / n, "periodic", tol=tol, precision=precision, phi=phi, ctx=ctx)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if st < 0 or hist[-1] > tol:
+            raise RuntimeError(f"solve did not converge: status {st}, hist {hist}")
+        if it >= warmup:
+            lat.append((t1 - t0) * 1e3)
+            setup_ms, fmg_ms, cms = ctx.last_timing()
+            cyc.extend(cms)
+            hists.append(hist)
+            kt.append(ctx.kernel_timing())
+        print(f"# {precision} step {it - warmup:+d}: {1e3 * (t1 - t0):.2f} ms, cycles {len(hist) - 1}, "
+              f"r = {hist[-1]:.2e}", file=sys.stderr, flush=True)
+    return lat, cyc, hists, kt
+
+
+def cpu_baseline(n: int, cycles: int = 3):
+    """The CPU oracle on a bounded sample: set-up plus `cycles` V(2,2) cycles from zero on the
+    same n^3 clump density; GDoF/s per V-cycle = n^3 / mean cycle time."""
+    import numpy as np
+
+    import oracle
+    import workloads as wl
+    rho = wl.gaussian_clumps(n, 2)
+    st = oracle.State(rho, 1.0 / n, "periodic")
+    st.set_phi(np.zeros_like(rho))
+    t0 = time.perf_counter()
+    for _ in range(cycles):
+        st.vcycle()
+    dt = (time.perf_counter() - t0) / cycles
+    return {"value": n ** 3 / dt / 1e9, "unit": "GDoF/s per V-cycle", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{n}^3 clump density, {cycles} V(2,2) cycles from zero (FMG not timed), "
+                      f"{dt * 1e3:.0f} ms per cycle"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
+              file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_2302_13903_amd as mg
+    import workloads as wl
+
+    n = args.n
+    t0 = time.perf_counter()
+    rho_h = wl.gaussian_clumps(n, args.seed)
+    rho = torch.from_numpy(rho_h).to("cuda:0")
+    del rho_h
+    print(f"# input {n}^3 generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    ctx = mg.Context(0)
+    ctx.set_kernel_timing(True)
+    lat, cyc, hists, kt = run_solves(mg, ctx, rho, n, "fp64", args.steps, args.warmup, args.tol)
+    t_v = statistics.median(cyc)
+    value = n ** 3 / (t_v * 1e-3) / 1e9
+    # per kernel (finest-level smoothing passes), summed over the timed steps
+    agg = {}
+    for recs in kt:
+        for r in recs:
+            a = agg.setdefault(r["name"], {"launches": 0, "total_ms": 0.0, "bytes_per_launch": r["bytes_per_launch"]})
+            a["launches"] += r["launches"]
+            a["total_ms"] += r["total_ms"]
+    passes = []
+    for name, a in agg.items():
+        avg = a["total_ms"] / max(a["launches"], 1)
+        passes.append({"kernel": name, "launches": a["launches"], "avg_launch_ms": avg,
+                       "algorithmic_bytes_per_launch": a["bytes_per_launch"],
+                       "achieved_GBs": a["bytes_per_launch"] / (avg * 1e-3) / 1e9 if avg > 0 else None})
+    dom = max(passes, key=lambda q: q["avg_launch_ms"] * q["launches"])
+    achieved = dom["achieved_GBs"]
+    traffic = measured_traffic(dom["kernel"], n)
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": None if achieved is None else achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": dom["kernel"], "algorithmic_bytes_per_launch": dom["algorithmic_bytes_per_launch"],
+                "avg_launch_ms": dom["avg_launch_ms"], "launches": dom["launches"], "passes": passes}
+
+    out = {
+        "metric": "GDoF/s per V-cycle + % HBM roofline at 512^3; p50/p99 solve latency, mixed vs FP64",
+        "value": value,
+        "unit": "GDoF/s per V-cycle",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": statistics.mean(lat),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"C2 Gaussian clumps {n}^3 periodic, FMG + V(2,2) to relative residual "
+                               f"{args.tol:g}", "n": n, "tol": args.tol, "cycles_per_solve": len(hists[-1]) - 1},
+        "roofline": roofline,
+        "v_cycle_ms_median": t_v,
+        "solve_latency_ms": {"p50": pct(lat, 0.5), "p99": pct(lat, 0.99)},
+    }
+    ctx.set_kernel_timing(False)
+    if not args.no_mixed:
+        lat_m, cyc_m, hists_m, _ = run_solves(mg, ctx, rho, n, "mixed", args.steps, args.warmup, args.tol)
+        tvm = statistics.median(cyc_m)
+        out["mixed"] = {"value": n ** 3 / (tvm * 1e-3) / 1e9, "unit": "GDoF/s per outer cycle",
+                        "ms_per_step": statistics.mean(lat_m), "cycles_per_solve": len(hists_m[-1]) - 1,
+                        "cycle_ms_median": tvm,
+                        "solve_latency_ms": {"p50": pct(lat_m, 0.5), "p99": pct(lat_m, 0.99)}}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(n)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

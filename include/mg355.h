@@ -124,12 +124,15 @@ int mg_solve(mg_ctx *ctx, const mg_params *p, const mg_bc *bc, const double *rho
 int mg_last_timing(const mg_ctx *ctx, double *setup_ms, double *fmg_ms, double *cycle_ms,
                    int cap, int *n);
 
-/* Kernel-level timing of the finest-level smoothing kernels during the last mg_solve:
- * number of launches and their summed duration (HIP events around each launch).
- * Enabled by mg_set_kernel_timing(ctx, 1); off by default. */
+/* Kernel-level timing of the finest-level smoothing kernels of the V-cycles of the last
+ * mg_solve, from HIP events recorded on the solve stream around each launch.  Enabled by
+ * mg_set_kernel_timing(ctx, 1); off by default (the events cost a little host time).
+ * Entry `index` (0-based, one per kernel name): launch count, summed duration (ms), the
+ * algorithmic HBM bytes of one launch, and the kernel name (as the profiler lists it).
+ * Returns MG_ERR_INVALID_ARG past the last entry. */
 int mg_set_kernel_timing(mg_ctx *ctx, int on);
-int mg_kernel_timing(const mg_ctx *ctx, int *launches, double *total_ms, double *bytes_per_launch,
-                     char *name, int name_cap);
+int mg_kernel_timing(const mg_ctx *ctx, int index, int *launches, double *total_ms,
+                     double *bytes_per_launch, char *name, int name_cap);
 
 /* Multipole set-up (Appendix A): centre of mass (unless use_origin) and the 25 moments
  * Q_lm, l <= lmax, of rho (device, n^3) with cell volume dx^3.  origin_out (host, 3) and

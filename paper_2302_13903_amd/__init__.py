@@ -97,10 +97,19 @@ class Context:
         self._lib.mg_set_kernel_timing(self.handle, 1 if on else 0)
 
     def kernel_timing(self):
-        n, ms, by = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
-        name = ctypes.create_string_buffer(128)
-        self._lib.mg_kernel_timing(self.handle, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by), name, 128)
-        return {"launches": n.value, "total_ms": ms.value, "bytes_per_launch": by.value, "name": name.value.decode()}
+        """Per-kernel records of the last solve's finest-level passes (see mg_kernel_timing)."""
+        out = []
+        idx = 0
+        while True:
+            n, ms, by = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
+            name = ctypes.create_string_buffer(256)
+            st = self._lib.mg_kernel_timing(self.handle, idx, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by),
+                                            name, 256)
+            if st != MG_OK:
+                return out
+            out.append({"launches": n.value, "total_ms": ms.value, "bytes_per_launch": by.value,
+                        "name": name.value.decode()})
+            idx += 1
 
 
 _default_ctx = {}

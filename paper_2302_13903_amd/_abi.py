@@ -69,7 +69,7 @@ def lib():
         "mg_solve": (i, [_vp, ctypes.POINTER(MgParams), ctypes.POINTER(MgBC), _vp, _vp, _dp, _ip, _vp]),
         "mg_last_timing": (i, [_vp, _dp, _dp, _dp, i, _ip]),
         "mg_set_kernel_timing": (i, [_vp, i]),
-        "mg_kernel_timing": (i, [_vp, _ip, _dp, _dp, ctypes.c_char_p, i]),
+        "mg_kernel_timing": (i, [_vp, i, _ip, _dp, _dp, ctypes.c_char_p, i]),
         "mg_multipole_moments": (i, [_vp, i, d, _vp, i, i, _dp, _dp, _dp, _vp]),
         "mg_op_half_sweep": (i, [_vp, i, d, d, i, ctypes.POINTER(MgLevelBC), _vp, _vp, _vp]),
         "mg_op_smooth": (i, [_vp, i, d, d, i, ctypes.POINTER(MgLevelBC), _vp, _vp, _vp]),

@@ -35,12 +35,20 @@ struct mg_ctx {
   std::vector<hipEvent_t> ev_cycle;
   double setup_ms = 0, fmg_ms = 0;
   std::vector<double> cycle_ms;
-  // kernel timing of the finest-level smoothing kernel
+  // kernel timing of the finest-level smoothing kernels: events around each launch, then
+  // per kernel name the launch count, summed duration and algorithmic bytes per launch
   int ktiming = 0;
   std::vector<hipEvent_t> kev;
-  int klaunches = 0;
-  double kms = 0, kbytes = 0;
-  std::string kname;
+  std::vector<int> kev_id;
+  struct KStat {
+    std::string name;
+    int launches = 0;
+    double ms = 0, bytes = 0;
+  };
+  std::vector<KStat> kstats;
+  // scratch of the operator entry points (ping-pong partner of a caller's array)
+  void* op_scratch = nullptr;
+  size_t op_scratch_cap = 0;
 };
 
 namespace {
@@ -74,6 +82,7 @@ struct Layout {
   size_t f64L = 0;             // FP64 finest source
   size_t u64[16], f64[16];     // FP64 levels 0..L-1 (FP64 mode)
   size_t u32[16], f32[16];     // FP32 levels 0..L (mixed mode)
+  size_t u2[16];               // second (ping-pong) buffer of the levels swept by fused passes
   size_t faces[16];            // 6 extended face arrays per level
   size_t total = 0;
 };
@@ -100,6 +109,8 @@ Layout make_layout(int n, int precision) {
       y.f32[l] = take(cells(l) * 4);
     }
     y.faces[l] = take(6 * face_sz(l) * 8);
+    y.u2[l] = (size_t)-1;
+    if ((1 << l) >= kFusedMinN) y.u2[l] = take(cells(l) * (y.mixed ? 4 : 8));
   }
   y.total = off;
   return y;
@@ -159,6 +170,7 @@ template <typename T>
 struct Hier {
   int L = 0, T_top = 0;
   T* u[16];
+  T* u2[16];          // ping-pong partner of u[l] for fused levels, else nullptr
   T* f[16];
   double h[16];
   LevelBC phys[16];
@@ -170,27 +182,7 @@ struct Hier {
 struct Solver {
   mg_ctx* c;
   hipStream_t s;
-  int fused_ok = 1;
-
-  // smoothing sweeps on one level; the finest FP64 level may use the fused kernel
-  template <typename T>
-  void smooth(Hier<T>& H, int l, int sweeps, const LevelBC& bc, bool timed) {
-    if (sweeps <= 0) return;
-    const int n = 1 << l;
-    if (fused_ok && fused_supported<T>(n)) {
-      if (timed && c->ktiming) kernel_begin();
-      launch_fused_smooth<T>(H.u[l], H.f[l], n, H.h[l], H.omega, sweeps, bc, s);
-      if (timed && c->ktiming) kernel_end(fused_smooth_name<T>(n, sweeps), fused_smooth_bytes<T>(n, sweeps));
-      return;
-    }
-    for (int it = 0; it < sweeps; ++it)
-      for (int colour = 0; colour < 2; ++colour) {
-        if (timed && c->ktiming) kernel_begin();
-        launch_half_sweep<T>(H.u[l], H.f[l], n, H.h[l], H.omega, colour, bc, s);
-        // algorithmic bytes: all of u read, f read and u written on one colour
-        if (timed && c->ktiming) kernel_end("k_half_sweep", (double)cells(l) * 2.0 * sizeof(T));
-      }
-  }
+  bool use_fused = true;
 
   void kernel_begin() {
     hipEvent_t e;
@@ -198,13 +190,20 @@ struct Solver {
     (void)hipEventRecord(e, s);
     c->kev.push_back(e);
   }
+  // algorithmic bytes of one launch are recorded with its name
   void kernel_end(const std::string& name, double bytes) {
     hipEvent_t e;
     (void)hipEventCreate(&e);
     (void)hipEventRecord(e, s);
     c->kev.push_back(e);
-    c->kname = name;
-    c->kbytes = bytes;
+    int id = -1;
+    for (size_t q = 0; q < c->kstats.size(); ++q)
+      if (c->kstats[q].name == name) id = (int)q;
+    if (id < 0) {
+      c->kstats.push_back(mg_ctx::KStat{name, 0, 0.0, bytes});
+      id = (int)c->kstats.size() - 1;
+    }
+    c->kev_id.push_back(id);
   }
 
   template <typename T>
@@ -228,20 +227,71 @@ struct Solver {
   }
 
   // Alg. 1 on level l (l >= T_top).  At the tail level the whole remaining recursion runs in
-  // one LDS-resident workgroup.
+  // one LDS-resident workgroup.  Large levels run four fused passes (sweep; sweep + restricted
+  // defect; prolonged correction + sweep; sweep [+ defect norm]).  Returns true when the sum
+  // of squared defects of the result is in c->scal[2] (want_norm on a fused finest level).
   template <typename T>
-  void vcycle(Hier<T>& H, int l, const LevelBC& bc, bool top_call) {
+  bool vcycle(Hier<T>& H, int l, const LevelBC& bc, bool top_call, bool want_norm) {
     if (l == H.T_top) {
       tail(H, top_call ? TAIL_LOAD_U : 0, bc);
-      return;
+      return false;
     }
     const int n = 1 << l;
-    const bool timed = top_call && l == H.L;
-    smooth(H, l, H.npre, bc, timed);
-    launch_defect_restrict<T>(H.u[l], H.f[l], H.f[l - 1], H.u[l - 1], n, H.h[l], bc, s);
-    vcycle(H, l - 1, H.hom, false);
+    const double h = H.h[l];
+    const bool timed = top_call && l == H.L && c->ktiming;
+    const double cellsT = (double)cells(l) * sizeof(T);
+    if (use_fused && H.u2[l]) {
+      T* cur = H.u[l];
+      T* oth = H.u2[l];
+      for (int it = 0; it < H.npre; ++it) {
+        const bool last = it == H.npre - 1;
+        if (timed) kernel_begin();
+        if (last) fused_sweep_defect<T>(cur, oth, H.f[l], H.f[l - 1], H.u[l - 1], n, h, H.omega, bc, s);
+        else fused_sweep<T>(cur, oth, H.f[l], n, h, H.omega, bc, s);
+        if (timed) kernel_end(fused_pass_name<T>(false, last ? 1 : 0), 3 * cellsT + (last ? cellsT / 4 : 0.0));
+        std::swap(cur, oth);
+      }
+      if (H.npre == 0) launch_defect_restrict<T>(cur, H.f[l], H.f[l - 1], H.u[l - 1], n, h, bc, s);
+      vcycle(H, l - 1, H.hom, false, false);
+      bool normed = false;
+      if (H.npost == 0) launch_prolong<T>(H.u[l - 1], cur, n / 2, H.hom, 0, s);
+      for (int it = 0; it < H.npost; ++it) {
+        const bool last = it == H.npost - 1;
+        if (timed) kernel_begin();
+        if (it == 0) {
+          fused_prolong_sweep<T>(cur, oth, H.f[l], H.u[l - 1], H.hom, n, h, H.omega, bc, s);
+          if (timed) kernel_end(fused_pass_name<T>(true, 0), 3 * cellsT + cellsT / 8);
+        } else if (last && want_norm) {
+          const int np = fused_sweep_norm<T>(cur, oth, H.f[l], c->part, n, h, H.omega, bc, s);
+          if (timed) kernel_end(fused_pass_name<T>(false, 2), 3 * cellsT);
+          launch_sum_partials(c->part, np, c->scal + 2, s);
+          normed = true;
+        } else {
+          fused_sweep<T>(cur, oth, H.f[l], n, h, H.omega, bc, s);
+          if (timed) kernel_end(fused_pass_name<T>(false, 0), 3 * cellsT);
+        }
+        std::swap(cur, oth);
+      }
+      if (cur != H.u[l]) (void)hipMemcpyAsync(H.u[l], cur, cells(l) * sizeof(T), hipMemcpyDeviceToDevice, s);
+      return normed;
+    }
+    for (int it = 0; it < H.npre; ++it)
+      for (int colour = 0; colour < 2; ++colour) {
+        if (timed) kernel_begin();
+        launch_half_sweep<T>(H.u[l], H.f[l], n, h, H.omega, colour, bc, s);
+        // algorithmic bytes: all of u read, f read and u written on one colour
+        if (timed) kernel_end("k_half_sweep", 2 * cellsT);
+      }
+    launch_defect_restrict<T>(H.u[l], H.f[l], H.f[l - 1], H.u[l - 1], n, h, bc, s);
+    vcycle(H, l - 1, H.hom, false, false);
     launch_prolong<T>(H.u[l - 1], H.u[l], n / 2, H.hom, 0, s);
-    smooth(H, l, H.npost, bc, timed);
+    for (int it = 0; it < H.npost; ++it)
+      for (int colour = 0; colour < 2; ++colour) {
+        if (timed) kernel_begin();
+        launch_half_sweep<T>(H.u[l], H.f[l], n, h, H.omega, colour, bc, s);
+        if (timed) kernel_end("k_half_sweep", 2 * cellsT);
+      }
+    return false;
   }
 
   // Alg. 2: FMG over all levels with each level's physical description.
@@ -250,7 +300,7 @@ struct Solver {
     tail(H, TAIL_FMG, H.phys[H.T_top]);
     for (int l = H.T_top + 1; l <= H.L; ++l) {
       launch_prolong<T>(H.u[l - 1], H.u[l], 1 << (l - 1), H.phys[l - 1], 1, s);
-      vcycle(H, l, H.phys[l], false);
+      vcycle(H, l, H.phys[l], false, false);
     }
   }
 };
@@ -316,6 +366,7 @@ void mg_ctx_destroy(mg_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   if (c->ws) (void)hipFree(c->ws);
+  if (c->op_scratch) (void)hipFree(c->op_scratch);
   if (c->part) (void)hipFree(c->part);
   if (c->scal) (void)hipFree(c->scal);
   if (c->hscal) (void)hipHostFree(c->hscal);
@@ -340,14 +391,16 @@ int mg_set_kernel_timing(mg_ctx* c, int on) {
   return MG_OK;
 }
 
-int mg_kernel_timing(const mg_ctx* c, int* launches, double* total_ms, double* bytes_per_launch, char* name,
-                     int name_cap) {
+int mg_kernel_timing(const mg_ctx* c, int index, int* launches, double* total_ms, double* bytes_per_launch,
+                     char* name, int name_cap) {
   if (!c) return MG_ERR_INVALID_ARG;
-  if (launches) *launches = c->klaunches;
-  if (total_ms) *total_ms = c->kms;
-  if (bytes_per_launch) *bytes_per_launch = c->kbytes;
+  if (index < 0 || index >= (int)c->kstats.size()) return MG_ERR_INVALID_ARG;
+  const auto& k = c->kstats[index];
+  if (launches) *launches = k.launches;
+  if (total_ms) *total_ms = k.ms;
+  if (bytes_per_launch) *bytes_per_launch = k.bytes;
   if (name && name_cap > 0) {
-    std::strncpy(name, c->kname.c_str(), name_cap - 1);
+    std::strncpy(name, k.name.c_str(), name_cap - 1);
     name[name_cap - 1] = 0;
   }
   return MG_OK;
@@ -427,8 +480,8 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
   if (st != MG_OK) return st;
   for (auto e : c->kev) (void)hipEventDestroy(e);
   c->kev.clear();
-  c->klaunches = 0;
-  c->kms = 0;
+  c->kev_id.clear();
+  c->kstats.clear();
 
   const int L = y.L;
   const size_t n3 = cells(L);
@@ -458,7 +511,7 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
   LevelBC phys[16], hom;
   setup_faces(c, y, p, bc, rho, s, phys, &hom);
 
-  Solver S{c, s};
+  Solver S{c, s, true};
   Hier<double> H64;
   Hier<float> H32;
   auto fill_common = [&](auto& H, int tail_top) {
@@ -481,12 +534,15 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
     }
     H64.u[L] = phi;
     H64.f[L] = f64L;
+    for (int l = 0; l <= L; ++l)
+      H64.u2[l] = y.u2[l] == (size_t)-1 ? nullptr : reinterpret_cast<double*>(c->ws + y.u2[l]);
     for (int l = L; l >= 1; --l) launch_restrict<double, double>(H64.f[l], H64.f[l - 1], 1 << (l - 1), s);
   } else {
     fill_common(H32, tail_max);
     for (int l = 0; l <= L; ++l) {
       H32.u[l] = reinterpret_cast<float*>(c->ws + y.u32[l]);
       H32.f[l] = reinterpret_cast<float*>(c->ws + y.f32[l]);
+      H32.u2[l] = y.u2[l] == (size_t)-1 ? nullptr : reinterpret_cast<float*>(c->ws + y.u2[l]);
     }
     for (int l = L; l >= 1; --l) launch_restrict<float, float>(H32.f[l], H32.f[l - 1], 1 << (l - 1), s);
   }
@@ -530,15 +586,15 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
   if (p->fixed_cycles > 0 || r > p->tol) {
     for (int cyc = 0; cyc < ncyc; ++cyc) {
       if (!mixed) {
-        S.vcycle(H64, L, phys[L], true);
-        launch_defect_norm(phi, f64L, nullptr, p->n, p->dx, phys[L], c->part, c->scal + 2, s);
+        const bool normed = S.vcycle(H64, L, phys[L], true, true);
+        if (!normed) launch_defect_norm(phi, f64L, nullptr, p->n, p->dx, phys[L], c->part, c->scal + 2, s);
       } else {
         // defect correction: e32 solves L e = r32 from zero with homogeneous conditions
         if (L == H32.T_top) {
           S.tail(H32, 0, hom);
         } else {
           HIP_CHECK(c, hipMemsetAsync(H32.u[L], 0, n3 * sizeof(float), s));
-          S.vcycle(H32, L, hom, true);
+          S.vcycle(H32, L, hom, true, false);
         }
         launch_add_f32(phi, H32.u[L], n3, s);
         launch_defect_norm(phi, f64L, H32.f[L], p->n, p->dx, phys[L], c->part, c->scal + 2, s);
@@ -578,8 +634,11 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
     prev = c->ev_cycle[cyc];
   }
   if (c->ktiming) {
-    for (size_t q = 0; q + 1 < c->kev.size(); q += 2) c->kms += elapsed(c->kev[q], c->kev[q + 1]);
-    c->klaunches = (int)(c->kev.size() / 2);
+    for (size_t q = 0; q + 1 < c->kev.size(); q += 2) {
+      auto& k = c->kstats[c->kev_id[q / 2]];
+      k.ms += elapsed(c->kev[q], c->kev[q + 1]);
+      k.launches += 1;
+    }
   }
   return status;
 }
@@ -595,6 +654,24 @@ int op_prologue(mg_ctx* c, int n) {
 }
 int op_epilogue(mg_ctx* c) {
   HIP_CHECK(c, hipGetLastError());
+  return MG_OK;
+}
+int op_scratch(mg_ctx* c, size_t bytes, double** out) {
+  if (bytes > c->op_scratch_cap) {
+    if (c->op_scratch) {
+      HIP_CHECK(c, hipDeviceSynchronize());
+      HIP_CHECK(c, hipFree(c->op_scratch));
+      c->op_scratch = nullptr;
+      c->op_scratch_cap = 0;
+    }
+    if (hipMalloc(&c->op_scratch, bytes) != hipSuccess) {
+      c->op_scratch = nullptr;
+      (void)hipGetLastError();
+      return fail(c, MG_ERR_OOM, "operator scratch allocation failed");
+    }
+    c->op_scratch_cap = bytes;
+  }
+  *out = reinterpret_cast<double*>(c->op_scratch);
   return MG_OK;
 }
 }  // namespace
@@ -617,8 +694,17 @@ int mg_op_smooth(mg_ctx* c, int n, double h, double omega, int sweeps, const mg_
   if (n < 2 || sweeps < 0 || sweeps > 4) return fail(c, MG_ERR_INVALID_ARG, "n >= 2, sweeps 0..4");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const LevelBC b = to_level_bc(bc);
-  if (fused_supported<double>(n)) {
-    launch_fused_smooth<double>(u, f, n, h, omega, sweeps, b, s);
+  if (fused_supported<double>(n) && sweeps > 0) {
+    double* tmp = nullptr;
+    st = op_scratch(c, cells(ilog2(n)) * sizeof(double), &tmp);
+    if (st) return st;
+    double* cur = u;
+    double* oth = tmp;
+    for (int it = 0; it < sweeps; ++it) {
+      fused_sweep<double>(cur, oth, f, n, h, omega, b, s);
+      std::swap(cur, oth);
+    }
+    if (cur != u) HIP_CHECK(c, hipMemcpyAsync(u, cur, cells(ilog2(n)) * sizeof(double), hipMemcpyDeviceToDevice, s));
   } else {
     for (int it = 0; it < sweeps; ++it)
       for (int colour = 0; colour < 2; ++colour) launch_half_sweep<double>(u, f, n, h, omega, colour, b, s);
@@ -667,9 +753,25 @@ int mg_op_down(mg_ctx* c, int n, double h, double omega, int npre, const mg_leve
   int st = op_prologue(c, n);
   if (st) return st;
   if (n < 2 || npre < 0 || npre > 4) return fail(c, MG_ERR_INVALID_ARG, "n >= 2, npre 0..4");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const LevelBC b = to_level_bc(bc);
+  if (fused_supported<double>(n) && npre > 0) {
+    double* tmp = nullptr;
+    st = op_scratch(c, cells(ilog2(n)) * sizeof(double), &tmp);
+    if (st) return st;
+    double* cur = u;
+    double* oth = tmp;
+    for (int it = 0; it < npre; ++it) {
+      if (it == npre - 1) fused_sweep_defect<double>(cur, oth, f, fc, uc, n, h, omega, b, s);
+      else fused_sweep<double>(cur, oth, f, n, h, omega, b, s);
+      std::swap(cur, oth);
+    }
+    if (cur != u) HIP_CHECK(c, hipMemcpyAsync(u, cur, cells(ilog2(n)) * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return op_epilogue(c);
+  }
   st = mg_op_smooth(c, n, h, omega, npre, bc, u, f, stream);
   if (st) return st;
-  launch_defect_restrict<double>(u, f, fc, uc, n, h, to_level_bc(bc), reinterpret_cast<hipStream_t>(stream));
+  launch_defect_restrict<double>(u, f, fc, uc, n, h, b, s);
   return op_epilogue(c);
 }
 
@@ -678,7 +780,23 @@ int mg_op_up(mg_ctx* c, int n, double h, double omega, int npost, const mg_level
   int st = op_prologue(c, n);
   if (st) return st;
   if (n < 2 || npost < 0 || npost > 4) return fail(c, MG_ERR_INVALID_ARG, "n >= 2, npost 0..4");
-  launch_prolong<double>(uc, u, n / 2, to_level_bc(bc_coarse), 0, reinterpret_cast<hipStream_t>(stream));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const LevelBC b = to_level_bc(bc), bcc = to_level_bc(bc_coarse);
+  if (fused_supported<double>(n) && npost > 0) {
+    double* tmp = nullptr;
+    st = op_scratch(c, cells(ilog2(n)) * sizeof(double), &tmp);
+    if (st) return st;
+    double* cur = u;
+    double* oth = tmp;
+    for (int it = 0; it < npost; ++it) {
+      if (it == 0) fused_prolong_sweep<double>(cur, oth, f, uc, bcc, n, h, omega, b, s);
+      else fused_sweep<double>(cur, oth, f, n, h, omega, b, s);
+      std::swap(cur, oth);
+    }
+    if (cur != u) HIP_CHECK(c, hipMemcpyAsync(u, cur, cells(ilog2(n)) * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return op_epilogue(c);
+  }
+  launch_prolong<double>(uc, u, n / 2, bcc, 0, s);
   return mg_op_smooth(c, n, h, omega, npost, bc, u, f, stream);
 }
 

@@ -1,4 +1,7 @@
-// mg_fused.h -- bandwidth-optimised fused smoothing kernels for the large levels.
+// mg_fused.h -- fused z-marching smoothing passes for the large levels (internal).
+//
+// Every pass reads u from `uin` and writes the swept u to `uout` (uin != uout): tiles overlap
+// in their halos, so the update cannot be in place.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -9,20 +12,38 @@
 
 namespace mg {
 
-// True when the fused kernel handles an n^3 level in precision T.
+// Smallest level size handled by the fused passes (smaller levels use the per-operator kernels).
+constexpr int kFusedMinN = 64;
+
 template <typename T>
 bool fused_supported(int n);
 
-// `sweeps` red-then-black RB-SOR sweeps of u (eqs. rbsor1-2), identical in result to
-// 2*sweeps single-colour launches.
+// One red-then-black sweep.
 template <typename T>
-void launch_fused_smooth(T* u, const T* f, int n, double h, double omega, int sweeps, const LevelBC& bc,
-                         hipStream_t s);
+void fused_sweep(const T* uin, T* uout, const T* f, int n, double h, double omega, const LevelBC& bc,
+                 hipStream_t s);
 
-// Kernel name and algorithmic HBM bytes of one launch (for the roofline report).
+// One sweep, then the defect restricted into fc (coarse level) and uc0 cleared.
 template <typename T>
-std::string fused_smooth_name(int n, int sweeps);
+void fused_sweep_defect(const T* uin, T* uout, const T* f, T* fc, T* uc0, int n, double h, double omega,
+                        const LevelBC& bc, hipStream_t s);
+
+// u += trilinear(ec) on the fly (ec's ghosts from bcc), then one sweep.
 template <typename T>
-double fused_smooth_bytes(int n, int sweeps);
+void fused_prolong_sweep(const T* uin, T* uout, const T* f, const T* ec, const LevelBC& bcc, int n, double h,
+                         double omega, const LevelBC& bc, hipStream_t s);
+
+// One sweep, then one partial sum of squared defects per block into part; returns the number
+// of partials written.
+template <typename T>
+int fused_sweep_norm(const T* uin, T* uout, const T* f, double* part, int n, double h, double omega,
+                     const LevelBC& bc, hipStream_t s);
+
+template <typename T>
+int fused_grid_blocks(int n, int hx);
+
+// Names of the pass kernels as the profiler lists them.
+template <typename T>
+std::string fused_pass_name(bool pro, int out);
 
 }  // namespace mg

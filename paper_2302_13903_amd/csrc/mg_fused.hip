@@ -1,33 +1,503 @@
-// mg_fused.hip -- fused multi-sweep smoothing kernels (large levels).
+// mg_fused.hip -- fused, z-marching RB-SOR passes for the large levels (bandwidth path).
+//
+// One launch = one full smoothing sweep (red half-sweep, then black; eqs. rbsor1-2) over the
+// level, streamed through registers so u and f cross HBM once per sweep (24 B per cell in
+// FP64 instead of 48 for two single-colour launches).  Optional fused stages:
+//   PRO : on load, add the trilinear prolongation of the coarse correction (Alg. 1 steps 5-6);
+//   OUT=1 (DEF) : after the sweep, the defect f - L u (eq. defect) restricted to the coarse
+//         level (eq. restriction; Alg. 1 steps 2-3), and the coarse correction cleared;
+//   OUT=2 (NORM): after the sweep, sum of squared defects for the stopping test (Sec. 2.3.7).
+//
+// Layout of one workgroup (W wavefronts, 64 lanes each): a tile of 128 x (R*W) cells in x-y,
+// lane l holding the x-pair (x0+2l, x0+2l+1) of R consecutive rows; the workgroup marches in
+// z over a chunk of planes.  Each cell keeps a ring of RING planes of u and f in registers:
+// at the step that loads plane P, the red update runs on plane P-1, the black update on P-2
+// and the defect on P-3, so every stage reads its z-neighbours in the right colour state.
+// x-neighbours across lanes move by cross-lane shuffles, y-neighbours across the wave bands
+// through a double-buffered LDS exchange (one barrier per stage).  Tiles overlap by a halo of
+// `hx` cells (the stages' dependency radius, rounded up to even) and are recomputed, so tiles
+// are independent; results go to a separate output array (ping-pong), never in place.
+// Boundary ghosts are evaluated on the fly (Sec. 2.3.6) for cells on non-periodic faces.
 #include "mg_fused.h"
+
+#include <cstring>
+#include <type_traits>
+
+#include "mg_launch.h"
 
 namespace mg {
 
+namespace {
+
+constexpr int kRing = 5;
+constexpr int kLanes = 64;
+constexpr int kTileX = 2 * kLanes;
+
+struct FusedArgs {
+  const void* uin;
+  void* uout;
+  const void* f;
+  const void* ec;     // PRO: coarse correction (n/2)^3
+  void* fc;           // DEF: coarse source (n/2)^3
+  void* uc0;          // DEF: coarse correction to clear
+  double* part;       // NORM: one partial sum per block
+  LevelBC bc;         // this level
+  LevelBC bcc;        // PRO: coarse level (homogeneous)
+  int n, L, hx, xo, yo, zc, tiles_x, tiles_y, chunks_z, ntiles;
+  double h2, ih2, omega;
+};
+
 template <typename T>
-bool fused_supported(int) {
-  return false;
+__device__ __forceinline__ T shfl_from_left(T v) {   // value of lane-1 (lane 0 keeps its own)
+  return __shfl_up(v, 1, kLanes);
+}
+template <typename T>
+__device__ __forceinline__ T shfl_from_right(T v) {  // value of lane+1 (lane 63 keeps its own)
+  return __shfl_down(v, 1, kLanes);
 }
 
 template <typename T>
-void launch_fused_smooth(T*, const T*, int, double, double, int, const LevelBC&, hipStream_t) {}
-
-template <typename T>
-std::string fused_smooth_name(int, int) {
-  return "none";
+__device__ __forceinline__ T ghost_of(const LevelBC& bc, int face, int n, int t1, int t2, T c) {
+  if (bc.kind[face] == BC_ZERO_GRADIENT) return c;
+  return (T)(2.0 * face_b(bc, face, n, t1, t2)) - c;
 }
 
 template <typename T>
-double fused_smooth_bytes(int, int) {
-  return 0.0;
+__device__ __forceinline__ T coarse_at(const T* __restrict__ e, int nc, int Lc, int X, int Y, int Z,
+                                       const LevelBC& bcc) {
+  if ((unsigned)X < (unsigned)nc && (unsigned)Y < (unsigned)nc && (unsigned)Z < (unsigned)nc)
+    return e[cidx(Lc, X, Y, Z)];
+  return ghost_any(e, nc, Lc, X, Y, Z, bcc);
 }
 
-template bool fused_supported<double>(int);
-template bool fused_supported<float>(int);
-template void launch_fused_smooth<double>(double*, const double*, int, double, double, int, const LevelBC&, hipStream_t);
-template void launch_fused_smooth<float>(float*, const float*, int, double, double, int, const LevelBC&, hipStream_t);
-template std::string fused_smooth_name<double>(int, int);
-template std::string fused_smooth_name<float>(int, int);
-template double fused_smooth_bytes<double>(int, int);
-template double fused_smooth_bytes<float>(int, int);
+template <typename T>
+struct alignas(2 * sizeof(T)) Pair {
+  T a, b;
+};
+
+template <typename T, int R, int W, bool PRO, int OUT>
+__global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
+  constexpr int HZ = OUT ? 3 : 2;    // z planes loaded ahead of the chunk
+  __shared__ Pair<T> xch[2][W][2][kLanes];
+  // f of planes P-1, P-2, P-3 for this thread's cells: private per thread (f is only read at
+  // the cell itself), kept in LDS to leave the registers to the u ring
+  __shared__ Pair<T> fl[3][R][W * kLanes];
+
+  const int lane = threadIdx.x & (kLanes - 1);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int tid = threadIdx.x;
+  // XCD-aware order: consecutive block ids go to different XCDs, so give each XCD a
+  // contiguous run of tiles (neighbouring tiles then share that XCD's L2 for their halos).
+  const int nb = gridDim.x;
+  const int bid = blockIdx.x;
+  const int tile = (bid & 7) * (nb >> 3) + (bid >> 3);
+  double acc = 0.0;
+  if (tile < A.ntiles) {
+    const int tx = tile % A.tiles_x;
+    const int ty = (tile / A.tiles_x) % A.tiles_y;
+    const int cz = tile / (A.tiles_x * A.tiles_y);
+    const int n = A.n, L = A.L, nm = n - 1;
+    const T* __restrict__ uin = reinterpret_cast<const T*>(A.uin);
+    T* __restrict__ uout = reinterpret_cast<T*>(A.uout);
+    const T* __restrict__ fin = reinterpret_cast<const T*>(A.f);
+    const bool px = A.bc.kind[0] == BC_PERIODIC;
+    const bool py = A.bc.kind[2] == BC_PERIODIC;
+    const bool pz = A.bc.kind[4] == BC_PERIODIC;
+    const T h2 = (T)A.h2, ih2 = (T)A.ih2, omega = (T)A.omega;
+
+    const int xs = tx * A.xo;                     // first output column
+    const int xa = xs - A.hx + 2 * lane;          // this lane's even column
+    const bool in_x = px || (xa >= 0 && xa < n);
+    const int xag = xa & nm;
+    const bool out_x = xa >= xs && xa < xs + A.xo && xa < n;
+    const bool bnd_xl = !px && xa == 0;           // cell a on the -x face
+    const bool bnd_xr = !px && xa + 1 == nm;      // cell b on the +x face
+
+    const int ys = ty * A.yo;
+    int yv[R], ygv[R];
+    bool in_y[R], out_y[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int y = ys - A.hx + w * R + r;
+      yv[r] = y;
+      ygv[r] = y & nm;
+      in_y[r] = py || (y >= 0 && y < n);
+      out_y[r] = y >= ys && y < ys + A.yo && y < n;
+    }
+    const int z0 = cz * A.zc;
+    const int zend = min(z0 + A.zc, n);
+    const int zstart = z0 - HZ;
+    const int nsteps = (zend - z0) + 2 * HZ;
+    // does any cell of this wave touch a non-periodic face in x or y?
+    const bool wave_bnd_xy = (!px && (xs - A.hx <= 0 || xs - A.hx + kTileX - 1 >= nm)) ||
+                             (!py && (yv[0] <= 0 || yv[R - 1] >= nm));
+
+    // u: ring of kRing planes (slot = plane index mod kRing, compile-time after unrolling);
+    // f: LDS slots (plane mod 3) holding planes P-1, P-2, P-3.
+    T u[kRing][R][2];
+    T pu[R][2], pf[R][2];
+    T stash[R / 2 > 0 ? R / 2 : 1];
+#pragma unroll
+    for (int s = 0; s < kRing; ++s)
+#pragma unroll
+      for (int r = 0; r < R; ++r) u[s][r][0] = u[s][r][1] = (T)0;
+    auto fslot = [&](int p) __attribute__((always_inline)) { return ((p % 3) + 3) % 3; };
+    auto fget = [&](int p, int r, int q) __attribute__((always_inline)) {
+      const Pair<T> v = fl[fslot(p)][r][tid];
+      return q ? v.b : v.a;
+    };
+#pragma unroll
+    for (int q = 0; q < (R / 2 > 0 ? R / 2 : 1); ++q) stash[q] = (T)0;
+
+    // ---- load of u on plane P (with the prolonged coarse correction added) and f on P-1
+    auto load_plane = [&](int P) __attribute__((always_inline)) {
+      const bool in_z = pz || (P >= 0 && P < n);
+      const bool in_zf = pz || (P - 1 >= 0 && P - 1 < n);
+      const int Pg = P & nm, Pfg = (P - 1) & nm;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (in_x && in_y[r] && in_z) {
+          const size_t off = ((size_t)Pg << (2 * L)) + ((size_t)ygv[r] << L) + (size_t)xag;
+          const Pair<T> vu = *reinterpret_cast<const Pair<T>*>(uin + off);
+          pu[r][0] = vu.a; pu[r][1] = vu.b;
+        } else {
+          pu[r][0] = pu[r][1] = (T)0;
+        }
+        if (in_x && in_y[r] && in_zf) {
+          const size_t off = ((size_t)Pfg << (2 * L)) + ((size_t)ygv[r] << L) + (size_t)xag;
+          const Pair<T> vf = *reinterpret_cast<const Pair<T>*>(fin + off);
+          pf[r][0] = vf.a; pf[r][1] = vf.b;
+        } else {
+          pf[r][0] = pf[r][1] = (T)0;
+        }
+      }
+      if (PRO) {
+        const T* __restrict__ ec = reinterpret_cast<const T*>(A.ec);
+        const int nc = n >> 1, Lc = L - 1;
+        const int X = (px ? xag : xa) >> 1;
+        const int Pz = pz ? Pg : P;
+        const int Z = Pz >> 1;
+        const int zlo = (Pz & 1) ? Z : Z - 1;          // taps (zlo, zlo+1)
+        const T wz0 = (Pz & 1) ? (T)0.75 : (T)0.25, wz1 = (Pz & 1) ? (T)0.25 : (T)0.75;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int yy = py ? ygv[r] : yv[r];
+          const int Y = yy >> 1;
+          const int ylo = (yy & 1) ? Y : Y - 1;
+          const T wy0 = (yy & 1) ? (T)0.75 : (T)0.25, wy1 = (yy & 1) ? (T)0.25 : (T)0.75;
+          const T c00 = coarse_at(ec, nc, Lc, X, ylo, zlo, A.bcc);
+          const T c10 = coarse_at(ec, nc, Lc, X, ylo + 1, zlo, A.bcc);
+          const T c01 = coarse_at(ec, nc, Lc, X, ylo, zlo + 1, A.bcc);
+          const T c11 = coarse_at(ec, nc, Lc, X, ylo + 1, zlo + 1, A.bcc);
+          const T c = wz0 * (wy0 * c00 + wy1 * c10) + wz1 * (wy0 * c01 + wy1 * c11);
+          // the edge lanes 0 and 63 get their own value back: wrong, but within the halo
+          const T cl = shfl_from_left(c), cr = shfl_from_right(c);
+          if (in_x && in_y[r] && in_z) {
+            pu[r][0] += (T)0.25 * cl + (T)0.75 * c;
+            pu[r][1] += (T)0.75 * c + (T)0.25 * cr;
+          }
+        }
+      }
+    };
+
+    // ---- exchange of the band-edge rows of one plane between the wave bands
+    int xbuf = 0;
+    auto exchange = [&](const T (&pl)[R][2], T (&below)[2], T (&above)[2]) __attribute__((always_inline)) {
+      xch[xbuf][w][0][lane] = Pair<T>{pl[0][0], pl[0][1]};
+      xch[xbuf][w][1][lane] = Pair<T>{pl[R - 1][0], pl[R - 1][1]};
+      __syncthreads();
+      const Pair<T> vb = xch[xbuf][w > 0 ? w - 1 : w][1][lane];
+      const Pair<T> va = xch[xbuf][w < W - 1 ? w + 1 : w][0][lane];
+      below[0] = vb.a; below[1] = vb.b;
+      above[0] = va.a; above[1] = va.b;
+      xbuf ^= 1;
+    };
+
+    // ---- one colour of the RB-SOR update on plane p held in ring slots (s0; sm, sp)
+    auto half_sweep = [&](T (&pm)[R][2], T (&pc)[R][2], T (&pp)[R][2], int p,
+                          int colour) __attribute__((always_inline)) {
+      T below[2], above[2];
+      exchange(pc, below, above);
+      const bool in_z = pz || (p >= 0 && p < n);
+      const bool bnd_z0 = !pz && p == 0, bnd_z1 = !pz && p == nm;
+      // 0: the even column of row 0 has this colour (the same for every lane of the wave)
+      const int q0 = __builtin_amdgcn_readfirstlane((yv[0] + p + colour) & 1);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int q = (q0 + r) & 1;                  // wave-uniform
+        const T ca = pc[r][0], cb = pc[r][1];
+        const T c = q ? cb : ca;
+        // the cross-lane x neighbour: lane-1's odd column or lane+1's even column
+        const T xo_l = shfl_from_left(cb), xo_r = shfl_from_right(ca);
+        T xm = q ? ca : xo_l;
+        T xp = q ? xo_r : cb;
+        T ym = r > 0 ? (q ? pc[r - 1][1] : pc[r - 1][0]) : (q ? below[1] : below[0]);
+        T yp = r < R - 1 ? (q ? pc[r + 1][1] : pc[r + 1][0]) : (q ? above[1] : above[0]);
+        T zm = q ? pm[r][1] : pm[r][0];
+        T zp = q ? pp[r][1] : pp[r][0];
+        if ((wave_bnd_xy || bnd_z0 || bnd_z1) && in_x && in_y[r] && in_z) {
+          // face-array coordinates in [0, n): wrapped on periodic axes, in range otherwise
+          const int xw = xag + q, yw = ygv[r], pw = p & nm;
+          if (q == 0 && bnd_xl) xm = ghost_of(A.bc, 0, n, yw, pw, c);
+          if (q == 1 && bnd_xr) xp = ghost_of(A.bc, 1, n, yw, pw, c);
+          if (!py && yv[r] == 0) ym = ghost_of(A.bc, 2, n, xw, pw, c);
+          if (!py && yv[r] == nm) yp = ghost_of(A.bc, 3, n, xw, pw, c);
+          if (bnd_z0) zm = ghost_of(A.bc, 4, n, xw, yw, c);
+          if (bnd_z1) zp = ghost_of(A.bc, 5, n, xw, yw, c);
+        }
+        const T fv = fget(p, r, q);
+        const T nb = ((((xm + xp) + ym) + yp) + zm) + zp;
+        const T nv = c + omega * ((nb - h2 * fv) / (T)6 - c);
+        pc[r][0] = q ? ca : nv;
+        pc[r][1] = q ? nv : cb;
+      }
+    };
+
+    // ---- defect of both columns on plane p; restriction (DEF) or sum of squares (NORM)
+    auto defect_out = [&](T (&pm)[R][2], T (&pc)[R][2], T (&pp)[R][2], int p) __attribute__((always_inline)) {
+      T below[2], above[2];
+      exchange(pc, below, above);
+      const bool in_z = pz || (p >= 0 && p < n);
+      const bool bnd_z0 = !pz && p == 0, bnd_z1 = !pz && p == nm;
+      const bool out_z = p >= z0 && p < zend;
+      T d[R][2];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const T ca = pc[r][0], cb = pc[r][1];
+        const T la = shfl_from_left(cb), rb = shfl_from_right(ca);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const T c = q ? cb : ca;
+          T xm = q ? ca : la;
+          T xp = q ? rb : cb;
+          T ym = r > 0 ? pc[r - 1][q] : below[q];
+          T yp = r < R - 1 ? pc[r + 1][q] : above[q];
+          T zm = pm[r][q], zp = pp[r][q];
+          if ((wave_bnd_xy || bnd_z0 || bnd_z1) && in_x && in_y[r] && in_z) {
+            const int xw = xag + q, yw = ygv[r], pw = p & nm;
+            if (q == 0 && bnd_xl) xm = ghost_of(A.bc, 0, n, yw, pw, c);
+            if (q == 1 && bnd_xr) xp = ghost_of(A.bc, 1, n, yw, pw, c);
+            if (!py && yv[r] == 0) ym = ghost_of(A.bc, 2, n, xw, pw, c);
+            if (!py && yv[r] == nm) yp = ghost_of(A.bc, 3, n, xw, pw, c);
+            if (bnd_z0) zm = ghost_of(A.bc, 4, n, xw, yw, c);
+            if (bnd_z1) zp = ghost_of(A.bc, 5, n, xw, yw, c);
+          }
+          const T nb = ((((xm + xp) + ym) + yp) + zm) + zp;
+          d[r][q] = fget(p, r, q) - (nb - (T)6 * c) * ih2;
+        }
+      }
+      if (OUT == 2) {
+        if (out_z && out_x) {
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+            if (out_y[r]) acc += (double)d[r][0] * (double)d[r][0] + (double)d[r][1] * (double)d[r][1];
+        }
+      } else if (OUT == 1) {
+        T* __restrict__ fcp = reinterpret_cast<T*>(A.fc);
+        T* __restrict__ ucp = reinterpret_cast<T*>(A.uc0);
+        const int pg = pz ? (p & nm) : p;
+#pragma unroll
+        for (int q2 = 0; q2 < R / 2; ++q2) {
+          const T s = (d[2 * q2][0] + d[2 * q2][1]) + (d[2 * q2 + 1][0] + d[2 * q2 + 1][1]);
+          if ((pg & 1) == 0) {
+            stash[q2] = s;
+          } else if (out_z && out_x && out_y[2 * q2]) {
+            const int Lc = L - 1;
+            const size_t ci = cidx(Lc, xag >> 1, ygv[2 * q2] >> 1, pg >> 1);
+            fcp[ci] = (stash[q2] + s) * (T)0.125;
+            ucp[ci] = (T)0;
+          }
+        }
+      }
+    };
+
+    load_plane(zstart);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      u[0][r][0] = pu[r][0]; u[0][r][1] = pu[r][1];
+      fl[fslot(zstart - 1)][r][tid] = Pair<T>{pf[r][0], pf[r][1]};
+    }
+    // one pipeline step; K = t mod kRing is a compile-time constant so every ring slot is a
+    // fixed register set
+    auto step = [&](int g, auto kk) __attribute__((always_inline)) {
+      constexpr int k = decltype(kk)::value;
+      const int t = g + k;
+      if (t >= nsteps) return;
+      const int P = zstart + t;                  // plane held in slot k
+      if (t + 1 < nsteps) load_plane(P + 1);     // prefetch; consumed at the end of the step
+      constexpr int s1 = (k + kRing - 1) % kRing, s2 = (k + kRing - 2) % kRing;
+      constexpr int s3 = (k + kRing - 3) % kRing, s4 = (k + kRing - 4) % kRing;
+      // red on P-1 (neighbours P-2, P), black on P-2 (P-3, P-1), defect on P-3 (P-4, P-2)
+      half_sweep(u[s2], u[s1], u[k], P - 1, 0);
+      half_sweep(u[s3], u[s2], u[s1], P - 2, 1);
+      {
+        const int p = P - 2;
+        if (p >= z0 && p < zend && out_x) {
+          const int pg = p & nm;
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+            if (out_y[r]) {
+              const size_t off = ((size_t)pg << (2 * L)) + ((size_t)ygv[r] << L) + (size_t)xag;
+              *reinterpret_cast<Pair<T>*>(uout + off) = Pair<T>{u[s2][r][0], u[s2][r][1]};
+            }
+        }
+      }
+      if (OUT) defect_out(u[s4], u[s3], u[s2], P - 3);
+      if (t + 1 < nsteps) {
+        constexpr int sn = (k + 1) % kRing;
+        // f(P) replaces f(P-3), which this thread's defect stage has finished reading
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          u[sn][r][0] = pu[r][0]; u[sn][r][1] = pu[r][1];
+          fl[fslot(P)][r][tid] = Pair<T>{pf[r][0], pf[r][1]};
+        }
+      }
+    };
+    for (int g = 0; g < nsteps; g += kRing) {
+      step(g, std::integral_constant<int, 0>{});
+      step(g, std::integral_constant<int, 1>{});
+      step(g, std::integral_constant<int, 2>{});
+      step(g, std::integral_constant<int, 3>{});
+      step(g, std::integral_constant<int, 4>{});
+    }
+  }
+  if (OUT == 2) {
+    // the exchange buffer is free once every wave has left the march
+    double* red = reinterpret_cast<double*>(&xch[0][0][0][0]);
+    acc = wave_sum(acc);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int q = 0; q < W; ++q) s += red[q];
+      A.part[blockIdx.x] = s;
+    }
+  }
+}
+
+// Tile configuration per precision: R rows per lane, W waves per workgroup, z chunk.
+template <typename T>
+struct Cfg;
+template <>
+struct Cfg<double> {
+  static constexpr int R = 2, W = 16;
+};
+template <>
+struct Cfg<float> {
+  static constexpr int R = 2, W = 16;
+};
+
+int zchunk_for(int n) {
+  if (n >= 512) return 64;
+  if (n >= 256) return 32;
+  return 16;
+}
+
+template <typename T, bool PRO, int OUT>
+void launch_pass(FusedArgs A, hipStream_t s) {
+  constexpr int R = Cfg<T>::R, W = Cfg<T>::W;
+  A.xo = kTileX - 2 * A.hx;
+  A.yo = R * W - 2 * A.hx;
+  A.zc = min(zchunk_for(A.n), A.n);
+  A.tiles_x = (A.n + A.xo - 1) / A.xo;
+  A.tiles_y = (A.n + A.yo - 1) / A.yo;
+  A.chunks_z = (A.n + A.zc - 1) / A.zc;
+  A.ntiles = A.tiles_x * A.tiles_y * A.chunks_z;
+  const int grid = (A.ntiles + 7) / 8 * 8;
+  hipLaunchKernelGGL((k_fused<T, R, W, PRO, OUT>), dim3(grid), dim3(kLanes * W), 0, s, A);
+}
+
+template <typename T>
+FusedArgs base_args(const T* uin, T* uout, const T* f, int n, double h, double omega, const LevelBC& bc) {
+  FusedArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.uin = uin;
+  A.uout = uout;
+  A.f = f;
+  A.bc = bc;
+  A.n = n;
+  A.L = ilog2(n);
+  A.h2 = h * h;
+  A.ih2 = 1.0 / (h * h);
+  A.omega = omega;
+  return A;
+}
+
+}  // namespace
+
+template <typename T>
+bool fused_supported(int n) {
+  return n >= kFusedMinN;
+}
+
+template <typename T>
+void fused_sweep(const T* uin, T* uout, const T* f, int n, double h, double omega, const LevelBC& bc, hipStream_t s) {
+  FusedArgs A = base_args(uin, uout, f, n, h, omega, bc);
+  A.hx = 2;
+  launch_pass<T, false, 0>(A, s);
+}
+
+template <typename T>
+void fused_sweep_defect(const T* uin, T* uout, const T* f, T* fc, T* uc0, int n, double h, double omega,
+                        const LevelBC& bc, hipStream_t s) {
+  FusedArgs A = base_args(uin, uout, f, n, h, omega, bc);
+  A.hx = 4;
+  A.fc = fc;
+  A.uc0 = uc0;
+  launch_pass<T, false, 1>(A, s);
+}
+
+template <typename T>
+void fused_prolong_sweep(const T* uin, T* uout, const T* f, const T* ec, const LevelBC& bcc, int n, double h,
+                         double omega, const LevelBC& bc, hipStream_t s) {
+  FusedArgs A = base_args(uin, uout, f, n, h, omega, bc);
+  // the prolongation of an edge lane lacks one coarse column, so the dependency radius of
+  // this pass is 3 (2 for the sweep + 1); the halo is rounded up to even
+  A.hx = 4;
+  A.ec = ec;
+  A.bcc = bcc;
+  launch_pass<T, true, 0>(A, s);
+}
+
+template <typename T>
+int fused_grid_blocks(int n, int hx) {
+  constexpr int R = Cfg<T>::R, W = Cfg<T>::W;
+  const int xo = kTileX - 2 * hx, yo = R * W - 2 * hx, zc = min(zchunk_for(n), n);
+  const int nt = ((n + xo - 1) / xo) * ((n + yo - 1) / yo) * ((n + zc - 1) / zc);
+  return (nt + 7) / 8 * 8;
+}
+
+template <typename T>
+int fused_sweep_norm(const T* uin, T* uout, const T* f, double* part, int n, double h, double omega, const LevelBC& bc,
+                     hipStream_t s) {
+  FusedArgs A = base_args(uin, uout, f, n, h, omega, bc);
+  A.hx = 4;
+  A.part = part;
+  launch_pass<T, false, 2>(A, s);
+  return fused_grid_blocks<T>(n, 4);
+}
+
+template <typename T>
+std::string fused_pass_name(bool pro, int out) {
+  constexpr int R = Cfg<T>::R, W = Cfg<T>::W;
+  return std::string("k_fused<") + (sizeof(T) == 8 ? "double" : "float") + ", " + std::to_string(R) + ", " +
+         std::to_string(W) + ", " + (pro ? "true" : "false") + ", " + std::to_string(out) + ">";
+}
+
+#define MG_FUSED_INST(T)                                                                                        \
+  template bool fused_supported<T>(int);                                                                        \
+  template void fused_sweep<T>(const T*, T*, const T*, int, double, double, const LevelBC&, hipStream_t);        \
+  template void fused_sweep_defect<T>(const T*, T*, const T*, T*, T*, int, double, double, const LevelBC&,       \
+                                      hipStream_t);                                                             \
+  template void fused_prolong_sweep<T>(const T*, T*, const T*, const T*, const LevelBC&, int, double, double,    \
+                                       const LevelBC&, hipStream_t);                                            \
+  template int fused_sweep_norm<T>(const T*, T*, const T*, double*, int, double, double, const LevelBC&,         \
+                                   hipStream_t);                                                                \
+  template int fused_grid_blocks<T>(int, int);                                                                  \
+  template std::string fused_pass_name<T>(bool, int);
+
+MG_FUSED_INST(double)
+MG_FUSED_INST(float)
 
 }  // namespace mg

@@ -471,6 +471,10 @@ int reduce_blocks(size_t n3) {
   return (int)(b < 1 ? 1 : b);
 }
 
+void launch_sum_partials(const double* part, int np, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBlock), 0, s, part, np, 1, out, 1);
+}
+
 void launch_sum(const double* x, size_t n3, int what, double* part, double* out, hipStream_t s) {
   const int nb = reduce_blocks(n3);
   hipLaunchKernelGGL(k_sum_partials, dim3(nb), dim3(kBlock), 0, s, x, n3, what, part);

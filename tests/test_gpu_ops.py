@@ -188,3 +188,19 @@ def test_multipole_moments(mg, n):
     o2, q2 = mg.mg_multipole_moments(dev(rho), 1.0 / n, lmax=2, origin=(0.4, 0.5, 0.6))
     o2r, q2r = oracle.multipole_moments(rho, 1.0 / n, lmax=2, origin=np.array([0.4, 0.5, 0.6]))
     assert np.allclose(q2[:9], q2r[:9], rtol=1e-11, atol=1e-13 * abs(q2r[0])) and np.all(np.array(q2[9:]) == 0)
+
+
+@pytest.mark.parametrize("n", [64, 128, 256])
+@pytest.mark.parametrize("ks", range(len(KIND_SETS)))
+def test_prolong_then_one_sweep(mg, n, ks):
+    """The fused prolongation + sweep pass alone (npost = 1): correct at the tile seams, where
+    the outermost lanes of a tile lack a neighbouring coarse column."""
+    kinds = KIND_SETS[ks]
+    hom = [k if k in (PERIODIC, ZERO_GRADIENT) else FIXED for k in kinds]
+    u, f, bext = case(n, 900 + n + ks, kinds)
+    e = np.random.default_rng(n + ks).standard_normal((n // 2,) * 3)
+    h = 1.0 / n
+    ref = oracle.smooth(oracle.prolong_add(e, u, hom), f, h, 1.15, kinds, bext)
+    du = dev(u)
+    mg.mg_op_up(du, dev(f), dev(e), h, 1.15, 1, kinds, dbext(bext), kinds_coarse=hom)
+    assert close(host(du), ref, np.abs(ref).max())

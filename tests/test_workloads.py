@@ -25,8 +25,8 @@ def test_sphere_mass_by_volume_fraction():
     assert np.linalg.norm(c - 0.5) <= 0.05 + 1e-15
 
 
-def test_clumps_windowing_is_invisible():
-    """Windowed evaluation equals the full-grid sum of the clumps to round-off."""
+def test_clumps_match_direct_sum():
+    """The matrix-product evaluation equals the clump-by-clump sum to round-off."""
     n = 32
     rho = wl.gaussian_clumps(n, 8, n_clumps=4, remove_mean=False)
     rng = np.random.default_rng(8)
