@@ -120,6 +120,8 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy 1 GiB device to device (reference for profiler byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -137,6 +139,14 @@ def main() -> int:
     rho = torch.from_numpy(rho_h).to("cuda:0")
     del rho_h
     print(f"# input {n}^3 generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("# calibration copy: 1073741824 bytes read, 1073741824 bytes written", file=sys.stderr, flush=True)
+        del src, dst
 
     ctx = mg.Context(0)
     ctx.set_kernel_timing(True)

@@ -40,7 +40,7 @@ int fused_sweep_norm(const T* uin, T* uout, const T* f, double* part, int n, dou
                      const LevelBC& bc, hipStream_t s);
 
 template <typename T>
-int fused_grid_blocks(int n, int hx);
+int fused_grid_blocks(int n, int hx, int hy);
 
 // Names of the pass kernels as the profiler lists them.
 template <typename T>

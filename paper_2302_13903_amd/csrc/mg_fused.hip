@@ -13,7 +13,7 @@
 // z over a chunk of planes.  Each cell keeps a ring of RING planes of u and f in registers:
 // at the step that loads plane P, the red update runs on plane P-1, the black update on P-2
 // and the defect on P-3, so every stage reads its z-neighbours in the right colour state.
-// x-neighbours across lanes move by cross-lane shuffles, y-neighbours across the wave bands
+// x-neighbours across lanes move by DPP wave shifts, y-neighbours across the wave bands
 // through a double-buffered LDS exchange (one barrier per stage).  Tiles overlap by a halo of
 // `hx` cells (the stages' dependency radius, rounded up to even) and are recomputed, so tiles
 // are independent; results go to a separate output array (ping-pong), never in place.
@@ -29,7 +29,6 @@ namespace mg {
 
 namespace {
 
-constexpr int kRing = 5;
 constexpr int kLanes = 64;
 constexpr int kTileX = 2 * kLanes;
 
@@ -43,17 +42,36 @@ struct FusedArgs {
   double* part;       // NORM: one partial sum per block
   LevelBC bc;         // this level
   LevelBC bcc;        // PRO: coarse level (homogeneous)
-  int n, L, hx, xo, yo, zc, tiles_x, tiles_y, chunks_z, ntiles;
+  int n, L, hx, hy, xo, yo, zc, tiles_x, tiles_y, chunks_z, ntiles;
   double h2, ih2, omega;
 };
 
+// Whole-wave shift by one lane through DPP (register-speed cross-lane move): wave_shr:1 gives
+// lane i the value of lane i-1, wave_shl:1 the value of lane i+1; lanes without a source
+// keep their own value.
+constexpr int kDppWaveShr1 = 0x138;
+constexpr int kDppWaveShl1 = 0x130;
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+  const int i = __builtin_bit_cast(int, v);
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(i, i, CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = (int)(b & 0xffffffffLL), hi = (int)(b >> 32);
+  const int lo2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
+  const int hi2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((long long)hi2 << 32) | (long long)(unsigned)lo2);
+}
 template <typename T>
 __device__ __forceinline__ T shfl_from_left(T v) {   // value of lane-1 (lane 0 keeps its own)
-  return __shfl_up(v, 1, kLanes);
+  return dpp_move<kDppWaveShr1>(v);
 }
 template <typename T>
 __device__ __forceinline__ T shfl_from_right(T v) {  // value of lane+1 (lane 63 keeps its own)
-  return __shfl_down(v, 1, kLanes);
+  return dpp_move<kDppWaveShl1>(v);
 }
 
 template <typename T>
@@ -78,6 +96,7 @@ struct alignas(2 * sizeof(T)) Pair {
 template <typename T, int R, int W, bool PRO, int OUT>
 __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
   constexpr int HZ = OUT ? 3 : 2;    // z planes loaded ahead of the chunk
+  constexpr int kRing = OUT ? 5 : 4; // u planes alive: P .. P-3 (and P-4 for the defect stage)
   __shared__ Pair<T> xch[2][W][2][kLanes];
   // f of planes P-1, P-2, P-3 for this thread's cells: private per thread (f is only read at
   // the cell itself), kept in LDS to leave the registers to the u ring
@@ -104,6 +123,7 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
     const bool py = A.bc.kind[2] == BC_PERIODIC;
     const bool pz = A.bc.kind[4] == BC_PERIODIC;
     const T h2 = (T)A.h2, ih2 = (T)A.ih2, omega = (T)A.omega;
+    const T inv6 = (T)(1.0 / 6.0);
 
     const int xs = tx * A.xo;                     // first output column
     const int xa = xs - A.hx + 2 * lane;          // this lane's even column
@@ -118,7 +138,7 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
     bool in_y[R], out_y[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int y = ys - A.hx + w * R + r;
+      const int y = ys - A.hy + w * R + r;
       yv[r] = y;
       ygv[r] = y & nm;
       in_y[r] = py || (y >= 0 && y < n);
@@ -172,6 +192,9 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
         }
       }
       if (PRO) {
+        // Trilinear prolongation (weights 1/4, 3/4 per axis) of the coarse correction.  Rows
+        // come in aligned pairs (2Y, 2Y+1) sharing coarse rows Y-1, Y, Y+1; the lane's coarse
+        // column X is interpolated in y and z, and its x-neighbours come from lanes -+1.
         const T* __restrict__ ec = reinterpret_cast<const T*>(A.ec);
         const int nc = n >> 1, Lc = L - 1;
         const int X = (px ? xag : xa) >> 1;
@@ -180,21 +203,23 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
         const int zlo = (Pz & 1) ? Z : Z - 1;          // taps (zlo, zlo+1)
         const T wz0 = (Pz & 1) ? (T)0.75 : (T)0.25, wz1 = (Pz & 1) ? (T)0.25 : (T)0.75;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const int yy = py ? ygv[r] : yv[r];
-          const int Y = yy >> 1;
-          const int ylo = (yy & 1) ? Y : Y - 1;
-          const T wy0 = (yy & 1) ? (T)0.75 : (T)0.25, wy1 = (yy & 1) ? (T)0.25 : (T)0.75;
-          const T c00 = coarse_at(ec, nc, Lc, X, ylo, zlo, A.bcc);
-          const T c10 = coarse_at(ec, nc, Lc, X, ylo + 1, zlo, A.bcc);
-          const T c01 = coarse_at(ec, nc, Lc, X, ylo, zlo + 1, A.bcc);
-          const T c11 = coarse_at(ec, nc, Lc, X, ylo + 1, zlo + 1, A.bcc);
-          const T c = wz0 * (wy0 * c00 + wy1 * c10) + wz1 * (wy0 * c01 + wy1 * c11);
-          // the edge lanes 0 and 63 get their own value back: wrong, but within the halo
-          const T cl = shfl_from_left(c), cr = shfl_from_right(c);
-          if (in_x && in_y[r] && in_z) {
-            pu[r][0] += (T)0.25 * cl + (T)0.75 * c;
-            pu[r][1] += (T)0.75 * c + (T)0.25 * cr;
+        for (int q2 = 0; q2 < R / 2; ++q2) {
+          const int Y = (py ? ygv[2 * q2] : yv[2 * q2]) >> 1;   // the pair's coarse row
+          T cz[3];
+#pragma unroll
+          for (int dy = 0; dy < 3; ++dy)
+            cz[dy] = wz0 * coarse_at(ec, nc, Lc, X, Y - 1 + dy, zlo, A.bcc) +
+                     wz1 * coarse_at(ec, nc, Lc, X, Y - 1 + dy, zlo + 1, A.bcc);
+#pragma unroll
+          for (int rr = 0; rr < 2; ++rr) {
+            const int r = 2 * q2 + rr;
+            const T c = rr ? (T)0.75 * cz[1] + (T)0.25 * cz[2] : (T)0.25 * cz[0] + (T)0.75 * cz[1];
+            // the edge lanes 0 and 63 get their own value back: wrong, but within the halo
+            const T cl = shfl_from_left(c), cr = shfl_from_right(c);
+            if (in_x && in_y[r] && in_z) {
+              pu[r][0] += (T)0.25 * cl + (T)0.75 * c;
+              pu[r][1] += (T)0.75 * c + (T)0.25 * cr;
+            }
           }
         }
       }
@@ -213,7 +238,8 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
       xbuf ^= 1;
     };
 
-    // ---- one colour of the RB-SOR update on plane p held in ring slots (s0; sm, sp)
+    // ---- one colour of the RB-SOR update (eqs. rbsor1-2) on plane p held in pc, its
+    // z-neighbour planes in pm (p-1) and pp (p+1)
     auto half_sweep = [&](T (&pm)[R][2], T (&pc)[R][2], T (&pp)[R][2], int p,
                           int colour) __attribute__((always_inline)) {
       T below[2], above[2];
@@ -246,8 +272,8 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
           if (bnd_z1) zp = ghost_of(A.bc, 5, n, xw, yw, c);
         }
         const T fv = fget(p, r, q);
-        const T nb = ((((xm + xp) + ym) + yp) + zm) + zp;
-        const T nv = c + omega * ((nb - h2 * fv) / (T)6 - c);
+        const T nbs = ((((xm + xp) + ym) + yp) + zm) + zp;
+        const T nv = c + omega * ((nbs - h2 * fv) * inv6 - c);
         pc[r][0] = q ? ca : nv;
         pc[r][1] = q ? nv : cb;
       }
@@ -260,9 +286,8 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
       const bool in_z = pz || (p >= 0 && p < n);
       const bool bnd_z0 = !pz && p == 0, bnd_z1 = !pz && p == nm;
       const bool out_z = p >= z0 && p < zend;
-      T d[R][2];
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
+      // defect of both columns of row r (eq. defect)
+      auto row_defect = [&](int r, T (&d)[2]) __attribute__((always_inline)) {
         const T ca = pc[r][0], cb = pc[r][1];
         const T la = shfl_from_left(cb), rb = shfl_from_right(ca);
 #pragma unroll
@@ -282,15 +307,16 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
             if (bnd_z0) zm = ghost_of(A.bc, 4, n, xw, yw, c);
             if (bnd_z1) zp = ghost_of(A.bc, 5, n, xw, yw, c);
           }
-          const T nb = ((((xm + xp) + ym) + yp) + zm) + zp;
-          d[r][q] = fget(p, r, q) - (nb - (T)6 * c) * ih2;
+          const T nbs = ((((xm + xp) + ym) + yp) + zm) + zp;
+          d[q] = fget(p, r, q) - (nbs - (T)6 * c) * ih2;
         }
-      }
+      };
       if (OUT == 2) {
-        if (out_z && out_x) {
 #pragma unroll
-          for (int r = 0; r < R; ++r)
-            if (out_y[r]) acc += (double)d[r][0] * (double)d[r][0] + (double)d[r][1] * (double)d[r][1];
+        for (int r = 0; r < R; ++r) {
+          T d[2];
+          row_defect(r, d);
+          if (out_z && out_x && out_y[r]) acc += (double)d[0] * (double)d[0] + (double)d[1] * (double)d[1];
         }
       } else if (OUT == 1) {
         T* __restrict__ fcp = reinterpret_cast<T*>(A.fc);
@@ -298,7 +324,10 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
         const int pg = pz ? (p & nm) : p;
 #pragma unroll
         for (int q2 = 0; q2 < R / 2; ++q2) {
-          const T s = (d[2 * q2][0] + d[2 * q2][1]) + (d[2 * q2 + 1][0] + d[2 * q2 + 1][1]);
+          T d0[2], d1[2];
+          row_defect(2 * q2, d0);
+          row_defect(2 * q2 + 1, d1);
+          const T s = (d0[0] + d0[1]) + (d1[0] + d1[1]);
           if ((pg & 1) == 0) {
             stash[q2] = s;
           } else if (out_z && out_x && out_y[2 * q2]) {
@@ -326,7 +355,7 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
       const int P = zstart + t;                  // plane held in slot k
       if (t + 1 < nsteps) load_plane(P + 1);     // prefetch; consumed at the end of the step
       constexpr int s1 = (k + kRing - 1) % kRing, s2 = (k + kRing - 2) % kRing;
-      constexpr int s3 = (k + kRing - 3) % kRing, s4 = (k + kRing - 4) % kRing;
+      constexpr int s3 = (k + kRing - 3) % kRing, s4 = (k + 2 * kRing - 4) % kRing;
       // red on P-1 (neighbours P-2, P), black on P-2 (P-3, P-1), defect on P-3 (P-4, P-2)
       half_sweep(u[s2], u[s1], u[k], P - 1, 0);
       half_sweep(u[s3], u[s2], u[s1], P - 2, 1);
@@ -358,7 +387,7 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
       step(g, std::integral_constant<int, 1>{});
       step(g, std::integral_constant<int, 2>{});
       step(g, std::integral_constant<int, 3>{});
-      step(g, std::integral_constant<int, 4>{});
+      if (kRing > 4) step(g, std::integral_constant<int, 4 % kRing>{});
     }
   }
   if (OUT == 2) {
@@ -376,16 +405,17 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
   }
 }
 
-// Tile configuration per precision: R rows per lane, W waves per workgroup, z chunk.
-template <typename T>
-struct Cfg;
-template <>
-struct Cfg<double> {
+// Tile configuration per precision and pass kind: R rows per lane, W waves per workgroup
+// (tile 128 x R*W).  The restricted-defect pass keeps one more plane and the most temporaries
+// live, so in FP64 it runs fewer, wider lanes (R = 4) to stay within the register file
+// (measured faster than R = 2 for that pass, slower for the others).
+template <typename T, int OUT>
+struct Cfg {
   static constexpr int R = 2, W = 16;
 };
 template <>
-struct Cfg<float> {
-  static constexpr int R = 2, W = 16;
+struct Cfg<double, 1> {
+  static constexpr int R = 4, W = 8;
 };
 
 int zchunk_for(int n) {
@@ -396,9 +426,9 @@ int zchunk_for(int n) {
 
 template <typename T, bool PRO, int OUT>
 void launch_pass(FusedArgs A, hipStream_t s) {
-  constexpr int R = Cfg<T>::R, W = Cfg<T>::W;
+  constexpr int R = Cfg<T, OUT>::R, W = Cfg<T, OUT>::W;
   A.xo = kTileX - 2 * A.hx;
-  A.yo = R * W - 2 * A.hx;
+  A.yo = R * W - 2 * A.hy;
   A.zc = min(zchunk_for(A.n), A.n);
   A.tiles_x = (A.n + A.xo - 1) / A.xo;
   A.tiles_y = (A.n + A.yo - 1) / A.yo;
@@ -434,7 +464,8 @@ bool fused_supported(int n) {
 template <typename T>
 void fused_sweep(const T* uin, T* uout, const T* f, int n, double h, double omega, const LevelBC& bc, hipStream_t s) {
   FusedArgs A = base_args(uin, uout, f, n, h, omega, bc);
-  A.hx = 2;
+  A.hx = 2;   // dependency radius of one sweep
+  A.hy = 2;
   launch_pass<T, false, 0>(A, s);
 }
 
@@ -442,7 +473,8 @@ template <typename T>
 void fused_sweep_defect(const T* uin, T* uout, const T* f, T* fc, T* uc0, int n, double h, double omega,
                         const LevelBC& bc, hipStream_t s) {
   FusedArgs A = base_args(uin, uout, f, n, h, omega, bc);
-  A.hx = 4;
+  A.hx = 4;   // sweep (2) + defect (1), rounded up to even: restriction pairs align
+  A.hy = 4;
   A.fc = fc;
   A.uc0 = uc0;
   launch_pass<T, false, 1>(A, s);
@@ -455,15 +487,16 @@ void fused_prolong_sweep(const T* uin, T* uout, const T* f, const T* ec, const L
   // the prolongation of an edge lane lacks one coarse column, so the dependency radius of
   // this pass is 3 (2 for the sweep + 1); the halo is rounded up to even
   A.hx = 4;
+  A.hy = 2;   // along y a row's prolongation needs no other row
   A.ec = ec;
   A.bcc = bcc;
   launch_pass<T, true, 0>(A, s);
 }
 
 template <typename T>
-int fused_grid_blocks(int n, int hx) {
-  constexpr int R = Cfg<T>::R, W = Cfg<T>::W;
-  const int xo = kTileX - 2 * hx, yo = R * W - 2 * hx, zc = min(zchunk_for(n), n);
+int fused_grid_blocks(int n, int hx, int hy) {
+  constexpr int R = Cfg<T, 2>::R, W = Cfg<T, 2>::W;   // the norm pass's tiling
+  const int xo = kTileX - 2 * hx, yo = R * W - 2 * hy, zc = min(zchunk_for(n), n);
   const int nt = ((n + xo - 1) / xo) * ((n + yo - 1) / yo) * ((n + zc - 1) / zc);
   return (nt + 7) / 8 * 8;
 }
@@ -472,15 +505,17 @@ template <typename T>
 int fused_sweep_norm(const T* uin, T* uout, const T* f, double* part, int n, double h, double omega, const LevelBC& bc,
                      hipStream_t s) {
   FusedArgs A = base_args(uin, uout, f, n, h, omega, bc);
-  A.hx = 4;
+  A.hx = 4;   // sweep (2) + defect (1); even in x so lane pairs start on even columns
+  A.hy = 3;
   A.part = part;
   launch_pass<T, false, 2>(A, s);
-  return fused_grid_blocks<T>(n, 4);
+  return fused_grid_blocks<T>(n, 4, 3);
 }
 
 template <typename T>
 std::string fused_pass_name(bool pro, int out) {
-  constexpr int R = Cfg<T>::R, W = Cfg<T>::W;
+  const int R = out == 1 ? Cfg<T, 1>::R : out == 2 ? Cfg<T, 2>::R : Cfg<T, 0>::R;
+  const int W = out == 1 ? Cfg<T, 1>::W : out == 2 ? Cfg<T, 2>::W : Cfg<T, 0>::W;
   return std::string("k_fused<") + (sizeof(T) == 8 ? "double" : "float") + ", " + std::to_string(R) + ", " +
          std::to_string(W) + ", " + (pro ? "true" : "false") + ", " + std::to_string(out) + ">";
 }
@@ -494,7 +529,7 @@ std::string fused_pass_name(bool pro, int out) {
                                        const LevelBC&, hipStream_t);                                            \
   template int fused_sweep_norm<T>(const T*, T*, const T*, double*, int, double, double, const LevelBC&,         \
                                    hipStream_t);                                                                \
-  template int fused_grid_blocks<T>(int, int);                                                                  \
+  template int fused_grid_blocks<T>(int, int, int);                                                             \
   template std::string fused_pass_name<T>(bool, int);
 
 MG_FUSED_INST(double)

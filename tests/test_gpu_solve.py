@@ -39,12 +39,22 @@ def run_both(mg, rho, kinds, faces=None, cycles=6, **kw):
     return ref, np.asarray(rh), phi.cpu().numpy(), np.asarray(hist), st
 
 
-def hist_close(h_gpu, h_ref):
-    """Residual histories agree elementwise: 1e-6 relative plus an absolute 1e-13, the size of
-    the round-off noise in a relative residual (FMA contraction and summation order differ)."""
+def residual_floor(phi, rho, gauge_free=True):
+    """Round-off floor of the relative residual RMS(f - L phi)/RMS(f): each defect carries an
+    error of about eps * 12 max|phi| / h^2 (seven terms of size |phi|/h^2)."""
+    n = phi.shape[0]
+    f = 4 * math.pi * rho
+    if gauge_free:
+        f = f - f.mean()
+    return 12 * np.finfo(float).eps * np.abs(phi).max() * n * n / math.sqrt(np.mean(f * f))
+
+
+def hist_close(h_gpu, h_ref, floor=1e-13):
+    """Residual histories agree elementwise: 1e-6 relative plus ten times the round-off floor
+    of the relative residual (FMA contraction and summation order differ between the sides)."""
     assert len(h_gpu) == len(h_ref)
     for a, b in zip(h_gpu, h_ref):
-        assert abs(a - b) <= 1e-6 * b + 1e-13, (h_gpu, h_ref)
+        assert abs(a - b) <= 1e-6 * b + 10 * floor, (h_gpu, h_ref, floor)
 
 
 @pytest.mark.parametrize("n", [2, 4, 16, 32, 64])
@@ -56,7 +66,7 @@ def test_c1_sine_modes(mg, n):
     ref, rh, got, gh, st = run_both(mg, rho, "periodic", cycles=6)
     assert st == mg.MG_OK
     assert rel(got, ref) < 1e-10
-    hist_close(gh, rh)
+    hist_close(gh, rh, residual_floor(ref, rho))
 
 
 @pytest.mark.parametrize("kinds", [
@@ -72,7 +82,7 @@ def test_boundary_kinds(mg, kinds, n):
     faces = [rng.standard_normal((n, n)) * 0.1 if k == FIXED else None for k in kinds]
     ref, rh, got, gh, st = run_both(mg, rho, kinds, faces, cycles=8)
     assert rel(got, ref) < 1e-10, rel(got, ref)
-    hist_close(gh, rh)
+    hist_close(gh, rh, residual_floor(ref, rho, all(k in (PERIODIC, ZERO_GRADIENT) for k in kinds)))
 
 
 @pytest.mark.parametrize("n", [16, 64])
@@ -80,7 +90,7 @@ def test_multipole_sphere(mg, n):
     rho, c = wl.uniform_sphere(n, 2)
     ref, rh, got, gh, st = run_both(mg, rho, [MULTIPOLE] * 6, cycles=8, lmax=4)
     assert rel(got, ref) < 1e-10
-    hist_close(gh, rh)
+    hist_close(gh, rh, residual_floor(ref, rho, False))
 
 
 def test_tol_stop_matches_oracle(mg):
@@ -100,7 +110,7 @@ def test_mgi_mode(mg):
     ref, rh, _ = oracle.solve(rho, 1.0 / n, "periodic", mode="mgi", phi0=guess, fixed_cycles=5)
     phi, hist, st = mg.solve(dev(rho), 1.0 / n, "periodic", mode="mgi", phi=dev(guess), fixed_cycles=5)
     assert rel(phi.cpu().numpy(), ref) < 1e-10
-    hist_close(np.asarray(hist), rh)
+    hist_close(np.asarray(hist), rh, residual_floor(ref, rho))
 
 
 @pytest.mark.parametrize("kinds", ["periodic", "fixed"])
