@@ -83,6 +83,7 @@ struct Layout {
   size_t u64[16], f64[16];     // FP64 levels 0..L-1 (FP64 mode)
   size_t u32[16], f32[16];     // FP32 levels 0..L (mixed mode)
   size_t u2[16];               // second (ping-pong) buffer of the levels swept by fused passes
+  size_t phi2 = (size_t)-1;    // mixed mode: ping-pong partner of the caller's FP64 phi
   size_t faces[16];            // 6 extended face arrays per level
   size_t total = 0;
 };
@@ -98,6 +99,7 @@ Layout make_layout(int n, int precision) {
     return o;
   };
   y.f64L = take(cells(y.L) * 8);
+  if (y.mixed && n >= kFusedMinN) y.phi2 = take(cells(y.L) * 8);
   for (int l = 0; l <= y.L; ++l) {
     y.u64[l] = y.f64[l] = y.u32[l] = y.f32[l] = 0;
     if (!y.mixed && l < y.L) {
@@ -583,6 +585,8 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
   }
   int status = p->fixed_cycles > 0 ? MG_OK : MG_NOT_CONVERGED;
   int slow = 0, done_cycles = 0;
+  double* phi_cur = phi;     // mixed mode alternates phi with its ping-pong partner
+  double* phi_oth = y.phi2 == (size_t)-1 ? nullptr : reinterpret_cast<double*>(c->ws + y.phi2);
   if (p->fixed_cycles > 0 || r > p->tol) {
     for (int cyc = 0; cyc < ncyc; ++cyc) {
       if (!mixed) {
@@ -596,8 +600,16 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
           HIP_CHECK(c, hipMemsetAsync(H32.u[L], 0, n3 * sizeof(float), s));
           S.vcycle(H32, L, hom, true, false);
         }
-        launch_add_f32(phi, H32.u[L], n3, s);
-        launch_defect_norm(phi, f64L, H32.f[L], p->n, p->dx, phys[L], c->part, c->scal + 2, s);
+        if (phi_oth) {
+          // phi += e and the FP64 defect (with its FP32 copy and norm) in one streaming pass
+          const int np = fused_mixed_update_defect(phi_cur, phi_oth, H32.u[L], f64L, H32.f[L], c->part, p->n, p->dx,
+                                                   phys[L], s);
+          launch_sum_partials(c->part, np, c->scal + 2, s);
+          std::swap(phi_cur, phi_oth);
+        } else {
+          launch_add_f32(phi, H32.u[L], n3, s);
+          launch_defect_norm(phi, f64L, H32.f[L], p->n, p->dx, phys[L], c->part, c->scal + 2, s);
+        }
       }
       HIP_CHECK(c, hipEventRecord(c->ev_cycle[cyc], s));
       HIP_CHECK(c, hipMemcpyAsync(c->hscal + 2, c->scal + 2, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -615,6 +627,7 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
     status = MG_OK;
   }
   *n_hist = nh;
+  if (phi_cur != phi) HIP_CHECK(c, hipMemcpyAsync(phi, phi_cur, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
 
   // ---- gauge (Sec. 2.3.6): zero mean potential when no face fixes the zero point
   if (gauge_free) {

@@ -39,6 +39,12 @@ template <typename T>
 int fused_sweep_norm(const T* uin, T* uout, const T* f, double* part, int n, double h, double omega,
                      const LevelBC& bc, hipStream_t s);
 
+// Mixed precision, FP64 part of one defect-correction step: phi_out = phi_in + e (e FP32),
+// then the defect f - L phi_out, its FP32 copy r32 and one partial sum of squares per block;
+// returns the number of partials.
+int fused_mixed_update_defect(double* phi_in, double* phi_out, const float* e, const double* f, float* r32,
+                              double* part, int n, double h, const LevelBC& bc, hipStream_t s);
+
 template <typename T>
 int fused_grid_blocks(int n, int hx, int hy);
 

@@ -40,6 +40,8 @@ struct FusedArgs {
   void* fc;           // DEF: coarse source (n/2)^3
   void* uc0;          // DEF: coarse correction to clear
   double* part;       // NORM: one partial sum per block
+  const float* e32;   // MIX: FP32 correction added to u on load
+  float* r32;         // MIX: FP32 copy of the defect
   LevelBC bc;         // this level
   LevelBC bcc;        // PRO: coarse level (homogeneous)
   int n, L, hx, hy, xo, yo, zc, tiles_x, tiles_y, chunks_z, ntiles;
@@ -93,10 +95,14 @@ struct alignas(2 * sizeof(T)) Pair {
   T a, b;
 };
 
-template <typename T, int R, int W, bool PRO, int OUT>
+// MIX (no sweep, OUT = 2): u = u + e32 on load, then the defect of the updated u, its sum of
+// squares and its FP32 copy -- the FP64 part of one mixed-precision defect-correction step.
+template <typename T, int R, int W, bool PRO, int OUT, bool MIX = false>
 __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
-  constexpr int HZ = OUT ? 3 : 2;    // z planes loaded ahead of the chunk
-  constexpr int kRing = OUT ? 5 : 4; // u planes alive: P .. P-3 (and P-4 for the defect stage)
+  constexpr bool SWEEP = !MIX;
+  constexpr int DLAG = SWEEP ? 3 : 1;                  // the defect runs on plane P - DLAG
+  constexpr int HZ = OUT ? DLAG : 2;                   // z planes loaded ahead of the chunk
+  constexpr int kRing = OUT ? DLAG + 2 : 4;            // u planes alive
   __shared__ Pair<T> xch[2][W][2][kLanes];
   // f of planes P-1, P-2, P-3 for this thread's cells: private per thread (f is only read at
   // the cell itself), kept in LDS to leave the registers to the u ring
@@ -180,6 +186,11 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
           const size_t off = ((size_t)Pg << (2 * L)) + ((size_t)ygv[r] << L) + (size_t)xag;
           const Pair<T> vu = *reinterpret_cast<const Pair<T>*>(uin + off);
           pu[r][0] = vu.a; pu[r][1] = vu.b;
+          if (MIX) {
+            const float2 ve = *reinterpret_cast<const float2*>(A.e32 + off);
+            pu[r][0] += (T)ve.x;
+            pu[r][1] += (T)ve.y;
+          }
         } else {
           pu[r][0] = pu[r][1] = (T)0;
         }
@@ -316,7 +327,13 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
         for (int r = 0; r < R; ++r) {
           T d[2];
           row_defect(r, d);
-          if (out_z && out_x && out_y[r]) acc += (double)d[0] * (double)d[0] + (double)d[1] * (double)d[1];
+          if (out_z && out_x && out_y[r]) {
+            acc += (double)d[0] * (double)d[0] + (double)d[1] * (double)d[1];
+            if (MIX) {
+              const size_t off = ((size_t)(p & nm) << (2 * L)) + ((size_t)ygv[r] << L) + (size_t)xag;
+              *reinterpret_cast<float2*>(A.r32 + off) = make_float2((float)d[0], (float)d[1]);
+            }
+          }
         }
       } else if (OUT == 1) {
         T* __restrict__ fcp = reinterpret_cast<T*>(A.fc);
@@ -355,23 +372,30 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
       const int P = zstart + t;                  // plane held in slot k
       if (t + 1 < nsteps) load_plane(P + 1);     // prefetch; consumed at the end of the step
       constexpr int s1 = (k + kRing - 1) % kRing, s2 = (k + kRing - 2) % kRing;
-      constexpr int s3 = (k + kRing - 3) % kRing, s4 = (k + 2 * kRing - 4) % kRing;
-      // red on P-1 (neighbours P-2, P), black on P-2 (P-3, P-1), defect on P-3 (P-4, P-2)
-      half_sweep(u[s2], u[s1], u[k], P - 1, 0);
-      half_sweep(u[s3], u[s2], u[s1], P - 2, 1);
+      constexpr int s3 = (k + 2 * kRing - 3) % kRing, s4 = (k + 2 * kRing - 4) % kRing;
+      // red on P-1 (neighbours P-2, P), black on P-2 (P-3, P-1), defect on P-3 (P-4, P-2);
+      // without the sweep the (updated) plane P is final at once and the defect runs on P-1
+      if (SWEEP) {
+        half_sweep(u[s2], u[s1], u[k], P - 1, 0);
+        half_sweep(u[s3], u[s2], u[s1], P - 2, 1);
+      }
       {
-        const int p = P - 2;
+        constexpr int sf = SWEEP ? s2 : k;     // slot of the plane that is final this step
+        const int p = SWEEP ? P - 2 : P;
         if (p >= z0 && p < zend && out_x) {
           const int pg = p & nm;
 #pragma unroll
           for (int r = 0; r < R; ++r)
             if (out_y[r]) {
               const size_t off = ((size_t)pg << (2 * L)) + ((size_t)ygv[r] << L) + (size_t)xag;
-              *reinterpret_cast<Pair<T>*>(uout + off) = Pair<T>{u[s2][r][0], u[s2][r][1]};
+              *reinterpret_cast<Pair<T>*>(uout + off) = Pair<T>{u[sf][r][0], u[sf][r][1]};
             }
         }
       }
-      if (OUT) defect_out(u[s4], u[s3], u[s2], P - 3);
+      if (OUT) {
+        if (SWEEP) defect_out(u[s4], u[s3], u[s2], P - 3);
+        else defect_out(u[s2], u[s1], u[k], P - 1);
+      }
       if (t + 1 < nsteps) {
         constexpr int sn = (k + 1) % kRing;
         // f(P) replaces f(P-3), which this thread's defect stage has finished reading
@@ -386,7 +410,7 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
       step(g, std::integral_constant<int, 0>{});
       step(g, std::integral_constant<int, 1>{});
       step(g, std::integral_constant<int, 2>{});
-      step(g, std::integral_constant<int, 3>{});
+      if (kRing > 3) step(g, std::integral_constant<int, 3 % kRing>{});
       if (kRing > 4) step(g, std::integral_constant<int, 4 % kRing>{});
     }
   }
@@ -424,7 +448,7 @@ int zchunk_for(int n) {
   return 16;
 }
 
-template <typename T, bool PRO, int OUT>
+template <typename T, bool PRO, int OUT, bool MIX = false>
 void launch_pass(FusedArgs A, hipStream_t s) {
   constexpr int R = Cfg<T, OUT>::R, W = Cfg<T, OUT>::W;
   A.xo = kTileX - 2 * A.hx;
@@ -435,7 +459,7 @@ void launch_pass(FusedArgs A, hipStream_t s) {
   A.chunks_z = (A.n + A.zc - 1) / A.zc;
   A.ntiles = A.tiles_x * A.tiles_y * A.chunks_z;
   const int grid = (A.ntiles + 7) / 8 * 8;
-  hipLaunchKernelGGL((k_fused<T, R, W, PRO, OUT>), dim3(grid), dim3(kLanes * W), 0, s, A);
+  hipLaunchKernelGGL((k_fused<T, R, W, PRO, OUT, MIX>), dim3(grid), dim3(kLanes * W), 0, s, A);
 }
 
 template <typename T>
@@ -510,6 +534,18 @@ int fused_sweep_norm(const T* uin, T* uout, const T* f, double* part, int n, dou
   A.part = part;
   launch_pass<T, false, 2>(A, s);
   return fused_grid_blocks<T>(n, 4, 3);
+}
+
+int fused_mixed_update_defect(double* phi_in, double* phi_out, const float* e, const double* f, float* r32,
+                              double* part, int n, double h, const LevelBC& bc, hipStream_t s) {
+  FusedArgs A = base_args<double>(phi_in, phi_out, f, n, h, 1.0, bc);
+  A.hx = 2;   // defect only: radius 1, rounded up to even
+  A.hy = 1;
+  A.part = part;
+  A.e32 = e;
+  A.r32 = r32;
+  launch_pass<double, false, 2, true>(A, s);
+  return fused_grid_blocks<double>(n, 2, 1);
 }
 
 template <typename T>

@@ -37,8 +37,9 @@ def test_footprint_model():
     assert 19.2 < fp64 / 512 ** 3 < 19.7
     p.precision = _abi.MG_PREC_MIXED
     mixed = lib.mg_footprint_bytes(ctypes.byref(p))
-    # FP64 source + FP32 (e, r, ping-pong e) on all levels: about 8 + 12 * 8/7 bytes per cell
-    assert 21.5 < mixed / 512 ** 3 < 22.0
+    # FP64 source + FP64 ping-pong phi + FP32 (e, r, ping-pong e) on all levels:
+    # about 16 + 12 * 8/7 bytes per finest cell
+    assert 29.5 < mixed / 512 ** 3 < 30.0
 
 
 def test_binding_has_the_abi_names():

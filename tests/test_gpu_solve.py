@@ -113,14 +113,13 @@ def test_mgi_mode(mg):
     hist_close(np.asarray(hist), rh, residual_floor(ref, rho))
 
 
-@pytest.mark.parametrize("kinds", ["periodic", "fixed"])
-def test_mixed_precision_reaches_fp64(mg, kinds):
+@pytest.mark.parametrize("kinds,n", [("periodic", 64), ("fixed", 64), ("periodic", 128), ("multipole", 128)])
+def test_mixed_precision_reaches_fp64(mg, kinds, n):
     """FP32 inner V-cycles inside FP64 defect correction reach the FP64 accuracy: phi agrees
     with the oracle converged to its floor, within 1e-10 relative."""
-    n = 64
-    if kinds == "fixed":
+    if kinds in ("fixed", "multipole"):
         rho, c = wl.uniform_sphere(n, 1)
-        faces = wl.sphere_face_values(n, c, 0.25, rho.sum() / n ** 3)
+        faces = wl.sphere_face_values(n, c, 0.25, rho.sum() / n ** 3) if kinds == "fixed" else None
     else:
         rho, faces = wl.gaussian_clumps(n, 2), None
     ref, rh, _ = oracle.solve(rho, 1.0 / n, kinds, fixed_b=faces, tol=1e-13, max_cycles=40)
