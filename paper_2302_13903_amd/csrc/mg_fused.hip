@@ -553,7 +553,7 @@ std::string fused_pass_name(bool pro, int out) {
   const int R = out == 1 ? Cfg<T, 1>::R : out == 2 ? Cfg<T, 2>::R : Cfg<T, 0>::R;
   const int W = out == 1 ? Cfg<T, 1>::W : out == 2 ? Cfg<T, 2>::W : Cfg<T, 0>::W;
   return std::string("k_fused<") + (sizeof(T) == 8 ? "double" : "float") + ", " + std::to_string(R) + ", " +
-         std::to_string(W) + ", " + (pro ? "true" : "false") + ", " + std::to_string(out) + ">";
+         std::to_string(W) + ", " + (pro ? "true" : "false") + ", " + std::to_string(out) + ", false>";
 }
 
 #define MG_FUSED_INST(T)                                                                                        \

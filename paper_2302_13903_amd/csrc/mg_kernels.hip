@@ -34,7 +34,7 @@ __global__ void __launch_bounds__(kBlock) k_half_sweep(T* __restrict__ u, const 
   const size_t c = cidx(L, i, j, k);
   const T uc = u[c];
   const T nb = neighbour_sum(u, n, L, i, j, k, c, uc, bc);
-  u[c] = uc + omega * ((nb - h2 * f[c]) / (T)6 - uc);
+  u[c] = uc + omega * ((nb - h2 * f[c]) * (T)(1.0 / 6.0) - uc);
 }
 
 template <typename T>
@@ -137,45 +137,67 @@ void launch_restrict(const Tin* uf, Tout* uc, int nc, hipStream_t s) {
 
 // cubic = 0: uf += trilinear(uc) (eq. trilinear, Alg. 1 steps 5-6);
 // cubic = 1: uf  = tricubic(uc)  (FMG prolongation, Alg. 2 step 3).
-// One work item per fine cell; the 3x3x3 coarse neighbourhood uses ghost_any() near faces.
+// One work item per coarse cell: it gathers the 3x3x3 coarse neighbourhood once (ghost_any()
+// near faces) and writes its 8 children as four 2-cell row segments.
 template <typename T, int CUBIC>
 __global__ void __launch_bounds__(kBlock) k_prolong(const T* __restrict__ uc, T* __restrict__ uf, int Lc,
                                                      LevelBC bcc) {
-  const int nc = 1 << Lc, L = Lc + 1, n = 2 * nc;
-  const size_t c = (size_t)blockIdx.x * kBlock + threadIdx.x;
-  if (c >= ((size_t)1 << (3 * L))) return;
-  const int i = (int)(c & (size_t)(n - 1));
-  const int j = (int)((c >> L) & (size_t)(n - 1));
-  const int k = (int)(c >> (2 * L));
-  const int I = i >> 1, J = j >> 1, K = k >> 1;
-  T wx[3], wy[3], wz[3];
-  if (CUBIC) { cub_w(i & 1, wx); cub_w(j & 1, wy); cub_w(k & 1, wz); }
-  else { lin_w(i & 1, wx); lin_w(j & 1, wy); lin_w(k & 1, wz); }
+  const int nc = 1 << Lc, L = Lc + 1;
+  const size_t C = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (C >= ((size_t)1 << (3 * Lc))) return;
+  const int I = (int)(C & (size_t)(nc - 1));
+  const int J = (int)((C >> Lc) & (size_t)(nc - 1));
+  const int K = (int)(C >> (2 * Lc));
   const bool inner = I > 0 && I < nc - 1 && J > 0 && J < nc - 1 && K > 0 && K < nc - 1;
-  T s = (T)0;
+  T v[3][3][3];
 #pragma unroll
-  for (int cz = -1; cz <= 1; ++cz) {
-    if (!CUBIC && wz[cz + 1] == (T)0) continue;
+  for (int cz = 0; cz < 3; ++cz)
 #pragma unroll
-    for (int by = -1; by <= 1; ++by) {
-      if (!CUBIC && wy[by + 1] == (T)0) continue;
+    for (int by = 0; by < 3; ++by)
 #pragma unroll
-      for (int ax = -1; ax <= 1; ++ax) {
-        if (!CUBIC && wx[ax + 1] == (T)0) continue;
-        const T w = wx[ax + 1] * wy[by + 1] * wz[cz + 1];
-        const T v = inner ? uc[cidx(Lc, I + ax, J + by, K + cz)] : ghost_any(uc, nc, Lc, I + ax, J + by, K + cz, bcc);
-        s += w * v;
+      for (int ax = 0; ax < 3; ++ax)
+        v[cz][by][ax] = inner ? uc[cidx(Lc, I + ax - 1, J + by - 1, K + cz - 1)]
+                              : ghost_any(uc, nc, Lc, I + ax - 1, J + by - 1, K + cz - 1, bcc);
+#pragma unroll
+  for (int zc = 0; zc < 2; ++zc)
+#pragma unroll
+    for (int yc = 0; yc < 2; ++yc) {
+      T wz[3], wy[3];
+      if (CUBIC) { cub_w<T>(zc, wz); cub_w<T>(yc, wy); }
+      else { lin_w<T>(zc, wz); lin_w<T>(yc, wy); }
+      T out[2];
+#pragma unroll
+      for (int xc = 0; xc < 2; ++xc) {
+        T wx[3];
+        if (CUBIC) cub_w<T>(xc, wx);
+        else lin_w<T>(xc, wx);
+        T acc = (T)0;
+#pragma unroll
+        for (int cz = 0; cz < 3; ++cz)
+#pragma unroll
+          for (int by = 0; by < 3; ++by)
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+              if (!CUBIC && (wx[ax] == (T)0 || wy[by] == (T)0 || wz[cz] == (T)0)) continue;
+              acc += (wx[ax] * wy[by] * wz[cz]) * v[cz][by][ax];
+            }
+        out[xc] = acc;
+      }
+      const size_t f0 = cidx(L, 2 * I, 2 * J + yc, 2 * K + zc);
+      if (CUBIC) {
+        uf[f0] = out[0];
+        uf[f0 + 1] = out[1];
+      } else {
+        uf[f0] += out[0];
+        uf[f0 + 1] += out[1];
       }
     }
-  }
-  if (CUBIC) uf[c] = s;
-  else uf[c] += s;
 }
 
 template <typename T>
 void launch_prolong(const T* uc, T* uf, int nc, const LevelBC& bcc, int cubic, hipStream_t s) {
   const int Lc = ilog2(nc);
-  const dim3 g(grid_for((size_t)1 << (3 * (Lc + 1))));
+  const dim3 g(grid_for((size_t)1 << (3 * Lc)));
   if (cubic) hipLaunchKernelGGL((k_prolong<T, 1>), g, dim3(kBlock), 0, s, uc, uf, Lc, bcc);
   else hipLaunchKernelGGL((k_prolong<T, 0>), g, dim3(kBlock), 0, s, uc, uf, Lc, bcc);
 }
@@ -211,13 +233,14 @@ void launch_coarsest(T* u, const T* f, double h, const LevelBC& bc, hipStream_t 
 // mode bits: TAIL_FMG runs Alg. 2 on levels 0..T with the physical description of each level
 // and writes u_T; otherwise one V-cycle (Alg. 1) at level T with bc_top (u_T loaded from
 // global when TAIL_LOAD_U, else started from zero) and homogeneous descriptions below.
-constexpr int kTailThreads = 512;
+constexpr int kTailThreads = 1024;
 
-template <typename T>
-struct TailLDS {
-  T* u[5];
-  T* f[5];
-};
+// Start of level l within the LDS arrays (levels 0..top stored back to back).
+__host__ __device__ constexpr int level_offset(int l) {
+  int o = 0;
+  for (int q = 0; q < l; ++q) o += 1 << (3 * q);
+  return o;
+}
 
 template <typename T>
 __device__ __forceinline__ T lds_nb(const T* u, int n, int L, int i, int j, int k, T uc, const LevelBC& bc) {
@@ -225,16 +248,21 @@ __device__ __forceinline__ T lds_nb(const T* u, int n, int L, int i, int j, int 
   return neighbour_sum(u, n, L, i, j, k, c, uc, bc);
 }
 
+// One smoothing sweep on an LDS-resident level: work items enumerate only the cells of the
+// current colour (the x-pair index p picks the pair's cell of that colour), so no lane idles.
 template <typename T>
 __device__ void tail_smooth(T* u, const T* f, int L, T h2, T omega, const LevelBC& bc) {
-  const int n = 1 << L, n3 = 1 << (3 * L);
+  const int n = 1 << L;
+  const T inv6 = (T)(1.0 / 6.0);
+  const int half = 1 << (3 * L - 1);
   for (int colour = 0; colour < 2; ++colour) {
-    for (int c = threadIdx.x; c < n3; c += blockDim.x) {
-      const int i = c & (n - 1), j = (c >> L) & (n - 1), k = c >> (2 * L);
-      if (((i + j + k) & 1) != colour) continue;
+    for (int t = threadIdx.x; t < half; t += blockDim.x) {
+      const int p = t & ((n >> 1) - 1), j = (t >> (L - 1)) & (n - 1), k = t >> (2 * L - 1);
+      const int i = 2 * p + ((j + k + colour) & 1);
+      const int c = (int)cidx(L, i, j, k);
       const T uc = u[c];
       const T nb = lds_nb(u, n, L, i, j, k, uc, bc);
-      u[c] = uc + omega * ((nb - h2 * f[c]) / (T)6 - uc);
+      u[c] = uc + omega * ((nb - h2 * f[c]) * inv6 - uc);
     }
     __syncthreads();
   }
@@ -266,16 +294,20 @@ __device__ void tail_prolong(const T* uc, T* uf, int L, const LevelBC& bcc) {
   for (int c = threadIdx.x; c < n3; c += blockDim.x) {
     const int i = c & (n - 1), j = (c >> L) & (n - 1), k = c >> (2 * L);
     const int I = i >> 1, J = j >> 1, K = k >> 1;
+    const bool inner = I > 0 && I < nc - 1 && J > 0 && J < nc - 1 && K > 0 && K < nc - 1;
     T wx[3], wy[3], wz[3];
     if (CUBIC) { cub_w(i & 1, wx); cub_w(j & 1, wy); cub_w(k & 1, wz); }
     else { lin_w(i & 1, wx); lin_w(j & 1, wy); lin_w(k & 1, wz); }
     T s = (T)0;
+#pragma unroll
     for (int cz = -1; cz <= 1; ++cz)
+#pragma unroll
       for (int by = -1; by <= 1; ++by)
+#pragma unroll
         for (int ax = -1; ax <= 1; ++ax) {
           const T w = wx[ax + 1] * wy[by + 1] * wz[cz + 1];
           if (w == (T)0) continue;
-          s += w * ghost_any(uc, nc, Lc, I + ax, J + by, K + cz, bcc);
+          s += w * (inner ? uc[cidx(Lc, I + ax, J + by, K + cz)] : ghost_any(uc, nc, Lc, I + ax, J + by, K + cz, bcc));
         }
     if (CUBIC) uf[c] = s;
     else uf[c] += s;
@@ -283,23 +315,36 @@ __device__ void tail_prolong(const T* uc, T* uf, int L, const LevelBC& bcc) {
   __syncthreads();
 }
 
-// V-cycle from level top down to 0 and back, with bc_top on level `top` and `hom` below.
+// Per-launch metadata copied to LDS once, so per-level lookups with a runtime level index
+// read LDS instead of spilling the argument block to private memory.
+struct TailMeta {
+  LevelBC phys[5];
+  LevelBC top;   // description of the top level in V-cycle mode
+  LevelBC hom;
+  double h2[5];
+};
+
+// V-cycle from level `topl` down to 0 and back, with bc_top on level topl and the
+// homogeneous description below.
 template <typename T>
-__device__ void tail_vcycle(TailLDS<T>& s, int top, const TailArgs& a, const LevelBC& bc_top) {
-  const T omega = (T)a.omega;
-  for (int l = top; l >= 1; --l) {
-    const LevelBC& bc = l == top ? bc_top : a.hom;
-    const T h2 = (T)(a.h[l] * a.h[l]);
-    for (int it = 0; it < a.npre; ++it) tail_smooth(s.u[l], s.f[l], l, h2, omega, bc);
-    tail_defect_restrict(s.u[l], s.f[l], s.f[l - 1], s.u[l - 1], l, (T)(1.0 / (a.h[l] * a.h[l])), bc);
+__device__ void tail_vcycle(T* base, int total, int topl, const TailMeta& m, const LevelBC& bc_top, int npre,
+                            int npost, T omega) {
+  for (int l = topl; l >= 1; --l) {
+    const LevelBC& bc = l == topl ? bc_top : m.hom;
+    T* u = base + level_offset(l);
+    T* f = base + total + level_offset(l);
+    const T h2 = (T)m.h2[l];
+    for (int it = 0; it < npre; ++it) tail_smooth(u, f, l, h2, omega, bc);
+    tail_defect_restrict(u, f, base + total + level_offset(l - 1), base + level_offset(l - 1), l, (T)(1.0 / m.h2[l]),
+                         bc);
   }
-  if (threadIdx.x == 0) s.u[0][0] = coarsest_value(s.f[0][0], (T)(a.h[0] * a.h[0]), top == 0 ? bc_top : a.hom);
+  if (threadIdx.x == 0) base[0] = coarsest_value(base[total], (T)m.h2[0], topl == 0 ? bc_top : m.hom);
   __syncthreads();
-  for (int l = 1; l <= top; ++l) {
-    const LevelBC& bc = l == top ? bc_top : a.hom;
-    const T h2 = (T)(a.h[l] * a.h[l]);
-    tail_prolong<T, 0>(s.u[l - 1], s.u[l], l, a.hom);
-    for (int it = 0; it < a.npost; ++it) tail_smooth(s.u[l], s.f[l], l, h2, omega, bc);
+  for (int l = 1; l <= topl; ++l) {
+    const LevelBC& bc = l == topl ? bc_top : m.hom;
+    T* u = base + level_offset(l);
+    tail_prolong<T, 0>(base + level_offset(l - 1), u, l, m.hom);
+    for (int it = 0; it < npost; ++it) tail_smooth(u, base + total + level_offset(l), l, (T)m.h2[l], omega, bc);
   }
 }
 
@@ -308,49 +353,57 @@ __global__ void __launch_bounds__(kTailThreads) k_tail(TailArgs a) {
   const T* const* fg = reinterpret_cast<const T* const*>(a.fg);
   T* ug = reinterpret_cast<T*>(a.ug);
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ TailMeta m;
   T* base = reinterpret_cast<T*>(smem_raw);
-  TailLDS<T> s;
-  int off = 0;
-  for (int l = 0; l <= a.top; ++l) {
-    const int n3 = 1 << (3 * l);
-    s.u[l] = base + off;
-    s.f[l] = base + off + a.total;
-    off += n3;
+  const int total = a.total, top = a.top;
+  if (threadIdx.x == 0) {
+    for (int l = 0; l < 5; ++l) {
+      m.phys[l] = a.phys[l];
+      m.h2[l] = a.h[l] * a.h[l];
+    }
+    m.top = a.bc_top;
+    m.hom = a.hom;
   }
-  const int top = a.top;
+  __syncthreads();
   const int ntop = 1 << (3 * top);
+  const T omega = (T)a.omega;
   if (a.mode & TAIL_FMG) {
     for (int l = 0; l <= top; ++l) {
       const int n3 = 1 << (3 * l);
-      for (int c = threadIdx.x; c < n3; c += blockDim.x) s.f[l][c] = fg[l][c];
+      const T* src = fg[l];
+      T* dst = base + total + level_offset(l);
+      for (int c = threadIdx.x; c < n3; c += blockDim.x) dst[c] = src[c];
     }
     __syncthreads();
-    if (threadIdx.x == 0) s.u[0][0] = coarsest_value(s.f[0][0], (T)(a.h[0] * a.h[0]), a.phys[0]);
+    if (threadIdx.x == 0) base[0] = coarsest_value(base[total], (T)m.h2[0], m.phys[0]);
     __syncthreads();
+    // Alg. 2: tricubic prolongation, then one V-cycle with the level's own physical
+    // description; the V-cycle on level l overwrites the sources below with restricted
+    // defects, which FMG no longer needs (it proceeds upwards).
     for (int l = 1; l <= top; ++l) {
-      tail_prolong<T, 1>(s.u[l - 1], s.u[l], l, a.phys[l - 1]);
-      // The V-cycle on level l overwrites the source of level l-1 and below with restricted
-      // defects; FMG has finished with them (it proceeds upwards).
-      tail_vcycle(s, l, a, a.phys[l]);
+      tail_prolong<T, 1>(base + level_offset(l - 1), base + level_offset(l), l, m.phys[l - 1]);
+      tail_vcycle(base, total, l, m, m.phys[l], a.npre, a.npost, omega);
     }
   } else {
+    T* u = base + level_offset(top);
+    T* f = base + total + level_offset(top);
+    const T* src = fg[top];
     for (int c = threadIdx.x; c < ntop; c += blockDim.x) {
-      s.f[top][c] = fg[top][c];
-      s.u[top][c] = (a.mode & TAIL_LOAD_U) ? ug[c] : (T)0;
+      f[c] = src[c];
+      u[c] = (a.mode & TAIL_LOAD_U) ? ug[c] : (T)0;
     }
     __syncthreads();
-    tail_vcycle(s, top, a, a.bc_top);
+    tail_vcycle(base, total, top, m, m.top, a.npre, a.npost, omega);
   }
-  for (int c = threadIdx.x; c < ntop; c += blockDim.x) ug[c] = s.u[top][c];
+  const T* u = base + level_offset(top);
+  for (int c = threadIdx.x; c < ntop; c += blockDim.x) ug[c] = u[c];
 }
 
 template <typename T>
 void launch_tail(const TailArgs& a, hipStream_t s) {
-  size_t total = 0;
-  for (int l = 0; l <= a.top; ++l) total += (size_t)1 << (3 * l);
   TailArgs b = a;
-  b.total = (int)total;
-  const size_t lds = 2 * total * sizeof(T);
+  b.total = level_offset(a.top + 1);
+  const size_t lds = 2 * (size_t)b.total * sizeof(T);
   hipLaunchKernelGGL(k_tail<T>, dim3(1), dim3(kTailThreads), lds, s, b);
 }
 
