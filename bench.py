@@ -13,6 +13,8 @@ in HBM.  The JSON line reports:
                 its mean launch time (HIP events on the solve stream) against 8 TB/s;
   cpu_baseline  the CPU oracle timed on a bounded sample of the same workload;
   mixed         the same numbers for the mixed-precision solve; p50/p99 solve latency.
+  serving       a mixed-size request stream through the serving runtime: saturated
+                throughput and p50/p99 latency at 0.5 and 0.9 of it, FP64 and mixed.
 
 python bench.py [--steps K] [--warmup W] [--n N] [--no-cpu-baseline] [--no-mixed]
 """
@@ -110,6 +112,44 @@ def cpu_baseline(n: int, cycles: int = 3):
                       f"{dt * 1e3:.0f} ms per cycle"}
 
 
+def serving_leg(n_requests: int, workers: int, seed: int):
+    """Mixed-size request stream (sizes 64-512, periodic / fixed / multipole faces, Poisson
+    arrivals) through the native serving runtime: first all requests at once (saturated
+    throughput mu), then open-loop at 0.5 mu and 0.9 mu; FP64 and mixed precision."""
+    import torch
+
+    import workloads as wl
+    from paper_2302_13903_amd import serving
+    sizes = (64, 128, 256, 512)
+    pool = {n: [torch.from_numpy(wl.gaussian_clumps(n, seed + 17 * k + n, remove_mean=False)).to("cuda:0")
+                for k in range(2)] for n in sizes}
+    srv = serving.Server(workers=workers)
+    out = {"workers": workers, "requests": n_requests, "sizes": list(sizes),
+           "bcs": ["periodic", "fixed", "multipole"], "tol": 1e-10}
+    for prec in ("fp64", "mixed"):
+        def reqs(rate):
+            tr = wl.serving_trace(n_requests, seed, rate if rate else 1.0, sizes=sizes)
+            return [serving.Request(rho=pool[t["n"]][t["seed"] % 2], bc=t["bc"], precision=prec,
+                                    arrival_ms=t["t"] if rate else 0.0) for t in tr]
+        srv.run([serving.Request(rho=pool[n][k % 2], bc="multipole", precision=prec)
+                 for n in sizes for k in range(workers)])  # warm-up: resident hierarchies
+        res = {}
+        sat = serving.summary(srv.run(reqs(None)))
+        res["saturated"] = sat
+        mu = sat["solves_per_s"] / 1e3  # requests per ms
+        for frac in (0.5, 0.9):
+            r = srv.run(reqs(frac * mu))
+            bad = [q.status for q in r if q.status != 0]
+            if bad:
+                raise RuntimeError(f"serving: {len(bad)} requests failed: {bad[:5]}")
+            res[f"rate_{frac}"] = serving.summary(r)
+        out[prec] = res
+        print(f"# serving {prec}: saturated {sat['solves_per_s']:.1f} solves/s, "
+              f"p99 at 0.9 mu {res['rate_0.9']['latency_ms']['p99']:.1f} ms", file=sys.stderr, flush=True)
+    out["hierarchies"] = srv.stats()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,6 +160,9 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=240,
+                    help="requests per serving run (0: skip the serving leg)")
+    ap.add_argument("--serve-workers", type=int, default=4)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device to device (reference for profiler byte counters)")
     args = ap.parse_args()
@@ -201,6 +244,8 @@ def main() -> int:
                         "ms_per_step": statistics.mean(lat_m), "cycles_per_solve": len(hists_m[-1]) - 1,
                         "cycle_ms_median": tvm,
                         "solve_latency_ms": {"p50": pct(lat_m, 0.5), "p99": pct(lat_m, 0.99)}}
+    if args.serve_requests > 0:
+        out["serving"] = serving_leg(args.serve_requests, args.serve_workers, args.seed)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n)
     print(json.dumps(out), flush=True)

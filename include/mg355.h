@@ -107,6 +107,11 @@ const char *mg_last_error(const mg_ctx *ctx);
  * boundary arrays, reduction scratch); 0 for invalid parameters.  Used for admission. */
 size_t mg_footprint_bytes(const mg_params *p);
 
+/* Size the context's workspace for solves with these parameters now (one allocation), so
+ * that later solves of the same or smaller size allocate nothing.  MG_ERR_OOM when the
+ * device cannot hold it (the previous workspace is then released). */
+int mg_ctx_reserve(mg_ctx *ctx, const mg_params *p);
+
 /* Full solve (Sec. 2.3.7, Alg. 1, Alg. 2).
  *   rho   device, n^3 FP64, read only.
  *   phi   device, n^3 FP64; output (and the initial guess when mode = MG_MODE_MGI).
@@ -182,6 +187,80 @@ int mg_op_down(mg_ctx *ctx, int n, double h, double omega, int npre, const mg_le
 int mg_op_up(mg_ctx *ctx, int n, double h, double omega, int npost, const mg_level_bc *bc,
              const mg_level_bc *bc_coarse, double *u, const double *f, const double *uc,
              void *stream);
+
+/* ---- serving runtime ---------------------------------------------------------------
+ *
+ * A request stream of independent solves (different sizes, boundary kinds and precisions)
+ * on one device.  `workers` host threads each drive one HIP stream of default priority, so
+ * solves overlap on the device.  Admission is by HBM footprint: a request starts only when
+ * its hierarchy (mg_footprint_bytes + one n^3 FP64 result slot) fits in `hbm_budget` next to
+ * the hierarchies in use.  Hierarchies stay resident after a solve and are reused by the next
+ * request of the same (n, precision); idle hierarchies of other sizes are released
+ * (least recently used first) only when a new one would not fit.  Every kernel of a solve is
+ * deterministic, so a request's phi and history do not depend on what runs beside it. */
+
+typedef struct mg_server mg_server;
+
+typedef struct {
+  int device;           /* HIP device                                                      */
+  int workers;          /* host threads = concurrent solves, 1..64                         */
+  size_t hbm_budget;    /* bytes for resident hierarchies; 0 = 80 % of the free memory     */
+  int policy;           /* MG_SERVE_FIFO: strict arrival order; MG_SERVE_SKIP: a later
+                           request that fits may start while the head waits for memory     */
+  int simulate;         /* 1: no device work; a request occupies its worker for sim_ms
+                           (tests of the scheduler without a GPU)                          */
+} mg_server_config;
+
+#define MG_SERVE_FIFO 0
+#define MG_SERVE_SKIP 1
+
+typedef struct {
+  /* in */
+  mg_params params;
+  mg_bc bc;
+  const double *rho;    /* device, n^3; read only                                          */
+  double *phi;          /* device, n^3 output, or NULL: written to the hierarchy's result
+                           slot and discarded (MG_MODE_MGI needs phi)                      */
+  double arrival_ms;    /* submission time, ms after the start of mg_server_run            */
+  double sim_ms;        /* simulate mode: service time                                     */
+  int hist_cap;         /* capacity of hist (0: no history returned)                       */
+  double *hist;         /* host, hist_cap entries, or NULL                                 */
+  /* out */
+  int status;           /* mg_solve's return value; MG_ERR_OOM if it can never fit         */
+  int n_hist;
+  double resid;         /* last relative residual                                          */
+  double admit_ms;      /* picked by a worker (memory granted)                             */
+  double start_ms;      /* hierarchy ready, solve enqueued                                 */
+  double end_ms;        /* solve complete (result in phi)                                  */
+  int worker;
+  int reused;           /* 1 if a resident hierarchy was reused                            */
+} mg_request;
+
+typedef struct {
+  int created;          /* hierarchies allocated                                           */
+  int reused;           /* requests served by a resident hierarchy                         */
+  int evicted;          /* idle hierarchies released to make room                          */
+  int rejected;         /* requests larger than the whole budget                           */
+  int max_concurrent;   /* most solves in flight at once                                   */
+  size_t resident_bytes;  /* bytes held by hierarchies now                                 */
+  size_t peak_bytes;    /* most bytes held at once                                         */
+} mg_server_stats;
+
+int mg_server_create(mg_server **srv, const mg_server_config *cfg);
+void mg_server_destroy(mg_server *srv);
+const char *mg_server_last_error(const mg_server *srv);
+
+/* Allocate `count` resident hierarchies for requests like p (warm-up), within the budget. */
+int mg_server_reserve(mg_server *srv, const mg_params *p, int count);
+
+/* Serve `n` requests (host array): each is submitted at its arrival_ms (open loop; 0 for
+ * all = closed batch), scheduled by the policy and solved on a worker's stream.  Blocks
+ * until every request is complete; outputs are written into the array.  Per-request errors
+ * are in reqs[i].status; the return value is MG_OK unless the run itself failed. */
+int mg_server_run(mg_server *srv, mg_request *reqs, int n);
+
+/* Counters since mg_server_create. */
+int mg_server_get_stats(const mg_server *srv, mg_server_stats *out);
 
 #ifdef __cplusplus
 }

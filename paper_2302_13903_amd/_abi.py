@@ -40,6 +40,28 @@ class MgLevelBC(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int * 6), ("b", ctypes.c_void_p * 6)]
 
 
+MG_SERVE_FIFO, MG_SERVE_SKIP = 0, 1
+
+
+class MgServerConfig(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("workers", ctypes.c_int), ("hbm_budget", ctypes.c_size_t),
+                ("policy", ctypes.c_int), ("simulate", ctypes.c_int)]
+
+
+class MgRequest(ctypes.Structure):
+    _fields_ = [("params", MgParams), ("bc", MgBC), ("rho", ctypes.c_void_p), ("phi", ctypes.c_void_p),
+                ("arrival_ms", ctypes.c_double), ("sim_ms", ctypes.c_double), ("hist_cap", ctypes.c_int),
+                ("hist", ctypes.POINTER(ctypes.c_double)), ("status", ctypes.c_int), ("n_hist", ctypes.c_int),
+                ("resid", ctypes.c_double), ("admit_ms", ctypes.c_double), ("start_ms", ctypes.c_double),
+                ("end_ms", ctypes.c_double), ("worker", ctypes.c_int), ("reused", ctypes.c_int)]
+
+
+class MgServerStats(ctypes.Structure):
+    _fields_ = [("created", ctypes.c_int), ("reused", ctypes.c_int), ("evicted", ctypes.c_int),
+                ("rejected", ctypes.c_int), ("max_concurrent", ctypes.c_int), ("resident_bytes", ctypes.c_size_t),
+                ("peak_bytes", ctypes.c_size_t)]
+
+
 _lib = None
 _vp = ctypes.c_void_p
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -66,6 +88,13 @@ def lib():
         "mg_ctx_destroy": (None, [_vp]),
         "mg_last_error": (ctypes.c_char_p, [_vp]),
         "mg_footprint_bytes": (ctypes.c_size_t, [ctypes.POINTER(MgParams)]),
+        "mg_ctx_reserve": (i, [_vp, ctypes.POINTER(MgParams)]),
+        "mg_server_create": (i, [ctypes.POINTER(_vp), ctypes.POINTER(MgServerConfig)]),
+        "mg_server_destroy": (None, [_vp]),
+        "mg_server_last_error": (ctypes.c_char_p, [_vp]),
+        "mg_server_reserve": (i, [_vp, ctypes.POINTER(MgParams), i]),
+        "mg_server_run": (i, [_vp, ctypes.POINTER(MgRequest), i]),
+        "mg_server_get_stats": (i, [_vp, ctypes.POINTER(MgServerStats)]),
         "mg_solve": (i, [_vp, ctypes.POINTER(MgParams), ctypes.POINTER(MgBC), _vp, _vp, _dp, _ip, _vp]),
         "mg_last_timing": (i, [_vp, _dp, _dp, _dp, i, _ip]),
         "mg_set_kernel_timing": (i, [_vp, i]),

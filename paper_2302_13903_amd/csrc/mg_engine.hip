@@ -387,6 +387,14 @@ size_t mg_footprint_bytes(const mg_params* p) {
   return make_layout(p->n, p->precision).total + sizeof(double) * (kMaxPartials * 32 + kScal);
 }
 
+int mg_ctx_reserve(mg_ctx* c, const mg_params* p) {
+  if (!c || !p) return MG_ERR_INVALID_ARG;
+  if (!is_pow2(p->n) || p->n < 2 || p->n > 2048) return fail(c, MG_ERR_INVALID_ARG, "n must be a power of two in [2, 2048]");
+  if (p->precision != MG_PREC_FP64 && p->precision != MG_PREC_MIXED) return fail(c, MG_ERR_INVALID_ARG, "bad precision");
+  HIP_CHECK(c, hipSetDevice(c->device));
+  return ensure_ws(c, make_layout(p->n, p->precision).total);
+}
+
 int mg_set_kernel_timing(mg_ctx* c, int on) {
   if (!c) return MG_ERR_INVALID_ARG;
   c->ktiming = on ? 1 : 0;

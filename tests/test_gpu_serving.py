@@ -1,0 +1,102 @@
+"""Serving runtime on the GPU: a request's result does not depend on what runs beside it
+(alone == in-mix, bitwise: every kernel and reduction is deterministic), the server's solve is
+the plain mg_solve, and resident hierarchies are reused across requests."""
+import numpy as np
+import pytest
+
+import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2302_13903_amd as mg  # noqa: E402
+from paper_2302_13903_amd import serving  # noqa: E402
+from paper_2302_13903_amd._abi import MG_ERR_INVALID_ARG  # noqa: E402
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def clumps(n, seed, remove_mean):
+    return dev(wl.gaussian_clumps(n, seed, remove_mean=remove_mean))
+
+
+CASES = [  # (n, bc, precision)
+    (64, "periodic", "fp64"),
+    (128, "fixed", "fp64"),
+    (64, "multipole", "mixed"),
+    (128, "periodic", "mixed"),
+    (64, "zero_gradient", "fp64"),
+]
+
+
+def make_requests(rhos, phis):
+    return [serving.Request(rho=rhos[i], bc=bc, precision=prec, phi=phis[i], want_hist=True, tol=1e-10)
+            for i, (n, bc, prec) in enumerate(CASES)]
+
+
+def test_alone_equals_in_mix_bitwise():
+    print("serving alone vs mix", flush=True)
+    rhos = [clumps(n, 100 + i, bc == "periodic") for i, (n, bc, _) in enumerate(CASES)]
+    alone_phi = [torch.zeros_like(r) for r in rhos]
+    srv1 = serving.Server(workers=1)
+    alone = []
+    for i in range(len(CASES)):
+        rq = make_requests(rhos, alone_phi)[i]
+        srv1.run([rq])
+        assert rq.status >= 0, (CASES[i], rq.status)
+        alone.append(rq)
+    torch.cuda.synchronize()
+    mix_phi = [torch.full_like(r, 7.0) for r in rhos]
+    mix = make_requests(rhos, mix_phi)
+    fill = [serving.Request(rho=clumps(256, 7, True), bc="periodic"),
+            serving.Request(rho=clumps(128, 8, False), bc="multipole", precision="mixed"),
+            serving.Request(rho=clumps(256, 9, True), bc="periodic", precision="mixed")]
+    for k, r in enumerate(fill):
+        r.arrival_ms = 0.0
+    for k, r in enumerate(mix):
+        r.arrival_ms = 1.0 * k
+    srv4 = serving.Server(workers=4)
+    out = srv4.run(fill + mix)
+    assert all(r.status == 0 for r in out), [r.status for r in out]
+    assert srv4.stats()["max_concurrent"] >= 2
+    for i, (a, b) in enumerate(zip(alone, mix)):
+        assert a.hist == b.hist, CASES[i]
+        assert torch.equal(alone_phi[i], mix_phi[i]), CASES[i]
+
+
+def test_server_matches_direct_solve():
+    print("serving vs direct", flush=True)
+    rho = clumps(128, 3, False)
+    phi_d, hist_d, st_d = mg.solve(rho, 1.0 / 128, "multipole", tol=1e-10)
+    phi_s = torch.zeros_like(rho)
+    srv = serving.Server(workers=2)
+    (r,) = srv.run([serving.Request(rho=rho, bc="multipole", phi=phi_s, want_hist=True)])
+    assert r.status == st_d
+    assert r.hist == hist_d
+    assert torch.equal(phi_s, phi_d)
+
+
+def test_reuse_and_repeat_are_identical():
+    print("serving reuse", flush=True)
+    rho = clumps(64, 4, True)
+    srv = serving.Server(workers=2)
+    phis = [torch.zeros_like(rho) for _ in range(4)]
+    # a 128^3 request between dirties nothing it shares: hierarchies are per (n, precision)
+    rs = [serving.Request(rho=rho, phi=phis[0]), serving.Request(rho=clumps(128, 5, True), arrival_ms=0.0),
+          serving.Request(rho=rho, phi=phis[1], arrival_ms=5.0)]
+    srv.run(rs)
+    srv.run([serving.Request(rho=rho, phi=phis[2]), serving.Request(rho=rho, phi=phis[3])])
+    assert all(r.status == 0 for r in rs)
+    for p in phis[1:]:
+        assert torch.equal(p, phis[0])
+    st = srv.stats()
+    assert st["reused"] >= 2 and st["created"] <= 4
+
+
+def test_mgi_without_phi_is_an_error():
+    rho = clumps(32, 6, True)
+    srv = serving.Server(workers=1)
+    (r,) = srv.run([serving.Request(rho=rho, mode="mgi")])
+    assert r.status == MG_ERR_INVALID_ARG
