@@ -57,8 +57,13 @@ extern "C" {
 #define MG_PREC_MIXED 1        /* FP32 smoothing / restriction / prolongation inside FP64
                                   defect-correction (FP64 residual and phi update) */
 
-#define MG_LAYOUT_DENSE 0      /* one n^3 array per level */
-#define MG_LAYOUT_BLOCKS 1     /* MeshBlock decomposition: block_n^3 blocks + root grid */
+#define MG_LAYOUT_DENSE 0      /* one n^3 array per level, x fastest */
+#define MG_LAYOUT_BLOCKS 1     /* MeshBlock decomposition (Sec. 3.2): rho and phi hold
+                                  (n/block_n)^3 blocks of block_n^3 cells, blocks in Morton
+                                  order of their coordinates (bits of bx, by, bz interleaved,
+                                  x lowest), each block x fastest.  Block levels are coarsened
+                                  to one cell per block; those cells form the dense root grid.
+                                  block_n in {2, 4, 8, 16}; multipole faces unsupported. */
 
 typedef struct mg_ctx mg_ctx;
 
@@ -75,7 +80,7 @@ typedef struct {
   int fixed_cycles; /* > 0: run exactly this many V-cycles and ignore tol               [0] */
   int precision;    /* MG_PREC_FP64 or MG_PREC_MIXED                                    [FP64] */
   int layout;       /* MG_LAYOUT_DENSE or MG_LAYOUT_BLOCKS                              [DENSE] */
-  int block_n;      /* MeshBlock size for MG_LAYOUT_BLOCKS (power of two, < n)         [16] */
+  int block_n;      /* MeshBlock side for MG_LAYOUT_BLOCKS (2..16, power of two, < n)   [16] */
 } mg_params;
 
 /* Boundary description of a solve. */
@@ -111,6 +116,21 @@ size_t mg_footprint_bytes(const mg_params *p);
  * that later solves of the same or smaller size allocate nothing.  MG_ERR_OOM when the
  * device cannot hold it (the previous workspace is then released). */
 int mg_ctx_reserve(mg_ctx *ctx, const mg_params *p);
+
+/* Autotuner of the MeshBlock layout (layout = MG_LAYOUT_BLOCKS): for every block level of a
+ * solve with these parameters, times each schedule of the block sweep (threads per
+ * workgroup, blocks staged per workgroup, one or two sweeps fused per launch) over `reps`
+ * launches on scratch arrays and keeps the fastest in the context; later solves use it.
+ * Every schedule gives bitwise the same result.  Allocates and frees its own scratch
+ * (3 n^3 arrays); synchronises the device.  No-op for the dense layout. */
+int mg_autotune(mg_ctx *ctx, const mg_params *p, int reps);
+
+/* The context's schedules as text, one line each: "blk fp64|fp32 Lm Lb threads G S"
+ * (Lm = log2 block side on that level, Lb = log2 blocks per side).  Writes at most cap bytes
+ * (NUL-terminated) and returns the length needed including the NUL.  mg_tuning_set reads the
+ * same format (e.g. from a cache file) and rejects schedules the device cannot run. */
+int mg_tuning_get(const mg_ctx *ctx, char *buf, int cap);
+int mg_tuning_set(mg_ctx *ctx, const char *text);
 
 /* Full solve (Sec. 2.3.7, Alg. 1, Alg. 2).
  *   rho   device, n^3 FP64, read only.

@@ -22,7 +22,7 @@ from ._abi import (MG_BC_FIXED, MG_BC_MULTIPOLE, MG_BC_PERIODIC, MG_BC_ZERO_GRAD
                    MG_LAYOUT_DENSE, MG_MODE_FMG, MG_MODE_MGI, MG_PREC_FP64, MG_PREC_MIXED, MG_NOT_CONVERGED,
                    MG_OK, MG_STALLED, MgError, STATUS_NAMES)
 
-__all__ = ["Context", "solve", "mg_solve", "mg_footprint_bytes", "params", "boundary", "level_bc",
+__all__ = ["Context", "solve", "to_blocks", "from_blocks", "morton_order", "mg_solve", "mg_footprint_bytes", "params", "boundary", "level_bc",
            "mg_op_half_sweep", "mg_op_smooth", "mg_op_defect", "mg_op_restrict", "mg_op_prolong_add",
            "mg_op_prolong_fmg", "mg_op_coarsest", "mg_op_down", "mg_op_up", "mg_multipole_moments",
            "MgError", "KINDS"]
@@ -112,6 +112,84 @@ class Context:
             idx += 1
 
 
+    def reserve(self, n: int, precision: str = "fp64", layout: str = "dense", block_n: int = 16):
+        p = params(n, 1.0 / n, precision=precision, layout=layout, block_n=block_n)
+        self.check(self._lib.mg_ctx_reserve(self.handle, ctypes.byref(p)), "mg_ctx_reserve")
+
+    def autotune(self, n: int, block_n: int = 16, precision: str = "fp64", reps: int = 5,
+                 cache: Optional[str] = None) -> str:
+        """Pick the block-sweep schedules of MeshBlock-layout solves of this shape (see
+        mg_autotune).  With ``cache`` (a JSON file) a stored result for this device and shape
+        is loaded instead of timing, and a new result is stored.  Returns the schedule text."""
+        import json
+        import os
+        key = None
+        if cache:
+            import torch
+            key = f"{torch.cuda.get_device_name(self.device)}|n={n}|block_n={block_n}|{precision}"
+            try:
+                with open(cache) as fh:
+                    stored = json.load(fh)
+            except (OSError, ValueError):
+                stored = {}
+            if key in stored:
+                self.set_tuning(stored[key])
+                return stored[key]
+        p = params(n, 1.0 / n, precision=precision, layout="blocks", block_n=block_n)
+        self.check(self._lib.mg_autotune(self.handle, ctypes.byref(p), int(reps)), "mg_autotune")
+        text = self.tuning()
+        if cache:
+            stored[key] = text
+            os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+            with open(cache, "w") as fh:
+                json.dump(stored, fh, indent=1)
+        return text
+
+    def tuning(self) -> str:
+        need = self._lib.mg_tuning_get(self.handle, None, 0)
+        buf = ctypes.create_string_buffer(max(need, 1))
+        self._lib.mg_tuning_get(self.handle, buf, len(buf))
+        return buf.value.decode()
+
+    def set_tuning(self, text: str):
+        self.check(self._lib.mg_tuning_set(self.handle, text.encode()), "mg_tuning_set")
+
+
+def morton_order(nb: int):
+    """Row-major (bz, by, bx) block numbers listed in Morton order (x bit lowest): element q is
+    the row-major number of the block stored q-th in the MeshBlock layout."""
+    import numpy as np
+    lb = max(nb - 1, 0).bit_length()
+    q = np.arange(nb ** 3, dtype=np.int64)
+    c = [np.zeros_like(q) for _ in range(3)]
+    for bit in range(lb):
+        for a in range(3):
+            c[a] |= ((q >> (3 * bit + a)) & 1) << bit
+    bx, by, bz = c
+    return (bz * nb + by) * nb + bx
+
+
+def to_blocks(x, block_n: int):
+    """Dense (n, n, n) [z][y][x] tensor -> MeshBlock layout (flat, blocks in Morton order)."""
+    import torch
+    n, m = x.shape[0], block_n
+    nb = n // m
+    b = x.reshape(nb, m, nb, m, nb, m).permute(0, 2, 4, 1, 3, 5).reshape(nb ** 3, m ** 3)
+    idx = torch.as_tensor(morton_order(nb), device=x.device)
+    return b.index_select(0, idx).reshape(-1).contiguous()
+
+
+def from_blocks(xb, n: int, block_n: int):
+    """Inverse of to_blocks."""
+    import torch
+    m = block_n
+    nb = n // m
+    idx = torch.as_tensor(morton_order(nb), device=xb.device)
+    rows = torch.empty((nb ** 3, m ** 3), dtype=xb.dtype, device=xb.device)
+    rows[idx] = xb.reshape(nb ** 3, m ** 3)
+    return rows.reshape(nb, nb, nb, m, m, m).permute(0, 3, 1, 4, 2, 5).reshape(n, n, n).contiguous()
+
+
 _default_ctx = {}
 
 
@@ -180,9 +258,17 @@ def solve(rho, dx: float, bc="periodic", fixed_b=None, lmax: int = 4, origin=Non
     """Solve nabla^2 phi = 4 pi G rho on the device.  ``rho``: contiguous float64 (n, n, n) tensor
     on the GPU.  Returns ``(phi, hist, status)``."""
     import torch
-    if rho.dtype != torch.float64 or rho.dim() != 3:
-        raise ValueError("rho must be a float64 (n, n, n) tensor")
-    n = rho.shape[0]
+    if layout == "blocks":
+        # MeshBlock layout: rho is flat (n^3,) in Morton block order (see to_blocks)
+        if rho.dtype != torch.float64 or rho.dim() != 1:
+            raise ValueError("rho must be a flat float64 tensor in the MeshBlock layout")
+        n = round(rho.numel() ** (1.0 / 3.0))
+        if n ** 3 != rho.numel():
+            raise ValueError("rho must hold n^3 values")
+    else:
+        if rho.dtype != torch.float64 or rho.dim() != 3:
+            raise ValueError("rho must be a float64 (n, n, n) tensor")
+        n = rho.shape[0]
     ctx = ctx or default_context(rho.device.index or 0)
     p = params(n, dx, tol=tol, max_cycles=max_cycles, fixed_cycles=fixed_cycles, npre=npre, npost=npost,
                omega=omega, mode=mode, precision=precision, layout=layout, block_n=block_n, four_pi_g=four_pi_g)

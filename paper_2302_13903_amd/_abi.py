@@ -89,6 +89,9 @@ def lib():
         "mg_last_error": (ctypes.c_char_p, [_vp]),
         "mg_footprint_bytes": (ctypes.c_size_t, [ctypes.POINTER(MgParams)]),
         "mg_ctx_reserve": (i, [_vp, ctypes.POINTER(MgParams)]),
+        "mg_autotune": (i, [_vp, ctypes.POINTER(MgParams), i]),
+        "mg_tuning_get": (i, [_vp, ctypes.c_char_p, i]),
+        "mg_tuning_set": (i, [_vp, ctypes.c_char_p]),
         "mg_server_create": (i, [ctypes.POINTER(_vp), ctypes.POINTER(MgServerConfig)]),
         "mg_server_destroy": (None, [_vp]),
         "mg_server_last_error": (ctypes.c_char_p, [_vp]),

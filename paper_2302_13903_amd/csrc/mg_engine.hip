@@ -10,10 +10,13 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <sstream>
 #include <string>
 #include <vector>
 
 #include "../../include/mg355.h"
+#include "mg_blocks.h"
 #include "mg_fused.h"
 #include "mg_launch.h"
 
@@ -49,6 +52,8 @@ struct mg_ctx {
   // scratch of the operator entry points (ping-pong partner of a caller's array)
   void* op_scratch = nullptr;
   size_t op_scratch_cap = 0;
+  // block-sweep schedules chosen by mg_autotune (or set), keyed by (precision, Lm, Lb)
+  std::map<int, BlkTune> blk_tune;
 };
 
 namespace {
@@ -88,7 +93,9 @@ struct Layout {
   size_t total = 0;
 };
 
-Layout make_layout(int n, int precision) {
+// Lb >= 0: MeshBlock layout with 2^Lb blocks per side (levels above Lb are block levels,
+// each swept out of place, so each has a ping-pong partner).
+Layout make_layout(int n, int precision, int Lb = -1) {
   Layout y;
   y.L = ilog2(n);
   y.mixed = precision == MG_PREC_MIXED;
@@ -112,10 +119,16 @@ Layout make_layout(int n, int precision) {
     }
     y.faces[l] = take(6 * face_sz(l) * 8);
     y.u2[l] = (size_t)-1;
-    if ((1 << l) >= kFusedMinN) y.u2[l] = take(cells(l) * (y.mixed ? 4 : 8));
+    if ((1 << l) >= kFusedMinN || (Lb >= 0 && l > Lb)) y.u2[l] = take(cells(l) * (y.mixed ? 4 : 8));
   }
   y.total = off;
   return y;
+}
+
+// log2 of the blocks per side of a MeshBlock-layout solve, -1 for the dense layout.
+int layout_lb(const mg_params* p) {
+  if (p->layout != MG_LAYOUT_BLOCKS || !is_pow2(p->block_n) || p->block_n < 2 || p->block_n >= p->n) return -1;
+  return ilog2(p->n / p->block_n);
 }
 
 int validate(mg_ctx* c, const mg_params* p, const mg_bc* bc) {
@@ -129,8 +142,10 @@ int validate(mg_ctx* c, const mg_params* p, const mg_bc* bc) {
   if (p->mode != MG_MODE_FMG && p->mode != MG_MODE_MGI) return fail(c, MG_ERR_INVALID_ARG, "bad mode");
   if (p->precision != MG_PREC_FP64 && p->precision != MG_PREC_MIXED) return fail(c, MG_ERR_INVALID_ARG, "bad precision");
   if (p->layout != MG_LAYOUT_DENSE && p->layout != MG_LAYOUT_BLOCKS) return fail(c, MG_ERR_INVALID_ARG, "bad layout");
-  if (p->layout == MG_LAYOUT_BLOCKS && (!is_pow2(p->block_n) || p->block_n < 2 || p->block_n >= p->n))
-    return fail(c, MG_ERR_INVALID_ARG, "block_n must be a power of two below n");
+  if (p->layout == MG_LAYOUT_BLOCKS &&
+      (!is_pow2(p->block_n) || p->block_n < 2 || p->block_n > (1 << kBlkMaxLm) || p->block_n >= p->n ||
+       p->n / p->block_n > 1024))
+    return fail(c, MG_ERR_INVALID_ARG, "block_n must be a power of two in [2, 16], below n, with at most 1024 blocks per side");
   for (int f = 0; f < 6; ++f)
     if (bc->kind[f] < MG_BC_PERIODIC || bc->kind[f] > MG_BC_MULTIPOLE) return fail(c, MG_ERR_INVALID_ARG, "bad face kind");
   for (int a = 0; a < 3; ++a)
@@ -301,8 +316,88 @@ struct Solver {
   void fmg(Hier<T>& H) {
     tail(H, TAIL_FMG, H.phys[H.T_top]);
     for (int l = H.T_top + 1; l <= H.L; ++l) {
-      launch_prolong<T>(H.u[l - 1], H.u[l], 1 << (l - 1), H.phys[l - 1], 1, s);
-      vcycle(H, l, H.phys[l], false, false);
+      if (Lb >= 0 && l > Lb) {
+        blk_prolong<T>(H.u[l - 1], H.u[l], l - Lb, Lb, H.phys[l - 1], 1, s);
+        vcycle_blk(H, l, H.phys[l]);
+      } else {
+        launch_prolong<T>(H.u[l - 1], H.u[l], 1 << (l - 1), H.phys[l - 1], 1, s);
+        vcycle(H, l, H.phys[l], false, false);
+      }
+    }
+  }
+
+  // ---- MeshBlock layout (Sec. 3.2): levels above Lb are block levels, Lb and below the root
+  // grid and its dense hierarchy.
+  int Lb = -1;
+  bool timed_top = false;   // kernel timing of the finest block level (V-cycles after FMG)
+
+  template <typename T>
+  BlkTune blk_tune(int Lm) const {
+    const int key = (sizeof(T) == 8 ? 0 : 1000) + 100 * Lm + Lb;
+    auto it = c->blk_tune.find(key);
+    if (it != c->blk_tune.end() && blk_tune_valid(it->second, Lm, Lb, sizeof(T), c->lds_per_block)) return it->second;
+    return blk_default_tune(Lm, Lb, sizeof(T));
+  }
+
+  // npre (or npost) sweeps of block level l, ping-ponging between H.u[l] and H.u2[l], fused
+  // S at a time as the schedule says; returns the array holding the result.
+  template <typename T>
+  T* blk_sweeps(Hier<T>& H, int l, T* cur, int count, const LevelBC& bc) {
+    const int Lm = l - Lb;
+    const BlkTune t = blk_tune<T>(Lm);
+    T* oth = cur == H.u[l] ? H.u2[l] : H.u[l];
+    int left = count;
+    const bool timed = timed_top && l == H.L && c->ktiming;
+    while (left > 0) {
+      BlkTune ti = t;
+      ti.S = (t.S == 2 && left >= 2) ? 2 : 1;
+      if (!blk_tune_valid(ti, Lm, Lb, sizeof(T), c->lds_per_block)) ti = blk_default_tune(Lm, Lb, sizeof(T));
+      if (timed) kernel_begin();
+      blk_sweep<T>(cur, oth, H.f[l], Lm, Lb, ti, H.h[l], H.omega, bc, s);
+      if (timed)
+        kernel_end(std::string("k_blk_sweep<") + (sizeof(T) == 8 ? "double" : "float") + ", " + std::to_string(Lm) +
+                       ", " + std::to_string(ti.S) + ">",
+                   3.0 * (double)cells(l) * sizeof(T));
+      std::swap(cur, oth);
+      left -= ti.S;
+    }
+    return cur;
+  }
+
+  // Alg. 1 on block level l: every block at once, one launch per operator; the level below
+  // block level Lm = 1 is the root grid (gathered by the restriction, scattered by the
+  // prolongation), solved by the dense recursion.
+  template <typename T>
+  void vcycle_blk(Hier<T>& H, int l, const LevelBC& bc) {
+    if (l <= Lb) {
+      vcycle(H, l, bc, false, false);
+      return;
+    }
+    const int Lm = l - Lb;
+    T* cur = blk_sweeps(H, l, H.u[l], H.npre, bc);
+    blk_defect_restrict<T>(cur, H.f[l], H.f[l - 1], H.u[l - 1], Lm, Lb, H.h[l], bc, s);
+    vcycle_blk(H, l - 1, H.hom);
+    blk_prolong<T>(H.u[l - 1], cur, Lm, Lb, H.hom, 0, s);
+    cur = blk_sweeps(H, l, cur, H.npost, bc);
+    if (cur != H.u[l]) (void)hipMemcpyAsync(H.u[l], cur, cells(l) * sizeof(T), hipMemcpyDeviceToDevice, s);
+  }
+
+  // Source hierarchy f_{l-1} = restriction of f_l (Alg. 2 step 1) in either layout.
+  template <typename T>
+  void restrict_sources(Hier<T>& H) {
+    for (int l = H.L; l >= 1; --l) {
+      if (Lb >= 0 && l > Lb) blk_restrict<T, T>(H.f[l], H.f[l - 1], l - Lb, Lb, s);
+      else launch_restrict<T, T>(H.f[l], H.f[l - 1], 1 << (l - 1), s);
+    }
+  }
+
+  // Sum of squared finest-level defects into out (device); optionally the FP32 defect.
+  void defect_norm(const double* u, const double* f, float* r32, int n, double h, const LevelBC& bc, double* out) {
+    if (Lb >= 0) {
+      const int np = blk_defect_norm(u, f, r32, ilog2(n) - Lb, Lb, h, bc, c->part, s);
+      launch_sum_partials(c->part, np, out, s);
+    } else {
+      launch_defect_norm(u, f, r32, n, h, bc, c->part, out, s);
     }
   }
 };
@@ -359,6 +454,8 @@ int mg_ctx_create(mg_ctx** out, int device) {
   }
   // the FP64 coarse tail keeps levels <= 16^3 in LDS when the device allows it per block
   c->tail64_top = tail_prepare(c->lds_per_block);
+  blk_prepare<double>(c->lds_per_block);
+  blk_prepare<float>(c->lds_per_block);
   *out = c;
   return MG_OK;
 }
@@ -384,7 +481,7 @@ const char* mg_last_error(const mg_ctx* c) { return c ? c->err.c_str() : "null c
 
 size_t mg_footprint_bytes(const mg_params* p) {
   if (!p || !is_pow2(p->n) || p->n < 2 || p->n > 2048) return 0;
-  return make_layout(p->n, p->precision).total + sizeof(double) * (kMaxPartials * 32 + kScal);
+  return make_layout(p->n, p->precision, layout_lb(p)).total + sizeof(double) * (kMaxPartials * 32 + kScal);
 }
 
 int mg_ctx_reserve(mg_ctx* c, const mg_params* p) {
@@ -392,7 +489,7 @@ int mg_ctx_reserve(mg_ctx* c, const mg_params* p) {
   if (!is_pow2(p->n) || p->n < 2 || p->n > 2048) return fail(c, MG_ERR_INVALID_ARG, "n must be a power of two in [2, 2048]");
   if (p->precision != MG_PREC_FP64 && p->precision != MG_PREC_MIXED) return fail(c, MG_ERR_INVALID_ARG, "bad precision");
   HIP_CHECK(c, hipSetDevice(c->device));
-  return ensure_ws(c, make_layout(p->n, p->precision).total);
+  return ensure_ws(c, make_layout(p->n, p->precision, layout_lb(p)).total);
 }
 
 int mg_set_kernel_timing(mg_ctx* c, int on) {
@@ -482,10 +579,14 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
   int st = validate(c, p, bc);
   if (st != MG_OK) return st;
   if (!rho || !phi || !hist || !n_hist) return fail(c, MG_ERR_INVALID_ARG, "null rho/phi/hist/n_hist");
-  if (p->layout == MG_LAYOUT_BLOCKS) return fail(c, MG_ERR_UNSUPPORTED, "block layout is not available in this build");
+  if (p->layout == MG_LAYOUT_BLOCKS)
+    for (int f = 0; f < 6; ++f)
+      if (bc->kind[f] == MG_BC_MULTIPOLE)
+        return fail(c, MG_ERR_UNSUPPORTED, "multipole faces need the dense layout");
   HIP_CHECK(c, hipSetDevice(c->device));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const Layout y = make_layout(p->n, p->precision);
+  const int Lb = layout_lb(p);
+  const Layout y = make_layout(p->n, p->precision, Lb);
   st = ensure_ws(c, y.total);
   if (st != MG_OK) return st;
   for (auto e : c->kev) (void)hipEventDestroy(e);
@@ -499,7 +600,7 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
   for (int f = 0; f < 6; ++f)
     if (bc->kind[f] == MG_BC_FIXED || bc->kind[f] == MG_BC_MULTIPOLE) gauge_free = false;
   const bool mixed = y.mixed;
-  const int tail_max = mixed ? 4 : c->tail64_top;
+  const int tail_max = std::min(mixed ? 4 : c->tail64_top, Lb >= 0 ? Lb : 99);
 
   HIP_CHECK(c, hipEventRecord(c->ev0, s));
   HIP_CHECK(c, hipMemsetAsync(c->scal, 0, sizeof(double) * kScal, s));
@@ -522,6 +623,7 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
   setup_faces(c, y, p, bc, rho, s, phys, &hom);
 
   Solver S{c, s, true};
+  S.Lb = Lb;
   Hier<double> H64;
   Hier<float> H32;
   auto fill_common = [&](auto& H, int tail_top) {
@@ -546,7 +648,7 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
     H64.f[L] = f64L;
     for (int l = 0; l <= L; ++l)
       H64.u2[l] = y.u2[l] == (size_t)-1 ? nullptr : reinterpret_cast<double*>(c->ws + y.u2[l]);
-    for (int l = L; l >= 1; --l) launch_restrict<double, double>(H64.f[l], H64.f[l - 1], 1 << (l - 1), s);
+    S.restrict_sources(H64);
   } else {
     fill_common(H32, tail_max);
     for (int l = 0; l <= L; ++l) {
@@ -554,7 +656,7 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
       H32.f[l] = reinterpret_cast<float*>(c->ws + y.f32[l]);
       H32.u2[l] = y.u2[l] == (size_t)-1 ? nullptr : reinterpret_cast<float*>(c->ws + y.u2[l]);
     }
-    for (int l = L; l >= 1; --l) launch_restrict<float, float>(H32.f[l], H32.f[l - 1], 1 << (l - 1), s);
+    S.restrict_sources(H32);
   }
   HIP_CHECK(c, hipEventRecord(c->ev_setup, s));
 
@@ -568,7 +670,7 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
     }
   }
   // ---- residual of the start (Sec. 2.3.7); mixed: also its FP32 copy as the inner RHS
-  launch_defect_norm(phi, f64L, mixed ? H32.f[L] : nullptr, p->n, p->dx, phys[L], c->part, c->scal + 2, s);
+  S.defect_norm(phi, f64L, mixed ? H32.f[L] : nullptr, p->n, p->dx, phys[L], c->scal + 2);
   HIP_CHECK(c, hipEventRecord(c->ev_fmg, s));
   HIP_CHECK(c, hipMemcpyAsync(c->hscal, c->scal, sizeof(double) * 16, hipMemcpyDeviceToHost, s));
   HIP_CHECK(c, hipStreamSynchronize(s));
@@ -597,7 +699,16 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
   double* phi_oth = y.phi2 == (size_t)-1 ? nullptr : reinterpret_cast<double*>(c->ws + y.phi2);
   if (p->fixed_cycles > 0 || r > p->tol) {
     for (int cyc = 0; cyc < ncyc; ++cyc) {
-      if (!mixed) {
+      S.timed_top = true;
+      if (!mixed && Lb >= 0) {
+        S.vcycle_blk(H64, L, phys[L]);
+        S.defect_norm(phi, f64L, nullptr, p->n, p->dx, phys[L], c->scal + 2);
+      } else if (mixed && Lb >= 0) {
+        HIP_CHECK(c, hipMemsetAsync(H32.u[L], 0, n3 * sizeof(float), s));
+        S.vcycle_blk(H32, L, hom);
+        launch_add_f32(phi, H32.u[L], n3, s);
+        S.defect_norm(phi, f64L, H32.f[L], p->n, p->dx, phys[L], c->scal + 2);
+      } else if (!mixed) {
         const bool normed = S.vcycle(H64, L, phys[L], true, true);
         if (!normed) launch_defect_norm(phi, f64L, nullptr, p->n, p->dx, phys[L], c->part, c->scal + 2, s);
       } else {
@@ -663,6 +774,117 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
   }
   return status;
 }
+
+// ============================================================== autotuner
+
+namespace {
+
+template <typename T>
+int autotune_blocks(mg_ctx* c, const mg_params* p, int Lb, int reps) {
+  const int L = ilog2(p->n);
+  const size_t cellsL = cells(L);
+  T* buf[3] = {nullptr, nullptr, nullptr};
+  for (auto& b : buf)
+    if (hipMalloc((void**)&b, cellsL * sizeof(T)) != hipSuccess) {
+      (void)hipGetLastError();
+      for (auto& q : buf)
+        if (q) (void)hipFree(q);
+      return fail(c, MG_ERR_OOM, "autotune scratch allocation failed");
+    }
+  hipStream_t s = nullptr;
+  HIP_CHECK(c, hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  for (auto& b : buf) HIP_CHECK(c, hipMemsetAsync(b, 0, cellsL * sizeof(T), s));
+  hipEvent_t e0, e1;
+  HIP_CHECK(c, hipEventCreate(&e0));
+  HIP_CHECK(c, hipEventCreate(&e1));
+  LevelBC bc;
+  for (int f = 0; f < 6; ++f) { bc.kind[f] = BC_PERIODIC; bc.b[f] = nullptr; }
+  for (int l = Lb + 1; l <= L; ++l) {
+    const int Lm = l - Lb;
+    const double h = p->dx * (double)(1LL << (L - l));
+    BlkTune best = blk_default_tune(Lm, Lb, sizeof(T));
+    double best_ms = 1e30;
+    for (int S = 1; S <= 2; ++S)
+      for (int threads : {256, 512, 1024})
+        for (int G = 1; G <= 256; G *= 2) {
+          const BlkTune t{threads, G, S};
+          if (!blk_tune_valid(t, Lm, Lb, sizeof(T), c->lds_per_block)) continue;
+          const int tw = (1 << Lm) + 4 * S;
+          if (G > 1 && (size_t)G * tw * tw * tw > 40000) continue;   // beyond ~4 workgroups' worth per CU
+          blk_sweep<T>(buf[0], buf[1], buf[2], Lm, Lb, t, h, p->omega, bc, s);
+          HIP_CHECK(c, hipEventRecord(e0, s));
+          for (int r = 0; r < reps; ++r) blk_sweep<T>(buf[r & 1], buf[(r + 1) & 1], buf[2], Lm, Lb, t, h, p->omega, bc, s);
+          HIP_CHECK(c, hipEventRecord(e1, s));
+          HIP_CHECK(c, hipEventSynchronize(e1));
+          HIP_CHECK(c, hipGetLastError());
+          const double ms = elapsed(e0, e1) / (reps * S);   // per sweep
+          if (ms < best_ms) { best_ms = ms; best = t; }
+        }
+    c->blk_tune[(sizeof(T) == 8 ? 0 : 1000) + 100 * Lm + Lb] = best;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(s);
+  for (auto& b : buf) (void)hipFree(b);
+  return MG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mg_autotune(mg_ctx* c, const mg_params* p, int reps) {
+  if (!c || !p) return MG_ERR_INVALID_ARG;
+  mg_bc bc;
+  std::memset(&bc, 0, sizeof(bc));
+  int st = validate(c, p, &bc);
+  if (st != MG_OK) return st;
+  if (reps < 1 || reps > 1000) return fail(c, MG_ERR_INVALID_ARG, "reps in 1..1000");
+  HIP_CHECK(c, hipSetDevice(c->device));
+  const int Lb = layout_lb(p);
+  if (Lb < 0) return MG_OK;   // the dense passes have fixed shapes
+  st = p->precision == MG_PREC_MIXED ? autotune_blocks<float>(c, p, Lb, reps) : autotune_blocks<double>(c, p, Lb, reps);
+  return st;
+}
+
+int mg_tuning_get(const mg_ctx* c, char* buf, int cap) {
+  if (!c) return MG_ERR_INVALID_ARG;
+  std::ostringstream o;
+  for (const auto& kv : c->blk_tune) {
+    const int key = kv.first;
+    o << "blk " << (key >= 1000 ? "fp32" : "fp64") << " " << (key % 1000) / 100 << " " << key % 100 << " "
+      << kv.second.threads << " " << kv.second.G << " " << kv.second.S << "\n";
+  }
+  const std::string t = o.str();
+  if (buf && cap > 0) {
+    std::strncpy(buf, t.c_str(), (size_t)cap - 1);
+    buf[cap - 1] = 0;
+  }
+  return (int)t.size() + 1;
+}
+
+int mg_tuning_set(mg_ctx* c, const char* text) {
+  if (!c || !text) return MG_ERR_INVALID_ARG;
+  std::istringstream in(text);
+  std::string line;
+  std::map<int, BlkTune> add;
+  while (std::getline(in, line)) {
+    if (line.empty()) continue;
+    std::istringstream ls(line);
+    std::string tag, prec;
+    int Lm, Lb, threads, G, S;
+    if (!(ls >> tag >> prec >> Lm >> Lb >> threads >> G >> S) || tag != "blk" || (prec != "fp64" && prec != "fp32"))
+      return fail(c, MG_ERR_INVALID_ARG, "bad tuning line: " + line);
+    const BlkTune t{threads, G, S};
+    if (Lb < 0 || Lb > 10 || !blk_tune_valid(t, Lm, Lb, prec == "fp64" ? 8 : 4, c->lds_per_block))
+      return fail(c, MG_ERR_INVALID_ARG, "invalid schedule: " + line);
+    add[(prec == "fp64" ? 0 : 1000) + 100 * Lm + Lb] = t;
+  }
+  for (const auto& kv : add) c->blk_tune[kv.first] = kv.second;
+  return MG_OK;
+}
+
+}  // extern "C"
 
 // ============================================================== operator entry points
 
