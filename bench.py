@@ -13,6 +13,8 @@ in HBM.  The JSON line reports:
                 its mean launch time (HIP events on the solve stream) against 8 TB/s;
   cpu_baseline  the CPU oracle timed on a bounded sample of the same workload;
   mixed         the same numbers for the mixed-precision solve; p50/p99 solve latency.
+  batched       the 256^3 lognormal field as 4096 MeshBlocks of 16^3 (autotuned), FP64 and
+                mixed, beside the dense FP64 solve of the same field;
   serving       a mixed-size request stream through the serving runtime: saturated
                 throughput and p50/p99 latency at 0.5 and 0.9 of it, FP64 and mixed.
 
@@ -112,6 +114,62 @@ def cpu_baseline(n: int, cycles: int = 3):
                       f"{dt * 1e3:.0f} ms per cycle"}
 
 
+def batched_leg(steps: int, seed: int, n: int = 256, block_n: int = 16):
+    """Configuration 4: the 256^3 lognormal field (exp of a Gaussian random field with
+    P(k) ~ k^-4, mean removed, periodic) as 4096 MeshBlocks of 16^3 with autotuned block
+    sweeps, FP64 and mixed precision, beside the dense FP64 solve of the same field."""
+    import torch
+
+    import paper_2302_13903_amd as mg
+    import workloads as wl
+    rho_h = wl.lognormal_grf(n, seed)
+    rho_h -= rho_h.mean()
+    rho = torch.from_numpy(rho_h).to("cuda:0")
+    rho_b = mg.to_blocks(rho, block_n)
+    ctx = mg.Context(0)
+    out = {"workload": f"C4 lognormal GRF {n}^3 periodic as {(n // block_n) ** 3} blocks of {block_n}^3",
+           "tol": 1e-10}
+    tune = {}
+    for prec in ("fp64", "mixed"):
+        tune[prec] = ctx.autotune(n, block_n, prec, reps=5)
+    out["schedules"] = tune
+    phi_dense = None
+    for name, x, layout, prec in (("dense_fp64", rho, "dense", "fp64"), ("blocks_fp64", rho_b, "blocks", "fp64"),
+                                  ("blocks_mixed", rho_b, "blocks", "mixed")):
+        lat, cyc = [], []
+        ctx.set_kernel_timing(name == "blocks_fp64")
+        for it in range(steps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            phi, hist, st = mg.solve(x, 1.0 / n, "periodic", tol=1e-10, precision=prec, layout=layout,
+                                     block_n=block_n, ctx=ctx)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            if st != 0:
+                raise RuntimeError(f"{name}: status {st}, hist {hist}")
+            if it > 0:
+                lat.append((t1 - t0) * 1e3)
+                cyc.extend(ctx.last_timing()[2])
+        rec = {"value": n ** 3 / (statistics.median(cyc) * 1e-3) / 1e9, "unit": "GDoF/s per V-cycle",
+               "cycle_ms_median": statistics.median(cyc), "cycles": len(hist) - 1,
+               "solve_ms": {"p50": pct(lat, 0.5), "p99": pct(lat, 0.99)}}
+        if name == "dense_fp64":
+            phi_dense = phi
+        else:
+            phi_d = mg.from_blocks(phi, n, block_n)
+            rec["rel_diff_vs_dense"] = float(torch.linalg.norm(phi_d - phi_dense) / torch.linalg.norm(phi_dense))
+        if name == "blocks_fp64":
+            rec["kernels"] = [{"kernel": k["name"], "launches": k["launches"],
+                               "avg_launch_ms": k["total_ms"] / max(k["launches"], 1),
+                               "achieved_GBs": k["bytes_per_launch"] * k["launches"] / (k["total_ms"] * 1e-3) / 1e9}
+                              for k in ctx.kernel_timing()]
+        out[name] = rec
+        print(f"# batched {name}: {rec['value']:.2f} GDoF/s per V-cycle, {rec['cycles']} cycles",
+              file=sys.stderr, flush=True)
+    ctx.set_kernel_timing(False)
+    return out
+
+
 def serving_leg(n_requests: int, workers: int, seed: int):
     """Mixed-size request stream (sizes 64-512, periodic / fixed / multipole faces, Poisson
     arrivals) through the native serving runtime: first all requests at once (saturated
@@ -163,6 +221,7 @@ def main() -> int:
     ap.add_argument("--serve-requests", type=int, default=240,
                     help="requests per serving run (0: skip the serving leg)")
     ap.add_argument("--serve-workers", type=int, default=4)
+    ap.add_argument("--no-batched", action="store_true", help="skip the MeshBlock (4096 x 16^3) leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device to device (reference for profiler byte counters)")
     args = ap.parse_args()
@@ -244,6 +303,8 @@ def main() -> int:
                         "ms_per_step": statistics.mean(lat_m), "cycles_per_solve": len(hists_m[-1]) - 1,
                         "cycle_ms_median": tvm,
                         "solve_latency_ms": {"p50": pct(lat_m, 0.5), "p99": pct(lat_m, 0.99)}}
+    if not args.no_batched:
+        out["batched"] = batched_leg(args.steps, args.seed)
     if args.serve_requests > 0:
         out["serving"] = serving_leg(args.serve_requests, args.serve_workers, args.seed)
     if not args.no_cpu_baseline:
