@@ -117,18 +117,23 @@ size_t mg_footprint_bytes(const mg_params *p);
  * device cannot hold it (the previous workspace is then released). */
 int mg_ctx_reserve(mg_ctx *ctx, const mg_params *p);
 
-/* Autotuner of the MeshBlock layout (layout = MG_LAYOUT_BLOCKS): for every block level of a
- * solve with these parameters, times each schedule of the block sweep (threads per
- * workgroup, blocks staged per workgroup, one or two sweeps fused per launch) over `reps`
- * launches on scratch arrays and keeps the fastest in the context; later solves use it.
- * Every schedule gives bitwise the same result.  Allocates and frees its own scratch
- * (3 n^3 arrays); synchronises the device.  No-op for the dense layout. */
+/* Autotuner.  For every level of a solve with these parameters it times the alternative
+ * schedules over `reps` launches on scratch arrays and keeps the fastest in the context;
+ * later solves use it.
+ *   MG_LAYOUT_BLOCKS: the block sweep (threads per workgroup, blocks staged per workgroup,
+ *     one or two sweeps fused per launch).  Every schedule gives bitwise the same result.
+ *   MG_LAYOUT_DENSE (n >= 64): whether the restricted defect (and, on the FP64 finest level,
+ *     the residual norm) is fused into the last smoothing pass or runs as its own streaming
+ *     pass.  The two differ only in floating-point contraction (same expressions).
+ * Allocates and frees its own scratch (3 n^3 arrays); synchronises its own stream. */
 int mg_autotune(mg_ctx *ctx, const mg_params *p, int reps);
 
 /* The context's schedules as text, one line each: "blk fp64|fp32 Lm Lb threads G S"
- * (Lm = log2 block side on that level, Lb = log2 blocks per side).  Writes at most cap bytes
- * (NUL-terminated) and returns the length needed including the NUL.  mg_tuning_set reads the
- * same format (e.g. from a cache file) and rejects schedules the device cannot run. */
+ * (Lm = log2 block side on that level, Lb = log2 blocks per side) and
+ * "pass fp64|fp32 l split" (level l = log2 n_l; split bit 0: defect pass separate, bit 1:
+ * norm pass separate).  Writes at most cap bytes (NUL-terminated) and returns the length
+ * needed including the NUL.  mg_tuning_set reads the same format (e.g. from a cache file)
+ * and rejects schedules the device cannot run. */
 int mg_tuning_get(const mg_ctx *ctx, char *buf, int cap);
 int mg_tuning_set(mg_ctx *ctx, const char *text);
 

@@ -117,16 +117,17 @@ class Context:
         self.check(self._lib.mg_ctx_reserve(self.handle, ctypes.byref(p)), "mg_ctx_reserve")
 
     def autotune(self, n: int, block_n: int = 16, precision: str = "fp64", reps: int = 5,
-                 cache: Optional[str] = None) -> str:
-        """Pick the block-sweep schedules of MeshBlock-layout solves of this shape (see
-        mg_autotune).  With ``cache`` (a JSON file) a stored result for this device and shape
-        is loaded instead of timing, and a new result is stored.  Returns the schedule text."""
+                 cache: Optional[str] = None, layout: str = "blocks") -> str:
+        """Pick the schedules of solves of this shape (see mg_autotune): block-sweep shapes for
+        the MeshBlock layout, defect/norm pass fusion for the dense layout.  With ``cache`` (a
+        JSON file) a stored result for this device and shape is loaded instead of timing, and
+        a new result is stored.  Returns the context's schedule text."""
         import json
         import os
         key = None
         if cache:
             import torch
-            key = f"{torch.cuda.get_device_name(self.device)}|n={n}|block_n={block_n}|{precision}"
+            key = f"{torch.cuda.get_device_name(self.device)}|n={n}|{layout}|block_n={block_n}|{precision}"
             try:
                 with open(cache) as fh:
                     stored = json.load(fh)
@@ -135,7 +136,7 @@ class Context:
             if key in stored:
                 self.set_tuning(stored[key])
                 return stored[key]
-        p = params(n, 1.0 / n, precision=precision, layout="blocks", block_n=block_n)
+        p = params(n, 1.0 / n, precision=precision, layout=layout, block_n=block_n)
         self.check(self._lib.mg_autotune(self.handle, ctypes.byref(p), int(reps)), "mg_autotune")
         text = self.tuning()
         if cache:

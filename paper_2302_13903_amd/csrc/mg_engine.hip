@@ -54,6 +54,10 @@ struct mg_ctx {
   size_t op_scratch_cap = 0;
   // block-sweep schedules chosen by mg_autotune (or set), keyed by (precision, Lm, Lb)
   std::map<int, BlkTune> blk_tune;
+  // dense fused passes: whether the restricted defect (bit 0) and the finest-level norm
+  // (bit 1) run fused into the last smoothing pass or as separate defect-only passes,
+  // keyed by (precision, level); absent = the default of split_default()
+  std::map<int, int> pass_split;
 };
 
 namespace {
@@ -243,6 +247,16 @@ struct Solver {
     launch_tail<T>(a, s);
   }
 
+  // Fusion schedule of level l's defect stages: bit 0 = restricted defect as its own pass,
+  // bit 1 = norm as its own pass.  FP64 default: separate (the fused FP64 passes run short of
+  // registers); FP32 default: fused.
+  template <typename T>
+  int split_of(int l) const {
+    auto it = c->pass_split.find((sizeof(T) == 8 ? 0 : 1000) + l);
+    if (it != c->pass_split.end()) return it->second;
+    return sizeof(T) == 8 ? 3 : 0;
+  }
+
   // Alg. 1 on level l (l >= T_top).  At the tail level the whole remaining recursion runs in
   // one LDS-resident workgroup.  Large levels run four fused passes (sweep; sweep + restricted
   // defect; prolonged correction + sweep; sweep [+ defect norm]).  Returns true when the sum
@@ -258,17 +272,26 @@ struct Solver {
     const bool timed = top_call && l == H.L && c->ktiming;
     const double cellsT = (double)cells(l) * sizeof(T);
     if (use_fused && H.u2[l]) {
+      const int split = split_of<T>(l);
+      const bool sdef = (split & 1) != 0, snorm = (split & 2) != 0;
       T* cur = H.u[l];
       T* oth = H.u2[l];
       for (int it = 0; it < H.npre; ++it) {
-        const bool last = it == H.npre - 1;
+        const bool fuse = it == H.npre - 1 && !sdef;
         if (timed) kernel_begin();
-        if (last) fused_sweep_defect<T>(cur, oth, H.f[l], H.f[l - 1], H.u[l - 1], n, h, H.omega, bc, s);
+        if (fuse) fused_sweep_defect<T>(cur, oth, H.f[l], H.f[l - 1], H.u[l - 1], n, h, H.omega, bc, s);
         else fused_sweep<T>(cur, oth, H.f[l], n, h, H.omega, bc, s);
-        if (timed) kernel_end(fused_pass_name<T>(false, last ? 1 : 0), 3 * cellsT + (last ? cellsT / 4 : 0.0));
+        if (timed) kernel_end(fused_pass_name<T>(false, fuse ? 1 : 0), 3 * cellsT + (fuse ? cellsT / 4 : 0.0));
         std::swap(cur, oth);
       }
-      if (H.npre == 0) launch_defect_restrict<T>(cur, H.f[l], H.f[l - 1], H.u[l - 1], n, h, bc, s);
+      if (H.npre == 0) {
+        launch_defect_restrict<T>(cur, H.f[l], H.f[l - 1], H.u[l - 1], n, h, bc, s);
+      } else if (sdef) {
+        if (timed) kernel_begin();
+        fused_defect_restrict<T>(cur, H.f[l], H.f[l - 1], H.u[l - 1], n, h, bc, s);
+        // algorithmic bytes: u and f read, coarse source and correction written
+        if (timed) kernel_end(fused_pass_name<T>(false, 1, false), 2 * cellsT + cellsT / 4);
+      }
       vcycle(H, l - 1, H.hom, false, false);
       bool normed = false;
       if (H.npost == 0) launch_prolong<T>(H.u[l - 1], cur, n / 2, H.hom, 0, s);
@@ -278,7 +301,7 @@ struct Solver {
         if (it == 0) {
           fused_prolong_sweep<T>(cur, oth, H.f[l], H.u[l - 1], H.hom, n, h, H.omega, bc, s);
           if (timed) kernel_end(fused_pass_name<T>(true, 0), 3 * cellsT + cellsT / 8);
-        } else if (last && want_norm) {
+        } else if (last && want_norm && !snorm) {
           const int np = fused_sweep_norm<T>(cur, oth, H.f[l], c->part, n, h, H.omega, bc, s);
           if (timed) kernel_end(fused_pass_name<T>(false, 2), 3 * cellsT);
           launch_sum_partials(c->part, np, c->scal + 2, s);
@@ -288,6 +311,13 @@ struct Solver {
           if (timed) kernel_end(fused_pass_name<T>(false, 0), 3 * cellsT);
         }
         std::swap(cur, oth);
+      }
+      if (want_norm && !normed && sizeof(T) == 8) {
+        if (timed) kernel_begin();
+        const int np = fused_defect_norm<T>(cur, H.f[l], c->part, n, h, bc, s);
+        if (timed) kernel_end(fused_pass_name<T>(false, 2, false), 2 * cellsT);
+        launch_sum_partials(c->part, np, c->scal + 2, s);
+        normed = true;
       }
       if (cur != H.u[l]) (void)hipMemcpyAsync(H.u[l], cur, cells(l) * sizeof(T), hipMemcpyDeviceToDevice, s);
       return normed;
@@ -829,6 +859,69 @@ int autotune_blocks(mg_ctx* c, const mg_params* p, int Lb, int reps) {
   return MG_OK;
 }
 
+// Dense layout: for each fused level, time the restricted defect fused into the last
+// pre-smoothing pass against a plain sweep followed by the defect-only pass (and, for the FP64
+// finest level, the same for the norm), and keep the faster schedule.
+template <typename T>
+int autotune_dense(mg_ctx* c, const mg_params* p, int reps) {
+  const int L = ilog2(p->n);
+  const size_t cellsL = cells(L);
+  T* buf[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  const size_t sz[5] = {cellsL, cellsL, cellsL, cellsL / 8, cellsL / 8};
+  for (int q = 0; q < 5; ++q)
+    if (hipMalloc((void**)&buf[q], sz[q] * sizeof(T)) != hipSuccess) {
+      (void)hipGetLastError();
+      for (auto& b : buf)
+        if (b) (void)hipFree(b);
+      return fail(c, MG_ERR_OOM, "autotune scratch allocation failed");
+    }
+  hipStream_t s = nullptr;
+  HIP_CHECK(c, hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  for (int q = 0; q < 5; ++q) HIP_CHECK(c, hipMemsetAsync(buf[q], 0, sz[q] * sizeof(T), s));
+  hipEvent_t e0, e1;
+  HIP_CHECK(c, hipEventCreate(&e0));
+  HIP_CHECK(c, hipEventCreate(&e1));
+  LevelBC bc;
+  for (int f = 0; f < 6; ++f) { bc.kind[f] = BC_PERIODIC; bc.b[f] = nullptr; }
+  auto time_it = [&](auto&& body) -> double {
+    body();
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps; ++r) body();
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    return elapsed(e0, e1) / reps;
+  };
+  for (int l = ilog2(kFusedMinN); l <= L; ++l) {
+    const int n = 1 << l;
+    const double h = p->dx * (double)(1LL << (L - l));
+    const double t_fused = time_it([&] {
+      fused_sweep_defect<T>(buf[0], buf[1], buf[2], buf[3], buf[4], n, h, p->omega, bc, s);
+    });
+    const double t_split = time_it([&] {
+      fused_sweep<T>(buf[0], buf[1], buf[2], n, h, p->omega, bc, s);
+      fused_defect_restrict<T>(buf[1], buf[2], buf[3], buf[4], n, h, bc, s);
+    });
+    int split = t_split < t_fused ? 1 : 0;
+    if (sizeof(T) == 8 && l == L) {
+      const double t_nf = time_it([&] {
+        (void)fused_sweep_norm<T>(buf[0], buf[1], buf[2], c->part, n, h, p->omega, bc, s);
+      });
+      const double t_ns = time_it([&] {
+        fused_sweep<T>(buf[0], buf[1], buf[2], n, h, p->omega, bc, s);
+        (void)fused_defect_norm<T>(buf[1], buf[2], c->part, n, h, bc, s);
+      });
+      if (t_ns < t_nf) split |= 2;
+    }
+    HIP_CHECK(c, hipGetLastError());
+    c->pass_split[(sizeof(T) == 8 ? 0 : 1000) + l] = split;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(s);
+  for (auto& b : buf) (void)hipFree(b);
+  return MG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -842,7 +935,10 @@ int mg_autotune(mg_ctx* c, const mg_params* p, int reps) {
   if (reps < 1 || reps > 1000) return fail(c, MG_ERR_INVALID_ARG, "reps in 1..1000");
   HIP_CHECK(c, hipSetDevice(c->device));
   const int Lb = layout_lb(p);
-  if (Lb < 0) return MG_OK;   // the dense passes have fixed shapes
+  if (Lb < 0) {
+    if (p->n < kFusedMinN) return MG_OK;
+    return p->precision == MG_PREC_MIXED ? autotune_dense<float>(c, p, reps) : autotune_dense<double>(c, p, reps);
+  }
   st = p->precision == MG_PREC_MIXED ? autotune_blocks<float>(c, p, Lb, reps) : autotune_blocks<double>(c, p, Lb, reps);
   return st;
 }
@@ -855,6 +951,8 @@ int mg_tuning_get(const mg_ctx* c, char* buf, int cap) {
     o << "blk " << (key >= 1000 ? "fp32" : "fp64") << " " << (key % 1000) / 100 << " " << key % 100 << " "
       << kv.second.threads << " " << kv.second.G << " " << kv.second.S << "\n";
   }
+  for (const auto& kv : c->pass_split)
+    o << "pass " << (kv.first >= 1000 ? "fp32" : "fp64") << " " << kv.first % 1000 << " " << kv.second << "\n";
   const std::string t = o.str();
   if (buf && cap > 0) {
     std::strncpy(buf, t.c_str(), (size_t)cap - 1);
@@ -868,10 +966,19 @@ int mg_tuning_set(mg_ctx* c, const char* text) {
   std::istringstream in(text);
   std::string line;
   std::map<int, BlkTune> add;
+  std::map<int, int> add_pass;
   while (std::getline(in, line)) {
     if (line.empty()) continue;
     std::istringstream ls(line);
     std::string tag, prec;
+    if (line.rfind("pass ", 0) == 0) {
+      int l, split;
+      if (!(ls >> tag >> prec >> l >> split) || (prec != "fp64" && prec != "fp32") || l < 0 || l > 11 || split < 0 ||
+          split > 3)
+        return fail(c, MG_ERR_INVALID_ARG, "bad tuning line: " + line);
+      add_pass[(prec == "fp64" ? 0 : 1000) + l] = split;
+      continue;
+    }
     int Lm, Lb, threads, G, S;
     if (!(ls >> tag >> prec >> Lm >> Lb >> threads >> G >> S) || tag != "blk" || (prec != "fp64" && prec != "fp32"))
       return fail(c, MG_ERR_INVALID_ARG, "bad tuning line: " + line);
@@ -881,6 +988,7 @@ int mg_tuning_set(mg_ctx* c, const char* text) {
     add[(prec == "fp64" ? 0 : 1000) + 100 * Lm + Lb] = t;
   }
   for (const auto& kv : add) c->blk_tune[kv.first] = kv.second;
+  for (const auto& kv : add_pass) c->pass_split[kv.first] = kv.second;
   return MG_OK;
 }
 

@@ -45,11 +45,19 @@ int fused_sweep_norm(const T* uin, T* uout, const T* f, double* part, int n, dou
 int fused_mixed_update_defect(double* phi_in, double* phi_out, const float* e, const double* f, float* r32,
                               double* part, int n, double h, const LevelBC& bc, hipStream_t s);
 
+// Defect-only streaming passes over the input u (nothing swept, u not written):
+// the defect restricted into fc with uc0 cleared (Alg. 1 steps 2-3) ...
+template <typename T>
+void fused_defect_restrict(const T* u, const T* f, T* fc, T* uc0, int n, double h, const LevelBC& bc, hipStream_t s);
+// ... or one partial sum of squared defects per block into part (returns their number).
+template <typename T>
+int fused_defect_norm(const T* u, const T* f, double* part, int n, double h, const LevelBC& bc, hipStream_t s);
+
 template <typename T>
 int fused_grid_blocks(int n, int hx, int hy);
 
-// Names of the pass kernels as the profiler lists them.
+// Names of the pass kernels as the profiler lists them (sweep = false: the defect-only pass).
 template <typename T>
-std::string fused_pass_name(bool pro, int out);
+std::string fused_pass_name(bool pro, int out, bool sweep = true);
 
 }  // namespace mg

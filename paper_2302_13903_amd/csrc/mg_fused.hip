@@ -95,11 +95,20 @@ struct alignas(2 * sizeof(T)) Pair {
   T a, b;
 };
 
-// MIX (no sweep, OUT = 2): u = u + e32 on load, then the defect of the updated u, its sum of
-// squares and its FP32 copy -- the FP64 part of one mixed-precision defect-correction step.
-template <typename T, int R, int W, bool PRO, int OUT, bool MIX = false>
+// MODE selects the pass body:
+//   MODE_SWEEP : one smoothing sweep, then the OUT stage on the swept u;
+//   MODE_MIX   : no sweep, OUT = 2: u = u + e32 on load, written out, then the defect of the
+//                updated u, its sum of squares and its FP32 copy -- the FP64 part of one
+//                mixed-precision defect-correction step;
+//   MODE_DEF   : no sweep, u is not written: only the OUT stage on the input u (the defect
+//                restricted to the coarse level, or its sum of squares).
+enum : int { MODE_SWEEP = 0, MODE_MIX = 1, MODE_DEF = 2 };
+
+template <typename T, int R, int W, bool PRO, int OUT, int MODE = MODE_SWEEP>
 __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
-  constexpr bool SWEEP = !MIX;
+  constexpr bool SWEEP = MODE == MODE_SWEEP;
+  constexpr bool MIX = MODE == MODE_MIX;
+  constexpr bool WRITE_U = MODE != MODE_DEF;
   constexpr int DLAG = SWEEP ? 3 : 1;                  // the defect runs on plane P - DLAG
   constexpr int HZ = OUT ? DLAG : 2;                   // z planes loaded ahead of the chunk
   constexpr int kRing = OUT ? DLAG + 2 : 4;            // u planes alive
@@ -379,7 +388,7 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
         half_sweep(u[s2], u[s1], u[k], P - 1, 0);
         half_sweep(u[s3], u[s2], u[s1], P - 2, 1);
       }
-      {
+      if (WRITE_U) {
         constexpr int sf = SWEEP ? s2 : k;     // slot of the plane that is final this step
         const int p = SWEEP ? P - 2 : P;
         if (p >= z0 && p < zend && out_x) {
@@ -448,9 +457,9 @@ int zchunk_for(int n) {
   return 16;
 }
 
-template <typename T, bool PRO, int OUT, bool MIX = false>
+template <typename T, bool PRO, int OUT, int MODE = MODE_SWEEP>
 void launch_pass(FusedArgs A, hipStream_t s) {
-  constexpr int R = Cfg<T, OUT>::R, W = Cfg<T, OUT>::W;
+  constexpr int R = MODE == MODE_SWEEP ? Cfg<T, OUT>::R : 2, W = MODE == MODE_SWEEP ? Cfg<T, OUT>::W : 16;
   A.xo = kTileX - 2 * A.hx;
   A.yo = R * W - 2 * A.hy;
   A.zc = min(zchunk_for(A.n), A.n);
@@ -459,7 +468,7 @@ void launch_pass(FusedArgs A, hipStream_t s) {
   A.chunks_z = (A.n + A.zc - 1) / A.zc;
   A.ntiles = A.tiles_x * A.tiles_y * A.chunks_z;
   const int grid = (A.ntiles + 7) / 8 * 8;
-  hipLaunchKernelGGL((k_fused<T, R, W, PRO, OUT, MIX>), dim3(grid), dim3(kLanes * W), 0, s, A);
+  hipLaunchKernelGGL((k_fused<T, R, W, PRO, OUT, MODE>), dim3(grid), dim3(kLanes * W), 0, s, A);
 }
 
 template <typename T>
@@ -519,7 +528,8 @@ void fused_prolong_sweep(const T* uin, T* uout, const T* f, const T* ec, const L
 
 template <typename T>
 int fused_grid_blocks(int n, int hx, int hy) {
-  constexpr int R = Cfg<T, 2>::R, W = Cfg<T, 2>::W;   // the norm pass's tiling
+  constexpr int R = 2, W = 16;   // the tiling of every pass with a norm (Cfg<T, 2>, no-sweep modes)
+  static_assert(Cfg<T, 2>::R == R && Cfg<T, 2>::W == W, "norm passes share one tiling");
   const int xo = kTileX - 2 * hx, yo = R * W - 2 * hy, zc = min(zchunk_for(n), n);
   const int nt = ((n + xo - 1) / xo) * ((n + yo - 1) / yo) * ((n + zc - 1) / zc);
   return (nt + 7) / 8 * 8;
@@ -544,16 +554,38 @@ int fused_mixed_update_defect(double* phi_in, double* phi_out, const float* e, c
   A.part = part;
   A.e32 = e;
   A.r32 = r32;
-  launch_pass<double, false, 2, true>(A, s);
+  launch_pass<double, false, 2, MODE_MIX>(A, s);
   return fused_grid_blocks<double>(n, 2, 1);
 }
 
 template <typename T>
-std::string fused_pass_name(bool pro, int out) {
-  const int R = out == 1 ? Cfg<T, 1>::R : out == 2 ? Cfg<T, 2>::R : Cfg<T, 0>::R;
-  const int W = out == 1 ? Cfg<T, 1>::W : out == 2 ? Cfg<T, 2>::W : Cfg<T, 0>::W;
+void fused_defect_restrict(const T* u, const T* f, T* fc, T* uc0, int n, double h, const LevelBC& bc, hipStream_t s) {
+  FusedArgs A = base_args(u, (T*)nullptr, f, n, h, 1.0, bc);
+  A.hx = 2;   // defect only: radius 1, rounded up to even
+  A.hy = 2;   // even, so that restriction row pairs align
+  A.fc = fc;
+  A.uc0 = uc0;
+  launch_pass<T, false, 1, MODE_DEF>(A, s);
+}
+
+template <typename T>
+int fused_defect_norm(const T* u, const T* f, double* part, int n, double h, const LevelBC& bc, hipStream_t s) {
+  FusedArgs A = base_args(u, (T*)nullptr, f, n, h, 1.0, bc);
+  A.hx = 2;
+  A.hy = 1;
+  A.part = part;
+  launch_pass<T, false, 2, MODE_DEF>(A, s);
+  return fused_grid_blocks<T>(n, 2, 1);
+}
+
+template <typename T>
+std::string fused_pass_name(bool pro, int out, bool sweep) {
+  int R = out == 1 ? Cfg<T, 1>::R : out == 2 ? Cfg<T, 2>::R : Cfg<T, 0>::R;
+  int W = out == 1 ? Cfg<T, 1>::W : out == 2 ? Cfg<T, 2>::W : Cfg<T, 0>::W;
+  if (!sweep) { R = 2; W = 16; }
   return std::string("k_fused<") + (sizeof(T) == 8 ? "double" : "float") + ", " + std::to_string(R) + ", " +
-         std::to_string(W) + ", " + (pro ? "true" : "false") + ", " + std::to_string(out) + ", false>";
+         std::to_string(W) + ", " + (pro ? "true" : "false") + ", " + std::to_string(out) + ", " +
+         std::to_string(sweep ? MODE_SWEEP : MODE_DEF) + ">";
 }
 
 #define MG_FUSED_INST(T)                                                                                        \
@@ -566,7 +598,9 @@ std::string fused_pass_name(bool pro, int out) {
   template int fused_sweep_norm<T>(const T*, T*, const T*, double*, int, double, double, const LevelBC&,         \
                                    hipStream_t);                                                                \
   template int fused_grid_blocks<T>(int, int, int);                                                             \
-  template std::string fused_pass_name<T>(bool, int);
+  template void fused_defect_restrict<T>(const T*, const T*, T*, T*, int, double, const LevelBC&, hipStream_t);  \
+  template int fused_defect_norm<T>(const T*, const T*, double*, int, double, const LevelBC&, hipStream_t);       \
+  template std::string fused_pass_name<T>(bool, int, bool);
 
 MG_FUSED_INST(double)
 MG_FUSED_INST(float)

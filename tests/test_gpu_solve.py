@@ -166,3 +166,33 @@ def test_spectral_256(mg):
     f -= f.mean()
     ref = ex.spectral_solve(f, 1.0 / n, [PERIODIC] * 6)
     assert rel(phi.cpu().numpy(), ref) < 1e-9
+
+
+@pytest.mark.parametrize("kinds", ["periodic", [FIXED] * 6])
+def test_pass_fusion_schedules_agree(mg, kinds):
+    """The restricted defect and the norm fused into the last smoothing pass or run as their own
+    defect-only passes: the same expressions of the same values, so the same result up to
+    floating-point contraction, and both equal to the oracle."""
+    n = 128
+    rho = wl.gaussian_clumps(n, 31, remove_mean=kinds == "periodic")
+    ref, rh, _ = oracle.solve(rho, 1.0 / n, kinds, fixed_cycles=4)
+    out = {}
+    for name, split in (("fused", 0), ("split", 3)):
+        ctx = mg.Context(0)
+        ctx.set_tuning("".join(f"pass fp64 {l} {split}\n" for l in (6, 7)))
+        phi, hist, st = mg.solve(dev(rho), 1.0 / n, kinds, fixed_cycles=4, ctx=ctx)
+        out[name] = (phi.cpu().numpy(), hist)
+        assert rel(out[name][0], ref) < 1e-10, name
+        hist_close(hist, rh, residual_floor(ref, rho, kinds == "periodic"))
+    assert rel(out["fused"][0], out["split"][0]) < 1e-13
+
+
+def test_dense_autotune_sets_pass_schedules(mg):
+    ctx = mg.Context(0)
+    text = ctx.autotune(128, precision="fp64", reps=2, layout="dense")
+    lines = [l.split() for l in text.strip().splitlines() if l.startswith("pass")]
+    assert {int(l[2]) for l in lines} == {6, 7}
+    rho = wl.gaussian_clumps(128, 4)
+    a, ah, _ = mg.solve(dev(rho), 1.0 / 128, "periodic", fixed_cycles=3, ctx=ctx)
+    b, bh, _ = mg.solve(dev(rho), 1.0 / 128, "periodic", fixed_cycles=3)
+    assert rel(a.cpu().numpy(), b.cpu().numpy()) < 1e-13
