@@ -124,14 +124,18 @@ int mg_ctx_reserve(mg_ctx *ctx, const mg_params *p);
  *     one or two sweeps fused per launch).  Every schedule gives bitwise the same result.
  *   MG_LAYOUT_DENSE (n >= 64): whether the restricted defect (and, on the FP64 finest level,
  *     the residual norm) is fused into the last smoothing pass or runs as its own streaming
- *     pass.  The two differ only in floating-point contraction (same expressions).
+ *     pass, and whether sweeps run one per pass or two per pass (temporally blocked).  The
+ *     alternatives differ only in floating-point contraction (same expressions).
  * Allocates and frees its own scratch (3 n^3 arrays); synchronises its own stream. */
 int mg_autotune(mg_ctx *ctx, const mg_params *p, int reps);
 
 /* The context's schedules as text, one line each: "blk fp64|fp32 Lm Lb threads G S"
  * (Lm = log2 block side on that level, Lb = log2 blocks per side) and
  * "pass fp64|fp32 l split" (level l = log2 n_l; split bit 0: defect pass separate, bit 1:
- * norm pass separate).  Writes at most cap bytes (NUL-terminated) and returns the length
+ * norm pass separate), "fusedmin fp64|fp32 n" (smallest level size swept by the fused
+ * z-marching passes, a power of two >= 64; smaller levels run one launch per operator) and
+ * "tail fp64|fp32 l" (highest level, 1..4, solved by the single-workgroup LDS tail) and
+ * "tb fp64|fp32 0|1" (1: large-level sweeps two per pass over HBM).  Writes at most cap bytes (NUL-terminated) and returns the length
  * needed including the NUL.  mg_tuning_set reads the same format (e.g. from a cache file)
  * and rejects schedules the device cannot run. */
 int mg_tuning_get(const mg_ctx *ctx, char *buf, int cap);

@@ -19,6 +19,7 @@
 #include "mg_blocks.h"
 #include "mg_fused.h"
 #include "mg_launch.h"
+#include "mg_tblock.h"
 
 using namespace mg;
 
@@ -58,6 +59,14 @@ struct mg_ctx {
   // (bit 1) run fused into the last smoothing pass or as separate defect-only passes,
   // keyed by (precision, level); absent = the default of split_default()
   std::map<int, int> pass_split;
+  // smallest level swept by the fused z-marching passes (smaller levels: one launch per
+  // operator) and highest level of the LDS coarse tail, per precision [0 = FP64, 1 = FP32];
+  // 0 = the built-in default
+  int fused_min_n[2] = {0, 0};
+  int tail_top[2] = {0, 0};
+  // large-level smoothing: 1 = temporally blocked passes (two sweeps per pass over HBM),
+  // 0 = one sweep per pass; -1 = the built-in default
+  int tblock[2] = {-1, -1};
 };
 
 namespace {
@@ -204,6 +213,10 @@ struct Solver {
   mg_ctx* c;
   hipStream_t s;
   bool use_fused = true;
+  int fused_min_n64 = kFusedDefaultMinN, fused_min_n32 = kFusedDefaultMinN;
+  // the next top-level V-cycle starts from u = 0 without u having been cleared: its first
+  // sweep must not read u (set by the caller, consumed by vcycle)
+  bool zero_start = false;
 
   void kernel_begin() {
     hipEvent_t e;
@@ -257,12 +270,29 @@ struct Solver {
     return sizeof(T) == 8 ? 3 : 0;
   }
 
+  template <typename T>
+  bool tblock_on() const {
+    const int v = c->tblock[sizeof(T) == 8 ? 0 : 1];
+    return v < 0 ? false : v == 1;
+  }
+
   // Alg. 1 on level l (l >= T_top).  At the tail level the whole remaining recursion runs in
   // one LDS-resident workgroup.  Large levels run four fused passes (sweep; sweep + restricted
   // defect; prolonged correction + sweep; sweep [+ defect norm]).  Returns true when the sum
   // of squared defects of the result is in c->scal[2] (want_norm on a fused finest level).
   template <typename T>
   bool vcycle(Hier<T>& H, int l, const LevelBC& bc, bool top_call, bool want_norm) {
+    if (top_call && zero_start) {
+      // only the one-sweep fused path starts with a plain sweep that can skip reading u;
+      // elsewhere u is cleared first
+      const bool fused_first = use_fused && H.u2[l] && l != H.T_top &&
+                               (1 << l) >= (sizeof(T) == 8 ? fused_min_n64 : fused_min_n32) && !tblock_on<T>() &&
+                               H.npre >= 1 && !(H.npre == 1 && !(split_of<T>(l) & 1));
+      if (!fused_first) {
+        (void)hipMemsetAsync(H.u[l], 0, cells(l) * sizeof(T), s);
+        zero_start = false;
+      }
+    }
     if (l == H.T_top) {
       tail(H, top_call ? TAIL_LOAD_U : 0, bc);
       return false;
@@ -271,16 +301,65 @@ struct Solver {
     const double h = H.h[l];
     const bool timed = top_call && l == H.L && c->ktiming;
     const double cellsT = (double)cells(l) * sizeof(T);
-    if (use_fused && H.u2[l]) {
+    if (use_fused && H.u2[l] && n >= (sizeof(T) == 8 ? fused_min_n64 : fused_min_n32) && tblock_on<T>()) {
+      // temporally blocked: sweeps two at a time per pass; the restricted defect and the norm
+      // as defect-only passes
+      T* cur = H.u[l];
+      T* oth = H.u2[l];
+      auto sweeps = [&](int count, const T* ec) {
+        int left = count;
+        while (left > 0) {
+          const int ns = left >= 2 ? 2 : 1;
+          if (timed) kernel_begin();
+          tb_sweeps<T>(cur, oth, H.f[l], ec, H.hom, ns, n, h, H.omega, bc, s);
+          if (timed) kernel_end(tb_name<T>(ns, ec != nullptr), 3 * cellsT + (ec ? cellsT / 8 : 0.0));
+          std::swap(cur, oth);
+          left -= ns;
+          ec = nullptr;
+        }
+      };
+      sweeps(H.npre, nullptr);
+      if (H.npre == 0) {
+        launch_defect_restrict<T>(cur, H.f[l], H.f[l - 1], H.u[l - 1], n, h, bc, s);
+      } else {
+        if (timed) kernel_begin();
+        fused_defect_restrict<T>(cur, H.f[l], H.f[l - 1], H.u[l - 1], n, h, bc, s);
+        if (timed) kernel_end(fused_pass_name<T>(false, 1, false), 2 * cellsT + cellsT / 4);
+      }
+      vcycle(H, l - 1, H.hom, false, false);
+      if (H.npost == 0) {
+        launch_prolong<T>(H.u[l - 1], cur, n / 2, H.hom, 0, s);
+      } else {
+        // the prolonged correction enters with the first sweep (one-sweep pass: the coarse
+        // taps leave no registers for a second), the remaining sweeps two per pass
+        if (timed) kernel_begin();
+        fused_prolong_sweep<T>(cur, oth, H.f[l], H.u[l - 1], H.hom, n, h, H.omega, bc, s);
+        if (timed) kernel_end(fused_pass_name<T>(true, 0), 3 * cellsT + cellsT / 8);
+        std::swap(cur, oth);
+        sweeps(H.npost - 1, nullptr);
+      }
+      bool normed = false;
+      if (want_norm && sizeof(T) == 8) {
+        if (timed) kernel_begin();
+        const int np = fused_defect_norm<T>(cur, H.f[l], c->part, n, h, bc, s);
+        if (timed) kernel_end(fused_pass_name<T>(false, 2, false), 2 * cellsT);
+        launch_sum_partials(c->part, np, c->scal + 2, s);
+        normed = true;
+      }
+      if (cur != H.u[l]) (void)hipMemcpyAsync(H.u[l], cur, cells(l) * sizeof(T), hipMemcpyDeviceToDevice, s);
+      return normed;
+    }
+    if (use_fused && H.u2[l] && n >= (sizeof(T) == 8 ? fused_min_n64 : fused_min_n32)) {
       const int split = split_of<T>(l);
       const bool sdef = (split & 1) != 0, snorm = (split & 2) != 0;
       T* cur = H.u[l];
       T* oth = H.u2[l];
       for (int it = 0; it < H.npre; ++it) {
         const bool fuse = it == H.npre - 1 && !sdef;
+        const bool zin = it == 0 && top_call && zero_start && !fuse;
         if (timed) kernel_begin();
         if (fuse) fused_sweep_defect<T>(cur, oth, H.f[l], H.f[l - 1], H.u[l - 1], n, h, H.omega, bc, s);
-        else fused_sweep<T>(cur, oth, H.f[l], n, h, H.omega, bc, s);
+        else fused_sweep<T>(zin ? nullptr : cur, oth, H.f[l], n, h, H.omega, bc, s);
         if (timed) kernel_end(fused_pass_name<T>(false, fuse ? 1 : 0), 3 * cellsT + (fuse ? cellsT / 4 : 0.0));
         std::swap(cur, oth);
       }
@@ -630,7 +709,9 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
   for (int f = 0; f < 6; ++f)
     if (bc->kind[f] == MG_BC_FIXED || bc->kind[f] == MG_BC_MULTIPOLE) gauge_free = false;
   const bool mixed = y.mixed;
-  const int tail_max = std::min(mixed ? 4 : c->tail64_top, Lb >= 0 ? Lb : 99);
+  int tail_max = mixed ? 4 : c->tail64_top;
+  if (c->tail_top[mixed ? 1 : 0] > 0) tail_max = std::min(tail_max, c->tail_top[mixed ? 1 : 0]);
+  tail_max = std::min(tail_max, Lb >= 0 ? Lb : 99);
 
   HIP_CHECK(c, hipEventRecord(c->ev0, s));
   HIP_CHECK(c, hipMemsetAsync(c->scal, 0, sizeof(double) * kScal, s));
@@ -654,6 +735,8 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
 
   Solver S{c, s, true};
   S.Lb = Lb;
+  if (c->fused_min_n[0] > 0) S.fused_min_n64 = c->fused_min_n[0];
+  if (c->fused_min_n[1] > 0) S.fused_min_n32 = c->fused_min_n[1];
   Hier<double> H64;
   Hier<float> H32;
   auto fill_common = [&](auto& H, int tail_top) {
@@ -746,8 +829,11 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
         if (L == H32.T_top) {
           S.tail(H32, 0, hom);
         } else {
-          HIP_CHECK(c, hipMemsetAsync(H32.u[L], 0, n3 * sizeof(float), s));
+          // the correction starts from zero: the first sweep does not read it (or the
+          // V-cycle clears it when its first pass cannot skip the read)
+          S.zero_start = true;
           S.vcycle(H32, L, hom, true, false);
+          S.zero_start = false;
         }
         if (phi_oth) {
           // phi += e and the FP64 defect (with its FP32 copy and norm) in one streaming pass
@@ -912,6 +998,17 @@ int autotune_dense(mg_ctx* c, const mg_params* p, int reps) {
       });
       if (t_ns < t_nf) split |= 2;
     }
+    if (l == L) {
+      // sweep fusion: two one-sweep passes against one temporally blocked two-sweep pass
+      const double t_one = time_it([&] {
+        fused_sweep<T>(buf[0], buf[1], buf[2], n, h, p->omega, bc, s);
+        fused_sweep<T>(buf[1], buf[0], buf[2], n, h, p->omega, bc, s);
+      });
+      const double t_two = time_it([&] {
+        tb_sweeps<T>(buf[0], buf[1], buf[2], nullptr, bc, 2, n, h, p->omega, bc, s);
+      });
+      c->tblock[sizeof(T) == 8 ? 0 : 1] = t_two < t_one ? 1 : 0;
+    }
     HIP_CHECK(c, hipGetLastError());
     c->pass_split[(sizeof(T) == 8 ? 0 : 1000) + l] = split;
   }
@@ -953,6 +1050,11 @@ int mg_tuning_get(const mg_ctx* c, char* buf, int cap) {
   }
   for (const auto& kv : c->pass_split)
     o << "pass " << (kv.first >= 1000 ? "fp32" : "fp64") << " " << kv.first % 1000 << " " << kv.second << "\n";
+  for (int q = 0; q < 2; ++q) {
+    if (c->fused_min_n[q] > 0) o << "fusedmin " << (q ? "fp32" : "fp64") << " " << c->fused_min_n[q] << "\n";
+    if (c->tail_top[q] > 0) o << "tail " << (q ? "fp32" : "fp64") << " " << c->tail_top[q] << "\n";
+    if (c->tblock[q] >= 0) o << "tb " << (q ? "fp32" : "fp64") << " " << c->tblock[q] << "\n";
+  }
   const std::string t = o.str();
   if (buf && cap > 0) {
     std::strncpy(buf, t.c_str(), (size_t)cap - 1);
@@ -967,10 +1069,32 @@ int mg_tuning_set(mg_ctx* c, const char* text) {
   std::string line;
   std::map<int, BlkTune> add;
   std::map<int, int> add_pass;
+  std::vector<std::pair<int, int>> add_misc;
   while (std::getline(in, line)) {
     if (line.empty()) continue;
     std::istringstream ls(line);
     std::string tag, prec;
+    if (line.rfind("tb ", 0) == 0) {
+      int v;
+      if (!(ls >> tag >> prec >> v) || (prec != "fp64" && prec != "fp32") || (v != 0 && v != 1))
+        return fail(c, MG_ERR_INVALID_ARG, "bad tuning line: " + line);
+      add_misc.push_back({4 + (prec == "fp64" ? 0 : 1), v});
+      continue;
+    }
+    if (line.rfind("fusedmin ", 0) == 0 || line.rfind("tail ", 0) == 0) {
+      int v;
+      if (!(ls >> tag >> prec >> v) || (prec != "fp64" && prec != "fp32"))
+        return fail(c, MG_ERR_INVALID_ARG, "bad tuning line: " + line);
+      const int q = prec == "fp64" ? 0 : 1;
+      if (tag == "fusedmin") {
+        if (!is_pow2(v) || v < kFusedMinN || v > 4096) return fail(c, MG_ERR_INVALID_ARG, "fusedmin: power of two >= 64");
+        add_misc.push_back({q, v});
+      } else {
+        if (v < 1 || v > 4) return fail(c, MG_ERR_INVALID_ARG, "tail: level 1..4");
+        add_misc.push_back({2 + q, v});
+      }
+      continue;
+    }
     if (line.rfind("pass ", 0) == 0) {
       int l, split;
       if (!(ls >> tag >> prec >> l >> split) || (prec != "fp64" && prec != "fp32") || l < 0 || l > 11 || split < 0 ||
@@ -989,6 +1113,11 @@ int mg_tuning_set(mg_ctx* c, const char* text) {
   }
   for (const auto& kv : add) c->blk_tune[kv.first] = kv.second;
   for (const auto& kv : add_pass) c->pass_split[kv.first] = kv.second;
+  for (const auto& kv : add_misc) {
+    if (kv.first < 2) c->fused_min_n[kv.first] = kv.second;
+    else if (kv.first < 4) c->tail_top[kv.first - 2] = kv.second;
+    else c->tblock[kv.first - 4] = kv.second;
+  }
   return MG_OK;
 }
 

@@ -12,13 +12,16 @@
 
 namespace mg {
 
-// Smallest level size handled by the fused passes (smaller levels use the per-operator kernels).
+// Smallest level size the fused passes can handle, and the smallest the solver uses them for
+// by default (below it a z-marching workgroup has too few planes and tiles to hide latency,
+// and one launch per operator is faster: measured on 512^3 V-cycles).
 constexpr int kFusedMinN = 64;
+constexpr int kFusedDefaultMinN = 256;
 
 template <typename T>
 bool fused_supported(int n);
 
-// One red-then-black sweep.
+// One red-then-black sweep.  uin == nullptr: u is zero on input (not read).
 template <typename T>
 void fused_sweep(const T* uin, T* uout, const T* f, int n, double h, double omega, const LevelBC& bc,
                  hipStream_t s);

@@ -179,7 +179,7 @@ def test_pass_fusion_schedules_agree(mg, kinds):
     out = {}
     for name, split in (("fused", 0), ("split", 3)):
         ctx = mg.Context(0)
-        ctx.set_tuning("".join(f"pass fp64 {l} {split}\n" for l in (6, 7)))
+        ctx.set_tuning("fusedmin fp64 64\n" + "".join(f"pass fp64 {l} {split}\n" for l in (6, 7)))
         phi, hist, st = mg.solve(dev(rho), 1.0 / n, kinds, fixed_cycles=4, ctx=ctx)
         out[name] = (phi.cpu().numpy(), hist)
         assert rel(out[name][0], ref) < 1e-10, name
@@ -189,6 +189,7 @@ def test_pass_fusion_schedules_agree(mg, kinds):
 
 def test_dense_autotune_sets_pass_schedules(mg):
     ctx = mg.Context(0)
+    ctx.set_tuning("fusedmin fp64 64\n")
     text = ctx.autotune(128, precision="fp64", reps=2, layout="dense")
     lines = [l.split() for l in text.strip().splitlines() if l.startswith("pass")]
     assert {int(l[2]) for l in lines} == {6, 7}
@@ -196,3 +197,93 @@ def test_dense_autotune_sets_pass_schedules(mg):
     a, ah, _ = mg.solve(dev(rho), 1.0 / 128, "periodic", fixed_cycles=3, ctx=ctx)
     b, bh, _ = mg.solve(dev(rho), 1.0 / 128, "periodic", fixed_cycles=3)
     assert rel(a.cpu().numpy(), b.cpu().numpy()) < 1e-13
+
+
+@pytest.mark.parametrize("fusedmin,tail", [(64, 4), (128, 3), (256, 2)])
+def test_level_schedules_agree(mg, fusedmin, tail):
+    """Where the fused passes start and how many levels the LDS tail holds change only the
+    launch structure, not the method: every schedule matches the oracle."""
+    n = 256
+    rho = wl.gaussian_clumps(n, 41, n_clumps=16, remove_mean=False)
+    faces = [np.full((n, n), -0.5)] * 6
+    ref, rh, _ = oracle.solve(rho, 1.0 / n, [FIXED] * 6, fixed_b=faces, fixed_cycles=3)
+    ctx = mg.Context(0)
+    ctx.set_tuning(f"fusedmin fp64 {fusedmin}\ntail fp64 {tail}\n")
+    phi, hist, st = mg.solve(dev(rho), 1.0 / n, [FIXED] * 6, fixed_b=[dev(b) for b in faces], fixed_cycles=3,
+                             ctx=ctx)
+    assert rel(phi.cpu().numpy(), ref) < 1e-10
+    hist_close(hist, rh, residual_floor(ref, rho, False))
+
+
+TB_KINDS = [
+    "periodic",
+    [FIXED] * 6,
+    [ZERO_GRADIENT] * 6,
+    [PERIODIC, PERIODIC, FIXED, FIXED, ZERO_GRADIENT, ZERO_GRADIENT],
+    [FIXED, ZERO_GRADIENT, ZERO_GRADIENT, FIXED, PERIODIC, PERIODIC],
+]
+
+
+@pytest.mark.parametrize("kinds", TB_KINDS)
+@pytest.mark.parametrize("n", [64, 128, 256])
+def test_temporal_blocking_matches_oracle(mg, kinds, n):
+    """Two sweeps per pass (temporally blocked) on every level from 64^3: the same V-cycles."""
+    print(f"tb fp64 n={n} kinds={kinds}", flush=True)
+    gauge_free = kinds == "periodic" or kinds == [ZERO_GRADIENT] * 6
+    rho = wl.gaussian_clumps(n, 50 + n, n_clumps=12, remove_mean=gauge_free)
+    faces = None
+    if not gauge_free:
+        rng = np.random.default_rng(n)
+        faces = [rng.normal(size=(n, n)) * 0.2 for _ in range(6)]
+    ref, rh, _ = oracle.solve(rho, 1.0 / n, kinds, fixed_b=faces, fixed_cycles=4)
+    ctx = mg.Context(0)
+    ctx.set_tuning("tb fp64 1\nfusedmin fp64 64\n")
+    dfaces = None if faces is None else [dev(b) for b in faces]
+    phi, hist, st = mg.solve(dev(rho), 1.0 / n, kinds, fixed_b=dfaces, fixed_cycles=4, ctx=ctx)
+    assert st == mg.MG_OK
+    assert rel(phi.cpu().numpy(), ref) < 1e-10
+    hist_close(hist, rh, residual_floor(ref, rho, gauge_free))
+
+
+@pytest.mark.parametrize("kinds", ["periodic", [FIXED] * 6])
+def test_temporal_blocking_mixed(mg, kinds):
+    print(f"tb mixed kinds={kinds}", flush=True)
+    n = 128
+    gauge_free = kinds == "periodic"
+    rho = wl.gaussian_clumps(n, 77, remove_mean=gauge_free)
+    ref, _, _ = oracle.solve(rho, 1.0 / n, kinds, tol=1e-13, max_cycles=40)
+    ctx = mg.Context(0)
+    ctx.set_tuning("tb fp32 1\nfusedmin fp32 64\n")
+    phi, hist, st = mg.solve(dev(rho), 1.0 / n, kinds, precision="mixed", tol=1e-11, max_cycles=40, ctx=ctx)
+    assert hist[-1] < 1e-10
+    assert rel(phi.cpu().numpy(), ref) < 1e-10
+
+
+@pytest.mark.parametrize("npre,npost", [(1, 1), (3, 2), (2, 3)])
+def test_temporal_blocking_odd_sweep_counts(mg, npre, npost):
+    """Sweep counts that are not pairs mix two-sweep and one-sweep passes."""
+    n = 64
+    rho = wl.gaussian_clumps(n, 9, remove_mean=True)
+    ref, rh, _ = oracle.solve(rho, 1.0 / n, "periodic", fixed_cycles=3, npre=npre, npost=npost)
+    ctx = mg.Context(0)
+    ctx.set_tuning("tb fp64 1\nfusedmin fp64 64\n")
+    phi, hist, st = mg.solve(dev(rho), 1.0 / n, "periodic", fixed_cycles=3, npre=npre, npost=npost, ctx=ctx)
+    assert rel(phi.cpu().numpy(), ref) < 1e-10
+    hist_close(hist, rh, residual_floor(ref, rho, True))
+
+
+@pytest.mark.parametrize("kinds", ["periodic", [FIXED] * 6])
+def test_mixed_zero_start_first_sweep(mg, kinds):
+    """The mixed inner V-cycle's first sweep skips reading the (zero) correction: results equal
+    those of the path that clears the correction first (one-sweep-per-pass vs blocked)."""
+    n = 256
+    gauge_free = kinds == "periodic"
+    rho = wl.gaussian_clumps(n, 13, remove_mean=gauge_free)
+    outs = []
+    for text in ("tb fp32 0\n", "tb fp32 1\n"):
+        ctx = mg.Context(0)
+        ctx.set_tuning(text)
+        phi, hist, st = mg.solve(dev(rho), 1.0 / n, kinds, precision="mixed", fixed_cycles=3, ctx=ctx)
+        outs.append((phi.cpu().numpy(), hist))
+    assert rel(outs[0][0], outs[1][0]) < 1e-12
+    assert np.allclose(outs[0][1], outs[1][1], rtol=1e-6)
