@@ -505,6 +505,9 @@ struct Solver {
     if (Lb >= 0) {
       const int np = blk_defect_norm(u, f, r32, ilog2(n) - Lb, Lb, h, bc, c->part, s);
       launch_sum_partials(c->part, np, out, s);
+    } else if (n >= kFusedMinN) {
+      const int np = fused_defect_norm<double>(u, f, c->part, n, h, bc, s, r32);
+      launch_sum_partials(c->part, np, out, s);
     } else {
       launch_defect_norm(u, f, r32, n, h, bc, c->part, out, s);
     }
@@ -727,8 +730,7 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
     HIP_CHECK(c, hipStreamSynchronize(s));
     shift = -p->four_pi_g * (c->hscal[0] / (double)n3);
   }
-  launch_source(rho, f64L, f32L, n3, p->four_pi_g, shift, s);
-  launch_sum(f64L, n3, 1, c->part, c->scal + 1, s);
+  launch_source(rho, f64L, f32L, n3, p->four_pi_g, shift, c->part, c->scal + 1, s);
 
   LevelBC phys[16], hom;
   setup_faces(c, y, p, bc, rho, s, phys, &hom);
@@ -823,7 +825,7 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
         S.defect_norm(phi, f64L, H32.f[L], p->n, p->dx, phys[L], c->scal + 2);
       } else if (!mixed) {
         const bool normed = S.vcycle(H64, L, phys[L], true, true);
-        if (!normed) launch_defect_norm(phi, f64L, nullptr, p->n, p->dx, phys[L], c->part, c->scal + 2, s);
+        if (!normed) S.defect_norm(phi, f64L, nullptr, p->n, p->dx, phys[L], c->scal + 2);
       } else {
         // defect correction: e32 solves L e = r32 from zero with homogeneous conditions
         if (L == H32.T_top) {
@@ -843,7 +845,7 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
           std::swap(phi_cur, phi_oth);
         } else {
           launch_add_f32(phi, H32.u[L], n3, s);
-          launch_defect_norm(phi, f64L, H32.f[L], p->n, p->dx, phys[L], c->part, c->scal + 2, s);
+          S.defect_norm(phi, f64L, H32.f[L], p->n, p->dx, phys[L], c->scal + 2);
         }
       }
       HIP_CHECK(c, hipEventRecord(c->ev_cycle[cyc], s));

@@ -52,9 +52,12 @@ int fused_mixed_update_defect(double* phi_in, double* phi_out, const float* e, c
 // the defect restricted into fc with uc0 cleared (Alg. 1 steps 2-3) ...
 template <typename T>
 void fused_defect_restrict(const T* u, const T* f, T* fc, T* uc0, int n, double h, const LevelBC& bc, hipStream_t s);
-// ... or one partial sum of squared defects per block into part (returns their number).
+// ... or one partial sum of squared defects per block into part (returns their number),
+// with the defect's FP32 copy into r32 when given (the right-hand side of a mixed-precision
+// correction cycle).
 template <typename T>
-int fused_defect_norm(const T* u, const T* f, double* part, int n, double h, const LevelBC& bc, hipStream_t s);
+int fused_defect_norm(const T* u, const T* f, double* part, int n, double h, const LevelBC& bc, hipStream_t s,
+                      float* r32 = nullptr);
 
 template <typename T>
 int fused_grid_blocks(int n, int hx, int hy);

@@ -343,7 +343,7 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
           row_defect(r, d);
           if (out_z && out_x && out_y[r]) {
             acc += (double)d[0] * (double)d[0] + (double)d[1] * (double)d[1];
-            if (MIX) {
+            if (MIX || (MODE == MODE_DEF && A.r32)) {
               const size_t off = ((size_t)(p & nm) << (2 * L)) + ((size_t)ygv[r] << L) + (size_t)xag;
               *reinterpret_cast<float2*>(A.r32 + off) = make_float2((float)d[0], (float)d[1]);
             }
@@ -575,11 +575,13 @@ void fused_defect_restrict(const T* u, const T* f, T* fc, T* uc0, int n, double 
 }
 
 template <typename T>
-int fused_defect_norm(const T* u, const T* f, double* part, int n, double h, const LevelBC& bc, hipStream_t s) {
+int fused_defect_norm(const T* u, const T* f, double* part, int n, double h, const LevelBC& bc, hipStream_t s,
+                      float* r32) {
   FusedArgs A = base_args(u, (T*)nullptr, f, n, h, 1.0, bc);
   A.hx = 2;
   A.hy = 1;
   A.part = part;
+  A.r32 = r32;
   launch_pass<T, false, 2, MODE_DEF>(A, s);
   return fused_grid_blocks<T>(n, 2, 1);
 }
@@ -605,7 +607,7 @@ std::string fused_pass_name(bool pro, int out, bool sweep) {
                                    hipStream_t);                                                                \
   template int fused_grid_blocks<T>(int, int, int);                                                             \
   template void fused_defect_restrict<T>(const T*, const T*, T*, T*, int, double, const LevelBC&, hipStream_t);  \
-  template int fused_defect_norm<T>(const T*, const T*, double*, int, double, const LevelBC&, hipStream_t);       \
+  template int fused_defect_norm<T>(const T*, const T*, double*, int, double, const LevelBC&, hipStream_t, float*); \
   template std::string fused_pass_name<T>(bool, int, bool);
 
 MG_FUSED_INST(double)

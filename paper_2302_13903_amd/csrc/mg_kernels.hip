@@ -429,21 +429,6 @@ size_t tail_lds_bytes(int top, size_t elem) {
 
 // ------------------------------------------------------------------ elementwise / set-up
 
-// f = a * rho + c (the source 4 pi G rho, mean-shifted when gauge-free), in FP64, plus the
-// FP32 copy when f32 != nullptr.
-__global__ void __launch_bounds__(kBlock) k_source(const double* __restrict__ rho, double* __restrict__ f,
-                                                    float* __restrict__ f32, size_t n3, double a, double c) {
-  const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
-  if (t >= n3) return;
-  const double v = a * rho[t] + c;
-  f[t] = v;
-  if (f32) f32[t] = (float)v;
-}
-
-void launch_source(const double* rho, double* f, float* f32, size_t n3, double a, double c, hipStream_t s) {
-  hipLaunchKernelGGL(k_source, dim3(grid_for(n3)), dim3(kBlock), 0, s, rho, f, f32, n3, a, c);
-}
-
 // u += shift (gauge fix, Sec. 2.3.6)
 __global__ void __launch_bounds__(kBlock) k_shift(double* __restrict__ u, size_t n3, const double* __restrict__ sum,
                                                    double scale) {
@@ -563,6 +548,31 @@ void launch_defect_norm(const double* u, const double* f, float* r32, int n, dou
   const int nb = reduce_blocks(n3);
   hipLaunchKernelGGL(k_defect_norm, dim3(nb), dim3(kBlock), 0, s, u, f, r32, n, L, 1.0 / (h * h), bc, part);
   hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBlock), 0, s, part, nb, 1, out, 1);
+}
+
+// f = a * rho + c (the source 4 pi G rho, mean-shifted when gauge-free), in FP64, plus the
+// FP32 copy when f32 != nullptr, and one partial sum of f^2 per block (fixed grid and tree,
+// so the sum is reproducible).
+__global__ void __launch_bounds__(kBlock) k_source(const double* __restrict__ rho, double* __restrict__ f,
+                                                    float* __restrict__ f32, size_t n3, double a, double c,
+                                                    double* __restrict__ part) {
+  __shared__ double red[kBlock / 64];
+  double acc = 0.0;
+  for (size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x; t < n3; t += (size_t)gridDim.x * kBlock) {
+    const double v = a * rho[t] + c;
+    f[t] = v;
+    if (f32) f32[t] = (float)v;
+    acc += v * v;
+  }
+  const double r = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+void launch_source(const double* rho, double* f, float* f32, size_t n3, double a, double c, double* part,
+                   double* sumsq, hipStream_t s) {
+  const int nb = reduce_blocks(n3);
+  hipLaunchKernelGGL(k_source, dim3(nb), dim3(kBlock), 0, s, rho, f, f32, n3, a, c, part);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBlock), 0, s, part, nb, 1, sumsq, 1);
 }
 
 // ------------------------------------------------------------------ boundary face arrays

@@ -54,7 +54,9 @@ size_t tail_lds_bytes(int top, size_t elem);
 // Allows the FP64 tail its dynamic LDS; returns the highest level it can hold (3 or 4).
 int tail_prepare(size_t lds_per_block);
 
-void launch_source(const double* rho, double* f, float* f32, size_t n3, double a, double c, hipStream_t s);
+// f = a rho + c (and its FP32 copy when f32 != nullptr); sumsq[0] = sum of f^2 (device)
+void launch_source(const double* rho, double* f, float* f32, size_t n3, double a, double c, double* part,
+                   double* sumsq, hipStream_t s);
 void launch_sub_mean(double* u, size_t n3, const double* sum_dev, hipStream_t s);
 void launch_f32_to_f64(const float* a, double* b, size_t n3, hipStream_t s);
 void launch_add_f32(double* phi, const float* e, size_t n3, hipStream_t s);
