@@ -121,7 +121,9 @@ int mg_ctx_reserve(mg_ctx *ctx, const mg_params *p);
  * schedules over `reps` launches on scratch arrays and keeps the fastest in the context;
  * later solves use it.
  *   MG_LAYOUT_BLOCKS: the block sweep (threads per workgroup, blocks staged per workgroup,
- *     one or two sweeps fused per launch).  Every schedule gives bitwise the same result.
+ *     one or two sweeps fused per launch; every such schedule gives bitwise the same result)
+ *     and, for block levels of at least 256 cells per side, whether the streaming z-marching
+ *     passes that cross block boundaries replace the per-block halo-tile sweeps.
  *   MG_LAYOUT_DENSE (n >= 64): whether the restricted defect (and, on the FP64 finest level,
  *     the residual norm) is fused into the last smoothing pass or runs as its own streaming
  *     pass, and whether sweeps run one per pass or two per pass (temporally blocked).  The
@@ -135,7 +137,8 @@ int mg_autotune(mg_ctx *ctx, const mg_params *p, int reps);
  * norm pass separate), "fusedmin fp64|fp32 n" (smallest level size swept by the fused
  * z-marching passes, a power of two >= 64; smaller levels run one launch per operator) and
  * "tail fp64|fp32 l" (highest level, 1..4, solved by the single-workgroup LDS tail) and
- * "tb fp64|fp32 0|1" (1: large-level sweeps two per pass over HBM).  Writes at most cap bytes (NUL-terminated) and returns the length
+ * "tb fp64|fp32 0|1" (1: large-level sweeps two per pass over HBM) and "blkz fp64|fp32 0|1"
+ * (MeshBlock layout, 1: streaming passes across blocks on the large block levels).  Writes at most cap bytes (NUL-terminated) and returns the length
  * needed including the NUL.  mg_tuning_set reads the same format (e.g. from a cache file)
  * and rejects schedules the device cannot run. */
 int mg_tuning_get(const mg_ctx *ctx, char *buf, int cap);

@@ -21,38 +21,6 @@ namespace {
 
 constexpr int kBlkThreads = 256;   // defect/restriction/prolongation/norm kernels
 
-__device__ __forceinline__ unsigned spread3(unsigned v) {
-  v &= 0x3ffu;
-  v = (v | (v << 16)) & 0x030000FFu;
-  v = (v | (v << 8)) & 0x0300F00Fu;
-  v = (v | (v << 4)) & 0x030C30C3u;
-  v = (v | (v << 2)) & 0x09249249u;
-  return v;
-}
-__device__ __forceinline__ unsigned compact3(unsigned v) {
-  v &= 0x09249249u;
-  v = (v | (v >> 2)) & 0x030C30C3u;
-  v = (v | (v >> 4)) & 0x0300F00Fu;
-  v = (v | (v >> 8)) & 0x030000FFu;
-  v = (v | (v >> 16)) & 0x3ffu;
-  return v;
-}
-__device__ __forceinline__ unsigned morton3(int bx, int by, int bz) {
-  return spread3((unsigned)bx) | (spread3((unsigned)by) << 1) | (spread3((unsigned)bz) << 2);
-}
-__device__ __forceinline__ void demorton3(unsigned b, int& bx, int& by, int& bz) {
-  bx = (int)compact3(b);
-  by = (int)compact3(b >> 1);
-  bz = (int)compact3(b >> 2);
-}
-
-// Storage index of global cell (i, j, k), all in [0, 2^(Lm+Lb)).
-__device__ __forceinline__ size_t bidx(int Lm, int i, int j, int k) {
-  const int mm = (1 << Lm) - 1;
-  return ((size_t)morton3(i >> Lm, j >> Lm, k >> Lm) << (3 * Lm)) |
-         (size_t)(((k & mm) << (2 * Lm)) | ((j & mm) << Lm) | (i & mm));
-}
-
 // Workgroups in a contiguous run per XCD (consecutive workgroups go round the 8 XCDs), so that
 // Morton-neighbouring blocks, which share halos, are swept by the same XCD and its L2.
 __device__ __forceinline__ unsigned xcd_remap(unsigned bid, unsigned nwg) {

@@ -35,6 +35,46 @@ __device__ __forceinline__ size_t cidx(int L, int i, int j, int k) {
   return ((size_t)k << (2 * L)) | ((size_t)j << L) | (size_t)i;
 }
 
+// ---- MeshBlock layout: blocks of 2^Lm cells per side, stored one after another in Morton
+// (Z-curve) order of their block coordinates (x bit lowest), each block dense, x fastest.
+__device__ __forceinline__ unsigned spread3(unsigned v) {
+  v &= 0x3ffu;
+  v = (v | (v << 16)) & 0x030000FFu;
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+__device__ __forceinline__ unsigned compact3(unsigned v) {
+  v &= 0x09249249u;
+  v = (v | (v >> 2)) & 0x030C30C3u;
+  v = (v | (v >> 4)) & 0x0300F00Fu;
+  v = (v | (v >> 8)) & 0x030000FFu;
+  v = (v | (v >> 16)) & 0x3ffu;
+  return v;
+}
+__device__ __forceinline__ unsigned morton3(int bx, int by, int bz) {
+  return spread3((unsigned)bx) | (spread3((unsigned)by) << 1) | (spread3((unsigned)bz) << 2);
+}
+__device__ __forceinline__ void demorton3(unsigned b, int& bx, int& by, int& bz) {
+  bx = (int)compact3(b);
+  by = (int)compact3(b >> 1);
+  bz = (int)compact3(b >> 2);
+}
+
+// Storage index of global cell (i, j, k), all in [0, 2^(Lm+Lb)), of a MeshBlock-layout level.
+__device__ __forceinline__ size_t bidx(int Lm, int i, int j, int k) {
+  const int mm = (1 << Lm) - 1;
+  return ((size_t)morton3(i >> Lm, j >> Lm, k >> Lm) << (3 * Lm)) |
+         (size_t)(((k & mm) << (2 * Lm)) | ((j & mm) << Lm) | (i & mm));
+}
+
+// Storage index of cell (i, j, k) of a level of 2^L cells per side: dense when Lm = 0 (the
+// dense layout, or a root grid), MeshBlock layout with 2^Lm-cell blocks otherwise.
+__device__ __forceinline__ size_t lidx(int L, int Lm, int i, int j, int k) {
+  return Lm == 0 ? cidx(L, i, j, k) : bidx(Lm, i, j, k);
+}
+
 // Value of a face-adjacent ghost for the 7-point stencil: `uc` is the boundary cell's own
 // value, `opp` points at the opposite active cell (read only for periodic faces).
 template <typename T>
@@ -63,9 +103,10 @@ __device__ __forceinline__ T neighbour_sum(const T* __restrict__ u, int n, int L
 // Value at (i, j, k) with each index in [-1, n], edges and corners included, under the rule
 // that ghosts are filled axis by axis (x, then y over the x ghosts, then z over both).  The
 // last-filled axis is resolved first; each step maps value = s * inner + t.
+// Lm > 0: u is a MeshBlock-layout level with 2^Lm-cell blocks.
 template <typename T>
 __device__ __forceinline__ T ghost_any(const T* __restrict__ u, int n, int L, int i, int j, int k,
-                                       const LevelBC& bc) {
+                                       const LevelBC& bc, int Lm = 0) {
   T s = (T)1, t = (T)0;
   if (k < 0 || k >= n) {
     const int face = k < 0 ? 4 : 5;
@@ -97,7 +138,7 @@ __device__ __forceinline__ T ghost_any(const T* __restrict__ u, int n, int L, in
       i = i < 0 ? 0 : n - 1;
     }
   }
-  return s * u[cidx(L, i, j, k)] + t;
+  return s * u[lidx(L, Lm, i, j, k)] + t;
 }
 
 // 1-D prolongation weights for coarse offsets -1, 0, +1 (Sec. 2.3.1): `upper` selects the

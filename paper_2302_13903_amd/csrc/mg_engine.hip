@@ -55,6 +55,9 @@ struct mg_ctx {
   size_t op_scratch_cap = 0;
   // block-sweep schedules chosen by mg_autotune (or set), keyed by (precision, Lm, Lb)
   std::map<int, BlkTune> blk_tune;
+  // MeshBlock layout: sweep the block levels of at least fused_min_n cells per side with the
+  // streaming z-marching passes (1) or with the per-block halo-tile sweeps (0); -1 = default
+  int blk_zmarch[2] = {-1, -1};
   // dense fused passes: whether the restricted defect (bit 0) and the finest-level norm
   // (bit 1) run fused into the last smoothing pass or as separate defect-only passes,
   // keyed by (precision, level); absent = the default of split_default()
@@ -477,12 +480,41 @@ struct Solver {
   // block level Lm = 1 is the root grid (gathered by the restriction, scattered by the
   // prolongation), solved by the dense recursion.
   template <typename T>
+  bool blk_zmarch_on(int l) const {
+    const int v = c->blk_zmarch[sizeof(T) == 8 ? 0 : 1];
+    return (v < 0 ? true : v == 1) && (1 << l) >= (sizeof(T) == 8 ? fused_min_n64 : fused_min_n32);
+  }
+
+  template <typename T>
   void vcycle_blk(Hier<T>& H, int l, const LevelBC& bc) {
     if (l <= Lb) {
       vcycle(H, l, bc, false, false);
       return;
     }
     const int Lm = l - Lb;
+    if (blk_zmarch_on<T>(l) && H.npre > 0 && H.npost > 0) {
+      // streaming passes across block boundaries: one sweep per pass, the restricted defect
+      // as its own pass, the prolonged correction entering with the first post-sweep
+      const bool timed = timed_top && l == H.L && c->ktiming;
+      const double cellsT = (double)cells(l) * sizeof(T);
+      T* cur = H.u[l];
+      T* oth = H.u2[l];
+      auto pass = [&](const T* ec) {
+        if (timed) kernel_begin();
+        fused_blk_sweep<T>(cur, oth, H.f[l], ec, H.hom, Lm, Lb, H.h[l], H.omega, bc, s);
+        if (timed) kernel_end(fused_blk_pass_name<T>(ec != nullptr, 0), 3 * cellsT + (ec ? cellsT / 8 : 0.0));
+        std::swap(cur, oth);
+      };
+      for (int it = 0; it < H.npre; ++it) pass(nullptr);
+      if (timed) kernel_begin();
+      fused_blk_defect_restrict<T>(cur, H.f[l], H.f[l - 1], H.u[l - 1], Lm, Lb, H.h[l], bc, s);
+      if (timed) kernel_end(fused_blk_pass_name<T>(false, 1), 2 * cellsT + cellsT / 4);
+      vcycle_blk(H, l - 1, H.hom);
+      pass(H.u[l - 1]);
+      for (int it = 1; it < H.npost; ++it) pass(nullptr);
+      if (cur != H.u[l]) (void)hipMemcpyAsync(H.u[l], cur, cells(l) * sizeof(T), hipMemcpyDeviceToDevice, s);
+      return;
+    }
     T* cur = blk_sweeps(H, l, H.u[l], H.npre, bc);
     blk_defect_restrict<T>(cur, H.f[l], H.f[l - 1], H.u[l - 1], Lm, Lb, H.h[l], bc, s);
     vcycle_blk(H, l - 1, H.hom);
@@ -502,7 +534,10 @@ struct Solver {
 
   // Sum of squared finest-level defects into out (device); optionally the FP32 defect.
   void defect_norm(const double* u, const double* f, float* r32, int n, double h, const LevelBC& bc, double* out) {
-    if (Lb >= 0) {
+    if (Lb >= 0 && n >= kFusedMinN) {
+      const int np = fused_blk_defect_norm<double>(u, f, c->part, ilog2(n) - Lb, Lb, h, bc, s, r32);
+      launch_sum_partials(c->part, np, out, s);
+    } else if (Lb >= 0) {
       const int np = blk_defect_norm(u, f, r32, ilog2(n) - Lb, Lb, h, bc, c->part, s);
       launch_sum_partials(c->part, np, out, s);
     } else if (n >= kFusedMinN) {
@@ -939,6 +974,16 @@ int autotune_blocks(mg_ctx* c, const mg_params* p, int Lb, int reps) {
           if (ms < best_ms) { best_ms = ms; best = t; }
         }
     c->blk_tune[(sizeof(T) == 8 ? 0 : 1000) + 100 * Lm + Lb] = best;
+    if (l == L && (1 << l) >= kFusedDefaultMinN) {
+      // the finest block level: halo-tile sweeps against the streaming passes across blocks
+      (void)hipEventRecord(e0, s);
+      for (int r = 0; r < reps; ++r)
+        fused_blk_sweep<T>(buf[r & 1], buf[(r + 1) & 1], buf[2], nullptr, bc, Lm, Lb, h, p->omega, bc, s);
+      (void)hipEventRecord(e1, s);
+      HIP_CHECK(c, hipEventSynchronize(e1));
+      const double t_z = elapsed(e0, e1) / reps;
+      c->blk_zmarch[sizeof(T) == 8 ? 0 : 1] = t_z < best_ms ? 1 : 0;
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1056,6 +1101,7 @@ int mg_tuning_get(const mg_ctx* c, char* buf, int cap) {
     if (c->fused_min_n[q] > 0) o << "fusedmin " << (q ? "fp32" : "fp64") << " " << c->fused_min_n[q] << "\n";
     if (c->tail_top[q] > 0) o << "tail " << (q ? "fp32" : "fp64") << " " << c->tail_top[q] << "\n";
     if (c->tblock[q] >= 0) o << "tb " << (q ? "fp32" : "fp64") << " " << c->tblock[q] << "\n";
+    if (c->blk_zmarch[q] >= 0) o << "blkz " << (q ? "fp32" : "fp64") << " " << c->blk_zmarch[q] << "\n";
   }
   const std::string t = o.str();
   if (buf && cap > 0) {
@@ -1076,11 +1122,11 @@ int mg_tuning_set(mg_ctx* c, const char* text) {
     if (line.empty()) continue;
     std::istringstream ls(line);
     std::string tag, prec;
-    if (line.rfind("tb ", 0) == 0) {
+    if (line.rfind("tb ", 0) == 0 || line.rfind("blkz ", 0) == 0) {
       int v;
       if (!(ls >> tag >> prec >> v) || (prec != "fp64" && prec != "fp32") || (v != 0 && v != 1))
         return fail(c, MG_ERR_INVALID_ARG, "bad tuning line: " + line);
-      add_misc.push_back({4 + (prec == "fp64" ? 0 : 1), v});
+      add_misc.push_back({(tag == "tb" ? 4 : 6) + (prec == "fp64" ? 0 : 1), v});
       continue;
     }
     if (line.rfind("fusedmin ", 0) == 0 || line.rfind("tail ", 0) == 0) {
@@ -1118,7 +1164,8 @@ int mg_tuning_set(mg_ctx* c, const char* text) {
   for (const auto& kv : add_misc) {
     if (kv.first < 2) c->fused_min_n[kv.first] = kv.second;
     else if (kv.first < 4) c->tail_top[kv.first - 2] = kv.second;
-    else c->tblock[kv.first - 4] = kv.second;
+    else if (kv.first < 6) c->tblock[kv.first - 4] = kv.second;
+    else c->blk_zmarch[kv.first - 6] = kv.second;
   }
   return MG_OK;
 }

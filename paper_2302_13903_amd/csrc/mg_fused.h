@@ -59,6 +59,22 @@ template <typename T>
 int fused_defect_norm(const T* u, const T* f, double* part, int n, double h, const LevelBC& bc, hipStream_t s,
                       float* r32 = nullptr);
 
+// The same streaming passes on a MeshBlock-layout level (blocks of 2^Lm cells, 2^Lb blocks per
+// side; the coarse level is the layout below: blocks of 2^(Lm-1) cells, or the dense root
+// grid when Lm = 1).  fused_blk_sweep: one sweep, with the prolonged correction ec added first
+// when ec != nullptr.
+template <typename T>
+void fused_blk_sweep(const T* uin, T* uout, const T* f, const T* ec, const LevelBC& bcc, int Lm, int Lb, double h,
+                     double omega, const LevelBC& bc, hipStream_t s);
+template <typename T>
+void fused_blk_defect_restrict(const T* u, const T* f, T* fc, T* uc0, int Lm, int Lb, double h, const LevelBC& bc,
+                               hipStream_t s);
+template <typename T>
+int fused_blk_defect_norm(const T* u, const T* f, double* part, int Lm, int Lb, double h, const LevelBC& bc,
+                          hipStream_t s, float* r32 = nullptr);
+template <typename T>
+std::string fused_blk_pass_name(bool pro, int out);
+
 template <typename T>
 int fused_grid_blocks(int n, int hx, int hy);
 

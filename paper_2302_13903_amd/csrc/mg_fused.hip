@@ -46,6 +46,7 @@ struct FusedArgs {
   LevelBC bcc;        // PRO: coarse level (homogeneous)
   int n, L, hx, hy, xo, yo, zc, tiles_x, tiles_y, chunks_z, ntiles;
   int zero_in;        // u is known to be zero on input: it is not read
+  int Lm;             // BLK: log2 of the block side on this level (the coarse level: Lm - 1)
   double h2, ih2, omega;
 };
 
@@ -84,11 +85,11 @@ __device__ __forceinline__ T ghost_of(const LevelBC& bc, int face, int n, int t1
 }
 
 template <typename T>
-__device__ __forceinline__ T coarse_at(const T* __restrict__ e, int nc, int Lc, int X, int Y, int Z,
+__device__ __forceinline__ T coarse_at(const T* __restrict__ e, int nc, int Lc, int Lmc, int X, int Y, int Z,
                                        const LevelBC& bcc) {
   if ((unsigned)X < (unsigned)nc && (unsigned)Y < (unsigned)nc && (unsigned)Z < (unsigned)nc)
-    return e[cidx(Lc, X, Y, Z)];
-  return ghost_any(e, nc, Lc, X, Y, Z, bcc);
+    return e[lidx(Lc, Lmc, X, Y, Z)];
+  return ghost_any(e, nc, Lc, X, Y, Z, bcc, Lmc);
 }
 
 template <typename T>
@@ -105,7 +106,11 @@ struct alignas(2 * sizeof(T)) Pair {
 //                restricted to the coarse level, or its sum of squares).
 enum : int { MODE_SWEEP = 0, MODE_MIX = 1, MODE_DEF = 2 };
 
-template <typename T, int R, int W, bool PRO, int OUT, int MODE = MODE_SWEEP>
+// BLK: the level is in the MeshBlock layout (blocks of 2^A.Lm cells, Morton order); the tile
+// streams across block boundaries exactly as across a dense array (an x-pair never straddles
+// two blocks), and the coarse level is in the layout below it (blocks of 2^(A.Lm-1) cells, or
+// the dense root grid when that is one cell).
+template <typename T, int R, int W, bool PRO, int OUT, int MODE = MODE_SWEEP, bool BLK = false>
 __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
   constexpr bool SWEEP = MODE == MODE_SWEEP;
   constexpr bool MIX = MODE == MODE_MIX;
@@ -135,6 +140,10 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
     const T* __restrict__ uin = reinterpret_cast<const T*>(A.uin);
     T* __restrict__ uout = reinterpret_cast<T*>(A.uout);
     const T* __restrict__ fin = reinterpret_cast<const T*>(A.f);
+    // storage index of cell (x, y, z) of this level
+    auto fidx = [&](int x, int y, int z) __attribute__((always_inline)) {
+      return BLK ? bidx(A.Lm, x, y, z) : cidx(L, x, y, z);
+    };
     const bool px = A.bc.kind[0] == BC_PERIODIC;
     const bool py = A.bc.kind[2] == BC_PERIODIC;
     const bool pz = A.bc.kind[4] == BC_PERIODIC;
@@ -193,7 +202,7 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if (in_x && in_y[r] && in_z) {
-          const size_t off = ((size_t)Pg << (2 * L)) + ((size_t)ygv[r] << L) + (size_t)xag;
+          const size_t off = fidx(xag, ygv[r], Pg);
           if (A.zero_in) {
             pu[r][0] = pu[r][1] = (T)0;
           } else {
@@ -209,7 +218,7 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
           pu[r][0] = pu[r][1] = (T)0;
         }
         if (in_x && in_y[r] && in_zf) {
-          const size_t off = ((size_t)Pfg << (2 * L)) + ((size_t)ygv[r] << L) + (size_t)xag;
+          const size_t off = fidx(xag, ygv[r], Pfg);
           const Pair<T> vf = *reinterpret_cast<const Pair<T>*>(fin + off);
           pf[r][0] = vf.a; pf[r][1] = vf.b;
         } else {
@@ -221,7 +230,7 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
         // come in aligned pairs (2Y, 2Y+1) sharing coarse rows Y-1, Y, Y+1; the lane's coarse
         // column X is interpolated in y and z, and its x-neighbours come from lanes -+1.
         const T* __restrict__ ec = reinterpret_cast<const T*>(A.ec);
-        const int nc = n >> 1, Lc = L - 1;
+        const int nc = n >> 1, Lc = L - 1, Lmc = BLK ? A.Lm - 1 : 0;
         const int X = (px ? xag : xa) >> 1;
         const int Pz = pz ? Pg : P;
         const int Z = Pz >> 1;
@@ -233,8 +242,8 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
           T cz[3];
 #pragma unroll
           for (int dy = 0; dy < 3; ++dy)
-            cz[dy] = wz0 * coarse_at(ec, nc, Lc, X, Y - 1 + dy, zlo, A.bcc) +
-                     wz1 * coarse_at(ec, nc, Lc, X, Y - 1 + dy, zlo + 1, A.bcc);
+            cz[dy] = wz0 * coarse_at(ec, nc, Lc, Lmc, X, Y - 1 + dy, zlo, A.bcc) +
+                     wz1 * coarse_at(ec, nc, Lc, Lmc, X, Y - 1 + dy, zlo + 1, A.bcc);
 #pragma unroll
           for (int rr = 0; rr < 2; ++rr) {
             const int r = 2 * q2 + rr;
@@ -344,7 +353,7 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
           if (out_z && out_x && out_y[r]) {
             acc += (double)d[0] * (double)d[0] + (double)d[1] * (double)d[1];
             if (MIX || (MODE == MODE_DEF && A.r32)) {
-              const size_t off = ((size_t)(p & nm) << (2 * L)) + ((size_t)ygv[r] << L) + (size_t)xag;
+              const size_t off = fidx(xag, ygv[r], p & nm);
               *reinterpret_cast<float2*>(A.r32 + off) = make_float2((float)d[0], (float)d[1]);
             }
           }
@@ -363,7 +372,7 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
             stash[q2] = s;
           } else if (out_z && out_x && out_y[2 * q2]) {
             const int Lc = L - 1;
-            const size_t ci = cidx(Lc, xag >> 1, ygv[2 * q2] >> 1, pg >> 1);
+            const size_t ci = lidx(Lc, BLK ? A.Lm - 1 : 0, xag >> 1, ygv[2 * q2] >> 1, pg >> 1);
             fcp[ci] = (stash[q2] + s) * (T)0.125;
             ucp[ci] = (T)0;
           }
@@ -401,7 +410,7 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
 #pragma unroll
           for (int r = 0; r < R; ++r)
             if (out_y[r]) {
-              const size_t off = ((size_t)pg << (2 * L)) + ((size_t)ygv[r] << L) + (size_t)xag;
+              const size_t off = fidx(xag, ygv[r], pg);
               *reinterpret_cast<Pair<T>*>(uout + off) = Pair<T>{u[sf][r][0], u[sf][r][1]};
             }
         }
@@ -462,7 +471,7 @@ int zchunk_for(int n) {
   return 16;
 }
 
-template <typename T, bool PRO, int OUT, int MODE = MODE_SWEEP>
+template <typename T, bool PRO, int OUT, int MODE = MODE_SWEEP, bool BLK = false>
 void launch_pass(FusedArgs A, hipStream_t s) {
   constexpr int R = MODE == MODE_SWEEP ? Cfg<T, OUT>::R : 2, W = MODE == MODE_SWEEP ? Cfg<T, OUT>::W : 16;
   A.xo = kTileX - 2 * A.hx;
@@ -473,7 +482,7 @@ void launch_pass(FusedArgs A, hipStream_t s) {
   A.chunks_z = (A.n + A.zc - 1) / A.zc;
   A.ntiles = A.tiles_x * A.tiles_y * A.chunks_z;
   const int grid = (A.ntiles + 7) / 8 * 8;
-  hipLaunchKernelGGL((k_fused<T, R, W, PRO, OUT, MODE>), dim3(grid), dim3(kLanes * W), 0, s, A);
+  hipLaunchKernelGGL((k_fused<T, R, W, PRO, OUT, MODE, BLK>), dim3(grid), dim3(kLanes * W), 0, s, A);
 }
 
 template <typename T>
@@ -586,6 +595,57 @@ int fused_defect_norm(const T* u, const T* f, double* part, int n, double h, con
   return fused_grid_blocks<T>(n, 2, 1);
 }
 
+// ---- the same passes on a MeshBlock-layout level (blocks of 2^Lm cells, 2^Lb per side)
+
+template <typename T>
+void fused_blk_sweep(const T* uin, T* uout, const T* f, const T* ec, const LevelBC& bcc, int Lm, int Lb, double h,
+                     double omega, const LevelBC& bc, hipStream_t s) {
+  FusedArgs A = base_args(uin, uout, f, 1 << (Lm + Lb), h, omega, bc);
+  A.Lm = Lm;
+  A.hy = 2;
+  if (ec) {
+    A.hx = 4;
+    A.ec = ec;
+    A.bcc = bcc;
+    launch_pass<T, true, 0, MODE_SWEEP, true>(A, s);
+  } else {
+    A.hx = 2;
+    launch_pass<T, false, 0, MODE_SWEEP, true>(A, s);
+  }
+}
+
+template <typename T>
+void fused_blk_defect_restrict(const T* u, const T* f, T* fc, T* uc0, int Lm, int Lb, double h, const LevelBC& bc,
+                               hipStream_t s) {
+  FusedArgs A = base_args(u, (T*)nullptr, f, 1 << (Lm + Lb), h, 1.0, bc);
+  A.Lm = Lm;
+  A.hx = 2;
+  A.hy = 2;
+  A.fc = fc;
+  A.uc0 = uc0;
+  launch_pass<T, false, 1, MODE_DEF, true>(A, s);
+}
+
+template <typename T>
+int fused_blk_defect_norm(const T* u, const T* f, double* part, int Lm, int Lb, double h, const LevelBC& bc,
+                          hipStream_t s, float* r32) {
+  const int n = 1 << (Lm + Lb);
+  FusedArgs A = base_args(u, (T*)nullptr, f, n, h, 1.0, bc);
+  A.Lm = Lm;
+  A.hx = 2;
+  A.hy = 1;
+  A.part = part;
+  A.r32 = r32;
+  launch_pass<T, false, 2, MODE_DEF, true>(A, s);
+  return fused_grid_blocks<T>(n, 2, 1);
+}
+
+template <typename T>
+std::string fused_blk_pass_name(bool pro, int out) {
+  return std::string("k_fused<") + (sizeof(T) == 8 ? "double" : "float") + ", 2, 16, " + (pro ? "true" : "false") +
+         ", " + std::to_string(out) + ", " + std::to_string(out ? MODE_DEF : MODE_SWEEP) + ", true>";
+}
+
 template <typename T>
 std::string fused_pass_name(bool pro, int out, bool sweep) {
   int R = out == 1 ? Cfg<T, 1>::R : out == 2 ? Cfg<T, 2>::R : Cfg<T, 0>::R;
@@ -608,7 +668,14 @@ std::string fused_pass_name(bool pro, int out, bool sweep) {
   template int fused_grid_blocks<T>(int, int, int);                                                             \
   template void fused_defect_restrict<T>(const T*, const T*, T*, T*, int, double, const LevelBC&, hipStream_t);  \
   template int fused_defect_norm<T>(const T*, const T*, double*, int, double, const LevelBC&, hipStream_t, float*); \
-  template std::string fused_pass_name<T>(bool, int, bool);
+  template std::string fused_pass_name<T>(bool, int, bool);                                                     \
+  template void fused_blk_sweep<T>(const T*, T*, const T*, const T*, const LevelBC&, int, int, double, double,   \
+                                   const LevelBC&, hipStream_t);                                                \
+  template void fused_blk_defect_restrict<T>(const T*, const T*, T*, T*, int, int, double, const LevelBC&,       \
+                                             hipStream_t);                                                      \
+  template int fused_blk_defect_norm<T>(const T*, const T*, double*, int, int, double, const LevelBC&,           \
+                                        hipStream_t, float*);                                                   \
+  template std::string fused_blk_pass_name<T>(bool, int);
 
 MG_FUSED_INST(double)
 MG_FUSED_INST(float)

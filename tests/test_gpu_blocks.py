@@ -172,3 +172,39 @@ def test_c4_lognormal_256_blocks_vs_dense(mg):
         assert st == mg.MG_OK, prec
         assert gh[-1] <= 1e-10
         assert rel(got, d) < 1e-9, prec
+
+
+@pytest.mark.parametrize("n,block_n,kinds", CASES)
+def test_blocks_streaming_passes_match_oracle(mg, n, block_n, kinds):
+    """The streaming z-marching passes run across block boundaries (forced down to 64^3 here):
+    the same V-cycles as the oracle."""
+    if n < 64:
+        pytest.skip("streaming passes need 64 cells per side")
+    print(f"blocks z-march vs oracle n={n} block_n={block_n} kinds={kinds}", flush=True)
+    periodic_all = kinds == "periodic"
+    rho = wl.gaussian_clumps(n, 7 + n + block_n, n_clumps=8, remove_mean=periodic_all)
+    gauge_free = periodic_all or kinds == [ZERO_GRADIENT] * 6
+    faces = None
+    if not gauge_free:
+        rng = np.random.default_rng(n * block_n)
+        faces = [rng.normal(size=(n, n)) * 0.1 for _ in range(6)]
+    ref, rh, rst = oracle.solve(rho, 1.0 / n, kinds, fixed_b=faces, fixed_cycles=5)
+    ctx = mg.Context(0)
+    ctx.set_tuning("fusedmin fp64 64\nblkz fp64 1\n")
+    got, gh, st, _ = solve_blocks(mg, rho, kinds, block_n, faces=faces, ctx=ctx, fixed_cycles=5)
+    assert st == mg.MG_OK
+    assert rel(got, ref) < 1e-10
+    fl = floor_of(ref, rho, gauge_free)
+    for a, b in zip(gh, rh):
+        assert abs(a - b) <= 1e-6 * b + 10 * fl, (gh, rh)
+
+
+def test_blocks_streaming_mixed(mg):
+    n = 128
+    rho = wl.gaussian_clumps(n, 17, remove_mean=True)
+    ref, _, _ = oracle.solve(rho, 1.0 / n, "periodic", tol=1e-13, max_cycles=40)
+    ctx = mg.Context(0)
+    ctx.set_tuning("fusedmin fp32 64\nblkz fp32 1\n")
+    got, gh, st, _ = solve_blocks(mg, rho, "periodic", 16, ctx=ctx, precision="mixed", tol=1e-11, max_cycles=40)
+    assert gh[-1] < 1e-10
+    assert rel(got, ref) < 1e-10
