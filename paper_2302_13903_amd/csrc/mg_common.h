@@ -102,42 +102,35 @@ __device__ __forceinline__ T neighbour_sum(const T* __restrict__ u, int n, int L
 
 // Value at (i, j, k) with each index in [-1, n], edges and corners included, under the rule
 // that ghosts are filled axis by axis (x, then y over the x ghosts, then z over both).  The
-// last-filled axis is resolved first; each step maps value = s * inner + t.
+// last-filled axis is resolved first; each step maps value = s * inner + t.  Faces are picked
+// with compile-time indices only (so a boundary description held in registers stays there).
 // Lm > 0: u is a MeshBlock-layout level with 2^Lm-cell blocks.
+template <typename T>
+__device__ __forceinline__ void ghost_axis(const LevelBC& bc, int lo_face, int n, int& c, int t1, int t2, T& s,
+                                           T& t) {
+  if (c >= 0 && c < n) return;
+  const bool lo = c < 0;
+  const int kd = lo ? bc.kind[lo_face] : bc.kind[lo_face + 1];
+  if (kd == BC_PERIODIC) {
+    c = lo ? n - 1 : 0;
+    return;
+  }
+  if (kd != BC_ZERO_GRADIENT) {
+    const double* b = lo ? bc.b[lo_face] : bc.b[lo_face + 1];
+    const double bv = b ? b[(size_t)(t2 + 1) * (size_t)(n + 2) + (size_t)(t1 + 1)] : 0.0;
+    t += s * (T)(2.0 * bv);
+    s = -s;
+  }
+  c = lo ? 0 : n - 1;
+}
+
 template <typename T>
 __device__ __forceinline__ T ghost_any(const T* __restrict__ u, int n, int L, int i, int j, int k,
                                        const LevelBC& bc, int Lm = 0) {
   T s = (T)1, t = (T)0;
-  if (k < 0 || k >= n) {
-    const int face = k < 0 ? 4 : 5;
-    const int kd = bc.kind[face];
-    if (kd == BC_PERIODIC) {
-      k = k < 0 ? n - 1 : 0;
-    } else {
-      if (kd != BC_ZERO_GRADIENT) { t += s * (T)(2.0 * face_b(bc, face, n, i, j)); s = -s; }
-      k = k < 0 ? 0 : n - 1;
-    }
-  }
-  if (j < 0 || j >= n) {
-    const int face = j < 0 ? 2 : 3;
-    const int kd = bc.kind[face];
-    if (kd == BC_PERIODIC) {
-      j = j < 0 ? n - 1 : 0;
-    } else {
-      if (kd != BC_ZERO_GRADIENT) { t += s * (T)(2.0 * face_b(bc, face, n, i, k)); s = -s; }
-      j = j < 0 ? 0 : n - 1;
-    }
-  }
-  if (i < 0 || i >= n) {
-    const int face = i < 0 ? 0 : 1;
-    const int kd = bc.kind[face];
-    if (kd == BC_PERIODIC) {
-      i = i < 0 ? n - 1 : 0;
-    } else {
-      if (kd != BC_ZERO_GRADIENT) { t += s * (T)(2.0 * face_b(bc, face, n, j, k)); s = -s; }
-      i = i < 0 ? 0 : n - 1;
-    }
-  }
+  ghost_axis<T>(bc, 4, n, k, i, j, s, t);
+  ghost_axis<T>(bc, 2, n, j, i, k, s, t);
+  ghost_axis<T>(bc, 0, n, i, j, k, s, t);
   return s * u[lidx(L, Lm, i, j, k)] + t;
 }
 

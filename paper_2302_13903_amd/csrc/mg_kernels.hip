@@ -235,12 +235,9 @@ void launch_coarsest(T* u, const T* f, double h, const LevelBC& bc, hipStream_t 
 // global when TAIL_LOAD_U, else started from zero) and homogeneous descriptions below.
 constexpr int kTailThreads = 1024;
 
-// Start of level l within the LDS arrays (levels 0..top stored back to back).
-__host__ __device__ constexpr int level_offset(int l) {
-  int o = 0;
-  for (int q = 0; q < l; ++q) o += 1 << (3 * q);
-  return o;
-}
+// Start of level l within the LDS arrays (levels 0..top stored back to back): the cells of
+// levels 0..l-1, sum of 8^q for q < l = (8^l - 1) / 7.
+__host__ __device__ __forceinline__ constexpr int level_offset(int l) { return ((1 << (3 * l)) - 1) / 7; }
 
 template <typename T>
 __device__ __forceinline__ T lds_nb(const T* u, int n, int L, int i, int j, int k, T uc, const LevelBC& bc) {
@@ -251,11 +248,13 @@ __device__ __forceinline__ T lds_nb(const T* u, int n, int L, int i, int j, int 
 // One smoothing sweep on an LDS-resident level: work items enumerate only the cells of the
 // current colour (the x-pair index p picks the pair's cell of that colour), so no lane idles.
 template <typename T>
-__device__ void tail_smooth(T* u, const T* f, int L, T h2, T omega, const LevelBC& bc) {
+__device__ __forceinline__ void tail_smooth(T* u, const T* f, int L, T h2, T omega, const LevelBC& bc) {
   const int n = 1 << L;
   const T inv6 = (T)(1.0 / 6.0);
   const int half = 1 << (3 * L - 1);
+#pragma unroll 1
   for (int colour = 0; colour < 2; ++colour) {
+#pragma unroll 1
     for (int t = threadIdx.x; t < half; t += blockDim.x) {
       const int p = t & ((n >> 1) - 1), j = (t >> (L - 1)) & (n - 1), k = t >> (2 * L - 1);
       const int i = 2 * p + ((j + k + colour) & 1);
@@ -269,8 +268,9 @@ __device__ void tail_smooth(T* u, const T* f, int L, T h2, T omega, const LevelB
 }
 
 template <typename T>
-__device__ void tail_defect_restrict(const T* u, const T* f, T* fc, T* uc0, int L, T ih2, const LevelBC& bc) {
+__device__ __forceinline__ void tail_defect_restrict(const T* u, const T* f, T* fc, T* uc0, int L, T ih2, const LevelBC& bc) {
   const int n = 1 << L, Lc = L - 1, nc = n >> 1, nc3 = 1 << (3 * Lc);
+#pragma unroll 1
   for (int C = threadIdx.x; C < nc3; C += blockDim.x) {
     const int I = C & (nc - 1), J = (C >> Lc) & (nc - 1), K = C >> (2 * Lc);
     T s = (T)0;
@@ -289,8 +289,9 @@ __device__ void tail_defect_restrict(const T* u, const T* f, T* fc, T* uc0, int 
 }
 
 template <typename T, int CUBIC>
-__device__ void tail_prolong(const T* uc, T* uf, int L, const LevelBC& bcc) {
+__device__ __forceinline__ void tail_prolong(const T* uc, T* uf, int L, const LevelBC& bcc) {
   const int n = 1 << L, n3 = 1 << (3 * L), Lc = L - 1, nc = n >> 1;
+#pragma unroll 1
   for (int c = threadIdx.x; c < n3; c += blockDim.x) {
     const int i = c & (n - 1), j = (c >> L) & (n - 1), k = c >> (2 * L);
     const int I = i >> 1, J = j >> 1, K = k >> 1;
@@ -327,23 +328,28 @@ struct TailMeta {
 // V-cycle from level `topl` down to 0 and back, with bc_top on level topl and the
 // homogeneous description below.
 template <typename T>
-__device__ void tail_vcycle(T* base, int total, int topl, const TailMeta& m, const LevelBC& bc_top, int npre,
+__device__ __forceinline__ void tail_vcycle(T* base, int total, int topl, const TailMeta& m, const LevelBC& bc_top, int npre,
                             int npost, T omega) {
+#pragma unroll 1
   for (int l = topl; l >= 1; --l) {
-    const LevelBC& bc = l == topl ? bc_top : m.hom;
+    const LevelBC bc = l == topl ? bc_top : m.hom;   // by value: kinds in registers
     T* u = base + level_offset(l);
     T* f = base + total + level_offset(l);
     const T h2 = (T)m.h2[l];
+#pragma unroll 1
     for (int it = 0; it < npre; ++it) tail_smooth(u, f, l, h2, omega, bc);
     tail_defect_restrict(u, f, base + total + level_offset(l - 1), base + level_offset(l - 1), l, (T)(1.0 / m.h2[l]),
                          bc);
   }
-  if (threadIdx.x == 0) base[0] = coarsest_value(base[total], (T)m.h2[0], topl == 0 ? bc_top : m.hom);
+  const LevelBC hom = m.hom;
+  if (threadIdx.x == 0) base[0] = coarsest_value(base[total], (T)m.h2[0], topl == 0 ? bc_top : hom);
   __syncthreads();
+#pragma unroll 1
   for (int l = 1; l <= topl; ++l) {
-    const LevelBC& bc = l == topl ? bc_top : m.hom;
+    const LevelBC bc = l == topl ? bc_top : hom;
     T* u = base + level_offset(l);
-    tail_prolong<T, 0>(base + level_offset(l - 1), u, l, m.hom);
+    tail_prolong<T, 0>(base + level_offset(l - 1), u, l, hom);
+#pragma unroll 1
     for (int it = 0; it < npost; ++it) tail_smooth(u, base + total + level_offset(l), l, (T)m.h2[l], omega, bc);
   }
 }
@@ -367,7 +373,8 @@ __global__ void __launch_bounds__(kTailThreads) k_tail(TailArgs a) {
   __syncthreads();
   const int ntop = 1 << (3 * top);
   const T omega = (T)a.omega;
-  if (a.mode & TAIL_FMG) {
+  const bool fmg = (a.mode & TAIL_FMG) != 0;
+  if (fmg) {
     for (int l = 0; l <= top; ++l) {
       const int n3 = 1 << (3 * l);
       const T* src = fg[l];
@@ -376,14 +383,6 @@ __global__ void __launch_bounds__(kTailThreads) k_tail(TailArgs a) {
     }
     __syncthreads();
     if (threadIdx.x == 0) base[0] = coarsest_value(base[total], (T)m.h2[0], m.phys[0]);
-    __syncthreads();
-    // Alg. 2: tricubic prolongation, then one V-cycle with the level's own physical
-    // description; the V-cycle on level l overwrites the sources below with restricted
-    // defects, which FMG no longer needs (it proceeds upwards).
-    for (int l = 1; l <= top; ++l) {
-      tail_prolong<T, 1>(base + level_offset(l - 1), base + level_offset(l), l, m.phys[l - 1]);
-      tail_vcycle(base, total, l, m, m.phys[l], a.npre, a.npost, omega);
-    }
   } else {
     T* u = base + level_offset(top);
     T* f = base + total + level_offset(top);
@@ -392,8 +391,21 @@ __global__ void __launch_bounds__(kTailThreads) k_tail(TailArgs a) {
       f[c] = src[c];
       u[c] = (a.mode & TAIL_LOAD_U) ? ug[c] : (T)0;
     }
-    __syncthreads();
-    tail_vcycle(base, total, top, m, m.top, a.npre, a.npost, omega);
+  }
+  __syncthreads();
+  // Alg. 2 (FMG): on each level l = 1..top, the tricubic prolongation, then one V-cycle with
+  // the level's own physical description (the V-cycle on level l overwrites the sources below
+  // with restricted defects, which FMG no longer needs: it proceeds upwards).  V-cycle mode:
+  // the one V-cycle on level top.  One copy of the V-cycle code serves both (a small kernel
+  // image keeps the instruction cache warm across the many short phases).
+#pragma unroll 1
+  for (int l = fmg ? 1 : top; l <= top; ++l) {
+    if (fmg) {
+      const LevelBC below = m.phys[l - 1];
+      tail_prolong<T, 1>(base + level_offset(l - 1), base + level_offset(l), l, below);
+    }
+    const LevelBC here = fmg ? m.phys[l] : m.top;
+    tail_vcycle(base, total, l, m, here, a.npre, a.npost, omega);
   }
   const T* u = base + level_offset(top);
   for (int c = threadIdx.x; c < ntop; c += blockDim.x) ug[c] = u[c];
