@@ -181,6 +181,7 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
     // f: LDS slots (plane mod 3) holding planes P-1, P-2, P-3.
     T u[kRing][R][2];
     T pu[R][2], pf[R][2];
+    T pc[PRO ? R / 2 : 1][3][2];   // PRO: coarse taps (rows Y-1..Y+1, planes zlo, zlo+1) of the next plane
     T stash[R / 2 > 0 ? R / 2 : 1];
 #pragma unroll
     for (int s = 0; s < kRing; ++s)
@@ -228,32 +229,47 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
       if (PRO) {
         // Trilinear prolongation (weights 1/4, 3/4 per axis) of the coarse correction.  Rows
         // come in aligned pairs (2Y, 2Y+1) sharing coarse rows Y-1, Y, Y+1; the lane's coarse
-        // column X is interpolated in y and z, and its x-neighbours come from lanes -+1.
+        // column X is interpolated in y and z, and its x-neighbours come from lanes -+1.  Only
+        // the loads are issued here; prolong_apply adds the correction when the plane enters
+        // the ring, so the loads are in flight during the step like the u and f prefetch.
         const T* __restrict__ ec = reinterpret_cast<const T*>(A.ec);
         const int nc = n >> 1, Lc = L - 1, Lmc = BLK ? A.Lm - 1 : 0;
         const int X = (px ? xag : xa) >> 1;
         const int Pz = pz ? Pg : P;
         const int Z = Pz >> 1;
         const int zlo = (Pz & 1) ? Z : Z - 1;          // taps (zlo, zlo+1)
-        const T wz0 = (Pz & 1) ? (T)0.75 : (T)0.25, wz1 = (Pz & 1) ? (T)0.25 : (T)0.75;
 #pragma unroll
         for (int q2 = 0; q2 < R / 2; ++q2) {
           const int Y = (py ? ygv[2 * q2] : yv[2 * q2]) >> 1;   // the pair's coarse row
-          T cz[3];
 #pragma unroll
-          for (int dy = 0; dy < 3; ++dy)
-            cz[dy] = wz0 * coarse_at(ec, nc, Lc, Lmc, X, Y - 1 + dy, zlo, A.bcc) +
-                     wz1 * coarse_at(ec, nc, Lc, Lmc, X, Y - 1 + dy, zlo + 1, A.bcc);
+          for (int dy = 0; dy < 3; ++dy) {
+            pc[q2][dy][0] = coarse_at(ec, nc, Lc, Lmc, X, Y - 1 + dy, zlo, A.bcc);
+            pc[q2][dy][1] = coarse_at(ec, nc, Lc, Lmc, X, Y - 1 + dy, zlo + 1, A.bcc);
+          }
+        }
+      }
+    };
+
+    // ---- add the prolonged correction fetched with plane P to the prefetched u of P
+    auto prolong_apply = [&](int P) __attribute__((always_inline)) {
+      if (!PRO) return;
+      const bool in_z = pz || (P >= 0 && P < n);
+      const int Pz = pz ? (P & nm) : P;
+      const T wz0 = (Pz & 1) ? (T)0.75 : (T)0.25, wz1 = (Pz & 1) ? (T)0.25 : (T)0.75;
 #pragma unroll
-          for (int rr = 0; rr < 2; ++rr) {
-            const int r = 2 * q2 + rr;
-            const T c = rr ? (T)0.75 * cz[1] + (T)0.25 * cz[2] : (T)0.25 * cz[0] + (T)0.75 * cz[1];
-            // the edge lanes 0 and 63 get their own value back: wrong, but within the halo
-            const T cl = shfl_from_left(c), cr = shfl_from_right(c);
-            if (in_x && in_y[r] && in_z) {
-              pu[r][0] += (T)0.25 * cl + (T)0.75 * c;
-              pu[r][1] += (T)0.75 * c + (T)0.25 * cr;
-            }
+      for (int q2 = 0; q2 < R / 2; ++q2) {
+        T cz[3];
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) cz[dy] = wz0 * pc[q2][dy][0] + wz1 * pc[q2][dy][1];
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr) {
+          const int r = 2 * q2 + rr;
+          const T c = rr ? (T)0.75 * cz[1] + (T)0.25 * cz[2] : (T)0.25 * cz[0] + (T)0.75 * cz[1];
+          // the edge lanes 0 and 63 get their own value back: wrong, but within the halo
+          const T cl = shfl_from_left(c), cr = shfl_from_right(c);
+          if (in_x && in_y[r] && in_z) {
+            pu[r][0] += (T)0.25 * cl + (T)0.75 * c;
+            pu[r][1] += (T)0.75 * c + (T)0.25 * cr;
           }
         }
       }
@@ -381,6 +397,7 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
     };
 
     load_plane(zstart);
+    prolong_apply(zstart);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       u[0][r][0] = pu[r][0]; u[0][r][1] = pu[r][1];
@@ -420,6 +437,7 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
         else defect_out(u[s2], u[s1], u[k], P - 1);
       }
       if (t + 1 < nsteps) {
+        prolong_apply(P + 1);
         constexpr int sn = (k + 1) % kRing;
         // f(P) replaces f(P-3), which this thread's defect stage has finished reading
 #pragma unroll
@@ -653,7 +671,7 @@ std::string fused_pass_name(bool pro, int out, bool sweep) {
   if (!sweep) { R = 2; W = 16; }
   return std::string("k_fused<") + (sizeof(T) == 8 ? "double" : "float") + ", " + std::to_string(R) + ", " +
          std::to_string(W) + ", " + (pro ? "true" : "false") + ", " + std::to_string(out) + ", " +
-         std::to_string(sweep ? MODE_SWEEP : MODE_DEF) + ">";
+         std::to_string(sweep ? MODE_SWEEP : MODE_DEF) + ", false>";
 }
 
 #define MG_FUSED_INST(T)                                                                                        \
