@@ -220,6 +220,10 @@ struct Solver {
   // the next top-level V-cycle starts from u = 0 without u having been cleared: its first
   // sweep must not read u (set by the caller, consumed by vcycle)
   bool zero_start = false;
+  // the first pre-smoothing sweep of the next top-level V-cycle has already run (the head
+  // pass, which also measured the residual of its input): its result is in u2 (consumed by
+  // vcycle)
+  bool head_done = false;
 
   void kernel_begin() {
     hipEvent_t e;
@@ -271,6 +275,26 @@ struct Solver {
     auto it = c->pass_split.find((sizeof(T) == 8 ? 0 : 1000) + l);
     if (it != c->pass_split.end()) return it->second;
     return sizeof(T) == 8 ? 3 : 0;
+  }
+
+  // FP64, dense: can the first pre-sweep of the finest level's V-cycle run as a head pass (a
+  // one-sweep streaming pass that also takes the residual norm of its input)?
+  bool head_possible(const Hier<double>& H) const {
+    const int L = H.L;
+    return use_fused && H.u2[L] && L != H.T_top && Lb < 0 && (1 << L) >= fused_min_n64 && !tblock_on<double>() &&
+           H.npre >= 1 && ((split_of<double>(L) & 1) || H.npre >= 2);
+  }
+
+  // The head pass: first pre-sweep of the next V-cycle (u -> u2) and the residual norm of u
+  // (the iterate the stopping test of Sec. 2.3.7 is about) into c->scal[2].
+  void head(Hier<double>& H, const LevelBC& bc) {
+    const int L = H.L, n = 1 << L;
+    const bool timed = timed_top && c->ktiming;
+    if (timed) kernel_begin();
+    const int np = fused_sweep_input_norm<double>(H.u[L], H.u2[L], H.f[L], c->part, n, H.h[L], H.omega, bc, s);
+    if (timed) kernel_end(fused_pass_name<double>(false, 3), 3.0 * (double)cells(L) * sizeof(double));
+    launch_sum_partials(c->part, np, c->scal + 2, s);
+    head_done = true;
   }
 
   template <typename T>
@@ -357,7 +381,13 @@ struct Solver {
       const bool sdef = (split & 1) != 0, snorm = (split & 2) != 0;
       T* cur = H.u[l];
       T* oth = H.u2[l];
-      for (int it = 0; it < H.npre; ++it) {
+      int it0 = 0;
+      if (top_call && head_done) {
+        std::swap(cur, oth);
+        it0 = 1;
+        head_done = false;
+      }
+      for (int it = it0; it < H.npre; ++it) {
         const bool fuse = it == H.npre - 1 && !sdef;
         const bool zin = it == 0 && top_call && zero_start && !fuse;
         if (timed) kernel_begin();
@@ -819,8 +849,11 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
       launch_f32_to_f64(H32.u[L], phi, n3, s);
     }
   }
-  // ---- residual of the start (Sec. 2.3.7); mixed: also its FP32 copy as the inner RHS
-  S.defect_norm(phi, f64L, mixed ? H32.f[L] : nullptr, p->n, p->dx, phys[L], c->scal + 2);
+  // ---- residual of the start (Sec. 2.3.7); mixed: also its FP32 copy as the inner RHS.  FP64
+  // on the fused path: taken by the head pass, which is also the first sweep of V-cycle 1
+  const bool head_mode = !mixed && Lb < 0 && S.head_possible(H64);
+  if (head_mode) S.head(H64, phys[L]);
+  else S.defect_norm(phi, f64L, mixed ? H32.f[L] : nullptr, p->n, p->dx, phys[L], c->scal + 2);
   HIP_CHECK(c, hipEventRecord(c->ev_fmg, s));
   HIP_CHECK(c, hipMemcpyAsync(c->hscal, c->scal, sizeof(double) * 16, hipMemcpyDeviceToHost, s));
   HIP_CHECK(c, hipStreamSynchronize(s));
@@ -850,7 +883,15 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
   if (p->fixed_cycles > 0 || r > p->tol) {
     for (int cyc = 0; cyc < ncyc; ++cyc) {
       S.timed_top = true;
-      if (!mixed && Lb >= 0) {
+      if (head_mode) {
+        // the rest of this V-cycle (its first sweep ran in the head pass), then the head of the
+        // next one, which measures this cycle's result; after the last allowed cycle the
+        // residual alone (a head's sweep would be discarded)
+        S.head_done = true;
+        S.vcycle(H64, L, phys[L], true, false);
+        if (cyc + 1 < ncyc) S.head(H64, phys[L]);
+        else S.defect_norm(phi, f64L, nullptr, p->n, p->dx, phys[L], c->scal + 2);
+      } else if (!mixed && Lb >= 0) {
         S.vcycle_blk(H64, L, phys[L]);
         S.defect_norm(phi, f64L, nullptr, p->n, p->dx, phys[L], c->scal + 2);
       } else if (mixed && Lb >= 0) {

@@ -42,6 +42,12 @@ template <typename T>
 int fused_sweep_norm(const T* uin, T* uout, const T* f, double* part, int n, double h, double omega,
                      const LevelBC& bc, hipStream_t s);
 
+// One sweep, and one partial sum of squared defects per block of the INPUT u (the residual of
+// the iterate the sweep starts from); returns the number of partials.
+template <typename T>
+int fused_sweep_input_norm(const T* uin, T* uout, const T* f, double* part, int n, double h, double omega,
+                           const LevelBC& bc, hipStream_t s);
+
 // Mixed precision, FP64 part of one defect-correction step: phi_out = phi_in + e (e FP32),
 // then the defect f - L phi_out, its FP32 copy r32 and one partial sum of squares per block;
 // returns the number of partials.

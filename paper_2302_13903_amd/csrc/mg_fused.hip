@@ -115,13 +115,21 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
   constexpr bool SWEEP = MODE == MODE_SWEEP;
   constexpr bool MIX = MODE == MODE_MIX;
   constexpr bool WRITE_U = MODE != MODE_DEF;
+  // OUT = 3 (with a sweep): the sum of squared defects of the INPUT u, taken in the red stage
+  // before it updates the plane (no defect stage behind the sweep)
+  constexpr bool INNORM = SWEEP && OUT == 3;
+  constexpr bool DSTAGE = OUT == 1 || OUT == 2;
   constexpr int DLAG = SWEEP ? 3 : 1;                  // the defect runs on plane P - DLAG
-  constexpr int HZ = OUT ? DLAG : 2;                   // z planes loaded ahead of the chunk
-  constexpr int kRing = OUT ? DLAG + 2 : 4;            // u planes alive
+  constexpr int HZ = DSTAGE ? DLAG : 2;                // z planes loaded ahead of the chunk
+  constexpr int kRing = DSTAGE ? DLAG + 2 : 4;         // u planes alive
   __shared__ Pair<T> xch[2][W][2][kLanes];
   // f of planes P-1, P-2, P-3 for this thread's cells: private per thread (f is only read at
   // the cell itself), kept in LDS to leave the registers to the u ring
-  __shared__ Pair<T> fl[3][R][W * kLanes];
+  // (a sweep without a defect stage needs f of P-1 and P-2 only)
+  constexpr int NF = DSTAGE ? 3 : 2;
+  __shared__ Pair<T> fl[NF][R][W * kLanes];
+  // INNORM: input values of plane P-2, private per thread like f
+  __shared__ Pair<T> uol[INNORM ? R : 1][INNORM ? W * kLanes : 1];
 
   const int lane = threadIdx.x & (kLanes - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -182,12 +190,14 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
     T u[kRing][R][2];
     T pu[R][2], pf[R][2];
     T pc[PRO ? R / 2 : 1][3][2];   // PRO: coarse taps (rows Y-1..Y+1, planes zlo, zlo+1) of the next plane
+#pragma unroll
+    for (int r = 0; r < (INNORM ? R : 0); ++r) uol[r][tid] = Pair<T>{(T)0, (T)0};
     T stash[R / 2 > 0 ? R / 2 : 1];
 #pragma unroll
     for (int s = 0; s < kRing; ++s)
 #pragma unroll
       for (int r = 0; r < R; ++r) u[s][r][0] = u[s][r][1] = (T)0;
-    auto fslot = [&](int p) __attribute__((always_inline)) { return ((p % 3) + 3) % 3; };
+    auto fslot = [&](int p) __attribute__((always_inline)) { return ((p % NF) + NF) % NF; };
     auto fget = [&](int p, int r, int q) __attribute__((always_inline)) {
       const Pair<T> v = fl[fslot(p)][r][tid];
       return q ? v.b : v.a;
@@ -296,6 +306,41 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
       exchange(pc, below, above);
       const bool in_z = pz || (p >= 0 && p < n);
       const bool bnd_z0 = !pz && p == 0, bnd_z1 = !pz && p == nm;
+      const bool out_zn = INNORM && p >= z0 && p < zend;
+      if (INNORM && colour == 0) {
+        // defect of the input on plane p, black cells (the red cells' comes with their update
+        // below, whose neighbour sum is the input's): pc, below/above and pp still hold input
+        // values (the red update of p comes next, p+1 was only just loaded); a black cell's
+        // z-neighbour below is red and already updated, so its input value comes from uol
+        const int qr = __builtin_amdgcn_readfirstlane((yv[0] + p) & 1);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int q = ((qr + r) & 1) ^ 1;   // the black cell of the pair (wave-uniform)
+          const T ca = pc[r][0], cb = pc[r][1];
+          const T c = q ? cb : ca;
+          const T la = shfl_from_left(cb), rb = shfl_from_right(ca);
+          T xm = q ? ca : la;
+          T xp = q ? rb : cb;
+          T ym = r > 0 ? (q ? pc[r - 1][1] : pc[r - 1][0]) : (q ? below[1] : below[0]);
+          T yp = r < R - 1 ? (q ? pc[r + 1][1] : pc[r + 1][0]) : (q ? above[1] : above[0]);
+          const Pair<T> zo = uol[r][tid];
+          T zm = q ? zo.b : zo.a;
+          T zp = q ? pp[r][1] : pp[r][0];
+          if ((wave_bnd_xy || bnd_z0 || bnd_z1) && in_x && in_y[r] && in_z) {
+            const int xw = xag + q, yw = ygv[r], pw = p & nm;
+            if (q == 0 && bnd_xl) xm = ghost_of(A.bc, 0, n, yw, pw, c);
+            if (q == 1 && bnd_xr) xp = ghost_of(A.bc, 1, n, yw, pw, c);
+            if (!py && yv[r] == 0) ym = ghost_of(A.bc, 2, n, xw, pw, c);
+            if (!py && yv[r] == nm) yp = ghost_of(A.bc, 3, n, xw, pw, c);
+            if (bnd_z0) zm = ghost_of(A.bc, 4, n, xw, yw, c);
+            if (bnd_z1) zp = ghost_of(A.bc, 5, n, xw, yw, c);
+          }
+          const T nbs = ((((xm + xp) + ym) + yp) + zm) + zp;
+          const T d = fget(p, r, q) - (nbs - (T)6 * c) * ih2;
+          if (out_zn && out_x && out_y[r]) acc += (double)d * (double)d;
+          uol[r][tid] = Pair<T>{ca, cb};
+        }
+      }
       // 0: the even column of row 0 has this colour (the same for every lane of the wave)
       const int q0 = __builtin_amdgcn_readfirstlane((yv[0] + p + colour) & 1);
 #pragma unroll
@@ -323,6 +368,11 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
         }
         const T fv = fget(p, r, q);
         const T nbs = ((((xm + xp) + ym) + yp) + zm) + zp;
+        if (INNORM && colour == 0) {
+          // the red cell's input defect: every neighbour of a red cell is black, still input
+          const T d = fv - (nbs - (T)6 * c) * ih2;
+          if (out_zn && out_x && out_y[r]) acc += (double)d * (double)d;
+        }
         const T nv = c + omega * ((nbs - h2 * fv) * inv6 - c);
         pc[r][0] = q ? ca : nv;
         pc[r][1] = q ? nv : cb;
@@ -432,7 +482,7 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
             }
         }
       }
-      if (OUT) {
+      if (DSTAGE) {
         if (SWEEP) defect_out(u[s4], u[s3], u[s2], P - 3);
         else defect_out(u[s2], u[s1], u[k], P - 1);
       }
@@ -455,7 +505,7 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
       if (kRing > 4) step(g, std::integral_constant<int, 4 % kRing>{});
     }
   }
-  if (OUT == 2) {
+  if (OUT == 2 || OUT == 3) {
     // the exchange buffer is free once every wave has left the march
     double* red = reinterpret_cast<double*>(&xch[0][0][0][0]);
     acc = wave_sum(acc);
@@ -481,6 +531,12 @@ struct Cfg {
 template <>
 struct Cfg<double, 1> {
   static constexpr int R = 4, W = 8;
+};
+// the sweep that also takes the input's defect norm: 12 waves leave each ~170 registers
+// (with 16 waves, 128, and the input-defect operands spill)
+template <>
+struct Cfg<double, 3> {
+  static constexpr int R = 2, W = 12;
 };
 
 int zchunk_for(int n) {
@@ -579,6 +635,21 @@ int fused_sweep_norm(const T* uin, T* uout, const T* f, double* part, int n, dou
   return fused_grid_blocks<T>(n, 4, 3);
 }
 
+template <typename T>
+int fused_sweep_input_norm(const T* uin, T* uout, const T* f, double* part, int n, double h, double omega,
+                           const LevelBC& bc, hipStream_t s) {
+  FusedArgs A = base_args(uin, uout, f, n, h, omega, bc);
+  A.hx = 2;   // the input defect's radius (1) is inside the sweep's
+  A.hy = 2;
+  A.part = part;
+  launch_pass<T, false, 3>(A, s);
+  // one partial per workgroup of the launch (launch_pass's grid)
+  constexpr int R = Cfg<T, 3>::R, W = Cfg<T, 3>::W;
+  const int xo = kTileX - 2 * A.hx, yo = R * W - 2 * A.hy, zc = min(zchunk_for(n), n);
+  const int nt = ((n + xo - 1) / xo) * ((n + yo - 1) / yo) * ((n + zc - 1) / zc);
+  return (nt + 7) / 8 * 8;
+}
+
 int fused_mixed_update_defect(double* phi_in, double* phi_out, const float* e, const double* f, float* r32,
                               double* part, int n, double h, const LevelBC& bc, hipStream_t s) {
   FusedArgs A = base_args<double>(phi_in, phi_out, f, n, h, 1.0, bc);
@@ -666,8 +737,8 @@ std::string fused_blk_pass_name(bool pro, int out) {
 
 template <typename T>
 std::string fused_pass_name(bool pro, int out, bool sweep) {
-  int R = out == 1 ? Cfg<T, 1>::R : out == 2 ? Cfg<T, 2>::R : Cfg<T, 0>::R;
-  int W = out == 1 ? Cfg<T, 1>::W : out == 2 ? Cfg<T, 2>::W : Cfg<T, 0>::W;
+  int R = out == 1 ? Cfg<T, 1>::R : out == 2 ? Cfg<T, 2>::R : out == 3 ? Cfg<T, 3>::R : Cfg<T, 0>::R;
+  int W = out == 1 ? Cfg<T, 1>::W : out == 2 ? Cfg<T, 2>::W : out == 3 ? Cfg<T, 3>::W : Cfg<T, 0>::W;
   if (!sweep) { R = 2; W = 16; }
   return std::string("k_fused<") + (sizeof(T) == 8 ? "double" : "float") + ", " + std::to_string(R) + ", " +
          std::to_string(W) + ", " + (pro ? "true" : "false") + ", " + std::to_string(out) + ", " +
@@ -684,6 +755,8 @@ std::string fused_pass_name(bool pro, int out, bool sweep) {
   template int fused_sweep_norm<T>(const T*, T*, const T*, double*, int, double, double, const LevelBC&,         \
                                    hipStream_t);                                                                \
   template int fused_grid_blocks<T>(int, int, int);                                                             \
+  template int fused_sweep_input_norm<T>(const T*, T*, const T*, double*, int, double, double, const LevelBC&,    \
+                                         hipStream_t);                                                          \
   template void fused_defect_restrict<T>(const T*, const T*, T*, T*, int, double, const LevelBC&, hipStream_t);  \
   template int fused_defect_norm<T>(const T*, const T*, double*, int, double, const LevelBC&, hipStream_t, float*); \
   template std::string fused_pass_name<T>(bool, int, bool);                                                     \
