@@ -520,24 +520,25 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
   }
 }
 
-// Tile configuration per precision and pass kind: R rows per lane, W waves per workgroup
-// (tile 128 x R*W).  The restricted-defect pass keeps one more plane and the most temporaries
-// live, so in FP64 it runs fewer, wider lanes (R = 4) to stay within the register file
-// (measured faster than R = 2 for that pass, slower for the others).
-template <typename T, int OUT>
-struct Cfg {
-  static constexpr int R = 2, W = 16;
-};
-template <>
-struct Cfg<double, 1> {
-  static constexpr int R = 4, W = 8;
-};
-// the sweep that also takes the input's defect norm: 12 waves leave each ~170 registers
-// (with 16 waves, 128, and the input-defect operands spill)
-template <>
-struct Cfg<double, 3> {
-  static constexpr int R = 2, W = 12;
-};
+// Tile shape per precision and pass kind: R rows per lane, W waves per workgroup (tile
+// 128 x R*W).  Measured: R = 2, W = 16 for most passes; the FP64 pass with the fused
+// restricted defect keeps one more plane and the most temporaries live, so it runs fewer,
+// wider lanes (R = 4, W = 8); the FP64 head pass (sweep + input norm) needs ~150 registers
+// (W = 12).  Passes without a sweep, and every pass with a norm, use R = 2, W = 16 (four rows
+// per lane for the FP32 sweep measured slower: occupancy falls from 7 to 4 waves per SIMD).
+template <typename T, bool PRO, int OUT, int MODE>
+constexpr int cfg_R() {
+  if (MODE != MODE_SWEEP) return 2;
+  if (sizeof(T) == 8 && OUT == 1) return 4;
+  return 2;
+}
+template <typename T, bool PRO, int OUT, int MODE>
+constexpr int cfg_W() {
+  if (MODE != MODE_SWEEP) return 16;
+  if (sizeof(T) == 8 && OUT == 1) return 8;
+  if (sizeof(T) == 8 && OUT == 3) return 12;
+  return 16;
+}
 
 int zchunk_for(int n) {
   if (n >= 512) return 64;
@@ -547,7 +548,7 @@ int zchunk_for(int n) {
 
 template <typename T, bool PRO, int OUT, int MODE = MODE_SWEEP, bool BLK = false>
 void launch_pass(FusedArgs A, hipStream_t s) {
-  constexpr int R = MODE == MODE_SWEEP ? Cfg<T, OUT>::R : 2, W = MODE == MODE_SWEEP ? Cfg<T, OUT>::W : 16;
+  constexpr int R = cfg_R<T, PRO, OUT, MODE>(), W = cfg_W<T, PRO, OUT, MODE>();
   A.xo = kTileX - 2 * A.hx;
   A.yo = R * W - 2 * A.hy;
   A.zc = min(zchunk_for(A.n), A.n);
@@ -617,8 +618,10 @@ void fused_prolong_sweep(const T* uin, T* uout, const T* f, const T* ec, const L
 
 template <typename T>
 int fused_grid_blocks(int n, int hx, int hy) {
-  constexpr int R = 2, W = 16;   // the tiling of every pass with a norm (Cfg<T, 2>, no-sweep modes)
-  static_assert(Cfg<T, 2>::R == R && Cfg<T, 2>::W == W, "norm passes share one tiling");
+  constexpr int R = 2, W = 16;   // the tiling of the norm passes (fused or defect-only)
+  static_assert(cfg_R<T, false, 2, MODE_SWEEP>() == R && cfg_W<T, false, 2, MODE_SWEEP>() == W &&
+                    cfg_R<T, false, 2, MODE_DEF>() == R && cfg_W<T, false, 2, MODE_DEF>() == W,
+                "norm passes share one tiling");
   const int xo = kTileX - 2 * hx, yo = R * W - 2 * hy, zc = min(zchunk_for(n), n);
   const int nt = ((n + xo - 1) / xo) * ((n + yo - 1) / yo) * ((n + zc - 1) / zc);
   return (nt + 7) / 8 * 8;
@@ -644,7 +647,7 @@ int fused_sweep_input_norm(const T* uin, T* uout, const T* f, double* part, int 
   A.part = part;
   launch_pass<T, false, 3>(A, s);
   // one partial per workgroup of the launch (launch_pass's grid)
-  constexpr int R = Cfg<T, 3>::R, W = Cfg<T, 3>::W;
+  constexpr int R = cfg_R<T, false, 3, MODE_SWEEP>(), W = cfg_W<T, false, 3, MODE_SWEEP>();
   const int xo = kTileX - 2 * A.hx, yo = R * W - 2 * A.hy, zc = min(zchunk_for(n), n);
   const int nt = ((n + xo - 1) / xo) * ((n + yo - 1) / yo) * ((n + zc - 1) / zc);
   return (nt + 7) / 8 * 8;
@@ -730,19 +733,33 @@ int fused_blk_defect_norm(const T* u, const T* f, double* part, int Lm, int Lb, 
 }
 
 template <typename T>
+std::string kname(int R, int W, bool pro, int out, int mode, bool blk) {
+  return std::string("k_fused<") + (sizeof(T) == 8 ? "double" : "float") + ", " + std::to_string(R) + ", " +
+         std::to_string(W) + ", " + (pro ? "true" : "false") + ", " + std::to_string(out) + ", " +
+         std::to_string(mode) + ", " + (blk ? "true" : "false") + ">";
+}
+
+template <typename T>
 std::string fused_blk_pass_name(bool pro, int out) {
-  return std::string("k_fused<") + (sizeof(T) == 8 ? "double" : "float") + ", 2, 16, " + (pro ? "true" : "false") +
-         ", " + std::to_string(out) + ", " + std::to_string(out ? MODE_DEF : MODE_SWEEP) + ", true>";
+  // the block passes: plain or prolonging sweeps, and the defect-only restricted defect
+  if (out) return kname<T>(2, 16, false, out, MODE_DEF, true);
+  if (pro) return kname<T>(cfg_R<T, true, 0, MODE_SWEEP>(), cfg_W<T, true, 0, MODE_SWEEP>(), true, 0, MODE_SWEEP, true);
+  return kname<T>(cfg_R<T, false, 0, MODE_SWEEP>(), cfg_W<T, false, 0, MODE_SWEEP>(), false, 0, MODE_SWEEP, true);
 }
 
 template <typename T>
 std::string fused_pass_name(bool pro, int out, bool sweep) {
-  int R = out == 1 ? Cfg<T, 1>::R : out == 2 ? Cfg<T, 2>::R : out == 3 ? Cfg<T, 3>::R : Cfg<T, 0>::R;
-  int W = out == 1 ? Cfg<T, 1>::W : out == 2 ? Cfg<T, 2>::W : out == 3 ? Cfg<T, 3>::W : Cfg<T, 0>::W;
-  if (!sweep) { R = 2; W = 16; }
-  return std::string("k_fused<") + (sizeof(T) == 8 ? "double" : "float") + ", " + std::to_string(R) + ", " +
-         std::to_string(W) + ", " + (pro ? "true" : "false") + ", " + std::to_string(out) + ", " +
-         std::to_string(sweep ? MODE_SWEEP : MODE_DEF) + ", false>";
+  if (!sweep) return kname<T>(2, 16, pro, out, MODE_DEF, false);
+  int R = 2, W = 16;
+  switch (out) {
+    case 1: R = cfg_R<T, false, 1, MODE_SWEEP>(); W = cfg_W<T, false, 1, MODE_SWEEP>(); break;
+    case 2: R = cfg_R<T, false, 2, MODE_SWEEP>(); W = cfg_W<T, false, 2, MODE_SWEEP>(); break;
+    case 3: R = cfg_R<T, false, 3, MODE_SWEEP>(); W = cfg_W<T, false, 3, MODE_SWEEP>(); break;
+    default:
+      R = pro ? cfg_R<T, true, 0, MODE_SWEEP>() : cfg_R<T, false, 0, MODE_SWEEP>();
+      W = pro ? cfg_W<T, true, 0, MODE_SWEEP>() : cfg_W<T, false, 0, MODE_SWEEP>();
+  }
+  return kname<T>(R, W, pro, out, MODE_SWEEP, false);
 }
 
 #define MG_FUSED_INST(T)                                                                                        \
