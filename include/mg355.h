@@ -210,7 +210,9 @@ int mg_op_coarsest(mg_ctx *ctx, double h, const mg_level_bc *bc, double *u, cons
                    void *stream);
 
 /* Fused down step of a V-cycle level (Alg. 1 steps 1-3): `npre` smoothing sweeps of u,
- * then fc = restriction of the defect f - L u; uc = 0.  u, f: device n^3; fc, uc: (n/2)^3. */
+ * then fc = restriction of the defect f - L u; uc = 0.  u, f: device n^3; fc, uc: (n/2)^3.
+ * The defect runs fused into the last sweep or as its own pass as the context's schedule
+ * says ("pass" lines of mg_tuning_set; default: its own pass). */
 int mg_op_down(mg_ctx *ctx, int n, double h, double omega, int npre, const mg_level_bc *bc,
                double *u, const double *f, double *fc, double *uc, void *stream);
 

@@ -1329,13 +1329,18 @@ int mg_op_down(mg_ctx* c, int n, double h, double omega, int npre, const mg_leve
     double* tmp = nullptr;
     st = op_scratch(c, cells(ilog2(n)) * sizeof(double), &tmp);
     if (st) return st;
+    // the context's schedule, as in the solver: the restricted defect fused into the last
+    // sweep or as its own pass
+    auto it_split = c->pass_split.find(ilog2(n));
+    const bool sdef = it_split != c->pass_split.end() ? (it_split->second & 1) != 0 : true;
     double* cur = u;
     double* oth = tmp;
     for (int it = 0; it < npre; ++it) {
-      if (it == npre - 1) fused_sweep_defect<double>(cur, oth, f, fc, uc, n, h, omega, b, s);
+      if (it == npre - 1 && !sdef) fused_sweep_defect<double>(cur, oth, f, fc, uc, n, h, omega, b, s);
       else fused_sweep<double>(cur, oth, f, n, h, omega, b, s);
       std::swap(cur, oth);
     }
+    if (sdef) fused_defect_restrict<double>(cur, f, fc, uc, n, h, b, s);
     if (cur != u) HIP_CHECK(c, hipMemcpyAsync(u, cur, cells(ilog2(n)) * sizeof(double), hipMemcpyDeviceToDevice, s));
     return op_epilogue(c);
   }
