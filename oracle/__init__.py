@@ -83,6 +83,8 @@ def _load():
     lib.oracle_multipole_potential.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp,
                                                ctypes.c_int, _dp, ctypes.c_double]
     lib.oracle_multipole_potential.restype = ctypes.c_double
+    lib.oracle_gravity.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, _ip, ctypes.POINTER(_dp), _dp, _dp,
+                                   _dp]
     lib.oracle_num_threads.restype = ctypes.c_int
     lib.oracle_set_threads.argtypes = [ctypes.c_int]
     _lib = lib
@@ -301,6 +303,30 @@ def coarsest(h, f, kinds, bext=None):
     lib.oracle_op_coarsest(float(h), _ptr(u), _ptr(ff), _kinds(kinds).ctypes.data_as(_ip),
                            _face_ptrs(bext, keep))
     return float(u[0])
+
+
+def gravity(phi, h, kinds, bext=None, rho=None, faces=False):
+    """g = -grad phi in the cell-centred scheme of Sec. 2.4 (eq. acceleration): returns
+    g (3, n, n, n); with rho also rho*g (3, n, n, n); with faces=True also the face values
+    (gx (n, n, n+1), gy (n, n+1, n), gz (n+1, n, n)), each indexed [k][j][i]."""
+    lib = _load()
+    phi = _f64(phi)
+    n = phi.shape[0]
+    g = np.zeros((3, n, n, n))
+    rg = np.zeros((3, n, n, n)) if rho is not None else None
+    gf = np.zeros(3 * n * n * (n + 1)) if faces else None
+    rho_a = _f64(rho) if rho is not None else None
+    keep = []
+    lib.oracle_gravity(n, float(h), _ptr(phi), _ptr(rho_a) if rho_a is not None else None,
+                       _kinds(kinds).ctypes.data_as(_ip), _face_ptrs(bext, keep), _ptr(g),
+                       _ptr(rg) if rg is not None else None, _ptr(gf) if gf is not None else None)
+    out = [g]
+    if rho is not None:
+        out.append(rg)
+    if faces:
+        m = n * n * (n + 1)
+        out.append((gf[:m].reshape(n, n, n + 1), gf[m:2 * m].reshape(n, n + 1, n), gf[2 * m:].reshape(n + 1, n, n)))
+    return out[0] if len(out) == 1 else tuple(out)
 
 
 def multipole_moments(rho, dx, lmax=4, origin=None):

@@ -688,6 +688,49 @@ void oracle_op_coarsest(double h, double *u, const double *f, const int *kind,
   u[0] = gu[gidx(1, 0, 0, 0)];
 }
 
+/* Gravitational acceleration g = -grad phi (eq. acceleration) in the cell-centred source-term
+ * scheme of Sec. 2.4: on each cell face the difference of the two adjacent potentials divided
+ * by h, with the sign of -grad; in each cell the mean of its two faces along each axis; and the
+ * momentum source rho g.  Ghost potentials across the domain surface follow the boundary rule
+ * of Sec. 2.3.6 (fill_ghosts), so a fixed face gives -(phi_0 - b)/(h/2) and a zero-gradient face
+ * gives 0.
+ *   g     3 n^3: g_x, g_y, g_z, each x fastest;
+ *   rhog  3 n^3 or NULL: rho g_x, rho g_y, rho g_z (rho must then be given);
+ *   gface 3 n^2 (n+1) or NULL: the face values, x faces as [k][j][i'] with i' = 0..n (face
+ *         i' between cells i'-1 and i'), then y faces [k][j'][i], then z faces [k'][j][i]. */
+void oracle_gravity(int n, double h, const double *phi, const double *rho, const int *kind,
+                    const double *const *bext, double *g, double *rhog, double *gface) {
+  obc bc = make_bc(kind, bext);
+  double *gp = to_ghosted(phi, n);
+  fill_ghosts(gp, n, &bc);
+  size_t n3 = (size_t)n * n * n, nf = (size_t)n * n * (n + 1);
+#pragma omp parallel for schedule(static)
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        size_t c = ((size_t)k * n + j) * n + i;
+        double p0 = gp[gidx(n, i, j, k)];
+        /* faces on the low and high side of the cell along x, y, z */
+        double fx0 = -(p0 - gp[gidx(n, i - 1, j, k)]) / h, fx1 = -(gp[gidx(n, i + 1, j, k)] - p0) / h;
+        double fy0 = -(p0 - gp[gidx(n, i, j - 1, k)]) / h, fy1 = -(gp[gidx(n, i, j + 1, k)] - p0) / h;
+        double fz0 = -(p0 - gp[gidx(n, i, j, k - 1)]) / h, fz1 = -(gp[gidx(n, i, j, k + 1)] - p0) / h;
+        double cg[3] = {0.5 * (fx0 + fx1), 0.5 * (fy0 + fy1), 0.5 * (fz0 + fz1)};
+        for (int a = 0; a < 3; ++a) {
+          g[a * n3 + c] = cg[a];
+          if (rhog) rhog[a * n3 + c] = rho[c] * cg[a];
+        }
+        if (gface) {
+          gface[((size_t)k * n + j) * (n + 1) + i] = fx0;
+          gface[nf + ((size_t)k * (n + 1) + j) * n + i] = fy0;
+          gface[2 * nf + ((size_t)k * n + j) * n + i] = fz0;
+          if (i == n - 1) gface[((size_t)k * n + j) * (n + 1) + n] = fx1;
+          if (j == n - 1) gface[nf + ((size_t)k * (n + 1) + n) * n + i] = fy1;
+          if (k == n - 1) gface[2 * nf + ((size_t)n * n + j) * n + i] = fz1;
+        }
+      }
+  free(gp);
+}
+
 /* per-level boundary face arrays computed by the solver set-up (for parity of set-up) */
 int oracle_state_levels(ostate *s) { return s->L; }
 
