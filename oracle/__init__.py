@@ -52,8 +52,9 @@ def _load():
     lib.oracle_solve.restype = ctypes.c_int
     lib.oracle_solve.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _ip,
                                  ctypes.POINTER(_dp), ctypes.c_int, ctypes.c_int, _dp,
-                                 ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                 ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                  ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp, _dp, _ip]
+    lib.oracle_set_scheme.argtypes = [vp, ctypes.c_int]
     lib.oracle_state_create.restype = vp
     lib.oracle_state_create.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _ip,
                                         ctypes.POINTER(_dp), ctypes.c_int, ctypes.c_int, _dp,
@@ -131,10 +132,12 @@ def set_threads(t: int) -> None:
 # ------------------------------------------------------------------ whole solve
 
 def solve(rho, dx, kinds, fixed_b=None, lmax=4, origin=None, npre=2, npost=2, omega=1.15,
-          mode="fmg", phi0=None, tol=1e-10, max_cycles=50, fixed_cycles=0, four_pi_g=FOUR_PI_G):
+          mode="fmg", phi0=None, tol=1e-10, max_cycles=50, fixed_cycles=0, four_pi_g=FOUR_PI_G,
+          scheme="cs"):
     """Oracle solve of nabla^2 phi = 4 pi G rho (eq. poisson).
 
     ``fixed_b``: six (n, n) face-centre arrays (or None) for FIXED faces.
+    ``scheme``: "cs" (correction scheme, Alg. 1) or "fas" (Alg. 3) for the iterations.
     Returns ``(phi, hist, status)``.
     """
     lib = _load()
@@ -150,7 +153,8 @@ def solve(rho, dx, kinds, fixed_b=None, lmax=4, origin=None, npre=2, npost=2, om
     nh = ctypes.c_int(0)
     st = lib.oracle_solve(n, float(dx), float(four_pi_g), _ptr(rho), k.ctypes.data_as(_ip), bp,
                           int(lmax), int(origin is not None), _ptr(org), int(npre), int(npost),
-                          float(omega), 0 if mode == "fmg" else 1, float(tol), int(max_cycles),
+                          float(omega), 0 if mode == "fmg" else 1, 1 if scheme == "fas" else 0,
+                          float(tol), int(max_cycles),
                           int(fixed_cycles), _ptr(phi), _ptr(hist), ctypes.byref(nh))
     return phi, hist[: nh.value].copy(), st
 
@@ -159,7 +163,7 @@ class State:
     """Step-by-step access to the oracle iteration (set-up, FMG, single V-cycles)."""
 
     def __init__(self, rho, dx, kinds, fixed_b=None, lmax=4, origin=None, npre=2, npost=2,
-                 omega=1.15, four_pi_g=FOUR_PI_G):
+                 omega=1.15, four_pi_g=FOUR_PI_G, scheme="cs"):
         self._lib = _load()
         self.rho = _f64(rho)
         self.n = self.rho.shape[0]
@@ -174,6 +178,7 @@ class State:
                                                 int(npost), float(omega), ctypes.byref(err))
         if not self._s:
             raise ValueError(f"oracle set-up failed with status {err.value}")
+        self._lib.oracle_set_scheme(self._s, 1 if scheme == "fas" else 0)
 
     def __del__(self):
         if getattr(self, "_s", None):

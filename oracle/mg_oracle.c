@@ -367,6 +367,8 @@ typedef struct {
   obc *phys;          /* physical boundary description per level */
   obc hom;            /* homogeneous description (same on all levels) */
   double *bstore;     /* storage for all per-level face arrays */
+  int fas;            /* 1: iterate with the Full Approximation Scheme (Alg. 3) */
+  double **pbar;      /* FAS: restricted potential per level (Sec. 3.2.1's extra storage) */
   double rms_f;
   double q[25], origin[3];
 } ostate;
@@ -391,8 +393,78 @@ static void vcycle(ostate *s, int l, const obc *bc) {
   for (int it = 0; it < s->npost; ++it) smooth(s->u[l], s->f[l], n, h, s->omega, bc);   /* 7 */
 }
 
-/* Alg. 2 (FMG): coarsest solve, then per level tricubic prolongation and one V-cycle, each
- * level using the physical boundary description evaluated at its own geometry. */
+/* out = L_h u (eq. discretized2) on the active cells, ghosts of u from bc. */
+static void laplacian(double *u, double *out, int n, double h, const obc *bc) {
+  fill_ghosts(u, n, bc);
+  double ih2 = 1.0 / (h * h);
+#pragma omp parallel for schedule(static)
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        size_t c = gidx(n, i, j, k);
+        double nb = u[gidx(n, i - 1, j, k)] + u[gidx(n, i + 1, j, k)] + u[gidx(n, i, j - 1, k)] +
+                    u[gidx(n, i, j + 1, k)] + u[gidx(n, i, j, k - 1)] + u[gidx(n, i, j, k + 1)];
+        out[c] = (nb - 6.0 * u[c]) * ih2;
+      }
+}
+
+/* Alg. 3 (FAS) on level l.  Every level solves the original equation for the potential, so
+ * every level uses the physical boundary description at its own geometry (Sec. 2.3.6); the
+ * coarse-grid correction psi - phibar then obeys the homogeneous conditions, which its
+ * prolongation uses.  On the single coarsest cell the equation is solved with the physical
+ * conditions starting from phibar (Sec. 2.3.2): when no face fixes the zero point the cell's
+ * value is arbitrary and phibar is kept (a zero correction). */
+static void fas(ostate *s, int l) {
+  int n = s->nl[l], nc = n / 2;
+  double h = s->hl[l];
+  const obc *bc = &s->phys[l];
+  size_t g3c = (size_t)(nc + 2) * (nc + 2) * (nc + 2);
+  for (int it = 0; it < s->npre; ++it) smooth(s->u[l], s->f[l], n, h, s->omega, bc);   /* 1 */
+  defect(s->u[l], s->f[l], s->d[l], n, h, bc);                                         /* 2 */
+  restrict8(s->d[l], s->d[l - 1], nc);                                                  /* 3 */
+  restrict8(s->u[l], s->pbar[l - 1], nc);                                               /* 4 */
+  laplacian(s->pbar[l - 1], s->f[l - 1], nc, s->hl[l - 1], &s->phys[l - 1]);            /* 5 */
+  for (int k = 0; k < nc; ++k)
+    for (int j = 0; j < nc; ++j)
+      for (int i = 0; i < nc; ++i) {
+        size_t c = gidx(nc, i, j, k);
+        s->f[l - 1][c] = s->d[l - 1][c] + s->f[l - 1][c];
+      }
+  memcpy(s->u[l - 1], s->pbar[l - 1], sizeof(double) * g3c);                           /* 6 */
+  if (l - 1 == 0) {
+    double keep = s->u[0][gidx(1, 0, 0, 0)];
+    coarsest(s->u[0], s->f[0], s->hl[0], &s->phys[0]);
+    int fixes = 0;
+    for (int face = 0; face < 6; ++face)
+      fixes |= s->phys[0].kind[face] != OR_PERIODIC && s->phys[0].kind[face] != OR_ZERO_GRADIENT;
+    if (!fixes) s->u[0][gidx(1, 0, 0, 0)] = keep;
+  } else {
+    fas(s, l - 1);
+  }
+  for (int k = 0; k < nc; ++k)                                                           /* 7 */
+    for (int j = 0; j < nc; ++j)
+      for (int i = 0; i < nc; ++i) {
+        size_t c = gidx(nc, i, j, k);
+        s->u[l - 1][c] = s->u[l - 1][c] - s->pbar[l - 1][c];
+      }
+  fill_ghosts(s->u[l - 1], nc, &s->hom);
+  prolong(s->u[l - 1], nc, s->u[l], 0, 1);                                               /* 8, 9 */
+  for (int it = 0; it < s->npost; ++it) smooth(s->u[l], s->f[l], n, h, s->omega, bc);   /* 10 */
+}
+
+/* one iteration on level l in the chosen scheme */
+static void cycle(ostate *s, int l) {
+  if (s->fas) {
+    if (l == 0) coarsest(s->u[0], s->f[0], s->hl[0], &s->phys[0]);
+    else fas(s, l);
+  } else {
+    vcycle(s, l, &s->phys[l]);
+  }
+}
+
+/* Alg. 2 (FMG): coarsest solve, then per level tricubic prolongation and one V-cycle (or one
+ * FAS iteration), each level using the physical boundary description evaluated at its own
+ * geometry. */
 static void fmg(ostate *s) {
   size_t n0 = 27;
   memset(s->u[0], 0, sizeof(double) * n0);
@@ -400,7 +472,7 @@ static void fmg(ostate *s) {
   for (int l = 1; l <= s->L; ++l) {
     fill_ghosts(s->u[l - 1], s->nl[l - 1], &s->phys[l - 1]);
     prolong(s->u[l - 1], s->nl[l - 1], s->u[l], 1, 0);
-    vcycle(s, l, &s->phys[l]);
+    cycle(s, l);
   }
 }
 
@@ -415,8 +487,8 @@ static int is_pow2(int n) { return n >= 1 && (n & (n - 1)) == 0; }
 
 void oracle_state_destroy(ostate *s) {
   if (!s) return;
-  for (int l = 0; l <= s->L; ++l) { free(s->u[l]); free(s->f[l]); free(s->d[l]); }
-  free(s->u); free(s->f); free(s->d); free(s->nl); free(s->hl); free(s->phys); free(s->bstore);
+  for (int l = 0; l <= s->L; ++l) { free(s->u[l]); free(s->f[l]); free(s->d[l]); free(s->pbar[l]); }
+  free(s->u); free(s->f); free(s->d); free(s->pbar); free(s->nl); free(s->hl); free(s->phys); free(s->bstore);
   free(s);
 }
 
@@ -452,6 +524,7 @@ ostate *oracle_state_create(int n, double dx, double four_pi_g, const double *rh
   s->u = (double **)calloc(L + 1, sizeof(double *));
   s->f = (double **)calloc(L + 1, sizeof(double *));
   s->d = (double **)calloc(L + 1, sizeof(double *));
+  s->pbar = (double **)calloc(L + 1, sizeof(double *));
   s->phys = (obc *)calloc(L + 1, sizeof(obc));
   for (int l = 0; l <= L; ++l) {
     int nl = 1 << l;
@@ -461,6 +534,7 @@ ostate *oracle_state_create(int n, double dx, double four_pi_g, const double *rh
     s->u[l] = (double *)calloc(g3, sizeof(double));
     s->f[l] = (double *)calloc(g3, sizeof(double));
     s->d[l] = (double *)calloc(g3, sizeof(double));
+    s->pbar[l] = (double *)calloc(g3, sizeof(double));
   }
 
   /* source f = 4 pi G rho (eq. poisson); mean removed when no face fixes the zero point */
@@ -539,9 +613,12 @@ ostate *oracle_state_create(int n, double dx, double four_pi_g, const double *rh
 
 void oracle_fmg(ostate *s) { fmg(s); }
 
-/* one V-cycle on the finest level; returns the relative residual after it */
+/* scheme of the iterations: 0 = correction scheme (Alg. 1), 1 = FAS (Alg. 3) */
+void oracle_set_scheme(ostate *s, int fas) { s->fas = fas != 0; }
+
+/* one V-cycle (or FAS iteration) on the finest level; returns the relative residual after it */
 double oracle_vcycle(ostate *s) {
-  vcycle(s, s->L, &s->phys[s->L]);
+  cycle(s, s->L);
   return residual_norm(s);
 }
 
@@ -569,20 +646,22 @@ void oracle_get_origin_moments(ostate *s, double *origin, double *q) {
   for (int t = 0; t < 25; ++t) q[t] = s->q[t];
 }
 
-/* Whole solve (Sec. 2.3.7): FMG (mode 0) or V-cycles from the given phi (mode 1), then
+/* Whole solve (Sec. 2.3.7): FMG (mode 0) or V-cycles from the given phi (mode 1), with the
+ * correction scheme (scheme 0, Alg. 1) or FAS (scheme 1, Alg. 3) as the iteration, then
  * V-cycles until the relative residual is <= tol, stalls (two consecutive cycles each
  * reducing it by less than 10 %), or max_cycles is reached; fixed_cycles > 0 runs exactly
  * that many cycles.  hist receives r after FMG (or of the initial guess) and after each
  * cycle; *n_hist its length. */
 int oracle_solve(int n, double dx, double four_pi_g, const double *rho, const int *kind,
                  const double *const *bfix, int lmax, int use_origin, const double *origin,
-                 int npre, int npost, double omega, int mode, double tol, int max_cycles,
+                 int npre, int npost, double omega, int mode, int scheme, double tol, int max_cycles,
                  int fixed_cycles, double *phi, double *hist, int *n_hist) {
   int err;
   ostate *s = oracle_state_create(n, dx, four_pi_g, rho, kind, bfix, lmax, use_origin, origin,
                                   npre, npost, omega, &err);
   *n_hist = 0;
   if (!s) return err;
+  s->fas = scheme != 0;
   if (mode == 0) fmg(s);
   else oracle_set_phi(s, phi);
   double r = residual_norm(s);
