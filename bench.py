@@ -13,6 +13,8 @@ in HBM.  The JSON line reports:
                 its mean launch time (HIP events on the solve stream) against 8 TB/s;
   cpu_baseline  the CPU oracle timed on a bounded sample of the same workload;
   mixed         the same numbers for the mixed-precision solve; p50/p99 solve latency.
+  gravity       g = -grad phi and rho g of the solved potential (Sec. 2.4): mean launch time
+                and its HBM roofline (64 algorithmic bytes per cell), CPU oracle beside it;
   batched       the 256^3 lognormal field as 4096 MeshBlocks of 16^3 (autotuned), FP64 and
                 mixed, beside the dense FP64 solve of the same field;
   serving       a mixed-size request stream through the serving runtime: saturated
@@ -112,6 +114,51 @@ def cpu_baseline(n: int, cycles: int = 3):
             "kind": "oracle",
             "sample": f"{n}^3 clump density, {cycles} V(2,2) cycles from zero (FMG not timed), "
                       f"{dt * 1e3:.0f} ms per cycle"}
+
+
+def gravity_leg(mg, ctx, rho, n: int, reps: int, with_cpu: bool):
+    """g = -grad phi and rho g of the solved potential (the step after the solve): one launch
+    of the streaming gravity kernel per call, reps calls bracketed by HIP events on the stream
+    they run on.  Algorithmic bytes per cell: phi and rho read, g and rho g written = 64."""
+    import torch
+    phi, _, _ = mg.solve(rho, 1.0 / n, "periodic", tol=1e-10, ctx=ctx)
+    p = mg.params(n, 1.0 / n)
+    b = mg.boundary("periodic")
+    g = torch.empty((3, n, n, n), dtype=torch.float64, device=rho.device)
+    rg = torch.empty_like(g)
+    s = torch.cuda.current_stream()
+    for _ in range(3):
+        mg.mg_gravity(ctx, p, b, phi, rho, g, rg, None, s)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        mg.mg_gravity(ctx, p, b, phi, rho, g, rg, None, s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    kernel = mg.mg_gravity_kernel_name(p, True, True, False)
+    by = 64 * n ** 3
+    achieved = by / (ms * 1e-3) / 1e9
+    out = {"kernel": kernel, "outputs": "g, rho g", "launches": reps, "avg_launch_ms": ms,
+           "algorithmic_bytes_per_launch": by, "Gcells_per_s": n ** 3 / (ms * 1e-3) / 1e9,
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kernel, n)}}
+    del g, rg
+    if with_cpu:
+        import numpy as np
+
+        import oracle
+        m = 256
+        rng = np.random.default_rng(0)
+        ph, rh = rng.uniform(-1, 1, (m, m, m)), rng.uniform(0, 2, (m, m, m))
+        t0 = time.perf_counter()
+        oracle.gravity(ph, 1.0 / m, "periodic", rho=rh)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": m ** 3 / dt / 1e9, "unit": "Gcells/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "sample": f"{m}^3 random potential and density, g and rho g, "
+                                                           f"{dt * 1e3:.0f} ms"}
+    return out
 
 
 def batched_leg(steps: int, seed: int, n: int = 256, block_n: int = 16):
@@ -222,6 +269,7 @@ def main() -> int:
                     help="requests per serving run (0: skip the serving leg)")
     ap.add_argument("--serve-workers", type=int, default=4)
     ap.add_argument("--no-batched", action="store_true", help="skip the MeshBlock (4096 x 16^3) leg")
+    ap.add_argument("--no-gravity", action="store_true", help="skip the g = -grad phi leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device to device (reference for profiler byte counters)")
     args = ap.parse_args()
@@ -296,6 +344,8 @@ def main() -> int:
         "solve_latency_ms": {"p50": pct(lat, 0.5), "p99": pct(lat, 0.99)},
     }
     ctx.set_kernel_timing(False)
+    if not args.no_gravity:
+        out["gravity"] = gravity_leg(mg, ctx, rho, n, 20, not args.no_cpu_baseline)
     if not args.no_mixed:
         lat_m, cyc_m, hists_m, _ = run_solves(mg, ctx, rho, n, "mixed", args.steps, args.warmup, args.tol)
         tvm = statistics.median(cyc_m)

@@ -57,13 +57,20 @@ extern "C" {
 #define MG_PREC_MIXED 1        /* FP32 smoothing / restriction / prolongation inside FP64
                                   defect-correction (FP64 residual and phi update) */
 
+#define MG_SCHEME_CS 0         /* V-cycles in the correction scheme (Alg. 1)             */
+#define MG_SCHEME_FAS 1        /* Full Approximation Scheme iterations (Alg. 3; FMG with FAS,
+                                  Sec. 2.3.5): every level solves for the potential with its
+                                  own physical boundary values; on this linear problem it
+                                  reaches the correction scheme's iterates up to rounding.
+                                  FP64 and the dense layout only (else MG_ERR_UNSUPPORTED). */
+
 #define MG_LAYOUT_DENSE 0      /* one n^3 array per level, x fastest */
 #define MG_LAYOUT_BLOCKS 1     /* MeshBlock decomposition (Sec. 3.2): rho and phi hold
                                   (n/block_n)^3 blocks of block_n^3 cells, blocks in Morton
                                   order of their coordinates (bits of bx, by, bz interleaved,
                                   x lowest), each block x fastest.  Block levels are coarsened
                                   to one cell per block; those cells form the dense root grid.
-                                  block_n in {2, 4, 8, 16}; multipole faces unsupported. */
+                                  block_n in {2, 4, 8, 16}. */
 
 typedef struct mg_ctx mg_ctx;
 
@@ -81,6 +88,7 @@ typedef struct {
   int precision;    /* MG_PREC_FP64 or MG_PREC_MIXED                                    [FP64] */
   int layout;       /* MG_LAYOUT_DENSE or MG_LAYOUT_BLOCKS                              [DENSE] */
   int block_n;      /* MeshBlock side for MG_LAYOUT_BLOCKS (2..16, power of two, < n)   [16] */
+  int scheme;       /* MG_SCHEME_CS or MG_SCHEME_FAS                                    [CS] */
 } mg_params;
 
 /* Boundary description of a solve. */
@@ -176,6 +184,38 @@ int mg_kernel_timing(const mg_ctx *ctx, int index, int *launches, double *total_
  * q_out (host, 25, index l*l + l + m) receive the results. */
 int mg_multipole_moments(mg_ctx *ctx, int n, double dx, const double *rho, int lmax, int use_origin,
                          const double *origin, double *origin_out, double *q_out, void *stream);
+
+/* Gravitational acceleration g = -grad phi (eq. acceleration) in the cell-centred
+ * source-term scheme of Sec. 2.4, from the potential of a solve:
+ *   face   g_{x,i-1/2} = (phi_{i-1} - phi_i) / dx   (likewise y, z), where a potential
+ *          across the domain surface is the ghost of the solve's boundary rule: periodic
+ *          -> the opposite cell; zero-gradient -> the adjacent cell (face value 0); fixed
+ *          and multipole -> 2 b - adjacent cell (face value (b - phi_0) / (dx/2));
+ *   cell   g_x = (g_{x,i-1/2} + g_{x,i+1/2}) / 2;
+ *   source (rho g)_x = rho g_x   (the momentum source term).
+ * For a power-of-two dx every value is the correctly rounded result of these formulas.
+ *   p      n, dx, four_pi_g (multipole faces), layout, block_n; the iteration fields are
+ *          validated as for mg_solve and otherwise ignored.
+ *   bc     as for mg_solve; MULTIPOLE faces are recomputed from rho as the solve does.
+ *   phi    device, n^3 FP64 in the layout of p; read only.
+ *   rho    device, n^3 FP64 in the layout of p; required for rhog and MULTIPOLE faces,
+ *          else may be NULL.
+ *   g      device, 3 n^3 FP64 (g_x, g_y, g_z one after another, each in the layout of p),
+ *          or NULL.
+ *   rhog   device, 3 n^3 FP64 like g, or NULL.
+ *   gface  device, 3 n^2 (n+1) FP64, or NULL; dense layout only (MG_ERR_UNSUPPORTED
+ *          otherwise): x faces [k][j][i'] with i' = 0..n (face i' lies between cells i'-1
+ *          and i'), then y faces [k][j'][i], then z faces [k'][j][i].
+ * At least one output must be given.  Asynchronous on `stream` (no host synchronisation);
+ * face arrays of FIXED/MULTIPOLE faces use the context's scratch. */
+int mg_gravity(mg_ctx *ctx, const mg_params *p, const mg_bc *bc, const double *phi,
+               const double *rho, double *g, double *rhog, double *gface, void *stream);
+
+/* Name of the kernel mg_gravity launches for these parameters and outputs (nonzero
+ * want_* = that output is given), as profilers list it, written to buf (cap bytes,
+ * NUL-terminated); returns the length needed with the NUL. */
+int mg_gravity_kernel_name(const mg_params *p, int want_g, int want_rhog, int want_gface, char *buf,
+                           int cap);
 
 /* ---- operator entry points (each operator alone, for parity checks) ---------------- */
 

@@ -25,7 +25,7 @@ from ._abi import (MG_BC_FIXED, MG_BC_MULTIPOLE, MG_BC_PERIODIC, MG_BC_ZERO_GRAD
 __all__ = ["Context", "solve", "to_blocks", "from_blocks", "morton_order", "mg_solve", "mg_footprint_bytes", "params", "boundary", "level_bc",
            "mg_op_half_sweep", "mg_op_smooth", "mg_op_defect", "mg_op_restrict", "mg_op_prolong_add",
            "mg_op_prolong_fmg", "mg_op_coarsest", "mg_op_down", "mg_op_up", "mg_multipole_moments",
-           "MgError", "KINDS"]
+           "gravity", "mg_gravity", "mg_gravity_kernel_name", "MgError", "KINDS"]
 
 KINDS = {"periodic": MG_BC_PERIODIC, "zero_gradient": MG_BC_ZERO_GRADIENT, "fixed": MG_BC_FIXED,
          "multipole": MG_BC_MULTIPOLE}
@@ -212,6 +212,8 @@ def params(n: int, dx: float, **kw) -> _abi.MgParams:
             v = {"fp64": MG_PREC_FP64, "mixed": MG_PREC_MIXED}[v]
         if k == "layout" and isinstance(v, str):
             v = {"dense": MG_LAYOUT_DENSE, "blocks": MG_LAYOUT_BLOCKS}[v]
+        if k == "scheme" and isinstance(v, str):
+            v = {"cs": _abi.MG_SCHEME_CS, "fas": _abi.MG_SCHEME_FAS}[v]
         setattr(p, k, v)
     return p
 
@@ -255,9 +257,10 @@ def mg_solve(ctx: Context, p: _abi.MgParams, bc: _abi.MgBC, rho, phi, stream=Non
 def solve(rho, dx: float, bc="periodic", fixed_b=None, lmax: int = 4, origin=None, tol: float = 1e-10,
           max_cycles: int = 50, fixed_cycles: int = 0, npre: int = 2, npost: int = 2, omega: float = 1.15,
           mode: str = "fmg", precision: str = "fp64", layout: str = "dense", block_n: int = 16, phi=None,
-          four_pi_g: float = 4.0 * math.pi, ctx: Optional[Context] = None, stream=None):
+          four_pi_g: float = 4.0 * math.pi, scheme: str = "cs", ctx: Optional[Context] = None, stream=None):
     """Solve nabla^2 phi = 4 pi G rho on the device.  ``rho``: contiguous float64 (n, n, n) tensor
-    on the GPU.  Returns ``(phi, hist, status)``."""
+    on the GPU.  ``scheme``: "cs" (correction-scheme V-cycles) or "fas" (Full Approximation
+    Scheme).  Returns ``(phi, hist, status)``."""
     import torch
     if layout == "blocks":
         # MeshBlock layout: rho is flat (n^3,) in Morton block order (see to_blocks)
@@ -272,12 +275,57 @@ def solve(rho, dx: float, bc="periodic", fixed_b=None, lmax: int = 4, origin=Non
         n = rho.shape[0]
     ctx = ctx or default_context(rho.device.index or 0)
     p = params(n, dx, tol=tol, max_cycles=max_cycles, fixed_cycles=fixed_cycles, npre=npre, npost=npost,
-               omega=omega, mode=mode, precision=precision, layout=layout, block_n=block_n, four_pi_g=four_pi_g)
+               omega=omega, mode=mode, precision=precision, layout=layout, block_n=block_n, four_pi_g=four_pi_g,
+               scheme=scheme)
     b = boundary(bc, fixed_b, lmax, origin)
     if phi is None:
         phi = torch.zeros_like(rho)
     st, hist = mg_solve(ctx, p, b, rho, phi, stream)
     return phi, hist, st
+
+
+def mg_gravity(ctx: Context, p: _abi.MgParams, bc: _abi.MgBC, phi, rho=None, g=None, rhog=None, gface=None,
+               stream=None) -> int:
+    """Raw ``mg_gravity``: writes the given outputs, asynchronously on the stream."""
+    st = ctx._lib.mg_gravity(ctx.handle, ctypes.byref(p), ctypes.byref(bc), _ptr(phi), _ptr(rho), _ptr(g),
+                             _ptr(rhog), _ptr(gface), _stream(stream))
+    return ctx.check(st, "mg_gravity")
+
+
+def mg_gravity_kernel_name(p: _abi.MgParams, g=True, rhog=False, gface=False) -> str:
+    buf = ctypes.create_string_buffer(256)
+    _abi.lib().mg_gravity_kernel_name(ctypes.byref(p), int(g), int(rhog), int(gface), buf, 256)
+    return buf.value.decode()
+
+
+def gravity(phi, dx: float, bc="periodic", rho=None, fixed_b=None, lmax: int = 4, origin=None,
+            want_g: bool = True, want_rhog: bool = False, want_faces: bool = False, layout: str = "dense",
+            block_n: int = 16, four_pi_g: float = 4.0 * math.pi, ctx: Optional[Context] = None, stream=None):
+    """Gravitational acceleration g = -grad phi of a solved potential (cell-centred scheme of
+    the paper's Sec. 2.4).  Returns a dict with "g" (3, n, n, n) [or (3, n^3) in the MeshBlock
+    layout], "rhog" like g, and "faces" = (gx (n, n, n+1), gy (n, n+1, n), gz (n+1, n, n))
+    for the outputs asked for."""
+    import torch
+    if phi.dtype != torch.float64:
+        raise ValueError("phi must be float64")
+    n = phi.shape[0] if layout == "dense" else round(phi.numel() ** (1.0 / 3.0))
+    ctx = ctx or default_context(phi.device.index or 0)
+    p = params(n, dx, layout=layout, block_n=block_n, four_pi_g=four_pi_g)
+    b = boundary(bc, fixed_b, lmax, origin)
+    shape = (3, n, n, n) if layout == "dense" else (3, n ** 3)
+    out = {}
+    g = torch.empty(shape, dtype=torch.float64, device=phi.device) if want_g else None
+    rg = torch.empty(shape, dtype=torch.float64, device=phi.device) if want_rhog else None
+    gf = torch.empty(3 * n * n * (n + 1), dtype=torch.float64, device=phi.device) if want_faces else None
+    mg_gravity(ctx, p, b, phi, rho, g, rg, gf, stream)
+    if want_g:
+        out["g"] = g
+    if want_rhog:
+        out["rhog"] = rg
+    if want_faces:
+        m = n * n * (n + 1)
+        out["faces"] = (gf[:m].view(n, n, n + 1), gf[m:2 * m].view(n, n + 1, n), gf[2 * m:].view(n + 1, n, n))
+    return out
 
 
 # ------------------------------------------------------------------ operator entry points

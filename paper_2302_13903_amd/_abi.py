@@ -18,6 +18,7 @@ MG_BC_PERIODIC, MG_BC_ZERO_GRADIENT, MG_BC_FIXED, MG_BC_MULTIPOLE = 0, 1, 2, 3
 MG_MODE_FMG, MG_MODE_MGI = 0, 1
 MG_PREC_FP64, MG_PREC_MIXED = 0, 1
 MG_LAYOUT_DENSE, MG_LAYOUT_BLOCKS = 0, 1
+MG_SCHEME_CS, MG_SCHEME_FAS = 0, 1
 
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", 2: "STALLED", -1: "INVALID_ARG", -2: "UNSUPPORTED", -3: "OOM",
                 -4: "DEVICE", -5: "NONFINITE"}
@@ -28,7 +29,7 @@ class MgParams(ctypes.Structure):
                 ("mode", ctypes.c_int), ("npre", ctypes.c_int), ("npost", ctypes.c_int),
                 ("omega", ctypes.c_double), ("tol", ctypes.c_double), ("max_cycles", ctypes.c_int),
                 ("fixed_cycles", ctypes.c_int), ("precision", ctypes.c_int), ("layout", ctypes.c_int),
-                ("block_n", ctypes.c_int)]
+                ("block_n", ctypes.c_int), ("scheme", ctypes.c_int)]
 
 
 class MgBC(ctypes.Structure):
@@ -103,6 +104,8 @@ def lib():
         "mg_set_kernel_timing": (i, [_vp, i]),
         "mg_kernel_timing": (i, [_vp, i, _ip, _dp, _dp, ctypes.c_char_p, i]),
         "mg_multipole_moments": (i, [_vp, i, d, _vp, i, i, _dp, _dp, _dp, _vp]),
+        "mg_gravity": (i, [_vp, ctypes.POINTER(MgParams), ctypes.POINTER(MgBC), _vp, _vp, _vp, _vp, _vp, _vp]),
+        "mg_gravity_kernel_name": (i, [ctypes.POINTER(MgParams), i, i, i, ctypes.c_char_p, i]),
         "mg_op_half_sweep": (i, [_vp, i, d, d, i, ctypes.POINTER(MgLevelBC), _vp, _vp, _vp]),
         "mg_op_smooth": (i, [_vp, i, d, d, i, ctypes.POINTER(MgLevelBC), _vp, _vp, _vp]),
         "mg_op_defect": (i, [_vp, i, d, ctypes.POINTER(MgLevelBC), _vp, _vp, _vp, _vp]),

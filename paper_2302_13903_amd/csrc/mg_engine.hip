@@ -106,12 +106,14 @@ struct Layout {
   size_t u2[16];               // second (ping-pong) buffer of the levels swept by fused passes
   size_t phi2 = (size_t)-1;    // mixed mode: ping-pong partner of the caller's FP64 phi
   size_t faces[16];            // 6 extended face arrays per level
+  size_t pbar[16];             // FAS: restricted potential of levels 0..L-1
   size_t total = 0;
 };
 
 // Lb >= 0: MeshBlock layout with 2^Lb blocks per side (levels above Lb are block levels,
 // each swept out of place, so each has a ping-pong partner).
-Layout make_layout(int n, int precision, int Lb = -1) {
+// fas: the restricted-potential arrays of the Full Approximation Scheme (FP64 levels below L).
+Layout make_layout(int n, int precision, int Lb = -1, bool fas = false) {
   Layout y;
   y.L = ilog2(n);
   y.mixed = precision == MG_PREC_MIXED;
@@ -134,6 +136,7 @@ Layout make_layout(int n, int precision, int Lb = -1) {
       y.f32[l] = take(cells(l) * 4);
     }
     y.faces[l] = take(6 * face_sz(l) * 8);
+    y.pbar[l] = (fas && l < y.L) ? take(cells(l) * 8) : (size_t)-1;
     y.u2[l] = (size_t)-1;
     if ((1 << l) >= kFusedMinN || (Lb >= 0 && l > Lb)) y.u2[l] = take(cells(l) * (y.mixed ? 4 : 8));
   }
@@ -168,6 +171,9 @@ int validate(mg_ctx* c, const mg_params* p, const mg_bc* bc) {
     if ((bc->kind[2 * a] == MG_BC_PERIODIC) != (bc->kind[2 * a + 1] == MG_BC_PERIODIC))
       return fail(c, MG_ERR_INVALID_ARG, "periodic faces must be paired per axis");
   if (bc->lmax < 0 || bc->lmax > 4) return fail(c, MG_ERR_INVALID_ARG, "lmax in 0..4");
+  if (p->scheme != MG_SCHEME_CS && p->scheme != MG_SCHEME_FAS) return fail(c, MG_ERR_INVALID_ARG, "bad scheme");
+  if (p->scheme == MG_SCHEME_FAS && (p->precision != MG_PREC_FP64 || p->layout != MG_LAYOUT_DENSE))
+    return fail(c, MG_ERR_UNSUPPORTED, "FAS runs in FP64 on the dense layout");
   return MG_OK;
 }
 
@@ -453,6 +459,61 @@ struct Solver {
     return false;
   }
 
+  // ---- Full Approximation Scheme (Alg. 3), FP64 dense: every level keeps its physical
+  // boundary description; pbar[l] holds the restricted potential of level l < L.
+
+  // `count` smoothing sweeps of level l starting from `cur` (H.u[l] or, on levels swept by the
+  // streaming passes, either ping-pong array); returns the array holding the result.
+  double* fas_sweeps(Hier<double>& H, int l, double* cur, int count, const LevelBC& bc) {
+    const int n = 1 << l;
+    if (use_fused && H.u2[l] && n >= fused_min_n64) {
+      double* oth = cur == H.u[l] ? H.u2[l] : H.u[l];
+      for (int it = 0; it < count; ++it) {
+        fused_sweep<double>(cur, oth, H.f[l], n, H.h[l], H.omega, bc, s);
+        std::swap(cur, oth);
+      }
+      return cur;
+    }
+    for (int it = 0; it < count; ++it)
+      for (int colour = 0; colour < 2; ++colour) launch_half_sweep<double>(cur, H.f[l], n, H.h[l], H.omega, colour, bc, s);
+    return cur;
+  }
+
+  static bool fixes_zero(const LevelBC& bc) {
+    for (int f = 0; f < 6; ++f)
+      if (bc.kind[f] != BC_PERIODIC && bc.kind[f] != BC_ZERO_GRADIENT) return true;
+    return false;
+  }
+
+  void fas_cycle(Hier<double>& H, double* const* pbar, int l) {
+    if (l == 0) {
+      // the single cell with its physical conditions, from the iterate phibar; when no face
+      // fixes the zero point any value solves it and phibar is kept (zero correction)
+      if (fixes_zero(H.phys[0])) launch_coarsest<double>(H.u[0], H.f[0], H.h[0], H.phys[0], s);
+      return;
+    }
+    const int n = 1 << l;
+    const LevelBC& bc = H.phys[l];
+    double* cur = fas_sweeps(H, l, H.u[l], H.npre, bc);                                      // 1
+    launch_fas_restrict(cur, H.f[l], H.f[l - 1], pbar[l - 1], H.u[l - 1], n, H.h[l], bc, s);  // 2-4, 6
+    launch_fas_source(pbar[l - 1], H.f[l - 1], n / 2, H.h[l - 1], H.phys[l - 1], s);         // 5
+    fas_cycle(H, pbar, l - 1);                                                               // 6
+    launch_fas_correction(H.u[l - 1], pbar[l - 1], cells(l - 1), s);                         // 7
+    // the correction obeys the homogeneous conditions (physical values cancel in psi - phibar)
+    launch_prolong<double>(H.u[l - 1], cur, n / 2, H.hom, 0, s);                             // 8, 9
+    cur = fas_sweeps(H, l, cur, H.npost, bc);                                                // 10
+    if (cur != H.u[l]) (void)hipMemcpyAsync(H.u[l], cur, cells(l) * sizeof(double), hipMemcpyDeviceToDevice, s);
+  }
+
+  // Alg. 2 with FAS in place of the V-cycle.
+  void fas_fmg(Hier<double>& H, double* const* pbar) {
+    launch_coarsest<double>(H.u[0], H.f[0], H.h[0], H.phys[0], s);
+    for (int l = 1; l <= H.L; ++l) {
+      launch_prolong<double>(H.u[l - 1], H.u[l], 1 << (l - 1), H.phys[l - 1], 1, s);
+      fas_cycle(H, pbar, l);
+    }
+  }
+
   // Alg. 2: FMG over all levels with each level's physical description.
   template <typename T>
   void fmg(Hier<T>& H) {
@@ -607,6 +668,7 @@ void mg_default_params(mg_params* p) {
   p->precision = MG_PREC_FP64;
   p->layout = MG_LAYOUT_DENSE;
   p->block_n = 16;
+  p->scheme = MG_SCHEME_CS;
 }
 
 int mg_ctx_create(mg_ctx** out, int device) {
@@ -658,7 +720,8 @@ const char* mg_last_error(const mg_ctx* c) { return c ? c->err.c_str() : "null c
 
 size_t mg_footprint_bytes(const mg_params* p) {
   if (!p || !is_pow2(p->n) || p->n < 2 || p->n > 2048) return 0;
-  return make_layout(p->n, p->precision, layout_lb(p)).total + sizeof(double) * (kMaxPartials * 32 + kScal);
+  return make_layout(p->n, p->precision, layout_lb(p), p->scheme == MG_SCHEME_FAS).total +
+         sizeof(double) * (kMaxPartials * 32 + kScal);
 }
 
 int mg_ctx_reserve(mg_ctx* c, const mg_params* p) {
@@ -666,7 +729,7 @@ int mg_ctx_reserve(mg_ctx* c, const mg_params* p) {
   if (!is_pow2(p->n) || p->n < 2 || p->n > 2048) return fail(c, MG_ERR_INVALID_ARG, "n must be a power of two in [2, 2048]");
   if (p->precision != MG_PREC_FP64 && p->precision != MG_PREC_MIXED) return fail(c, MG_ERR_INVALID_ARG, "bad precision");
   HIP_CHECK(c, hipSetDevice(c->device));
-  return ensure_ws(c, make_layout(p->n, p->precision, layout_lb(p)).total);
+  return ensure_ws(c, make_layout(p->n, p->precision, layout_lb(p), p->scheme == MG_SCHEME_FAS).total);
 }
 
 int mg_set_kernel_timing(mg_ctx* c, int on) {
@@ -712,7 +775,10 @@ int setup_faces(mg_ctx* c, const Layout& y, const mg_params* p, const mg_bc* bc,
   bool any_mp = false;
   for (int f = 0; f < 6; ++f) any_mp |= bc->kind[f] == MG_BC_MULTIPOLE;
   double* mps = c->scal + kMpoleOff;
-  if (any_mp) launch_multipole_moments(rho, p->n, p->dx, bc->lmax, bc->use_origin, bc->origin, c->part, mps, s);
+  const int Lb = layout_lb(p);
+  if (any_mp)
+    launch_multipole_moments(rho, p->n, Lb >= 0 ? L - Lb : 0, p->dx, bc->lmax, bc->use_origin, bc->origin, c->part,
+                             mps, s);
   const double G = p->four_pi_g / (4.0 * M_PI);
   for (int l = L; l >= 0; --l) {
     double* fb = reinterpret_cast<double*>(c->ws + y.faces[l]);
@@ -756,14 +822,11 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
   int st = validate(c, p, bc);
   if (st != MG_OK) return st;
   if (!rho || !phi || !hist || !n_hist) return fail(c, MG_ERR_INVALID_ARG, "null rho/phi/hist/n_hist");
-  if (p->layout == MG_LAYOUT_BLOCKS)
-    for (int f = 0; f < 6; ++f)
-      if (bc->kind[f] == MG_BC_MULTIPOLE)
-        return fail(c, MG_ERR_UNSUPPORTED, "multipole faces need the dense layout");
   HIP_CHECK(c, hipSetDevice(c->device));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int Lb = layout_lb(p);
-  const Layout y = make_layout(p->n, p->precision, Lb);
+  const bool fas = p->scheme == MG_SCHEME_FAS;
+  const Layout y = make_layout(p->n, p->precision, Lb, fas);
   st = ensure_ws(c, y.total);
   if (st != MG_OK) return st;
   for (auto e : c->kev) (void)hipEventDestroy(e);
@@ -841,8 +904,13 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
   HIP_CHECK(c, hipEventRecord(c->ev_setup, s));
 
   // ---- FMG sweep (Alg. 2) or the caller's initial guess
+  double* pbar[16] = {nullptr};
+  if (fas)
+    for (int l = 0; l < L; ++l) pbar[l] = reinterpret_cast<double*>(c->ws + y.pbar[l]);
   if (p->mode == MG_MODE_FMG) {
-    if (!mixed) {
+    if (fas) {
+      S.fas_fmg(H64, pbar);
+    } else if (!mixed) {
       S.fmg(H64);
     } else {
       S.fmg(H32);
@@ -851,7 +919,7 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
   }
   // ---- residual of the start (Sec. 2.3.7); mixed: also its FP32 copy as the inner RHS.  FP64
   // on the fused path: taken by the head pass, which is also the first sweep of V-cycle 1
-  const bool head_mode = !mixed && Lb < 0 && S.head_possible(H64);
+  const bool head_mode = !mixed && !fas && Lb < 0 && S.head_possible(H64);
   if (head_mode) S.head(H64, phys[L]);
   else S.defect_norm(phi, f64L, mixed ? H32.f[L] : nullptr, p->n, p->dx, phys[L], c->scal + 2);
   HIP_CHECK(c, hipEventRecord(c->ev_fmg, s));
@@ -883,7 +951,10 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
   if (p->fixed_cycles > 0 || r > p->tol) {
     for (int cyc = 0; cyc < ncyc; ++cyc) {
       S.timed_top = true;
-      if (head_mode) {
+      if (fas) {
+        S.fas_cycle(H64, pbar, L);
+        S.defect_norm(phi, f64L, nullptr, p->n, p->dx, phys[L], c->scal + 2);
+      } else if (head_mode) {
         // the rest of this V-cycle (its first sweep ran in the head pass), then the head of the
         // next one, which measures this cycle's result; after the last allowed cycle the
         // residual alone (a head's sweep would be discarded)
@@ -1384,7 +1455,7 @@ int mg_multipole_moments(mg_ctx* c, int n, double dx, const double* rho, int lma
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   double* mps = c->scal + kMpoleOff;
   HIP_CHECK(c, hipMemsetAsync(c->scal, 0, sizeof(double) * kScal, s));
-  launch_multipole_moments(rho, n, dx, lmax, use_origin, origin, c->part, mps, s);
+  launch_multipole_moments(rho, n, 0, dx, lmax, use_origin, origin, c->part, mps, s);
   HIP_CHECK(c, hipMemcpyAsync(c->hscal, c->scal, sizeof(double) * kScal, hipMemcpyDeviceToHost, s));
   HIP_CHECK(c, hipStreamSynchronize(s));
   if (origin_out)
@@ -1392,6 +1463,68 @@ int mg_multipole_moments(mg_ctx* c, int n, double dx, const double* rho, int lma
   if (q_out)
     for (int q = 0; q < 25; ++q) q_out[q] = c->hscal[kMpoleOff + 7 + q];
   return op_epilogue(c);
+}
+
+int mg_gravity(mg_ctx* c, const mg_params* p, const mg_bc* bc, const double* phi, const double* rho, double* g,
+               double* rhog, double* gface, void* stream) {
+  if (!c) return MG_ERR_INVALID_ARG;
+  int st = validate(c, p, bc);
+  if (st != MG_OK) return st;
+  if (!phi) return fail(c, MG_ERR_INVALID_ARG, "null phi");
+  if (!g && !rhog && !gface) return fail(c, MG_ERR_INVALID_ARG, "no output requested");
+  bool any_mp = false, any_fixed = false;
+  for (int f = 0; f < 6; ++f) {
+    any_mp |= bc->kind[f] == MG_BC_MULTIPOLE;
+    any_fixed |= bc->kind[f] == MG_BC_FIXED && bc->fixed_b[f];
+  }
+  if ((rhog || any_mp) && !rho) return fail(c, MG_ERR_INVALID_ARG, "rho is required for rhog and multipole faces");
+  const int Lb = layout_lb(p);
+  if (gface && Lb >= 0) return fail(c, MG_ERR_UNSUPPORTED, "face accelerations are written for the dense layout only");
+  HIP_CHECK(c, hipSetDevice(c->device));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int n = p->n, L = ilog2(n);
+  const int Lm = Lb >= 0 ? L - Lb : 0;
+  // boundary description of the finest level, as the solve builds it (Sec. 2.3.6, App. A)
+  LevelBC lb;
+  double* fb = nullptr;
+  if (any_mp || any_fixed) {
+    st = op_scratch(c, 6 * face_sz(L) * sizeof(double), &fb);
+    if (st) return st;
+  }
+  double* mp_out[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  for (int f = 0; f < 6; ++f) {
+    const int k = bc->kind[f];
+    lb.kind[f] = k == MG_BC_MULTIPOLE ? MG_BC_FIXED : k;
+    lb.b[f] = nullptr;
+    double* e = fb ? fb + (size_t)f * face_sz(L) : nullptr;
+    if (k == MG_BC_FIXED && bc->fixed_b[f]) {
+      launch_face_extend(bc->fixed_b[f], e, n, s);
+      lb.b[f] = e;
+    } else if (k == MG_BC_MULTIPOLE) {
+      mp_out[f] = e;
+      lb.b[f] = e;
+    }
+  }
+  if (any_mp) {
+    double* mps = c->scal + kMpoleOff;
+    launch_multipole_moments(rho, n, Lm, p->dx, bc->lmax, bc->use_origin, bc->origin, c->part, mps, s);
+    launch_multipole_faces(mps, bc->lmax, p->four_pi_g / (4.0 * M_PI), n, p->dx, n * p->dx, mp_out, s);
+  }
+  launch_gravity(phi, rho, g, rhog, gface, n, Lm, p->dx, lb, s);
+  return op_epilogue(c);
+}
+
+int mg_gravity_kernel_name(const mg_params* p, int want_g, int want_rhog, int want_gface, char* buf, int cap) {
+  if (!p || !is_pow2(p->n) || p->n < 2) return MG_ERR_INVALID_ARG;
+  const int Lb = layout_lb(p);
+  const std::string nm =
+      gravity_kernel_name(p->n, Lb >= 0 ? ilog2(p->n) - Lb : 0, want_g != 0, want_rhog != 0, want_gface != 0);
+  const int len = (int)nm.size() + 1;
+  if (buf && cap > 0) {
+    std::strncpy(buf, nm.c_str(), (size_t)cap);
+    buf[cap - 1] = 0;
+  }
+  return len;
 }
 
 }  // extern "C"

@@ -106,6 +106,79 @@ void launch_defect_restrict(const T* u, const T* f, T* fc, T* uc0, int n, double
                      f, fc, uc0, n, L, (T)(1.0 / (h * h)), bc);
 }
 
+// ------------------------------------------------------------------ FAS transfers (Alg. 3)
+
+// Alg. 3 steps 2-4 and the coarse initial guess of step 6: per coarse cell the restricted
+// defect of its 8 children (into fc), the restricted potential phibar (into pbar) and the
+// coarse iterate set to phibar (into uc).
+__global__ void __launch_bounds__(kBlock) k_fas_restrict(const double* __restrict__ u, const double* __restrict__ f,
+                                                          double* __restrict__ fc, double* __restrict__ pbar,
+                                                          double* __restrict__ uc, int n, int L, double ih2,
+                                                          LevelBC bc) {
+  const int nc = n >> 1, Lc = L - 1;
+  const size_t C = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (C >= ((size_t)1 << (3 * Lc))) return;
+  const int I = (int)(C & (size_t)(nc - 1));
+  const int J = (int)((C >> Lc) & (size_t)(nc - 1));
+  const int K = (int)(C >> (2 * Lc));
+  double sd = 0.0, su = 0.0;
+#pragma unroll
+  for (int c3 = 0; c3 < 2; ++c3)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int i = 2 * I + a, j = 2 * J + b, k = 2 * K + c3;
+        const size_t c = cidx(L, i, j, k);
+        const double ucv = u[c];
+        const double nb = neighbour_sum(u, n, L, i, j, k, c, ucv, bc);
+        sd += f[c] - (nb - 6.0 * ucv) * ih2;
+        su += ucv;
+      }
+  fc[C] = sd * 0.125;
+  const double pb = su * 0.125;
+  pbar[C] = pb;
+  uc[C] = pb;
+}
+
+void launch_fas_restrict(const double* u, const double* f, double* fc, double* pbar, double* uc, int n, double h,
+                         const LevelBC& bc, hipStream_t s) {
+  const int L = ilog2(n);
+  hipLaunchKernelGGL(k_fas_restrict, dim3(grid_for((size_t)1 << (3 * (L - 1)))), dim3(kBlock), 0, s, u, f, fc, pbar,
+                     uc, n, L, 1.0 / (h * h), bc);
+}
+
+// Alg. 3 step 5 on the coarse level: f += L phibar, with phibar's ghosts from the level's
+// physical description.
+__global__ void __launch_bounds__(kBlock) k_fas_source(const double* __restrict__ pbar, double* __restrict__ f, int n,
+                                                        int L, double ih2, LevelBC bc) {
+  const size_t c = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= ((size_t)1 << (3 * L))) return;
+  const int i = (int)(c & (size_t)(n - 1));
+  const int j = (int)((c >> L) & (size_t)(n - 1));
+  const int k = (int)(c >> (2 * L));
+  const double pc = pbar[c];
+  const double nb = neighbour_sum(pbar, n, L, i, j, k, c, pc, bc);
+  f[c] = f[c] + (nb - 6.0 * pc) * ih2;
+}
+
+void launch_fas_source(const double* pbar, double* f, int n, double h, const LevelBC& bc, hipStream_t s) {
+  const int L = ilog2(n);
+  hipLaunchKernelGGL(k_fas_source, dim3(grid_for((size_t)1 << (3 * L))), dim3(kBlock), 0, s, pbar, f, n, L,
+                     1.0 / (h * h), bc);
+}
+
+// Alg. 3 step 7: the coarse-grid correction psi - phibar, in place of psi.
+__global__ void __launch_bounds__(kBlock) k_fas_correction(double* __restrict__ u, const double* __restrict__ pbar,
+                                                            size_t n3) {
+  const size_t c = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (c < n3) u[c] = u[c] - pbar[c];
+}
+
+void launch_fas_correction(double* u, const double* pbar, size_t n3, hipStream_t s) {
+  hipLaunchKernelGGL(k_fas_correction, dim3(grid_for(n3)), dim3(kBlock), 0, s, u, pbar, n3);
+}
+
 // ------------------------------------------------------------------ restriction (eq. restriction)
 
 template <typename Tin, typename Tout>

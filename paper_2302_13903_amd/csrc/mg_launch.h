@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <string>
 
 #include "mg_common.h"
 
@@ -54,6 +55,13 @@ size_t tail_lds_bytes(int top, size_t elem);
 // Allows the FP64 tail its dynamic LDS; returns the highest level it can hold (3 or 4).
 int tail_prepare(size_t lds_per_block);
 
+// FAS (Alg. 3): fc = restricted defect, pbar = uc = restricted u; f += L pbar on the coarse
+// level; u -= pbar (the coarse-grid correction)
+void launch_fas_restrict(const double* u, const double* f, double* fc, double* pbar, double* uc, int n, double h,
+                         const LevelBC& bc, hipStream_t s);
+void launch_fas_source(const double* pbar, double* f, int n, double h, const LevelBC& bc, hipStream_t s);
+void launch_fas_correction(double* u, const double* pbar, size_t n3, hipStream_t s);
+
 // f = a rho + c (and its FP32 copy when f32 != nullptr); sumsq[0] = sum of f^2 (device)
 void launch_source(const double* rho, double* f, float* f32, size_t n3, double a, double c, double* part,
                    double* sumsq, hipStream_t s);
@@ -74,9 +82,16 @@ void launch_face_restrict(const double* ef, double* ec, int nc, hipStream_t s);
 
 // multipole (mg_multipole.hip)
 // moments[0..3] = (M, Mx, My, Mz) sums; origin[3]; q[25]
-void launch_multipole_moments(const double* rho, int n, double dx, int lmax, int use_origin, const double* origin_host,
-                              double* part, double* scratch, hipStream_t s);
+// rho of n^3 cells, dense (Lm = 0) or in the MeshBlock layout with 2^Lm-cell blocks
+void launch_multipole_moments(const double* rho, int n, int Lm, double dx, int lmax, int use_origin,
+                              const double* origin_host, double* part, double* scratch, hipStream_t s);
 void launch_multipole_faces(const double* scratch, int lmax, double G, int nl, double hl, double length,
                             double* faces[6], hipStream_t s);
+
+// gravitational acceleration (mg_gravity.hip): g, rhog (3 n^3 each) and gface (3 n^2 (n+1),
+// dense layout only) from phi, any of them null; returns the number of workgroups launched
+int launch_gravity(const double* phi, const double* rho, double* g, double* rhog, double* gface, int n, int Lm,
+                   double dx, const LevelBC& bc, hipStream_t s);
+std::string gravity_kernel_name(int n, int Lm, bool g, bool rhog, bool gface);
 
 }  // namespace mg

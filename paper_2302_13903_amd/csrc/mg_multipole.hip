@@ -68,8 +68,26 @@ __device__ __forceinline__ void block_sums(double* v, double* red, double* part)
   }
 }
 
+// Cell (i, j, k) stored at index c of a level of 2^L cells per side: dense (Lm = 0), or the
+// MeshBlock layout with 2^Lm-cell blocks in Morton order.
+__device__ __forceinline__ void cell_of(size_t c, int L, int Lm, int& i, int& j, int& k) {
+  if (Lm == 0) {
+    const int n = 1 << L;
+    i = (int)(c & (size_t)(n - 1));
+    j = (int)((c >> L) & (size_t)(n - 1));
+    k = (int)(c >> (2 * L));
+    return;
+  }
+  int bx, by, bz;
+  demorton3((unsigned)(c >> (3 * Lm)), bx, by, bz);
+  const int r = (int)(c & (size_t)((1 << (3 * Lm)) - 1)), mm = (1 << Lm) - 1;
+  i = (bx << Lm) + (r & mm);
+  j = (by << Lm) + ((r >> Lm) & mm);
+  k = (bz << Lm) + (r >> (2 * Lm));
+}
+
 // Mass and first moments: (sum rho dV, sum rho x dV, sum rho y dV, sum rho z dV).
-__global__ void __launch_bounds__(kMBlock) k_mass_partials(const double* __restrict__ rho, int L, double dx,
+__global__ void __launch_bounds__(kMBlock) k_mass_partials(const double* __restrict__ rho, int L, int Lm, double dx,
                                                             double* __restrict__ part) {
   __shared__ double red[4 * kMBlock / 64];
   const int n = 1 << L;
@@ -77,7 +95,8 @@ __global__ void __launch_bounds__(kMBlock) k_mass_partials(const double* __restr
   const double dv = dx * dx * dx;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   for (size_t c = (size_t)blockIdx.x * kMBlock + threadIdx.x; c < n3; c += (size_t)gridDim.x * kMBlock) {
-    const int i = (int)(c & (size_t)(n - 1)), j = (int)((c >> L) & (size_t)(n - 1)), k = (int)(c >> (2 * L));
+    int i, j, k;
+    cell_of(c, L, Lm, i, j, k);
     const double m = rho[c] * dv;
     v[0] += m;
     v[1] += m * ((i + 0.5) * dx);
@@ -101,8 +120,8 @@ __global__ void k_set_origin(double* scratch, int use_origin, double ox, double 
   }
 }
 
-__global__ void __launch_bounds__(kMBlock) k_moment_partials(const double* __restrict__ rho, int L, double dx,
-                                                              int lmax, const double* __restrict__ scratch,
+__global__ void __launch_bounds__(kMBlock) k_moment_partials(const double* __restrict__ rho, int L, int Lm,
+                                                              double dx, int lmax, const double* __restrict__ scratch,
                                                               double* __restrict__ part) {
   __shared__ double red[25 * kMBlock / 64];
   const int n = 1 << L;
@@ -114,7 +133,8 @@ __global__ void __launch_bounds__(kMBlock) k_moment_partials(const double* __res
 #pragma unroll
   for (int q = 0; q < 25; ++q) acc[q] = 0.0;
   for (size_t c = (size_t)blockIdx.x * kMBlock + threadIdx.x; c < n3; c += (size_t)gridDim.x * kMBlock) {
-    const int i = (int)(c & (size_t)(n - 1)), j = (int)((c >> L) & (size_t)(n - 1)), k = (int)(c >> (2 * L));
+    int i, j, k;
+    cell_of(c, L, Lm, i, j, k);
     const double m = rho[c] * dv;
     double S[25];
     schmidt_solid((i + 0.5) * dx - ox, (j + 0.5) * dx - oy, (k + 0.5) * dx - oz, S);
@@ -144,19 +164,19 @@ __global__ void __launch_bounds__(kMBlock) k_sum_columns(const double* __restric
   }
 }
 
-void launch_multipole_moments(const double* rho, int n, double dx, int lmax, int use_origin, const double* origin_host,
-                              double* part, double* scratch, hipStream_t s) {
+void launch_multipole_moments(const double* rho, int n, int Lm, double dx, int lmax, int use_origin,
+                              const double* origin_host, double* part, double* scratch, hipStream_t s) {
   const int L = ilog2(n);
   const size_t n3 = (size_t)1 << (3 * L);
   int nb = reduce_blocks(n3);
   if (!use_origin) {
-    hipLaunchKernelGGL(k_mass_partials, dim3(nb), dim3(kMBlock), 0, s, rho, L, dx, part);
+    hipLaunchKernelGGL(k_mass_partials, dim3(nb), dim3(kMBlock), 0, s, rho, L, Lm, dx, part);
     hipLaunchKernelGGL(k_sum_columns, dim3(1), dim3(kMBlock), 0, s, part, nb, 4, scratch);
   }
   const double ox = use_origin ? origin_host[0] : 0.0, oy = use_origin ? origin_host[1] : 0.0,
                oz = use_origin ? origin_host[2] : 0.0;
   hipLaunchKernelGGL(k_set_origin, dim3(1), dim3(64), 0, s, scratch, use_origin, ox, oy, oz, 0.5 * n * dx);
-  hipLaunchKernelGGL(k_moment_partials, dim3(nb), dim3(kMBlock), 0, s, rho, L, dx, lmax, scratch, part);
+  hipLaunchKernelGGL(k_moment_partials, dim3(nb), dim3(kMBlock), 0, s, rho, L, Lm, dx, lmax, scratch, part);
   hipLaunchKernelGGL(k_sum_columns, dim3(1), dim3(kMBlock), 0, s, part, nb, 25, scratch + 7);
 }
 

@@ -54,3 +54,16 @@ def test_missing_library_fails_loudly(monkeypatch):
     monkeypatch.setattr(_abi, "LIB_PATH", "/nonexistent/libmg355.so")
     with pytest.raises(_abi.MgError):
         _abi.lib()
+
+
+def test_gravity_kernel_names():
+    """The name mg_gravity reports for the kernel it launches (what bench.py looks up in the
+    profiler summaries): the per-cell kernel below 128^3, the streaming pass from 128^3, with
+    the output set as its last template argument."""
+    import paper_2302_13903_amd as mg
+    assert mg.mg_gravity_kernel_name(mg.params(64, 1 / 64)).endswith("k_grav_cell<false>(mg::(anonymous namespace)::GravArgs)")
+    name = mg.mg_gravity_kernel_name(mg.params(512, 1 / 512), True, True, False)
+    assert name == "void mg::(anonymous namespace)::k_grav_stream<4, 4, false, 3>(mg::(anonymous namespace)::GravArgs)"
+    name = mg.mg_gravity_kernel_name(mg.params(256, 1 / 256, layout="blocks", block_n=16), True, False, True)
+    assert "k_grav_stream<4, 4, true, 1>" in name      # no face output in the MeshBlock layout
+    assert mg.mg_gravity_kernel_name(mg.params(12, 1 / 12)) == ""

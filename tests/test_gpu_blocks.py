@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import workloads as wl
-from oracle import FIXED, PERIODIC, ZERO_GRADIENT
+from oracle import FIXED, MULTIPOLE, PERIODIC, ZERO_GRADIENT
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -152,10 +152,22 @@ def test_bad_schedule_rejected(mg):
         ctx.set_tuning("blk fp64 4 4 300 1 1\n")
 
 
-def test_blocks_multipole_unsupported(mg):
-    rho = wl.gaussian_clumps(32, 1, remove_mean=False)
-    with pytest.raises(mg.MgError):
-        solve_blocks(mg, rho, "multipole", 8)
+@pytest.mark.parametrize("n,block_n,tuning", [(32, 8, ""), (64, 16, ""), (128, 16, "fusedmin fp64 64\n")])
+def test_blocks_multipole_matches_oracle(mg, n, block_n, tuning):
+    """Multipole faces in the MeshBlock layout: the moments are summed over the blocks (cell
+    positions from the block coordinates), the rest is the same V-cycle."""
+    print(f"blocks multipole n={n} block_n={block_n}", flush=True)
+    rho, _ = wl.uniform_sphere(n, 5)
+    ref, rh, _ = oracle.solve(rho, 1.0 / n, [MULTIPOLE] * 6, fixed_cycles=5, lmax=4)
+    ctx = mg.Context(0)
+    if tuning:
+        ctx.set_tuning(tuning)
+    got, gh, st, _ = solve_blocks(mg, rho, "multipole", block_n, ctx=ctx, fixed_cycles=5, lmax=4)
+    assert st == mg.MG_OK
+    assert rel(got, ref) < 1e-10
+    fl = floor_of(ref, rho, False)
+    for a, b in zip(gh, rh):
+        assert abs(a - b) <= 1e-6 * b + 10 * fl, (gh, rh)
 
 
 def test_c4_lognormal_256_blocks_vs_dense(mg):

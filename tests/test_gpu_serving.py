@@ -100,3 +100,27 @@ def test_mgi_without_phi_is_an_error():
     srv = serving.Server(workers=1)
     (r,) = srv.run([serving.Request(rho=rho, mode="mgi")])
     assert r.status == MG_ERR_INVALID_ARG
+
+
+def test_admission_under_a_small_budget():
+    """A budget of about two 128^3 hierarchies: 256^3 requests are rejected, 64^3 and 128^3
+    ones are served with hierarchies created, reused and evicted on the device while other
+    workers solve; every served result equals the direct solve."""
+    print("serving small budget", flush=True)
+    fp128 = mg.mg_footprint_bytes(mg.params(128, 1 / 128)) + 128 ** 3 * 8 + 256
+    srv = serving.Server(workers=3, hbm_budget=int(2.5 * fp128))
+    rhos = {64: clumps(64, 31, True), 128: clumps(128, 32, True), 256: clumps(256, 33, True)}
+    want = {n: mg.solve(rhos[n], 1.0 / n, "periodic")[0] for n in (64, 128)}
+    sizes = [128, 64, 256, 128, 64, 128, 64, 128]
+    phis = [torch.zeros_like(rhos[n]) for n in sizes]
+    reqs = [serving.Request(rho=rhos[n], phi=phis[i], arrival_ms=0.5 * i) for i, n in enumerate(sizes)]
+    srv.run(reqs)
+    st = srv.stats()
+    assert reqs[2].status == mg._abi.MG_ERR_OOM
+    for i, r in enumerate(reqs):
+        if sizes[i] == 256:
+            continue
+        assert r.status == 0, (i, r.status)
+        assert torch.equal(phis[i], want[sizes[i]]), i
+    assert st["rejected"] == 1 and st["peak_bytes"] <= int(2.5 * fp128)
+    assert st["created"] >= 2
