@@ -13,6 +13,8 @@ in HBM.  The JSON line reports:
                 its mean launch time (HIP events on the solve stream) against 8 TB/s;
   cpu_baseline  the CPU oracle timed on a bounded sample of the same workload;
   mixed         the same numbers for the mixed-precision solve; p50/p99 solve latency.
+  fas           the same solve with Full Approximation Scheme iterations (Alg. 3): per-cycle
+                rate, its finest-level passes and the roofline of the dominant one;
   gravity       g = -grad phi and rho g of the solved potential (Sec. 2.4): mean launch time
                 and its HBM roofline (64 algorithmic bytes per cell), CPU oracle beside it;
   batched       the 256^3 lognormal field as 4096 MeshBlocks of 16^3 (autotuned), FP64 and
@@ -59,6 +61,12 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def short_name(kernel: str) -> str:
+    """Kernel name as the profile summaries key it: no return type, namespaces or arguments."""
+    k = kernel.replace("(anonymous namespace)::", "").replace("mg::", "").replace("void ", "")
+    return k.split("(")[0]
+
+
 def measured_traffic(kernel: str, n: int):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None
     when there is none or the kernel sources changed since the counters were taken."""
@@ -69,18 +77,19 @@ def measured_traffic(kernel: str, n: int):
         return None
     if t.get("source_hash") != kernel_source_hash():
         return None
-    entry = t.get("kernels", {}).get(f"{kernel}@{n}")
+    entry = t.get("kernels", {}).get(f"{short_name(kernel)}@{n}")
     return None if entry is None else entry.get("bytes_per_launch")
 
 
-def run_solves(mg, ctx, rho, n, precision, steps, warmup, tol):
+def run_solves(mg, ctx, rho, n, precision, steps, warmup, tol, scheme="cs"):
     import torch
     phi = torch.zeros_like(rho)
     lat, cyc, hists, kt = [], [], [], []
     for it in range(warmup + steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        phi, hist, st = mg.solve(rho, 1.0 / n, "periodic", tol=tol, precision=precision, phi=phi, ctx=ctx)
+        phi, hist, st = mg.solve(rho, 1.0 / n, "periodic", tol=tol, precision=precision, phi=phi, ctx=ctx,
+                                 scheme=scheme)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         if st < 0 or hist[-1] > tol:
@@ -91,9 +100,26 @@ def run_solves(mg, ctx, rho, n, precision, steps, warmup, tol):
             cyc.extend(cms)
             hists.append(hist)
             kt.append(ctx.kernel_timing())
-        print(f"# {precision} step {it - warmup:+d}: {1e3 * (t1 - t0):.2f} ms, cycles {len(hist) - 1}, "
+        print(f"# {precision} {scheme} step {it - warmup:+d}: {1e3 * (t1 - t0):.2f} ms, cycles {len(hist) - 1}, "
               f"r = {hist[-1]:.2e}", file=sys.stderr, flush=True)
     return lat, cyc, hists, kt
+
+
+def pass_table(kt):
+    """Per kernel (finest-level passes), summed over the timed steps."""
+    agg = {}
+    for recs in kt:
+        for r in recs:
+            a = agg.setdefault(r["name"], {"launches": 0, "total_ms": 0.0, "bytes_per_launch": r["bytes_per_launch"]})
+            a["launches"] += r["launches"]
+            a["total_ms"] += r["total_ms"]
+    passes = []
+    for name, a in agg.items():
+        avg = a["total_ms"] / max(a["launches"], 1)
+        passes.append({"kernel": name, "launches": a["launches"], "avg_launch_ms": avg,
+                       "algorithmic_bytes_per_launch": a["bytes_per_launch"],
+                       "achieved_GBs": a["bytes_per_launch"] / (avg * 1e-3) / 1e9 if avg > 0 else None})
+    return passes
 
 
 def cpu_baseline(n: int, cycles: int = 3):
@@ -270,6 +296,7 @@ def main() -> int:
     ap.add_argument("--serve-workers", type=int, default=4)
     ap.add_argument("--no-batched", action="store_true", help="skip the MeshBlock (4096 x 16^3) leg")
     ap.add_argument("--no-gravity", action="store_true", help="skip the g = -grad phi leg")
+    ap.add_argument("--no-fas", action="store_true", help="skip the Full Approximation Scheme leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device to device (reference for profiler byte counters)")
     args = ap.parse_args()
@@ -303,19 +330,7 @@ def main() -> int:
     lat, cyc, hists, kt = run_solves(mg, ctx, rho, n, "fp64", args.steps, args.warmup, args.tol)
     t_v = statistics.median(cyc)
     value = n ** 3 / (t_v * 1e-3) / 1e9
-    # per kernel (finest-level smoothing passes), summed over the timed steps
-    agg = {}
-    for recs in kt:
-        for r in recs:
-            a = agg.setdefault(r["name"], {"launches": 0, "total_ms": 0.0, "bytes_per_launch": r["bytes_per_launch"]})
-            a["launches"] += r["launches"]
-            a["total_ms"] += r["total_ms"]
-    passes = []
-    for name, a in agg.items():
-        avg = a["total_ms"] / max(a["launches"], 1)
-        passes.append({"kernel": name, "launches": a["launches"], "avg_launch_ms": avg,
-                       "algorithmic_bytes_per_launch": a["bytes_per_launch"],
-                       "achieved_GBs": a["bytes_per_launch"] / (avg * 1e-3) / 1e9 if avg > 0 else None})
+    passes = pass_table(kt)
     dom = max(passes, key=lambda q: q["avg_launch_ms"] * q["launches"])
     achieved = dom["achieved_GBs"]
     traffic = measured_traffic(dom["kernel"], n)
@@ -346,6 +361,21 @@ def main() -> int:
     ctx.set_kernel_timing(False)
     if not args.no_gravity:
         out["gravity"] = gravity_leg(mg, ctx, rho, n, 20, not args.no_cpu_baseline)
+    if not args.no_fas:
+        ctx.set_kernel_timing(True)
+        lat_f, cyc_f, hists_f, kt_f = run_solves(mg, ctx, rho, n, "fp64", max(2, args.steps // 2), 1, args.tol,
+                                                 scheme="fas")
+        ctx.set_kernel_timing(False)
+        tvf = statistics.median(cyc_f)
+        pf = pass_table(kt_f)
+        domf = max(pf, key=lambda q: q["avg_launch_ms"] * q["launches"])
+        out["fas"] = {"value": n ** 3 / (tvf * 1e-3) / 1e9, "unit": "GDoF/s per FAS cycle",
+                      "ms_per_step": statistics.mean(lat_f), "cycles_per_solve": len(hists_f[-1]) - 1,
+                      "cycle_ms_median": tvf,
+                      "roofline": {"bound": "hbm", "achieved": domf["achieved_GBs"], "peak": HBM_PEAK_GBS,
+                                   "unit": "GB/s", "frac": domf["achieved_GBs"] / HBM_PEAK_GBS,
+                                   "traffic": measured_traffic(domf["kernel"], n), "kernel": domf["kernel"],
+                                   "passes": pf}}
     if not args.no_mixed:
         lat_m, cyc_m, hists_m, _ = run_solves(mg, ctx, rho, n, "mixed", args.steps, args.warmup, args.tol)
         tvm = statistics.median(cyc_m)

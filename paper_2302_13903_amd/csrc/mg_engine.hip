@@ -466,16 +466,24 @@ struct Solver {
   // streaming passes, either ping-pong array); returns the array holding the result.
   double* fas_sweeps(Hier<double>& H, int l, double* cur, int count, const LevelBC& bc) {
     const int n = 1 << l;
+    const bool timed = timed_top && l == H.L && c->ktiming;
+    const double cellsT = (double)cells(l) * sizeof(double);
     if (use_fused && H.u2[l] && n >= fused_min_n64) {
       double* oth = cur == H.u[l] ? H.u2[l] : H.u[l];
       for (int it = 0; it < count; ++it) {
+        if (timed) kernel_begin();
         fused_sweep<double>(cur, oth, H.f[l], n, H.h[l], H.omega, bc, s);
+        if (timed) kernel_end(fused_pass_name<double>(false, 0), 3 * cellsT);
         std::swap(cur, oth);
       }
       return cur;
     }
     for (int it = 0; it < count; ++it)
-      for (int colour = 0; colour < 2; ++colour) launch_half_sweep<double>(cur, H.f[l], n, H.h[l], H.omega, colour, bc, s);
+      for (int colour = 0; colour < 2; ++colour) {
+        if (timed) kernel_begin();
+        launch_half_sweep<double>(cur, H.f[l], n, H.h[l], H.omega, colour, bc, s);
+        if (timed) kernel_end("k_half_sweep", 2 * cellsT);
+      }
     return cur;
   }
 
@@ -494,14 +502,36 @@ struct Solver {
     }
     const int n = 1 << l;
     const LevelBC& bc = H.phys[l];
+    const bool timed = timed_top && l == H.L && c->ktiming;
+    const double cellsT = (double)cells(l) * sizeof(double);
+    const bool streamed = use_fused && H.u2[l] && n >= fused_min_n64;
     double* cur = fas_sweeps(H, l, H.u[l], H.npre, bc);                                      // 1
-    launch_fas_restrict(cur, H.f[l], H.f[l - 1], pbar[l - 1], H.u[l - 1], n, H.h[l], bc, s);  // 2-4, 6
+    // 2-4 and the coarse start of 6: restricted defect, phibar, u_{l-1} = phibar; algorithmic
+    // bytes: u and f read, three coarse arrays written
+    if (timed) kernel_begin();
+    if (streamed) fused_fas_restrict(cur, H.f[l], H.f[l - 1], pbar[l - 1], H.u[l - 1], n, H.h[l], bc, s);
+    else launch_fas_restrict(cur, H.f[l], H.f[l - 1], pbar[l - 1], H.u[l - 1], n, H.h[l], bc, s);
+    if (timed) kernel_end(streamed ? fused_fas_restrict_name() : "k_fas_restrict", 2 * cellsT + 3 * cellsT / 8);
     launch_fas_source(pbar[l - 1], H.f[l - 1], n / 2, H.h[l - 1], H.phys[l - 1], s);         // 5
     fas_cycle(H, pbar, l - 1);                                                               // 6
     launch_fas_correction(H.u[l - 1], pbar[l - 1], cells(l - 1), s);                         // 7
-    // the correction obeys the homogeneous conditions (physical values cancel in psi - phibar)
-    launch_prolong<double>(H.u[l - 1], cur, n / 2, H.hom, 0, s);                             // 8, 9
-    cur = fas_sweeps(H, l, cur, H.npost, bc);                                                // 10
+    // 8-10: the correction obeys the homogeneous conditions (the physical values cancel in
+    // psi - phibar); on streamed levels it enters with the first post-sweep, as in Alg. 1
+    int post = H.npost;
+    if (streamed && post > 0) {
+      double* oth = cur == H.u[l] ? H.u2[l] : H.u[l];
+      if (timed) kernel_begin();
+      fused_prolong_sweep<double>(cur, oth, H.f[l], H.u[l - 1], H.hom, n, H.h[l], H.omega, bc, s);
+      if (timed) kernel_end(fused_pass_name<double>(true, 0), 3 * cellsT + cellsT / 8);
+      cur = oth;
+      --post;
+    } else {
+      if (timed) kernel_begin();
+      launch_prolong<double>(H.u[l - 1], cur, n / 2, H.hom, 0, s);
+      // algorithmic bytes: u read and written, the coarse correction read
+      if (timed) kernel_end("k_prolong<double, 0>", 2 * cellsT + cellsT / 8);
+    }
+    cur = fas_sweeps(H, l, cur, post, bc);                                                   // 10
     if (cur != H.u[l]) (void)hipMemcpyAsync(H.u[l], cur, cells(l) * sizeof(double), hipMemcpyDeviceToDevice, s);
   }
 

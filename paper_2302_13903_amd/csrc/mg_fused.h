@@ -88,4 +88,10 @@ int fused_grid_blocks(int n, int hx, int hy);
 template <typename T>
 std::string fused_pass_name(bool pro, int out, bool sweep = true);
 
+// Full Approximation Scheme (Alg. 3 steps 2-4) in one streaming pass over a dense FP64 level:
+// fc = restricted defect f - L u, pbar = uc = restricted u.
+void fused_fas_restrict(const double* u, const double* f, double* fc, double* pbar, double* uc, int n, double h,
+                        const LevelBC& bc, hipStream_t s);
+std::string fused_fas_restrict_name();
+
 }  // namespace mg

@@ -38,7 +38,8 @@ struct FusedArgs {
   const void* f;
   const void* ec;     // PRO: coarse correction (n/2)^3
   void* fc;           // DEF: coarse source (n/2)^3
-  void* uc0;          // DEF: coarse correction to clear
+  void* uc0;          // DEF: coarse correction to clear (FASDEF: coarse start = restricted u)
+  void* pbar;         // FASDEF: restricted u
   double* part;       // NORM: one partial sum per block
   const float* e32;   // MIX: FP32 correction added to u on load
   float* r32;         // MIX: FP32 copy of the defect
@@ -102,9 +103,12 @@ struct alignas(2 * sizeof(T)) Pair {
 //   MODE_MIX   : no sweep, OUT = 2: u = u + e32 on load, written out, then the defect of the
 //                updated u, its sum of squares and its FP32 copy -- the FP64 part of one
 //                mixed-precision defect-correction step;
+//   MODE_FASDEF: MODE_DEF with OUT = 1 for the Full Approximation Scheme (Alg. 3 steps 2-4):
+//                besides the restricted defect, the restricted u goes to pbar and to the
+//                coarse start uc0;
 //   MODE_DEF   : no sweep, u is not written: only the OUT stage on the input u (the defect
 //                restricted to the coarse level, or its sum of squares).
-enum : int { MODE_SWEEP = 0, MODE_MIX = 1, MODE_DEF = 2 };
+enum : int { MODE_SWEEP = 0, MODE_MIX = 1, MODE_DEF = 2, MODE_FASDEF = 3 };
 
 // BLK: the level is in the MeshBlock layout (blocks of 2^A.Lm cells, Morton order); the tile
 // streams across block boundaries exactly as across a dense array (an x-pair never straddles
@@ -114,7 +118,9 @@ template <typename T, int R, int W, bool PRO, int OUT, int MODE = MODE_SWEEP, bo
 __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
   constexpr bool SWEEP = MODE == MODE_SWEEP;
   constexpr bool MIX = MODE == MODE_MIX;
-  constexpr bool WRITE_U = MODE != MODE_DEF;
+  constexpr bool WRITE_U = MODE == MODE_SWEEP || MODE == MODE_MIX;
+  constexpr bool FASR = MODE == MODE_FASDEF;
+  static_assert(!FASR || OUT == 1, "the FAS restriction rides on the restricted-defect stage");
   // OUT = 3 (with a sweep): the sum of squared defects of the INPUT u, taken in the red stage
   // before it updates the plane (no defect stage behind the sweep)
   constexpr bool INNORM = SWEEP && OUT == 3;
@@ -193,6 +199,7 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
 #pragma unroll
     for (int r = 0; r < (INNORM ? R : 0); ++r) uol[r][tid] = Pair<T>{(T)0, (T)0};
     T stash[R / 2 > 0 ? R / 2 : 1];
+    T stash_u[FASR && R / 2 > 0 ? R / 2 : 1];   // FASDEF: restricted u of the even plane
 #pragma unroll
     for (int s = 0; s < kRing; ++s)
 #pragma unroll
@@ -427,6 +434,7 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
       } else if (OUT == 1) {
         T* __restrict__ fcp = reinterpret_cast<T*>(A.fc);
         T* __restrict__ ucp = reinterpret_cast<T*>(A.uc0);
+        T* __restrict__ pbp = reinterpret_cast<T*>(A.pbar);
         const int pg = pz ? (p & nm) : p;
 #pragma unroll
         for (int q2 = 0; q2 < R / 2; ++q2) {
@@ -434,13 +442,21 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
           row_defect(2 * q2, d0);
           row_defect(2 * q2 + 1, d1);
           const T s = (d0[0] + d0[1]) + (d1[0] + d1[1]);
+          const T su = FASR ? (pc[2 * q2][0] + pc[2 * q2][1]) + (pc[2 * q2 + 1][0] + pc[2 * q2 + 1][1]) : (T)0;
           if ((pg & 1) == 0) {
             stash[q2] = s;
+            if (FASR) stash_u[q2] = su;
           } else if (out_z && out_x && out_y[2 * q2]) {
             const int Lc = L - 1;
             const size_t ci = lidx(Lc, BLK ? A.Lm - 1 : 0, xag >> 1, ygv[2 * q2] >> 1, pg >> 1);
             fcp[ci] = (stash[q2] + s) * (T)0.125;
-            ucp[ci] = (T)0;
+            if (FASR) {
+              const T pb = (stash_u[q2] + su) * (T)0.125;
+              pbp[ci] = pb;
+              ucp[ci] = pb;
+            } else {
+              ucp[ci] = (T)0;
+            }
           }
         }
       }
@@ -675,6 +691,17 @@ void fused_defect_restrict(const T* u, const T* f, T* fc, T* uc0, int n, double 
   launch_pass<T, false, 1, MODE_DEF>(A, s);
 }
 
+void fused_fas_restrict(const double* u, const double* f, double* fc, double* pbar, double* uc, int n, double h,
+                        const LevelBC& bc, hipStream_t s) {
+  FusedArgs A = base_args(u, (double*)nullptr, f, n, h, 1.0, bc);
+  A.hx = 2;   // defect only: radius 1, rounded up to even
+  A.hy = 2;   // even, so that restriction row pairs align
+  A.fc = fc;
+  A.uc0 = uc;
+  A.pbar = pbar;
+  launch_pass<double, false, 1, MODE_FASDEF>(A, s);
+}
+
 template <typename T>
 int fused_defect_norm(const T* u, const T* f, double* part, int n, double h, const LevelBC& bc, hipStream_t s,
                       float* r32) {
@@ -761,6 +788,8 @@ std::string fused_pass_name(bool pro, int out, bool sweep) {
   }
   return kname<T>(R, W, pro, out, MODE_SWEEP, false);
 }
+
+std::string fused_fas_restrict_name() { return kname<double>(2, 16, false, 1, MODE_FASDEF, false); }
 
 #define MG_FUSED_INST(T)                                                                                        \
   template bool fused_supported<T>(int);                                                                        \
