@@ -1,0 +1,186 @@
+"""Pins of the refined-mesh oracle (Sec. 3.3; level boundaries eqs. masscons-lbext; FAS V-cycle
+on MeshBlock, Octet and root levels) against facts that do not come from it: the composite
+operator is exact for linear fields and conserves mass (the paper's reason for the
+conservative formulation), equals the uniform 7-point operator away from level boundaries,
+the multigrid iteration converges to the dense direct solve of the composite system (whose
+solution is a fixed point of one V-cycle), and the refined solution of a smooth density is
+second-order accurate against the analytic potential, well ahead of the uniform coarse grid.
+CPU only."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import amr
+
+FPG = 4 * math.pi
+
+
+def grids(m, k=None):
+    out = []
+    for l in range(m.Lam + 1):
+        x, y, z = m.centres(l, k)
+        Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+        out.append((X, Y, Z))
+    return out
+
+
+MESHES = {
+    "one level": lambda: amr.AmrMesh(4, 4, [((1, 1, 1), (3, 3, 3))]),
+    "two levels": lambda: amr.AmrMesh(4, 4, [((1, 1, 1), (3, 3, 3)), ((3, 3, 3), (5, 5, 5))]),
+    "off-centre box": lambda: amr.AmrMesh(4, 2, [((1, 2, 1), (3, 3, 2))]),
+}
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_linear_fields_are_exact(name):
+    """Linear phi with fixed faces holding its values: every ghost (physical, fine-side
+    interpolation, coarse-side extrapolation) is exact, so L phi = 0 in every active cell,
+    on both sides of every level boundary."""
+    m = MESHES[name]()
+    a = (0.7, -1.3, 2.1)
+    lin = lambda x, y, z: 0.4 + a[0] * x + a[1] * y + a[2] * z
+    phi = [lin(X, Y, Z) for X, Y, Z in grids(m)]
+    L = amr.composite_laplacian(m, phi, [amr.FIXED] * 6, lin)
+    hmin = m.patches[m.Lam][m.K].h
+    assert max(np.abs(x).max() for x in L) < 1e-10 / hmin ** 2 * 1e-3
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_mass_conservation(name):
+    """Periodic domain, arbitrary phi: the volume integral of the composite Laplacian vanishes
+    (the fluxes through every coarse face equal the mean of the four fine fluxes, eq. masscons,
+    so they telescope).  A non-conservative level boundary leaves a residue of order
+    h^2 |L phi|."""
+    m = MESHES[name]()
+    rng = np.random.default_rng(1)
+    phi = [rng.normal(size=m.patches[l][m.K].n[::-1]) for l in range(m.Lam + 1)]
+    L = amr.composite_laplacian(m, phi, [amr.PERIODIC] * 6)
+    tot = sum(m.patches[l][m.K].h ** 3 * L[l].sum() for l in range(m.Lam + 1))
+    scale = sum(m.patches[l][m.K].h ** 3 * np.abs(L[l]).sum() for l in range(m.Lam + 1))
+    assert abs(tot) < 1e-13 * scale
+
+
+def test_uniform_operator_away_from_level_boundaries():
+    """Cells whose six neighbours are in their own patch see the plain 7-point operator: the
+    uniform oracle's defect on the root patch agrees there (to rounding)."""
+    m = MESHES["one level"]()
+    rng = np.random.default_rng(2)
+    phi = [rng.normal(size=m.patches[l][m.K].n[::-1]) for l in range(m.Lam + 1)]
+    L = amr.composite_laplacian(m, phi, [amr.PERIODIC] * 6)
+    p0 = m.patches[0][m.K]
+    d = oracle.defect(phi[0], np.zeros_like(phi[0]), p0.h, oracle.PERIODIC)     # -L phi
+    (x0, y0, z0), (x1, y1, z1) = p0.hole
+    far = np.ones_like(phi[0], dtype=bool)
+    far[z0 - 1:z1 + 1, y0 - 1:y1 + 1, x0 - 1:x1 + 1] = False
+    assert np.max(np.abs(L[0][far] + d[far])) < 1e-12 * np.abs(d).max()
+
+
+def dense_composite_solve(m, rho, kinds, bfun):
+    """Assemble the composite operator column by column (unit potentials on the active cells)
+    and solve L phi = f directly."""
+    act = [m.patches[l][m.K].active() for l in range(m.Lam + 1)]
+    sizes = [int(a.sum()) for a in act]
+    N = sum(sizes)
+
+    def unpack(v):
+        out, o = [], 0
+        for l in range(m.Lam + 1):
+            a = np.zeros(act[l].shape)
+            a[act[l]] = v[o:o + sizes[l]]
+            out.append(a)
+            o += sizes[l]
+        return out
+
+    def pack(arrs):
+        return np.concatenate([arrs[l][act[l]] for l in range(m.Lam + 1)])
+
+    g = pack(amr.composite_laplacian(m, unpack(np.zeros(N)), kinds, bfun))
+    A = np.zeros((N, N))
+    for c in range(N):
+        e = np.zeros(N)
+        e[c] = 1.0
+        A[:, c] = pack(amr.composite_laplacian(m, unpack(e), kinds, None))
+    f = pack([FPG * r for r in rho])
+    return unpack(np.linalg.solve(A, f - g))
+
+
+@pytest.mark.parametrize("name", ["one level", "off-centre box"])
+def test_converges_to_dense_composite_solve(name):
+    m = amr.AmrMesh(4, 2, [((1, 1, 1), (3, 3, 3))]) if name == "one level" else MESHES[name]()
+    rng = np.random.default_rng(3)
+    rho = [rng.uniform(0, 1, m.patches[l][m.K].n[::-1]) for l in range(m.Lam + 1)]
+    bfun = lambda x, y, z: 0.1 * x - 0.2 * y * z
+    ref = dense_composite_solve(m, rho, [amr.FIXED] * 6, bfun)
+    phi, hist = amr.solve(m, rho, [amr.FIXED] * 6, bfun, tol=1e-13)
+    assert hist[-1] <= 1e-13
+    num = math.sqrt(sum(np.sum((phi[l] - ref[l]) ** 2) for l in range(m.Lam + 1)))
+    den = math.sqrt(sum(np.sum(ref[l] ** 2) for l in range(m.Lam + 1)))
+    assert num / den < 1e-11
+    # the exact composite solution is a fixed point of one V-cycle
+    phi1, h1 = amr.solve(m, rho, [amr.FIXED] * 6, bfun, phi0=ref, cycles=1)
+    assert h1[0] < 1e-12 and h1[1] < 1e-12
+    assert max(np.abs(phi1[l] - ref[l]).max() for l in range(m.Lam + 1)) < 1e-12 * max(np.abs(r).max() for r in ref)
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_vcycle_contracts(name):
+    """FAS V(2,2) on the refined mesh reduces the composite residual by at least 5x per cycle
+    (measured ~15x), from zero to below 1e-10 within 12 cycles."""
+    m = MESHES[name]()
+    rho = []
+    for X, Y, Z in grids(m):
+        r = np.sqrt((X - 0.5) ** 2 + (Y - 0.5) ** 2 + (Z - 0.5) ** 2)
+        rho.append(np.where(r < 0.2, 1.0, 0.0))
+    phi, hist = amr.solve(m, rho, [amr.PERIODIC] * 6, cycles=12)
+    assert hist[-1] < 1e-10
+    for a, b in zip(hist[1:6], hist[2:7]):
+        assert b < 0.2 * a
+
+
+def _gaussian_case(NB, nb):
+    """Gaussian density (sigma = 0.04, centred in the refined box) with its analytic potential
+    -M erf(r / (sqrt(2) sigma)) / r on the domain faces; returns (refined-region error,
+    error of the uniform root-resolution solve in the same region)."""
+    from scipy.special import erf
+    sig, c = 0.04, np.array([0.5, 0.5, 0.5])
+    M = (2 * math.pi * sig * sig) ** 1.5
+
+    def exact(x, y, z):
+        r = np.maximum(np.sqrt((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2), 1e-12)
+        return -M * erf(r / (math.sqrt(2) * sig)) / r
+
+    def dens(X, Y, Z):
+        return np.exp(-((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2) / (2 * sig * sig))
+
+    m = amr.AmrMesh(NB, nb, [((1, 1, 1), (3, 3, 3))])
+    gs = grids(m)
+    phi, hist = amr.solve(m, [dens(*g) for g in gs], [amr.FIXED] * 6, exact, tol=1e-11)
+    err_fine = np.abs(phi[1] - exact(*gs[1])).max()
+    n = NB * nb
+    x = (np.arange(n) + 0.5) / n
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    faces = []
+    for face in range(6):
+        axis, side = face // 2, face % 2
+        t = [q for q in range(3) if q != axis]
+        co = [None, None, None]
+        co[axis] = np.array(0.0 if side == 0 else 1.0)
+        co[t[0]] = x[None, :]
+        co[t[1]] = x[:, None]
+        faces.append(np.ascontiguousarray(np.broadcast_to(exact(*co), (n, n))))
+    phi_u, _, _ = oracle.solve(dens(X, Y, Z), 1.0 / n, [oracle.FIXED] * 6, fixed_b=faces, tol=1e-11)
+    lo, hi = m.patches[0][m.K].hole
+    sl = (slice(lo[2], hi[2]), slice(lo[1], hi[1]), slice(lo[0], hi[0]))
+    return err_fine, np.abs(phi_u - exact(X, Y, Z))[sl].max()
+
+
+def test_refinement_accuracy_against_analytic():
+    """Second-order accuracy through the level boundary: in the refined region the error
+    against the analytic potential is about a quarter of the uniform coarse grid's (measured
+    0.30), and it falls about fourfold when the resolution doubles (measured 3.9x)."""
+    e4, _ = _gaussian_case(4, 4)
+    e8, u8 = _gaussian_case(4, 8)
+    assert e8 < 0.35 * u8, (e8, u8)
+    assert e8 < 0.3 * e4, (e4, e8)
