@@ -217,6 +217,53 @@ int mg_gravity(mg_ctx *ctx, const mg_params *p, const mg_bc *bc, const double *p
 int mg_gravity_kernel_name(const mg_params *p, int want_g, int want_rhog, int want_gface, char *buf,
                            int cap);
 
+/* ---- statically refined mesh (Sec. 3.3) --------------------------------------------
+ *
+ * The unit cube as NB^3 root MeshBlocks of nb^3 cells, with `levels` nested refinement
+ * boxes: box lam (1..levels) is a box of level-(lam-1) MeshBlocks, [box_lo, box_hi) per axis
+ * in level-(lam-1) block units, each refined into 2 x 2 x 2 level-lam MeshBlocks.  Box 1
+ * lies inside the root grid and box lam inside box lam-1 (in level-(lam-1) units: inside
+ * [2 lo_{lam-1}, 2 hi_{lam-1})), each with at least one block of margin (2:1 balance).
+ * Refinement level lam is one dense patch per MeshBlock level: patch 0 is the root grid at
+ * (NB nb)^3 cells; patch lam >= 1 covers box lam at cell width 1/(NB nb 2^lam); its dims come
+ * from mg_amr_patch_dims.  Cells of a patch under the next finer box are covered: ignored on
+ * input, 0 on output. */
+#define MG_AMR_MAX_LEVELS 8
+typedef struct {
+  int NB;                               /* root blocks per side (power of two, <= 256)      */
+  int nb;                               /* cells per block side (power of two, 2..64)       */
+  int levels;                           /* refinement levels, 0..MG_AMR_MAX_LEVELS          */
+  int box_lo[MG_AMR_MAX_LEVELS][3];     /* box of level lam at index lam-1, (x, y, z)       */
+  int box_hi[MG_AMR_MAX_LEVELS][3];
+} mg_amr_mesh;
+
+/* Cells per axis (x, y, z) of patch lam (0..levels) at the finest MeshBlock level. */
+int mg_amr_patch_dims(const mg_amr_mesh *mesh, int lam, int dims[3]);
+
+/* FAS V-cycles (Alg. 3) on the refined mesh, from the initial guess in phi (MG_MODE_MGI):
+ * MeshBlock levels with every refinement level smoothed together, the conservative level
+ * boundary (eqs. masscons, transgrad, piint, lbint, lbext: interpolated fine ghosts, one
+ * extrapolated coarse ghost per face of the refined region) before every colour and defect,
+ * Octet levels finest first, a uniform FAS V-cycle on the NB^3 root grid, and corrections
+ * prolongated through the normal level boundary (restriction into the covered coarse cells,
+ * trilinear prolongation into the finer patch's ghost shell).
+ *   p     dx = 1/(NB nb) (the unit cube); four_pi_g, npre, npost, omega, tol, max_cycles,
+ *         fixed_cycles as for mg_solve; mode MG_MODE_MGI and precision FP64 (else
+ *         MG_ERR_UNSUPPORTED).
+ *   bc    periodic, zero-gradient or fixed faces (fixed_b: device (NB nb)^2 face-centre
+ *         arrays; coarser levels take 2 x 2 area means); multipole: MG_ERR_UNSUPPORTED.
+ *   rho   host array of levels+1 device pointers, patch lam's density (dims of
+ *         mg_amr_patch_dims, x fastest), read only.
+ *   phi   host array of levels+1 device pointers, same shapes: the initial guess on input,
+ *         the potential on output (volume-weighted mean removed when no face is fixed).
+ *   hist  host, relative composite residual RMS(f - L phi)/RMS(f) (cell-volume weighted) of
+ *         the initial guess and after each cycle; n_hist its length.
+ * Allocates its workspace per call (device memory, freed before returning) and synchronises
+ * `stream`. */
+int mg_amr_solve(mg_ctx *ctx, const mg_params *p, const mg_amr_mesh *mesh, const mg_bc *bc,
+                 const double *const *rho, double *const *phi, double *hist, int *n_hist,
+                 void *stream);
+
 /* ---- operator entry points (each operator alone, for parity checks) ---------------- */
 
 /* One colour (0 = red, (i+j+k) even; 1 = black) of the RB-SOR smoother, eqs. rbsor1-2:

@@ -164,6 +164,14 @@ def fill_physical(u: np.ndarray, p: Patch, kinds, bfun: Optional[Callable], homo
             else:
                 if homogeneous or bfun is None:
                     b = 0.0
+                elif isinstance(bfun, FaceArrays):
+                    # arrays at this level's resolution, the ring repeating the nearest value
+                    arr = bfun.at(nx if axis != 0 else ny)[face]
+                    t = _transverse(axis)
+                    m1, m2 = (nx, ny, nz)[t[0]], (nx, ny, nz)[t[1]]
+                    i1 = np.arange(m1 + 2) - 1 if t[0] < axis else np.arange(m1)
+                    i2 = np.arange(m2 + 2) - 1 if t[1] < axis else np.arange(m2)
+                    b = arr[np.clip(i2, 0, m2 - 1)[:, None], np.clip(i1, 0, m1 - 1)[None, :]]
                 else:
                     # face points: the transverse cell centres (ghost positions included)
                     coords = []
@@ -178,6 +186,30 @@ def fill_physical(u: np.ndarray, p: Patch, kinds, bfun: Optional[Callable], homo
                     b = np.transpose(bfun(X, Y, Z), (2, 1, 0))     # -> [z][y][x]
                     b = np.squeeze(b, axis=ax)
                 u[sg] = 2.0 * b - u[sa]
+
+
+class FaceArrays:
+    """Fixed-face values given as six (N, N) arrays at the finest root resolution (indexed
+    [t2][t1], the transverse axes in increasing order); coarser levels take 2 x 2 area means,
+    as the uniform solver does."""
+
+    def __init__(self, faces):
+        self.levels = {}
+        cur = [np.asarray(b, dtype=np.float64) if b is not None else None for b in faces]
+        n = next(b.shape[0] for b in cur if b is not None)
+        while True:
+            self.levels[n] = [np.zeros((n, n)) if b is None else b for b in cur]
+            if n == 1:
+                break
+            cur = [0.25 * (b[0::2, 0::2] + b[0::2, 1::2] + b[1::2, 0::2] + b[1::2, 1::2]) if b is not None else None
+                   for b in self.levels[n]]
+            n //= 2
+
+    def at(self, n):
+        return self.levels[n]
+
+    def point(self, face):
+        return float(self.levels[1][face][0, 0])
 
 
 # ------------------------------------------------------------------ conservative level boundary
@@ -451,11 +483,17 @@ class AmrState:
                     axis, side = face // 2, face % 2
                     pt = [0.5, 0.5, 0.5]
                     pt[axis] = 0.0 if side == 0 else 1.0
-                    b = 0.0 if self.bfun is None else float(self.bfun(np.array(pt[0]), np.array(pt[1]), np.array(pt[2])))
+                    if self.bfun is None:
+                        b = 0.0
+                    elif isinstance(self.bfun, FaceArrays):
+                        b = self.bfun.point(face)
+                    else:
+                        b = float(self.bfun(np.array(pt[0]), np.array(pt[1]), np.array(pt[2])))
                     sa -= 1.0
                     sb += 2.0 * b
             if sa != 6.0:
-                u[1, 1, 1] = (sb - f[1, 1, 1]) / (6.0 - sa)      # h = 1 on the single cell
+                h = 1.0                                           # the unit cube's single cell
+                u[1, 1, 1] = (sb - h * h * f[1, 1, 1]) / (6.0 - sa)
 
         def fas(n):
             u, f = us[n], fs[n]

@@ -25,7 +25,8 @@ from ._abi import (MG_BC_FIXED, MG_BC_MULTIPOLE, MG_BC_PERIODIC, MG_BC_ZERO_GRAD
 __all__ = ["Context", "solve", "to_blocks", "from_blocks", "morton_order", "mg_solve", "mg_footprint_bytes", "params", "boundary", "level_bc",
            "mg_op_half_sweep", "mg_op_smooth", "mg_op_defect", "mg_op_restrict", "mg_op_prolong_add",
            "mg_op_prolong_fmg", "mg_op_coarsest", "mg_op_down", "mg_op_up", "mg_multipole_moments",
-           "gravity", "mg_gravity", "mg_gravity_kernel_name", "MgError", "KINDS"]
+           "gravity", "mg_gravity", "mg_gravity_kernel_name", "amr_mesh", "amr_patch_dims", "amr_solve",
+           "mg_amr_solve", "MgError", "KINDS"]
 
 KINDS = {"periodic": MG_BC_PERIODIC, "zero_gradient": MG_BC_ZERO_GRADIENT, "fixed": MG_BC_FIXED,
          "multipole": MG_BC_MULTIPOLE}
@@ -326,6 +327,62 @@ def gravity(phi, dx: float, bc="periodic", rho=None, fixed_b=None, lmax: int = 4
         m = n * n * (n + 1)
         out["faces"] = (gf[:m].view(n, n, n + 1), gf[m:2 * m].view(n, n + 1, n), gf[2 * m:].view(n + 1, n, n))
     return out
+
+
+# ------------------------------------------------------------------ refined mesh
+
+def amr_mesh(NB: int, nb: int, boxes) -> _abi.MgAmrMesh:
+    """Refined-mesh description: NB^3 root blocks of nb^3 cells; boxes[lam-1] = ((lo), (hi)) of
+    refinement level lam in level-(lam-1) block units, (x, y, z)."""
+    m = _abi.MgAmrMesh()
+    m.NB, m.nb, m.levels = int(NB), int(nb), len(boxes)
+    for q, (lo, hi) in enumerate(boxes):
+        for a in range(3):
+            m.box_lo[q][a] = int(lo[a])
+            m.box_hi[q][a] = int(hi[a])
+    return m
+
+
+def amr_patch_dims(mesh: _abi.MgAmrMesh, lam: int):
+    """(nx, ny, nz) of patch lam at the finest level."""
+    d = (ctypes.c_int * 3)()
+    st = _abi.lib().mg_amr_patch_dims(ctypes.byref(mesh), int(lam), d)
+    if st < 0:
+        raise MgError(f"mg_amr_patch_dims: {STATUS_NAMES.get(st, st)}")
+    return tuple(d)
+
+
+def mg_amr_solve(ctx: Context, p: _abi.MgParams, mesh: _abi.MgAmrMesh, bc: _abi.MgBC, rho, phi, stream=None):
+    """Raw ``mg_amr_solve``: rho and phi are lists of device tensors (one per patch, shape
+    (nz, ny, nx)); returns (status, hist list)."""
+    n = mesh.levels + 1
+    rp = (_abi._vp * n)(*[_ptr(r) for r in rho])
+    pp = (_abi._vp * n)(*[_ptr(q) for q in phi])
+    cap = max(p.max_cycles, p.fixed_cycles) + 1
+    hist = (ctypes.c_double * cap)()
+    nh = ctypes.c_int(0)
+    st = ctx._lib.mg_amr_solve(ctx.handle, ctypes.byref(p), ctypes.byref(mesh), ctypes.byref(bc), rp, pp, hist,
+                               ctypes.byref(nh), _stream(stream))
+    ctx.check(st, "mg_amr_solve")
+    return st, [hist[i] for i in range(nh.value)]
+
+
+def amr_solve(mesh: _abi.MgAmrMesh, rho, bc="periodic", fixed_b=None, phi=None, tol: float = 1e-10,
+              max_cycles: int = 50, fixed_cycles: int = 0, npre: int = 2, npost: int = 2, omega: float = 1.15,
+              four_pi_g: float = 4.0 * math.pi, ctx: Optional[Context] = None, stream=None):
+    """Solve on a statically refined mesh (V-cycles from phi, zero by default).  rho: list of
+    float64 device tensors, one per patch (shape (nz, ny, nx) from amr_patch_dims).  Returns
+    (phi list, hist, status)."""
+    import torch
+    ctx = ctx or default_context(rho[0].device.index or 0)
+    N = mesh.NB * mesh.nb
+    p = params(N, 1.0 / N, tol=tol, max_cycles=max_cycles, fixed_cycles=fixed_cycles, npre=npre, npost=npost,
+               omega=omega, mode="mgi", four_pi_g=four_pi_g)
+    b = boundary(bc, fixed_b)
+    if phi is None:
+        phi = [torch.zeros_like(r) for r in rho]
+    st, hist = mg_amr_solve(ctx, p, mesh, b, rho, phi, stream)
+    return phi, hist, st
 
 
 # ------------------------------------------------------------------ operator entry points

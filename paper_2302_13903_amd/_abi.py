@@ -37,6 +37,14 @@ class MgBC(ctypes.Structure):
                 ("use_origin", ctypes.c_int), ("origin", ctypes.c_double * 3)]
 
 
+MG_AMR_MAX_LEVELS = 8
+
+
+class MgAmrMesh(ctypes.Structure):
+    _fields_ = [("NB", ctypes.c_int), ("nb", ctypes.c_int), ("levels", ctypes.c_int),
+                ("box_lo", (ctypes.c_int * 3) * MG_AMR_MAX_LEVELS), ("box_hi", (ctypes.c_int * 3) * MG_AMR_MAX_LEVELS)]
+
+
 class MgLevelBC(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int * 6), ("b", ctypes.c_void_p * 6)]
 
@@ -105,6 +113,9 @@ def lib():
         "mg_kernel_timing": (i, [_vp, i, _ip, _dp, _dp, ctypes.c_char_p, i]),
         "mg_multipole_moments": (i, [_vp, i, d, _vp, i, i, _dp, _dp, _dp, _vp]),
         "mg_gravity": (i, [_vp, ctypes.POINTER(MgParams), ctypes.POINTER(MgBC), _vp, _vp, _vp, _vp, _vp, _vp]),
+        "mg_amr_patch_dims": (i, [ctypes.POINTER(MgAmrMesh), i, _ip]),
+        "mg_amr_solve": (i, [_vp, ctypes.POINTER(MgParams), ctypes.POINTER(MgAmrMesh), ctypes.POINTER(MgBC),
+                             ctypes.POINTER(_vp), ctypes.POINTER(_vp), _dp, _ip, _vp]),
         "mg_gravity_kernel_name": (i, [ctypes.POINTER(MgParams), i, i, i, ctypes.c_char_p, i]),
         "mg_op_half_sweep": (i, [_vp, i, d, d, i, ctypes.POINTER(MgLevelBC), _vp, _vp, _vp]),
         "mg_op_smooth": (i, [_vp, i, d, d, i, ctypes.POINTER(MgLevelBC), _vp, _vp, _vp]),

@@ -1,0 +1,906 @@
+// mg_amr.hip -- the multigrid solver on a statically refined mesh (Sec. 3.3): FAS V-cycles
+// (Alg. 3) over the MeshBlock levels, the Octet levels and the root grid.
+//
+// Mesh: NB^3 root MeshBlocks of nb^3 cells; refinement level lam = 1..Lam is one box of
+// level-(lam-1) MeshBlocks refined 2:1, nested inside box lam-1 with a margin of at least one
+// block.  On MG level k (2^k cells per MeshBlock side) each refinement level is one dense
+// patch with a one-cell ghost layer; cells under the next finer box are covered.
+//
+// Level boundaries: before every colour of the smoother and before every defect, the fine
+// patch's ghost faces are interpolated from the coarse patch (transverse coarse gradients,
+// eqs. transgrad and piint, then eq. lbint between those points and the first fine cells) and
+// the coarse side gets one ghost per hole face by extrapolation through the area mean of the
+// first fine cells (eq. lbext), so the face fluxes match (eq. masscons).  Before a
+// correction is prolongated, the normal level boundary restricts the finer patch into the
+// covered coarse cells and prolongates the coarse patch into the finer patch's ghost shell.
+//
+// Every operator is one plain launch over a patch (the refined levels are small next to the
+// uniform path; this is the correctness-first form of the refined solver).  Arithmetic follows
+// the same expressions in the same order as the oracle, so results agree to rounding.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mg355.h"
+#include "mg_launch.h"
+
+namespace mg {
+
+namespace {
+
+constexpr int kB = 256;
+
+struct Dims {
+  int n[3];   // active cells per axis (x, y, z)
+};
+
+__host__ __device__ inline size_t gx(const Dims& d, int x, int y, int z) {
+  return ((size_t)(z + 1) * (size_t)(d.n[1] + 2) + (size_t)(y + 1)) * (size_t)(d.n[0] + 2) + (size_t)(x + 1);
+}
+inline size_t ghosted(const Dims& d) { return (size_t)(d.n[0] + 2) * (d.n[1] + 2) * (d.n[2] + 2); }
+__host__ __device__ inline size_t cells(const Dims& d) { return (size_t)d.n[0] * d.n[1] * d.n[2]; }
+inline unsigned blocks(size_t work) { return (unsigned)std::max<size_t>(1, (work + kB - 1) / kB); }
+
+struct Hole {
+  int on;
+  int lo[3], hi[3];       // covered cells, local [lo, hi)
+  const double* cg[6];    // per hole face: ghost seen from the active cell outside it, [t2][t1]
+};
+
+__device__ inline bool covered(const Hole& H, int x, int y, int z) {
+  return H.on && x >= H.lo[0] && x < H.hi[0] && y >= H.lo[1] && y < H.hi[1] && z >= H.lo[2] && z < H.hi[2];
+}
+
+// Neighbour value across one face of active cell (x, y, z): the stored neighbour, or the
+// hole face's ghost when the neighbour is covered.
+__device__ inline double nbv(const double* __restrict__ u, const Dims& d, const Hole& H, int x, int y, int z,
+                             int axis, int dir) {
+  int p[3] = {x, y, z};
+  p[axis] += dir;
+  if (covered(H, p[0], p[1], p[2])) {
+    const int face = 2 * axis + (dir > 0 ? 0 : 1);   // entering through the hole's low face from below
+    const int t1 = axis == 0 ? 1 : 0, t2 = axis == 2 ? 1 : 2;
+    const int m1 = H.hi[t1] - H.lo[t1];
+    return H.cg[face][(size_t)(p[t2] - H.lo[t2]) * m1 + (p[t1] - H.lo[t1])];
+  }
+  return u[gx(d, p[0], p[1], p[2])];
+}
+
+__device__ inline double nbsum(const double* __restrict__ u, const Dims& d, const Hole& H, int x, int y, int z) {
+  const double xm = nbv(u, d, H, x, y, z, 0, -1), xp = nbv(u, d, H, x, y, z, 0, 1);
+  const double ym = nbv(u, d, H, x, y, z, 1, -1), yp = nbv(u, d, H, x, y, z, 1, 1);
+  const double zm = nbv(u, d, H, x, y, z, 2, -1), zp = nbv(u, d, H, x, y, z, 2, 1);
+  return ((((xm + xp) + ym) + yp) + zm) + zp;
+}
+
+__device__ inline void cell_of(size_t t, const Dims& d, int& x, int& y, int& z) {
+  x = (int)(t % d.n[0]);
+  y = (int)((t / d.n[0]) % d.n[1]);
+  z = (int)(t / ((size_t)d.n[0] * d.n[1]));
+}
+
+// ---- physical ghosts of the root patch, one axis per launch (x, then y over the x ghosts,
+// then z over both), Sec. 2.3.6; fixed faces read b (bn x bn, [t2][t1]) clamped to the face
+struct Phys {
+  int kind[6];
+  const double* b[6];
+  int bn;
+};
+
+__global__ void __launch_bounds__(kB) k_fill_phys(double* __restrict__ u, Dims d, int axis, Phys P, int hom) {
+  const int m1 = axis == 0 ? d.n[1] : d.n[0] + 2, off1 = axis == 0 ? 0 : -1;
+  const int m2 = axis == 2 ? d.n[1] + 2 : d.n[2], off2 = axis == 2 ? -1 : 0;
+  const size_t t = (size_t)blockIdx.x * kB + threadIdx.x;
+  if (t >= (size_t)2 * m1 * m2) return;
+  const int side = (int)(t / ((size_t)m1 * m2));
+  const int r = (int)(t % ((size_t)m1 * m2));
+  const int c1 = r % m1 + off1, c2 = r / m1 + off2;
+  const int na = d.n[axis];
+  const int g = side ? na : -1, a = side ? na - 1 : 0, o = side ? 0 : na - 1;
+  auto at = [&](int q) {
+    if (axis == 0) return gx(d, q, c1, c2);
+    if (axis == 1) return gx(d, c1, q, c2);
+    return gx(d, c1, c2, q);
+  };
+  const int face = 2 * axis + side;
+  const int kd = P.kind[face];
+  if (kd == BC_PERIODIC) {
+    u[at(g)] = u[at(o)];
+  } else if (kd == BC_ZERO_GRADIENT) {
+    u[at(g)] = u[at(a)];
+  } else {
+    double b = 0.0;
+    if (!hom && P.b[face]) {
+      const int i1 = min(max(c1, 0), P.bn - 1), i2 = min(max(c2, 0), P.bn - 1);
+      b = P.b[face][(size_t)i2 * P.bn + i1];
+    }
+    u[at(g)] = 2.0 * b - u[at(a)];
+  }
+}
+
+// ---- conservative level boundary (eqs. transgrad, piint, lbint; lbext on the coarse side)
+struct Cons {
+  double* uf;
+  Dims df;
+  const double* uc;
+  Dims dc;
+  int lo[3], hi[3];   // the fine box in coarse local cells
+  double* cg[6];      // coarse ghosts per face, or nullptr
+};
+
+__global__ void __launch_bounds__(kB) k_cons(Cons A, int axis) {
+  const int t1a = axis == 0 ? 1 : 0, t2a = axis == 2 ? 1 : 2;
+  const int nf1 = A.df.n[t1a], nf2 = A.df.n[t2a];
+  const size_t t = (size_t)blockIdx.x * kB + threadIdx.x;
+  if (t >= (size_t)2 * nf1 * nf2) return;
+  const int side = (int)(t / ((size_t)nf1 * nf2));
+  const int r = (int)(t % ((size_t)nf1 * nf2));
+  const int j1 = r % nf1, j2 = r / nf1;
+  const int J1 = A.lo[t1a] + (j1 >> 1), J2 = A.lo[t2a] + (j2 >> 1);
+  const int cl = side ? A.hi[axis] : A.lo[axis] - 1;
+  auto cidx = [&](int q1, int q2) {
+    int p[3];
+    p[axis] = cl;
+    p[t1a] = q1;
+    p[t2a] = q2;
+    return gx(A.dc, p[0], p[1], p[2]);
+  };
+  auto fidx = [&](int layer, int q1, int q2) {
+    int p[3];
+    p[axis] = layer;
+    p[t1a] = q1;
+    p[t2a] = q2;
+    return gx(A.df, p[0], p[1], p[2]);
+  };
+  const double C = A.uc[cidx(J1, J2)];
+  const double d1 = A.uc[cidx(J1 + 1, J2)] - A.uc[cidx(J1 - 1, J2)];
+  const double d2 = A.uc[cidx(J1, J2 + 1)] - A.uc[cidx(J1, J2 - 1)];
+  const double s1 = (j1 & 1) ? 1.0 : -1.0, s2 = (j2 & 1) ? 1.0 : -1.0;
+  const double cross = (C + s1 * (d1 * 0.125)) + s2 * (d2 * 0.125);
+  const int first = side ? A.df.n[axis] - 1 : 0;
+  const double F = A.uf[fidx(first, j1, j2)];
+  A.uf[fidx(side ? A.df.n[axis] : -1, j1, j2)] = (1.0 / 3.0) * F + (2.0 / 3.0) * cross;
+  if (A.cg[0] && !(j1 & 1) && !(j2 & 1)) {
+    const double fr = 0.25 * (((F + A.uf[fidx(first, j1 + 1, j2)]) + A.uf[fidx(first, j1, j2 + 1)]) +
+                              A.uf[fidx(first, j1 + 1, j2 + 1)]);
+    const int m1 = A.hi[t1a] - A.lo[t1a];
+    A.cg[2 * axis + side][(size_t)(J2 - A.lo[t2a]) * m1 + (J1 - A.lo[t1a])] = (4.0 / 3.0) * fr - (1.0 / 3.0) * C;
+  }
+}
+
+// ---- RB-SOR on the active cells of one colour (eqs. rbsor1-2); colour by global parity
+__global__ void __launch_bounds__(kB) k_smooth(double* __restrict__ u, const double* __restrict__ f, Dims d, int o0,
+                                                int o1, int o2, Hole H, double h2, double omega, int colour) {
+  const size_t t = (size_t)blockIdx.x * kB + threadIdx.x;
+  if (t >= cells(d)) return;
+  int x, y, z;
+  cell_of(t, d, x, y, z);
+  if ((((o0 + x) + (o1 + y) + (o2 + z)) & 1) != colour || covered(H, x, y, z)) return;
+  const size_t c = gx(d, x, y, z);
+  const double uc = u[c];
+  const double nb = nbsum(u, d, H, x, y, z);
+  u[c] = uc + omega * ((nb - h2 * f[c]) / 6.0 - uc);
+}
+
+// ---- out = a + s L u on the active cells (defect: a = f, s = -1; FAS source: a = restricted
+// defect, s = +1); covered cells get 0
+__global__ void __launch_bounds__(kB) k_lap(const double* __restrict__ u, const double* __restrict__ a,
+                                             double* __restrict__ out, Dims d, Hole H, double ih2, double s) {
+  const size_t t = (size_t)blockIdx.x * kB + threadIdx.x;
+  if (t >= cells(d)) return;
+  int x, y, z;
+  cell_of(t, d, x, y, z);
+  const size_t c = gx(d, x, y, z);
+  if (covered(H, x, y, z)) {
+    out[c] = 0.0;
+    return;
+  }
+  const double L = (nbsum(u, d, H, x, y, z) - 6.0 * u[c]) * ih2;
+  out[c] = a[c] + s * L;
+}
+
+// ---- 8-cell mean (eq. restriction) of the fine patch into coarse cells [0, nr) written at
+// coarse local offset o; covered fine cells count as 0 when the fine hole is given
+__global__ void __launch_bounds__(kB) k_restrict(const double* __restrict__ uf, Dims df, Hole Hf, double* out1,
+                                                  double* out2, Dims dc, int o0, int o1, int o2, Dims nr) {
+  const size_t t = (size_t)blockIdx.x * kB + threadIdx.x;
+  if (t >= cells(nr)) return;
+  int X, Y, Z;
+  cell_of(t, nr, X, Y, Z);
+  double s = 0.0;
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int x = 2 * X + a, y = 2 * Y + b, z = 2 * Z + c;
+        s += covered(Hf, x, y, z) ? 0.0 : uf[gx(df, x, y, z)];
+      }
+  const double v = s / 8.0;
+  const size_t o = gx(dc, o0 + X, o1 + Y, o2 + Z);
+  out1[o] = v;
+  if (out2) out2[o] = v;
+}
+
+// ---- trilinear prolongation (eq. trilinear), separable x then y then z as in the oracle.
+// Fine cells [lo, hi) per axis (ghost indices allowed); parent coarse cell = (fine global >>
+// 1) - coarse origin.  mode 0: add on active fine cells; 1: set, only on the ghost shell.
+__global__ void __launch_bounds__(kB) k_prolong(const double* __restrict__ uc, Dims dc, int co0, int co1, int co2,
+                                                 double* __restrict__ uf, Dims df, int fo0, int fo1, int fo2,
+                                                 Hole Hf, int lx, int ly, int lz, Dims span, int mode) {
+  const size_t t = (size_t)blockIdx.x * kB + threadIdx.x;
+  if (t >= cells(span)) return;
+  int x, y, z;
+  cell_of(t, span, x, y, z);
+  x += lx;
+  y += ly;
+  z += lz;
+  const bool shell = x < 0 || y < 0 || z < 0 || x >= df.n[0] || y >= df.n[1] || z >= df.n[2];
+  if (mode == 0 && (shell || covered(Hf, x, y, z))) return;
+  if (mode == 1 && !shell) return;
+  const int gxg = fo0 + x, gyg = fo1 + y, gzg = fo2 + z;
+  const int X = (gxg >> 1) - co0, Y = (gyg >> 1) - co1, Z = (gzg >> 1) - co2;
+  const int ux = gxg & 1, uy = gyg & 1, uz = gzg & 1;
+  // per axis: lower child 1/4 c[I-1] + 3/4 c[I]; upper 3/4 c[I] + 1/4 c[I+1]
+  auto lin = [](double cm, double c0, double cp, int up) { return up ? 0.75 * c0 + 0.25 * cp : 0.25 * cm + 0.75 * c0; };
+  double ty[3][3];
+#pragma unroll
+  for (int c = -1; c <= 1; ++c)
+#pragma unroll
+    for (int b = -1; b <= 1; ++b)
+      ty[c + 1][b + 1] = lin(uc[gx(dc, X - 1, Y + b, Z + c)], uc[gx(dc, X, Y + b, Z + c)],
+                             uc[gx(dc, X + 1, Y + b, Z + c)], ux);
+  double tz[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) tz[c] = lin(ty[c][0], ty[c][1], ty[c][2], uy);
+  const double v = lin(tz[0], tz[1], tz[2], uz);
+  const size_t o = gx(df, x, y, z);
+  uf[o] = mode == 0 ? uf[o] + v : v;
+}
+
+// out = u - p on the active cells (0 on covered cells)
+__global__ void __launch_bounds__(kB) k_sub(const double* __restrict__ u, const double* __restrict__ p,
+                                             double* __restrict__ out, Dims d, Hole H) {
+  const size_t t = (size_t)blockIdx.x * kB + threadIdx.x;
+  if (t >= cells(d)) return;
+  int x, y, z;
+  cell_of(t, d, x, y, z);
+  const size_t c = gx(d, x, y, z);
+  out[c] = covered(H, x, y, z) ? 0.0 : u[c] - p[c];
+}
+
+// dense caller array <-> ghosted patch: a*src + c on active cells, 0 on covered cells
+__global__ void __launch_bounds__(kB) k_load(const double* __restrict__ src, double* __restrict__ dst, Dims d, Hole H,
+                                              double a, double c) {
+  const size_t t = (size_t)blockIdx.x * kB + threadIdx.x;
+  if (t >= cells(d)) return;
+  int x, y, z;
+  cell_of(t, d, x, y, z);
+  dst[gx(d, x, y, z)] = covered(H, x, y, z) ? 0.0 : a * src[t] + c;
+}
+__global__ void __launch_bounds__(kB) k_store(const double* __restrict__ src, double* __restrict__ dst, Dims d, Hole H,
+                                               double c) {
+  const size_t t = (size_t)blockIdx.x * kB + threadIdx.x;
+  if (t >= cells(d)) return;
+  int x, y, z;
+  cell_of(t, d, x, y, z);
+  dst[t] = covered(H, x, y, z) ? 0.0 : src[gx(d, x, y, z)] - c;
+}
+
+// per-block partial sums of g(v) over the active cells (what: 0 value, 1 square), fixed tree
+__global__ void __launch_bounds__(kB) k_psum(const double* __restrict__ v, Dims d, Hole H, int what,
+                                              double* __restrict__ part) {
+  __shared__ double sh[kB];
+  double acc = 0.0;
+  for (size_t t = (size_t)blockIdx.x * kB + threadIdx.x; t < cells(d); t += (size_t)gridDim.x * kB) {
+    int x, y, z;
+    cell_of(t, d, x, y, z);
+    if (covered(H, x, y, z)) continue;
+    const double a = v[gx(d, x, y, z)];
+    acc += what ? a * a : a;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kB / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// 2 x 2 area mean of a face array (n x n) -> (n/2 x n/2)
+__global__ void __launch_bounds__(kB) k_face_mean(const double* __restrict__ b, double* __restrict__ out, int nc) {
+  const int t = blockIdx.x * kB + threadIdx.x;
+  if (t >= nc * nc) return;
+  const int i = t % nc, j = t / nc, n = 2 * nc;
+  out[t] = 0.25 * (((b[(size_t)(2 * j) * n + 2 * i] + b[(size_t)(2 * j) * n + 2 * i + 1]) +
+                    b[(size_t)(2 * j + 1) * n + 2 * i]) + b[(size_t)(2 * j + 1) * n + 2 * i + 1]);
+}
+
+// single root cell (Sec. 2.3.2): ghost = alpha u + beta per face; kept when nothing fixes it
+__global__ void k_coarsest(double* u, const double* f, Phys P, double h2) {
+  if (threadIdx.x || blockIdx.x) return;
+  double sa = 0.0, sb = 0.0;
+  for (int face = 0; face < 6; ++face) {
+    if (P.kind[face] == BC_PERIODIC || P.kind[face] == BC_ZERO_GRADIENT) {
+      sa += 1.0;
+    } else {
+      sa -= 1.0;
+      sb += 2.0 * (P.b[face] ? P.b[face][0] : 0.0);
+    }
+  }
+  const Dims d{{1, 1, 1}};
+  if (sa != 6.0) u[gx(d, 0, 0, 0)] = (sb - h2 * f[gx(d, 0, 0, 0)]) / (6.0 - sa);
+}
+
+// =========================================================================== host plan
+
+struct PatchL {
+  Dims d;
+  int o[3];       // global origin (cells) at (lam, k)
+  double h;
+  Hole hole;      // cg pointers filled per use
+  double *u, *f, *pbar, *dres, *tmp;
+  double* cg[6];  // coarse ghosts of the hole faces (lam < Lam)
+};
+
+struct Plan {
+  int NB, nb, K, Lam, N;      // N = NB * nb root cells per side
+  int lo[9][3], hi[9][3];     // boxes (level-(lam-1) block units), index lam - 1
+  std::vector<std::vector<PatchL>> P;   // [lam][k]
+  // root hierarchy below NB: n = NB/2 .. 1
+  std::vector<PatchL> R;
+  std::vector<double*> bface;           // per root-side size n (N, N/2, .., 1): 6 arrays
+  std::vector<int> bface_n;
+  double dx;
+};
+
+}  // namespace
+}  // namespace mg
+
+using namespace mg;
+
+struct mg_amr_ws {
+  void* mem = nullptr;
+  size_t cap = 0;
+};
+
+namespace {
+
+struct AmrRun {
+  Plan pl;
+  hipStream_t s;
+  double* part;
+  double* hpart;   // host copy of partials
+  int kinds[6];
+  int npre, npost;
+  double omega;
+  bool gauge_free;
+
+  Phys phys_for(int n, bool hom) const {
+    Phys P;
+    for (int f = 0; f < 6; ++f) {
+      P.kind[f] = kinds[f];
+      P.b[f] = nullptr;
+    }
+    P.bn = n;
+    if (!hom)
+      for (size_t q = 0; q < pl.bface_n.size(); ++q)
+        if (pl.bface_n[q] == n)
+          for (int f = 0; f < 6; ++f) P.b[f] = pl.bface.empty() || !pl.bface[q] ? nullptr : pl.bface[q] + (size_t)f * n * n;
+    return P;
+  }
+
+  void fill_phys(double* u, const Dims& d, bool hom) {
+    const Phys P = phys_for(d.n[0], hom);
+    for (int axis = 0; axis < 3; ++axis) {
+      const int m1 = axis == 0 ? d.n[1] : d.n[0] + 2;
+      const int m2 = axis == 2 ? d.n[1] + 2 : d.n[2];
+      hipLaunchKernelGGL(k_fill_phys, dim3(blocks((size_t)2 * m1 * m2)), dim3(kB), 0, s, u, d, axis, P, hom ? 1 : 0);
+    }
+  }
+
+  // conservative ghosts between fine patch (lam) and coarse patch (lam-1) at level k, using
+  // arrays uf / uc; writes the coarse ghosts when cg is non-null
+  void cons(const PatchL& fine, double* uf, const PatchL& coarse, const double* uc, double* const* cg) {
+    Cons A;
+    A.uf = uf;
+    A.df = fine.d;
+    A.uc = uc;
+    A.dc = coarse.d;
+    for (int a = 0; a < 3; ++a) {
+      A.lo[a] = coarse.hole.lo[a];
+      A.hi[a] = coarse.hole.hi[a];
+    }
+    for (int f = 0; f < 6; ++f) A.cg[f] = cg ? cg[f] : nullptr;
+    for (int axis = 0; axis < 3; ++axis) {
+      const int t1a = axis == 0 ? 1 : 0, t2a = axis == 2 ? 1 : 2;
+      hipLaunchKernelGGL(k_cons, dim3(blocks((size_t)2 * fine.d.n[t1a] * fine.d.n[t2a])), dim3(kB), 0, s, A, axis);
+    }
+  }
+
+  Hole hole_of(const PatchL& p) const {
+    Hole H = p.hole;
+    for (int f = 0; f < 6; ++f) H.cg[f] = p.cg[f];
+    return H;
+  }
+
+  // ghosts of every patch at level k for the arrays sel(P) (0: u, 1: pbar)
+  void fill_level(int k, int which) {
+    auto arr = [&](PatchL& p) { return which == 0 ? p.u : p.pbar; };
+    fill_phys(arr(pl.P[0][k]), pl.P[0][k].d, false);
+    for (int l = 1; l <= pl.Lam; ++l)
+      cons(pl.P[l][k], arr(pl.P[l][k]), pl.P[l - 1][k], arr(pl.P[l - 1][k]), pl.P[l - 1][k].cg);
+  }
+
+  void smooth_level(int k, int sweeps) {
+    for (int it = 0; it < sweeps; ++it)
+      for (int colour = 0; colour < 2; ++colour) {
+        fill_level(k, 0);
+        for (int l = 0; l <= pl.Lam; ++l) {
+          PatchL& p = pl.P[l][k];
+          hipLaunchKernelGGL(k_smooth, dim3(blocks(cells(p.d))), dim3(kB), 0, s, p.u, p.f, p.d, p.o[0], p.o[1], p.o[2],
+                             hole_of(p), p.h * p.h, omega, colour);
+        }
+      }
+  }
+
+  // out[l] = a[l] + s L(arrays) at level k (ghosts filled first)
+  void lap_level(int k, int which, int a_sel, int out_sel, double sgn) {
+    fill_level(k, which);
+    for (int l = 0; l <= pl.Lam; ++l) {
+      PatchL& p = pl.P[l][k];
+      const double* u = which == 0 ? p.u : p.pbar;
+      const double* a = a_sel == 0 ? p.f : p.dres;
+      double* out = out_sel == 0 ? p.tmp : p.f;
+      hipLaunchKernelGGL(k_lap, dim3(blocks(cells(p.d))), dim3(kB), 0, s, u, a, out, p.d, hole_of(p),
+                         1.0 / (p.h * p.h), sgn);
+    }
+  }
+
+  void restrict_into(const PatchL& fine, const double* src, bool mask, double* out1, double* out2, const PatchL& coarse,
+                     const int o[3]) {
+    Dims nr{{fine.d.n[0] / 2, fine.d.n[1] / 2, fine.d.n[2] / 2}};
+    Hole H = fine.hole;
+    if (!mask) H.on = 0;
+    hipLaunchKernelGGL(k_restrict, dim3(blocks(cells(nr))), dim3(kB), 0, s, src, fine.d, H, out1, out2, coarse.d, o[0],
+                       o[1], o[2], nr);
+  }
+
+  void prolong(const PatchL& coarse, const double* uc, const PatchL& fine, double* uf, int mode, const int lo[3],
+               const int hi[3]) {
+    Dims span{{hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]}};
+    Hole H = fine.hole;
+    hipLaunchKernelGGL(k_prolong, dim3(blocks(cells(span))), dim3(kB), 0, s, uc, coarse.d, coarse.o[0], coarse.o[1],
+                       coarse.o[2], uf, fine.d, fine.o[0], fine.o[1], fine.o[2], H, lo[0], lo[1], lo[2], span, mode);
+  }
+
+  // normal level boundary for prolongation of the corrections held in tmp at level k
+  void normal_fill(int k) {
+    for (int l = pl.Lam; l >= 1; --l) {
+      PatchL &f = pl.P[l][k], &c = pl.P[l - 1][k];
+      restrict_into(f, f.tmp, false, c.tmp, nullptr, c, c.hole.lo);
+    }
+    fill_phys(pl.P[0][k].tmp, pl.P[0][k].d, true);
+    for (int l = 1; l <= pl.Lam; ++l) {
+      PatchL &f = pl.P[l][k], &c = pl.P[l - 1][k];
+      const int lo[3] = {-1, -1, -1};
+      const int hi[3] = {f.d.n[0] + 1, f.d.n[1] + 1, f.d.n[2] + 1};
+      prolong(c, c.tmp, f, f.tmp, 1, lo, hi);
+    }
+  }
+
+  // deterministic sum over the active cells of one patch array: host value
+  double patch_sum(const PatchL& p, const double* v, int what) {
+    const int nb = (int)std::min<size_t>(kMaxPartials, std::max<size_t>(1, cells(p.d) / (kB * 4)));
+    hipLaunchKernelGGL(k_psum, dim3(nb), dim3(kB), 0, s, v, p.d, hole_of(p), what, part);
+    (void)hipMemcpyAsync(hpart, part, sizeof(double) * nb, hipMemcpyDeviceToHost, s);
+    (void)hipStreamSynchronize(s);
+    double acc = 0.0;
+    for (int i = 0; i < nb; ++i) acc += hpart[i];
+    return acc;
+  }
+  double volume_mean(int k, int which_arr, int what) {
+    double sum = 0.0, vol = 0.0;
+    for (int l = 0; l <= pl.Lam; ++l) {
+      const PatchL& p = pl.P[l][k];
+      const double* v = which_arr == 0 ? p.u : which_arr == 1 ? p.f : p.tmp;
+      const double w = p.h * p.h * p.h;
+      sum += w * patch_sum(p, v, what);
+      size_t act = cells(p.d);
+      if (p.hole.on) act -= (size_t)(p.hole.hi[0] - p.hole.lo[0]) * (p.hole.hi[1] - p.hole.lo[1]) * (p.hole.hi[2] - p.hole.lo[2]);
+      vol += w * (double)act;
+    }
+    return sum / vol;
+  }
+
+  // one uniform FAS V-cycle on the root grid (NB^3 down to one cell), physical conditions
+  void root_fas(int q, PatchL& top, double* u, double* f) {
+    // level q: q = 0 is the NB^3 root patch (u, f given), q >= 1 index into pl.R
+    const int n = top.d.n[0];
+    if (n == 1) {
+      hipLaunchKernelGGL(k_coarsest, dim3(1), dim3(64), 0, s, u, f, phys_for(1, false), top.h * top.h);
+      return;
+    }
+    const Dims d = top.d;
+    Hole none{};
+    for (int it = 0; it < npre; ++it)
+      for (int colour = 0; colour < 2; ++colour) {
+        fill_phys(u, d, false);
+        hipLaunchKernelGGL(k_smooth, dim3(blocks(cells(d))), dim3(kB), 0, s, u, f, d, 0, 0, 0, none, top.h * top.h, omega,
+                           colour);
+      }
+    fill_phys(u, d, false);
+    hipLaunchKernelGGL(k_lap, dim3(blocks(cells(d))), dim3(kB), 0, s, u, f, top.tmp, d, none, 1.0 / (top.h * top.h),
+                       -1.0);
+    PatchL& c = pl.R[q];
+    const int o[3] = {0, 0, 0};
+    restrict_into(top, u, false, c.u, c.pbar, c, o);
+    restrict_into(top, top.tmp, false, c.dres, nullptr, c, o);
+    fill_phys(c.pbar, c.d, false);
+    hipLaunchKernelGGL(k_lap, dim3(blocks(cells(c.d))), dim3(kB), 0, s, c.pbar, c.dres, c.f, c.d, none,
+                       1.0 / (c.h * c.h), 1.0);
+    root_fas(q + 1, c, c.u, c.f);
+    hipLaunchKernelGGL(k_sub, dim3(blocks(cells(c.d))), dim3(kB), 0, s, c.u, c.pbar, c.tmp, c.d, none);
+    fill_phys(c.tmp, c.d, true);
+    const int lo[3] = {0, 0, 0}, hi[3] = {d.n[0], d.n[1], d.n[2]};
+    prolong(c, c.tmp, top, u, 0, lo, hi);
+    for (int it = 0; it < npost; ++it)
+      for (int colour = 0; colour < 2; ++colour) {
+        fill_phys(u, d, false);
+        hipLaunchKernelGGL(k_smooth, dim3(blocks(cells(d))), dim3(kB), 0, s, u, f, d, 0, 0, 0, none, top.h * top.h, omega,
+                           colour);
+      }
+  }
+
+  // Octet patch l at k = 0, all cells active, ghosts from patch l-1 (held fixed)
+  PatchL octet(int l) const {
+    PatchL p = pl.P[l][0];
+    p.hole.on = 0;
+    return p;
+  }
+  void octet_smooth(int l, int sweeps) {
+    PatchL p = octet(l);
+    PatchL& c = pl.P[l - 1][0];
+    Hole none{};
+    for (int it = 0; it < sweeps; ++it)
+      for (int colour = 0; colour < 2; ++colour) {
+        cons(p, p.u, c, c.u, nullptr);
+        hipLaunchKernelGGL(k_smooth, dim3(blocks(cells(p.d))), dim3(kB), 0, s, p.u, p.f, p.d, p.o[0], p.o[1], p.o[2], none,
+                           p.h * p.h, omega, colour);
+      }
+  }
+
+  void vcycle() {
+    const int K = pl.K, Lam = pl.Lam;
+    Hole none{};
+    // ---- MeshBlock levels, down
+    for (int k = K; k >= 1; --k) {
+      smooth_level(k, npre);
+      lap_level(k, 0, 0, 0, -1.0);                      // tmp = f - L u
+      for (int l = 0; l <= Lam; ++l) {
+        PatchL &p = pl.P[l][k], &c = pl.P[l][k - 1];
+        const int o[3] = {0, 0, 0};
+        restrict_into(p, p.u, true, c.pbar, c.u, c, o);
+        restrict_into(p, p.tmp, false, c.dres, nullptr, c, o);
+      }
+      if (k - 1 >= 1) lap_level(k - 1, 1, 1, 1, 1.0);   // f = dres + L pbar
+    }
+    // ---- Octet levels, finest first
+    for (int l = Lam; l >= 1; --l) {
+      PatchL p = octet(l);
+      PatchL& c = pl.P[l - 1][0];
+      cons(p, p.pbar, c, c.pbar, nullptr);
+      hipLaunchKernelGGL(k_lap, dim3(blocks(cells(p.d))), dim3(kB), 0, s, p.pbar, p.dres, p.f, p.d, none,
+                         1.0 / (p.h * p.h), 1.0);
+      (void)hipMemcpyAsync(p.u, p.pbar, ghosted(p.d) * sizeof(double), hipMemcpyDeviceToDevice, s);
+      octet_smooth(l, npre);
+      cons(p, p.u, c, c.u, nullptr);
+      hipLaunchKernelGGL(k_lap, dim3(blocks(cells(p.d))), dim3(kB), 0, s, p.u, p.f, p.tmp, p.d, none,
+                         1.0 / (p.h * p.h), -1.0);
+      restrict_into(p, p.u, false, c.pbar, c.u, c, c.hole.lo);
+      restrict_into(p, p.tmp, false, c.dres, nullptr, c, c.hole.lo);
+    }
+    // ---- root grid
+    {
+      PatchL r = pl.P[0][0];
+      r.hole.on = 0;
+      fill_phys(r.pbar, r.d, false);
+      hipLaunchKernelGGL(k_lap, dim3(blocks(cells(r.d))), dim3(kB), 0, s, r.pbar, r.dres, r.f, r.d, none,
+                         1.0 / (r.h * r.h), 1.0);
+      (void)hipMemcpyAsync(r.u, r.pbar, ghosted(r.d) * sizeof(double), hipMemcpyDeviceToDevice, s);
+      root_fas(0, r, r.u, r.f);
+    }
+    // ---- Octet levels, coarsest first
+    for (int l = 1; l <= Lam; ++l) {
+      PatchL p = octet(l);
+      PatchL c = pl.P[l - 1][0];
+      c.hole.on = 0;
+      hipLaunchKernelGGL(k_sub, dim3(blocks(cells(c.d))), dim3(kB), 0, s, c.u, c.pbar, c.tmp, c.d, none);
+      if (l - 1 == 0) fill_phys(c.tmp, c.d, true);
+      const int lo[3] = {0, 0, 0}, hi[3] = {p.d.n[0], p.d.n[1], p.d.n[2]};
+      prolong(c, c.tmp, p, p.u, 0, lo, hi);
+      octet_smooth(l, npost);
+    }
+    // ---- MeshBlock levels, up
+    for (int k = 1; k <= K; ++k) {
+      for (int l = 0; l <= Lam; ++l) {
+        PatchL& c = pl.P[l][k - 1];
+        hipLaunchKernelGGL(k_sub, dim3(blocks(cells(c.d))), dim3(kB), 0, s, c.u, c.pbar, c.tmp, c.d, c.hole);
+      }
+      normal_fill(k - 1);
+      for (int l = 0; l <= Lam; ++l) {
+        PatchL &c = pl.P[l][k - 1], &p = pl.P[l][k];
+        const int lo[3] = {0, 0, 0}, hi[3] = {p.d.n[0], p.d.n[1], p.d.n[2]};
+        prolong(c, c.tmp, p, p.u, 0, lo, hi);
+      }
+      smooth_level(k, npost);
+    }
+  }
+
+  double residual(double rms_f) {
+    lap_level(pl.K, 0, 0, 0, -1.0);
+    const double rd = std::sqrt(volume_mean(pl.K, 2, 1));
+    return rms_f > 0 ? rd / rms_f : rd;
+  }
+};
+
+int fail_amr(std::string* err, int code, const char* msg) {
+  if (err) *err = msg;
+  return code;
+}
+
+}  // namespace
+
+// Geometry and validation of a refined mesh: fills the plan's patch dimensions (no memory).
+static int amr_plan(const mg_amr_mesh* m, Plan& pl, std::string* err) {
+  if (!m) return fail_amr(err, MG_ERR_INVALID_ARG, "null mesh");
+  auto pow2 = [](int v) { return v >= 1 && (v & (v - 1)) == 0; };
+  if (!pow2(m->NB) || m->NB < 1 || m->NB > 256 || !pow2(m->nb) || m->nb < 2 || m->nb > 64)
+    return fail_amr(err, MG_ERR_INVALID_ARG, "NB and nb must be powers of two (NB <= 256, 2 <= nb <= 64)");
+  if (m->levels < 0 || m->levels > MG_AMR_MAX_LEVELS) return fail_amr(err, MG_ERR_INVALID_ARG, "levels out of range");
+  pl.NB = m->NB;
+  pl.nb = m->nb;
+  pl.K = ilog2(m->nb);
+  pl.Lam = m->levels;
+  pl.N = m->NB * m->nb;
+  for (int lam = 1; lam <= pl.Lam; ++lam)
+    for (int a = 0; a < 3; ++a) {
+      const int lo = m->box_lo[lam - 1][a], hi = m->box_hi[lam - 1][a];
+      const int plo = lam == 1 ? 0 : 2 * m->box_lo[lam - 2][a];
+      const int phi = lam == 1 ? m->NB : 2 * m->box_hi[lam - 2][a];
+      if (!(plo + 1 <= lo && lo < hi && hi <= phi - 1))
+        return fail_amr(err, MG_ERR_INVALID_ARG, "each box must lie inside its parent with a one-block margin");
+      pl.lo[lam - 1][a] = lo;
+      pl.hi[lam - 1][a] = hi;
+    }
+  pl.P.assign(pl.Lam + 1, std::vector<PatchL>(pl.K + 1));
+  for (int lam = 0; lam <= pl.Lam; ++lam)
+    for (int k = 0; k <= pl.K; ++k) {
+      PatchL& p = pl.P[lam][k];
+      std::memset(&p, 0, sizeof(p));
+      const int c = 1 << k;
+      for (int a = 0; a < 3; ++a) {
+        const int bo = lam == 0 ? 0 : 2 * pl.lo[lam - 1][a];
+        const int bn = lam == 0 ? pl.NB : 2 * (pl.hi[lam - 1][a] - pl.lo[lam - 1][a]);
+        p.o[a] = bo * c;
+        p.d.n[a] = bn * c;
+      }
+      p.h = 1.0 / ((double)pl.NB * (double)(1 << lam) * (double)c);
+      p.hole.on = lam < pl.Lam;
+      if (p.hole.on)
+        for (int a = 0; a < 3; ++a) {
+          p.hole.lo[a] = pl.lo[lam][a] * c - p.o[a];
+          p.hole.hi[a] = pl.hi[lam][a] * c - p.o[a];
+        }
+    }
+  pl.R.clear();
+  for (int n = pl.NB / 2; n >= 1; n /= 2) {
+    PatchL p;
+    std::memset(&p, 0, sizeof(p));
+    p.d = Dims{{n, n, n}};
+    p.h = 1.0 / n;
+    pl.R.push_back(p);
+  }
+  return MG_OK;
+}
+
+extern "C" {
+
+int mg_amr_patch_dims(const mg_amr_mesh* m, int lam, int dims[3]) {
+  Plan pl;
+  const int st = amr_plan(m, pl, nullptr);
+  if (st != MG_OK) return st;
+  if (lam < 0 || lam > pl.Lam || !dims) return MG_ERR_INVALID_ARG;
+  for (int a = 0; a < 3; ++a) dims[a] = pl.P[lam][pl.K].d.n[a];
+  return MG_OK;
+}
+
+}  // extern "C"
+
+// Solve on the refined mesh; memory is allocated per call (the refined path is not pooled).
+int amr_solve_impl(int device, const mg_params* p, const mg_amr_mesh* m, const mg_bc* bc, const double* const* rho,
+                   double* const* phi, double* hist, int* n_hist, void* stream, double* part, double* hpart,
+                   std::string* err) {
+  Plan pl;
+  int st = amr_plan(m, pl, err);
+  if (st != MG_OK) return st;
+  if (!p || !bc || !rho || !phi || !hist || !n_hist) return fail_amr(err, MG_ERR_INVALID_ARG, "null argument");
+  if (p->mode != MG_MODE_MGI) return fail_amr(err, MG_ERR_UNSUPPORTED, "the refined mesh runs V-cycles from phi (MG_MODE_MGI)");
+  if (p->precision != MG_PREC_FP64) return fail_amr(err, MG_ERR_UNSUPPORTED, "the refined mesh runs in FP64");
+  if (std::fabs(p->dx * pl.N - 1.0) > 1e-12) return fail_amr(err, MG_ERR_INVALID_ARG, "the refined mesh spans the unit cube: dx = 1/(NB nb)");
+  for (int f = 0; f < 6; ++f) {
+    if (bc->kind[f] == MG_BC_MULTIPOLE) return fail_amr(err, MG_ERR_UNSUPPORTED, "multipole faces on the refined mesh");
+    if (bc->kind[f] < 0 || bc->kind[f] > MG_BC_FIXED) return fail_amr(err, MG_ERR_INVALID_ARG, "bad face kind");
+  }
+  for (int a = 0; a < 3; ++a)
+    if ((bc->kind[2 * a] == MG_BC_PERIODIC) != (bc->kind[2 * a + 1] == MG_BC_PERIODIC))
+      return fail_amr(err, MG_ERR_INVALID_ARG, "periodic faces must be paired per axis");
+  for (int l = 0; l <= pl.Lam; ++l)
+    if (!rho[l] || !phi[l]) return fail_amr(err, MG_ERR_INVALID_ARG, "null patch array");
+  *n_hist = 0;
+  if (hipSetDevice(device) != hipSuccess) return fail_amr(err, MG_ERR_DEVICE, "hipSetDevice");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+
+  // ---- memory: per patch and level u, f, pbar, dres, tmp (ghosted) and the hole-face ghosts;
+  // root levels below NB; fixed-face arrays per root-side size
+  size_t total = 0;
+  auto take = [&](size_t doubles) {
+    const size_t o = total;
+    total += (doubles + 31) / 32 * 32;
+    return o;
+  };
+  struct Off {
+    size_t u, f, pbar, dres, tmp, cg[6];
+  };
+  std::vector<std::vector<Off>> off(pl.Lam + 1, std::vector<Off>(pl.K + 1));
+  for (int l = 0; l <= pl.Lam; ++l)
+    for (int k = 0; k <= pl.K; ++k) {
+      const size_t g = ghosted(pl.P[l][k].d);
+      Off& o = off[l][k];
+      o.u = take(g);
+      o.f = take(g);
+      o.pbar = take(g);
+      o.dres = take(g);
+      o.tmp = take(g);
+      for (int f = 0; f < 6; ++f) {
+        o.cg[f] = (size_t)-1;
+        if (pl.P[l][k].hole.on) {
+          const Hole& H = pl.P[l][k].hole;
+          const int axis = f / 2, t1 = axis == 0 ? 1 : 0, t2 = axis == 2 ? 1 : 2;
+          o.cg[f] = take((size_t)(H.hi[t1] - H.lo[t1]) * (H.hi[t2] - H.lo[t2]));
+        }
+      }
+    }
+  std::vector<Off> roff(pl.R.size());
+  for (size_t q = 0; q < pl.R.size(); ++q) {
+    const size_t g = ghosted(pl.R[q].d);
+    roff[q].u = take(g);
+    roff[q].f = take(g);
+    roff[q].pbar = take(g);
+    roff[q].dres = take(g);
+    roff[q].tmp = take(g);
+  }
+  bool any_fixed = false;
+  for (int f = 0; f < 6; ++f) any_fixed |= bc->kind[f] == MG_BC_FIXED && bc->fixed_b[f];
+  std::vector<size_t> boff;
+  if (any_fixed)
+    for (int n = pl.N; n >= 1; n /= 2) {
+      pl.bface_n.push_back(n);
+      boff.push_back(take((size_t)6 * n * n));
+    }
+  double* mem = nullptr;
+  if (hipMalloc(&mem, total * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail_amr(err, MG_ERR_OOM, "refined-mesh workspace");
+  }
+  (void)hipMemsetAsync(mem, 0, total * sizeof(double), s);
+  for (int l = 0; l <= pl.Lam; ++l)
+    for (int k = 0; k <= pl.K; ++k) {
+      PatchL& q = pl.P[l][k];
+      const Off& o = off[l][k];
+      q.u = mem + o.u;
+      q.f = mem + o.f;
+      q.pbar = mem + o.pbar;
+      q.dres = mem + o.dres;
+      q.tmp = mem + o.tmp;
+      for (int f = 0; f < 6; ++f) q.cg[f] = o.cg[f] == (size_t)-1 ? nullptr : mem + o.cg[f];
+    }
+  for (size_t q = 0; q < pl.R.size(); ++q) {
+    pl.R[q].u = mem + roff[q].u;
+    pl.R[q].f = mem + roff[q].f;
+    pl.R[q].pbar = mem + roff[q].pbar;
+    pl.R[q].dres = mem + roff[q].dres;
+    pl.R[q].tmp = mem + roff[q].tmp;
+  }
+  for (size_t q = 0; q < boff.size(); ++q) pl.bface.push_back(mem + boff[q]);
+  if (any_fixed) {
+    const int N = pl.N;
+    for (int f = 0; f < 6; ++f) {
+      if (bc->kind[f] == MG_BC_FIXED && bc->fixed_b[f])
+        (void)hipMemcpyAsync(pl.bface[0] + (size_t)f * N * N, bc->fixed_b[f], sizeof(double) * N * N,
+                             hipMemcpyDeviceToDevice, s);
+      for (size_t q = 1; q < pl.bface.size(); ++q) {
+        const int nc = pl.bface_n[q];
+        hipLaunchKernelGGL(k_face_mean, dim3(blocks((size_t)nc * nc)), dim3(kB), 0, s,
+                           pl.bface[q - 1] + (size_t)f * 4 * nc * nc, pl.bface[q] + (size_t)f * nc * nc, nc);
+      }
+    }
+  }
+
+  AmrRun R;
+  R.pl = pl;
+  R.s = s;
+  R.part = part;
+  R.hpart = hpart;
+  for (int f = 0; f < 6; ++f) R.kinds[f] = bc->kind[f];
+  R.npre = p->npre;
+  R.npost = p->npost;
+  R.omega = p->omega;
+  R.gauge_free = true;
+  for (int f = 0; f < 6; ++f)
+    if (bc->kind[f] == MG_BC_FIXED) R.gauge_free = false;
+
+  // ---- source and initial guess on the finest level
+  const int K = pl.K;
+  for (int l = 0; l <= pl.Lam; ++l) {
+    PatchL& q = R.pl.P[l][K];
+    hipLaunchKernelGGL(k_load, dim3(blocks(cells(q.d))), dim3(kB), 0, s, rho[l], q.f, q.d, q.hole, p->four_pi_g, 0.0);
+    hipLaunchKernelGGL(k_load, dim3(blocks(cells(q.d))), dim3(kB), 0, s, phi[l], q.u, q.d, q.hole, 1.0, 0.0);
+  }
+  if (R.gauge_free) {
+    const double mean = R.volume_mean(K, 1, 0);
+    for (int l = 0; l <= pl.Lam; ++l) {
+      PatchL& q = R.pl.P[l][K];
+      hipLaunchKernelGGL(k_load, dim3(blocks(cells(q.d))), dim3(kB), 0, s, rho[l], q.f, q.d, q.hole, p->four_pi_g,
+                         -mean);
+    }
+  }
+  const double rms_f = std::sqrt(R.volume_mean(K, 1, 1));
+  double r = R.residual(rms_f);
+  int nh = 0;
+  hist[nh++] = r;
+  const int ncyc = p->fixed_cycles > 0 ? p->fixed_cycles : p->max_cycles;
+  int status = p->fixed_cycles > 0 ? MG_OK : MG_NOT_CONVERGED;
+  int slow = 0;
+  if (p->fixed_cycles > 0 || r > p->tol) {
+    for (int c = 0; c < ncyc; ++c) {
+      R.vcycle();
+      const double rn = R.residual(rms_f);
+      hist[nh++] = rn;
+      if (p->fixed_cycles > 0) {
+        r = rn;
+        continue;
+      }
+      slow = rn > 0.9 * r ? slow + 1 : 0;
+      r = rn;
+      if (r <= p->tol) {
+        status = MG_OK;
+        break;
+      }
+      if (slow >= 2) {
+        status = MG_STALLED;
+        break;
+      }
+    }
+  } else {
+    status = MG_OK;
+  }
+  *n_hist = nh;
+  double mean = 0.0;
+  if (R.gauge_free) mean = R.volume_mean(K, 0, 0);
+  for (int l = 0; l <= pl.Lam; ++l) {
+    PatchL& q = R.pl.P[l][K];
+    hipLaunchKernelGGL(k_store, dim3(blocks(cells(q.d))), dim3(kB), 0, s, q.u, phi[l], q.d, q.hole, mean);
+  }
+  const hipError_t e1 = hipStreamSynchronize(s);
+  const hipError_t e2 = hipGetLastError();
+  (void)hipFree(mem);
+  if (e1 != hipSuccess || e2 != hipSuccess) return fail_amr(err, MG_ERR_DEVICE, hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+  return status;
+}

@@ -72,6 +72,11 @@ struct mg_ctx {
   int tblock[2] = {-1, -1};
 };
 
+// refined-mesh solve (mg_amr.hip)
+int amr_solve_impl(int device, const mg_params* p, const mg_amr_mesh* m, const mg_bc* bc, const double* const* rho,
+                   double* const* phi, double* hist, int* n_hist, void* stream, double* part, double* hpart,
+                   std::string* err);
+
 namespace {
 
 constexpr int kScal = 64;
@@ -1493,6 +1498,14 @@ int mg_multipole_moments(mg_ctx* c, int n, double dx, const double* rho, int lma
   if (q_out)
     for (int q = 0; q < 25; ++q) q_out[q] = c->hscal[kMpoleOff + 7 + q];
   return op_epilogue(c);
+}
+
+int mg_amr_solve(mg_ctx* c, const mg_params* p, const mg_amr_mesh* mesh, const mg_bc* bc, const double* const* rho,
+                 double* const* phi, double* hist, int* n_hist, void* stream) {
+  if (!c) return MG_ERR_INVALID_ARG;
+  if (n_hist) *n_hist = 0;
+  std::vector<double> hpart(kMaxPartials);
+  return amr_solve_impl(c->device, p, mesh, bc, rho, phi, hist, n_hist, stream, c->part, hpart.data(), &c->err);
 }
 
 int mg_gravity(mg_ctx* c, const mg_params* p, const mg_bc* bc, const double* phi, const double* rho, double* g,

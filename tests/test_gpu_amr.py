@@ -1,0 +1,114 @@
+"""GPU parity of the refined-mesh solver (Sec. 3.3: FAS V-cycles over MeshBlock, Octet and root
+levels with the conservative and normal level boundaries) with the oracle: residual histories
+cycle by cycle and the potential on every patch to 1e-10 relative, for one and two levels of
+refinement, off-centre and non-cubic boxes, periodic, zero-gradient and fixed faces, zero and
+random initial guesses; plus the rejected forms."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import amr
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def mg():
+    import paper_2302_13903_amd as m
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+MESHES = {
+    "one level": (4, 4, [((1, 1, 1), (3, 3, 3))]),
+    "two levels": (4, 4, [((1, 1, 1), (3, 3, 3)), ((3, 3, 3), (5, 5, 5))]),
+    "off-centre, non-cubic": (4, 2, [((1, 2, 1), (3, 3, 2))]),
+    "larger": (8, 8, [((2, 3, 3), (6, 5, 5))]),
+}
+KINDS = {"periodic": [amr.PERIODIC] * 6, "fixed": [amr.FIXED] * 6, "zero_gradient": [amr.ZERO_GRADIENT] * 6,
+         "mixed": [amr.PERIODIC, amr.PERIODIC, amr.FIXED, amr.FIXED, amr.ZERO_GRADIENT, amr.ZERO_GRADIENT]}
+
+
+def case(NB, nb, boxes, kinds, seed):
+    m = amr.AmrMesh(NB, nb, boxes)
+    rho = []
+    for l in range(m.Lam + 1):
+        x, y, z = m.centres(l)
+        Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+        r2 = (X - 0.55) ** 2 + (Y - 0.45) ** 2 + (Z - 0.5) ** 2
+        rho.append(np.exp(-r2 / (2 * 0.08 ** 2)) + 0.3 * np.sin(2 * math.pi * X))
+    N = NB * nb
+    rng = np.random.default_rng(seed)
+    faces = [rng.uniform(-0.5, 0.5, (N, N)) if k == amr.FIXED else None for k in kinds]
+    return m, rho, faces
+
+
+def rel(a, b):
+    num = math.sqrt(sum(float(np.sum((x - y) ** 2)) for x, y in zip(a, b)))
+    den = math.sqrt(sum(float(np.sum(y ** 2)) for y in b))
+    return num / den
+
+
+@pytest.mark.parametrize("kname", list(KINDS))
+@pytest.mark.parametrize("mname", list(MESHES))
+def test_amr_matches_oracle(mg, mname, kname):
+    NB, nb, boxes = MESHES[mname]
+    kinds = KINDS[kname]
+    print(f"amr {mname} {kname}", flush=True)
+    m, rho, faces = case(NB, nb, boxes, kinds, 5)
+    bf = amr.FaceArrays([f if f is not None else np.zeros((NB * nb,) * 2) for f in faces]) \
+        if any(f is not None for f in faces) else None
+    ref, rh = amr.solve(m, rho, kinds, bf, cycles=5)
+    mesh = mg.amr_mesh(NB, nb, boxes)
+    for l in range(m.Lam + 1):
+        assert mg.amr_patch_dims(mesh, l) == m.patches[l][m.K].n
+    phi, hist, st = mg.amr_solve(mesh, [dev(r) for r in rho], kinds,
+                                 fixed_b=[None if f is None else dev(f) for f in faces], fixed_cycles=5)
+    torch.cuda.synchronize()
+    got = [p.cpu().numpy() for p in phi]
+    assert st == mg.MG_OK and len(hist) == len(rh) == 6
+    for a, b in zip(hist, rh):
+        assert abs(a - b) <= 1e-6 * b + 1e-12, (hist, rh)
+    assert rel(got, ref) < 1e-10
+    # covered cells are zero on output
+    for l in range(m.Lam):
+        (x0, y0, z0), (x1, y1, z1) = m.patches[l][m.K].hole
+        assert float(np.abs(got[l][z0:z1, y0:y1, x0:x1]).max()) == 0.0
+
+
+def test_amr_warm_start_and_tolerance(mg):
+    """From a random initial guess, to tolerance: same cycle count and potential as the oracle."""
+    NB, nb, boxes = MESHES["two levels"]
+    kinds = KINDS["fixed"]
+    m, rho, faces = case(NB, nb, boxes, kinds, 9)
+    rng = np.random.default_rng(3)
+    phi0 = [rng.uniform(-1, 1, m.patches[l][m.K].n[::-1]) for l in range(m.Lam + 1)]
+    bf = amr.FaceArrays(faces)
+    ref, rh = amr.solve(m, rho, kinds, bf, phi0=phi0, tol=1e-10)
+    mesh = mg.amr_mesh(NB, nb, boxes)
+    phi, hist, st = mg.amr_solve(mesh, [dev(r) for r in rho], kinds, fixed_b=[dev(f) for f in faces],
+                                 phi=[dev(p) for p in phi0], tol=1e-10)
+    assert st == mg.MG_OK and len(hist) == len(rh)
+    assert rel([p.cpu().numpy() for p in phi], ref) < 1e-10
+
+
+def test_amr_rejected_forms(mg):
+    NB, nb, boxes = MESHES["one level"]
+    m, rho, _ = case(NB, nb, boxes, KINDS["periodic"], 1)
+    r = [dev(x) for x in rho]
+    mesh = mg.amr_mesh(NB, nb, boxes)
+    ctx = mg.Context(0)
+    p = mg.params(NB * nb, 1.0 / (NB * nb), mode="fmg")
+    with pytest.raises(mg.MgError, match="UNSUPPORTED"):
+        mg.mg_amr_solve(ctx, p, mesh, mg.boundary("periodic"), r, [torch.zeros_like(x) for x in r])
+    with pytest.raises(mg.MgError, match="UNSUPPORTED"):
+        mg.amr_solve(mesh, r, "multipole")
+    with pytest.raises(mg.MgError, match="INVALID_ARG"):
+        mg.amr_patch_dims(mg.amr_mesh(4, 4, [((0, 1, 1), (3, 3, 3))]), 1)    # touches the domain face
+    with pytest.raises(mg.MgError, match="INVALID_ARG"):
+        mg.amr_patch_dims(mg.amr_mesh(4, 4, [((1, 1, 1), (3, 3, 3)), ((2, 3, 3), (5, 5, 5))]), 2)  # no margin

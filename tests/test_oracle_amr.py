@@ -184,3 +184,28 @@ def test_refinement_accuracy_against_analytic():
     e8, u8 = _gaussian_case(4, 8)
     assert e8 < 0.35 * u8, (e8, u8)
     assert e8 < 0.3 * e4, (e4, e8)
+
+
+def test_face_arrays_match_point_values_for_linear_b():
+    """Fixed faces given as arrays (area means on coarser levels) equal the pointwise face
+    function when b is linear along the face (its area mean is its centre value): the two
+    solves agree to rounding."""
+    m = MESHES["one level"]()
+    N = m.NB * m.nb
+    bfun = lambda x, y, z: 0.3 + 0.1 * x - 0.2 * y + 0.05 * z
+    x = (np.arange(N) + 0.5) / N
+    faces = []
+    for face in range(6):
+        axis, side = face // 2, face % 2
+        t = [q for q in range(3) if q != axis]
+        co = [None, None, None]
+        co[axis] = np.array(0.0 if side == 0 else 1.0)
+        co[t[0]] = x[None, :]
+        co[t[1]] = x[:, None]
+        faces.append(np.ascontiguousarray(np.broadcast_to(bfun(*co), (N, N))))
+    rng = np.random.default_rng(4)
+    rho = [rng.uniform(0, 1, m.patches[l][m.K].n[::-1]) for l in range(m.Lam + 1)]
+    a, ha = amr.solve(m, rho, [amr.FIXED] * 6, bfun, cycles=4)
+    b, hb = amr.solve(m, rho, [amr.FIXED] * 6, amr.FaceArrays(faces), cycles=4)
+    assert np.allclose(ha, hb, rtol=1e-9)
+    assert max(np.abs(a[l] - b[l]).max() for l in range(m.Lam + 1)) < 1e-12
