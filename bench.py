@@ -15,6 +15,8 @@ in HBM.  The JSON line reports:
   mixed         the same numbers for the mixed-precision solve; p50/p99 solve latency.
   fas           the same solve with Full Approximation Scheme iterations (Alg. 3): per-cycle
                 rate, its finest-level passes and the roofline of the dominant one;
+  amr           a refined mesh (256^3 root grid, central blocks refined once): FAS V-cycles to
+                1e-10, composite cells per second per cycle, the numpy oracle beside it;
   gravity       g = -grad phi and rho g of the solved potential (Sec. 2.4): mean launch time
                 and its HBM roofline (64 algorithmic bytes per cell), CPU oracle beside it;
   batched       the 256^3 lognormal field as 4096 MeshBlocks of 16^3 (autotuned), FP64 and
@@ -187,6 +189,78 @@ def gravity_leg(mg, ctx, rho, n: int, reps: int, with_cpu: bool):
     return out
 
 
+AMR_MESH = (16, 16, [((6, 6, 6), (10, 10, 10))])   # 256^3 root grid, central 4^3 blocks refined (128^3)
+
+
+def amr_patches(NB, nb, boxes, seed):
+    """Per-patch cell-centre axes and the clump density concentrated in the refined region."""
+    import numpy as np
+
+    import workloads as wl
+    rho = []
+    for lam in range(len(boxes) + 1):
+        c = 1.0 / (NB * nb * (1 << lam))
+        if lam == 0:
+            lo, n = (0, 0, 0), (NB * nb,) * 3
+        else:
+            blo, bhi = boxes[lam - 1]
+            lo = tuple(2 * blo[a] * nb for a in range(3))
+            n = tuple(2 * (bhi[a] - blo[a]) * nb for a in range(3))
+        ax = [(lo[a] + np.arange(n[a]) + 0.5) * c for a in range(3)]
+        rho.append(wl.clumps_on_axes(ax[0], ax[1], ax[2], seed))
+    return rho
+
+
+def amr_leg(mg, steps: int, seed: int, with_cpu: bool):
+    """Refined mesh (NEXT row of the paper's Sec. 3.3): 256^3 root grid of 16^3-cell MeshBlocks
+    with the central 4^3 blocks refined once (a 128^3 patch at twice the resolution), clumps
+    concentrated in the refined region, periodic, FAS V-cycles from zero to 1e-10.  The rate
+    counts the composite (active) cells per V-cycle."""
+    import torch
+    NB, nb, boxes = AMR_MESH
+    rho_h = amr_patches(NB, nb, boxes, seed)
+    rho = [torch.from_numpy(r).to("cuda:0") for r in rho_h]
+    mesh = mg.amr_mesh(NB, nb, boxes)
+    dof = sum(r.size for r in rho_h) - (4 * nb) ** 3
+    ctx = mg.Context(0)
+    lat, cyc = [], []
+    for it in range(1 + steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        phi, hist, st = mg.amr_solve(mesh, rho, "periodic", tol=1e-10, ctx=ctx)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) * 1e3
+        if st < 0 or hist[-1] > 1e-10:
+            raise RuntimeError(f"refined-mesh solve did not converge: {st}, {hist}")
+        if it > 0:
+            lat.append(dt)
+            cyc.append(len(hist) - 1)
+        print(f"# amr step {it - 1:+d}: {dt:.1f} ms, cycles {len(hist) - 1}, r = {hist[-1]:.2e}", file=sys.stderr,
+              flush=True)
+    ms_cycle = statistics.median(lat) / statistics.median(cyc)
+    out = {"workload": "256^3 root (16^3 blocks of 16^3), central 4^3 blocks refined once (128^3 patch), "
+                       "periodic clumps, FAS V(2,2) from zero to 1e-10",
+           "composite_cells": dof, "cycles_per_solve": cyc[-1], "solve_ms": statistics.median(lat),
+           "ms_per_cycle_incl_residual": ms_cycle, "value": dof / (ms_cycle * 1e-3) / 1e9,
+           "unit": "GDoF/s per V-cycle (composite cells)"}
+    if with_cpu:
+        import numpy as np
+
+        import oracle.amr as oamr
+        NBs, nbs, bxs = 8, 8, [((3, 3, 3), (5, 5, 5))]
+        m = oamr.AmrMesh(NBs, nbs, bxs)
+        st_o = oamr.AmrState(m, amr_patches(NBs, nbs, bxs, seed), [oamr.PERIODIC] * 6)
+        t0 = time.perf_counter()
+        st_o.vcycle()
+        dt = time.perf_counter() - t0
+        cells_o = sum(int(np.prod(m.patches[l][m.K].n)) for l in range(m.Lam + 1)) - (2 * nbs) ** 3
+        out["cpu_baseline"] = {"value": cells_o / dt / 1e9, "unit": "GDoF/s per V-cycle (composite cells)",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"one V-cycle of the numpy oracle on a 64^3 root grid with a 32^3 refined "
+                                         f"patch ({cells_o} cells), {dt * 1e3:.0f} ms"}
+    return out
+
+
 def batched_leg(steps: int, seed: int, n: int = 256, block_n: int = 16):
     """Configuration 4: the 256^3 lognormal field (exp of a Gaussian random field with
     P(k) ~ k^-4, mean removed, periodic) as 4096 MeshBlocks of 16^3 with autotuned block
@@ -297,6 +371,7 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true", help="skip the MeshBlock (4096 x 16^3) leg")
     ap.add_argument("--no-gravity", action="store_true", help="skip the g = -grad phi leg")
     ap.add_argument("--no-fas", action="store_true", help="skip the Full Approximation Scheme leg")
+    ap.add_argument("--no-amr", action="store_true", help="skip the refined-mesh leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device to device (reference for profiler byte counters)")
     args = ap.parse_args()
@@ -376,6 +451,8 @@ def main() -> int:
                                    "unit": "GB/s", "frac": domf["achieved_GBs"] / HBM_PEAK_GBS,
                                    "traffic": measured_traffic(domf["kernel"], n), "kernel": domf["kernel"],
                                    "passes": pf}}
+    if not args.no_amr:
+        out["amr"] = amr_leg(mg, 2, args.seed, not args.no_cpu_baseline)
     if not args.no_mixed:
         lat_m, cyc_m, hists_m, _ = run_solves(mg, ctx, rho, n, "mixed", args.steps, args.warmup, args.tol)
         tvm = statistics.median(cyc_m)

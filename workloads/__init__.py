@@ -112,6 +112,25 @@ def gaussian_clumps(n: int, seed: int, n_clumps: int = 64, background: float = 1
     return rho
 
 
+def clumps_on_axes(xs, ys, zs, seed: int, n_clumps: int = 32, centre=(0.5, 0.5, 0.5), spread: float = 0.08,
+                   wmin: float = 0.01, wmax: float = 0.03, background: float = 1.0) -> np.ndarray:
+    """Gaussian clumps concentrated around `centre` (centres normal with std `spread`, wrapped
+    into the unit box; widths U[wmin, wmax]; amplitudes LogNormal(0, 1)) plus a background,
+    evaluated on the tensor grid of the cell-centre axes xs, ys, zs (any resolution, so every
+    patch of a refined mesh samples the same field).  Periodic minimum-image distances.
+    Returns an array indexed [z][y][x]."""
+    rng = np.random.default_rng(seed)
+    centres = np.mod(rng.normal(centre, spread, size=(n_clumps, 3)), 1.0)
+    widths = rng.uniform(wmin, wmax, size=n_clumps)
+    amps = rng.lognormal(0.0, 1.0, size=n_clumps)
+    gx = np.stack([_periodic_gauss_1d(np.asarray(xs), float(centres[c, 0]), float(widths[c]), 1.0) for c in range(n_clumps)])
+    gy = np.stack([_periodic_gauss_1d(np.asarray(ys), float(centres[c, 1]), float(widths[c]), 1.0) for c in range(n_clumps)])
+    gz = np.stack([_periodic_gauss_1d(np.asarray(zs), float(centres[c, 2]), float(widths[c]), 1.0) for c in range(n_clumps)])
+    zc = (gz * amps[:, None]).T
+    yx = (gy[:, :, None] * gx[:, None, :]).reshape(n_clumps, len(ys) * len(xs))
+    return (zc @ yx).reshape(len(zs), len(ys), len(xs)) + background
+
+
 def uniform_sphere(n: int, seed: int, radius: float = 0.25, max_offset: float = 0.05,
                    density: float = 1.0, subcells: int = 10, length: float = 1.0):
     """Uniform sphere of the given radius centred at (L/2 + delta) with |delta| <= max_offset.
