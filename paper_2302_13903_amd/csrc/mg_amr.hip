@@ -44,6 +44,8 @@ __host__ __device__ inline size_t gx(const Dims& d, int x, int y, int z) {
 inline size_t ghosted(const Dims& d) { return (size_t)(d.n[0] + 2) * (d.n[1] + 2) * (d.n[2] + 2); }
 __host__ __device__ inline size_t cells(const Dims& d) { return (size_t)d.n[0] * d.n[1] * d.n[2]; }
 inline unsigned blocks(size_t work) { return (unsigned)std::max<size_t>(1, (work + kB - 1) / kB); }
+// work items of one colour of k_smooth (x-pairs when the x extent is even)
+inline size_t smooth_items(const Dims& d) { return (d.n[0] & 1) ? cells(d) : cells(d) / 2; }
 
 struct Hole {
   int on;
@@ -83,43 +85,66 @@ __device__ inline void cell_of(size_t t, const Dims& d, int& x, int& y, int& z) 
   z = (int)(t / ((size_t)d.n[0] * d.n[1]));
 }
 
-// ---- physical ghosts of the root patch, one axis per launch (x, then y over the x ghosts,
-// then z over both), Sec. 2.3.6; fixed faces read b (bn x bn, [t2][t1]) clamped to the face
+// ---- physical ghosts of the root patch (Sec. 2.3.6): filled axis by axis (x, then y over the
+// x ghosts, then z over both); fixed faces read b (bn x bn, [t2][t1]) clamped to the face
 struct Phys {
   int kind[6];
   const double* b[6];
   int bn;
 };
 
-__global__ void __launch_bounds__(kB) k_fill_phys(double* __restrict__ u, Dims d, int axis, Phys P, int hom) {
-  const int m1 = axis == 0 ? d.n[1] : d.n[0] + 2, off1 = axis == 0 ? 0 : -1;
-  const int m2 = axis == 2 ? d.n[1] + 2 : d.n[2], off2 = axis == 2 ? -1 : 0;
-  const size_t t = (size_t)blockIdx.x * kB + threadIdx.x;
-  if (t >= (size_t)2 * m1 * m2) return;
-  const int side = (int)(t / ((size_t)m1 * m2));
-  const int r = (int)(t % ((size_t)m1 * m2));
-  const int c1 = r % m1 + off1, c2 = r / m1 + off2;
-  const int na = d.n[axis];
-  const int g = side ? na : -1, a = side ? na - 1 : 0, o = side ? 0 : na - 1;
-  auto at = [&](int q) {
-    if (axis == 0) return gx(d, q, c1, c2);
-    if (axis == 1) return gx(d, c1, q, c2);
-    return gx(d, c1, c2, q);
-  };
-  const int face = 2 * axis + side;
-  const int kd = P.kind[face];
-  if (kd == BC_PERIODIC) {
-    u[at(g)] = u[at(o)];
-  } else if (kd == BC_ZERO_GRADIENT) {
-    u[at(g)] = u[at(a)];
+// All ghosts in one launch: every ghost cell is composed from an active cell by the face
+// rules in the order z, y, x (the last-filled axis outermost), value = s u + t, which is the
+// axis-by-axis fill written out; one thread per cell of the six ghost faces (edge and corner
+// cells are reached from two or three faces and written with the same value).
+__global__ void __launch_bounds__(kB) k_fill_phys1(double* __restrict__ u, Dims d, Phys P, int hom) {
+  const int n0 = d.n[0] + 2, n1 = d.n[1] + 2, n2 = d.n[2] + 2;
+  const size_t f0 = (size_t)n1 * n2, f1 = (size_t)n0 * n2, f2 = (size_t)n0 * n1;
+  size_t t = (size_t)blockIdx.x * kB + threadIdx.x;
+  int p[3];
+  if (t < 2 * f0) {
+    p[0] = t < f0 ? -1 : d.n[0];
+    t %= f0;
+    p[1] = (int)(t % n1) - 1;
+    p[2] = (int)(t / n1) - 1;
+  } else if ((t -= 2 * f0) < 2 * f1) {
+    p[1] = t < f1 ? -1 : d.n[1];
+    t %= f1;
+    p[0] = (int)(t % n0) - 1;
+    p[2] = (int)(t / n0) - 1;
+  } else if ((t -= 2 * f1) < 2 * f2) {
+    p[2] = t < f2 ? -1 : d.n[2];
+    t %= f2;
+    p[0] = (int)(t % n0) - 1;
+    p[1] = (int)(t / n0) - 1;
   } else {
-    double b = 0.0;
-    if (!hom && P.b[face]) {
-      const int i1 = min(max(c1, 0), P.bn - 1), i2 = min(max(c2, 0), P.bn - 1);
-      b = P.b[face][(size_t)i2 * P.bn + i1];
-    }
-    u[at(g)] = 2.0 * b - u[at(a)];
+    return;
   }
+  const int q[3] = {p[0], p[1], p[2]};
+  double sgn = 1.0, add = 0.0;
+  for (int axis = 2; axis >= 0; --axis) {
+    const int c = p[axis], na = d.n[axis];
+    if (c >= 0 && c < na) continue;
+    const int side = c < 0 ? 0 : 1, face = 2 * axis + side;
+    const int kd = P.kind[face];
+    if (kd == BC_PERIODIC) {
+      p[axis] = side ? 0 : na - 1;
+      continue;
+    }
+    if (kd != BC_ZERO_GRADIENT) {
+      double b = 0.0;
+      if (!hom && P.b[face]) {
+        // face value at the transverse position of the ghost (ring: the nearest face value)
+        const int t1 = axis == 0 ? 1 : 0, t2 = axis == 2 ? 1 : 2;
+        const int i1 = min(max(p[t1], 0), P.bn - 1), i2 = min(max(p[t2], 0), P.bn - 1);
+        b = P.b[face][(size_t)i2 * P.bn + i1];
+      }
+      add += sgn * (2.0 * b);
+      sgn = -sgn;
+    }
+    p[axis] = side ? na - 1 : 0;
+  }
+  u[gx(d, q[0], q[1], q[2])] = sgn * u[gx(d, p[0], p[1], p[2])] + add;
 }
 
 // ---- conservative level boundary (eqs. transgrad, piint, lbint; lbext on the coarse side)
@@ -132,7 +157,8 @@ struct Cons {
   double* cg[6];      // coarse ghosts per face, or nullptr
 };
 
-__global__ void __launch_bounds__(kB) k_cons(Cons A, int axis) {
+__global__ void __launch_bounds__(kB) k_cons(Cons A) {
+  const int axis = blockIdx.y;
   const int t1a = axis == 0 ? 1 : 0, t2a = axis == 2 ? 1 : 2;
   const int nf1 = A.df.n[t1a], nf2 = A.df.n[t2a];
   const size_t t = (size_t)blockIdx.x * kB + threadIdx.x;
@@ -173,12 +199,21 @@ __global__ void __launch_bounds__(kB) k_cons(Cons A, int axis) {
 }
 
 // ---- RB-SOR on the active cells of one colour (eqs. rbsor1-2); colour by global parity
+// With an even x extent one work item per x-pair updates the pair's cell of this colour;
+// otherwise one work item per cell.
 __global__ void __launch_bounds__(kB) k_smooth(double* __restrict__ u, const double* __restrict__ f, Dims d, int o0,
                                                 int o1, int o2, Hole H, double h2, double omega, int colour) {
   const size_t t = (size_t)blockIdx.x * kB + threadIdx.x;
-  if (t >= cells(d)) return;
   int x, y, z;
-  cell_of(t, d, x, y, z);
+  if ((d.n[0] & 1) == 0) {
+    const Dims dp{{d.n[0] / 2, d.n[1], d.n[2]}};
+    if (t >= cells(dp)) return;
+    cell_of(t, dp, x, y, z);
+    x = 2 * x + ((colour + o0 + (o1 + y) + (o2 + z)) & 1);
+  } else {
+    if (t >= cells(d)) return;
+    cell_of(t, d, x, y, z);
+  }
   if ((((o0 + x) + (o1 + y) + (o2 + z)) & 1) != colour || covered(H, x, y, z)) return;
   const size_t c = gx(d, x, y, z);
   const double uc = u[c];
@@ -398,11 +433,9 @@ struct AmrRun {
 
   void fill_phys(double* u, const Dims& d, bool hom) {
     const Phys P = phys_for(d.n[0], hom);
-    for (int axis = 0; axis < 3; ++axis) {
-      const int m1 = axis == 0 ? d.n[1] : d.n[0] + 2;
-      const int m2 = axis == 2 ? d.n[1] + 2 : d.n[2];
-      hipLaunchKernelGGL(k_fill_phys, dim3(blocks((size_t)2 * m1 * m2)), dim3(kB), 0, s, u, d, axis, P, hom ? 1 : 0);
-    }
+    const size_t faces = (size_t)2 * ((size_t)(d.n[1] + 2) * (d.n[2] + 2) + (size_t)(d.n[0] + 2) * (d.n[2] + 2) +
+                                      (size_t)(d.n[0] + 2) * (d.n[1] + 2));
+    hipLaunchKernelGGL(k_fill_phys1, dim3(blocks(faces)), dim3(kB), 0, s, u, d, P, hom ? 1 : 0);
   }
 
   // conservative ghosts between fine patch (lam) and coarse patch (lam-1) at level k, using
@@ -418,10 +451,12 @@ struct AmrRun {
       A.hi[a] = coarse.hole.hi[a];
     }
     for (int f = 0; f < 6; ++f) A.cg[f] = cg ? cg[f] : nullptr;
+    size_t most = 0;
     for (int axis = 0; axis < 3; ++axis) {
       const int t1a = axis == 0 ? 1 : 0, t2a = axis == 2 ? 1 : 2;
-      hipLaunchKernelGGL(k_cons, dim3(blocks((size_t)2 * fine.d.n[t1a] * fine.d.n[t2a])), dim3(kB), 0, s, A, axis);
+      most = std::max(most, (size_t)2 * fine.d.n[t1a] * fine.d.n[t2a]);
     }
+    hipLaunchKernelGGL(k_cons, dim3(blocks(most), 3), dim3(kB), 0, s, A);
   }
 
   Hole hole_of(const PatchL& p) const {
@@ -444,7 +479,7 @@ struct AmrRun {
         fill_level(k, 0);
         for (int l = 0; l <= pl.Lam; ++l) {
           PatchL& p = pl.P[l][k];
-          hipLaunchKernelGGL(k_smooth, dim3(blocks(cells(p.d))), dim3(kB), 0, s, p.u, p.f, p.d, p.o[0], p.o[1], p.o[2],
+          hipLaunchKernelGGL(k_smooth, dim3(blocks(smooth_items(p.d))), dim3(kB), 0, s, p.u, p.f, p.d, p.o[0], p.o[1], p.o[2],
                              hole_of(p), p.h * p.h, omega, colour);
         }
       }
@@ -532,7 +567,7 @@ struct AmrRun {
     for (int it = 0; it < npre; ++it)
       for (int colour = 0; colour < 2; ++colour) {
         fill_phys(u, d, false);
-        hipLaunchKernelGGL(k_smooth, dim3(blocks(cells(d))), dim3(kB), 0, s, u, f, d, 0, 0, 0, none, top.h * top.h, omega,
+        hipLaunchKernelGGL(k_smooth, dim3(blocks(smooth_items(d))), dim3(kB), 0, s, u, f, d, 0, 0, 0, none, top.h * top.h, omega,
                            colour);
       }
     fill_phys(u, d, false);
@@ -553,7 +588,7 @@ struct AmrRun {
     for (int it = 0; it < npost; ++it)
       for (int colour = 0; colour < 2; ++colour) {
         fill_phys(u, d, false);
-        hipLaunchKernelGGL(k_smooth, dim3(blocks(cells(d))), dim3(kB), 0, s, u, f, d, 0, 0, 0, none, top.h * top.h, omega,
+        hipLaunchKernelGGL(k_smooth, dim3(blocks(smooth_items(d))), dim3(kB), 0, s, u, f, d, 0, 0, 0, none, top.h * top.h, omega,
                            colour);
       }
   }
@@ -571,7 +606,7 @@ struct AmrRun {
     for (int it = 0; it < sweeps; ++it)
       for (int colour = 0; colour < 2; ++colour) {
         cons(p, p.u, c, c.u, nullptr);
-        hipLaunchKernelGGL(k_smooth, dim3(blocks(cells(p.d))), dim3(kB), 0, s, p.u, p.f, p.d, p.o[0], p.o[1], p.o[2], none,
+        hipLaunchKernelGGL(k_smooth, dim3(blocks(smooth_items(p.d))), dim3(kB), 0, s, p.u, p.f, p.d, p.o[0], p.o[1], p.o[2], none,
                            p.h * p.h, omega, colour);
       }
   }
