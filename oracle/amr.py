@@ -81,7 +81,7 @@ class AmrMesh:
     refinement level lam in level-(lam-1) block units."""
 
     def __init__(self, NB: int, nb: int, boxes: Sequence[Box]):
-        assert nb >= 2 and nb & (nb - 1) == 0
+        assert nb >= 1 and nb & (nb - 1) == 0     # nb = 1: operators at one cell per block only
         self.NB, self.nb = NB, nb
         self.K = int(round(math.log2(nb)))
         self.boxes = [tuple(tuple(int(v) for v in c) for c in b) for b in boxes]
@@ -321,9 +321,20 @@ class AmrState:
             for l in range(Lam + 1):
                 interior(self.f[l][K])[self.act[l][K]] -= mean
         self.rms_f = math.sqrt(self.volume_mean([interior(self.f[l][K]) ** 2 for l in range(Lam + 1)], K))
-        # root grid hierarchy (uniform, NB^3 down to 1)
+        # root grid hierarchy (uniform, NB^3 down to 1): potentials below NB, sources at every n
         self.root_L = int(round(math.log2(mesh.NB)))
         assert (1 << self.root_L) == mesh.NB
+        self.ru, self.rf, self.rfsrc = {}, {}, {}
+        n = mesh.NB
+        while n >= 1:
+            if n < mesh.NB:
+                self.ru[n] = np.zeros((n + 2,) * 3)
+            self.rf[n] = np.zeros((n + 2,) * 3)
+            n //= 2
+        # FMG sources: per patch at k = 0 (the Octet levels, covered cells filled from the
+        # finer Octets) and the MeshBlock levels
+        self.fsrc = [None] * (Lam + 1)
+        self.fsrc_mb = [[f.copy() for f in fl] for fl in self.f]
 
     # ---- reductions over the composite grid (active cells, volume weighted)
     def volume_mean(self, per_patch, k):
@@ -347,6 +358,22 @@ class AmrState:
         for l in range(1, self.m.Lam + 1):
             cgs[l - 1] = conservative_ghosts(P[l][k], arrs[l], P[l - 1][k], arrs[l - 1])
         return cgs
+
+    def laplacian_upto(self, k, arrs, top):
+        """Composite L of patches 0 .. top-1 at level k, the level boundary to patch `top`
+        included (patches finer than `top` ignored)."""
+        P = self.m.patches
+        fill_physical(arrs[0], P[0][k], self.kinds, self.bfun, False)
+        cgs = []
+        for l in range(1, top + 1):
+            # ghosts of patch l from patch l-1 (patch `top` only lends its first cells)
+            tgt = arrs[l] if l < top else arrs[l].copy()
+            cgs.append(conservative_ghosts(P[l][k], tgt, P[l - 1][k], arrs[l - 1]))
+        out = []
+        for l in range(top):
+            nb = neighbour_sum(P[l][k], arrs[l], cgs[l])
+            out.append((nb - 6.0 * interior(arrs[l])) * (1.0 / (P[l][k].h * P[l][k].h)))
+        return out
 
     def laplacian(self, k, arrs, homogeneous=False):
         cgs = self.fill(k, arrs, homogeneous)
@@ -417,7 +444,7 @@ class AmrState:
         a = axis_prolong(a, 0)
         return a
 
-    def normal_fill(self, k, arrs):
+    def normal_fill(self, k, arrs, homogeneous=True):
         """Normal level boundary for prolongation at level k (homogeneous physical conditions):
         each finer patch is restricted into the covered cells of the coarser one (finest
         first), the root patch gets its physical ghosts, then the ghost shell of each finer
@@ -427,7 +454,7 @@ class AmrState:
         for l in range(Lam, 0, -1):
             lo, hi = P[l - 1][k].hole
             interior(arrs[l - 1])[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] = self.restrict(interior(arrs[l]))
-        fill_physical(arrs[0], P[0][k], self.kinds, None, True)
+        fill_physical(arrs[0], P[0][k], self.kinds, None if homogeneous else self.bfun, homogeneous)
         for l in range(1, Lam + 1):
             lo, hi = P[l - 1][k].hole
             # coarse region: the hole with one coarse cell around, plus one more for the stencil
@@ -441,81 +468,71 @@ class AmrState:
             interior(g)[...] = keep
 
     # ---- the FAS V-cycle on the refined mesh
-    def root_solve_cycle(self, f_root, u_root):
-        """One uniform FAS V-cycle (Alg. 3) on the root grid (NB^3 -> 1) with the physical
-        conditions at each level's geometry; u_root (ghosted) is updated in place."""
-        NB = self.m.NB
-        levels = []
-        n = NB
-        while n >= 1:
-            levels.append(n)
-            n //= 2
-        # per level: ghosted u, f
-        us = {NB: u_root}
-        fs = {NB: f_root}
+    # ---- the root grid: a uniform hierarchy NB^3 .. 1 with the physical conditions of each
+    # level (Sec. 2.3.6); level NB shares the root patch's potential array
+    def root_u(self, n):
+        return self.u[0][0] if n == self.m.NB else self.ru[n]
 
-        def patch_of(n):
-            return Patch(0, 0, (0, 0, 0), (n, n, n), 1.0 / n)
+    def _root_patch(self, n):
+        return Patch(0, 0, (0, 0, 0), (n, n, n), 1.0 / n)
 
-        def smooth_uniform(u, f, n, sweeps):
-            p = patch_of(n)
-            z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
-            for _ in range(sweeps):
-                for colour in (0, 1):
-                    fill_physical(u, p, self.kinds, self.bfun, False)
-                    nb = neighbour_sum(p, u)
-                    c = interior(u)
-                    upd = c + self.omega * ((nb - p.h * p.h * interior(f)) / 6.0 - c)
-                    c[...] = np.where(((x + y + z) & 1) == colour, upd, c)
+    def root_smooth(self, n, sweeps):
+        u, f, p = self.root_u(n), self.rf[n], self._root_patch(n)
+        z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+        for _ in range(sweeps):
+            for colour in (0, 1):
+                fill_physical(u, p, self.kinds, self.bfun, False)
+                nb = neighbour_sum(p, u)
+                c = interior(u)
+                upd = c + self.omega * ((nb - p.h * p.h * interior(f)) / 6.0 - c)
+                c[...] = np.where(((x + y + z) & 1) == colour, upd, c)
 
-        def lap_uniform(u, n):
-            p = patch_of(n)
-            fill_physical(u, p, self.kinds, self.bfun, False)
-            return (neighbour_sum(p, u) - 6.0 * interior(u)) / (p.h * p.h)
+    def root_lap(self, u, n):
+        p = self._root_patch(n)
+        fill_physical(u, p, self.kinds, self.bfun, False)
+        return (neighbour_sum(p, u) - 6.0 * interior(u)) / (p.h * p.h)
 
-        def coarsest(u, f):
-            # one cell (Sec. 2.3.2): ghost = alpha u + beta per face; keep u if nothing fixes it
-            sa, sb = 0.0, 0.0
-            for face in range(6):
-                if self.kinds[face] in (PERIODIC, ZERO_GRADIENT):
-                    sa += 1.0
+    def root_coarsest(self):
+        """One cell (Sec. 2.3.2): ghost = alpha u + beta per face; u kept when nothing fixes it."""
+        u, f = self.root_u(1), self.rf[1]
+        sa, sb = 0.0, 0.0
+        for face in range(6):
+            if self.kinds[face] in (PERIODIC, ZERO_GRADIENT):
+                sa += 1.0
+            else:
+                axis, side = face // 2, face % 2
+                pt = [0.5, 0.5, 0.5]
+                pt[axis] = 0.0 if side == 0 else 1.0
+                if self.bfun is None:
+                    b = 0.0
+                elif isinstance(self.bfun, FaceArrays):
+                    b = self.bfun.point(face)
                 else:
-                    axis, side = face // 2, face % 2
-                    pt = [0.5, 0.5, 0.5]
-                    pt[axis] = 0.0 if side == 0 else 1.0
-                    if self.bfun is None:
-                        b = 0.0
-                    elif isinstance(self.bfun, FaceArrays):
-                        b = self.bfun.point(face)
-                    else:
-                        b = float(self.bfun(np.array(pt[0]), np.array(pt[1]), np.array(pt[2])))
-                    sa -= 1.0
-                    sb += 2.0 * b
-            if sa != 6.0:
-                h = 1.0                                           # the unit cube's single cell
-                u[1, 1, 1] = (sb - h * h * f[1, 1, 1]) / (6.0 - sa)
+                    b = float(self.bfun(np.array(pt[0]), np.array(pt[1]), np.array(pt[2])))
+                sa -= 1.0
+                sb += 2.0 * b
+        if sa != 6.0:
+            h = 1.0                                           # the unit cube's single cell
+            u[1, 1, 1] = (sb - h * h * f[1, 1, 1]) / (6.0 - sa)
 
-        def fas(n):
-            u, f = us[n], fs[n]
-            if n == 1:
-                coarsest(u, f)
-                return
-            smooth_uniform(u, f, n, self.npre)
-            d = interior(f) - lap_uniform(u, n)
-            nc = n // 2
-            uc = np.zeros((nc + 2,) * 3)
-            interior(uc)[...] = self.restrict(interior(u))
-            pb = uc.copy()
-            fc = np.zeros((nc + 2,) * 3)
-            interior(fc)[...] = self.restrict(d) + lap_uniform(pb, nc)
-            us[nc], fs[nc] = uc, fc
-            fas(nc)
-            delta = us[nc] - pb
-            fill_physical(delta, patch_of(nc), self.kinds, None, True)
-            interior(u)[...] += self.prolong(delta)
-            smooth_uniform(u, f, n, self.npost)
-
-        fas(NB)
+    def root_cycle(self, n):
+        """Uniform FAS V-cycle (Alg. 3) from root level n with its source in rf[n]."""
+        if n == 1:
+            self.root_coarsest()
+            return
+        u, f = self.root_u(n), self.rf[n]
+        self.root_smooth(n, self.npre)
+        d = interior(f) - self.root_lap(u, n)
+        nc = n // 2
+        uc = self.root_u(nc)
+        interior(uc)[...] = self.restrict(interior(u))
+        pb = uc.copy()
+        interior(self.rf[nc])[...] = self.restrict(d) + self.root_lap(pb, nc)
+        self.root_cycle(nc)
+        delta = uc - pb
+        fill_physical(delta, self._root_patch(nc), self.kinds, None, True)
+        interior(u)[...] += self.prolong(delta)
+        self.root_smooth(n, self.npost)
 
     def octet_smooth(self, l, sweeps):
         """RB-SOR on every cell of the Octet patch l (k = 0), the conservative ghosts from the
@@ -533,12 +550,23 @@ class AmrState:
                 upd = c + self.omega * ((nb - full.h * full.h * interior(self.f[l][0])) / 6.0 - c)
                 c[...] = np.where(par == colour, upd, c)
 
-    def vcycle(self):
+    def vcycle(self, top=None):
+        """One FAS V-cycle from `top`: ("mb", k) starts on MeshBlock level k (default: the
+        finest), ("oct", lam) on Octet level lam, ("root", n) on root level n.  A cycle from
+        an Octet level treats the uncovered cells of the coarser patches as part of their own
+        levels: their restricted potential is the current value and their restricted defect
+        their own, so their coarse source is their own source."""
         m, K, Lam = self.m, self.m.K, self.m.Lam
         P = m.patches
         all_l = range(Lam + 1)
+        kind, level = top if top is not None else ("mb", K)
+        if kind == "root":
+            self.root_cycle(level)
+            return
+        kt = level if kind == "mb" else 0
+        lam_top = Lam if kind == "mb" else level
         # ---- MeshBlock levels, down
-        for k in range(K, 0, -1):
+        for k in range(kt, 0, -1):
             self.smooth(k, self.npre)
             d = self.defect(k)
             for l in all_l:
@@ -551,17 +579,32 @@ class AmrState:
                 for l in all_l:
                     interior(self.f[l][k - 1])[...] = np.where(self.act[l][k - 1],
                                                                interior(self.dres[l][k - 1]) + Lc[l], 0.0)
+        if kind == "oct":
+            # the uncovered cells of the coarser patches belong to this Octet level's composite
+            # problem: phibar = their current value, restricted defect = their defect in that
+            # problem (composite operator at k = 0 over patches 0 .. lam_top, the conservative
+            # ghosts from the finer patch included); covered cells are filled from the Octets
+            # below as the cycle goes down
+            arrs = [self.u[l][0] for l in range(Lam + 1)]
+            Lc = self.laplacian_upto(0, arrs, lam_top)
+            srcs = [self.rfsrc[m.NB]] + [self.fsrc[l] for l in range(1, lam_top)]
+            for l in range(lam_top):
+                interior(self.dres[l][0])[...] = np.where(self.act[l][0], interior(srcs[l]) - Lc[l], 0.0)
+                self.pbar[l][0][...] = self.u[l][0]
         # ---- Octet levels, finest first (k = 0): smooth, then restrict into the coarser patch
-        for l in range(Lam, 0, -1):
+        for l in range(lam_top, 0, -1):
             fine, coarse = P[l][0], P[l - 1][0]
             # the octet operator: the full patch (covered cells hold the restricted finer
             # octets) with the conservative ghosts from the coarser patch
             full = Patch(l, 0, fine.origin, fine.n, fine.h, None)
-            pb = self.pbar[l][0]
-            conservative_ghosts(full, pb, coarse, self.pbar[l - 1][0])
-            Lp = (neighbour_sum(full, pb) - 6.0 * interior(pb)) / (full.h * full.h)
-            interior(self.f[l][0])[...] = interior(self.dres[l][0]) + Lp
-            interior(self.u[l][0])[...] = interior(pb)
+            if not (kind == "oct" and l == lam_top):
+                pb = self.pbar[l][0]
+                conservative_ghosts(full, pb, coarse, self.pbar[l - 1][0])
+                Lp = (neighbour_sum(full, pb) - 6.0 * interior(pb)) / (full.h * full.h)
+                interior(self.f[l][0])[...] = interior(self.dres[l][0]) + Lp
+                interior(self.u[l][0])[...] = interior(pb)
+            else:
+                interior(self.f[l][0])[...] = interior(self.fsrc[l])
             self.octet_smooth(l, self.npre)
             conservative_ghosts(full, self.u[l][0], coarse, self.u[l - 1][0])
             d = interior(self.f[l][0]) - (neighbour_sum(full, self.u[l][0]) - 6.0 * interior(self.u[l][0])) / (full.h * full.h)
@@ -577,12 +620,11 @@ class AmrState:
         pb0 = self.pbar[0][0]
         fill_physical(pb0, full0, self.kinds, self.bfun, False)
         L0 = (neighbour_sum(full0, pb0) - 6.0 * interior(pb0)) / (full0.h * full0.h)
-        f0 = np.zeros(pb0.shape)
-        interior(f0)[...] = interior(self.dres[0][0]) + L0
+        interior(self.rf[m.NB])[...] = interior(self.dres[0][0]) + L0
         interior(self.u[0][0])[...] = interior(pb0)
-        self.root_solve_cycle(f0, self.u[0][0])
+        self.root_cycle(m.NB)
         # ---- Octet levels, coarsest first: prolongated correction, then post-smoothing
-        for l in range(1, Lam + 1):
+        for l in range(1, lam_top + 1):
             coarse = P[l - 1][0]
             delta = self.u[l - 1][0] - self.pbar[l - 1][0]
             if l - 1 == 0:
@@ -592,7 +634,7 @@ class AmrState:
             interior(self.u[l][0])[...] += self.prolong(reg)
             self.octet_smooth(l, self.npost)
         # ---- MeshBlock levels, up
-        for k in range(1, K + 1):
+        for k in range(1, kt + 1):
             delta = [self.u[l][k - 1] - self.pbar[l][k - 1] for l in all_l]
             for l in all_l:
                 interior(delta[l])[~self.act[l][k - 1]] = 0.0
@@ -600,6 +642,92 @@ class AmrState:
             for l in all_l:
                 interior(self.u[l][k])[...] += np.where(self.act[l][k], self.prolong(delta[l]), 0.0)
             self.smooth(k, self.npost)
+
+    # ---- full multigrid (Alg. 2 with FAS in place of the V-cycle) on the refined hierarchy
+    @staticmethod
+    def prolong_cubic(c):
+        """Tricubic FMG prolongation (Sec. 2.3.1) of a ghost-filled coarse array: per axis the
+        lower child (5 c[I-1] + 30 c[I] - 3 c[I+1]) / 32, the upper (-3 c[I-1] + 30 c[I] +
+        5 c[I+1]) / 32, applied x, then y, then z."""
+        def axis_prolong(a, ax):
+            m = np.take(a, range(0, a.shape[ax] - 2), axis=ax)
+            c0 = np.take(a, range(1, a.shape[ax] - 1), axis=ax)
+            p_ = np.take(a, range(2, a.shape[ax]), axis=ax)
+            lo = ((5.0 / 32.0) * m + (30.0 / 32.0) * c0) + (-3.0 / 32.0) * p_
+            hi = ((-3.0 / 32.0) * m + (30.0 / 32.0) * c0) + (5.0 / 32.0) * p_
+            shp = list(lo.shape)
+            shp[ax] *= 2
+            out = np.empty(shp)
+            s_lo = [slice(None)] * 3
+            s_hi = [slice(None)] * 3
+            s_lo[ax] = slice(0, None, 2)
+            s_hi[ax] = slice(1, None, 2)
+            out[tuple(s_lo)] = lo
+            out[tuple(s_hi)] = hi
+            return out
+        a = axis_prolong(c, 2)
+        a = axis_prolong(a, 1)
+        return axis_prolong(a, 0)
+
+    def fmg_sources(self):
+        """Alg. 2 step 1: the source on every MeshBlock level (8-cell means per patch), on every
+        Octet level (covered cells: the means of the finer Octet level) and root level."""
+        m, K, Lam = self.m, self.m.K, self.m.Lam
+        P = m.patches
+        all_l = range(Lam + 1)
+        for k in range(K, 0, -1):
+            for l in all_l:
+                interior(self.f[l][k - 1])[...] = self.restrict(interior(self.f[l][k]))
+        self.fsrc_mb = [[f.copy() for f in fl] for fl in self.f]
+        for l in all_l:
+            self.fsrc[l] = self.f[l][0].copy()
+        for l in range(Lam, 0, -1):
+            lo, hi = P[l - 1][0].hole
+            interior(self.fsrc[l - 1])[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] = self.restrict(interior(self.fsrc[l]))
+        n = m.NB
+        self.rfsrc[n] = self.fsrc[0].copy()
+        while n > 1:
+            self.rfsrc[n // 2] = np.zeros((n // 2 + 2,) * 3)
+            interior(self.rfsrc[n // 2])[...] = self.restrict(interior(self.rfsrc[n]))
+            n //= 2
+
+    def fmg(self):
+        """Alg. 2 on the refined hierarchy: sources restricted to every level; the single root
+        cell solved; then root levels 2 .. NB, Octet levels 1 .. Lam and MeshBlock levels
+        1 .. K each start from the tricubic prolongation of the solution one level down
+        (ghosts: physical conditions on the root patch, the normal level boundary between
+        patches) and take one V-cycle from that level."""
+        m, K, Lam = self.m, self.m.K, self.m.Lam
+        P = m.patches
+        all_l = range(Lam + 1)
+        self.fmg_sources()
+        # root levels
+        self.rf[1][...] = self.rfsrc[1]
+        self.root_u(1)[...] = 0.0
+        self.root_coarsest()
+        n = 2
+        while n <= m.NB:
+            c = self.root_u(n // 2)
+            fill_physical(c, self._root_patch(n // 2), self.kinds, self.bfun, False)
+            interior(self.root_u(n))[...] = self.prolong_cubic(c)
+            self.rf[n][...] = self.rfsrc[n]
+            self.root_cycle(n)
+            n *= 2
+        # Octet levels
+        for l in range(1, Lam + 1):
+            c = self.u[l - 1][0]
+            lo, hi = P[l - 1][0].hole
+            reg = c[lo[2]:hi[2] + 2, lo[1]:hi[1] + 2, lo[0]:hi[0] + 2]
+            interior(self.u[l][0])[...] = self.prolong_cubic(reg)
+            self.vcycle(("oct", l))
+        # MeshBlock levels
+        for k in range(1, K + 1):
+            for l in all_l:
+                interior(self.f[l][k])[...] = np.where(self.act[l][k], interior(self.fsrc_mb[l][k]), 0.0)
+            self.normal_fill(k - 1, [self.u[l][k - 1] for l in all_l], homogeneous=False)
+            for l in all_l:
+                interior(self.u[l][k])[...] = np.where(self.act[l][k], self.prolong_cubic(self.u[l][k - 1]), 0.0)
+            self.vcycle(("mb", k))
 
     def residual(self) -> float:
         K = self.m.K
@@ -623,11 +751,15 @@ class AmrState:
             interior(self.u[l][K])[...] = np.where(self.act[l][K], phi[l], 0.0)
 
 
-def solve(mesh: AmrMesh, rho, kinds, bfun=None, phi0=None, cycles=None, tol=1e-10, max_cycles=60, **kw):
-    """V-cycles from phi0 (zero by default) until the relative composite residual is <= tol (or
-    `cycles` exactly).  Returns (phi per patch, residual history)."""
+def solve(mesh: AmrMesh, rho, kinds, bfun=None, phi0=None, cycles=None, tol=1e-10, max_cycles=60, mode="mgi",
+          **kw):
+    """FMG (mode "fmg") or V-cycles from phi0 (zero by default), then V-cycles until the
+    relative composite residual is <= tol (or `cycles` exactly).  Returns (phi per patch,
+    residual history)."""
     st = AmrState(mesh, rho, kinds, bfun, **kw)
-    if phi0 is not None:
+    if mode == "fmg":
+        st.fmg()
+    elif phi0 is not None:
         st.set_phi(phi0)
     hist = [st.residual()]
     n = cycles if cycles is not None else max_cycles

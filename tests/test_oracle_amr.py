@@ -209,3 +209,117 @@ def test_face_arrays_match_point_values_for_linear_b():
     b, hb = amr.solve(m, rho, [amr.FIXED] * 6, amr.FaceArrays(faces), cycles=4)
     assert np.allclose(ha, hb, rtol=1e-9)
     assert max(np.abs(a[l] - b[l]).max() for l in range(m.Lam + 1)) < 1e-12
+
+
+def test_fmg_converges_to_dense_composite_solve():
+    """FMG (Alg. 2 with FAS) on the refined hierarchy followed by V-cycles reaches the dense
+    direct solution of the composite system, from a far better start than zero."""
+    m = amr.AmrMesh(4, 2, [((1, 1, 1), (3, 3, 3))])
+    rng = np.random.default_rng(6)
+    rho = [rng.uniform(0, 1, m.patches[l][m.K].n[::-1]) for l in range(m.Lam + 1)]
+    bfun = lambda x, y, z: 0.1 * x - 0.2 * y * z
+    ref = dense_composite_solve(m, rho, [amr.FIXED] * 6, bfun)
+    phi, hist = amr.solve(m, rho, [amr.FIXED] * 6, bfun, tol=1e-13, mode="fmg")
+    assert hist[0] < 0.1 and hist[-1] <= 1e-13
+    num = math.sqrt(sum(np.sum((phi[l] - ref[l]) ** 2) for l in range(m.Lam + 1)))
+    den = math.sqrt(sum(np.sum(ref[l] ** 2) for l in range(m.Lam + 1)))
+    assert num / den < 1e-11
+
+
+def test_fmg_reaches_truncation_error():
+    """One FMG sweep already has an error against the analytic potential of the order of the
+    discretisation error (Sec. 2.3.4): within 1.5x of the converged solution's, on the
+    Gaussian of the accuracy test (two refinement levels)."""
+    from scipy.special import erf
+    sig, c = 0.04, np.array([0.5, 0.5, 0.5])
+    M = (2 * math.pi * sig * sig) ** 1.5
+
+    def exact(x, y, z):
+        r = np.maximum(np.sqrt((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2), 1e-12)
+        return -M * erf(r / (math.sqrt(2) * sig)) / r
+
+    m = amr.AmrMesh(4, 4, [((1, 1, 1), (3, 3, 3)), ((3, 3, 3), (5, 5, 5))])
+    gs = grids(m)
+    rho = [np.exp(-((X - 0.5) ** 2 + (Y - 0.5) ** 2 + (Z - 0.5) ** 2) / (2 * sig * sig)) for X, Y, Z in gs]
+    f0, _ = amr.solve(m, rho, [amr.FIXED] * 6, exact, mode="fmg", cycles=0)
+    fc, _ = amr.solve(m, rho, [amr.FIXED] * 6, exact, mode="fmg", tol=1e-11)
+    act = [m.patches[l][m.K].active() for l in range(m.Lam + 1)]
+    e0 = max(np.abs(f0[l] - exact(*gs[l]))[act[l]].max() for l in range(m.Lam + 1))
+    ec = max(np.abs(fc[l] - exact(*gs[l]))[act[l]].max() for l in range(m.Lam + 1))
+    assert e0 < 1.5 * ec, (e0, ec)
+
+
+TWO_SMALL = (4, 2, [((1, 1, 1), (3, 3, 3)), ((3, 3, 3), (5, 5, 5))])
+
+
+def test_fmg_sources_are_volume_means():
+    """Alg. 2 step 1 on the refined hierarchy: every Octet-level cell's source is the volume
+    mean of the finest composite source over the cell (a covered cell averages the finer
+    patches inside it), computed here directly from cell positions."""
+    NB, nb, boxes = TWO_SMALL
+    m = amr.AmrMesh(NB, nb, boxes)
+    rng = np.random.default_rng(8)
+    rho = [rng.uniform(0, 1, m.patches[l][m.K].n[::-1]) for l in range(m.Lam + 1)]
+    st = amr.AmrState(m, rho, [amr.FIXED] * 6)
+    st.fmg_sources()
+    for t in range(m.Lam + 1):
+        pt = m.patches[t][0]
+        acc = np.zeros(pt.n[::-1])
+        vol = np.zeros(pt.n[::-1])
+        B = pt.h
+        for l in range(t, m.Lam + 1):
+            p = m.patches[l][m.K]
+            act = p.active()
+            x, y, z = m.centres(l)
+            Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+            ix = np.floor(X / B).astype(int) - pt.origin[0]
+            iy = np.floor(Y / B).astype(int) - pt.origin[1]
+            iz = np.floor(Z / B).astype(int) - pt.origin[2]
+            sel = act & (ix >= 0) & (ix < pt.n[0]) & (iy >= 0) & (iy < pt.n[1]) & (iz >= 0) & (iz < pt.n[2])
+            np.add.at(acc, (iz[sel], iy[sel], ix[sel]), p.h ** 3 * FPG * rho[l][sel])
+            np.add.at(vol, (iz[sel], iy[sel], ix[sel]), p.h ** 3)
+        want = acc / vol
+        got = st.fsrc[t][1:-1, 1:-1, 1:-1] if t > 0 else st.rfsrc[NB][1:-1, 1:-1, 1:-1]
+        assert np.allclose(got, want, rtol=1e-13, atol=1e-12), t
+
+
+@pytest.mark.parametrize("lam", [1, 2])
+def test_octet_cycle_fixed_point(lam):
+    """A V-cycle started on Octet level lam leaves the exact solution of that level's composite
+    problem unchanged.  That problem is the composite operator of the same boxes at one cell
+    per MeshBlock (a mesh with nb = 1), solved here densely with the FMG sources; the uncovered
+    cells of the coarser patches must enter the cycle with their defect in this problem."""
+    NB, nb, boxes = TWO_SMALL
+    m = amr.AmrMesh(NB, nb, boxes)
+    rng = np.random.default_rng(9)
+    rho = [rng.uniform(0, 1, m.patches[l][m.K].n[::-1]) for l in range(m.Lam + 1)]
+    bfun = lambda x, y, z: 0.2 + 0.1 * x - 0.3 * z
+    st = amr.AmrState(m, rho, [amr.FIXED] * 6, bfun)
+    st.fmg_sources()
+    m1 = amr.AmrMesh(NB, 1, boxes[:lam])
+    srcs = [st.rfsrc[NB][1:-1, 1:-1, 1:-1]] + [st.fsrc[l][1:-1, 1:-1, 1:-1] for l in range(1, lam + 1)]
+    exact = dense_composite_solve(m1, [s / FPG for s in srcs], [amr.FIXED] * 6, bfun)
+    for l in range(lam + 1):
+        st.u[l][0][1:-1, 1:-1, 1:-1] = exact[l]
+    st.vcycle(("oct", lam))
+    act1 = [m1.patches[l][0].active() for l in range(lam + 1)]
+    scale = max(np.abs(e).max() for e in exact)
+    for l in range(lam + 1):
+        got = st.u[l][0][1:-1, 1:-1, 1:-1]
+        assert np.max(np.abs(got - exact[l])[act1[l]]) < 1e-11 * scale, l
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_fmg_exact_for_linear_potentials(name):
+    """f = 0 with fixed faces holding a linear field: the composite problem's solution is that
+    field, and every FMG stage reproduces it exactly (the tricubic and trilinear
+    prolongations, the physical ghosts and the normal level boundary are exact for linear
+    fields, and V-cycles leave an exact solution alone), so one FMG sweep alone returns it."""
+    m = MESHES[name]()
+    a = (0.7, -1.3, 2.1)
+    lin = lambda x, y, z: 0.4 + a[0] * x + a[1] * y + a[2] * z
+    rho = [np.zeros(m.patches[l][m.K].n[::-1]) for l in range(m.Lam + 1)]
+    phi, hist = amr.solve(m, rho, [amr.FIXED] * 6, lin, mode="fmg", cycles=0)
+    for l, (X, Y, Z) in enumerate(grids(m)):
+        act = m.patches[l][m.K].active()
+        assert np.max(np.abs(phi[l] - lin(X, Y, Z))[act]) < 1e-12, l
