@@ -15,8 +15,9 @@ in HBM.  The JSON line reports:
   mixed         the same numbers for the mixed-precision solve; p50/p99 solve latency.
   fas           the same solve with Full Approximation Scheme iterations (Alg. 3): per-cycle
                 rate, its finest-level passes and the roofline of the dominant one;
-  amr           a refined mesh (256^3 root grid, central blocks refined once): FAS V-cycles to
-                1e-10, composite cells per second per cycle, the numpy oracle beside it;
+  amr           a refined mesh (256^3 root grid, central blocks refined once): FMG and FAS
+                V-cycles to 1e-10, composite cells per second per cycle, the numpy oracle
+                beside it;
   gravity       g = -grad phi and rho g of the solved potential (Sec. 2.4): mean launch time
                 and its HBM roofline (64 algorithmic bytes per cell), CPU oracle beside it;
   batched       the 256^3 lognormal field as 4096 MeshBlocks of 16^3 (autotuned), FP64 and
@@ -212,10 +213,10 @@ def amr_patches(NB, nb, boxes, seed):
 
 
 def amr_leg(mg, steps: int, seed: int, with_cpu: bool):
-    """Refined mesh (NEXT row of the paper's Sec. 3.3): 256^3 root grid of 16^3-cell MeshBlocks
-    with the central 4^3 blocks refined once (a 128^3 patch at twice the resolution), clumps
-    concentrated in the refined region, periodic, FAS V-cycles from zero to 1e-10.  The rate
-    counts the composite (active) cells per V-cycle."""
+    """Refined mesh (the paper's Sec. 3.3): 256^3 root grid of 16^3-cell MeshBlocks with the
+    central 4^3 blocks refined once (a 128^3 patch at twice the resolution), clumps
+    concentrated in the refined region, periodic, FMG then FAS V-cycles to 1e-10.  The rate
+    counts the composite (active) cells per V-cycle (solve time over cycles, FMG included)."""
     import torch
     NB, nb, boxes = AMR_MESH
     rho_h = amr_patches(NB, nb, boxes, seed)
@@ -227,7 +228,7 @@ def amr_leg(mg, steps: int, seed: int, with_cpu: bool):
     for it in range(1 + steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        phi, hist, st = mg.amr_solve(mesh, rho, "periodic", tol=1e-10, ctx=ctx)
+        phi, hist, st = mg.amr_solve(mesh, rho, "periodic", tol=1e-10, mode="fmg", ctx=ctx)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) * 1e3
         if st < 0 or hist[-1] > 1e-10:
@@ -239,7 +240,7 @@ def amr_leg(mg, steps: int, seed: int, with_cpu: bool):
               flush=True)
     ms_cycle = statistics.median(lat) / statistics.median(cyc)
     out = {"workload": "256^3 root (16^3 blocks of 16^3), central 4^3 blocks refined once (128^3 patch), "
-                       "periodic clumps, FAS V(2,2) from zero to 1e-10",
+                       "periodic clumps, FMG + FAS V(2,2) to 1e-10",
            "composite_cells": dof, "cycles_per_solve": cyc[-1], "solve_ms": statistics.median(lat),
            "ms_per_cycle_incl_residual": ms_cycle, "value": dof / (ms_cycle * 1e-3) / 1e9,
            "unit": "GDoF/s per V-cycle (composite cells)"}

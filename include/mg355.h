@@ -240,22 +240,26 @@ typedef struct {
 /* Cells per axis (x, y, z) of patch lam (0..levels) at the finest MeshBlock level. */
 int mg_amr_patch_dims(const mg_amr_mesh *mesh, int lam, int dims[3]);
 
-/* FAS V-cycles (Alg. 3) on the refined mesh, from the initial guess in phi (MG_MODE_MGI):
+/* Full multigrid (Alg. 2 with FAS; MG_MODE_FMG) or V-cycles from the initial guess in phi
+ * (MG_MODE_MGI), then FAS V-cycles (Alg. 3) on the refined mesh:
  * MeshBlock levels with every refinement level smoothed together, the conservative level
  * boundary (eqs. masscons, transgrad, piint, lbint, lbext: interpolated fine ghosts, one
  * extrapolated coarse ghost per face of the refined region) before every colour and defect,
  * Octet levels finest first, a uniform FAS V-cycle on the NB^3 root grid, and corrections
  * prolongated through the normal level boundary (restriction into the covered coarse cells,
- * trilinear prolongation into the finer patch's ghost shell).
- *   p     dx = 1/(NB nb) (the unit cube); four_pi_g, npre, npost, omega, tol, max_cycles,
- *         fixed_cycles as for mg_solve; mode MG_MODE_MGI and precision FP64 (else
- *         MG_ERR_UNSUPPORTED).
+ * trilinear prolongation into the finer patch's ghost shell).  FMG restricts the source to
+ * every level, solves the root cell, then starts root levels, Octet levels and MeshBlock
+ * levels in turn from the tricubic prolongation of the solution below (the normal level
+ * boundary with physical root conditions for the ghosts) and runs one V-cycle from each.
+ *   p     dx = 1/(NB nb) (the unit cube); mode, four_pi_g, npre, npost, omega, tol,
+ *         max_cycles, fixed_cycles as for mg_solve; precision FP64 (else MG_ERR_UNSUPPORTED).
  *   bc    periodic, zero-gradient or fixed faces (fixed_b: device (NB nb)^2 face-centre
  *         arrays; coarser levels take 2 x 2 area means); multipole: MG_ERR_UNSUPPORTED.
  *   rho   host array of levels+1 device pointers, patch lam's density (dims of
  *         mg_amr_patch_dims, x fastest), read only.
- *   phi   host array of levels+1 device pointers, same shapes: the initial guess on input,
- *         the potential on output (volume-weighted mean removed when no face is fixed).
+ *   phi   host array of levels+1 device pointers, same shapes: the initial guess on input
+ *         (MG_MODE_MGI; ignored by FMG), the potential on output (volume-weighted mean removed
+ *         when no face is fixed).
  *   hist  host, relative composite residual RMS(f - L phi)/RMS(f) (cell-volume weighted) of
  *         the initial guess and after each cycle; n_hist its length.
  * Allocates its workspace per call (device memory, freed before returning) and synchronises

@@ -369,15 +369,15 @@ def mg_amr_solve(ctx: Context, p: _abi.MgParams, mesh: _abi.MgAmrMesh, bc: _abi.
 
 def amr_solve(mesh: _abi.MgAmrMesh, rho, bc="periodic", fixed_b=None, phi=None, tol: float = 1e-10,
               max_cycles: int = 50, fixed_cycles: int = 0, npre: int = 2, npost: int = 2, omega: float = 1.15,
-              four_pi_g: float = 4.0 * math.pi, ctx: Optional[Context] = None, stream=None):
-    """Solve on a statically refined mesh (V-cycles from phi, zero by default).  rho: list of
-    float64 device tensors, one per patch (shape (nz, ny, nx) from amr_patch_dims).  Returns
-    (phi list, hist, status)."""
+              mode: str = "mgi", four_pi_g: float = 4.0 * math.pi, ctx: Optional[Context] = None, stream=None):
+    """Solve on a statically refined mesh: FMG (mode "fmg") or V-cycles from phi (zero by
+    default).  rho: list of float64 device tensors, one per patch (shape (nz, ny, nx) from
+    amr_patch_dims).  Returns (phi list, hist, status)."""
     import torch
     ctx = ctx or default_context(rho[0].device.index or 0)
     N = mesh.NB * mesh.nb
     p = params(N, 1.0 / N, tol=tol, max_cycles=max_cycles, fixed_cycles=fixed_cycles, npre=npre, npost=npost,
-               omega=omega, mode="mgi", four_pi_g=four_pi_g)
+               omega=omega, mode=mode, four_pi_g=four_pi_g)
     b = boundary(bc, fixed_b)
     if phi is None:
         phi = [torch.zeros_like(r) for r in rho]

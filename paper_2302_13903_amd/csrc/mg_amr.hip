@@ -262,9 +262,11 @@ __global__ void __launch_bounds__(kB) k_restrict(const double* __restrict__ uf, 
   if (out2) out2[o] = v;
 }
 
-// ---- trilinear prolongation (eq. trilinear), separable x then y then z as in the oracle.
-// Fine cells [lo, hi) per axis (ghost indices allowed); parent coarse cell = (fine global >>
-// 1) - coarse origin.  mode 0: add on active fine cells; 1: set, only on the ghost shell.
+// ---- prolongation, separable x then y then z as in the oracle.  Fine cells [lo, hi) per axis
+// (ghost indices allowed); parent coarse cell = (fine global >> 1) - coarse origin.
+// mode 0: trilinear (eq. trilinear), added on active fine cells; 1: trilinear, set on the
+// ghost shell only; 2: tricubic FMG prolongation (Sec. 2.3.1), set on active cells (0 on
+// covered cells).
 __global__ void __launch_bounds__(kB) k_prolong(const double* __restrict__ uc, Dims dc, int co0, int co1, int co2,
                                                  double* __restrict__ uf, Dims df, int fo0, int fo1, int fo2,
                                                  Hole Hf, int lx, int ly, int lz, Dims span, int mode) {
@@ -276,13 +278,25 @@ __global__ void __launch_bounds__(kB) k_prolong(const double* __restrict__ uc, D
   y += ly;
   z += lz;
   const bool shell = x < 0 || y < 0 || z < 0 || x >= df.n[0] || y >= df.n[1] || z >= df.n[2];
-  if (mode == 0 && (shell || covered(Hf, x, y, z))) return;
+  if (mode != 1 && shell) return;
+  if (mode == 0 && covered(Hf, x, y, z)) return;
   if (mode == 1 && !shell) return;
+  if (mode == 2 && covered(Hf, x, y, z)) {
+    uf[gx(df, x, y, z)] = 0.0;
+    return;
+  }
   const int gxg = fo0 + x, gyg = fo1 + y, gzg = fo2 + z;
   const int X = (gxg >> 1) - co0, Y = (gyg >> 1) - co1, Z = (gzg >> 1) - co2;
   const int ux = gxg & 1, uy = gyg & 1, uz = gzg & 1;
   // per axis: lower child 1/4 c[I-1] + 3/4 c[I]; upper 3/4 c[I] + 1/4 c[I+1]
-  auto lin = [](double cm, double c0, double cp, int up) { return up ? 0.75 * c0 + 0.25 * cp : 0.25 * cm + 0.75 * c0; };
+  // tricubic: lower child (5 c[I-1] + 30 c[I] - 3 c[I+1]) / 32, upper (-3, 30, 5) / 32
+  const bool cubic = mode == 2;
+  auto lin = [cubic](double cm, double c0, double cp, int up) {
+    if (cubic)
+      return up ? ((-3.0 / 32.0) * cm + (30.0 / 32.0) * c0) + (5.0 / 32.0) * cp
+                : ((5.0 / 32.0) * cm + (30.0 / 32.0) * c0) + (-3.0 / 32.0) * cp;
+    return up ? 0.75 * c0 + 0.25 * cp : 0.25 * cm + 0.75 * c0;
+  };
   double ty[3][3];
 #pragma unroll
   for (int c = -1; c <= 1; ++c)
@@ -296,6 +310,12 @@ __global__ void __launch_bounds__(kB) k_prolong(const double* __restrict__ uc, D
   const double v = lin(tz[0], tz[1], tz[2], uz);
   const size_t o = gx(df, x, y, z);
   uf[o] = mode == 0 ? uf[o] + v : v;
+}
+
+// dst = src over the whole ghosted array
+__global__ void __launch_bounds__(kB) k_copy(const double* __restrict__ src, double* __restrict__ dst, size_t n) {
+  const size_t t = (size_t)blockIdx.x * kB + threadIdx.x;
+  if (t < n) dst[t] = src[t];
 }
 
 // out = u - p on the active cells (0 on covered cells)
@@ -325,6 +345,17 @@ __global__ void __launch_bounds__(kB) k_store(const double* __restrict__ src, do
   int x, y, z;
   cell_of(t, d, x, y, z);
   dst[t] = covered(H, x, y, z) ? 0.0 : src[gx(d, x, y, z)] - c;
+}
+
+// dst = src on the active cells, 0 on covered cells (both ghosted arrays)
+__global__ void __launch_bounds__(kB) k_load_ghosted(const double* __restrict__ src, double* __restrict__ dst, Dims d,
+                                                      Hole H) {
+  const size_t t = (size_t)blockIdx.x * kB + threadIdx.x;
+  if (t >= cells(d)) return;
+  int x, y, z;
+  cell_of(t, d, x, y, z);
+  const size_t c = gx(d, x, y, z);
+  dst[c] = covered(H, x, y, z) ? 0.0 : src[c];
 }
 
 // per-block partial sums of g(v) over the active cells (what: 0 value, 1 square), fixed tree
@@ -381,6 +412,7 @@ struct PatchL {
   double h;
   Hole hole;      // cg pointers filled per use
   double *u, *f, *pbar, *dres, *tmp;
+  double* src;    // FMG: the source restricted to this level
   double* cg[6];  // coarse ghosts of the hole faces (lam < Lam)
 };
 
@@ -516,18 +548,41 @@ struct AmrRun {
   }
 
   // normal level boundary for prolongation of the corrections held in tmp at level k
-  void normal_fill(int k) {
+  // the arrays tmp (corrections, homogeneous root conditions) or u (the solution, FMG)
+  void normal_fill(int k, bool on_u = false) {
+    auto arr = [&](PatchL& p) { return on_u ? p.u : p.tmp; };
     for (int l = pl.Lam; l >= 1; --l) {
       PatchL &f = pl.P[l][k], &c = pl.P[l - 1][k];
-      restrict_into(f, f.tmp, false, c.tmp, nullptr, c, c.hole.lo);
+      restrict_into(f, arr(f), false, arr(c), nullptr, c, c.hole.lo);
     }
-    fill_phys(pl.P[0][k].tmp, pl.P[0][k].d, true);
+    fill_phys(arr(pl.P[0][k]), pl.P[0][k].d, !on_u);
     for (int l = 1; l <= pl.Lam; ++l) {
       PatchL &f = pl.P[l][k], &c = pl.P[l - 1][k];
       const int lo[3] = {-1, -1, -1};
       const int hi[3] = {f.d.n[0] + 1, f.d.n[1] + 1, f.d.n[2] + 1};
-      prolong(c, c.tmp, f, f.tmp, 1, lo, hi);
+      prolong(c, arr(c), f, arr(f), 1, lo, hi);
     }
+  }
+
+  void copy(const double* src, double* dst, const Dims& d) {
+    hipLaunchKernelGGL(k_copy, dim3(blocks(ghosted(d))), dim3(kB), 0, s, src, dst, ghosted(d));
+  }
+
+  // root level n's arrays: n = NB is the root patch, below that pl.R
+  PatchL root_level(int n) {
+    if (n == pl.NB) {
+      PatchL r = pl.P[0][0];
+      r.hole.on = 0;
+      return r;
+    }
+    for (auto& q : pl.R)
+      if (q.d.n[0] == n) return q;
+    return pl.R.back();
+  }
+  int root_index(int n) const {   // index into pl.R of the level below n
+    int q = 0;
+    for (int m = pl.NB / 2; m > n / 2 && q < (int)pl.R.size(); m /= 2) ++q;
+    return q;
   }
 
   // deterministic sum over the active cells of one patch array: host value
@@ -611,11 +666,20 @@ struct AmrRun {
       }
   }
 
-  void vcycle() {
+  // one FAS V-cycle from the top level: kind 0 MeshBlock level `level`, 1 Octet level `level`,
+  // 2 root level `level` (cells per side)
+  void vcycle(int kind = 0, int level = -1) {
     const int K = pl.K, Lam = pl.Lam;
     Hole none{};
+    if (kind == 2) {
+      PatchL top = root_level(level);
+      root_fas(root_index(level), top, top.u, top.f);
+      return;
+    }
+    const int kt = kind == 0 ? (level < 0 ? K : level) : 0;
+    const int lam_top = kind == 0 ? Lam : level;
     // ---- MeshBlock levels, down
-    for (int k = K; k >= 1; --k) {
+    for (int k = kt; k >= 1; --k) {
       smooth_level(k, npre);
       lap_level(k, 0, 0, 0, -1.0);                      // tmp = f - L u
       for (int l = 0; l <= Lam; ++l) {
@@ -626,14 +690,34 @@ struct AmrRun {
       }
       if (k - 1 >= 1) lap_level(k - 1, 1, 1, 1, 1.0);   // f = dres + L pbar
     }
+    if (kind == 1) {
+      // the uncovered cells of the coarser patches belong to this Octet level's composite
+      // problem: phibar = current value, restricted defect = their defect in that problem
+      fill_phys(pl.P[0][0].u, pl.P[0][0].d, false);
+      for (int l = 1; l <= lam_top; ++l) {
+        PatchL f = pl.P[l][0];
+        if (l == lam_top) f.hole.on = 0;
+        cons(f, f.u, pl.P[l - 1][0], pl.P[l - 1][0].u, pl.P[l - 1][0].cg);
+      }
+      for (int l = 0; l < lam_top; ++l) {
+        PatchL& p = pl.P[l][0];
+        hipLaunchKernelGGL(k_lap, dim3(blocks(cells(p.d))), dim3(kB), 0, s, p.u, p.src, p.dres, p.d, hole_of(p),
+                           1.0 / (p.h * p.h), -1.0);
+        copy(p.u, p.pbar, p.d);
+      }
+    }
     // ---- Octet levels, finest first
-    for (int l = Lam; l >= 1; --l) {
+    for (int l = lam_top; l >= 1; --l) {
       PatchL p = octet(l);
       PatchL& c = pl.P[l - 1][0];
-      cons(p, p.pbar, c, c.pbar, nullptr);
-      hipLaunchKernelGGL(k_lap, dim3(blocks(cells(p.d))), dim3(kB), 0, s, p.pbar, p.dres, p.f, p.d, none,
-                         1.0 / (p.h * p.h), 1.0);
-      (void)hipMemcpyAsync(p.u, p.pbar, ghosted(p.d) * sizeof(double), hipMemcpyDeviceToDevice, s);
+      if (!(kind == 1 && l == lam_top)) {
+        cons(p, p.pbar, c, c.pbar, nullptr);
+        hipLaunchKernelGGL(k_lap, dim3(blocks(cells(p.d))), dim3(kB), 0, s, p.pbar, p.dres, p.f, p.d, none,
+                           1.0 / (p.h * p.h), 1.0);
+        (void)hipMemcpyAsync(p.u, p.pbar, ghosted(p.d) * sizeof(double), hipMemcpyDeviceToDevice, s);
+      } else {
+        copy(p.src, p.f, p.d);
+      }
       octet_smooth(l, npre);
       cons(p, p.u, c, c.u, nullptr);
       hipLaunchKernelGGL(k_lap, dim3(blocks(cells(p.d))), dim3(kB), 0, s, p.u, p.f, p.tmp, p.d, none,
@@ -652,7 +736,7 @@ struct AmrRun {
       root_fas(0, r, r.u, r.f);
     }
     // ---- Octet levels, coarsest first
-    for (int l = 1; l <= Lam; ++l) {
+    for (int l = 1; l <= lam_top; ++l) {
       PatchL p = octet(l);
       PatchL c = pl.P[l - 1][0];
       c.hole.on = 0;
@@ -663,7 +747,7 @@ struct AmrRun {
       octet_smooth(l, npost);
     }
     // ---- MeshBlock levels, up
-    for (int k = 1; k <= K; ++k) {
+    for (int k = 1; k <= kt; ++k) {
       for (int l = 0; l <= Lam; ++l) {
         PatchL& c = pl.P[l][k - 1];
         hipLaunchKernelGGL(k_sub, dim3(blocks(cells(c.d))), dim3(kB), 0, s, c.u, c.pbar, c.tmp, c.d, c.hole);
@@ -675,6 +759,71 @@ struct AmrRun {
         prolong(c, c.tmp, p, p.u, 0, lo, hi);
       }
       smooth_level(k, npost);
+    }
+  }
+
+  // Alg. 2 on the refined hierarchy (FAS in place of the V-cycle)
+  void fmg() {
+    const int K = pl.K, Lam = pl.Lam;
+    // sources on every level
+    for (int k = K; k >= 1; --k)
+      for (int l = 0; l <= Lam; ++l) {
+        PatchL &p = pl.P[l][k], &c = pl.P[l][k - 1];
+        const int o[3] = {0, 0, 0};
+        restrict_into(p, p.f, false, c.f, nullptr, c, o);
+      }
+    for (int k = 0; k <= K; ++k)
+      for (int l = 0; l <= Lam; ++l) copy(pl.P[l][k].f, pl.P[l][k].src, pl.P[l][k].d);
+    for (int l = Lam; l >= 1; --l) {
+      PatchL p = octet(l);
+      PatchL& c = pl.P[l - 1][0];
+      restrict_into(p, p.src, false, c.src, nullptr, c, c.hole.lo);
+    }
+    {
+      PatchL prev = root_level(pl.NB);
+      for (size_t q = 0; q < pl.R.size(); ++q) {
+        const int o[3] = {0, 0, 0};
+        restrict_into(prev, prev.src, false, pl.R[q].src, nullptr, pl.R[q], o);
+        prev = pl.R[q];
+      }
+    }
+    // root levels
+    {
+      PatchL one = root_level(1);
+      copy(one.src, one.f, one.d);
+      (void)hipMemsetAsync(one.u, 0, ghosted(one.d) * sizeof(double), s);
+      hipLaunchKernelGGL(k_coarsest, dim3(1), dim3(64), 0, s, one.u, one.f, phys_for(1, false), one.h * one.h);
+      for (int n = 2; n <= pl.NB; n *= 2) {
+        PatchL c = root_level(n / 2), p = root_level(n);
+        fill_phys(c.u, c.d, false);
+        const int lo[3] = {0, 0, 0}, hi[3] = {n, n, n};
+        prolong(c, c.u, p, p.u, 2, lo, hi);
+        copy(p.src, p.f, p.d);
+        vcycle(2, n);
+      }
+    }
+    // Octet levels
+    for (int l = 1; l <= Lam; ++l) {
+      PatchL p = octet(l);
+      PatchL c = pl.P[l - 1][0];
+      c.hole.on = 0;
+      const int lo[3] = {0, 0, 0}, hi[3] = {p.d.n[0], p.d.n[1], p.d.n[2]};
+      prolong(c, c.u, p, p.u, 2, lo, hi);
+      vcycle(1, l);
+    }
+    // MeshBlock levels
+    for (int k = 1; k <= K; ++k) {
+      for (int l = 0; l <= Lam; ++l) {
+        PatchL& p = pl.P[l][k];
+        hipLaunchKernelGGL(k_load_ghosted, dim3(blocks(cells(p.d))), dim3(kB), 0, s, p.src, p.f, p.d, p.hole);
+      }
+      normal_fill(k - 1, true);
+      for (int l = 0; l <= Lam; ++l) {
+        PatchL &c = pl.P[l][k - 1], &p = pl.P[l][k];
+        const int lo[3] = {0, 0, 0}, hi[3] = {p.d.n[0], p.d.n[1], p.d.n[2]};
+        prolong(c, c.u, p, p.u, 2, lo, hi);
+      }
+      vcycle(0, k);
     }
   }
 
@@ -766,7 +915,7 @@ int amr_solve_impl(int device, const mg_params* p, const mg_amr_mesh* m, const m
   int st = amr_plan(m, pl, err);
   if (st != MG_OK) return st;
   if (!p || !bc || !rho || !phi || !hist || !n_hist) return fail_amr(err, MG_ERR_INVALID_ARG, "null argument");
-  if (p->mode != MG_MODE_MGI) return fail_amr(err, MG_ERR_UNSUPPORTED, "the refined mesh runs V-cycles from phi (MG_MODE_MGI)");
+  if (p->mode != MG_MODE_MGI && p->mode != MG_MODE_FMG) return fail_amr(err, MG_ERR_INVALID_ARG, "bad mode");
   if (p->precision != MG_PREC_FP64) return fail_amr(err, MG_ERR_UNSUPPORTED, "the refined mesh runs in FP64");
   if (std::fabs(p->dx * pl.N - 1.0) > 1e-12) return fail_amr(err, MG_ERR_INVALID_ARG, "the refined mesh spans the unit cube: dx = 1/(NB nb)");
   for (int f = 0; f < 6; ++f) {
@@ -791,7 +940,7 @@ int amr_solve_impl(int device, const mg_params* p, const mg_amr_mesh* m, const m
     return o;
   };
   struct Off {
-    size_t u, f, pbar, dres, tmp, cg[6];
+    size_t u, f, pbar, dres, tmp, src, cg[6];
   };
   std::vector<std::vector<Off>> off(pl.Lam + 1, std::vector<Off>(pl.K + 1));
   for (int l = 0; l <= pl.Lam; ++l)
@@ -803,6 +952,7 @@ int amr_solve_impl(int device, const mg_params* p, const mg_amr_mesh* m, const m
       o.pbar = take(g);
       o.dres = take(g);
       o.tmp = take(g);
+      o.src = take(g);
       for (int f = 0; f < 6; ++f) {
         o.cg[f] = (size_t)-1;
         if (pl.P[l][k].hole.on) {
@@ -820,6 +970,7 @@ int amr_solve_impl(int device, const mg_params* p, const mg_amr_mesh* m, const m
     roff[q].pbar = take(g);
     roff[q].dres = take(g);
     roff[q].tmp = take(g);
+    roff[q].src = take(g);
   }
   bool any_fixed = false;
   for (int f = 0; f < 6; ++f) any_fixed |= bc->kind[f] == MG_BC_FIXED && bc->fixed_b[f];
@@ -844,6 +995,7 @@ int amr_solve_impl(int device, const mg_params* p, const mg_amr_mesh* m, const m
       q.pbar = mem + o.pbar;
       q.dres = mem + o.dres;
       q.tmp = mem + o.tmp;
+      q.src = mem + o.src;
       for (int f = 0; f < 6; ++f) q.cg[f] = o.cg[f] == (size_t)-1 ? nullptr : mem + o.cg[f];
     }
   for (size_t q = 0; q < pl.R.size(); ++q) {
@@ -852,6 +1004,7 @@ int amr_solve_impl(int device, const mg_params* p, const mg_amr_mesh* m, const m
     pl.R[q].pbar = mem + roff[q].pbar;
     pl.R[q].dres = mem + roff[q].dres;
     pl.R[q].tmp = mem + roff[q].tmp;
+    pl.R[q].src = mem + roff[q].src;
   }
   for (size_t q = 0; q < boff.size(); ++q) pl.bface.push_back(mem + boff[q]);
   if (any_fixed) {
@@ -897,6 +1050,7 @@ int amr_solve_impl(int device, const mg_params* p, const mg_amr_mesh* m, const m
     }
   }
   const double rms_f = std::sqrt(R.volume_mean(K, 1, 1));
+  if (p->mode == MG_MODE_FMG) R.fmg();
   double r = R.residual(rms_f);
   int nh = 0;
   hist[nh++] = r;
