@@ -138,3 +138,45 @@ def test_amr_rejected_forms(mg):
         mg.amr_patch_dims(mg.amr_mesh(4, 4, [((0, 1, 1), (3, 3, 3))]), 1)    # touches the domain face
     with pytest.raises(mg.MgError, match="INVALID_ARG"):
         mg.amr_patch_dims(mg.amr_mesh(4, 4, [((1, 1, 1), (3, 3, 3)), ((2, 3, 3), (5, 5, 5))]), 2)  # no margin
+
+
+def test_binary_potential(mg):
+    """The paper's refined-mesh test (Sec. 4.3) at root resolution 1/64 with four nested levels
+    (1/1024 at the stars): FMG and 3 V-cycles as the oracle's, then to 1e-10 with the
+    normalised error against the analytic potential below 1e-3."""
+    import workloads as wl
+    print("amr binary", flush=True)
+    NB, nb = 4, 16
+    boxes = wl.binary_mesh_boxes(NB)
+    m = amr.AmrMesh(NB, nb, boxes)
+    rho = [wl.binary_density_on_axes(*m.centres(l), m.patches[l][m.K].h) for l in range(m.Lam + 1)]
+    N = NB * nb
+    x = (np.arange(N) + 0.5) / N
+    faces = []
+    for face in range(6):
+        axis, side = face // 2, face % 2
+        t = [q for q in range(3) if q != axis]
+        co = [None, None, None]
+        co[axis] = np.array(0.0 if side == 0 else 1.0)
+        co[t[0]] = x[None, :]
+        co[t[1]] = x[:, None]
+        faces.append(np.array(np.broadcast_to(wl.binary_potential(*co), (N, N))))
+    ref, rh = amr.solve(m, rho, [amr.FIXED] * 6, amr.FaceArrays(faces), cycles=3, mode="fmg")
+    mesh = mg.amr_mesh(NB, nb, boxes)
+    drho = [dev(r) for r in rho]
+    dfaces = [dev(f) for f in faces]
+    phi, hist, st = mg.amr_solve(mesh, drho, "fixed", fixed_b=dfaces, fixed_cycles=3, mode="fmg")
+    assert len(hist) == len(rh) == 4
+    for a, b in zip(hist, rh):
+        assert abs(a - b) <= 1e-6 * b + 1e-12, (hist, rh)
+    assert rel([p.cpu().numpy() for p in phi], ref) < 1e-10
+    phi, hist, st = mg.amr_solve(mesh, drho, "fixed", fixed_b=dfaces, tol=1e-10, mode="fmg")
+    assert st == mg.MG_OK
+    err = []
+    for l in range(m.Lam + 1):
+        xs, ys, zs = m.centres(l)
+        Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+        ex = wl.binary_potential(X, Y, Z)
+        err.append(((phi[l].cpu().numpy() - ex) / ex)[m.patches[l][m.K].active()])
+    e = np.concatenate(err)
+    assert math.sqrt(np.mean(e * e)) < 1e-3

@@ -323,3 +323,33 @@ def test_fmg_exact_for_linear_potentials(name):
     for l, (X, Y, Z) in enumerate(grids(m)):
         act = m.patches[l][m.K].active()
         assert np.max(np.abs(phi[l] - lin(X, Y, Z))[act]) < 1e-12, l
+
+
+def _binary(NB, nb, **kw):
+    import workloads as wl
+    m = amr.AmrMesh(NB, nb, wl.binary_mesh_boxes(NB))
+    gs = grids(m)
+    rho = [wl.binary_density_on_axes(*m.centres(l), m.patches[l][m.K].h) for l in range(m.Lam + 1)]
+    phi, hist = amr.solve(m, rho, [amr.FIXED] * 6, wl.binary_potential, mode="fmg", **kw)
+    err = []
+    for l in range(m.Lam + 1):
+        ex = wl.binary_potential(*gs[l])
+        err.append(((phi[l] - ex) / ex)[m.patches[l][m.K].active()])
+    e = np.concatenate(err)
+    return math.sqrt(np.mean(e * e)), hist
+
+
+def test_binary_potential_second_order():
+    """The paper's refined-mesh test (Sec. 4.3): the unequal-mass binary on four nested levels
+    of refinement (16x the root resolution at the stars), analytic potential on the faces.
+    The normalised error against the analytic potential is small and falls about fourfold per
+    doubling of the root resolution (measured 3.0x from h = 1/32 to 1/64, where the stars
+    span a few fine cells); FMG reaches that error within a few V-cycles (saturation:
+    measured 12x, 3.7x, 1.5x, 1.07x of it after 0, 1, 2, 3 cycles)."""
+    e8, h8 = _binary(4, 8, tol=1e-10)
+    e16, h16 = _binary(4, 16, tol=1e-10)
+    assert h16[-1] <= 1e-10 and len(h16) - 1 <= 12
+    assert e16 < 1e-3
+    assert e8 / e16 > 2.5, (e8, e16)
+    f16, _ = _binary(4, 16, cycles=3)
+    assert f16 < 1.2 * e16, (f16, e16)

@@ -112,23 +112,58 @@ def gaussian_clumps(n: int, seed: int, n_clumps: int = 64, background: float = 1
     return rho
 
 
-def clumps_on_axes(xs, ys, zs, seed: int, n_clumps: int = 32, centre=(0.5, 0.5, 0.5), spread: float = 0.08,
-                   wmin: float = 0.01, wmax: float = 0.03, background: float = 1.0) -> np.ndarray:
-    """Gaussian clumps concentrated around `centre` (centres normal with std `spread`, wrapped
-    into the unit box; widths U[wmin, wmax]; amplitudes LogNormal(0, 1)) plus a background,
-    evaluated on the tensor grid of the cell-centre axes xs, ys, zs (any resolution, so every
-    patch of a refined mesh samples the same field).  Periodic minimum-image distances.
-    Returns an array indexed [z][y][x]."""
-    rng = np.random.default_rng(seed)
-    centres = np.mod(rng.normal(centre, spread, size=(n_clumps, 3)), 1.0)
-    widths = rng.uniform(wmin, wmax, size=n_clumps)
-    amps = rng.lognormal(0.0, 1.0, size=n_clumps)
-    gx = np.stack([_periodic_gauss_1d(np.asarray(xs), float(centres[c, 0]), float(widths[c]), 1.0) for c in range(n_clumps)])
-    gy = np.stack([_periodic_gauss_1d(np.asarray(ys), float(centres[c, 1]), float(widths[c]), 1.0) for c in range(n_clumps)])
-    gz = np.stack([_periodic_gauss_1d(np.asarray(zs), float(centres[c, 2]), float(widths[c]), 1.0) for c in range(n_clumps)])
-    zc = (gz * amps[:, None]).T
-    yx = (gy[:, :, None] * gx[:, None, :]).reshape(n_clumps, len(ys) * len(xs))
-    return (zc @ yx).reshape(len(zs), len(ys), len(xs)) + background
+# The unequal-mass binary of the refined-mesh test (Sec. 4.3): two uniform spheres of radius
+# 6/1024, masses 2 and 1, on the x axis at +6/1024 and -12/1024 from the centre of the box
+# (the paper's [-0.5, 0.5]^3 shifted to the unit cube).
+BINARY_R = 6.0 / 1024.0
+BINARY_STARS = ((2.0, (0.5 + 6.0 / 1024.0, 0.5, 0.5)), (1.0, (0.5 - 12.0 / 1024.0, 0.5, 0.5)))
+
+
+def binary_density_on_axes(xs, ys, zs, h: float, subcells: int = 10) -> np.ndarray:
+    """Density of the binary on the tensor grid of cell-centre axes (cells of width h): each
+    star a uniform sphere of density M / (4/3 pi R^3); cells the surface cuts take the mean
+    over subcells^3 sub-cell centres (the paper's smoothing).  Indexed [z][y][x]."""
+    xs, ys, zs = (np.asarray(a, dtype=np.float64) for a in (xs, ys, zs))
+    rho = np.zeros((len(zs), len(ys), len(xs)))
+    half_diag = 0.5 * math.sqrt(3.0) * h
+    s = (np.arange(subcells) + 0.5) / subcells - 0.5
+    oz, oy, ox = (a.ravel() * h for a in np.meshgrid(s, s, s, indexing="ij"))
+    for M, c in BINARY_STARS:
+        dens = M / (4.0 / 3.0 * math.pi * BINARY_R ** 3)
+        dz = (zs - c[2])[:, None, None]
+        dy = (ys - c[1])[None, :, None]
+        dx = (xs - c[0])[None, None, :]
+        r = np.sqrt(dx * dx + dy * dy + dz * dz)
+        rho += np.where(r <= BINARY_R - half_diag, dens, 0.0)
+        cut = np.argwhere(np.abs(r - BINARY_R) < half_diag)
+        for s0 in range(0, cut.shape[0], 4096):
+            cc = cut[s0:s0 + 4096]
+            pz = zs[cc[:, 0]][:, None] + oz[None, :] - c[2]
+            py = ys[cc[:, 1]][:, None] + oy[None, :] - c[1]
+            px = xs[cc[:, 2]][:, None] + ox[None, :] - c[0]
+            frac = ((px * px + py * py + pz * pz) < BINARY_R * BINARY_R).mean(axis=1)
+            rho[cc[:, 0], cc[:, 1], cc[:, 2]] += dens * frac
+    return rho
+
+
+def binary_potential(x, y, z, G: float = 1.0):
+    """The binary's analytic potential: the sum of the two uniform-sphere potentials."""
+    out = 0.0
+    for M, c in BINARY_STARS:
+        out = out + sphere_potential(x, y, z, c, BINARY_R, M, G)
+    return out
+
+
+def binary_mesh_boxes(NB: int, levels: int = 4):
+    """Nested refinement boxes of the binary test: level l covers [-0.5^(l+1), 0.5^(l+1)] around
+    the centre at 2^l times the root resolution, in level-(l-1) block units (NB root blocks
+    per side, NB >= 4 a power of two)."""
+    boxes = []
+    for l in range(1, levels + 1):
+        nblk = NB << (l - 1)          # level-(l-1) blocks per side of the whole domain
+        lo = nblk // 2 - NB // 4      # half-width 0.5^(l+1) is NB/4 level-(l-1) blocks
+        boxes.append(((lo,) * 3, (nblk - lo,) * 3))
+    return boxes
 
 
 def uniform_sphere(n: int, seed: int, radius: float = 0.25, max_offset: float = 0.05,
