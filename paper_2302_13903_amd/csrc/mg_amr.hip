@@ -25,7 +25,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/mg355.h"
+#include "mg355.h"
 #include "mg_launch.h"
 
 namespace mg {

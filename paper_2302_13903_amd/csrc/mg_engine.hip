@@ -15,7 +15,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/mg355.h"
+#include "mg355.h"
 #include "mg_blocks.h"
 #include "mg_fused.h"
 #include "mg_launch.h"

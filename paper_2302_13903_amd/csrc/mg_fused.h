@@ -81,9 +81,6 @@ int fused_blk_defect_norm(const T* u, const T* f, double* part, int Lm, int Lb, 
 template <typename T>
 std::string fused_blk_pass_name(bool pro, int out);
 
-template <typename T>
-int fused_grid_blocks(int n, int hx, int hy);
-
 // Names of the pass kernels as the profiler lists them (sweep = false: the defect-only pass).
 template <typename T>
 std::string fused_pass_name(bool pro, int out, bool sweep = true);

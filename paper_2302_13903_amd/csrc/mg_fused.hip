@@ -9,7 +9,8 @@
 //   OUT=2 (NORM): after the sweep, sum of squared defects for the stopping test (Sec. 2.3.7).
 //
 // Layout of one workgroup (W wavefronts, 64 lanes each): a tile of 128 x (R*W) cells in x-y,
-// lane l holding the x-pair (x0+2l, x0+2l+1) of R consecutive rows; the workgroup marches in
+// lane l holding the x-pair (x0+2l, x0+2l+1) of R consecutive rows, or (XS = 2) a tile of
+// 64 x (2*R*W) cells with each half-wave on its own band of R rows; the workgroup marches in
 // z over a chunk of planes.  Each cell keeps a ring of RING planes of u and f in registers:
 // at the step that loads plane P, the red update runs on plane P-1, the black update on P-2
 // and the defect on P-3, so every stage reads its z-neighbours in the right colour state.
@@ -110,12 +111,49 @@ struct alignas(2 * sizeof(T)) Pair {
 //                restricted to the coarse level, or its sum of squares).
 enum : int { MODE_SWEEP = 0, MODE_MIX = 1, MODE_DEF = 2, MODE_FASDEF = 3 };
 
+// Tile shape per precision and pass kind: R rows per lane, W waves per workgroup (tile
+// 128 x R*W).  Measured: R = 2, W = 16 for most passes; the FP64 pass with the fused
+// restricted defect keeps one more plane and the most temporaries live, so it runs fewer,
+// wider lanes (R = 4, W = 8); the FP64 head pass (sweep + input norm) needs ~150 registers
+// (W = 12).  Passes without a sweep, and every pass with a norm, use R = 2, W = 16 (four rows
+// per lane for the FP32 sweep measured slower: occupancy falls from 7 to 4 waves per SIMD).
+template <typename T, bool PRO, int OUT, int MODE>
+constexpr int cfg_R() {
+  if (MODE != MODE_SWEEP) return 2;
+  if (sizeof(T) == 8 && OUT == 1) return 4;
+  return 2;
+}
+template <typename T, bool PRO, int OUT, int MODE>
+constexpr int cfg_W() {
+  if (MODE != MODE_SWEEP) return 16;
+  if (sizeof(T) == 8 && OUT == 1) return 8;
+  if (sizeof(T) == 8 && OUT == 3) return 12;
+  return 16;
+}
+// x-segments per wave: 1 = a wave spans the tile's 128 columns; 2 = each half-wave spans 64
+// columns of its own band of R rows (tile 64 x 2RW: for the same cells per workgroup, a
+// squarer tile re-reads fewer halo cells).  Measured at 512^3 with the chunking below: the
+// sweep + input norm 0.89 -> 0.77 ms, the restricted defect 0.53 -> 0.51 ms, the FP32 sweep
+// 0.40 -> 0.38 ms, the FP64 sweep unchanged.  The passes that would spill registers with
+// the extra per-lane addressing (prolongation, the sweep + norm, four-row lanes) keep 1.
+template <typename T, bool PRO, int OUT, int MODE>
+constexpr int cfg_XS() {
+  if (PRO || cfg_R<T, PRO, OUT, MODE>() != 2 || (MODE == MODE_SWEEP && OUT == 2)) return 1;
+  return 2;
+}
+
 // BLK: the level is in the MeshBlock layout (blocks of 2^A.Lm cells, Morton order); the tile
 // streams across block boundaries exactly as across a dense array (an x-pair never straddles
 // two blocks), and the coarse level is in the layout below it (blocks of 2^(A.Lm-1) cells, or
 // the dense root grid when that is one cell).
-template <typename T, int R, int W, bool PRO, int OUT, int MODE = MODE_SWEEP, bool BLK = false>
+template <typename T, int R, int W, bool PRO, int OUT, int MODE = MODE_SWEEP, bool BLK = false, int XS = 1>
 __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
+  // XS = 2: the two halves of a wave hold two row bands; the colour of a lane's cells stays
+  // wave-uniform because the bands are R (even) rows apart
+  static_assert(XS == 1 || (XS == 2 && R % 2 == 0), "x-segments: 1, or 2 with an even row count");
+  constexpr int SL = kLanes / XS;      // lanes per x-segment
+  constexpr int TX = 2 * SL;           // tile width
+  constexpr int NBAND = W * XS;        // row bands of R rows
   constexpr bool SWEEP = MODE == MODE_SWEEP;
   constexpr bool MIX = MODE == MODE_MIX;
   constexpr bool WRITE_U = MODE == MODE_SWEEP || MODE == MODE_MIX;
@@ -128,7 +166,7 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
   constexpr int DLAG = SWEEP ? 3 : 1;                  // the defect runs on plane P - DLAG
   constexpr int HZ = DSTAGE ? DLAG : 2;                // z planes loaded ahead of the chunk
   constexpr int kRing = DSTAGE ? DLAG + 2 : 4;         // u planes alive
-  __shared__ Pair<T> xch[2][W][2][kLanes];
+  __shared__ Pair<T> xch[2][NBAND][2][SL];
   // f of planes P-1, P-2, P-3 for this thread's cells: private per thread (f is only read at
   // the cell itself), kept in LDS to leave the registers to the u ring
   // (a sweep without a defect stage needs f of P-1 and P-2 only)
@@ -139,6 +177,9 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
 
   const int lane = threadIdx.x & (kLanes - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int seg = XS == 1 ? 0 : lane / SL;
+  const int xl = lane - seg * SL;        // lane within the x-segment
+  const int band = w * XS + seg;
   const int tid = threadIdx.x;
   // XCD-aware order: consecutive block ids go to different XCDs, so give each XCD a
   // contiguous run of tiles (neighbouring tiles then share that XCD's L2 for their halos).
@@ -165,7 +206,7 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
     const T inv6 = (T)(1.0 / 6.0);
 
     const int xs = tx * A.xo;                     // first output column
-    const int xa = xs - A.hx + 2 * lane;          // this lane's even column
+    const int xa = xs - A.hx + 2 * xl;            // this lane's even column
     const bool in_x = px || (xa >= 0 && xa < n);
     const int xag = xa & nm;
     const bool out_x = xa >= xs && xa < xs + A.xo && xa < n;
@@ -177,7 +218,7 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
     bool in_y[R], out_y[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int y = ys - A.hy + w * R + r;
+      const int y = ys - A.hy + band * R + r;
       yv[r] = y;
       ygv[r] = y & nm;
       in_y[r] = py || (y >= 0 && y < n);
@@ -188,8 +229,9 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
     const int zstart = z0 - HZ;
     const int nsteps = (zend - z0) + 2 * HZ;
     // does any cell of this wave touch a non-periodic face in x or y?
-    const bool wave_bnd_xy = (!px && (xs - A.hx <= 0 || xs - A.hx + kTileX - 1 >= nm)) ||
-                             (!py && (yv[0] <= 0 || yv[R - 1] >= nm));
+    const int wy0 = ys - A.hy + w * XS * R, wy1 = wy0 + XS * R - 1;   // rows of the whole wave
+    const bool wave_bnd_xy = (!px && (xs - A.hx <= 0 || xs - A.hx + TX - 1 >= nm)) ||
+                             (!py && (wy0 <= 0 || wy1 >= nm));
 
     // u: ring of kRing planes (slot = plane index mod kRing, compile-time after unrolling);
     // f: LDS slots (plane mod 3) holding planes P-1, P-2, P-3.
@@ -213,7 +255,7 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
     for (int q = 0; q < (R / 2 > 0 ? R / 2 : 1); ++q) stash[q] = (T)0;
 
     // ---- load of u on plane P (with the prolonged coarse correction added) and f on P-1
-    auto load_plane = [&](int P) __attribute__((always_inline)) {
+    auto load_plane = [&](int P, bool first) __attribute__((always_inline)) {
       const bool in_z = pz || (P >= 0 && P < n);
       const bool in_zf = pz || (P - 1 >= 0 && P - 1 < n);
       const int Pg = P & nm, Pfg = (P - 1) & nm;
@@ -249,19 +291,25 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
         // column X is interpolated in y and z, and its x-neighbours come from lanes -+1.  Only
         // the loads are issued here; prolong_apply adds the correction when the plane enters
         // the ring, so the loads are in flight during the step like the u and f prefetch.
+        // Fine plane 2Z takes coarse planes (Z-1, Z), plane 2Z+1 (Z, Z+1): an even plane
+        // reuses the taps of the odd plane before it, an odd plane keeps its predecessor's
+        // upper plane as its lower one and loads one new plane (the first plane of the
+        // march loads both).
         const T* __restrict__ ec = reinterpret_cast<const T*>(A.ec);
         const int nc = n >> 1, Lc = L - 1, Lmc = BLK ? A.Lm - 1 : 0;
         const int X = (px ? xag : xa) >> 1;
         const int Pz = pz ? Pg : P;
         const int Z = Pz >> 1;
         const int zlo = (Pz & 1) ? Z : Z - 1;          // taps (zlo, zlo+1)
+        if (first || (P & 1)) {
 #pragma unroll
-        for (int q2 = 0; q2 < R / 2; ++q2) {
-          const int Y = (py ? ygv[2 * q2] : yv[2 * q2]) >> 1;   // the pair's coarse row
+          for (int q2 = 0; q2 < R / 2; ++q2) {
+            const int Y = (py ? ygv[2 * q2] : yv[2 * q2]) >> 1;   // the pair's coarse row
 #pragma unroll
-          for (int dy = 0; dy < 3; ++dy) {
-            pc[q2][dy][0] = coarse_at(ec, nc, Lc, Lmc, X, Y - 1 + dy, zlo, A.bcc);
-            pc[q2][dy][1] = coarse_at(ec, nc, Lc, Lmc, X, Y - 1 + dy, zlo + 1, A.bcc);
+            for (int dy = 0; dy < 3; ++dy) {
+              pc[q2][dy][0] = first ? coarse_at(ec, nc, Lc, Lmc, X, Y - 1 + dy, zlo, A.bcc) : pc[q2][dy][1];
+              pc[q2][dy][1] = coarse_at(ec, nc, Lc, Lmc, X, Y - 1 + dy, zlo + 1, A.bcc);
+            }
           }
         }
       }
@@ -295,11 +343,11 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
     // ---- exchange of the band-edge rows of one plane between the wave bands
     int xbuf = 0;
     auto exchange = [&](const T (&pl)[R][2], T (&below)[2], T (&above)[2]) __attribute__((always_inline)) {
-      xch[xbuf][w][0][lane] = Pair<T>{pl[0][0], pl[0][1]};
-      xch[xbuf][w][1][lane] = Pair<T>{pl[R - 1][0], pl[R - 1][1]};
+      xch[xbuf][band][0][xl] = Pair<T>{pl[0][0], pl[0][1]};
+      xch[xbuf][band][1][xl] = Pair<T>{pl[R - 1][0], pl[R - 1][1]};
       __syncthreads();
-      const Pair<T> vb = xch[xbuf][w > 0 ? w - 1 : w][1][lane];
-      const Pair<T> va = xch[xbuf][w < W - 1 ? w + 1 : w][0][lane];
+      const Pair<T> vb = xch[xbuf][band > 0 ? band - 1 : band][1][xl];
+      const Pair<T> va = xch[xbuf][band < NBAND - 1 ? band + 1 : band][0][xl];
       below[0] = vb.a; below[1] = vb.b;
       above[0] = va.a; above[1] = va.b;
       xbuf ^= 1;
@@ -462,7 +510,7 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
       }
     };
 
-    load_plane(zstart);
+    load_plane(zstart, true);
     prolong_apply(zstart);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -476,7 +524,7 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
       const int t = g + k;
       if (t >= nsteps) return;
       const int P = zstart + t;                  // plane held in slot k
-      if (t + 1 < nsteps) load_plane(P + 1);     // prefetch; consumed at the end of the step
+      if (t + 1 < nsteps) load_plane(P + 1, false);   // prefetch; consumed at the end of the step
       constexpr int s1 = (k + kRing - 1) % kRing, s2 = (k + kRing - 2) % kRing;
       constexpr int s3 = (k + 2 * kRing - 3) % kRing, s4 = (k + 2 * kRing - 4) % kRing;
       // red on P-1 (neighbours P-2, P), black on P-2 (P-3, P-1), defect on P-3 (P-4, P-2);
@@ -540,44 +588,45 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
   }
 }
 
-// Tile shape per precision and pass kind: R rows per lane, W waves per workgroup (tile
-// 128 x R*W).  Measured: R = 2, W = 16 for most passes; the FP64 pass with the fused
-// restricted defect keeps one more plane and the most temporaries live, so it runs fewer,
-// wider lanes (R = 4, W = 8); the FP64 head pass (sweep + input norm) needs ~150 registers
-// (W = 12).  Passes without a sweep, and every pass with a norm, use R = 2, W = 16 (four rows
-// per lane for the FP32 sweep measured slower: occupancy falls from 7 to 4 waves per SIMD).
-template <typename T, bool PRO, int OUT, int MODE>
-constexpr int cfg_R() {
-  if (MODE != MODE_SWEEP) return 2;
-  if (sizeof(T) == 8 && OUT == 1) return 4;
-  return 2;
-}
-template <typename T, bool PRO, int OUT, int MODE>
-constexpr int cfg_W() {
-  if (MODE != MODE_SWEEP) return 16;
-  if (sizeof(T) == 8 && OUT == 1) return 8;
-  if (sizeof(T) == 8 && OUT == 3) return 12;
-  return 16;
+constexpr int kCUs = 256;
+
+// Planes per workgroup (even, so restriction plane pairs never straddle two chunks).  One
+// workgroup per CU is resident (LDS bound), so the grid runs in rounds of kCUs workgroups;
+// the chunk count minimises (rounds) x (planes a workgroup marches, its 2 hz halo planes
+// included).  At 512^3 this gives the 64 x 64 tiles one round of 3 chunks: the FP64 sweep
+// takes 0.665 ms, against 0.77 ms with fixed 64-plane chunks (2.5 rounds).
+int zchunk_for(int n, int tiles_xy, int hz) {
+  if (n < 256) return min(16, n);
+  int best = n;
+  long best_cost = -1;
+  for (int c = 1; c <= n / 16; ++c) {
+    int zc = (n + c - 1) / c;
+    zc += zc & 1;
+    const long chunks = (n + zc - 1) / zc;
+    const long rounds = ((long)tiles_xy * chunks + kCUs - 1) / kCUs;
+    const long cost = rounds * (zc + 2 * hz);
+    if (best_cost < 0 || cost < best_cost) best_cost = cost, best = zc;
+  }
+  return best;
 }
 
-int zchunk_for(int n) {
-  if (n >= 512) return 64;
-  if (n >= 256) return 32;
-  return 16;
-}
-
+// Launches one pass; returns its grid size (the number of partial sums a norm pass writes).
 template <typename T, bool PRO, int OUT, int MODE = MODE_SWEEP, bool BLK = false>
-void launch_pass(FusedArgs A, hipStream_t s) {
+int launch_pass(FusedArgs A, hipStream_t s) {
   constexpr int R = cfg_R<T, PRO, OUT, MODE>(), W = cfg_W<T, PRO, OUT, MODE>();
-  A.xo = kTileX - 2 * A.hx;
-  A.yo = R * W - 2 * A.hy;
-  A.zc = min(zchunk_for(A.n), A.n);
+  constexpr int XS = cfg_XS<T, PRO, OUT, MODE>();
+  constexpr bool DSTAGE = OUT == 1 || OUT == 2;
+  constexpr int HZ = DSTAGE ? (MODE == MODE_SWEEP ? 3 : 1) : 2;   // the kernel's z halo
+  A.xo = kTileX / XS - 2 * A.hx;
+  A.yo = R * W * XS - 2 * A.hy;
   A.tiles_x = (A.n + A.xo - 1) / A.xo;
   A.tiles_y = (A.n + A.yo - 1) / A.yo;
+  A.zc = zchunk_for(A.n, A.tiles_x * A.tiles_y, HZ);
   A.chunks_z = (A.n + A.zc - 1) / A.zc;
   A.ntiles = A.tiles_x * A.tiles_y * A.chunks_z;
   const int grid = (A.ntiles + 7) / 8 * 8;
-  hipLaunchKernelGGL((k_fused<T, R, W, PRO, OUT, MODE, BLK>), dim3(grid), dim3(kLanes * W), 0, s, A);
+  hipLaunchKernelGGL((k_fused<T, R, W, PRO, OUT, MODE, BLK, XS>), dim3(grid), dim3(kLanes * W), 0, s, A);
+  return grid;
 }
 
 template <typename T>
@@ -637,25 +686,13 @@ void fused_prolong_sweep(const T* uin, T* uout, const T* f, const T* ec, const L
 }
 
 template <typename T>
-int fused_grid_blocks(int n, int hx, int hy) {
-  constexpr int R = 2, W = 16;   // the tiling of the norm passes (fused or defect-only)
-  static_assert(cfg_R<T, false, 2, MODE_SWEEP>() == R && cfg_W<T, false, 2, MODE_SWEEP>() == W &&
-                    cfg_R<T, false, 2, MODE_DEF>() == R && cfg_W<T, false, 2, MODE_DEF>() == W,
-                "norm passes share one tiling");
-  const int xo = kTileX - 2 * hx, yo = R * W - 2 * hy, zc = min(zchunk_for(n), n);
-  const int nt = ((n + xo - 1) / xo) * ((n + yo - 1) / yo) * ((n + zc - 1) / zc);
-  return (nt + 7) / 8 * 8;
-}
-
-template <typename T>
 int fused_sweep_norm(const T* uin, T* uout, const T* f, double* part, int n, double h, double omega, const LevelBC& bc,
                      hipStream_t s) {
   FusedArgs A = base_args(uin, uout, f, n, h, omega, bc);
   A.hx = 4;   // sweep (2) + defect (1); even in x so lane pairs start on even columns
   A.hy = 3;
   A.part = part;
-  launch_pass<T, false, 2>(A, s);
-  return fused_grid_blocks<T>(n, 4, 3);
+  return launch_pass<T, false, 2>(A, s);
 }
 
 template <typename T>
@@ -665,12 +702,7 @@ int fused_sweep_input_norm(const T* uin, T* uout, const T* f, double* part, int 
   A.hx = 2;   // the input defect's radius (1) is inside the sweep's
   A.hy = 2;
   A.part = part;
-  launch_pass<T, false, 3>(A, s);
-  // one partial per workgroup of the launch (launch_pass's grid)
-  constexpr int R = cfg_R<T, false, 3, MODE_SWEEP>(), W = cfg_W<T, false, 3, MODE_SWEEP>();
-  const int xo = kTileX - 2 * A.hx, yo = R * W - 2 * A.hy, zc = min(zchunk_for(n), n);
-  const int nt = ((n + xo - 1) / xo) * ((n + yo - 1) / yo) * ((n + zc - 1) / zc);
-  return (nt + 7) / 8 * 8;
+  return launch_pass<T, false, 3>(A, s);   // one partial per workgroup
 }
 
 int fused_mixed_update_defect(double* phi_in, double* phi_out, const float* e, const double* f, float* r32,
@@ -681,8 +713,7 @@ int fused_mixed_update_defect(double* phi_in, double* phi_out, const float* e, c
   A.part = part;
   A.e32 = e;
   A.r32 = r32;
-  launch_pass<double, false, 2, MODE_MIX>(A, s);
-  return fused_grid_blocks<double>(n, 2, 1);
+  return launch_pass<double, false, 2, MODE_MIX>(A, s);
 }
 
 template <typename T>
@@ -714,8 +745,7 @@ int fused_defect_norm(const T* u, const T* f, double* part, int n, double h, con
   A.hy = 1;
   A.part = part;
   A.r32 = r32;
-  launch_pass<T, false, 2, MODE_DEF>(A, s);
-  return fused_grid_blocks<T>(n, 2, 1);
+  return launch_pass<T, false, 2, MODE_DEF>(A, s);
 }
 
 // ---- the same passes on a MeshBlock-layout level (blocks of 2^Lm cells, 2^Lb per side)
@@ -759,41 +789,40 @@ int fused_blk_defect_norm(const T* u, const T* f, double* part, int Lm, int Lb, 
   A.hy = 1;
   A.part = part;
   A.r32 = r32;
-  launch_pass<T, false, 2, MODE_DEF, true>(A, s);
-  return fused_grid_blocks<T>(n, 2, 1);
+  return launch_pass<T, false, 2, MODE_DEF, true>(A, s);
 }
 
-template <typename T>
-std::string kname(int R, int W, bool pro, int out, int mode, bool blk) {
-  return std::string("k_fused<") + (sizeof(T) == 8 ? "double" : "float") + ", " + std::to_string(R) + ", " +
-         std::to_string(W) + ", " + (pro ? "true" : "false") + ", " + std::to_string(out) + ", " +
-         std::to_string(mode) + ", " + (blk ? "true" : "false") + ">";
+// The kernel name as the profiler lists it.
+template <typename T, bool PRO, int OUT, int MODE, bool BLK>
+std::string kname() {
+  auto b = [](bool v) { return std::string(v ? "true" : "false"); };
+  return std::string("k_fused<") + (sizeof(T) == 8 ? "double" : "float") + ", " +
+         std::to_string(cfg_R<T, PRO, OUT, MODE>()) + ", " + std::to_string(cfg_W<T, PRO, OUT, MODE>()) + ", " +
+         b(PRO) + ", " + std::to_string(OUT) + ", " + std::to_string(MODE) + ", " + b(BLK) + ", " +
+         std::to_string(cfg_XS<T, PRO, OUT, MODE>()) + ">";
 }
 
 template <typename T>
 std::string fused_blk_pass_name(bool pro, int out) {
   // the block passes: plain or prolonging sweeps, and the defect-only restricted defect
-  if (out) return kname<T>(2, 16, false, out, MODE_DEF, true);
-  if (pro) return kname<T>(cfg_R<T, true, 0, MODE_SWEEP>(), cfg_W<T, true, 0, MODE_SWEEP>(), true, 0, MODE_SWEEP, true);
-  return kname<T>(cfg_R<T, false, 0, MODE_SWEEP>(), cfg_W<T, false, 0, MODE_SWEEP>(), false, 0, MODE_SWEEP, true);
+  if (out == 1) return kname<T, false, 1, MODE_DEF, true>();
+  if (out == 2) return kname<T, false, 2, MODE_DEF, true>();
+  if (pro) return kname<T, true, 0, MODE_SWEEP, true>();
+  return kname<T, false, 0, MODE_SWEEP, true>();
 }
 
 template <typename T>
 std::string fused_pass_name(bool pro, int out, bool sweep) {
-  if (!sweep) return kname<T>(2, 16, pro, out, MODE_DEF, false);
-  int R = 2, W = 16;
+  if (!sweep) return out == 2 ? kname<T, false, 2, MODE_DEF, false>() : kname<T, false, 1, MODE_DEF, false>();
   switch (out) {
-    case 1: R = cfg_R<T, false, 1, MODE_SWEEP>(); W = cfg_W<T, false, 1, MODE_SWEEP>(); break;
-    case 2: R = cfg_R<T, false, 2, MODE_SWEEP>(); W = cfg_W<T, false, 2, MODE_SWEEP>(); break;
-    case 3: R = cfg_R<T, false, 3, MODE_SWEEP>(); W = cfg_W<T, false, 3, MODE_SWEEP>(); break;
-    default:
-      R = pro ? cfg_R<T, true, 0, MODE_SWEEP>() : cfg_R<T, false, 0, MODE_SWEEP>();
-      W = pro ? cfg_W<T, true, 0, MODE_SWEEP>() : cfg_W<T, false, 0, MODE_SWEEP>();
+    case 1: return kname<T, false, 1, MODE_SWEEP, false>();
+    case 2: return kname<T, false, 2, MODE_SWEEP, false>();
+    case 3: return kname<T, false, 3, MODE_SWEEP, false>();
+    default: return pro ? kname<T, true, 0, MODE_SWEEP, false>() : kname<T, false, 0, MODE_SWEEP, false>();
   }
-  return kname<T>(R, W, pro, out, MODE_SWEEP, false);
 }
 
-std::string fused_fas_restrict_name() { return kname<double>(2, 16, false, 1, MODE_FASDEF, false); }
+std::string fused_fas_restrict_name() { return kname<double, false, 1, MODE_FASDEF, false>(); }
 
 #define MG_FUSED_INST(T)                                                                                        \
   template bool fused_supported<T>(int);                                                                        \
@@ -804,7 +833,6 @@ std::string fused_fas_restrict_name() { return kname<double>(2, 16, false, 1, MO
                                        const LevelBC&, hipStream_t);                                            \
   template int fused_sweep_norm<T>(const T*, T*, const T*, double*, int, double, double, const LevelBC&,         \
                                    hipStream_t);                                                                \
-  template int fused_grid_blocks<T>(int, int, int);                                                             \
   template int fused_sweep_input_norm<T>(const T*, T*, const T*, double*, int, double, double, const LevelBC&,    \
                                          hipStream_t);                                                          \
   template void fused_defect_restrict<T>(const T*, const T*, T*, T*, int, double, const LevelBC&, hipStream_t);  \

@@ -20,7 +20,7 @@
 #include <thread>
 #include <vector>
 
-#include "../../include/mg355.h"
+#include "mg355.h"
 
 namespace {
 
