@@ -279,13 +279,14 @@ struct Solver {
   }
 
   // Fusion schedule of level l's defect stages: bit 0 = restricted defect as its own pass,
-  // bit 1 = norm as its own pass.  FP64 default: separate (the fused FP64 passes run short of
-  // registers); FP32 default: fused.
+  // bit 1 = norm as its own pass.  Default: the restricted defect fused into the last
+  // pre-sweep; the norm fused into the last post-sweep in FP32 and its own pass in FP64 (the
+  // fused FP64 sweep + norm runs short of registers).
   template <typename T>
   int split_of(int l) const {
     auto it = c->pass_split.find((sizeof(T) == 8 ? 0 : 1000) + l);
     if (it != c->pass_split.end()) return it->second;
-    return sizeof(T) == 8 ? 3 : 0;
+    return sizeof(T) == 8 ? 2 : 0;
   }
 
   // FP64, dense: can the first pre-sweep of the finest level's V-cycle run as a head pass (a
@@ -1438,7 +1439,7 @@ int mg_op_down(mg_ctx* c, int n, double h, double omega, int npre, const mg_leve
     // the context's schedule, as in the solver: the restricted defect fused into the last
     // sweep or as its own pass
     auto it_split = c->pass_split.find(ilog2(n));
-    const bool sdef = it_split != c->pass_split.end() ? (it_split->second & 1) != 0 : true;
+    const bool sdef = it_split != c->pass_split.end() ? (it_split->second & 1) != 0 : false;
     double* cur = u;
     double* oth = tmp;
     for (int it = 0; it < npre; ++it) {

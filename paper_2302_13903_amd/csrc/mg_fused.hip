@@ -112,22 +112,21 @@ struct alignas(2 * sizeof(T)) Pair {
 enum : int { MODE_SWEEP = 0, MODE_MIX = 1, MODE_DEF = 2, MODE_FASDEF = 3 };
 
 // Tile shape per precision and pass kind: R rows per lane, W waves per workgroup (tile
-// 128 x R*W).  Measured: R = 2, W = 16 for most passes; the FP64 pass with the fused
-// restricted defect keeps one more plane and the most temporaries live, so it runs fewer,
-// wider lanes (R = 4, W = 8); the FP64 head pass (sweep + input norm) needs ~150 registers
-// (W = 12).  Passes without a sweep, and every pass with a norm, use R = 2, W = 16 (four rows
-// per lane for the FP32 sweep measured slower: occupancy falls from 7 to 4 waves per SIMD).
+// 128 x R*W, or 64 x 2*R*W with split waves).  Measured: R = 2, W = 16 for most passes; the
+// FP64 passes with the fused restricted defect (one more plane and the most temporaries live,
+// ~155 registers) and the FP64 head pass (sweep + input norm, ~165) run 12 waves.  At 512^3
+// the fused FP64 sweep + restricted defect takes 0.96 ms with R = 2, W = 12 and split waves,
+// 1.28 ms with R = 4, W = 8, against 0.67 + 0.51 ms as a sweep and a defect-only pass.
+// Passes without a sweep, and every pass with a norm, use R = 2, W = 16 (four rows per lane
+// for the FP32 sweep measured slower: occupancy falls from 7 to 4 waves per SIMD).
 template <typename T, bool PRO, int OUT, int MODE>
 constexpr int cfg_R() {
-  if (MODE != MODE_SWEEP) return 2;
-  if (sizeof(T) == 8 && OUT == 1) return 4;
   return 2;
 }
 template <typename T, bool PRO, int OUT, int MODE>
 constexpr int cfg_W() {
   if (MODE != MODE_SWEEP) return 16;
-  if (sizeof(T) == 8 && OUT == 1) return 8;
-  if (sizeof(T) == 8 && OUT == 3) return 12;
+  if (sizeof(T) == 8 && (OUT == 1 || OUT == 3)) return 12;
   return 16;
 }
 // x-segments per wave: 1 = a wave spans the tile's 128 columns; 2 = each half-wave spans 64
@@ -135,10 +134,10 @@ constexpr int cfg_W() {
 // squarer tile re-reads fewer halo cells).  Measured at 512^3 with the chunking below: the
 // sweep + input norm 0.89 -> 0.77 ms, the restricted defect 0.53 -> 0.51 ms, the FP32 sweep
 // 0.40 -> 0.38 ms, the FP64 sweep unchanged.  The passes that would spill registers with
-// the extra per-lane addressing (prolongation, the sweep + norm, four-row lanes) keep 1.
+// the extra per-lane addressing (prolongation, the sweep + norm) keep 1.
 template <typename T, bool PRO, int OUT, int MODE>
 constexpr int cfg_XS() {
-  if (PRO || cfg_R<T, PRO, OUT, MODE>() != 2 || (MODE == MODE_SWEEP && OUT == 2)) return 1;
+  if (PRO || (MODE == MODE_SWEEP && OUT == 2)) return 1;
   return 2;
 }
 
