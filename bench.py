@@ -9,8 +9,10 @@ in HBM.  The JSON line reports:
   value         GDoF/s per V-cycle (FP64) = n^3 / median V-cycle time, V-cycles timed with
                 HIP events inside the library during the timed steps;
   ms_per_step   wall time of one FP64 solve (set-up + FMG + cycles to tolerance);
-  roofline      the dominant kernel (finest-level smoothing): algorithmic bytes per launch /
-                its mean launch time (HIP events on the solve stream) against 8 TB/s;
+  roofline      the dominant kernel (the finest-level pass with the largest summed time):
+                algorithmic bytes per launch / its mean launch time (HIP events on the solve
+                stream) against 8 TB/s; beside it, the V-cycle's algorithmic efficiency: the
+                57 bytes per DoF a fully fused V(2,2) cycle must move, over the V-cycle time;
   cpu_baseline  the CPU oracle timed on a bounded sample of the same workload;
   mixed         the same numbers for the mixed-precision solve; p50/p99 solve latency.
   fas           the same solve with Full Approximation Scheme iterations (Alg. 3): per-cycle
@@ -106,6 +108,18 @@ def run_solves(mg, ctx, rho, n, precision, steps, warmup, tol, scheme="cs"):
         print(f"# {precision} {scheme} step {it - warmup:+d}: {1e3 * (t1 - t0):.2f} ms, cycles {len(hist) - 1}, "
               f"r = {hist[-1]:.2e}", file=sys.stderr, flush=True)
     return lat, cyc, hists, kt
+
+
+FUSED_BYTES_PER_DOF = 57.0   # fully fused V(2,2) cycle, FP64: 50 B per finest cell x 8/7 for all levels
+
+
+def v_cycle_efficiency(n: int, t_v_ms: float):
+    """The V-cycle against the traffic a fully fused V(2,2) cycle needs (read phi, f and write
+    phi and the coarse source going down; read the coarse correction, phi, f and write phi going
+    up: 50 B per finest cell, 57 B per DoF over all levels), at 8 TB/s."""
+    achieved = FUSED_BYTES_PER_DOF * n ** 3 / (t_v_ms * 1e-3) / 1e9
+    return {"bytes_per_dof": FUSED_BYTES_PER_DOF, "v_cycle_ms": t_v_ms, "achieved": achieved,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS}
 
 
 def pass_table(kt):
@@ -431,7 +445,8 @@ def main() -> int:
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": None if achieved is None else achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": dom["kernel"], "algorithmic_bytes_per_launch": dom["algorithmic_bytes_per_launch"],
-                "avg_launch_ms": dom["avg_launch_ms"], "launches": dom["launches"], "passes": passes}
+                "avg_launch_ms": dom["avg_launch_ms"], "launches": dom["launches"], "passes": passes,
+                "v_cycle_algorithmic": v_cycle_efficiency(n, t_v)}
 
     out = {
         "metric": "GDoF/s per V-cycle + % HBM roofline at 512^3; p50/p99 solve latency, mixed vs FP64",
