@@ -602,6 +602,8 @@ int zchunk_for(int n, int tiles_xy, int hz) {
     int zc = (n + c - 1) / c;
     zc += zc & 1;
     const long chunks = (n + zc - 1) / zc;
+    // a norm pass writes one partial sum per workgroup: stay within the partials buffer
+    if ((long)tiles_xy * chunks > (long)kMaxPartials * 32 - 8) continue;
     const long rounds = ((long)tiles_xy * chunks + kCUs - 1) / kCUs;
     const long cost = rounds * (zc + 2 * hz);
     if (best_cost < 0 || cost < best_cost) best_cost = cost, best = zc;
