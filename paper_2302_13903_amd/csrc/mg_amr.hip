@@ -97,10 +97,9 @@ struct Phys {
 // rules in the order z, y, x (the last-filled axis outermost), value = s u + t, which is the
 // axis-by-axis fill written out; one thread per cell of the six ghost faces (edge and corner
 // cells are reached from two or three faces and written with the same value).
-__global__ void __launch_bounds__(kB) k_fill_phys1(double* __restrict__ u, Dims d, Phys P, int hom) {
+__device__ inline void fill_phys_body(double* __restrict__ u, const Dims& d, const Phys& P, int hom, size_t t) {
   const int n0 = d.n[0] + 2, n1 = d.n[1] + 2, n2 = d.n[2] + 2;
   const size_t f0 = (size_t)n1 * n2, f1 = (size_t)n0 * n2, f2 = (size_t)n0 * n1;
-  size_t t = (size_t)blockIdx.x * kB + threadIdx.x;
   int p[3];
   if (t < 2 * f0) {
     p[0] = t < f0 ? -1 : d.n[0];
@@ -146,6 +145,14 @@ __global__ void __launch_bounds__(kB) k_fill_phys1(double* __restrict__ u, Dims 
   }
   u[gx(d, q[0], q[1], q[2])] = sgn * u[gx(d, p[0], p[1], p[2])] + add;
 }
+__global__ void __launch_bounds__(kB) k_fill_phys1(double* __restrict__ u, Dims d, Phys P, int hom) {
+  fill_phys_body(u, d, P, hom, (size_t)blockIdx.x * kB + threadIdx.x);
+}
+// number of ghost cells of the six faces (edges and corners included)
+__host__ __device__ inline size_t ghost_faces(const Dims& d) {
+  return (size_t)2 * ((size_t)(d.n[1] + 2) * (d.n[2] + 2) + (size_t)(d.n[0] + 2) * (d.n[2] + 2) +
+                      (size_t)(d.n[0] + 2) * (d.n[1] + 2));
+}
 
 // ---- conservative level boundary (eqs. transgrad, piint, lbint; lbext on the coarse side)
 struct Cons {
@@ -157,11 +164,9 @@ struct Cons {
   double* cg[6];      // coarse ghosts per face, or nullptr
 };
 
-__global__ void __launch_bounds__(kB) k_cons(Cons A) {
-  const int axis = blockIdx.y;
+__device__ inline void cons_body(const Cons& A, int axis, size_t t) {
   const int t1a = axis == 0 ? 1 : 0, t2a = axis == 2 ? 1 : 2;
   const int nf1 = A.df.n[t1a], nf2 = A.df.n[t2a];
-  const size_t t = (size_t)blockIdx.x * kB + threadIdx.x;
   if (t >= (size_t)2 * nf1 * nf2) return;
   const int side = (int)(t / ((size_t)nf1 * nf2));
   const int r = (int)(t % ((size_t)nf1 * nf2));
@@ -198,12 +203,31 @@ __global__ void __launch_bounds__(kB) k_cons(Cons A) {
   }
 }
 
+// Batched launches: one launch runs one operator on several patches of a level, patch q on
+// blockIdx.y (blockIdx.z), each with its own arguments; the blocks past a patch's own extent
+// return at the bounds check of the shared body.
+constexpr int kMaxSet = MG_AMR_MAX_LEVELS + 1;
+template <typename A>
+struct Set {
+  A a[kMaxSet];
+};
+
+__global__ void __launch_bounds__(kB) k_cons(Cons A) { cons_body(A, blockIdx.y, (size_t)blockIdx.x * kB + threadIdx.x); }
+// All ghosts of one level: the level boundaries of the ncons finer patches (axis on
+// blockIdx.y, patch on blockIdx.z) and, on blockIdx.z = ncons, the physical ghosts of the root
+// patch.  Each part reads active cells only and writes its own ghosts.
+__global__ void __launch_bounds__(kB) k_ghosts_set(Set<Cons> S, int ncons, double* __restrict__ u0, Dims d0, Phys P0,
+                                                   int hom0) {
+  const size_t t = (size_t)blockIdx.x * kB + threadIdx.x;
+  if ((int)blockIdx.z < ncons) cons_body(S.a[blockIdx.z], blockIdx.y, t);
+  else if (blockIdx.y == 0) fill_phys_body(u0, d0, P0, hom0, t);
+}
+
 // ---- RB-SOR on the active cells of one colour (eqs. rbsor1-2); colour by global parity
 // With an even x extent one work item per x-pair updates the pair's cell of this colour;
 // otherwise one work item per cell.
-__global__ void __launch_bounds__(kB) k_smooth(double* __restrict__ u, const double* __restrict__ f, Dims d, int o0,
-                                                int o1, int o2, Hole H, double h2, double omega, int colour) {
-  const size_t t = (size_t)blockIdx.x * kB + threadIdx.x;
+__device__ inline void smooth_body(double* __restrict__ u, const double* __restrict__ f, const Dims& d, int o0, int o1,
+                                   int o2, const Hole& H, double h2, double omega, int colour, size_t t) {
   int x, y, z;
   if ((d.n[0] & 1) == 0) {
     const Dims dp{{d.n[0] / 2, d.n[1], d.n[2]}};
@@ -220,12 +244,27 @@ __global__ void __launch_bounds__(kB) k_smooth(double* __restrict__ u, const dou
   const double nb = nbsum(u, d, H, x, y, z);
   u[c] = uc + omega * ((nb - h2 * f[c]) / 6.0 - uc);
 }
+__global__ void __launch_bounds__(kB) k_smooth(double* __restrict__ u, const double* __restrict__ f, Dims d, int o0,
+                                                int o1, int o2, Hole H, double h2, double omega, int colour) {
+  smooth_body(u, f, d, o0, o1, o2, H, h2, omega, colour, (size_t)blockIdx.x * kB + threadIdx.x);
+}
+struct SmoothA {
+  double* u;
+  const double* f;
+  Dims d;
+  int o[3];
+  Hole H;
+  double h2;
+};
+__global__ void __launch_bounds__(kB) k_smooth_set(Set<SmoothA> S, double omega, int colour) {
+  const SmoothA& A = S.a[blockIdx.y];
+  smooth_body(A.u, A.f, A.d, A.o[0], A.o[1], A.o[2], A.H, A.h2, omega, colour, (size_t)blockIdx.x * kB + threadIdx.x);
+}
 
 // ---- out = a + s L u on the active cells (defect: a = f, s = -1; FAS source: a = restricted
 // defect, s = +1); covered cells get 0
-__global__ void __launch_bounds__(kB) k_lap(const double* __restrict__ u, const double* __restrict__ a,
-                                             double* __restrict__ out, Dims d, Hole H, double ih2, double s) {
-  const size_t t = (size_t)blockIdx.x * kB + threadIdx.x;
+__device__ inline void lap_body(const double* __restrict__ u, const double* __restrict__ a, double* __restrict__ out,
+                                const Dims& d, const Hole& H, double ih2, double s, size_t t) {
   if (t >= cells(d)) return;
   int x, y, z;
   cell_of(t, d, x, y, z);
@@ -237,12 +276,27 @@ __global__ void __launch_bounds__(kB) k_lap(const double* __restrict__ u, const 
   const double L = (nbsum(u, d, H, x, y, z) - 6.0 * u[c]) * ih2;
   out[c] = a[c] + s * L;
 }
+__global__ void __launch_bounds__(kB) k_lap(const double* __restrict__ u, const double* __restrict__ a,
+                                             double* __restrict__ out, Dims d, Hole H, double ih2, double s) {
+  lap_body(u, a, out, d, H, ih2, s, (size_t)blockIdx.x * kB + threadIdx.x);
+}
+struct LapA {
+  const double* u;
+  const double* a;
+  double* out;
+  Dims d;
+  Hole H;
+  double ih2;
+};
+__global__ void __launch_bounds__(kB) k_lap_set(Set<LapA> S, double s) {
+  const LapA& A = S.a[blockIdx.y];
+  lap_body(A.u, A.a, A.out, A.d, A.H, A.ih2, s, (size_t)blockIdx.x * kB + threadIdx.x);
+}
 
 // ---- 8-cell mean (eq. restriction) of the fine patch into coarse cells [0, nr) written at
 // coarse local offset o; covered fine cells count as 0 when the fine hole is given
-__global__ void __launch_bounds__(kB) k_restrict(const double* __restrict__ uf, Dims df, Hole Hf, double* out1,
-                                                  double* out2, Dims dc, int o0, int o1, int o2, Dims nr) {
-  const size_t t = (size_t)blockIdx.x * kB + threadIdx.x;
+__device__ inline void restrict_body(const double* __restrict__ uf, const Dims& df, const Hole& Hf, double* out1,
+                                     double* out2, const Dims& dc, int o0, int o1, int o2, const Dims& nr, size_t t) {
   if (t >= cells(nr)) return;
   int X, Y, Z;
   cell_of(t, nr, X, Y, Z);
@@ -261,16 +315,34 @@ __global__ void __launch_bounds__(kB) k_restrict(const double* __restrict__ uf, 
   out1[o] = v;
   if (out2) out2[o] = v;
 }
+__global__ void __launch_bounds__(kB) k_restrict(const double* __restrict__ uf, Dims df, Hole Hf, double* out1,
+                                                  double* out2, Dims dc, int o0, int o1, int o2, Dims nr) {
+  restrict_body(uf, df, Hf, out1, out2, dc, o0, o1, o2, nr, (size_t)blockIdx.x * kB + threadIdx.x);
+}
+struct RestrictA {
+  const double* uf;
+  Dims df;
+  Hole Hf;
+  double* out1;
+  double* out2;
+  Dims dc;
+  int o[3];
+  Dims nr;
+};
+__global__ void __launch_bounds__(kB) k_restrict_set(Set<RestrictA> S) {
+  const RestrictA& A = S.a[blockIdx.y];
+  restrict_body(A.uf, A.df, A.Hf, A.out1, A.out2, A.dc, A.o[0], A.o[1], A.o[2], A.nr,
+                (size_t)blockIdx.x * kB + threadIdx.x);
+}
 
 // ---- prolongation, separable x then y then z as in the oracle.  Fine cells [lo, hi) per axis
 // (ghost indices allowed); parent coarse cell = (fine global >> 1) - coarse origin.
 // mode 0: trilinear (eq. trilinear), added on active fine cells; 1: trilinear, set on the
 // ghost shell only; 2: tricubic FMG prolongation (Sec. 2.3.1), set on active cells (0 on
 // covered cells).
-__global__ void __launch_bounds__(kB) k_prolong(const double* __restrict__ uc, Dims dc, int co0, int co1, int co2,
-                                                 double* __restrict__ uf, Dims df, int fo0, int fo1, int fo2,
-                                                 Hole Hf, int lx, int ly, int lz, Dims span, int mode) {
-  const size_t t = (size_t)blockIdx.x * kB + threadIdx.x;
+__device__ inline void prolong_body(const double* __restrict__ uc, const Dims& dc, int co0, int co1, int co2,
+                                    double* __restrict__ uf, const Dims& df, int fo0, int fo1, int fo2, const Hole& Hf,
+                                    int lx, int ly, int lz, const Dims& span, int mode, size_t t) {
   if (t >= cells(span)) return;
   int x, y, z;
   cell_of(t, span, x, y, z);
@@ -311,6 +383,28 @@ __global__ void __launch_bounds__(kB) k_prolong(const double* __restrict__ uc, D
   const size_t o = gx(df, x, y, z);
   uf[o] = mode == 0 ? uf[o] + v : v;
 }
+__global__ void __launch_bounds__(kB) k_prolong(const double* __restrict__ uc, Dims dc, int co0, int co1, int co2,
+                                                 double* __restrict__ uf, Dims df, int fo0, int fo1, int fo2,
+                                                 Hole Hf, int lx, int ly, int lz, Dims span, int mode) {
+  prolong_body(uc, dc, co0, co1, co2, uf, df, fo0, fo1, fo2, Hf, lx, ly, lz, span, mode,
+               (size_t)blockIdx.x * kB + threadIdx.x);
+}
+struct ProlongA {
+  const double* uc;
+  Dims dc;
+  int co[3];
+  double* uf;
+  Dims df;
+  int fo[3];
+  Hole Hf;
+  int l[3];
+  Dims span;
+};
+__global__ void __launch_bounds__(kB) k_prolong_set(Set<ProlongA> S, int mode) {
+  const ProlongA& A = S.a[blockIdx.y];
+  prolong_body(A.uc, A.dc, A.co[0], A.co[1], A.co[2], A.uf, A.df, A.fo[0], A.fo[1], A.fo[2], A.Hf, A.l[0], A.l[1], A.l[2],
+               A.span, mode, (size_t)blockIdx.x * kB + threadIdx.x);
+}
 
 // dst = src over the whole ghosted array
 __global__ void __launch_bounds__(kB) k_copy(const double* __restrict__ src, double* __restrict__ dst, size_t n) {
@@ -319,15 +413,34 @@ __global__ void __launch_bounds__(kB) k_copy(const double* __restrict__ src, dou
 }
 
 // out = u - p on the active cells (0 on covered cells)
-__global__ void __launch_bounds__(kB) k_sub(const double* __restrict__ u, const double* __restrict__ p,
-                                             double* __restrict__ out, Dims d, Hole H) {
-  const size_t t = (size_t)blockIdx.x * kB + threadIdx.x;
+__device__ inline void sub_body(const double* __restrict__ u, const double* __restrict__ p, double* __restrict__ out,
+                                const Dims& d, const Hole& H, size_t t) {
   if (t >= cells(d)) return;
   int x, y, z;
   cell_of(t, d, x, y, z);
   const size_t c = gx(d, x, y, z);
   out[c] = covered(H, x, y, z) ? 0.0 : u[c] - p[c];
 }
+__global__ void __launch_bounds__(kB) k_sub(const double* __restrict__ u, const double* __restrict__ p,
+                                             double* __restrict__ out, Dims d, Hole H) {
+  sub_body(u, p, out, d, H, (size_t)blockIdx.x * kB + threadIdx.x);
+}
+struct SubA {
+  const double* u;
+  const double* p;
+  double* out;
+  Dims d;
+  Hole H;
+};
+__global__ void __launch_bounds__(kB) k_sub_set(Set<SubA> S) {
+  const SubA& A = S.a[blockIdx.y];
+  sub_body(A.u, A.p, A.out, A.d, A.H, (size_t)blockIdx.x * kB + threadIdx.x);
+}
+
+// kernel arguments are limited to 4 KiB
+static_assert(sizeof(Set<Cons>) <= 4096 && sizeof(Set<SmoothA>) <= 4096 && sizeof(Set<LapA>) <= 4096 &&
+                  sizeof(Set<RestrictA>) <= 4096 && sizeof(Set<ProlongA>) <= 4096 && sizeof(Set<SubA>) <= 4096,
+              "batched launch arguments");
 
 // dense caller array <-> ghosted patch: a*src + c on active cells, 0 on covered cells
 __global__ void __launch_bounds__(kB) k_load(const double* __restrict__ src, double* __restrict__ dst, Dims d, Hole H,
@@ -465,13 +578,29 @@ struct AmrRun {
 
   void fill_phys(double* u, const Dims& d, bool hom) {
     const Phys P = phys_for(d.n[0], hom);
-    const size_t faces = (size_t)2 * ((size_t)(d.n[1] + 2) * (d.n[2] + 2) + (size_t)(d.n[0] + 2) * (d.n[2] + 2) +
-                                      (size_t)(d.n[0] + 2) * (d.n[1] + 2));
-    hipLaunchKernelGGL(k_fill_phys1, dim3(blocks(faces)), dim3(kB), 0, s, u, d, P, hom ? 1 : 0);
+    hipLaunchKernelGGL(k_fill_phys1, dim3(blocks(ghost_faces(d))), dim3(kB), 0, s, u, d, P, hom ? 1 : 0);
   }
 
   // conservative ghosts between fine patch (lam) and coarse patch (lam-1) at level k, using
   // arrays uf / uc; writes the coarse ghosts when cg is non-null
+  static Cons cons_args(const PatchL& fine, double* uf, const PatchL& coarse, const double* uc, double* const* cg,
+                        size_t& most) {
+    Cons A;
+    A.uf = uf;
+    A.df = fine.d;
+    A.uc = uc;
+    A.dc = coarse.d;
+    for (int a = 0; a < 3; ++a) {
+      A.lo[a] = coarse.hole.lo[a];
+      A.hi[a] = coarse.hole.hi[a];
+    }
+    for (int f = 0; f < 6; ++f) A.cg[f] = cg ? cg[f] : nullptr;
+    for (int axis = 0; axis < 3; ++axis) {
+      const int t1a = axis == 0 ? 1 : 0, t2a = axis == 2 ? 1 : 2;
+      most = std::max(most, (size_t)2 * fine.d.n[t1a] * fine.d.n[t2a]);
+    }
+    return A;
+  }
   void cons(const PatchL& fine, double* uf, const PatchL& coarse, const double* uc, double* const* cg) {
     Cons A;
     A.uf = uf;
@@ -497,37 +626,101 @@ struct AmrRun {
     return H;
   }
 
-  // ghosts of every patch at level k for the arrays sel(P) (0: u, 1: pbar)
+  // ghosts of every patch at level k for the arrays sel(P) (0: u, 1: pbar): the physical
+  // ghosts of the root patch, and the level boundary of every finer patch in one launch (each
+  // reads active cells only and writes its own ghosts, so the patches are independent)
   void fill_level(int k, int which) {
     auto arr = [&](PatchL& p) { return which == 0 ? p.u : p.pbar; };
-    fill_phys(arr(pl.P[0][k]), pl.P[0][k].d, false);
+    Set<Cons> S{};
+    size_t most = ghost_faces(pl.P[0][k].d);
     for (int l = 1; l <= pl.Lam; ++l)
-      cons(pl.P[l][k], arr(pl.P[l][k]), pl.P[l - 1][k], arr(pl.P[l - 1][k]), pl.P[l - 1][k].cg);
+      S.a[l - 1] = cons_args(pl.P[l][k], arr(pl.P[l][k]), pl.P[l - 1][k], arr(pl.P[l - 1][k]), pl.P[l - 1][k].cg, most);
+    hipLaunchKernelGGL(k_ghosts_set, dim3(blocks(most), 3, pl.Lam + 1), dim3(kB), 0, s, S, pl.Lam, arr(pl.P[0][k]),
+                       pl.P[0][k].d, phys_for(pl.P[0][k].d.n[0], false), 0);
   }
 
   void smooth_level(int k, int sweeps) {
+    Set<SmoothA> S{};
+    size_t most = 0;
+    for (int l = 0; l <= pl.Lam; ++l) {
+      PatchL& p = pl.P[l][k];
+      S.a[l] = SmoothA{p.u, p.f, p.d, {p.o[0], p.o[1], p.o[2]}, hole_of(p), p.h * p.h};
+      most = std::max(most, smooth_items(p.d));
+    }
     for (int it = 0; it < sweeps; ++it)
       for (int colour = 0; colour < 2; ++colour) {
         fill_level(k, 0);
-        for (int l = 0; l <= pl.Lam; ++l) {
-          PatchL& p = pl.P[l][k];
-          hipLaunchKernelGGL(k_smooth, dim3(blocks(smooth_items(p.d))), dim3(kB), 0, s, p.u, p.f, p.d, p.o[0], p.o[1], p.o[2],
-                             hole_of(p), p.h * p.h, omega, colour);
-        }
+        hipLaunchKernelGGL(k_smooth_set, dim3(blocks(most), pl.Lam + 1), dim3(kB), 0, s, S, omega, colour);
       }
   }
 
   // out[l] = a[l] + s L(arrays) at level k (ghosts filled first)
   void lap_level(int k, int which, int a_sel, int out_sel, double sgn) {
     fill_level(k, which);
+    Set<LapA> S{};
+    size_t most = 0;
     for (int l = 0; l <= pl.Lam; ++l) {
       PatchL& p = pl.P[l][k];
       const double* u = which == 0 ? p.u : p.pbar;
       const double* a = a_sel == 0 ? p.f : p.dres;
       double* out = out_sel == 0 ? p.tmp : p.f;
-      hipLaunchKernelGGL(k_lap, dim3(blocks(cells(p.d))), dim3(kB), 0, s, u, a, out, p.d, hole_of(p),
-                         1.0 / (p.h * p.h), sgn);
+      S.a[l] = LapA{u, a, out, p.d, hole_of(p), 1.0 / (p.h * p.h)};
+      most = std::max(most, cells(p.d));
     }
+    hipLaunchKernelGGL(k_lap_set, dim3(blocks(most), pl.Lam + 1), dim3(kB), 0, s, S, sgn);
+  }
+
+  static RestrictA restrict_args(const PatchL& fine, const double* src, bool mask, double* out1, double* out2,
+                                 const PatchL& coarse, const int o[3]) {
+    RestrictA A;
+    A.uf = src;
+    A.df = fine.d;
+    A.Hf = fine.hole;
+    if (!mask) A.Hf.on = 0;
+    A.out1 = out1;
+    A.out2 = out2;
+    A.dc = coarse.d;
+    for (int a = 0; a < 3; ++a) A.o[a] = o[a];
+    A.nr = Dims{{fine.d.n[0] / 2, fine.d.n[1] / 2, fine.d.n[2] / 2}};
+    return A;
+  }
+  // the restrictions of every patch from level k to k-1: u into pbar and u (masked: covered
+  // cells count as 0), the defect in tmp into dres
+  void restrict_level(int k) {
+    Set<RestrictA> Su{}, Sd{};
+    size_t most = 0;
+    const int o[3] = {0, 0, 0};
+    for (int l = 0; l <= pl.Lam; ++l) {
+      PatchL &p = pl.P[l][k], &c = pl.P[l][k - 1];
+      Su.a[l] = restrict_args(p, p.u, true, c.pbar, c.u, c, o);
+      Sd.a[l] = restrict_args(p, p.tmp, false, c.dres, nullptr, c, o);
+      most = std::max(most, cells(Su.a[l].nr));
+    }
+    hipLaunchKernelGGL(k_restrict_set, dim3(blocks(most), pl.Lam + 1), dim3(kB), 0, s, Su);
+    hipLaunchKernelGGL(k_restrict_set, dim3(blocks(most), pl.Lam + 1), dim3(kB), 0, s, Sd);
+  }
+  // every patch at level k-1 -> k: the prolongated correction tmp added to u (mode 0), or the
+  // FMG start from u (mode 2)
+  void prolong_level(int k, int mode) {
+    Set<ProlongA> S{};
+    size_t most = 0;
+    for (int l = 0; l <= pl.Lam; ++l) {
+      PatchL &c = pl.P[l][k - 1], &p = pl.P[l][k];
+      ProlongA& A = S.a[l];
+      A.uc = mode == 0 ? c.tmp : c.u;
+      A.dc = c.d;
+      A.uf = p.u;
+      A.df = p.d;
+      A.Hf = p.hole;
+      for (int a = 0; a < 3; ++a) {
+        A.co[a] = c.o[a];
+        A.fo[a] = p.o[a];
+        A.l[a] = 0;
+      }
+      A.span = p.d;
+      most = std::max(most, cells(p.d));
+    }
+    hipLaunchKernelGGL(k_prolong_set, dim3(blocks(most), pl.Lam + 1), dim3(kB), 0, s, S, mode);
   }
 
   void restrict_into(const PatchL& fine, const double* src, bool mask, double* out1, double* out2, const PatchL& coarse,
@@ -682,12 +875,7 @@ struct AmrRun {
     for (int k = kt; k >= 1; --k) {
       smooth_level(k, npre);
       lap_level(k, 0, 0, 0, -1.0);                      // tmp = f - L u
-      for (int l = 0; l <= Lam; ++l) {
-        PatchL &p = pl.P[l][k], &c = pl.P[l][k - 1];
-        const int o[3] = {0, 0, 0};
-        restrict_into(p, p.u, true, c.pbar, c.u, c, o);
-        restrict_into(p, p.tmp, false, c.dres, nullptr, c, o);
-      }
+      restrict_level(k);
       if (k - 1 >= 1) lap_level(k - 1, 1, 1, 1, 1.0);   // f = dres + L pbar
     }
     if (kind == 1) {
@@ -748,16 +936,16 @@ struct AmrRun {
     }
     // ---- MeshBlock levels, up
     for (int k = 1; k <= kt; ++k) {
+      Set<SubA> S{};
+      size_t most = 0;
       for (int l = 0; l <= Lam; ++l) {
         PatchL& c = pl.P[l][k - 1];
-        hipLaunchKernelGGL(k_sub, dim3(blocks(cells(c.d))), dim3(kB), 0, s, c.u, c.pbar, c.tmp, c.d, c.hole);
+        S.a[l] = SubA{c.u, c.pbar, c.tmp, c.d, c.hole};
+        most = std::max(most, cells(c.d));
       }
+      hipLaunchKernelGGL(k_sub_set, dim3(blocks(most), Lam + 1), dim3(kB), 0, s, S);
       normal_fill(k - 1);
-      for (int l = 0; l <= Lam; ++l) {
-        PatchL &c = pl.P[l][k - 1], &p = pl.P[l][k];
-        const int lo[3] = {0, 0, 0}, hi[3] = {p.d.n[0], p.d.n[1], p.d.n[2]};
-        prolong(c, c.tmp, p, p.u, 0, lo, hi);
-      }
+      prolong_level(k, 0);
       smooth_level(k, npost);
     }
   }
@@ -818,11 +1006,7 @@ struct AmrRun {
         hipLaunchKernelGGL(k_load_ghosted, dim3(blocks(cells(p.d))), dim3(kB), 0, s, p.src, p.f, p.d, p.hole);
       }
       normal_fill(k - 1, true);
-      for (int l = 0; l <= Lam; ++l) {
-        PatchL &c = pl.P[l][k - 1], &p = pl.P[l][k];
-        const int lo[3] = {0, 0, 0}, hi[3] = {p.d.n[0], p.d.n[1], p.d.n[2]};
-        prolong(c, c.u, p, p.u, 2, lo, hi);
-      }
+      prolong_level(k, 2);
       vcycle(0, k);
     }
   }
