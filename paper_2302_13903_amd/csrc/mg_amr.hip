@@ -472,15 +472,25 @@ __global__ void __launch_bounds__(kB) k_load_ghosted(const double* __restrict__ 
 }
 
 // per-block partial sums of g(v) over the active cells (what: 0 value, 1 square), fixed tree
-__global__ void __launch_bounds__(kB) k_psum(const double* __restrict__ v, Dims d, Hole H, int what,
-                                              double* __restrict__ part) {
+// Partial sums over the active cells of several patches in one launch: patch q (blockIdx.y)
+// uses its own nb blocks, block b summing cells b*kB + i + j*nb*kB into part[q * stride + b],
+// so each patch's partials and their order are fixed by its own size.
+struct SumA {
+  const double* v;
+  Dims d;
+  Hole H;
+  int nb;
+};
+__global__ void __launch_bounds__(kB) k_psum_set(Set<SumA> S, int what, double* __restrict__ part, int stride) {
+  const SumA& A = S.a[blockIdx.y];
+  if ((int)blockIdx.x >= A.nb) return;
   __shared__ double sh[kB];
   double acc = 0.0;
-  for (size_t t = (size_t)blockIdx.x * kB + threadIdx.x; t < cells(d); t += (size_t)gridDim.x * kB) {
+  for (size_t t = (size_t)blockIdx.x * kB + threadIdx.x; t < cells(A.d); t += (size_t)A.nb * kB) {
     int x, y, z;
-    cell_of(t, d, x, y, z);
-    if (covered(H, x, y, z)) continue;
-    const double a = v[gx(d, x, y, z)];
+    cell_of(t, A.d, x, y, z);
+    if (covered(A.H, x, y, z)) continue;
+    const double a = A.v[gx(A.d, x, y, z)];
     acc += what ? a * a : a;
   }
   sh[threadIdx.x] = acc;
@@ -489,7 +499,7 @@ __global__ void __launch_bounds__(kB) k_psum(const double* __restrict__ v, Dims 
     if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+  if (threadIdx.x == 0) part[(size_t)blockIdx.y * stride + blockIdx.x] = sh[0];
 }
 
 // 2 x 2 area mean of a face array (n x n) -> (n/2 x n/2)
@@ -778,23 +788,28 @@ struct AmrRun {
     return q;
   }
 
-  // deterministic sum over the active cells of one patch array: host value
-  double patch_sum(const PatchL& p, const double* v, int what) {
-    const int nb = (int)std::min<size_t>(kMaxPartials, std::max<size_t>(1, cells(p.d) / (kB * 4)));
-    hipLaunchKernelGGL(k_psum, dim3(nb), dim3(kB), 0, s, v, p.d, hole_of(p), what, part);
-    (void)hipMemcpyAsync(hpart, part, sizeof(double) * nb, hipMemcpyDeviceToHost, s);
-    (void)hipStreamSynchronize(s);
-    double acc = 0.0;
-    for (int i = 0; i < nb; ++i) acc += hpart[i];
-    return acc;
-  }
+  // cell-volume-weighted mean over the active cells of level k (all patches): one launch and
+  // one copy of the partials, summed on the host patch by patch in block order
   double volume_mean(int k, int which_arr, int what) {
-    double sum = 0.0, vol = 0.0;
+    Set<SumA> S{};
+    int most = 1;
     for (int l = 0; l <= pl.Lam; ++l) {
       const PatchL& p = pl.P[l][k];
       const double* v = which_arr == 0 ? p.u : which_arr == 1 ? p.f : p.tmp;
+      const int nb = (int)std::min<size_t>(kMaxPartials, std::max<size_t>(1, cells(p.d) / (kB * 4)));
+      S.a[l] = SumA{v, p.d, hole_of(p), nb};
+      most = std::max(most, nb);
+    }
+    hipLaunchKernelGGL(k_psum_set, dim3(most, pl.Lam + 1), dim3(kB), 0, s, S, what, part, kMaxPartials);
+    (void)hipMemcpyAsync(hpart, part, sizeof(double) * kMaxPartials * (pl.Lam + 1), hipMemcpyDeviceToHost, s);
+    (void)hipStreamSynchronize(s);
+    double sum = 0.0, vol = 0.0;
+    for (int l = 0; l <= pl.Lam; ++l) {
+      const PatchL& p = pl.P[l][k];
       const double w = p.h * p.h * p.h;
-      sum += w * patch_sum(p, v, what);
+      double acc = 0.0;
+      for (int i = 0; i < S.a[l].nb; ++i) acc += hpart[(size_t)l * kMaxPartials + i];
+      sum += w * acc;
       size_t act = cells(p.d);
       if (p.hole.on) act -= (size_t)(p.hole.hi[0] - p.hole.lo[0]) * (p.hole.hi[1] - p.hole.lo[1]) * (p.hole.hi[2] - p.hole.lo[2]);
       vol += w * (double)act;

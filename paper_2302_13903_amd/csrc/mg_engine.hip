@@ -72,7 +72,8 @@ struct mg_ctx {
   int tblock[2] = {-1, -1};
 };
 
-// refined-mesh solve (mg_amr.hip)
+// refined-mesh solve (mg_amr.hip); part: device partials (kMaxPartials x 32 doubles), hpart:
+// host partials (kMaxPartials x (MG_AMR_MAX_LEVELS + 1) doubles)
 int amr_solve_impl(int device, const mg_params* p, const mg_amr_mesh* m, const mg_bc* bc, const double* const* rho,
                    double* const* phi, double* hist, int* n_hist, void* stream, double* part, double* hpart,
                    std::string* err);
@@ -1505,7 +1506,7 @@ int mg_amr_solve(mg_ctx* c, const mg_params* p, const mg_amr_mesh* mesh, const m
                  double* const* phi, double* hist, int* n_hist, void* stream) {
   if (!c) return MG_ERR_INVALID_ARG;
   if (n_hist) *n_hist = 0;
-  std::vector<double> hpart(kMaxPartials);
+  std::vector<double> hpart((size_t)kMaxPartials * (MG_AMR_MAX_LEVELS + 1));   // one row of partials per patch
   return amr_solve_impl(c->device, p, mesh, bc, rho, phi, hist, n_hist, stream, c->part, hpart.data(), &c->err);
 }
 
