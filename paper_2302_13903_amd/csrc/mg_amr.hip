@@ -45,7 +45,7 @@ inline size_t ghosted(const Dims& d) { return (size_t)(d.n[0] + 2) * (d.n[1] + 2
 __host__ __device__ inline size_t cells(const Dims& d) { return (size_t)d.n[0] * d.n[1] * d.n[2]; }
 inline unsigned blocks(size_t work) { return (unsigned)std::max<size_t>(1, (work + kB - 1) / kB); }
 // work items of one colour of k_smooth (x-pairs when the x extent is even)
-inline size_t smooth_items(const Dims& d) { return (d.n[0] & 1) ? cells(d) : cells(d) / 2; }
+__host__ __device__ inline size_t smooth_items(const Dims& d) { return (d.n[0] & 1) ? cells(d) : cells(d) / 2; }
 
 struct Hole {
   int on;
@@ -527,6 +527,84 @@ __global__ void k_coarsest(double* u, const double* f, Phys P, double h2) {
   if (sa != 6.0) u[gx(d, 0, 0, 0)] = (sb - h2 * f[gx(d, 0, 0, 0)]) / (6.0 - sa);
 }
 
+// ---- the small root levels (kRootTailN^3 cells and below) in one workgroup: the uniform FAS
+// V-cycle of the root grid from level q0 down to the single cell and back, every operator a
+// block-strided loop followed by a barrier (the levels are cached in the CU; its waves share
+// the L1, so a barrier orders their global-memory accesses).  Same bodies, same order of
+// operations as the per-operator launches.
+constexpr int kRootTailN = 16;
+constexpr int kRootTailThreads = 1024;
+constexpr int kMaxRoot = 10;   // root levels 256^3 .. 1
+struct RootLvl {
+  Dims d;
+  double h;
+  double *u, *f, *pbar, *dres, *tmp;
+  Phys phys;   // physical conditions at this level's face points
+};
+struct RootSet {
+  RootLvl l[kMaxRoot];
+};
+
+template <typename F>
+__device__ inline void forall(size_t work, F fn) {
+  for (size_t t = threadIdx.x; t < work; t += blockDim.x) fn(t);
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(kRootTailThreads) k_root_tail(RootSet S, int q0, int npre, int npost, double omega) {
+  const Hole none{};
+  auto smooth = [&](const RootLvl& L, int sweeps) {
+    for (int it = 0; it < sweeps; ++it)
+      for (int colour = 0; colour < 2; ++colour) {
+        forall(ghost_faces(L.d), [&](size_t t) { fill_phys_body(L.u, L.d, L.phys, 0, t); });
+        forall(smooth_items(L.d),
+               [&](size_t t) { smooth_body(L.u, L.f, L.d, 0, 0, 0, none, L.h * L.h, omega, colour, t); });
+      }
+  };
+  int q = q0;
+  // down: smooth, defect, FAS restriction of u and of the defect, coarse source
+  while (S.l[q].d.n[0] > 1) {
+    const RootLvl& L = S.l[q];
+    const RootLvl& C = S.l[q + 1];
+    smooth(L, npre);
+    forall(ghost_faces(L.d), [&](size_t t) { fill_phys_body(L.u, L.d, L.phys, 0, t); });
+    forall(cells(L.d), [&](size_t t) { lap_body(L.u, L.f, L.tmp, L.d, none, 1.0 / (L.h * L.h), -1.0, t); });
+    forall(cells(C.d), [&](size_t t) {
+      restrict_body(L.u, L.d, none, C.u, C.pbar, C.d, 0, 0, 0, C.d, t);
+      restrict_body(L.tmp, L.d, none, C.dres, nullptr, C.d, 0, 0, 0, C.d, t);
+    });
+    forall(ghost_faces(C.d), [&](size_t t) { fill_phys_body(C.pbar, C.d, C.phys, 0, t); });
+    forall(cells(C.d), [&](size_t t) { lap_body(C.pbar, C.dres, C.f, C.d, none, 1.0 / (C.h * C.h), 1.0, t); });
+    ++q;
+  }
+  // the single cell
+  if (threadIdx.x == 0) {
+    const RootLvl& L = S.l[q];
+    double sa = 0.0, sb = 0.0;
+    for (int face = 0; face < 6; ++face) {
+      if (L.phys.kind[face] == BC_PERIODIC || L.phys.kind[face] == BC_ZERO_GRADIENT) {
+        sa += 1.0;
+      } else {
+        sa -= 1.0;
+        sb += 2.0 * (L.phys.b[face] ? L.phys.b[face][0] : 0.0);
+      }
+    }
+    if (sa != 6.0) L.u[gx(L.d, 0, 0, 0)] = (sb - L.h * L.h * L.f[gx(L.d, 0, 0, 0)]) / (6.0 - sa);
+  }
+  __syncthreads();
+  // up: correction u - pbar, homogeneous ghosts, trilinear prolongation added, smooth
+  for (--q; q >= q0; --q) {
+    const RootLvl& L = S.l[q];
+    const RootLvl& C = S.l[q + 1];
+    forall(cells(C.d), [&](size_t t) { sub_body(C.u, C.pbar, C.tmp, C.d, none, t); });
+    forall(ghost_faces(C.d), [&](size_t t) { fill_phys_body(C.tmp, C.d, C.phys, 1, t); });
+    forall(cells(L.d), [&](size_t t) {
+      prolong_body(C.tmp, C.d, 0, 0, 0, L.u, L.d, 0, 0, 0, none, 0, 0, 0, L.d, 0, t);
+    });
+    smooth(L, npost);
+  }
+}
+
 // =========================================================================== host plan
 
 struct PatchL {
@@ -818,9 +896,24 @@ struct AmrRun {
   }
 
   // one uniform FAS V-cycle on the root grid (NB^3 down to one cell), physical conditions
+  // the root levels as the tail kernel sees them: entry 0 the NB^3 root patch, entry i the
+  // level pl.R[i-1]
+  RootSet root_set() {
+    RootSet S{};
+    for (int i = 0; i <= (int)pl.R.size() && i < kMaxRoot; ++i) {
+      PatchL p = i == 0 ? pl.P[0][0] : pl.R[i - 1];
+      S.l[i] = RootLvl{p.d, p.h, p.u, p.f, p.pbar, p.dres, p.tmp, phys_for(p.d.n[0], false)};
+    }
+    return S;
+  }
+
   void root_fas(int q, PatchL& top, double* u, double* f) {
     // level q: q = 0 is the NB^3 root patch (u, f given), q >= 1 index into pl.R
     const int n = top.d.n[0];
+    if (n <= kRootTailN && (int)pl.R.size() < kMaxRoot && u == top.u && f == top.f) {
+      hipLaunchKernelGGL(k_root_tail, dim3(1), dim3(kRootTailThreads), 0, s, root_set(), q, npre, npost, omega);
+      return;
+    }
     if (n == 1) {
       hipLaunchKernelGGL(k_coarsest, dim3(1), dim3(64), 0, s, u, f, phys_for(1, false), top.h * top.h);
       return;

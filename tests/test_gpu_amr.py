@@ -180,3 +180,23 @@ def test_binary_potential(mg):
         err.append(((phi[l].cpu().numpy() - ex) / ex)[m.patches[l][m.K].active()])
     e = np.concatenate(err)
     assert math.sqrt(np.mean(e * e)) < 1e-3
+
+
+@pytest.mark.parametrize("mode", ["mgi", "fmg"])
+@pytest.mark.parametrize("kname", ["periodic", "fixed"])
+def test_amr_large_root_grid(mg, kname, mode):
+    """A 32^3 root grid: its upper levels run one launch per operator, the levels from 16^3
+    down in one workgroup; both as the oracle, cycle by cycle."""
+    NB, nb, boxes = 32, 2, [((12, 13, 12), (20, 19, 21))]
+    kinds = KINDS[kname]
+    print(f"amr root 32^3 {kname} {mode}", flush=True)
+    m, rho, faces = case(NB, nb, boxes, kinds, 8)
+    bf = amr.FaceArrays(faces) if kname == "fixed" else None
+    ref, rh = amr.solve(m, rho, kinds, bf, cycles=3, mode=mode)
+    phi, hist, st = mg.amr_solve(mg.amr_mesh(NB, nb, boxes), [dev(r) for r in rho], kinds,
+                                 fixed_b=[None if f is None else dev(f) for f in faces], fixed_cycles=3, mode=mode)
+    torch.cuda.synchronize()
+    assert st == mg.MG_OK and len(hist) == len(rh) == 4
+    for a, b in zip(hist, rh):
+        assert abs(a - b) <= 1e-6 * b + 1e-12, (hist, rh)
+    assert rel([p.cpu().numpy() for p in phi], ref) < 1e-10
