@@ -42,6 +42,7 @@ __host__ __device__ inline size_t gx(const Dims& d, int x, int y, int z) {
   return ((size_t)(z + 1) * (size_t)(d.n[1] + 2) + (size_t)(y + 1)) * (size_t)(d.n[0] + 2) + (size_t)(x + 1);
 }
 inline size_t ghosted(const Dims& d) { return (size_t)(d.n[0] + 2) * (d.n[1] + 2) * (d.n[2] + 2); }
+__device__ inline size_t ghosted_d(const Dims& d) { return (size_t)(d.n[0] + 2) * (d.n[1] + 2) * (d.n[2] + 2); }
 __host__ __device__ inline size_t cells(const Dims& d) { return (size_t)d.n[0] * d.n[1] * d.n[2]; }
 inline unsigned blocks(size_t work) { return (unsigned)std::max<size_t>(1, (work + kB - 1) / kB); }
 // work items of one colour of k_smooth (x-pairs when the x extent is even)
@@ -551,7 +552,7 @@ __device__ inline void forall(size_t work, F fn) {
   __syncthreads();
 }
 
-__global__ void __launch_bounds__(kRootTailThreads) k_root_tail(RootSet S, int q0, int npre, int npost, double omega) {
+__device__ void root_tail_run(const RootSet& S, int q0, int npre, int npost, double omega) {
   const Hole none{};
   auto smooth = [&](const RootLvl& L, int sweeps) {
     for (int it = 0; it < sweeps; ++it)
@@ -602,6 +603,102 @@ __global__ void __launch_bounds__(kRootTailThreads) k_root_tail(RootSet S, int q
       prolong_body(C.tmp, C.d, 0, 0, 0, L.u, L.d, 0, 0, 0, none, 0, 0, 0, L.d, 0, t);
     });
     smooth(L, npost);
+  }
+}
+
+__global__ void __launch_bounds__(kRootTailThreads) k_root_tail(RootSet S, int q0, int npre, int npost, double omega) {
+  root_tail_run(S, q0, npre, npost, omega);
+}
+
+// ---- the middle of a refined-mesh V-cycle in one workgroup: the Octet levels (one cell per
+// MeshBlock of each refinement level) finest first, the root grid, the Octet levels coarsest
+// first -- the same operators in the same order as the per-operator launches, for meshes
+// whose Octet patches and root grid are small
+constexpr int kMidMaxCells = 32768;
+struct OctL {
+  Dims d;
+  int o[3];
+  double h;
+  double *u, *f, *pbar, *dres, *tmp;
+  int hlo[3], hhi[3];   // the covered box of the next level (patch lam < Lam), local cells
+};
+struct OctSet {
+  OctL l[kMaxSet];
+};
+
+__device__ inline Cons oct_cons(const OctL& F, double* uf, const OctL& C, const double* uc) {
+  Cons A;
+  A.uf = uf;
+  A.df = F.d;
+  A.uc = uc;
+  A.dc = C.d;
+  for (int a = 0; a < 3; ++a) {
+    A.lo[a] = C.hlo[a];
+    A.hi[a] = C.hhi[a];
+  }
+  for (int f = 0; f < 6; ++f) A.cg[f] = nullptr;
+  return A;
+}
+
+__device__ inline size_t cons_most(const Dims& df) {
+  size_t m = 0;
+  for (int axis = 0; axis < 3; ++axis) {
+    const int t1a = axis == 0 ? 1 : 0, t2a = axis == 2 ? 1 : 2;
+    m = max(m, (size_t)2 * df.n[t1a] * df.n[t2a]);
+  }
+  return m;
+}
+
+__global__ void __launch_bounds__(kRootTailThreads) k_mid(OctSet O, RootSet R, int Lam, int npre, int npost,
+                                                          double omega) {
+  const Hole none{};
+  auto cons_all = [&](const Cons& A) {
+    const size_t m = cons_most(A.df);
+    forall(3 * m, [&](size_t t) { cons_body(A, (int)(t / m), t % m); });
+  };
+  auto oct_smooth = [&](const OctL& P, const OctL& C, int sweeps) {
+    for (int it = 0; it < sweeps; ++it)
+      for (int colour = 0; colour < 2; ++colour) {
+        cons_all(oct_cons(P, P.u, C, C.u));
+        forall(smooth_items(P.d), [&](size_t t) {
+          smooth_body(P.u, P.f, P.d, P.o[0], P.o[1], P.o[2], none, P.h * P.h, omega, colour, t);
+        });
+      }
+  };
+  // Octet levels, finest first
+  for (int l = Lam; l >= 1; --l) {
+    const OctL& P = O.l[l];
+    const OctL& C = O.l[l - 1];
+    cons_all(oct_cons(P, P.pbar, C, C.pbar));
+    forall(cells(P.d), [&](size_t t) { lap_body(P.pbar, P.dres, P.f, P.d, none, 1.0 / (P.h * P.h), 1.0, t); });
+    forall(ghosted_d(P.d), [&](size_t t) { P.u[t] = P.pbar[t]; });
+    oct_smooth(P, C, npre);
+    cons_all(oct_cons(P, P.u, C, C.u));
+    forall(cells(P.d), [&](size_t t) { lap_body(P.u, P.f, P.tmp, P.d, none, 1.0 / (P.h * P.h), -1.0, t); });
+    const Dims nr{{P.d.n[0] / 2, P.d.n[1] / 2, P.d.n[2] / 2}};
+    forall(cells(nr), [&](size_t t) {
+      restrict_body(P.u, P.d, none, C.pbar, C.u, C.d, C.hlo[0], C.hlo[1], C.hlo[2], nr, t);
+      restrict_body(P.tmp, P.d, none, C.dres, nullptr, C.d, C.hlo[0], C.hlo[1], C.hlo[2], nr, t);
+    });
+  }
+  // root grid
+  {
+    const RootLvl& L = R.l[0];
+    forall(ghost_faces(L.d), [&](size_t t) { fill_phys_body(L.pbar, L.d, L.phys, 0, t); });
+    forall(cells(L.d), [&](size_t t) { lap_body(L.pbar, L.dres, L.f, L.d, none, 1.0 / (L.h * L.h), 1.0, t); });
+    forall(ghosted_d(L.d), [&](size_t t) { L.u[t] = L.pbar[t]; });
+    root_tail_run(R, 0, npre, npost, omega);
+  }
+  // Octet levels, coarsest first
+  for (int l = 1; l <= Lam; ++l) {
+    const OctL& P = O.l[l];
+    const OctL& C = O.l[l - 1];
+    forall(cells(C.d), [&](size_t t) { sub_body(C.u, C.pbar, C.tmp, C.d, none, t); });
+    if (l == 1) forall(ghost_faces(C.d), [&](size_t t) { fill_phys_body(C.tmp, C.d, R.l[0].phys, 1, t); });
+    forall(cells(P.d), [&](size_t t) {
+      prolong_body(C.tmp, C.d, C.o[0], C.o[1], C.o[2], P.u, P.d, P.o[0], P.o[1], P.o[2], none, 0, 0, 0, P.d, 0, t);
+    });
+    oct_smooth(P, C, npost);
   }
 }
 
@@ -967,41 +1064,18 @@ struct AmrRun {
       }
   }
 
-  // one FAS V-cycle from the top level: kind 0 MeshBlock level `level`, 1 Octet level `level`,
-  // 2 root level `level` (cells per side)
-  void vcycle(int kind = 0, int level = -1) {
-    const int K = pl.K, Lam = pl.Lam;
+  // can the middle of a V-cycle (Octet levels, root grid) run in one workgroup?
+  bool mid_fits() const {
+    if (pl.NB > kRootTailN || (int)pl.R.size() + 1 > kMaxRoot) return false;
+    for (int l = 0; l <= pl.Lam; ++l)
+      if (cells(pl.P[l][0].d) > (size_t)kMidMaxCells) return false;
+    return true;
+  }
+
+  // the middle of a V-cycle from its top level, one launch per operator: the Octet levels
+  // finest first (from lam_top), the root grid, the Octet levels coarsest first
+  void vcycle_middle(int kind, int lam_top) {
     Hole none{};
-    if (kind == 2) {
-      PatchL top = root_level(level);
-      root_fas(root_index(level), top, top.u, top.f);
-      return;
-    }
-    const int kt = kind == 0 ? (level < 0 ? K : level) : 0;
-    const int lam_top = kind == 0 ? Lam : level;
-    // ---- MeshBlock levels, down
-    for (int k = kt; k >= 1; --k) {
-      smooth_level(k, npre);
-      lap_level(k, 0, 0, 0, -1.0);                      // tmp = f - L u
-      restrict_level(k);
-      if (k - 1 >= 1) lap_level(k - 1, 1, 1, 1, 1.0);   // f = dres + L pbar
-    }
-    if (kind == 1) {
-      // the uncovered cells of the coarser patches belong to this Octet level's composite
-      // problem: phibar = current value, restricted defect = their defect in that problem
-      fill_phys(pl.P[0][0].u, pl.P[0][0].d, false);
-      for (int l = 1; l <= lam_top; ++l) {
-        PatchL f = pl.P[l][0];
-        if (l == lam_top) f.hole.on = 0;
-        cons(f, f.u, pl.P[l - 1][0], pl.P[l - 1][0].u, pl.P[l - 1][0].cg);
-      }
-      for (int l = 0; l < lam_top; ++l) {
-        PatchL& p = pl.P[l][0];
-        hipLaunchKernelGGL(k_lap, dim3(blocks(cells(p.d))), dim3(kB), 0, s, p.u, p.src, p.dres, p.d, hole_of(p),
-                           1.0 / (p.h * p.h), -1.0);
-        copy(p.u, p.pbar, p.d);
-      }
-    }
     // ---- Octet levels, finest first
     for (int l = lam_top; l >= 1; --l) {
       PatchL p = octet(l);
@@ -1041,6 +1115,55 @@ struct AmrRun {
       const int lo[3] = {0, 0, 0}, hi[3] = {p.d.n[0], p.d.n[1], p.d.n[2]};
       prolong(c, c.tmp, p, p.u, 0, lo, hi);
       octet_smooth(l, npost);
+    }
+  }
+
+  // one FAS V-cycle from the top level: kind 0 MeshBlock level `level`, 1 Octet level `level`,
+  // 2 root level `level` (cells per side)
+  void vcycle(int kind = 0, int level = -1) {
+    const int K = pl.K, Lam = pl.Lam;
+    Hole none{};
+    if (kind == 2) {
+      PatchL top = root_level(level);
+      root_fas(root_index(level), top, top.u, top.f);
+      return;
+    }
+    const int kt = kind == 0 ? (level < 0 ? K : level) : 0;
+    const int lam_top = kind == 0 ? Lam : level;
+    // ---- MeshBlock levels, down
+    for (int k = kt; k >= 1; --k) {
+      smooth_level(k, npre);
+      lap_level(k, 0, 0, 0, -1.0);                      // tmp = f - L u
+      restrict_level(k);
+      if (k - 1 >= 1) lap_level(k - 1, 1, 1, 1, 1.0);   // f = dres + L pbar
+    }
+    if (kind == 1) {
+      // the uncovered cells of the coarser patches belong to this Octet level's composite
+      // problem: phibar = current value, restricted defect = their defect in that problem
+      fill_phys(pl.P[0][0].u, pl.P[0][0].d, false);
+      for (int l = 1; l <= lam_top; ++l) {
+        PatchL f = pl.P[l][0];
+        if (l == lam_top) f.hole.on = 0;
+        cons(f, f.u, pl.P[l - 1][0], pl.P[l - 1][0].u, pl.P[l - 1][0].cg);
+      }
+      for (int l = 0; l < lam_top; ++l) {
+        PatchL& p = pl.P[l][0];
+        hipLaunchKernelGGL(k_lap, dim3(blocks(cells(p.d))), dim3(kB), 0, s, p.u, p.src, p.dres, p.d, hole_of(p),
+                           1.0 / (p.h * p.h), -1.0);
+        copy(p.u, p.pbar, p.d);
+      }
+    }
+    if (kind == 0 && mid_fits()) {
+      // the Octet levels, the root grid and the Octet levels back in one workgroup
+      OctSet O{};
+      for (int l = 0; l <= Lam; ++l) {
+        const PatchL& p = pl.P[l][0];
+        O.l[l] = OctL{p.d, {p.o[0], p.o[1], p.o[2]}, p.h, p.u, p.f, p.pbar, p.dres, p.tmp,
+                      {p.hole.lo[0], p.hole.lo[1], p.hole.lo[2]}, {p.hole.hi[0], p.hole.hi[1], p.hole.hi[2]}};
+      }
+      hipLaunchKernelGGL(k_mid, dim3(1), dim3(kRootTailThreads), 0, s, O, root_set(), Lam, npre, npost, omega);
+    } else {
+      vcycle_middle(kind, lam_top);
     }
     // ---- MeshBlock levels, up
     for (int k = 1; k <= kt; ++k) {
