@@ -614,7 +614,7 @@ __global__ void __launch_bounds__(kRootTailThreads) k_root_tail(RootSet S, int q
 // MeshBlock of each refinement level) finest first, the root grid, the Octet levels coarsest
 // first -- the same operators in the same order as the per-operator launches, for meshes
 // whose Octet patches and root grid are small
-constexpr int kMidMaxCells = 32768;
+constexpr int kMidMaxCells = 4096;   // 16^3: four cells per thread and operator
 struct OctL {
   Dims d;
   int o[3];
