@@ -170,6 +170,9 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
   // the cell itself), kept in LDS to leave the registers to the u ring
   // (a sweep without a defect stage needs f of P-1 and P-2 only)
   constexpr int NF = DSTAGE ? 3 : 2;
+  // where the final plane is stored: after the end-of-step ring update for the FP64 passes
+  // with the prolongation or the input norm (measured 2-4 % faster there, slower elsewhere)
+  constexpr bool STORE_LAST = sizeof(T) == 8 && SWEEP && !DSTAGE && (PRO || OUT == 3);
   __shared__ Pair<T> fl[NF][R][W * kLanes];
   // INNORM: input values of plane P-2, private per thread like f
   __shared__ Pair<T> uol[INNORM ? R : 1][INNORM ? W * kLanes : 1];
@@ -532,8 +535,9 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
         half_sweep(u[s2], u[s1], u[k], P - 1, 0);
         half_sweep(u[s3], u[s2], u[s1], P - 2, 1);
       }
-      if (WRITE_U) {
-        constexpr int sf = SWEEP ? s2 : k;     // slot of the plane that is final this step
+      // the plane that is final this step goes out (ring slot sf)
+      constexpr int sf = SWEEP ? s2 : k;
+      auto store_final = [&]() __attribute__((always_inline)) {
         const int p = SWEEP ? P - 2 : P;
         if (p >= z0 && p < zend && out_x) {
           const int pg = p & nm;
@@ -548,7 +552,8 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
               __builtin_nontemporal_store(v, reinterpret_cast<ntv2*>(uout + off));
             }
         }
-      }
+      };
+      if (WRITE_U && !STORE_LAST) store_final();
       if (DSTAGE) {
         if (SWEEP) defect_out(u[s4], u[s3], u[s2], P - 3);
         else defect_out(u[s2], u[s1], u[k], P - 1);
@@ -563,6 +568,9 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
           fl[fslot(P)][r][tid] = Pair<T>{pf[r][0], pf[r][1]};
         }
       }
+      // STORE_LAST: after the prefetched plane has entered the ring (sn is never sf), so the
+      // wait for the prefetch does not cover these stores
+      if (WRITE_U && STORE_LAST) store_final();
     };
     for (int g = 0; g < nsteps; g += kRing) {
       step(g, std::integral_constant<int, 0>{});
