@@ -11,8 +11,10 @@ in HBM.  The JSON line reports:
   ms_per_step   wall time of one FP64 solve (set-up + FMG + cycles to tolerance);
   roofline      the dominant kernel (the finest-level pass with the largest summed time):
                 algorithmic bytes per launch / its mean launch time (HIP events on the solve
-                stream) against 8 TB/s; beside it, the V-cycle's algorithmic efficiency: the
-                57 bytes per DoF a fully fused V(2,2) cycle must move, over the V-cycle time;
+                stream) against 8 TB/s; beside it, the V-cycle's algorithmic efficiency (the
+                57 bytes per DoF a fully fused V(2,2) cycle must move, over the V-cycle time)
+                and its counted bytes (profiler FETCH + WRITE of the finest-level passes x 8/7,
+                over the V-cycle time);
   cpu_baseline  the CPU oracle timed on a bounded sample of the same workload;
   mixed         the same numbers for the mixed-precision solve; p50/p99 solve latency.
   fas           the same solve with Full Approximation Scheme iterations (Alg. 3): per-cycle
@@ -120,6 +122,23 @@ def v_cycle_efficiency(n: int, t_v_ms: float):
     achieved = FUSED_BYTES_PER_DOF * n ** 3 / (t_v_ms * 1e-3) / 1e9
     return {"bytes_per_dof": FUSED_BYTES_PER_DOF, "v_cycle_ms": t_v_ms, "achieved": achieved,
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS}
+
+
+def v_cycle_counted(passes, cycles: int, n: int, t_v_ms: float):
+    """The V-cycle against HBM bytes counted by the profiler: the finest-level passes' FETCH +
+    WRITE bytes per launch (the committed counter summary) times their launches per cycle, times
+    8/7 for the coarser levels (each has an eighth of the cells of the one above); None without
+    a current counter summary for every pass."""
+    tot = 0.0
+    for q in passes:
+        t = measured_traffic(q["kernel"], n)
+        if t is None:
+            return None
+        tot += t * q["launches"]
+    per_cycle = tot / max(cycles, 1) * 8.0 / 7.0
+    achieved = per_cycle / (t_v_ms * 1e-3) / 1e9
+    return {"bytes_per_cycle": per_cycle, "v_cycle_ms": t_v_ms, "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS}
 
 
 def pass_table(kt):
@@ -446,7 +465,8 @@ def main() -> int:
                 "frac": None if achieved is None else achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": dom["kernel"], "algorithmic_bytes_per_launch": dom["algorithmic_bytes_per_launch"],
                 "avg_launch_ms": dom["avg_launch_ms"], "launches": dom["launches"], "passes": passes,
-                "v_cycle_algorithmic": v_cycle_efficiency(n, t_v)}
+                "v_cycle_algorithmic": v_cycle_efficiency(n, t_v),
+                "v_cycle_counted": v_cycle_counted(passes, len(cyc), n, t_v)}
 
     out = {
         "metric": "GDoF/s per V-cycle + % HBM roofline at 512^3; p50/p99 solve latency, mixed vs FP64",

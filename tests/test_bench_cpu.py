@@ -47,3 +47,18 @@ def test_traffic_lookup_and_staleness(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "absent.json"))
     assert bench.measured_traffic("void mg::k_x<1>(int)", 512) is None
 
+
+
+def test_v_cycle_counted(tmp_path, monkeypatch):
+    f = tmp_path / "traffic.json"
+    f.write_text(json.dumps({"source_hash": bench.kernel_source_hash(),
+                             "kernels": {"k_a@512": {"bytes_per_launch": 7e9}, "k_b@512": {"bytes_per_launch": 14e9}}}))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    passes = [{"kernel": "void mg::k_a(int)", "launches": 12}, {"kernel": "void mg::k_b(int)", "launches": 6}]
+    r = bench.v_cycle_counted(passes, 6, 512, 4.0)
+    # per cycle: (2 x 7 + 1 x 14) GB x 8/7 = 32 GB in 4 ms
+    assert r["bytes_per_cycle"] == pytest.approx(32e9)
+    assert r["achieved"] == pytest.approx(8000.0)
+    assert r["frac"] == pytest.approx(1.0)
+    passes.append({"kernel": "void mg::k_c(int)", "launches": 6})
+    assert bench.v_cycle_counted(passes, 6, 512, 4.0) is None
