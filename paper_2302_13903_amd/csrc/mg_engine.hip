@@ -500,7 +500,8 @@ struct Solver {
     return false;
   }
 
-  void fas_cycle(Hier<double>& H, double* const* pbar, int l) {
+  // done: pre-sweeps of the top level already run by the head pass (result in u2)
+  void fas_cycle(Hier<double>& H, double* const* pbar, int l, int done = 0) {
     if (l == 0) {
       // the single cell with its physical conditions, from the iterate phibar; when no face
       // fixes the zero point any value solves it and phibar is kept (zero correction)
@@ -512,13 +513,25 @@ struct Solver {
     const bool timed = timed_top && l == H.L && c->ktiming;
     const double cellsT = (double)cells(l) * sizeof(double);
     const bool streamed = use_fused && H.u2[l] && n >= fused_min_n64;
-    double* cur = fas_sweeps(H, l, H.u[l], H.npre, bc);                                      // 1
+    // 1: the pre-sweeps; on streamed levels the last one carries steps 2-4 (fused below)
+    const int pre = H.npre - done;
+    const bool fuse = streamed && pre >= 1;
+    double* cur = fas_sweeps(H, l, done > 0 ? H.u2[l] : H.u[l], fuse ? pre - 1 : pre, bc);
     // 2-4 and the coarse start of 6: restricted defect, phibar, u_{l-1} = phibar; algorithmic
-    // bytes: u and f read, three coarse arrays written
+    // bytes: u and f read, three coarse arrays written (+ u written with the sweep)
     if (timed) kernel_begin();
-    if (streamed) fused_fas_restrict(cur, H.f[l], H.f[l - 1], pbar[l - 1], H.u[l - 1], n, H.h[l], bc, s);
-    else launch_fas_restrict(cur, H.f[l], H.f[l - 1], pbar[l - 1], H.u[l - 1], n, H.h[l], bc, s);
-    if (timed) kernel_end(streamed ? fused_fas_restrict_name() : "k_fas_restrict", 2 * cellsT + 3 * cellsT / 8);
+    if (fuse) {
+      double* oth = cur == H.u[l] ? H.u2[l] : H.u[l];
+      fused_sweep_fas_restrict(cur, oth, H.f[l], H.f[l - 1], pbar[l - 1], H.u[l - 1], n, H.h[l], H.omega, bc, s);
+      cur = oth;
+    } else if (streamed) {
+      fused_fas_restrict(cur, H.f[l], H.f[l - 1], pbar[l - 1], H.u[l - 1], n, H.h[l], bc, s);
+    } else {
+      launch_fas_restrict(cur, H.f[l], H.f[l - 1], pbar[l - 1], H.u[l - 1], n, H.h[l], bc, s);
+    }
+    if (timed)
+      kernel_end(streamed ? fused_fas_restrict_name(fuse) : "k_fas_restrict",
+                 (fuse ? 3 * cellsT : 2 * cellsT) + 3 * cellsT / 8);
     launch_fas_source(pbar[l - 1], H.f[l - 1], n / 2, H.h[l - 1], H.phys[l - 1], s);         // 5
     fas_cycle(H, pbar, l - 1);                                                               // 6
     launch_fas_correction(H.u[l - 1], pbar[l - 1], cells(l - 1), s);                         // 7
@@ -956,7 +969,8 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
   }
   // ---- residual of the start (Sec. 2.3.7); mixed: also its FP32 copy as the inner RHS.  FP64
   // on the fused path: taken by the head pass, which is also the first sweep of V-cycle 1
-  const bool head_mode = !mixed && !fas && Lb < 0 && S.head_possible(H64);
+  // (of the FAS cycle 1 with the Full Approximation Scheme)
+  const bool head_mode = !mixed && Lb < 0 && S.head_possible(H64);
   if (head_mode) S.head(H64, phys[L]);
   else S.defect_norm(phi, f64L, mixed ? H32.f[L] : nullptr, p->n, p->dx, phys[L], c->scal + 2);
   HIP_CHECK(c, hipEventRecord(c->ev_fmg, s));
@@ -989,8 +1003,11 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
     for (int cyc = 0; cyc < ncyc; ++cyc) {
       S.timed_top = true;
       if (fas) {
-        S.fas_cycle(H64, pbar, L);
-        S.defect_norm(phi, f64L, nullptr, p->n, p->dx, phys[L], c->scal + 2);
+        // as below: the head pass of the next cycle measures this cycle's result
+        S.fas_cycle(H64, pbar, L, head_mode ? 1 : 0);
+        S.head_done = false;
+        if (head_mode && cyc + 1 < ncyc) S.head(H64, phys[L]);
+        else S.defect_norm(phi, f64L, nullptr, p->n, p->dx, phys[L], c->scal + 2);
       } else if (head_mode) {
         // the rest of this V-cycle (its first sweep ran in the head pass), then the head of the
         // next one, which measures this cycle's result; after the last allowed cycle the

@@ -89,6 +89,9 @@ std::string fused_pass_name(bool pro, int out, bool sweep = true);
 // fc = restricted defect f - L u, pbar = uc = restricted u.
 void fused_fas_restrict(const double* u, const double* f, double* fc, double* pbar, double* uc, int n, double h,
                         const LevelBC& bc, hipStream_t s);
-std::string fused_fas_restrict_name();
+// One sweep, then the same restriction stage as fused_fas_restrict on the swept u (uout).
+void fused_sweep_fas_restrict(const double* uin, double* uout, const double* f, double* fc, double* pbar, double* uc,
+                              int n, double h, double omega, const LevelBC& bc, hipStream_t s);
+std::string fused_fas_restrict_name(bool sweep = false);
 
 }  // namespace mg

@@ -109,7 +109,9 @@ struct alignas(2 * sizeof(T)) Pair {
 //                coarse start uc0;
 //   MODE_DEF   : no sweep, u is not written: only the OUT stage on the input u (the defect
 //                restricted to the coarse level, or its sum of squares).
-enum : int { MODE_SWEEP = 0, MODE_MIX = 1, MODE_DEF = 2, MODE_FASDEF = 3 };
+//   MODE_SWEEPFAS: one sweep, then the MODE_FASDEF stage on the swept u (the last pre-sweep
+//                of a FAS cycle with its restriction).
+enum : int { MODE_SWEEP = 0, MODE_MIX = 1, MODE_DEF = 2, MODE_FASDEF = 3, MODE_SWEEPFAS = 4 };
 
 // Tile shape per precision and pass kind: R rows per lane, W waves per workgroup (tile
 // 128 x R*W, or 64 x 2*R*W with split waves).  Measured: R = 2, W = 16 for most passes; the
@@ -125,7 +127,7 @@ constexpr int cfg_R() {
 }
 template <typename T, bool PRO, int OUT, int MODE>
 constexpr int cfg_W() {
-  if (MODE != MODE_SWEEP) return 16;
+  if (MODE != MODE_SWEEP && MODE != MODE_SWEEPFAS) return 16;
   if (sizeof(T) == 8 && (OUT == 1 || OUT == 3)) return 12;
   return 16;
 }
@@ -153,10 +155,10 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
   constexpr int SL = kLanes / XS;      // lanes per x-segment
   constexpr int TX = 2 * SL;           // tile width
   constexpr int NBAND = W * XS;        // row bands of R rows
-  constexpr bool SWEEP = MODE == MODE_SWEEP;
+  constexpr bool SWEEP = MODE == MODE_SWEEP || MODE == MODE_SWEEPFAS;
   constexpr bool MIX = MODE == MODE_MIX;
-  constexpr bool WRITE_U = MODE == MODE_SWEEP || MODE == MODE_MIX;
-  constexpr bool FASR = MODE == MODE_FASDEF;
+  constexpr bool WRITE_U = SWEEP || MODE == MODE_MIX;
+  constexpr bool FASR = MODE == MODE_FASDEF || MODE == MODE_SWEEPFAS;
   static_assert(!FASR || OUT == 1, "the FAS restriction rides on the restricted-defect stage");
   // OUT = 3 (with a sweep): the sum of squared defects of the INPUT u, taken in the red stage
   // before it updates the plane (no defect stage behind the sweep)
@@ -625,7 +627,7 @@ int launch_pass(FusedArgs A, hipStream_t s) {
   constexpr int R = cfg_R<T, PRO, OUT, MODE>(), W = cfg_W<T, PRO, OUT, MODE>();
   constexpr int XS = cfg_XS<T, PRO, OUT, MODE>();
   constexpr bool DSTAGE = OUT == 1 || OUT == 2;
-  constexpr int HZ = DSTAGE ? (MODE == MODE_SWEEP ? 3 : 1) : 2;   // the kernel's z halo
+  constexpr int HZ = DSTAGE ? (MODE == MODE_SWEEP || MODE == MODE_SWEEPFAS ? 3 : 1) : 2;   // the kernel's z halo
   A.xo = kTileX / XS - 2 * A.hx;
   A.yo = R * W * XS - 2 * A.hy;
   A.tiles_x = (A.n + A.xo - 1) / A.xo;
@@ -746,6 +748,17 @@ void fused_fas_restrict(const double* u, const double* f, double* fc, double* pb
   launch_pass<double, false, 1, MODE_FASDEF>(A, s);
 }
 
+void fused_sweep_fas_restrict(const double* uin, double* uout, const double* f, double* fc, double* pbar, double* uc,
+                              int n, double h, double omega, const LevelBC& bc, hipStream_t s) {
+  FusedArgs A = base_args(uin, uout, f, n, h, omega, bc);
+  A.hx = 4;   // sweep (2) + defect (1), rounded up to even: restriction pairs align
+  A.hy = 4;
+  A.fc = fc;
+  A.uc0 = uc;
+  A.pbar = pbar;
+  launch_pass<double, false, 1, MODE_SWEEPFAS>(A, s);
+}
+
 template <typename T>
 int fused_defect_norm(const T* u, const T* f, double* part, int n, double h, const LevelBC& bc, hipStream_t s,
                       float* r32) {
@@ -831,7 +844,9 @@ std::string fused_pass_name(bool pro, int out, bool sweep) {
   }
 }
 
-std::string fused_fas_restrict_name() { return kname<double, false, 1, MODE_FASDEF, false>(); }
+std::string fused_fas_restrict_name(bool sweep) {
+  return sweep ? kname<double, false, 1, MODE_SWEEPFAS, false>() : kname<double, false, 1, MODE_FASDEF, false>();
+}
 
 #define MG_FUSED_INST(T)                                                                                        \
   template bool fused_supported<T>(int);                                                                        \

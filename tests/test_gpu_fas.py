@@ -110,3 +110,28 @@ def test_fas_unsupported_forms(mg):
         mg.solve(rho, 1.0 / n, "periodic", scheme="fas", precision="mixed")
     with pytest.raises(mg.MgError, match="UNSUPPORTED"):
         mg.solve(mg.to_blocks(rho, 8), 1.0 / n, "periodic", scheme="fas", layout="blocks", block_n=8)
+
+
+@pytest.mark.parametrize("npre,npost", [(1, 1), (1, 2), (3, 2)])
+def test_fas_sweep_counts_streamed(mg, npre, npost):
+    """Streamed FAS levels with other sweep counts: the head pass takes the first pre-sweep (or
+    the only one), the last remaining pre-sweep carries the restriction, or the restriction
+    runs on its own; cycle by cycle as the oracle."""
+    n = 128
+    kinds = [PERIODIC, PERIODIC, FIXED, FIXED, ZERO_GRADIENT, ZERO_GRADIENT]
+    print(f"fas sweeps {npre},{npost}", flush=True)
+    rng = np.random.default_rng(7)
+    rho = wl.gaussian_clumps(n, 22, n_clumps=6, remove_mean=False)
+    faces = [rng.uniform(-0.5, 0.5, (n, n)) if k == FIXED else None for k in kinds]
+    ref, rh, _ = oracle.solve(rho, 1.0 / n, kinds, fixed_b=faces, fixed_cycles=4, npre=npre, npost=npost,
+                              scheme="fas")
+    ctx = mg.Context(0)
+    ctx.set_tuning("fusedmin fp64 64\n")
+    got, gh, st = mg.solve(dev(rho), 1.0 / n, kinds, fixed_b=[None if b is None else dev(b) for b in faces],
+                           fixed_cycles=4, npre=npre, npost=npost, scheme="fas", ctx=ctx)
+    got = got.cpu().numpy()
+    assert st == mg.MG_OK and rel(got, ref) < 1e-10
+    fl = floor_of(ref, rho, kinds)
+    assert len(gh) == len(rh) == 5
+    for a, b in zip(gh, rh):
+        assert abs(a - b) <= 1e-6 * b + 10 * fl, (gh, list(rh), fl)
