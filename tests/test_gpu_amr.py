@@ -200,3 +200,26 @@ def test_amr_large_root_grid(mg, kname, mode):
     for a, b in zip(hist, rh):
         assert abs(a - b) <= 1e-6 * b + 1e-12, (hist, rh)
     assert rel([p.cpu().numpy() for p in phi], ref) < 1e-10
+
+
+@pytest.mark.parametrize("mode", ["mgi", "fmg"])
+def test_amr_six_levels(mg, mode):
+    """Six nested refinement levels (seven patches per MeshBlock level in one batched launch,
+    seven Octet levels in the single-workgroup middle of the cycle): as the oracle."""
+    boxes, lo = [], 1
+    for _ in range(6):
+        boxes.append(((lo, lo, lo), (lo + 2, lo + 2, lo + 2)))
+        lo = 2 * lo + 1
+    NB, nb = 4, 4
+    kinds = KINDS["mixed"]
+    print(f"amr six levels {mode}", flush=True)
+    m, rho, faces = case(NB, nb, boxes, kinds, 12)
+    bf = amr.FaceArrays([f if f is not None else np.zeros((NB * nb,) * 2) for f in faces])
+    ref, rh = amr.solve(m, rho, kinds, bf, cycles=3, mode=mode)
+    phi, hist, st = mg.amr_solve(mg.amr_mesh(NB, nb, boxes), [dev(r) for r in rho], kinds,
+                                 fixed_b=[None if f is None else dev(f) for f in faces], fixed_cycles=3, mode=mode)
+    torch.cuda.synchronize()
+    assert st == mg.MG_OK and len(hist) == len(rh) == 4
+    for a, b in zip(hist, rh):
+        assert abs(a - b) <= 1e-6 * b + 1e-12, (hist, rh)
+    assert rel([p.cpu().numpy() for p in phi], ref) < 1e-10
