@@ -626,6 +626,8 @@ struct OctSet {
   OctL l[kMaxSet];
 };
 
+static_assert(sizeof(OctSet) + sizeof(RootSet) + 64 <= 4096, "k_mid arguments are limited to 4 KiB");
+
 __device__ inline Cons oct_cons(const OctL& F, double* uf, const OctL& C, const double* uc) {
   Cons A;
   A.uf = uf;
