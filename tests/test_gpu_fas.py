@@ -135,3 +135,23 @@ def test_fas_sweep_counts_streamed(mg, npre, npost):
     assert len(gh) == len(rh) == 5
     for a, b in zip(gh, rh):
         assert abs(a - b) <= 1e-6 * b + 10 * fl, (gh, list(rh), fl)
+
+
+@pytest.mark.parametrize("name", ["periodic", "fixed"])
+def test_fas_tolerance_streamed(mg, name):
+    """FAS to a tolerance on streamed levels: the head pass of each next cycle measures the
+    cycle's result and is discarded when the test stops; cycle count and potential as the
+    oracle's."""
+    n = 128
+    kinds = KIND_SETS[name]
+    print(f"fas tol streamed {name}", flush=True)
+    rng = np.random.default_rng(31)
+    rho = wl.gaussian_clumps(n, 23, n_clumps=6, remove_mean=name == "periodic")
+    faces = [rng.uniform(-0.5, 0.5, (n, n)) if k == FIXED else None for k in kinds]
+    ref, rh, _ = oracle.solve(rho, 1.0 / n, kinds, fixed_b=faces, tol=1e-9, scheme="fas")
+    ctx = mg.Context(0)
+    ctx.set_tuning("fusedmin fp64 64\n")
+    got, gh, st = mg.solve(dev(rho), 1.0 / n, kinds, fixed_b=[None if b is None else dev(b) for b in faces],
+                           tol=1e-9, scheme="fas", ctx=ctx)
+    assert st == mg.MG_OK and len(gh) == len(rh)
+    assert rel(got.cpu().numpy(), ref) < 1e-10
