@@ -84,6 +84,10 @@ def _load():
     lib.oracle_multipole_potential.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp,
                                                ctypes.c_int, _dp, ctypes.c_double]
     lib.oracle_multipole_potential.restype = ctypes.c_double
+    lib.oracle_multipole_moments_points.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, ctypes.c_int, ctypes.c_int,
+                                                    _dp, _dp, _dp]
+    lib.oracle_multipole_potential_points.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, ctypes.c_int, _dp,
+                                                      ctypes.c_double, _dp]
     lib.oracle_gravity.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, _ip, ctypes.POINTER(_dp), _dp, _dp,
                                    _dp]
     lib.oracle_num_threads.restype = ctypes.c_int
@@ -351,6 +355,31 @@ def multipole_potential(x, y, z, q, origin, lmax=4, G=1.0):
     q = _f64(q)
     o = _f64(origin)
     return lib.oracle_multipole_potential(float(x), float(y), float(z), _ptr(q), int(lmax), _ptr(o), float(G))
+
+
+def multipole_moments_points(x, y, z, mass, lmax=4, origin=None):
+    """Origin (centre of mass of the points unless given, 0.5 each for zero mass) and the 25
+    moments Q_lm of point masses (Appendix A summed over cells given as points)."""
+    lib = _load()
+    x, y, z, mass = (_f64(np.ravel(a)) for a in (x, y, z, mass))
+    org = _f64(origin if origin is not None else np.zeros(3))
+    out_o = np.zeros(3)
+    q = np.zeros(25)
+    lib.oracle_multipole_moments_points(x.size, _ptr(x), _ptr(y), _ptr(z), _ptr(mass), int(lmax),
+                                        int(origin is not None), _ptr(org), _ptr(out_o), _ptr(q))
+    return out_o, q
+
+
+def multipole_potential_points(x, y, z, q, origin, lmax=4, G=1.0):
+    """The truncated expansion (Appendix A) at arrays of points; returns an array of their shape."""
+    lib = _load()
+    shape = np.shape(x)
+    x, y, z = (_f64(np.ravel(a)) for a in np.broadcast_arrays(x, y, z))
+    q, o = _f64(q), _f64(origin)
+    out = np.zeros(x.size)
+    lib.oracle_multipole_potential_points(x.size, _ptr(x), _ptr(y), _ptr(z), _ptr(q), int(lmax), _ptr(o),
+                                          float(G), _ptr(out))
+    return out.reshape(shape)
 
 
 def extend_face(b):

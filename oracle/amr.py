@@ -33,7 +33,11 @@ Readings of the paper taken here (and in the GPU path):
     corrections psi - phibar are prolongated with the normal level boundary and homogeneous
     physical conditions;
   - domain faces are periodic, zero-gradient or fixed (b given as a function of position,
-    evaluated at every level's face points, as the multipole values of the uniform solver).
+    evaluated at every level's face points, as the multipole values of the uniform solver);
+  - multipole faces (Appendix A) take their moments over the composite grid: every active cell
+    of every patch at the finest MG level, at its centre with mass rho h^3 (covered cells
+    excluded, since the finer patch holds that mass); the truncated expansion is evaluated at
+    the face centres of every root level (N, N/2, .., 1 cells per side), not area-averaged.
 Parity unpinned parts: none beyond the pins of tests/test_oracle_amr.py.
 """
 from __future__ import annotations
@@ -210,6 +214,52 @@ class FaceArrays:
 
     def point(self, face):
         return float(self.levels[1][face][0, 0])
+
+
+def composite_moments(mesh: "AmrMesh", rho, lmax: int = 4, origin=None):
+    """Appendix A on the refined mesh: origin (composite centre of mass unless given) and the
+    25 moments Q_lm, summed over the active cells of every patch at the finest MG level (each
+    cell at its centre, mass rho h^3); rho[lam] is indexed [z][y][x], covered cells ignored."""
+    from . import multipole_moments_points
+    xs, ys, zs, ms = [], [], [], []
+    for lam in range(mesh.Lam + 1):
+        p = mesh.patches[lam][mesh.K]
+        cx, cy, cz = mesh.centres(lam)
+        Z, Y, X = np.meshgrid(cz, cy, cx, indexing="ij")
+        a = p.active()
+        xs.append(X[a])
+        ys.append(Y[a])
+        zs.append(Z[a])
+        ms.append(np.asarray(rho[lam], dtype=np.float64)[a] * p.h ** 3)
+    return multipole_moments_points(np.concatenate(xs), np.concatenate(ys), np.concatenate(zs),
+                                    np.concatenate(ms), lmax, origin)
+
+
+class MultipoleFaces(FaceArrays):
+    """Multipole faces (Appendix A) of the unit cube: the truncated expansion with moments q
+    about `origin`, evaluated at the face centres of each root level of n = N, N/2, .., 1
+    cells per side (arrays [t2][t1] like FaceArrays)."""
+
+    def __init__(self, N: int, q, origin, lmax: int = 4, G: float = 1.0):
+        from . import multipole_potential_points
+        self.levels = {}
+        n = N
+        while n >= 1:
+            t = (np.arange(n) + 0.5) / n
+            T2, T1 = np.meshgrid(t, t, indexing="ij")
+            faces = []
+            for face in range(6):
+                axis, P = face // 2, np.full_like(T1, 1.0 if face & 1 else 0.0)
+                x, y, z = (P, T1, T2) if axis == 0 else (T1, P, T2) if axis == 1 else (T1, T2, P)
+                faces.append(multipole_potential_points(x, y, z, q, origin, lmax, G))
+            self.levels[n] = faces
+            n //= 2
+
+
+def multipole_faces(mesh: "AmrMesh", rho, lmax: int = 4, origin=None, G: float = 1.0) -> MultipoleFaces:
+    """Open (multipole) boundary values for the refined mesh from its composite moments."""
+    o, q = composite_moments(mesh, rho, lmax, origin)
+    return MultipoleFaces(mesh.NB * mesh.nb, q, o, lmax, G)
 
 
 # ------------------------------------------------------------------ conservative level boundary

@@ -336,6 +336,47 @@ double oracle_multipole_potential(double x, double y, double z, const double *q,
   return -G * phi;
 }
 
+/* Appendix A over a set of point masses (a composite mesh's active cells, each at its centre
+ * with mass rho dV): origin (centre of mass unless given) and the moments Q_lm. */
+void oracle_multipole_moments_points(int npts, const double *x, const double *y, const double *z,
+                                     const double *mass, int lmax, int use_origin,
+                                     const double *origin_in, double *origin_out, double *q) {
+  double ox, oy, oz;
+  if (use_origin) {
+    ox = origin_in[0]; oy = origin_in[1]; oz = origin_in[2];
+  } else {
+    double m = 0.0, mx = 0.0, my = 0.0, mz = 0.0;
+    for (int p = 0; p < npts; ++p) {
+      m += mass[p];
+      mx += mass[p] * x[p];
+      my += mass[p] * y[p];
+      mz += mass[p] * z[p];
+    }
+    if (fabs(m) < 1e-300) {
+      ox = oy = oz = 0.5;
+    } else {
+      ox = mx / m; oy = my / m; oz = mz / m;
+    }
+  }
+  origin_out[0] = ox; origin_out[1] = oy; origin_out[2] = oz;
+  for (int t = 0; t < 25; ++t) q[t] = 0.0;
+  for (int p = 0; p < npts; ++p) {
+    double s[25];
+    solid_harmonics(x[p] - ox, y[p] - oy, z[p] - oz, s);
+    for (int l = 0; l <= lmax; ++l) {
+      double cl = sqrt(4.0 * PI / (2.0 * l + 1.0));
+      for (int m = -l; m <= l; ++m) q[l * l + l + m] += mass[p] * cl * s[l * l + l + m];
+    }
+  }
+}
+
+/* The truncated expansion at npts points. */
+void oracle_multipole_potential_points(int npts, const double *x, const double *y, const double *z,
+                                       const double *q, int lmax, const double *origin, double G,
+                                       double *out) {
+  for (int p = 0; p < npts; ++p) out[p] = oracle_multipole_potential(x[p], y[p], z[p], q, lmax, origin, G);
+}
+
 /* Multipole boundary values at the face points of a level with nl cells of width hl:
  * out[face] is an extended (nl+2)^2 array over transverse positions (t+1/2) hl, t=-1..nl. */
 static void multipole_faces(int nl, double hl, double length, const double *q, int lmax,
