@@ -253,8 +253,11 @@ int mg_amr_patch_dims(const mg_amr_mesh *mesh, int lam, int dims[3]);
  * boundary with physical root conditions for the ghosts) and runs one V-cycle from each.
  *   p     dx = 1/(NB nb) (the unit cube); mode, four_pi_g, npre, npost, omega, tol,
  *         max_cycles, fixed_cycles as for mg_solve; precision FP64 (else MG_ERR_UNSUPPORTED).
- *   bc    periodic, zero-gradient or fixed faces (fixed_b: device (NB nb)^2 face-centre
- *         arrays; coarser levels take 2 x 2 area means); multipole: MG_ERR_UNSUPPORTED.
+ *   bc    periodic, zero-gradient, fixed (fixed_b: device (NB nb)^2 face-centre arrays;
+ *         coarser levels take 2 x 2 area means) or multipole faces (Appendix A: moments up
+ *         to lmax over the composite grid, every patch's active cells at their centres,
+ *         about the composite centre of mass or origin; the expansion evaluated at the face
+ *         centres of every root level).
  *   rho   host array of levels+1 device pointers, patch lam's density (dims of
  *         mg_amr_patch_dims, x fastest), read only.
  *   phi   host array of levels+1 device pointers, same shapes: the initial guess on input

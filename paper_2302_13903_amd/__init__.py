@@ -369,16 +369,18 @@ def mg_amr_solve(ctx: Context, p: _abi.MgParams, mesh: _abi.MgAmrMesh, bc: _abi.
 
 def amr_solve(mesh: _abi.MgAmrMesh, rho, bc="periodic", fixed_b=None, phi=None, tol: float = 1e-10,
               max_cycles: int = 50, fixed_cycles: int = 0, npre: int = 2, npost: int = 2, omega: float = 1.15,
-              mode: str = "mgi", four_pi_g: float = 4.0 * math.pi, ctx: Optional[Context] = None, stream=None):
+              mode: str = "mgi", four_pi_g: float = 4.0 * math.pi, lmax: int = 4, origin=None,
+              ctx: Optional[Context] = None, stream=None):
     """Solve on a statically refined mesh: FMG (mode "fmg") or V-cycles from phi (zero by
     default).  rho: list of float64 device tensors, one per patch (shape (nz, ny, nx) from
-    amr_patch_dims).  Returns (phi list, hist, status)."""
+    amr_patch_dims).  Multipole faces expand the composite density about its centre of mass
+    (or `origin`) up to lmax.  Returns (phi list, hist, status)."""
     import torch
     ctx = ctx or default_context(rho[0].device.index or 0)
     N = mesh.NB * mesh.nb
     p = params(N, 1.0 / N, tol=tol, max_cycles=max_cycles, fixed_cycles=fixed_cycles, npre=npre, npost=npost,
                omega=omega, mode=mode, four_pi_g=four_pi_g)
-    b = boundary(bc, fixed_b)
+    b = boundary(bc, fixed_b, lmax, origin)
     if phi is None:
         phi = [torch.zeros_like(r) for r in rho]
     st, hist = mg_amr_solve(ctx, p, mesh, b, rho, phi, stream)

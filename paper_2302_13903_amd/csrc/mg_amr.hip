@@ -627,6 +627,7 @@ struct OctSet {
 };
 
 static_assert(sizeof(OctSet) + sizeof(RootSet) + 64 <= 4096, "k_mid arguments are limited to 4 KiB");
+static_assert(kMpMaxBoxes >= MG_AMR_MAX_LEVELS + 1, "one multipole box per refinement level");
 
 __device__ inline Cons oct_cons(const OctL& F, double* uf, const OctL& C, const double* uc) {
   Cons A;
@@ -1335,10 +1336,12 @@ int amr_solve_impl(int device, const mg_params* p, const mg_amr_mesh* m, const m
   if (p->mode != MG_MODE_MGI && p->mode != MG_MODE_FMG) return fail_amr(err, MG_ERR_INVALID_ARG, "bad mode");
   if (p->precision != MG_PREC_FP64) return fail_amr(err, MG_ERR_UNSUPPORTED, "the refined mesh runs in FP64");
   if (std::fabs(p->dx * pl.N - 1.0) > 1e-12) return fail_amr(err, MG_ERR_INVALID_ARG, "the refined mesh spans the unit cube: dx = 1/(NB nb)");
+  bool any_mp = false;
   for (int f = 0; f < 6; ++f) {
-    if (bc->kind[f] == MG_BC_MULTIPOLE) return fail_amr(err, MG_ERR_UNSUPPORTED, "multipole faces on the refined mesh");
-    if (bc->kind[f] < 0 || bc->kind[f] > MG_BC_FIXED) return fail_amr(err, MG_ERR_INVALID_ARG, "bad face kind");
+    if (bc->kind[f] < 0 || bc->kind[f] > MG_BC_MULTIPOLE) return fail_amr(err, MG_ERR_INVALID_ARG, "bad face kind");
+    any_mp |= bc->kind[f] == MG_BC_MULTIPOLE;
   }
+  if (any_mp && (bc->lmax < 0 || bc->lmax > 4)) return fail_amr(err, MG_ERR_INVALID_ARG, "lmax outside 0..4");
   for (int a = 0; a < 3; ++a)
     if ((bc->kind[2 * a] == MG_BC_PERIODIC) != (bc->kind[2 * a + 1] == MG_BC_PERIODIC))
       return fail_amr(err, MG_ERR_INVALID_ARG, "periodic faces must be paired per axis");
@@ -1389,7 +1392,7 @@ int amr_solve_impl(int device, const mg_params* p, const mg_amr_mesh* m, const m
     roff[q].tmp = take(g);
     roff[q].src = take(g);
   }
-  bool any_fixed = false;
+  bool any_fixed = any_mp;
   for (int f = 0; f < 6; ++f) any_fixed |= bc->kind[f] == MG_BC_FIXED && bc->fixed_b[f];
   std::vector<size_t> boff;
   if (any_fixed)
@@ -1397,6 +1400,9 @@ int amr_solve_impl(int device, const mg_params* p, const mg_amr_mesh* m, const m
       pl.bface_n.push_back(n);
       boff.push_back(take((size_t)6 * n * n));
     }
+  // multipole moments: per-block partials of every patch, then origin and Q_lm (32 values)
+  const size_t mp_part = any_mp ? take((size_t)multipole_box_blocks() * (pl.Lam + 1) * 25) : 0;
+  const size_t mp_scratch = any_mp ? take(32) : 0;
   double* mem = nullptr;
   if (hipMalloc(&mem, total * sizeof(double)) != hipSuccess) {
     (void)hipGetLastError();
@@ -1427,6 +1433,7 @@ int amr_solve_impl(int device, const mg_params* p, const mg_amr_mesh* m, const m
   if (any_fixed) {
     const int N = pl.N;
     for (int f = 0; f < 6; ++f) {
+      if (bc->kind[f] == MG_BC_MULTIPOLE) continue;
       if (bc->kind[f] == MG_BC_FIXED && bc->fixed_b[f])
         (void)hipMemcpyAsync(pl.bface[0] + (size_t)f * N * N, bc->fixed_b[f], sizeof(double) * N * N,
                              hipMemcpyDeviceToDevice, s);
@@ -1437,19 +1444,47 @@ int amr_solve_impl(int device, const mg_params* p, const mg_amr_mesh* m, const m
       }
     }
   }
+  if (any_mp) {
+    // Appendix A over the composite grid: the active cells of every patch at the finest
+    // level; the expansion is then evaluated at the face centres of every root level
+    MpBox boxes[kMpMaxBoxes];
+    for (int l = 0; l <= pl.Lam; ++l) {
+      const PatchL& q = pl.P[l][pl.K];
+      MpBox& B = boxes[l];
+      B.rho = rho[l];
+      B.h = q.h;
+      for (int a = 0; a < 3; ++a) {
+        B.n[a] = q.d.n[a];
+        B.o[a] = q.o[a];
+        B.hlo[a] = q.hole.on ? q.hole.lo[a] : 0;
+        B.hhi[a] = q.hole.on ? q.hole.hi[a] : 0;
+      }
+    }
+    double* mps = mem + mp_scratch;
+    launch_multipole_moments_boxes(boxes, pl.Lam + 1, bc->lmax, bc->use_origin, bc->origin, 0.5, mem + mp_part, mps,
+                                   s);
+    const double G = p->four_pi_g / (4.0 * M_PI);
+    for (size_t q = 0; q < pl.bface.size(); ++q) {
+      const int n = pl.bface_n[q];
+      double* out[6];
+      for (int f = 0; f < 6; ++f)
+        out[f] = bc->kind[f] == MG_BC_MULTIPOLE ? pl.bface[q] + (size_t)f * n * n : nullptr;
+      launch_multipole_faces(mps, bc->lmax, G, n, 1.0 / n, 1.0, out, s, 0);
+    }
+  }
 
   AmrRun R;
   R.pl = pl;
   R.s = s;
   R.part = part;
   R.hpart = hpart;
-  for (int f = 0; f < 6; ++f) R.kinds[f] = bc->kind[f];
+  for (int f = 0; f < 6; ++f) R.kinds[f] = bc->kind[f] == MG_BC_MULTIPOLE ? MG_BC_FIXED : bc->kind[f];
   R.npre = p->npre;
   R.npost = p->npost;
   R.omega = p->omega;
   R.gauge_free = true;
   for (int f = 0; f < 6; ++f)
-    if (bc->kind[f] == MG_BC_FIXED) R.gauge_free = false;
+    if (bc->kind[f] == MG_BC_FIXED || bc->kind[f] == MG_BC_MULTIPOLE) R.gauge_free = false;
 
   // ---- source and initial guess on the finest level
   const int K = pl.K;

@@ -85,8 +85,21 @@ void launch_face_restrict(const double* ef, double* ec, int nc, hipStream_t s);
 // rho of n^3 cells, dense (Lm = 0) or in the MeshBlock layout with 2^Lm-cell blocks
 void launch_multipole_moments(const double* rho, int n, int Lm, double dx, int lmax, int use_origin,
                               const double* origin_host, double* part, double* scratch, hipStream_t s);
+// faces[f]: (nl + 2 ext)^2 values over transverse positions (t + 1/2) hl, t = -ext .. nl - 1 + ext
 void launch_multipole_faces(const double* scratch, int lmax, double G, int nl, double hl, double length,
-                            double* faces[6], hipStream_t s);
+                            double* faces[6], hipStream_t s, int ext = 1);
+// Moments over the cells of up to kMpMaxBoxes boxes (dense, x fastest), skipping each box's
+// covered sub-box [hlo, hhi); cell (i, j, k) of a box sits at ((o + i + 1/2) h, ..).  part holds
+// multipole_box_blocks() * nbox * 25 doubles; scratch as above.
+constexpr int kMpMaxBoxes = 9;
+struct MpBox {
+  const double* rho;
+  int n[3], o[3], hlo[3], hhi[3];
+  double h;
+};
+int multipole_box_blocks();
+void launch_multipole_moments_boxes(const MpBox* boxes, int nbox, int lmax, int use_origin, const double* origin_host,
+                                    double centre, double* part, double* scratch, hipStream_t s);
 
 // gravitational acceleration (mg_gravity.hip): g, rhog (3 n^3 each) and gface (3 n^2 (n+1),
 // dense layout only) from phi, any of them null; returns the number of workgroups launched

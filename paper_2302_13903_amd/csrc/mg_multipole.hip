@@ -51,9 +51,9 @@ __device__ __forceinline__ void schmidt_solid(double x, double y, double z, doub
   S[24] = 0.125 * s35 * (x2 * (x2 - 3.0 * y2) - y2 * (3.0 * x2 - y2));
 }
 
-// Block-wide sums of NV values per thread into part[blockIdx.x * NV + v] (fixed tree).
+// Block-wide sums of NV values per thread into part[row * NV + v] (fixed tree).
 template <int NV>
-__device__ __forceinline__ void block_sums(double* v, double* red, double* part) {
+__device__ __forceinline__ void block_sums(double* v, double* red, double* part, size_t row) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
@@ -64,7 +64,7 @@ __device__ __forceinline__ void block_sums(double* v, double* red, double* part)
   if (threadIdx.x < NV) {
     double a = 0.0;
     for (int ww = 0; ww < kMBlock / 64; ++ww) a += red[ww * NV + threadIdx.x];
-    part[(size_t)blockIdx.x * NV + threadIdx.x] = a;
+    part[row * NV + threadIdx.x] = a;
   }
 }
 
@@ -103,7 +103,7 @@ __global__ void __launch_bounds__(kMBlock) k_mass_partials(const double* __restr
     v[2] += m * ((j + 0.5) * dx);
     v[3] += m * ((k + 0.5) * dx);
   }
-  block_sums<4>(v, red, part);
+  block_sums<4>(v, red, part, blockIdx.x);
 }
 
 // scratch layout: [0..3] mass sums, [4..6] origin, [7..31] Q_lm
@@ -141,7 +141,7 @@ __global__ void __launch_bounds__(kMBlock) k_moment_partials(const double* __res
 #pragma unroll
     for (int q = 0; q < 25; ++q) acc[q] += q < nq ? m * S[q] : 0.0;
   }
-  block_sums<25>(acc, red, part);
+  block_sums<25>(acc, red, part, blockIdx.x);
 }
 
 __global__ void __launch_bounds__(kMBlock) k_sum_columns(const double* __restrict__ part, int np, int nv,
@@ -180,17 +180,19 @@ void launch_multipole_moments(const double* rho, int n, int Lm, double dx, int l
   hipLaunchKernelGGL(k_sum_columns, dim3(1), dim3(kMBlock), 0, s, part, nb, 25, scratch + 7);
 }
 
-// Boundary values at the face points of one level (extended (nl+2)^2 arrays per face).
+// Boundary values at the face points of one level: (nl + 2 ext)^2 arrays per face over the
+// transverse positions (t + 1/2) hl, t = -ext .. nl - 1 + ext.
 __global__ void __launch_bounds__(kMBlock) k_multipole_faces(const double* __restrict__ scratch, int lmax, double G,
-                                                              int nl, double hl, double length, double* f0, double* f1,
-                                                              double* f2, double* f3, double* f4, double* f5) {
-  const int m = nl + 2;
+                                                              int nl, int ext, double hl, double length, double* f0,
+                                                              double* f1, double* f2, double* f3, double* f4,
+                                                              double* f5) {
+  const int m = nl + 2 * ext;
   const int t = blockIdx.x * kMBlock + threadIdx.x;
   const int face = blockIdx.y;
   if (t >= m * m) return;
   double* out = face == 0 ? f0 : face == 1 ? f1 : face == 2 ? f2 : face == 3 ? f3 : face == 4 ? f4 : f5;
   if (!out) return;
-  const double a = (t % m - 1 + 0.5) * hl, b = (t / m - 1 + 0.5) * hl;
+  const double a = (t % m - ext + 0.5) * hl, b = (t / m - ext + 0.5) * hl;
   const double pos = (face & 1) ? length : 0.0;
   const int axis = face >> 1;
   const double x = axis == 0 ? pos : a;
@@ -214,11 +216,87 @@ __global__ void __launch_bounds__(kMBlock) k_multipole_faces(const double* __res
 }
 
 void launch_multipole_faces(const double* scratch, int lmax, double G, int nl, double hl, double length,
-                            double* faces[6], hipStream_t s) {
-  const int m = nl + 2;
+                            double* faces[6], hipStream_t s, int ext) {
+  const int m = nl + 2 * ext;
   dim3 g((m * m + kMBlock - 1) / kMBlock, 6);
-  hipLaunchKernelGGL(k_multipole_faces, g, dim3(kMBlock), 0, s, scratch, lmax, G, nl, hl, length, faces[0],
+  hipLaunchKernelGGL(k_multipole_faces, g, dim3(kMBlock), 0, s, scratch, lmax, G, nl, ext, hl, length, faces[0],
                      faces[1], faces[2], faces[3], faces[4], faces[5]);
+}
+
+// ---- moments over a set of boxes (the active cells of a composite grid)
+
+struct MpBoxSet {
+  MpBox b[kMpMaxBoxes];
+};
+
+__device__ __forceinline__ bool box_cell(const MpBox& B, size_t c, int& i, int& j, int& k) {
+  i = (int)(c % (size_t)B.n[0]);
+  j = (int)((c / (size_t)B.n[0]) % (size_t)B.n[1]);
+  k = (int)(c / ((size_t)B.n[0] * B.n[1]));
+  return !(i >= B.hlo[0] && i < B.hhi[0] && j >= B.hlo[1] && j < B.hhi[1] && k >= B.hlo[2] && k < B.hhi[2]);
+}
+
+// Box blockIdx.y, grid-strided over its cells; partial row blockIdx.y * gridDim.x + blockIdx.x.
+__global__ void __launch_bounds__(kMBlock) k_box_mass_partials(MpBoxSet S, double* __restrict__ part) {
+  __shared__ double red[4 * kMBlock / 64];
+  const MpBox& B = S.b[blockIdx.y];
+  const size_t n3 = (size_t)B.n[0] * B.n[1] * B.n[2];
+  const double dv = B.h * B.h * B.h;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (size_t c = (size_t)blockIdx.x * kMBlock + threadIdx.x; c < n3; c += (size_t)gridDim.x * kMBlock) {
+    int i, j, k;
+    if (!box_cell(B, c, i, j, k)) continue;
+    const double m = B.rho[c] * dv;
+    v[0] += m;
+    v[1] += m * ((B.o[0] + i + 0.5) * B.h);
+    v[2] += m * ((B.o[1] + j + 0.5) * B.h);
+    v[3] += m * ((B.o[2] + k + 0.5) * B.h);
+  }
+  block_sums<4>(v, red, part, (size_t)blockIdx.y * gridDim.x + blockIdx.x);
+}
+
+__global__ void __launch_bounds__(kMBlock) k_box_moment_partials(MpBoxSet S, int lmax,
+                                                                  const double* __restrict__ scratch,
+                                                                  double* __restrict__ part) {
+  __shared__ double red[25 * kMBlock / 64];
+  const MpBox& B = S.b[blockIdx.y];
+  const size_t n3 = (size_t)B.n[0] * B.n[1] * B.n[2];
+  const double dv = B.h * B.h * B.h;
+  const double ox = scratch[4], oy = scratch[5], oz = scratch[6];
+  const int nq = (lmax + 1) * (lmax + 1);
+  double acc[25];
+#pragma unroll
+  for (int q = 0; q < 25; ++q) acc[q] = 0.0;
+  for (size_t c = (size_t)blockIdx.x * kMBlock + threadIdx.x; c < n3; c += (size_t)gridDim.x * kMBlock) {
+    int i, j, k;
+    if (!box_cell(B, c, i, j, k)) continue;
+    const double m = B.rho[c] * dv;
+    double S25[25];
+    schmidt_solid((B.o[0] + i + 0.5) * B.h - ox, (B.o[1] + j + 0.5) * B.h - oy, (B.o[2] + k + 0.5) * B.h - oz,
+                  S25);
+#pragma unroll
+    for (int q = 0; q < 25; ++q) acc[q] += q < nq ? m * S25[q] : 0.0;
+  }
+  block_sums<25>(acc, red, part, (size_t)blockIdx.y * gridDim.x + blockIdx.x);
+}
+
+int multipole_box_blocks() { return 256; }
+
+void launch_multipole_moments_boxes(const MpBox* boxes, int nbox, int lmax, int use_origin, const double* origin_host,
+                                    double centre, double* part, double* scratch, hipStream_t s) {
+  MpBoxSet S{};
+  for (int q = 0; q < nbox; ++q) S.b[q] = boxes[q];
+  const int nb = multipole_box_blocks();
+  const dim3 grid(nb, nbox);
+  if (!use_origin) {
+    hipLaunchKernelGGL(k_box_mass_partials, grid, dim3(kMBlock), 0, s, S, part);
+    hipLaunchKernelGGL(k_sum_columns, dim3(1), dim3(kMBlock), 0, s, part, nb * nbox, 4, scratch);
+  }
+  const double ox = use_origin ? origin_host[0] : 0.0, oy = use_origin ? origin_host[1] : 0.0,
+               oz = use_origin ? origin_host[2] : 0.0;
+  hipLaunchKernelGGL(k_set_origin, dim3(1), dim3(64), 0, s, scratch, use_origin, ox, oy, oz, centre);
+  hipLaunchKernelGGL(k_box_moment_partials, grid, dim3(kMBlock), 0, s, S, lmax, scratch, part);
+  hipLaunchKernelGGL(k_sum_columns, dim3(1), dim3(kMBlock), 0, s, part, nb * nbox, 25, scratch + 7);
 }
 
 }  // namespace mg

@@ -1,8 +1,8 @@
 """GPU parity of the refined-mesh solver (Sec. 3.3: FAS V-cycles over MeshBlock, Octet and root
 levels with the conservative and normal level boundaries) with the oracle: residual histories
 cycle by cycle and the potential on every patch to 1e-10 relative, for one and two levels of
-refinement, off-centre and non-cubic boxes, periodic, zero-gradient and fixed faces, zero and
-random initial guesses and the full-multigrid start; plus the rejected forms."""
+refinement, off-centre and non-cubic boxes, periodic, zero-gradient, fixed and multipole faces,
+zero and random initial guesses and the full-multigrid start; plus the rejected forms."""
 import math
 
 import numpy as np
@@ -132,8 +132,8 @@ def test_amr_rejected_forms(mg):
     p = mg.params(NB * nb, 1.0 / (NB * nb), mode="mgi", precision="mixed")
     with pytest.raises(mg.MgError, match="UNSUPPORTED"):
         mg.mg_amr_solve(ctx, p, mesh, mg.boundary("periodic"), r, [torch.zeros_like(x) for x in r])
-    with pytest.raises(mg.MgError, match="UNSUPPORTED"):
-        mg.amr_solve(mesh, r, "multipole")
+    with pytest.raises(mg.MgError, match="INVALID_ARG"):
+        mg.amr_solve(mesh, r, "multipole", lmax=5)
     with pytest.raises(mg.MgError, match="INVALID_ARG"):
         mg.amr_patch_dims(mg.amr_mesh(4, 4, [((0, 1, 1), (3, 3, 3))]), 1)    # touches the domain face
     with pytest.raises(mg.MgError, match="INVALID_ARG"):
@@ -223,3 +223,62 @@ def test_amr_six_levels(mg, mode):
     for a, b in zip(hist, rh):
         assert abs(a - b) <= 1e-6 * b + 1e-12, (hist, rh)
     assert rel([p.cpu().numpy() for p in phi], ref) < 1e-10
+
+
+MP_KINDS = {"multipole": ["multipole"] * 6,
+            "mixed": ["multipole", "multipole", "periodic", "periodic", "multipole", "zero_gradient"]}
+
+
+@pytest.mark.parametrize("origin", [None, (0.52, 0.47, 0.5)])
+@pytest.mark.parametrize("kname", list(MP_KINDS))
+@pytest.mark.parametrize("mname", list(MESHES))
+def test_amr_multipole_matches_oracle(mg, mname, kname, origin):
+    """Multipole faces (Appendix A) on the refined mesh: moments over the composite grid's
+    active cells, faces at every root level's face centres; V-cycles and FMG as the oracle's."""
+    NB, nb, boxes = MESHES[mname]
+    names = MP_KINDS[kname]
+    kinds = [amr.FIXED if k == "multipole" else amr.PERIODIC if k == "periodic" else amr.ZERO_GRADIENT
+             for k in names]
+    print(f"amr multipole {mname} {kname} {origin}", flush=True)
+    m, rho, _ = case(NB, nb, boxes, kinds, 5)
+    bf = amr.multipole_faces(m, rho, 4, None if origin is None else np.array(origin))
+    mesh = mg.amr_mesh(NB, nb, boxes)
+    drho = [dev(r) for r in rho]
+    for mode, cyc in (("mgi", 5), ("fmg", 3)):
+        ref, rh = amr.solve(m, rho, kinds, bf, cycles=cyc, mode=mode)
+        phi, hist, st = mg.amr_solve(mesh, drho, names, fixed_cycles=cyc, mode=mode, origin=origin)
+        torch.cuda.synchronize()
+        assert st == mg.MG_OK and len(hist) == len(rh) == cyc + 1
+        for a, b in zip(hist, rh):
+            assert abs(a - b) <= 1e-6 * b + 1e-12, (mode, hist, rh)
+        assert rel([p.cpu().numpy() for p in phi], ref) < 1e-10, mode
+
+
+def test_binary_potential_multipole(mg):
+    """The paper's refined-mesh test with its own boundaries (Sec. 4.3: open faces from the
+    hexadecapole expansion): FMG and 3 V-cycles as the oracle's, then to 1e-10 with the
+    normalised error against the analytic potential below 1e-3."""
+    import workloads as wl
+    print("amr binary multipole", flush=True)
+    NB, nb = 4, 16
+    boxes = wl.binary_mesh_boxes(NB)
+    m = amr.AmrMesh(NB, nb, boxes)
+    rho = [wl.binary_density_on_axes(*m.centres(l), m.patches[l][m.K].h) for l in range(m.Lam + 1)]
+    ref, rh = amr.solve(m, rho, [amr.FIXED] * 6, amr.multipole_faces(m, rho, 4), cycles=3, mode="fmg")
+    mesh = mg.amr_mesh(NB, nb, boxes)
+    drho = [dev(r) for r in rho]
+    phi, hist, st = mg.amr_solve(mesh, drho, "multipole", fixed_cycles=3, mode="fmg")
+    assert len(hist) == len(rh) == 4
+    for a, b in zip(hist, rh):
+        assert abs(a - b) <= 1e-6 * b + 1e-12, (hist, rh)
+    assert rel([p.cpu().numpy() for p in phi], ref) < 1e-10
+    phi, hist, st = mg.amr_solve(mesh, drho, "multipole", tol=1e-10, mode="fmg")
+    assert st == mg.MG_OK
+    err = []
+    for l in range(m.Lam + 1):
+        xs, ys, zs = m.centres(l)
+        Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+        ex = wl.binary_potential(X, Y, Z)
+        err.append(((phi[l].cpu().numpy() - ex) / ex)[m.patches[l][m.K].active()])
+    e = np.concatenate(err)
+    assert math.sqrt(np.mean(e * e)) < 1e-3
