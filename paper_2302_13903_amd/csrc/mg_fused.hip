@@ -175,6 +175,11 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
   // where the final plane is stored: after the end-of-step ring update for the FP64 passes
   // with the prolongation or the input norm (measured 2-4 % faster there, slower elsewhere)
   constexpr bool STORE_LAST = sizeof(T) == 8 && SWEEP && !DSTAGE && (PRO || OUT == 3);
+  // leave out the stages that feed no output: planes before the chunk and halo-only waves
+  // (measured 6 % faster on the FP64 sweep with the restricted defect and 11 % on the FP32
+  // sweep at 512^3; 1-17 % slower on the other passes, where the compiler then schedules the
+  // march worse)
+  constexpr bool SKIP = (sizeof(T) == 8 && SWEEP && OUT == 1) || (sizeof(T) == 4 && MODE == MODE_SWEEP && !PRO && OUT == 0);
   __shared__ Pair<T> fl[NF][R][W * kLanes];
   // INNORM: input values of plane P-2, private per thread like f
   __shared__ Pair<T> uol[INNORM ? R : 1][INNORM ? W * kLanes : 1];
@@ -236,6 +241,9 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
     const int wy0 = ys - A.hy + w * XS * R, wy1 = wy0 + XS * R - 1;   // rows of the whole wave
     const bool wave_bnd_xy = (!px && (xs - A.hx <= 0 || xs - A.hx + TX - 1 >= nm)) ||
                              (!py && (wy0 <= 0 || wy1 >= nm));
+    // does this wave hold an output row?  (with SKIP a wave of halo rows leaves out the
+    // defect stage)
+    const bool wave_out = wy1 >= ys && wy0 < min(ys + A.yo, n);
 
     // u: ring of kRing planes (slot = plane index mod kRing, compile-time after unrolling);
     // f: LDS slots (plane mod 3) holding planes P-1, P-2, P-3.
@@ -442,6 +450,7 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
     auto defect_out = [&](T (&pm)[R][2], T (&pc)[R][2], T (&pp)[R][2], int p) __attribute__((always_inline)) {
       T below[2], above[2];
       exchange(pc, below, above);
+      if (SKIP && !wave_out) return;   // wave-uniform, after the barrier
       const bool in_z = pz || (p >= 0 && p < n);
       const bool bnd_z0 = !pz && p == 0, bnd_z1 = !pz && p == nm;
       const bool out_z = p >= z0 && p < zend;
@@ -532,10 +541,14 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
       constexpr int s1 = (k + kRing - 1) % kRing, s2 = (k + kRing - 2) % kRing;
       constexpr int s3 = (k + 2 * kRing - 3) % kRing, s4 = (k + 2 * kRing - 4) % kRing;
       // red on P-1 (neighbours P-2, P), black on P-2 (P-3, P-1), defect on P-3 (P-4, P-2);
-      // without the sweep the (updated) plane P is final at once and the defect runs on P-1
+      // without the sweep the (updated) plane P is final at once and the defect runs on P-1.
+      // A stage runs only on planes that reach an output plane of the chunk: the defect on
+      // planes >= z0, the black colour on planes >= z0 - 1 (>= z0 without a defect stage),
+      // the red one plane further out (the same for the whole workgroup, barriers included)
+      constexpr int kRedLo = DSTAGE ? 2 : 1, kBlackLo = DSTAGE ? 1 : 0;
       if (SWEEP) {
-        half_sweep(u[s2], u[s1], u[k], P - 1, 0);
-        half_sweep(u[s3], u[s2], u[s1], P - 2, 1);
+        if (!SKIP || P - 1 >= z0 - kRedLo) half_sweep(u[s2], u[s1], u[k], P - 1, 0);
+        if (!SKIP || P - 2 >= z0 - kBlackLo) half_sweep(u[s3], u[s2], u[s1], P - 2, 1);
       }
       // the plane that is final this step goes out (ring slot sf)
       constexpr int sf = SWEEP ? s2 : k;
@@ -557,8 +570,11 @@ __global__ void __launch_bounds__(kLanes* W) k_fused(FusedArgs A) {
       };
       if (WRITE_U && !STORE_LAST) store_final();
       if (DSTAGE) {
-        if (SWEEP) defect_out(u[s4], u[s3], u[s2], P - 3);
-        else defect_out(u[s2], u[s1], u[k], P - 1);
+        if (SWEEP) {
+          if (!SKIP || P - 3 >= z0) defect_out(u[s4], u[s3], u[s2], P - 3);
+        } else if (!SKIP || P - 1 >= z0) {
+          defect_out(u[s2], u[s1], u[k], P - 1);
+        }
       }
       if (t + 1 < nsteps) {
         prolong_apply(P + 1);
