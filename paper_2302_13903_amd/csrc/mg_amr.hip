@@ -1461,8 +1461,12 @@ int amr_solve_impl(int device, const mg_params* p, const mg_amr_mesh* m, const m
       }
     }
     double* mps = mem + mp_scratch;
-    launch_multipole_moments_boxes(boxes, pl.Lam + 1, bc->lmax, bc->use_origin, bc->origin, 0.5, mem + mp_part, mps,
-                                   s);
+    if (launch_multipole_moments_boxes(boxes, pl.Lam + 1, bc->lmax, bc->use_origin, bc->origin, 0.5, mem + mp_part,
+                                       mps, s) != MG_OK) {
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(mem);
+      return fail_amr(err, MG_ERR_INVALID_ARG, "too many refinement levels for the multipole moments");
+    }
     const double G = p->four_pi_g / (4.0 * M_PI);
     for (size_t q = 0; q < pl.bface.size(); ++q) {
       const int n = pl.bface_n[q];

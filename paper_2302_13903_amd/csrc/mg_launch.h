@@ -98,8 +98,9 @@ struct MpBox {
   double h;
 };
 int multipole_box_blocks();
-void launch_multipole_moments_boxes(const MpBox* boxes, int nbox, int lmax, int use_origin, const double* origin_host,
-                                    double centre, double* part, double* scratch, hipStream_t s);
+// returns MG_ERR_INVALID_ARG (nothing launched) unless 1 <= nbox <= kMpMaxBoxes
+int launch_multipole_moments_boxes(const MpBox* boxes, int nbox, int lmax, int use_origin, const double* origin_host,
+                                   double centre, double* part, double* scratch, hipStream_t s);
 
 // gravitational acceleration (mg_gravity.hip): g, rhog (3 n^3 each) and gface (3 n^2 (n+1),
 // dense layout only) from phi, any of them null; returns the number of workgroups launched

@@ -7,6 +7,7 @@
 // harmonics of the paper's table, giving the Schmidt semi-normalised regular solid harmonics
 // S_lm(r) = sqrt(4 pi/(2l+1)) r^l Y_lm, which are plain polynomials:
 //   Q_lm = sum rho dV S_lm(r'),     phi = -G sum Q_lm S_lm(r) / r^(2l+1).
+#include "mg355.h"
 #include "mg_common.h"
 #include "mg_launch.h"
 
@@ -180,6 +181,15 @@ void launch_multipole_moments(const double* rho, int n, int Lm, double dx, int l
   hipLaunchKernelGGL(k_sum_columns, dim3(1), dim3(kMBlock), 0, s, part, nb, 25, scratch + 7);
 }
 
+// sum over m of Q_lm S_lm for one l, in increasing m
+template <int L>
+__device__ __forceinline__ double mp_band(const double* __restrict__ Q, const double (&S)[25]) {
+  double sl = 0.0;
+#pragma unroll
+  for (int q = L * L; q < (L + 1) * (L + 1); ++q) sl += Q[q] * S[q];
+  return sl;
+}
+
 // Boundary values at the face points of one level: (nl + 2 ext)^2 arrays per face over the
 // transverse positions (t + 1/2) hl, t = -ext .. nl - 1 + ext.
 __global__ void __launch_bounds__(kMBlock) k_multipole_faces(const double* __restrict__ scratch, int lmax, double G,
@@ -204,14 +214,13 @@ __global__ void __launch_bounds__(kMBlock) k_multipole_faces(const double* __res
   double S[25];
   schmidt_solid(rx, ry, rz, S);
   const double* Q = scratch + 7;
-  double phi = 0.0;
-  double rpow = r;   // r^(2l+1)
-  for (int l = 0; l <= lmax; ++l) {
-    double sl = 0.0;
-    for (int q = l * l; q < (l + 1) * (l + 1); ++q) sl += Q[q] * S[q];
-    phi += sl / rpow;
-    rpow *= r2;
-  }
+  // one band per l with compile-time indices, so S stays in registers
+  const double r3 = r * r2, r5 = r3 * r2, r7 = r5 * r2, r9 = r7 * r2;   // r^(2l+1)
+  double phi = mp_band<0>(Q, S) / r;
+  if (lmax >= 1) phi += mp_band<1>(Q, S) / r3;
+  if (lmax >= 2) phi += mp_band<2>(Q, S) / r5;
+  if (lmax >= 3) phi += mp_band<3>(Q, S) / r7;
+  if (lmax >= 4) phi += mp_band<4>(Q, S) / r9;
   out[t] = -G * phi;
 }
 
@@ -282,8 +291,9 @@ __global__ void __launch_bounds__(kMBlock) k_box_moment_partials(MpBoxSet S, int
 
 int multipole_box_blocks() { return 256; }
 
-void launch_multipole_moments_boxes(const MpBox* boxes, int nbox, int lmax, int use_origin, const double* origin_host,
-                                    double centre, double* part, double* scratch, hipStream_t s) {
+int launch_multipole_moments_boxes(const MpBox* boxes, int nbox, int lmax, int use_origin, const double* origin_host,
+                                   double centre, double* part, double* scratch, hipStream_t s) {
+  if (nbox < 1 || nbox > kMpMaxBoxes) return MG_ERR_INVALID_ARG;
   MpBoxSet S{};
   for (int q = 0; q < nbox; ++q) S.b[q] = boxes[q];
   const int nb = multipole_box_blocks();
@@ -297,6 +307,7 @@ void launch_multipole_moments_boxes(const MpBox* boxes, int nbox, int lmax, int 
   hipLaunchKernelGGL(k_set_origin, dim3(1), dim3(64), 0, s, scratch, use_origin, ox, oy, oz, centre);
   hipLaunchKernelGGL(k_box_moment_partials, grid, dim3(kMBlock), 0, s, S, lmax, scratch, part);
   hipLaunchKernelGGL(k_sum_columns, dim3(1), dim3(kMBlock), 0, s, part, nb * nbox, 25, scratch + 7);
+  return MG_OK;
 }
 
 }  // namespace mg
