@@ -468,3 +468,13 @@ def test_binary_multipole_faces_match_analytic_faces():
     den = sum(np.sum(b ** 2) for b in phi_an)
     rel = math.sqrt(num / den)
     assert rel < 1e-8, rel          # measured 9e-12
+
+
+def test_composite_multipole_zero_mass():
+    """No mass: the origin falls back to the domain centre and every moment and face value is 0."""
+    m = amr.AmrMesh(4, 2, [((1, 1, 1), (3, 3, 3))])
+    rho = [np.zeros(m.patches[l][m.K].n[::-1]) for l in range(m.Lam + 1)]
+    o, q = amr.composite_moments(m, rho, 4)
+    assert np.all(o == 0.5) and np.all(q == 0.0)
+    mf = amr.multipole_faces(m, rho, 4)
+    assert all(np.all(a == 0.0) for n in (8, 4, 2, 1) for a in mf.at(n))
