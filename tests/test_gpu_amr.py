@@ -254,6 +254,23 @@ def test_amr_multipole_matches_oracle(mg, mname, kname, origin):
         assert rel([p.cpu().numpy() for p in phi], ref) < 1e-10, mode
 
 
+@pytest.mark.parametrize("lmax", [0, 2])
+def test_amr_multipole_lower_orders(mg, lmax):
+    """Multipole faces truncated below the hexadecapole on the refined mesh."""
+    NB, nb, boxes = MESHES["two levels"]
+    kinds = [amr.FIXED] * 6
+    print(f"amr multipole lmax {lmax}", flush=True)
+    m, rho, _ = case(NB, nb, boxes, kinds, 3)
+    ref, rh = amr.solve(m, rho, kinds, amr.multipole_faces(m, rho, lmax), cycles=4)
+    mesh = mg.amr_mesh(NB, nb, boxes)
+    phi, hist, st = mg.amr_solve(mesh, [dev(r) for r in rho], "multipole", lmax=lmax, fixed_cycles=4)
+    torch.cuda.synchronize()
+    assert st == mg.MG_OK and len(hist) == len(rh) == 5
+    for a, b in zip(hist, rh):
+        assert abs(a - b) <= 1e-6 * b + 1e-12, (hist, rh)
+    assert rel([p.cpu().numpy() for p in phi], ref) < 1e-10
+
+
 def test_binary_potential_multipole(mg):
     """The paper's refined-mesh test with its own boundaries (Sec. 4.3: open faces from the
     hexadecapole expansion): FMG and 3 V-cycles as the oracle's, then to 1e-10 with the

@@ -93,6 +93,17 @@ def test_multipole_sphere(mg, n):
     hist_close(gh, rh, residual_floor(ref, rho, False))
 
 
+@pytest.mark.parametrize("lmax", [0, 1, 2, 3])
+def test_multipole_lower_orders(mg, lmax):
+    """Expansions truncated below the hexadecapole (each band of the face sum on or off) for an
+    off-centre clump field, so that every order carries moments."""
+    n = 64
+    rho = wl.gaussian_clumps(n, 5)
+    ref, rh, got, gh, st = run_both(mg, rho, [MULTIPOLE] * 6, cycles=6, lmax=lmax)
+    assert rel(got, ref) < 1e-10
+    hist_close(gh, rh, residual_floor(ref, rho, False))
+
+
 def test_tol_stop_matches_oracle(mg):
     """Stopping by tolerance: same cycle count and status as the oracle."""
     n = 64
