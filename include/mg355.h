@@ -111,8 +111,13 @@ typedef struct {
 
 void mg_default_params(mg_params *p);
 
-/* Create a context on HIP device `device` (workspace grows on demand and is reused). */
-int mg_ctx_create(mg_ctx **ctx, int device);
+/* Create a context on HIP device `device`.  The workspace grows on demand and is reused.
+ * hbm_budget caps the device bytes the context may hold (hierarchy workspace, operator and
+ * autotuner scratch, reduction scratch; mg_footprint_bytes gives what a solve needs): a call
+ * that would need more returns MG_ERR_OOM without allocating.  0 = no cap.  Returns
+ * MG_ERR_OOM when the budget cannot hold the context's fixed reduction scratch, and
+ * MG_ERR_DEVICE when the device cannot be used. */
+int mg_ctx_create(mg_ctx **ctx, int device, size_t hbm_budget);
 void mg_ctx_destroy(mg_ctx *ctx);
 const char *mg_last_error(const mg_ctx *ctx);
 
@@ -162,6 +167,18 @@ int mg_tuning_set(mg_ctx *ctx, const char *text);
  * Synchronises `stream` once per cycle (the stopping test runs on the host). */
 int mg_solve(mg_ctx *ctx, const mg_params *p, const mg_bc *bc, const double *rho, double *phi,
              double *hist, int *n_hist, void *stream);
+
+/* Short form of mg_solve (Sec. 2.3.7, Alg. 1, Alg. 2) with the defaults of mg_default_params:
+ * FMG start, V(2,2) cycles, omega = 1.15, four_pi_g = 4 pi, FP64, dense layout, at most 50
+ * cycles.  All six faces take bc_kind (MG_BC_*): FIXED faces hold b = 0; MULTIPOLE faces the
+ * l <= 4 expansion about the centre of mass (Appendix A).
+ *   n     cells per side (power of two, 2..2048); dx > 0; tol > 0 (relative residual).
+ *   rho   device, n^3 FP64, read only;  phi  device, n^3 FP64, output.
+ *   hist  host, capacity 51: the relative residual after FMG and after each V-cycle;
+ *   n_hist host: entries written.
+ * Returns as mg_solve. */
+int mg_solve_simple(mg_ctx *ctx, int n, const double *rho, int bc_kind, double dx, double tol, double *phi,
+                    double *hist, int *n_hist, void *stream);
 
 /* Timing of the last mg_solve on this context, from HIP events on its stream:
  * *fmg_ms = set-up + FMG sweep; cycle_ms[c] = wall time of V-cycle c (including its
@@ -284,6 +301,14 @@ int mg_op_half_sweep(mg_ctx *ctx, int n, double h, double omega, int colour, con
 int mg_op_smooth(mg_ctx *ctx, int n, double h, double omega, int sweeps, const mg_level_bc *bc,
                  double *u, const double *f, void *stream);
 
+/* Ghost fill of one level (Sec. 2.3.6): out (device, (n+2)^3 FP64, x fastest) receives u
+ * (device, n^3) at active index (i+1, j+1, k+1) and every ghost from bc: periodic faces the
+ * opposite active cell, zero-gradient faces the adjacent cell, fixed (and multipole) faces
+ * 2 b - adjacent cell.  Ghosts are filled axis by axis -- x, then y over the x ghosts, then z
+ * over both -- which defines the edge and corner ghosts the 27-point prolongations read.
+ * The operators evaluate these ghosts on the fly; this entry point exposes them. */
+int mg_op_fill(mg_ctx *ctx, int n, const mg_level_bc *bc, const double *u, double *out, void *stream);
+
 /* d = f - L_h u (eq. defect).  u, f, d: device, n^3 FP64. */
 int mg_op_defect(mg_ctx *ctx, int n, double h, const mg_level_bc *bc, const double *u,
                  const double *f, double *d, void *stream);
@@ -316,6 +341,33 @@ int mg_op_up(mg_ctx *ctx, int n, double h, double omega, int npost, const mg_lev
              const mg_level_bc *bc_coarse, double *u, const double *f, const double *uc,
              void *stream);
 
+/* FP32 forms of mg_op_smooth, mg_op_down and mg_op_up: the same passes, in the single
+ * precision the inner cycles of MG_PREC_MIXED run (u, f, fc, uc, uc: device FP32 arrays of
+ * the same shapes; h, omega and face values as above, rounded to FP32 by the kernels).
+ * zero_in != 0: u is zero on input and the first sweep does not read it (the first sweep of a
+ * mixed-precision correction cycle). */
+int mg_op_smooth_f32(mg_ctx *ctx, int n, double h, double omega, int sweeps, int zero_in, const mg_level_bc *bc,
+                     float *u, const float *f, void *stream);
+int mg_op_down_f32(mg_ctx *ctx, int n, double h, double omega, int npre, const mg_level_bc *bc, float *u,
+                   const float *f, float *fc, float *uc, void *stream);
+int mg_op_up_f32(mg_ctx *ctx, int n, double h, double omega, int npost, const mg_level_bc *bc,
+                 const mg_level_bc *bc_coarse, float *u, const float *f, const float *uc, void *stream);
+
+/* One smoothing sweep of u in place (eqs. rbsor1-2) and *sumsq = the sum over the level of
+ * the squared defect f - L_h u of the INPUT u (Sec. 2.3.7): the solver's first pre-sweep of a
+ * V-cycle, which also measures the residual of the iterate it starts from.  u: device n^3
+ * FP64 (in and out); f: device n^3 FP64; sumsq: host.  Synchronises the stream. */
+int mg_op_sweep_input_norm(mg_ctx *ctx, int n, double h, double omega, const mg_level_bc *bc, double *u,
+                           const double *f, double *sumsq, void *stream);
+
+/* FP64 half of one mixed-precision defect-correction step (the refinement around the FP32
+ * cycle): phi <- phi + e, then the defect d = f - L_h phi (eq. defect) of the updated phi,
+ * r32 = d rounded to FP32 (the next correction's right-hand side) and *sumsq = the sum of d^2
+ * over the level (Sec. 2.3.7), all in one pass.  phi: device n^3 FP64 (in and out); e, r32:
+ * device n^3 FP32; f: device n^3 FP64; sumsq: host.  Synchronises the stream. */
+int mg_op_mixed_update(mg_ctx *ctx, int n, double h, const mg_level_bc *bc, double *phi, const float *e,
+                       const double *f, float *r32, double *sumsq, void *stream);
+
 /* ---- serving runtime ---------------------------------------------------------------
  *
  * A request stream of independent solves (different sizes, boundary kinds and precisions)
@@ -323,8 +375,10 @@ int mg_op_up(mg_ctx *ctx, int n, double h, double omega, int npost, const mg_lev
  * solves overlap on the device.  Admission is by HBM footprint: a request starts only when
  * its hierarchy (mg_footprint_bytes + one n^3 FP64 result slot) fits in `hbm_budget` next to
  * the hierarchies in use.  Hierarchies stay resident after a solve and are reused by the next
- * request of the same (n, precision); idle hierarchies of other sizes are released
- * (least recently used first) only when a new one would not fit.  Every kernel of a solve is
+ * request of the same workspace class (n, precision, block_n of the MeshBlock layout, scheme);
+ * each is a context whose HBM budget is that class's footprint, so a solve never grows it
+ * beyond what admission counted.  Idle hierarchies of other classes are released (least
+ * recently used first) only when a new one would not fit.  Every kernel of a solve is
  * deterministic, so a request's phi and history do not depend on what runs beside it. */
 
 typedef struct mg_server mg_server;

@@ -23,8 +23,9 @@ from ._abi import (MG_BC_FIXED, MG_BC_MULTIPOLE, MG_BC_PERIODIC, MG_BC_ZERO_GRAD
                    MG_OK, MG_STALLED, MgError, STATUS_NAMES)
 
 __all__ = ["Context", "solve", "to_blocks", "from_blocks", "morton_order", "mg_solve", "mg_footprint_bytes", "params", "boundary", "level_bc",
-           "mg_op_half_sweep", "mg_op_smooth", "mg_op_defect", "mg_op_restrict", "mg_op_prolong_add",
-           "mg_op_prolong_fmg", "mg_op_coarsest", "mg_op_down", "mg_op_up", "mg_multipole_moments",
+           "mg_solve_simple", "mg_op_fill", "mg_op_half_sweep", "mg_op_smooth", "mg_op_defect", "mg_op_restrict", "mg_op_prolong_add",
+           "mg_op_prolong_fmg", "mg_op_coarsest", "mg_op_down", "mg_op_up", "mg_op_smooth_f32", "mg_op_down_f32",
+           "mg_op_up_f32", "mg_op_sweep_input_norm", "mg_op_mixed_update", "mg_multipole_moments",
            "gravity", "mg_gravity", "mg_gravity_kernel_name", "amr_mesh", "amr_patch_dims", "amr_solve",
            "mg_amr_solve", "MgError", "KINDS"]
 
@@ -59,10 +60,12 @@ def _stream(stream) -> Optional[int]:
 class Context:
     """Owns an ``mg_ctx`` (pooled device workspace, reused across solves)."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, hbm_budget: int = 0):
+        """``hbm_budget``: device bytes the context may hold (0 = no cap); a solve that would
+        need more fails with MG_ERR_OOM instead of allocating."""
         self._lib = _abi.lib()
         h = ctypes.c_void_p()
-        st = self._lib.mg_ctx_create(ctypes.byref(h), int(device))
+        st = self._lib.mg_ctx_create(ctypes.byref(h), int(device), int(hbm_budget))
         if st != MG_OK:
             raise MgError(f"mg_ctx_create failed: {STATUS_NAMES.get(st, st)}")
         self.handle = h
@@ -407,6 +410,23 @@ def mg_op_smooth(u, f, h, omega, sweeps, kinds, bext=None, ctx=None, stream=None
                    "mg_op_smooth")
 
 
+def mg_op_fill(u, out, kinds, bext=None, ctx=None, stream=None):
+    c = _ctx(ctx)
+    return c.check(c._lib.mg_op_fill(c.handle, u.shape[0], ctypes.byref(level_bc(kinds, bext)), _ptr(u), _ptr(out),
+                                     _stream(stream)), "mg_op_fill")
+
+
+def mg_solve_simple(rho, bc_kind, dx, tol, phi, ctx=None, stream=None):
+    """The short form of mg_solve (defaults; one kind on all six faces); returns (hist, status)."""
+    c = _ctx(ctx)
+    kind = KINDS[bc_kind] if isinstance(bc_kind, str) else int(bc_kind)
+    hist = (ctypes.c_double * 51)()
+    nh = ctypes.c_int()
+    st = c.check(c._lib.mg_solve_simple(c.handle, rho.shape[0], _ptr(rho), kind, float(dx), float(tol), _ptr(phi),
+                                        hist, ctypes.byref(nh), _stream(stream)), "mg_solve_simple")
+    return [hist[i] for i in range(nh.value)], st
+
+
 def mg_op_defect(u, f, d, h, kinds, bext=None, ctx=None, stream=None):
     c = _ctx(ctx)
     return c.check(c._lib.mg_op_defect(c.handle, u.shape[0], float(h), ctypes.byref(level_bc(kinds, bext)),
@@ -450,6 +470,48 @@ def mg_op_up(u, f, uc, h, omega, npost, kinds, bext=None, kinds_coarse=None, ctx
     return c.check(c._lib.mg_op_up(c.handle, u.shape[0], float(h), float(omega), int(npost),
                                    ctypes.byref(level_bc(kinds, bext)), ctypes.byref(level_bc(kc, None)), _ptr(u),
                                    _ptr(f), _ptr(uc), _stream(stream)), "mg_op_up")
+
+
+def mg_op_smooth_f32(u, f, h, omega, sweeps, kinds, bext=None, zero_in=False, ctx=None, stream=None):
+    c = _ctx(ctx)
+    return c.check(c._lib.mg_op_smooth_f32(c.handle, u.shape[0], float(h), float(omega), int(sweeps),
+                                           1 if zero_in else 0, ctypes.byref(level_bc(kinds, bext)), _ptr(u), _ptr(f),
+                                           _stream(stream)), "mg_op_smooth_f32")
+
+
+def mg_op_down_f32(u, f, fc, uc, h, omega, npre, kinds, bext=None, ctx=None, stream=None):
+    c = _ctx(ctx)
+    return c.check(c._lib.mg_op_down_f32(c.handle, u.shape[0], float(h), float(omega), int(npre),
+                                         ctypes.byref(level_bc(kinds, bext)), _ptr(u), _ptr(f), _ptr(fc), _ptr(uc),
+                                         _stream(stream)), "mg_op_down_f32")
+
+
+def mg_op_up_f32(u, f, uc, h, omega, npost, kinds, bext=None, kinds_coarse=None, ctx=None, stream=None):
+    c = _ctx(ctx)
+    kc = kinds_coarse if kinds_coarse is not None else kinds
+    return c.check(c._lib.mg_op_up_f32(c.handle, u.shape[0], float(h), float(omega), int(npost),
+                                       ctypes.byref(level_bc(kinds, bext)), ctypes.byref(level_bc(kc, None)), _ptr(u),
+                                       _ptr(f), _ptr(uc), _stream(stream)), "mg_op_up_f32")
+
+
+def mg_op_sweep_input_norm(u, f, h, omega, kinds, bext=None, ctx=None, stream=None):
+    """One sweep of u in place; returns the sum of squared defects of the input u."""
+    c = _ctx(ctx)
+    out = ctypes.c_double()
+    c.check(c._lib.mg_op_sweep_input_norm(c.handle, u.shape[0], float(h), float(omega),
+                                          ctypes.byref(level_bc(kinds, bext)), _ptr(u), _ptr(f), ctypes.byref(out),
+                                          _stream(stream)), "mg_op_sweep_input_norm")
+    return out.value
+
+
+def mg_op_mixed_update(phi, e, f, r32, h, kinds, bext=None, ctx=None, stream=None):
+    """phi += e; r32 = FP32(f - L phi); returns the sum of squared defects."""
+    c = _ctx(ctx)
+    out = ctypes.c_double()
+    c.check(c._lib.mg_op_mixed_update(c.handle, phi.shape[0], float(h), ctypes.byref(level_bc(kinds, bext)),
+                                      _ptr(phi), _ptr(e), _ptr(f), _ptr(r32), ctypes.byref(out), _stream(stream)),
+            "mg_op_mixed_update")
+    return out.value
 
 
 def mg_multipole_moments(rho, dx, lmax=4, origin=None, ctx=None, stream=None):

@@ -93,7 +93,7 @@ def lib():
     i = ctypes.c_int
     sig = {
         "mg_default_params": (None, [ctypes.POINTER(MgParams)]),
-        "mg_ctx_create": (i, [ctypes.POINTER(_vp), i]),
+        "mg_ctx_create": (i, [ctypes.POINTER(_vp), i, ctypes.c_size_t]),
         "mg_ctx_destroy": (None, [_vp]),
         "mg_last_error": (ctypes.c_char_p, [_vp]),
         "mg_footprint_bytes": (ctypes.c_size_t, [ctypes.POINTER(MgParams)]),
@@ -108,6 +108,7 @@ def lib():
         "mg_server_run": (i, [_vp, ctypes.POINTER(MgRequest), i]),
         "mg_server_get_stats": (i, [_vp, ctypes.POINTER(MgServerStats)]),
         "mg_solve": (i, [_vp, ctypes.POINTER(MgParams), ctypes.POINTER(MgBC), _vp, _vp, _dp, _ip, _vp]),
+        "mg_solve_simple": (i, [_vp, i, _vp, i, d, d, _vp, _dp, _ip, _vp]),
         "mg_last_timing": (i, [_vp, _dp, _dp, _dp, i, _ip]),
         "mg_set_kernel_timing": (i, [_vp, i]),
         "mg_kernel_timing": (i, [_vp, i, _ip, _dp, _dp, ctypes.c_char_p, i]),
@@ -119,12 +120,19 @@ def lib():
         "mg_gravity_kernel_name": (i, [ctypes.POINTER(MgParams), i, i, i, ctypes.c_char_p, i]),
         "mg_op_half_sweep": (i, [_vp, i, d, d, i, ctypes.POINTER(MgLevelBC), _vp, _vp, _vp]),
         "mg_op_smooth": (i, [_vp, i, d, d, i, ctypes.POINTER(MgLevelBC), _vp, _vp, _vp]),
+        "mg_op_fill": (i, [_vp, i, ctypes.POINTER(MgLevelBC), _vp, _vp, _vp]),
         "mg_op_defect": (i, [_vp, i, d, ctypes.POINTER(MgLevelBC), _vp, _vp, _vp, _vp]),
         "mg_op_restrict": (i, [_vp, i, _vp, _vp, _vp]),
         "mg_op_prolong_add": (i, [_vp, i, ctypes.POINTER(MgLevelBC), _vp, _vp, _vp]),
         "mg_op_prolong_fmg": (i, [_vp, i, ctypes.POINTER(MgLevelBC), _vp, _vp, _vp]),
         "mg_op_coarsest": (i, [_vp, d, ctypes.POINTER(MgLevelBC), _vp, _vp, _vp]),
         "mg_op_down": (i, [_vp, i, d, d, i, ctypes.POINTER(MgLevelBC), _vp, _vp, _vp, _vp, _vp]),
+        "mg_op_smooth_f32": (i, [_vp, i, d, d, i, i, ctypes.POINTER(MgLevelBC), _vp, _vp, _vp]),
+        "mg_op_down_f32": (i, [_vp, i, d, d, i, ctypes.POINTER(MgLevelBC), _vp, _vp, _vp, _vp, _vp]),
+        "mg_op_up_f32": (i, [_vp, i, d, d, i, ctypes.POINTER(MgLevelBC), ctypes.POINTER(MgLevelBC), _vp, _vp, _vp,
+                             _vp]),
+        "mg_op_sweep_input_norm": (i, [_vp, i, d, d, ctypes.POINTER(MgLevelBC), _vp, _vp, _dp, _vp]),
+        "mg_op_mixed_update": (i, [_vp, i, d, ctypes.POINTER(MgLevelBC), _vp, _vp, _vp, _vp, _dp, _vp]),
         "mg_op_up": (i, [_vp, i, d, d, i, ctypes.POINTER(MgLevelBC), ctypes.POINTER(MgLevelBC), _vp, _vp, _vp,
                          _vp]),
     }

@@ -26,6 +26,9 @@ using namespace mg;
 struct mg_ctx {
   int device = 0;
   std::string err;
+  // device bytes this context may hold (workspace, operator scratch, reduction scratch);
+  // 0 = no limit
+  size_t hbm_budget = 0;
   size_t lds_per_block = 65536;
   int tail64_top = 3;          // highest FP64 level held by the LDS coarse tail
   char* ws = nullptr;
@@ -192,8 +195,21 @@ LevelBC to_level_bc(const mg_level_bc* b) {
   return r;
 }
 
+// Device bytes the context holds besides its workspace and operator scratch.
+constexpr size_t kFixedBytes = sizeof(double) * (kMaxPartials * 32 + kScal);
+
+// Would holding `bytes` more (beyond what the context holds now, less `freed`) exceed its budget?
+bool over_budget(const mg_ctx* c, size_t bytes, size_t freed) {
+  if (c->hbm_budget == 0) return false;
+  const size_t held = kFixedBytes + c->ws_cap + c->op_scratch_cap - freed;
+  return held + bytes > c->hbm_budget;
+}
+
 int ensure_ws(mg_ctx* c, size_t bytes) {
   if (bytes <= c->ws_cap) return MG_OK;
+  if (over_budget(c, bytes, c->ws_cap))
+    return fail(c, MG_ERR_OOM, "workspace of " + std::to_string(bytes) + " bytes exceeds the context's HBM budget of " +
+                                   std::to_string(c->hbm_budget) + " bytes");
   if (c->ws) {
     HIP_CHECK(c, hipDeviceSynchronize());
     HIP_CHECK(c, hipFree(c->ws));
@@ -721,11 +737,13 @@ void mg_default_params(mg_params* p) {
   p->scheme = MG_SCHEME_CS;
 }
 
-int mg_ctx_create(mg_ctx** out, int device) {
+int mg_ctx_create(mg_ctx** out, int device, size_t hbm_budget) {
   if (!out) return MG_ERR_INVALID_ARG;
   *out = nullptr;
+  if (hbm_budget != 0 && hbm_budget < kFixedBytes) return MG_ERR_OOM;
   mg_ctx* c = new mg_ctx();
   c->device = device;
+  c->hbm_budget = hbm_budget;
   hipError_t e = hipSetDevice(device);
   if (e != hipSuccess) {
     delete c;
@@ -770,8 +788,7 @@ const char* mg_last_error(const mg_ctx* c) { return c ? c->err.c_str() : "null c
 
 size_t mg_footprint_bytes(const mg_params* p) {
   if (!p || !is_pow2(p->n) || p->n < 2 || p->n > 2048) return 0;
-  return make_layout(p->n, p->precision, layout_lb(p), p->scheme == MG_SCHEME_FAS).total +
-         sizeof(double) * (kMaxPartials * 32 + kScal);
+  return make_layout(p->n, p->precision, layout_lb(p), p->scheme == MG_SCHEME_FAS).total + kFixedBytes;
 }
 
 int mg_ctx_reserve(mg_ctx* c, const mg_params* p) {
@@ -1094,6 +1111,24 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
   return status;
 }
 
+extern "C" int mg_solve_simple(mg_ctx* c, int n, const double* rho, int bc_kind, double dx, double tol, double* phi,
+                               double* hist, int* n_hist, void* stream) {
+  if (!c) return MG_ERR_INVALID_ARG;
+  if (n_hist) *n_hist = 0;
+  if (bc_kind < MG_BC_PERIODIC || bc_kind > MG_BC_MULTIPOLE) return fail(c, MG_ERR_INVALID_ARG, "bad face kind");
+  if (!(tol > 0) || !std::isfinite(tol)) return fail(c, MG_ERR_INVALID_ARG, "tol must be positive");
+  mg_params p;
+  mg_default_params(&p);
+  p.n = n;
+  p.dx = dx;
+  p.tol = tol;
+  mg_bc bc;
+  std::memset(&bc, 0, sizeof(bc));
+  for (int f = 0; f < 6; ++f) bc.kind[f] = bc_kind;
+  bc.lmax = 4;
+  return mg_solve(c, &p, &bc, rho, phi, hist, n_hist, stream);
+}
+
 // ============================================================== autotuner
 
 namespace {
@@ -1103,6 +1138,7 @@ int autotune_blocks(mg_ctx* c, const mg_params* p, int Lb, int reps) {
   const int L = ilog2(p->n);
   const size_t cellsL = cells(L);
   T* buf[3] = {nullptr, nullptr, nullptr};
+  if (over_budget(c, 3 * cellsL * sizeof(T), 0)) return fail(c, MG_ERR_OOM, "autotune scratch exceeds the HBM budget");
   for (auto& b : buf)
     if (hipMalloc((void**)&b, cellsL * sizeof(T)) != hipSuccess) {
       (void)hipGetLastError();
@@ -1167,6 +1203,8 @@ int autotune_dense(mg_ctx* c, const mg_params* p, int reps) {
   const size_t cellsL = cells(L);
   T* buf[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   const size_t sz[5] = {cellsL, cellsL, cellsL, cellsL / 8, cellsL / 8};
+  if (over_budget(c, (3 * cellsL + cellsL / 4) * sizeof(T), 0))
+    return fail(c, MG_ERR_OOM, "autotune scratch exceeds the HBM budget");
   for (int q = 0; q < 5; ++q)
     if (hipMalloc((void**)&buf[q], sz[q] * sizeof(T)) != hipSuccess) {
       (void)hipGetLastError();
@@ -1353,6 +1391,8 @@ int op_epilogue(mg_ctx* c) {
 }
 int op_scratch(mg_ctx* c, size_t bytes, double** out) {
   if (bytes > c->op_scratch_cap) {
+    if (over_budget(c, bytes, c->op_scratch_cap))
+      return fail(c, MG_ERR_OOM, "operator scratch exceeds the context's HBM budget");
     if (c->op_scratch) {
       HIP_CHECK(c, hipDeviceSynchronize());
       HIP_CHECK(c, hipFree(c->op_scratch));
@@ -1369,6 +1409,98 @@ int op_scratch(mg_ctx* c, size_t bytes, double** out) {
   *out = reinterpret_cast<double*>(c->op_scratch);
   return MG_OK;
 }
+
+// `sweeps` full sweeps of u in place: on levels the streaming passes support, ping-ponging
+// with the operator scratch (zero_in: u is zero on input and the first sweep does not read
+// it, as in the first sweep of a mixed-precision correction cycle); else per colour.
+template <typename T>
+int op_smooth(mg_ctx* c, int n, double h, double omega, int sweeps, bool zero_in, const mg_level_bc* bc, T* u,
+              const T* f, void* stream) {
+  int st = op_prologue(c, n);
+  if (st) return st;
+  if (n < 2 || sweeps < 0 || sweeps > 4) return fail(c, MG_ERR_INVALID_ARG, "n >= 2, sweeps 0..4");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const LevelBC b = to_level_bc(bc);
+  if (fused_supported<T>(n) && sweeps > 0) {
+    double* tmp = nullptr;
+    st = op_scratch(c, cells(ilog2(n)) * sizeof(T), &tmp);
+    if (st) return st;
+    T* cur = u;
+    T* oth = reinterpret_cast<T*>(tmp);
+    for (int it = 0; it < sweeps; ++it) {
+      fused_sweep<T>(it == 0 && zero_in ? nullptr : cur, oth, f, n, h, omega, b, s);
+      std::swap(cur, oth);
+    }
+    if (cur != u) HIP_CHECK(c, hipMemcpyAsync(u, cur, cells(ilog2(n)) * sizeof(T), hipMemcpyDeviceToDevice, s));
+  } else {
+    if (zero_in && sweeps > 0) HIP_CHECK(c, hipMemsetAsync(u, 0, cells(ilog2(n)) * sizeof(T), s));
+    for (int it = 0; it < sweeps; ++it)
+      for (int colour = 0; colour < 2; ++colour) launch_half_sweep<T>(u, f, n, h, omega, colour, b, s);
+  }
+  return op_epilogue(c);
+}
+
+// Down step (Alg. 1 steps 1-3) with the context's fusion schedule for this precision.
+template <typename T>
+int op_down(mg_ctx* c, int n, double h, double omega, int npre, const mg_level_bc* bc, T* u, const T* f, T* fc, T* uc,
+            void* stream) {
+  int st = op_prologue(c, n);
+  if (st) return st;
+  if (n < 2 || npre < 0 || npre > 4) return fail(c, MG_ERR_INVALID_ARG, "n >= 2, npre 0..4");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const LevelBC b = to_level_bc(bc);
+  if (fused_supported<T>(n) && npre > 0) {
+    double* tmp = nullptr;
+    st = op_scratch(c, cells(ilog2(n)) * sizeof(T), &tmp);
+    if (st) return st;
+    // the context's schedule, as in the solver: the restricted defect fused into the last
+    // sweep or as its own pass
+    auto it_split = c->pass_split.find((sizeof(T) == 8 ? 0 : 1000) + ilog2(n));
+    const bool sdef = it_split != c->pass_split.end() ? (it_split->second & 1) != 0 : false;
+    T* cur = u;
+    T* oth = reinterpret_cast<T*>(tmp);
+    for (int it = 0; it < npre; ++it) {
+      if (it == npre - 1 && !sdef) fused_sweep_defect<T>(cur, oth, f, fc, uc, n, h, omega, b, s);
+      else fused_sweep<T>(cur, oth, f, n, h, omega, b, s);
+      std::swap(cur, oth);
+    }
+    if (sdef) fused_defect_restrict<T>(cur, f, fc, uc, n, h, b, s);
+    if (cur != u) HIP_CHECK(c, hipMemcpyAsync(u, cur, cells(ilog2(n)) * sizeof(T), hipMemcpyDeviceToDevice, s));
+    return op_epilogue(c);
+  }
+  st = op_smooth<T>(c, n, h, omega, npre, false, bc, u, f, stream);
+  if (st) return st;
+  launch_defect_restrict<T>(u, f, fc, uc, n, h, b, s);
+  return op_epilogue(c);
+}
+
+// Up step (Alg. 1 steps 5-7): the prolonged correction enters with the first post-sweep.
+template <typename T>
+int op_up(mg_ctx* c, int n, double h, double omega, int npost, const mg_level_bc* bc, const mg_level_bc* bc_coarse,
+          T* u, const T* f, const T* uc, void* stream) {
+  int st = op_prologue(c, n);
+  if (st) return st;
+  if (n < 2 || npost < 0 || npost > 4) return fail(c, MG_ERR_INVALID_ARG, "n >= 2, npost 0..4");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const LevelBC b = to_level_bc(bc), bcc = to_level_bc(bc_coarse);
+  if (fused_supported<T>(n) && npost > 0) {
+    double* tmp = nullptr;
+    st = op_scratch(c, cells(ilog2(n)) * sizeof(T), &tmp);
+    if (st) return st;
+    T* cur = u;
+    T* oth = reinterpret_cast<T*>(tmp);
+    for (int it = 0; it < npost; ++it) {
+      if (it == 0) fused_prolong_sweep<T>(cur, oth, f, uc, bcc, n, h, omega, b, s);
+      else fused_sweep<T>(cur, oth, f, n, h, omega, b, s);
+      std::swap(cur, oth);
+    }
+    if (cur != u) HIP_CHECK(c, hipMemcpyAsync(u, cur, cells(ilog2(n)) * sizeof(T), hipMemcpyDeviceToDevice, s));
+    return op_epilogue(c);
+  }
+  launch_prolong<T>(uc, u, n / 2, bcc, 0, s);
+  return op_smooth<T>(c, n, h, omega, npost, false, bc, u, f, stream);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1384,26 +1516,19 @@ int mg_op_half_sweep(mg_ctx* c, int n, double h, double omega, int colour, const
 
 int mg_op_smooth(mg_ctx* c, int n, double h, double omega, int sweeps, const mg_level_bc* bc, double* u,
                  const double* f, void* stream) {
+  return op_smooth<double>(c, n, h, omega, sweeps, false, bc, u, f, stream);
+}
+
+int mg_op_smooth_f32(mg_ctx* c, int n, double h, double omega, int sweeps, int zero_in, const mg_level_bc* bc,
+                     float* u, const float* f, void* stream) {
+  return op_smooth<float>(c, n, h, omega, sweeps, zero_in != 0, bc, u, f, stream);
+}
+
+int mg_op_fill(mg_ctx* c, int n, const mg_level_bc* bc, const double* u, double* out, void* stream) {
   int st = op_prologue(c, n);
   if (st) return st;
-  if (n < 2 || sweeps < 0 || sweeps > 4) return fail(c, MG_ERR_INVALID_ARG, "n >= 2, sweeps 0..4");
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const LevelBC b = to_level_bc(bc);
-  if (fused_supported<double>(n) && sweeps > 0) {
-    double* tmp = nullptr;
-    st = op_scratch(c, cells(ilog2(n)) * sizeof(double), &tmp);
-    if (st) return st;
-    double* cur = u;
-    double* oth = tmp;
-    for (int it = 0; it < sweeps; ++it) {
-      fused_sweep<double>(cur, oth, f, n, h, omega, b, s);
-      std::swap(cur, oth);
-    }
-    if (cur != u) HIP_CHECK(c, hipMemcpyAsync(u, cur, cells(ilog2(n)) * sizeof(double), hipMemcpyDeviceToDevice, s));
-  } else {
-    for (int it = 0; it < sweeps; ++it)
-      for (int colour = 0; colour < 2; ++colour) launch_half_sweep<double>(u, f, n, h, omega, colour, b, s);
-  }
+  if (!u || !out) return fail(c, MG_ERR_INVALID_ARG, "null u or out");
+  launch_fill(u, out, n, to_level_bc(bc), reinterpret_cast<hipStream_t>(stream));
   return op_epilogue(c);
 }
 
@@ -1445,59 +1570,74 @@ int mg_op_coarsest(mg_ctx* c, double h, const mg_level_bc* bc, double* u, const 
 
 int mg_op_down(mg_ctx* c, int n, double h, double omega, int npre, const mg_level_bc* bc, double* u, const double* f,
                double* fc, double* uc, void* stream) {
-  int st = op_prologue(c, n);
-  if (st) return st;
-  if (n < 2 || npre < 0 || npre > 4) return fail(c, MG_ERR_INVALID_ARG, "n >= 2, npre 0..4");
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const LevelBC b = to_level_bc(bc);
-  if (fused_supported<double>(n) && npre > 0) {
-    double* tmp = nullptr;
-    st = op_scratch(c, cells(ilog2(n)) * sizeof(double), &tmp);
-    if (st) return st;
-    // the context's schedule, as in the solver: the restricted defect fused into the last
-    // sweep or as its own pass
-    auto it_split = c->pass_split.find(ilog2(n));
-    const bool sdef = it_split != c->pass_split.end() ? (it_split->second & 1) != 0 : false;
-    double* cur = u;
-    double* oth = tmp;
-    for (int it = 0; it < npre; ++it) {
-      if (it == npre - 1 && !sdef) fused_sweep_defect<double>(cur, oth, f, fc, uc, n, h, omega, b, s);
-      else fused_sweep<double>(cur, oth, f, n, h, omega, b, s);
-      std::swap(cur, oth);
-    }
-    if (sdef) fused_defect_restrict<double>(cur, f, fc, uc, n, h, b, s);
-    if (cur != u) HIP_CHECK(c, hipMemcpyAsync(u, cur, cells(ilog2(n)) * sizeof(double), hipMemcpyDeviceToDevice, s));
-    return op_epilogue(c);
-  }
-  st = mg_op_smooth(c, n, h, omega, npre, bc, u, f, stream);
-  if (st) return st;
-  launch_defect_restrict<double>(u, f, fc, uc, n, h, b, s);
-  return op_epilogue(c);
+  return op_down<double>(c, n, h, omega, npre, bc, u, f, fc, uc, stream);
+}
+
+int mg_op_down_f32(mg_ctx* c, int n, double h, double omega, int npre, const mg_level_bc* bc, float* u, const float* f,
+                   float* fc, float* uc, void* stream) {
+  return op_down<float>(c, n, h, omega, npre, bc, u, f, fc, uc, stream);
 }
 
 int mg_op_up(mg_ctx* c, int n, double h, double omega, int npost, const mg_level_bc* bc, const mg_level_bc* bc_coarse,
              double* u, const double* f, const double* uc, void* stream) {
+  return op_up<double>(c, n, h, omega, npost, bc, bc_coarse, u, f, uc, stream);
+}
+
+int mg_op_up_f32(mg_ctx* c, int n, double h, double omega, int npost, const mg_level_bc* bc,
+                 const mg_level_bc* bc_coarse, float* u, const float* f, const float* uc, void* stream) {
+  return op_up<float>(c, n, h, omega, npost, bc, bc_coarse, u, f, uc, stream);
+}
+
+int mg_op_sweep_input_norm(mg_ctx* c, int n, double h, double omega, const mg_level_bc* bc, double* u,
+                           const double* f, double* sumsq, void* stream) {
   int st = op_prologue(c, n);
   if (st) return st;
-  if (n < 2 || npost < 0 || npost > 4) return fail(c, MG_ERR_INVALID_ARG, "n >= 2, npost 0..4");
+  if (n < 2 || !u || !f || !sumsq) return fail(c, MG_ERR_INVALID_ARG, "n >= 2 and every array");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const LevelBC b = to_level_bc(bc), bcc = to_level_bc(bc_coarse);
-  if (fused_supported<double>(n) && npost > 0) {
+  const LevelBC b = to_level_bc(bc);
+  const size_t n3 = cells(ilog2(n));
+  if (fused_supported<double>(n)) {
+    // the solver's head pass: the sweep, with the defect of its input summed on the way
     double* tmp = nullptr;
-    st = op_scratch(c, cells(ilog2(n)) * sizeof(double), &tmp);
+    st = op_scratch(c, n3 * sizeof(double), &tmp);
     if (st) return st;
-    double* cur = u;
-    double* oth = tmp;
-    for (int it = 0; it < npost; ++it) {
-      if (it == 0) fused_prolong_sweep<double>(cur, oth, f, uc, bcc, n, h, omega, b, s);
-      else fused_sweep<double>(cur, oth, f, n, h, omega, b, s);
-      std::swap(cur, oth);
-    }
-    if (cur != u) HIP_CHECK(c, hipMemcpyAsync(u, cur, cells(ilog2(n)) * sizeof(double), hipMemcpyDeviceToDevice, s));
-    return op_epilogue(c);
+    const int np = fused_sweep_input_norm<double>(u, tmp, f, c->part, n, h, omega, b, s);
+    launch_sum_partials(c->part, np, c->scal + 2, s);
+    HIP_CHECK(c, hipMemcpyAsync(u, tmp, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  } else {
+    launch_defect_norm(u, f, nullptr, n, h, b, c->part, c->scal + 2, s);
+    for (int colour = 0; colour < 2; ++colour) launch_half_sweep<double>(u, f, n, h, omega, colour, b, s);
   }
-  launch_prolong<double>(uc, u, n / 2, bcc, 0, s);
-  return mg_op_smooth(c, n, h, omega, npost, bc, u, f, stream);
+  HIP_CHECK(c, hipMemcpyAsync(c->hscal + 2, c->scal + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(c, hipStreamSynchronize(s));
+  *sumsq = c->hscal[2];
+  return op_epilogue(c);
+}
+
+int mg_op_mixed_update(mg_ctx* c, int n, double h, const mg_level_bc* bc, double* phi, const float* e, const double* f,
+                       float* r32, double* sumsq, void* stream) {
+  int st = op_prologue(c, n);
+  if (st) return st;
+  if (n < 2 || !phi || !e || !f || !r32 || !sumsq) return fail(c, MG_ERR_INVALID_ARG, "n >= 2 and every array");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const LevelBC b = to_level_bc(bc);
+  const size_t n3 = cells(ilog2(n));
+  if (n >= kFusedMinN) {
+    // the solver's streaming pass: phi + e, its defect, the FP32 copy and the partial sums
+    double* tmp = nullptr;
+    st = op_scratch(c, n3 * sizeof(double), &tmp);
+    if (st) return st;
+    const int np = fused_mixed_update_defect(phi, tmp, e, f, r32, c->part, n, h, b, s);
+    launch_sum_partials(c->part, np, c->scal + 2, s);
+    HIP_CHECK(c, hipMemcpyAsync(phi, tmp, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  } else {
+    launch_add_f32(phi, e, n3, s);
+    launch_defect_norm(phi, f, r32, n, h, b, c->part, c->scal + 2, s);
+  }
+  HIP_CHECK(c, hipMemcpyAsync(c->hscal + 2, c->scal + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(c, hipStreamSynchronize(s));
+  *sumsq = c->hscal[2];
+  return op_epilogue(c);
 }
 
 int mg_multipole_moments(mg_ctx* c, int n, double dx, const double* rho, int lmax, int use_origin, const double* origin,

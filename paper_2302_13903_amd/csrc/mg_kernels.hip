@@ -713,6 +713,27 @@ __global__ void __launch_bounds__(kBlock) k_face_restrict(const double* __restri
   ec[t] = (r0[2 * t1] + r0[2 * t1 + 1] + r1[2 * t1] + r1[2 * t1 + 1]) / 4.0;
 }
 
+// ------------------------------------------------------------------ ghost fill (Sec. 2.3.6)
+
+// The ghost-filled copy of one level: out is (n+2)^3, x fastest, with active cell (i, j, k) at
+// ((k+1)(n+2) + j+1)(n+2) + i+1 and every ghost -- faces, edges and corners -- set by the
+// axis-ordered rule the prolongations read (x first, then y over the x ghosts, then z over
+// both), i.e. the value ghost_any evaluates on the fly.
+__global__ void __launch_bounds__(kBlock) k_fill(const double* __restrict__ u, double* __restrict__ out, int n,
+                                                  int L, LevelBC bc) {
+  const size_t m = (size_t)n + 2;
+  const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= m * m * m) return;
+  const int i = (int)(t % m) - 1, j = (int)((t / m) % m) - 1, k = (int)(t / (m * m)) - 1;
+  const bool inside = i >= 0 && i < n && j >= 0 && j < n && k >= 0 && k < n;
+  out[t] = inside ? u[cidx(L, i, j, k)] : ghost_any(u, n, L, i, j, k, bc);
+}
+
+void launch_fill(const double* u, double* out, int n, const LevelBC& bc, hipStream_t s) {
+  const size_t m = (size_t)n + 2;
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(m * m * m)), dim3(kBlock), 0, s, u, out, n, ilog2(n), bc);
+}
+
 void launch_face_extend(const double* b, double* e, int n, hipStream_t s) {
   const int m = n + 2;
   hipLaunchKernelGGL(k_face_extend, dim3((m * m + kBlock - 1) / kBlock), dim3(kBlock), 0, s, b, e, n);

@@ -4,7 +4,7 @@
 // request at its arrival time into a pending queue.  `workers` threads, one HIP stream each,
 // take requests from the queue when their hierarchy fits the HBM budget, run mg_solve on
 // their stream and release the hierarchy, which stays resident for the next request of the
-// same (n, precision).  All bookkeeping (queue, pool, counters) is under one mutex; device
+// same workspace class (n, precision, MeshBlock side, scheme).  All bookkeeping (queue, pool, counters) is under one mutex; device
 // allocation, release and the solves themselves run outside it.
 #include <hip/hip_runtime.h>
 
@@ -26,10 +26,26 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-// A resident hierarchy: one solver context sized for (n, precision) plus an n^3 result slot.
+// Workspace class of a request: solves of one class need the same workspace (size,
+// precision, MeshBlock side for the block layout, scheme), so one resident hierarchy serves
+// every request of its class.
+struct Class {
+  int n = 0, precision = 0, block_n = 0, scheme = 0;
+  bool operator==(const Class& o) const {
+    return n == o.n && precision == o.precision && block_n == o.block_n && scheme == o.scheme;
+  }
+};
+
+Class class_of(const mg_params& p) {
+  return Class{p.n, p.precision, p.layout == MG_LAYOUT_BLOCKS ? p.block_n : 0, p.scheme};
+}
+
+// A resident hierarchy: one solver context sized for its class (with that footprint as the
+// context's HBM budget, so it never grows beyond what admission counted) plus an n^3 result
+// slot.
 struct Entry {
-  int n = 0;
-  int precision = 0;
+  Class cls;
+  mg_params params{};        // parameters the context is reserved for
   size_t bytes = 0;
   mg_ctx* ctx = nullptr;
   double* slot = nullptr;
@@ -87,16 +103,12 @@ int materialise(mg_server* s, Entry* e) {
     e->ready = true;
     return MG_OK;
   }
-  mg_params p;
-  mg_default_params(&p);
-  p.n = e->n;
-  p.dx = 1.0 / e->n;
-  p.precision = e->precision;
-  int st = mg_ctx_create(&e->ctx, s->cfg.device);
+  const mg_params& p = e->params;
+  int st = mg_ctx_create(&e->ctx, s->cfg.device, mg_footprint_bytes(&p));
   if (st != MG_OK) return st;
   st = mg_ctx_reserve(e->ctx, &p);
   if (st != MG_OK) return st;
-  if (hipMalloc((void**)&e->slot, (size_t)e->n * e->n * e->n * sizeof(double)) != hipSuccess) {
+  if (hipMalloc((void**)&e->slot, (size_t)p.n * p.n * p.n * sizeof(double)) != hipSuccess) {
     (void)hipGetLastError();
     return MG_ERR_OOM;
   }
@@ -104,13 +116,14 @@ int materialise(mg_server* s, Entry* e) {
   return MG_OK;
 }
 
-// Under the lock: find or make room for an entry of (n, precision).  Idle entries of other
-// sizes that must go to make room are moved into `evict` (the caller frees them unlocked).
+// Under the lock: find or make room for an entry of the class of p.  Idle entries of other
+// classes that must go to make room are moved into `evict` (the caller frees them unlocked).
 // Returns nullptr when the request must wait.
-Entry* acquire_locked(mg_server* s, int n, int precision, size_t bytes, std::vector<std::unique_ptr<Entry>>& evict,
+Entry* acquire_locked(mg_server* s, const mg_params& p, size_t bytes, std::vector<std::unique_ptr<Entry>>& evict,
                       bool* reused) {
+  const Class cls = class_of(p);
   for (auto& e : s->pool)
-    if (!e->busy && e->n == n && e->precision == precision) {
+    if (!e->busy && e->cls == cls) {
       e->busy = true;
       e->last_used = ++s->tick;
       *reused = e->ready;
@@ -131,8 +144,8 @@ Entry* acquire_locked(mg_server* s, int n, int precision, size_t bytes, std::vec
     s->stats.evicted++;
   }
   auto e = std::make_unique<Entry>();
-  e->n = n;
-  e->precision = precision;
+  e->cls = cls;
+  e->params = p;
   e->bytes = bytes;
   e->busy = true;
   e->last_used = ++s->tick;
@@ -159,7 +172,7 @@ int pick_locked(mg_server* s, Entry** out, std::vector<std::unique_ptr<Entry>>& 
       s->pending.erase(s->pending.begin() + q);
       continue;
     }
-    Entry* e = acquire_locked(s, r.params.n, r.params.precision, bytes, evict, reused);
+    Entry* e = acquire_locked(s, r.params, bytes, evict, reused);
     if (e) {
       s->pending.erase(s->pending.begin() + q);
       *out = e;
@@ -310,8 +323,8 @@ int mg_server_reserve(mg_server* s, const mg_params* p, int count) {
         return MG_ERR_OOM;
       }
       auto ne = std::make_unique<Entry>();
-      ne->n = p->n;
-      ne->precision = p->precision;
+      ne->cls = class_of(*p);
+      ne->params = *p;
       ne->bytes = bytes;
       ne->busy = true;
       ne->last_used = ++s->tick;

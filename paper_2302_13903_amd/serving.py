@@ -35,6 +35,9 @@ class Request:
     fixed_cycles: int = 0
     precision: str = "fp64"
     mode: str = "fmg"
+    layout: str = "dense"
+    block_n: int = 16
+    scheme: str = "cs"
     lmax: int = 4
     fixed_b: Optional[Sequence] = None
     phi: object = None
@@ -96,8 +99,9 @@ class Server:
         except Exception:
             pass
 
-    def reserve(self, n: int, precision: str = "fp64", count: int = 1):
-        p = params(n, 1.0 / n, precision=precision)
+    def reserve(self, n: int, precision: str = "fp64", count: int = 1, layout: str = "dense", block_n: int = 16,
+                scheme: str = "cs"):
+        p = params(n, 1.0 / n, precision=precision, layout=layout, block_n=block_n, scheme=scheme)
         st = self._lib.mg_server_reserve(self.handle, ctypes.byref(p), int(count))
         if st != MG_OK:
             raise MgError(f"mg_server_reserve: {STATUS_NAMES.get(st, st)}: "
@@ -111,7 +115,8 @@ class Server:
             dx = r.dx or (1.0 / n if n else 0.0)
             q = arr[i]
             q.params = params(n, dx, tol=r.tol, max_cycles=r.max_cycles, fixed_cycles=r.fixed_cycles,
-                              precision=r.precision, mode=r.mode)
+                              precision=r.precision, mode=r.mode, layout=r.layout, block_n=r.block_n,
+                              scheme=r.scheme)
             q.bc = boundary(r.bc, r.fixed_b, r.lmax)
             q.rho = _dev_ptr(r.rho) if not self.simulate else None
             q.phi = _dev_ptr(r.phi) if not self.simulate else None

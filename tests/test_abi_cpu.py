@@ -67,3 +67,25 @@ def test_gravity_kernel_names():
     name = mg.mg_gravity_kernel_name(mg.params(256, 1 / 256, layout="blocks", block_n=16), True, False, True)
     assert "k_grav_stream<4, 4, true, 1>" in name      # no face output in the MeshBlock layout
     assert mg.mg_gravity_kernel_name(mg.params(12, 1 / 12)) == ""
+
+
+def test_boundary_entry_points_declared():
+    """The boundary's short solve, the ghost-fill operator and the budgeted context are part of
+    the header (each exported; their GPU behaviour is covered by the parity tests)."""
+    declared = _abi.declared_functions()
+    for name in ("mg_solve", "mg_solve_simple", "mg_op_fill", "mg_ctx_create", "mg_footprint_bytes",
+                 "mg_last_error", "mg_ctx_destroy"):
+        assert name in declared, name
+    import re
+    src = open(_abi.HEADER).read()
+    assert re.search(r"int mg_ctx_create\(mg_ctx \*\*ctx, int device, size_t hbm_budget\);", src)
+
+
+def test_context_budget_below_fixed_scratch_is_refused():
+    """A budget that cannot hold the context's reduction scratch is refused before any device
+    call (MG_ERR_OOM), and a null output handle is an argument error."""
+    lib = _abi.lib()
+    h = ctypes.c_void_p()
+    assert lib.mg_ctx_create(ctypes.byref(h), 0, 1024) == _abi.MG_ERR_OOM
+    assert not h.value
+    assert lib.mg_ctx_create(None, 0, 0) == _abi.MG_ERR_INVALID_ARG

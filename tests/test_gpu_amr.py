@@ -48,10 +48,7 @@ def case(NB, nb, boxes, kinds, seed):
     return m, rho, faces
 
 
-def rel(a, b):
-    num = math.sqrt(sum(float(np.sum((x - y) ** 2)) for x, y in zip(a, b)))
-    den = math.sqrt(sum(float(np.sum(y ** 2)) for y in b))
-    return num / den
+from parity import rel, rel_l2  # noqa: E402  (relative L2 and element-wise bounds together)
 
 
 @pytest.mark.parametrize("kname", list(KINDS))

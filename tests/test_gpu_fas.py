@@ -34,8 +34,7 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
 
 
-def rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+from parity import rel, rel_l2  # noqa: E402  (relative L2 and element-wise bounds together)
 
 
 def floor_of(phi, rho, kinds):

@@ -124,3 +124,45 @@ def test_admission_under_a_small_budget():
         assert torch.equal(phis[i], want[sizes[i]]), i
     assert st["rejected"] == 1 and st["peak_bytes"] <= int(2.5 * fp128)
     assert st["created"] >= 2
+
+
+def test_served_results_match_the_oracle():
+    """Per-request oracle check of a served mix: every boundary kind of the request stream
+    (periodic, fixed b = 0, multipole l <= 4) at 64^3 and 128^3 in both precisions, served
+    together by four workers.  FP64 requests equal the oracle at their own cycle count (phi to
+    1e-10, relative L2 and element-wise; histories cycle by cycle); mixed-precision requests
+    equal the oracle converged to its round-off floor (phi to 1e-10)."""
+    import math
+
+    import oracle
+    from parity import rel
+    print("serving vs oracle", flush=True)
+    cases = [(n, bc, prec) for n in (64, 128) for bc in ("periodic", "fixed", "multipole")
+             for prec in ("fp64", "mixed")]
+    rhos_h = [wl.gaussian_clumps(n, 300 + i, remove_mean=bc == "periodic") for i, (n, bc, _) in enumerate(cases)]
+    rhos = [dev(r) for r in rhos_h]
+    phis = [torch.zeros_like(r) for r in rhos]
+    reqs = [serving.Request(rho=rhos[i], bc=bc, precision=prec, phi=phis[i], want_hist=True,
+                            tol=1e-10 if prec == "fp64" else 1e-11, arrival_ms=0.5 * i)
+            for i, (n, bc, prec) in enumerate(cases)]
+    srv = serving.Server(workers=4)
+    srv.run(reqs)
+    torch.cuda.synchronize()
+    assert srv.stats()["max_concurrent"] >= 2
+    for i, (n, bc, prec) in enumerate(cases):
+        r = reqs[i]
+        assert r.status == 0, (cases[i], r.status, r.hist)
+        got = phis[i].cpu().numpy()
+        if prec == "fp64":
+            ref, rh, _ = oracle.solve(rhos_h[i], 1.0 / n, bc, fixed_cycles=len(r.hist) - 1)
+            f = 4 * math.pi * rhos_h[i]
+            if bc == "periodic":
+                f = f - f.mean()
+            floor = 12 * np.finfo(float).eps * np.abs(ref).max() * n * n / math.sqrt(np.mean(f * f))
+            for a, b in zip(r.hist, rh):
+                assert abs(a - b) <= 1e-6 * b + 10 * floor, (cases[i], r.hist, rh)
+        else:
+            ref, rh, _ = oracle.solve(rhos_h[i], 1.0 / n, bc, tol=1e-13, max_cycles=40)
+        err = rel(got, ref)
+        print(f"served {cases[i]}: cycles {len(r.hist) - 1}, vs oracle {err:.2e}", flush=True)
+        assert err < 1e-10, (cases[i], err)

@@ -165,3 +165,40 @@ def test_fmg_coarse_boundary_values_are_restricted():
         b2 = s.face(2, face)[1:-1, 1:-1]
         assert np.allclose(b3, faces[face])
         assert np.allclose(b2, faces[face].reshape(4, 2, 4, 2).mean(axis=(1, 3)))
+
+
+@pytest.mark.parametrize("n,kinds", [
+    (32, "periodic"),
+    (64, [FIXED] * 6),
+    (32, [PERIODIC, PERIODIC, FIXED, FIXED, ZERO_GRADIENT, ZERO_GRADIENT]),
+    (32, [ZERO_GRADIENT] * 6),
+])
+def test_residual_history_is_the_defect_rms(n, kinds):
+    """Every history entry the oracle reports is RMS(f - L phi)/RMS(f) of the iterate it
+    returns (Sec. 2.3.7), recomputed with the matrix-free ghost rules of oracle.exact (itself
+    pinned: exact discrete solutions have round-off residuals).  For k = 0..4 V-cycles after
+    FMG, hist[k] of a k-cycle run matches that recomputation to 1e-12 relative plus 1 % of the
+    round-off floor (the returned phi is shifted to zero mean when gauge-free, which moves its
+    residual by round-off), and every run's history is a prefix of the next one's."""
+    gauge_free = kinds == "periodic" or kinds == [ZERO_GRADIENT] * 6
+    kk = [PERIODIC] * 6 if kinds == "periodic" else kinds
+    rho = wl.gaussian_clumps(n, 3, remove_mean=False)
+    rng = np.random.default_rng(1)
+    faces = [rng.standard_normal((n, n)) * 0.1 if k == FIXED else None for k in kk]
+    f = FPG * rho
+    if gauge_free:
+        f = f - f.mean()
+    prev = None
+    for k in range(5):
+        if k == 0:
+            phi, hist, st = oracle.solve(rho, 1.0 / n, kinds, fixed_b=faces, max_cycles=0)
+        else:
+            phi, hist, st = oracle.solve(rho, 1.0 / n, kinds, fixed_b=faces, fixed_cycles=k)
+        assert len(hist) == k + 1
+        r = ex.rel_residual(phi, f, 1.0 / n, kk, faces)
+        floor = 12 * np.finfo(float).eps * np.abs(phi).max() * n * n / math.sqrt(np.mean(f * f))
+        assert hist[-1] > 1e4 * floor          # every entry is far above the floor here
+        assert abs(hist[-1] - r) <= 1e-12 * r + 1e-2 * floor, (k, hist[-1], r, floor)
+        if prev is not None:
+            assert np.array_equal(hist[:-1], prev)
+        prev = hist

@@ -120,3 +120,22 @@ def test_invalid_config(bad):
     kw.update(bad)
     with pytest.raises((mg.MgError, KeyError)):
         serving.Server(**kw)
+
+
+def test_hierarchies_are_keyed_by_workspace_class():
+    """Requests of one size but another layout or scheme need another workspace: each gets a
+    hierarchy of its own class, accounted with its own footprint, and reuses only its class."""
+    kinds = [dict(), dict(layout="blocks", block_n=16), dict(layout="blocks", block_n=8), dict(scheme="fas")]
+    srv = serving.Server(workers=1, hbm_budget=1 << 40, simulate=True)
+    rs = []
+    for rep in range(2):
+        for kw in kinds:
+            rs.append(serving.Request(n=128, sim_ms=1.0, **kw))
+    srv.run(rs)
+    st = srv.stats()
+    assert all(r.status == 0 for r in rs)
+    assert st["created"] == len(kinds) and st["reused"] == len(kinds)
+    want = sum(mg.mg_footprint_bytes(mg.params(128, 1 / 128, **kw)) + 128 ** 3 * 8 + 256 for kw in kinds)
+    assert st["resident_bytes"] == want
+    # the FAS class holds the restricted potentials: a larger footprint than the plain one
+    assert mg.mg_footprint_bytes(mg.params(128, 1 / 128, scheme="fas")) > mg.mg_footprint_bytes(mg.params(128, 1 / 128))
