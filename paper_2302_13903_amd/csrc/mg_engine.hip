@@ -244,6 +244,10 @@ struct Solver {
   mg_ctx* c;
   hipStream_t s;
   bool use_fused = true;
+  // device reduction scratch of this solve (partials, scalars) and kernel timing on/off
+  double* part = nullptr;
+  double* scal = nullptr;
+  int ktiming = 0;
   int fused_min_n64 = kFusedDefaultMinN, fused_min_n32 = kFusedDefaultMinN;
   // the next top-level V-cycle starts from u = 0 without u having been cleared: its first
   // sweep must not read u (set by the caller, consumed by vcycle)
@@ -315,14 +319,14 @@ struct Solver {
   }
 
   // The head pass: first pre-sweep of the next V-cycle (u -> u2) and the residual norm of u
-  // (the iterate the stopping test of Sec. 2.3.7 is about) into c->scal[2].
+  // (the iterate the stopping test of Sec. 2.3.7 is about) into scal[2].
   void head(Hier<double>& H, const LevelBC& bc) {
     const int L = H.L, n = 1 << L;
-    const bool timed = timed_top && c->ktiming;
+    const bool timed = timed_top && ktiming;
     if (timed) kernel_begin();
-    const int np = fused_sweep_input_norm<double>(H.u[L], H.u2[L], H.f[L], c->part, n, H.h[L], H.omega, bc, s);
+    const int np = fused_sweep_input_norm<double>(H.u[L], H.u2[L], H.f[L], part, n, H.h[L], H.omega, bc, s);
     if (timed) kernel_end(fused_pass_name<double>(false, 3), 3.0 * (double)cells(L) * sizeof(double));
-    launch_sum_partials(c->part, np, c->scal + 2, s);
+    launch_sum_partials(part, np, scal + 2, s);
     head_done = true;
   }
 
@@ -335,7 +339,7 @@ struct Solver {
   // Alg. 1 on level l (l >= T_top).  At the tail level the whole remaining recursion runs in
   // one LDS-resident workgroup.  Large levels run four fused passes (sweep; sweep + restricted
   // defect; prolonged correction + sweep; sweep [+ defect norm]).  Returns true when the sum
-  // of squared defects of the result is in c->scal[2] (want_norm on a fused finest level).
+  // of squared defects of the result is in scal[2] (want_norm on a fused finest level).
   template <typename T>
   bool vcycle(Hier<T>& H, int l, const LevelBC& bc, bool top_call, bool want_norm) {
     if (top_call && zero_start) {
@@ -345,7 +349,7 @@ struct Solver {
                                (1 << l) >= (sizeof(T) == 8 ? fused_min_n64 : fused_min_n32) && !tblock_on<T>() &&
                                H.npre >= 1 && !(H.npre == 1 && !(split_of<T>(l) & 1));
       if (!fused_first) {
-        (void)hipMemsetAsync(H.u[l], 0, cells(l) * sizeof(T), s);
+        launch_zero(H.u[l], cells(l) * sizeof(T), s);
         zero_start = false;
       }
     }
@@ -355,7 +359,7 @@ struct Solver {
     }
     const int n = 1 << l;
     const double h = H.h[l];
-    const bool timed = top_call && l == H.L && c->ktiming;
+    const bool timed = top_call && l == H.L && ktiming;
     const double cellsT = (double)cells(l) * sizeof(T);
     if (use_fused && H.u2[l] && n >= (sizeof(T) == 8 ? fused_min_n64 : fused_min_n32) && tblock_on<T>()) {
       // temporally blocked: sweeps two at a time per pass; the restricted defect and the norm
@@ -397,9 +401,9 @@ struct Solver {
       bool normed = false;
       if (want_norm && sizeof(T) == 8) {
         if (timed) kernel_begin();
-        const int np = fused_defect_norm<T>(cur, H.f[l], c->part, n, h, bc, s);
+        const int np = fused_defect_norm<T>(cur, H.f[l], part, n, h, bc, s);
         if (timed) kernel_end(fused_pass_name<T>(false, 2, false), 2 * cellsT);
-        launch_sum_partials(c->part, np, c->scal + 2, s);
+        launch_sum_partials(part, np, scal + 2, s);
         normed = true;
       }
       if (cur != H.u[l]) (void)hipMemcpyAsync(H.u[l], cur, cells(l) * sizeof(T), hipMemcpyDeviceToDevice, s);
@@ -443,9 +447,9 @@ struct Solver {
           fused_prolong_sweep<T>(cur, oth, H.f[l], H.u[l - 1], H.hom, n, h, H.omega, bc, s);
           if (timed) kernel_end(fused_pass_name<T>(true, 0), 3 * cellsT + cellsT / 8);
         } else if (last && want_norm && !snorm) {
-          const int np = fused_sweep_norm<T>(cur, oth, H.f[l], c->part, n, h, H.omega, bc, s);
+          const int np = fused_sweep_norm<T>(cur, oth, H.f[l], part, n, h, H.omega, bc, s);
           if (timed) kernel_end(fused_pass_name<T>(false, 2), 3 * cellsT);
-          launch_sum_partials(c->part, np, c->scal + 2, s);
+          launch_sum_partials(part, np, scal + 2, s);
           normed = true;
         } else {
           fused_sweep<T>(cur, oth, H.f[l], n, h, H.omega, bc, s);
@@ -455,9 +459,9 @@ struct Solver {
       }
       if (want_norm && !normed && sizeof(T) == 8) {
         if (timed) kernel_begin();
-        const int np = fused_defect_norm<T>(cur, H.f[l], c->part, n, h, bc, s);
+        const int np = fused_defect_norm<T>(cur, H.f[l], part, n, h, bc, s);
         if (timed) kernel_end(fused_pass_name<T>(false, 2, false), 2 * cellsT);
-        launch_sum_partials(c->part, np, c->scal + 2, s);
+        launch_sum_partials(part, np, scal + 2, s);
         normed = true;
       }
       if (cur != H.u[l]) (void)hipMemcpyAsync(H.u[l], cur, cells(l) * sizeof(T), hipMemcpyDeviceToDevice, s);
@@ -489,7 +493,7 @@ struct Solver {
   // streaming passes, either ping-pong array); returns the array holding the result.
   double* fas_sweeps(Hier<double>& H, int l, double* cur, int count, const LevelBC& bc) {
     const int n = 1 << l;
-    const bool timed = timed_top && l == H.L && c->ktiming;
+    const bool timed = timed_top && l == H.L && ktiming;
     const double cellsT = (double)cells(l) * sizeof(double);
     if (use_fused && H.u2[l] && n >= fused_min_n64) {
       double* oth = cur == H.u[l] ? H.u2[l] : H.u[l];
@@ -526,7 +530,7 @@ struct Solver {
     }
     const int n = 1 << l;
     const LevelBC& bc = H.phys[l];
-    const bool timed = timed_top && l == H.L && c->ktiming;
+    const bool timed = timed_top && l == H.L && ktiming;
     const double cellsT = (double)cells(l) * sizeof(double);
     const bool streamed = use_fused && H.u2[l] && n >= fused_min_n64;
     // 1: the pre-sweeps; on streamed levels the last one carries steps 2-4 (fused below)
@@ -616,7 +620,7 @@ struct Solver {
     const BlkTune t = blk_tune<T>(Lm);
     T* oth = cur == H.u[l] ? H.u2[l] : H.u[l];
     int left = count;
-    const bool timed = timed_top && l == H.L && c->ktiming;
+    const bool timed = timed_top && l == H.L && ktiming;
     while (left > 0) {
       BlkTune ti = t;
       ti.S = (t.S == 2 && left >= 2) ? 2 : 1;
@@ -652,7 +656,7 @@ struct Solver {
     if (blk_zmarch_on<T>(l) && H.npre > 0 && H.npost > 0) {
       // streaming passes across block boundaries: one sweep per pass, the restricted defect
       // as its own pass, the prolonged correction entering with the first post-sweep
-      const bool timed = timed_top && l == H.L && c->ktiming;
+      const bool timed = timed_top && l == H.L && ktiming;
       const double cellsT = (double)cells(l) * sizeof(T);
       T* cur = H.u[l];
       T* oth = H.u2[l];
@@ -692,16 +696,16 @@ struct Solver {
   // Sum of squared finest-level defects into out (device); optionally the FP32 defect.
   void defect_norm(const double* u, const double* f, float* r32, int n, double h, const LevelBC& bc, double* out) {
     if (Lb >= 0 && n >= kFusedMinN) {
-      const int np = fused_blk_defect_norm<double>(u, f, c->part, ilog2(n) - Lb, Lb, h, bc, s, r32);
-      launch_sum_partials(c->part, np, out, s);
+      const int np = fused_blk_defect_norm<double>(u, f, part, ilog2(n) - Lb, Lb, h, bc, s, r32);
+      launch_sum_partials(part, np, out, s);
     } else if (Lb >= 0) {
-      const int np = blk_defect_norm(u, f, r32, ilog2(n) - Lb, Lb, h, bc, c->part, s);
-      launch_sum_partials(c->part, np, out, s);
+      const int np = blk_defect_norm(u, f, r32, ilog2(n) - Lb, Lb, h, bc, part, s);
+      launch_sum_partials(part, np, out, s);
     } else if (n >= kFusedMinN) {
-      const int np = fused_defect_norm<double>(u, f, c->part, n, h, bc, s, r32);
-      launch_sum_partials(c->part, np, out, s);
+      const int np = fused_defect_norm<double>(u, f, part, n, h, bc, s, r32);
+      launch_sum_partials(part, np, out, s);
     } else {
-      launch_defect_norm(u, f, r32, n, h, bc, c->part, out, s);
+      launch_defect_norm(u, f, r32, n, h, bc, part, out, s);
     }
   }
 };
@@ -836,19 +840,19 @@ int mg_last_timing(const mg_ctx* c, double* setup_ms, double* fmg_ms, double* cy
 namespace {
 
 // Build the per-level physical boundary descriptions in the workspace (Sec. 2.3.6, App. A).
-int setup_faces(mg_ctx* c, const Layout& y, const mg_params* p, const mg_bc* bc, const double* rho, hipStream_t s,
-                LevelBC* phys, LevelBC* hom) {
+int setup_faces(char* ws, double* part, double* scal, const Layout& y, const mg_params* p, const mg_bc* bc,
+                const double* rho, hipStream_t s, LevelBC* phys, LevelBC* hom) {
   const int L = y.L;
   bool any_mp = false;
   for (int f = 0; f < 6; ++f) any_mp |= bc->kind[f] == MG_BC_MULTIPOLE;
-  double* mps = c->scal + kMpoleOff;
+  double* mps = scal + kMpoleOff;
   const int Lb = layout_lb(p);
   if (any_mp)
-    launch_multipole_moments(rho, p->n, Lb >= 0 ? L - Lb : 0, p->dx, bc->lmax, bc->use_origin, bc->origin, c->part,
+    launch_multipole_moments(rho, p->n, Lb >= 0 ? L - Lb : 0, p->dx, bc->lmax, bc->use_origin, bc->origin, part,
                              mps, s);
   const double G = p->four_pi_g / (4.0 * M_PI);
   for (int l = L; l >= 0; --l) {
-    double* fb = reinterpret_cast<double*>(c->ws + y.faces[l]);
+    double* fb = reinterpret_cast<double*>(ws + y.faces[l]);
     double* mp_out[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     for (int f = 0; f < 6; ++f) {
       const int k = bc->kind[f];
@@ -857,7 +861,7 @@ int setup_faces(mg_ctx* c, const Layout& y, const mg_params* p, const mg_bc* bc,
       phys[l].b[f] = nullptr;
       if (k == MG_BC_FIXED) {
         if (l == L) launch_face_extend(bc->fixed_b[f], e, 1 << l, s);
-        else launch_face_restrict(reinterpret_cast<double*>(c->ws + y.faces[l + 1]) + (size_t)f * face_sz(l + 1), e,
+        else launch_face_restrict(reinterpret_cast<double*>(ws + y.faces[l + 1]) + (size_t)f * face_sz(l + 1), e,
                                   1 << l, s);
         phys[l].b[f] = e;
       } else if (k == MG_BC_MULTIPOLE) {
@@ -875,31 +879,39 @@ int setup_faces(mg_ctx* c, const Layout& y, const mg_params* p, const mg_bc* bc,
   // non-finite fixed values are reported with the rho check
   for (int f = 0; f < 6; ++f) {
     if (bc->kind[f] == MG_BC_FIXED && bc->fixed_b[f])
-      launch_sum(bc->fixed_b[f], (size_t)p->n * p->n, 2, c->part, c->scal + 8 + f, s);
+      launch_sum(bc->fixed_b[f], (size_t)p->n * p->n, 2, part, scal + 8 + f, s);
   }
   return MG_OK;
 }
 
 }  // namespace
 
-extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const double* rho, double* phi, double* hist,
-                        int* n_hist, void* stream) {
-  if (!c) return MG_ERR_INVALID_ARG;
-  if (n_hist) *n_hist = 0;
-  int st = validate(c, p, bc);
-  if (st != MG_OK) return st;
-  if (!rho || !phi || !hist || !n_hist) return fail(c, MG_ERR_INVALID_ARG, "null rho/phi/hist/n_hist");
-  HIP_CHECK(c, hipSetDevice(c->device));
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+namespace {
+
+// Device memory of one solve: the hierarchy workspace (laid out by make_layout), the
+// reduction partials and the device scalars.  `noalloc`: the memory is the library's static
+// scratch and the solve allocates nothing (no cycle or kernel timing events either).
+struct SolveMem {
+  char* ws = nullptr;
+  double* part = nullptr;
+  double* scal = nullptr;
+  bool noalloc = false;
+};
+
+int solve_impl(mg_ctx* c, const mg_params* p, const mg_bc* bc, const double* rho, double* phi, double* hist,
+               int* n_hist, hipStream_t s, const Layout& y, const SolveMem& mem) {
   const int Lb = layout_lb(p);
   const bool fas = p->scheme == MG_SCHEME_FAS;
-  const Layout y = make_layout(p->n, p->precision, Lb, fas);
-  st = ensure_ws(c, y.total);
-  if (st != MG_OK) return st;
-  for (auto e : c->kev) (void)hipEventDestroy(e);
-  c->kev.clear();
-  c->kev_id.clear();
-  c->kstats.clear();
+  char* const ws = mem.ws;
+  double* const part = mem.part;
+  double* const scal = mem.scal;
+  const int ktiming = mem.noalloc ? 0 : c->ktiming;
+  if (!mem.noalloc) {
+    for (auto e : c->kev) (void)hipEventDestroy(e);
+    c->kev.clear();
+    c->kev_id.clear();
+    c->kstats.clear();
+  }
 
   const int L = y.L;
   const size_t n3 = cells(L);
@@ -912,25 +924,28 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
   tail_max = std::min(tail_max, Lb >= 0 ? Lb : 99);
 
   HIP_CHECK(c, hipEventRecord(c->ev0, s));
-  HIP_CHECK(c, hipMemsetAsync(c->scal, 0, sizeof(double) * kScal, s));
+  launch_zero(scal, sizeof(double) * kScal, s);
 
   // ---- source (eq. poisson, f = 4 pi G rho; mean removed when gauge-free, Sec. 2.3.6)
-  double* f64L = reinterpret_cast<double*>(c->ws + y.f64L);
-  float* f32L = mixed ? reinterpret_cast<float*>(c->ws + y.f32[L]) : nullptr;
+  double* f64L = reinterpret_cast<double*>(ws + y.f64L);
+  float* f32L = mixed ? reinterpret_cast<float*>(ws + y.f32[L]) : nullptr;
   double shift = 0.0;
-  launch_sum(rho, n3, 0, c->part, c->scal + 0, s);
+  launch_sum(rho, n3, 0, part, scal + 0, s);
   if (gauge_free) {
     // the shift needs the mean on the host; this is the one extra synchronisation of set-up
-    HIP_CHECK(c, hipMemcpyAsync(c->hscal, c->scal, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(c, hipMemcpyAsync(c->hscal, scal, sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_CHECK(c, hipStreamSynchronize(s));
     shift = -p->four_pi_g * (c->hscal[0] / (double)n3);
   }
-  launch_source(rho, f64L, f32L, n3, p->four_pi_g, shift, c->part, c->scal + 1, s);
+  launch_source(rho, f64L, f32L, n3, p->four_pi_g, shift, part, scal + 1, s);
 
   LevelBC phys[16], hom;
-  setup_faces(c, y, p, bc, rho, s, phys, &hom);
+  setup_faces(ws, part, scal, y, p, bc, rho, s, phys, &hom);
 
   Solver S{c, s, true};
+  S.part = part;
+  S.scal = scal;
+  S.ktiming = ktiming;
   S.Lb = Lb;
   if (c->fused_min_n[0] > 0) S.fused_min_n64 = c->fused_min_n[0];
   if (c->fused_min_n[1] > 0) S.fused_min_n32 = c->fused_min_n[1];
@@ -951,20 +966,20 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
   if (!mixed) {
     fill_common(H64, tail_max);
     for (int l = 0; l < L; ++l) {
-      H64.u[l] = reinterpret_cast<double*>(c->ws + y.u64[l]);
-      H64.f[l] = reinterpret_cast<double*>(c->ws + y.f64[l]);
+      H64.u[l] = reinterpret_cast<double*>(ws + y.u64[l]);
+      H64.f[l] = reinterpret_cast<double*>(ws + y.f64[l]);
     }
     H64.u[L] = phi;
     H64.f[L] = f64L;
     for (int l = 0; l <= L; ++l)
-      H64.u2[l] = y.u2[l] == (size_t)-1 ? nullptr : reinterpret_cast<double*>(c->ws + y.u2[l]);
+      H64.u2[l] = y.u2[l] == (size_t)-1 ? nullptr : reinterpret_cast<double*>(ws + y.u2[l]);
     S.restrict_sources(H64);
   } else {
     fill_common(H32, tail_max);
     for (int l = 0; l <= L; ++l) {
-      H32.u[l] = reinterpret_cast<float*>(c->ws + y.u32[l]);
-      H32.f[l] = reinterpret_cast<float*>(c->ws + y.f32[l]);
-      H32.u2[l] = y.u2[l] == (size_t)-1 ? nullptr : reinterpret_cast<float*>(c->ws + y.u2[l]);
+      H32.u[l] = reinterpret_cast<float*>(ws + y.u32[l]);
+      H32.f[l] = reinterpret_cast<float*>(ws + y.f32[l]);
+      H32.u2[l] = y.u2[l] == (size_t)-1 ? nullptr : reinterpret_cast<float*>(ws + y.u2[l]);
     }
     S.restrict_sources(H32);
   }
@@ -973,7 +988,7 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
   // ---- FMG sweep (Alg. 2) or the caller's initial guess
   double* pbar[16] = {nullptr};
   if (fas)
-    for (int l = 0; l < L; ++l) pbar[l] = reinterpret_cast<double*>(c->ws + y.pbar[l]);
+    for (int l = 0; l < L; ++l) pbar[l] = reinterpret_cast<double*>(ws + y.pbar[l]);
   if (p->mode == MG_MODE_FMG) {
     if (fas) {
       S.fas_fmg(H64, pbar);
@@ -989,9 +1004,9 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
   // (of the FAS cycle 1 with the Full Approximation Scheme)
   const bool head_mode = !mixed && Lb < 0 && S.head_possible(H64);
   if (head_mode) S.head(H64, phys[L]);
-  else S.defect_norm(phi, f64L, mixed ? H32.f[L] : nullptr, p->n, p->dx, phys[L], c->scal + 2);
+  else S.defect_norm(phi, f64L, mixed ? H32.f[L] : nullptr, p->n, p->dx, phys[L], scal + 2);
   HIP_CHECK(c, hipEventRecord(c->ev_fmg, s));
-  HIP_CHECK(c, hipMemcpyAsync(c->hscal, c->scal, sizeof(double) * 16, hipMemcpyDeviceToHost, s));
+  HIP_CHECK(c, hipMemcpyAsync(c->hscal, scal, sizeof(double) * 16, hipMemcpyDeviceToHost, s));
   HIP_CHECK(c, hipStreamSynchronize(s));
   bool finite = std::isfinite(c->hscal[0]) && std::isfinite(c->hscal[1]);
   for (int f = 0; f < 6; ++f) finite = finite && c->hscal[8 + f] == 0.0;
@@ -1007,15 +1022,17 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
 
   // ---- V-cycles until the stopping test (Sec. 2.3.7)
   const int ncyc = p->fixed_cycles > 0 ? p->fixed_cycles : p->max_cycles;
-  while ((int)c->ev_cycle.size() < ncyc) {
+  // per-cycle timing events (created once, reused; none in the allocation-free form)
+  while (!mem.noalloc && (int)c->ev_cycle.size() < ncyc) {
     hipEvent_t e;
     HIP_CHECK(c, hipEventCreate(&e));
     c->ev_cycle.push_back(e);
   }
+  const bool cyc_timed = !mem.noalloc;
   int status = p->fixed_cycles > 0 ? MG_OK : MG_NOT_CONVERGED;
   int slow = 0, done_cycles = 0;
   double* phi_cur = phi;     // mixed mode alternates phi with its ping-pong partner
-  double* phi_oth = y.phi2 == (size_t)-1 ? nullptr : reinterpret_cast<double*>(c->ws + y.phi2);
+  double* phi_oth = y.phi2 == (size_t)-1 ? nullptr : reinterpret_cast<double*>(ws + y.phi2);
   if (p->fixed_cycles > 0 || r > p->tol) {
     for (int cyc = 0; cyc < ncyc; ++cyc) {
       S.timed_top = true;
@@ -1024,7 +1041,7 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
         S.fas_cycle(H64, pbar, L, head_mode ? 1 : 0);
         S.head_done = false;
         if (head_mode && cyc + 1 < ncyc) S.head(H64, phys[L]);
-        else S.defect_norm(phi, f64L, nullptr, p->n, p->dx, phys[L], c->scal + 2);
+        else S.defect_norm(phi, f64L, nullptr, p->n, p->dx, phys[L], scal + 2);
       } else if (head_mode) {
         // the rest of this V-cycle (its first sweep ran in the head pass), then the head of the
         // next one, which measures this cycle's result; after the last allowed cycle the
@@ -1032,18 +1049,18 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
         S.head_done = true;
         S.vcycle(H64, L, phys[L], true, false);
         if (cyc + 1 < ncyc) S.head(H64, phys[L]);
-        else S.defect_norm(phi, f64L, nullptr, p->n, p->dx, phys[L], c->scal + 2);
+        else S.defect_norm(phi, f64L, nullptr, p->n, p->dx, phys[L], scal + 2);
       } else if (!mixed && Lb >= 0) {
         S.vcycle_blk(H64, L, phys[L]);
-        S.defect_norm(phi, f64L, nullptr, p->n, p->dx, phys[L], c->scal + 2);
+        S.defect_norm(phi, f64L, nullptr, p->n, p->dx, phys[L], scal + 2);
       } else if (mixed && Lb >= 0) {
-        HIP_CHECK(c, hipMemsetAsync(H32.u[L], 0, n3 * sizeof(float), s));
+        launch_zero(H32.u[L], n3 * sizeof(float), s);
         S.vcycle_blk(H32, L, hom);
         launch_add_f32(phi, H32.u[L], n3, s);
-        S.defect_norm(phi, f64L, H32.f[L], p->n, p->dx, phys[L], c->scal + 2);
+        S.defect_norm(phi, f64L, H32.f[L], p->n, p->dx, phys[L], scal + 2);
       } else if (!mixed) {
         const bool normed = S.vcycle(H64, L, phys[L], true, true);
-        if (!normed) S.defect_norm(phi, f64L, nullptr, p->n, p->dx, phys[L], c->scal + 2);
+        if (!normed) S.defect_norm(phi, f64L, nullptr, p->n, p->dx, phys[L], scal + 2);
       } else {
         // defect correction: e32 solves L e = r32 from zero with homogeneous conditions
         if (L == H32.T_top) {
@@ -1057,17 +1074,17 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
         }
         if (phi_oth) {
           // phi += e and the FP64 defect (with its FP32 copy and norm) in one streaming pass
-          const int np = fused_mixed_update_defect(phi_cur, phi_oth, H32.u[L], f64L, H32.f[L], c->part, p->n, p->dx,
+          const int np = fused_mixed_update_defect(phi_cur, phi_oth, H32.u[L], f64L, H32.f[L], part, p->n, p->dx,
                                                    phys[L], s);
-          launch_sum_partials(c->part, np, c->scal + 2, s);
+          launch_sum_partials(part, np, scal + 2, s);
           std::swap(phi_cur, phi_oth);
         } else {
           launch_add_f32(phi, H32.u[L], n3, s);
-          S.defect_norm(phi, f64L, H32.f[L], p->n, p->dx, phys[L], c->scal + 2);
+          S.defect_norm(phi, f64L, H32.f[L], p->n, p->dx, phys[L], scal + 2);
         }
       }
-      HIP_CHECK(c, hipEventRecord(c->ev_cycle[cyc], s));
-      HIP_CHECK(c, hipMemcpyAsync(c->hscal + 2, c->scal + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+      if (cyc_timed) HIP_CHECK(c, hipEventRecord(c->ev_cycle[cyc], s));
+      HIP_CHECK(c, hipMemcpyAsync(c->hscal + 2, scal + 2, sizeof(double), hipMemcpyDeviceToHost, s));
       HIP_CHECK(c, hipStreamSynchronize(s));
       const double rn = rel(c->hscal[2]);
       hist[nh++] = rn;
@@ -1086,8 +1103,8 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
 
   // ---- gauge (Sec. 2.3.6): zero mean potential when no face fixes the zero point
   if (gauge_free) {
-    launch_sum(phi, n3, 0, c->part, c->scal + 3, s);
-    launch_sub_mean(phi, n3, c->scal + 3, s);
+    launch_sum(phi, n3, 0, part, scal + 3, s);
+    launch_sub_mean(phi, n3, scal + 3, s);
   }
   HIP_CHECK(c, hipStreamSynchronize(s));
   HIP_CHECK(c, hipGetLastError());
@@ -1097,11 +1114,11 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
   c->fmg_ms = elapsed(c->ev_setup, c->ev_fmg);
   c->cycle_ms.clear();
   hipEvent_t prev = c->ev_fmg;
-  for (int cyc = 0; cyc < done_cycles; ++cyc) {
+  for (int cyc = 0; cyc < done_cycles && cyc_timed; ++cyc) {
     c->cycle_ms.push_back(elapsed(prev, c->ev_cycle[cyc]));
     prev = c->ev_cycle[cyc];
   }
-  if (c->ktiming) {
+  if (ktiming) {
     for (size_t q = 0; q + 1 < c->kev.size(); q += 2) {
       auto& k = c->kstats[c->kev_id[q / 2]];
       k.ms += elapsed(c->kev[q], c->kev[q + 1]);
@@ -1109,6 +1126,26 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
     }
   }
   return status;
+}
+
+}  // namespace
+
+extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const double* rho, double* phi, double* hist,
+                        int* n_hist, void* stream) {
+  if (!c) return MG_ERR_INVALID_ARG;
+  if (n_hist) *n_hist = 0;
+  int st = validate(c, p, bc);
+  if (st != MG_OK) return st;
+  if (!rho || !phi || !hist || !n_hist) return fail(c, MG_ERR_INVALID_ARG, "null rho/phi/hist/n_hist");
+  HIP_CHECK(c, hipSetDevice(c->device));
+  const Layout y = make_layout(p->n, p->precision, layout_lb(p), p->scheme == MG_SCHEME_FAS);
+  st = ensure_ws(c, y.total);
+  if (st != MG_OK) return st;
+  SolveMem mem;
+  mem.ws = c->ws;
+  mem.part = c->part;
+  mem.scal = c->scal;
+  return solve_impl(c, p, bc, rho, phi, hist, n_hist, reinterpret_cast<hipStream_t>(stream), y, mem);
 }
 
 extern "C" int mg_solve_simple(mg_ctx* c, int n, const double* rho, int bc_kind, double dx, double tol, double* phi,

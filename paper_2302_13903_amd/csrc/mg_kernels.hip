@@ -4,6 +4,8 @@
 // large-level kernels, by the operator entry points, and as the building blocks of the
 // FP32 inner cycle of the mixed-precision path.  Each kernel is a streaming loop with
 // 64-bit indices and on-the-fly boundary ghosts (see mg_common.h).
+#include <algorithm>
+
 #include "mg_common.h"
 #include "mg_launch.h"
 
@@ -711,6 +713,31 @@ __global__ void __launch_bounds__(kBlock) k_face_restrict(const double* __restri
   const double* r0 = ef + (size_t)(2 * t2 + 1) * mf + 1;
   const double* r1 = ef + (size_t)(2 * t2 + 2) * mf + 1;
   ec[t] = (r0[2 * t1] + r0[2 * t1 + 1] + r1[2 * t1] + r1[2 * t1 + 1]) / 4.0;
+}
+
+// ------------------------------------------------------------------ clearing device memory
+
+// Zero `words` 8-byte words (a kernel rather than a memset node, so the clear is an ordinary
+// kernel wherever the stream's work is recorded).
+__global__ void __launch_bounds__(kBlock) k_zero(unsigned long long* __restrict__ p, size_t words) {
+  const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * kBlock;
+  for (size_t i = t; i < words; i += stride) p[i] = 0ull;
+}
+__global__ void k_zero_bytes(unsigned char* __restrict__ p, size_t bytes) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < bytes) p[t] = 0;
+}
+
+void launch_zero(void* p, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return;
+  const size_t words = bytes / 8, tail = bytes % 8;
+  if (words) {
+    const size_t g = std::min<size_t>((words + kBlock - 1) / kBlock, 8192);
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)g), dim3(kBlock), 0, s, reinterpret_cast<unsigned long long*>(p), words);
+  }
+  if (tail)
+    hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(8), 0, s, reinterpret_cast<unsigned char*>(p) + words * 8, tail);
 }
 
 // ------------------------------------------------------------------ ghost fill (Sec. 2.3.6)

@@ -77,6 +77,9 @@ void launch_sum_partials(const double* part, int np, double* out, hipStream_t s)
 void launch_defect_norm(const double* u, const double* f, float* r32, int n, double h, const LevelBC& bc,
                         double* part, double* out, hipStream_t s);
 
+// zero `bytes` of device memory at p (8-byte aligned) with a kernel
+void launch_zero(void* p, size_t bytes, hipStream_t s);
+
 // out ((n+2)^3) = u with its ghost layer, edges and corners included, filled from bc
 void launch_fill(const double* u, double* out, int n, const LevelBC& bc, hipStream_t s);
 
