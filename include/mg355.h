@@ -168,6 +168,22 @@ int mg_tuning_set(mg_ctx *ctx, const char *text);
 int mg_solve(mg_ctx *ctx, const mg_params *p, const mg_bc *bc, const double *rho, double *phi,
              double *hist, int *n_hist, void *stream);
 
+/* mg_solve for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same solve, the same kernels and
+ * the same results, but the hierarchy workspace, reduction partials and device scalars live
+ * in the library's static device scratch -- one 64 MiB array per device, held until the
+ * process ends -- and the call makes no hipMalloc/hipFree or other allocation (and records
+ * no per-cycle or kernel timing events: mg_last_timing reports set-up and FMG only).  The
+ * context must exist already (mg_ctx_create allocates).
+ *   Limit: footprint + reduction scratch <= 64 MiB, which holds every precision, layout and
+ *   scheme up to n = 128; larger solves return MG_ERR_OOM with nothing written.
+ *   Every call on one device shares that device's scratch and leaves the last call's contents
+ *   in it (each solve clears what must start at zero): calls that overlap on one device --
+ *   on different streams, contexts or host threads -- race and give undefined results.
+ * Arguments, outputs and status as for mg_solve. */
+int mg_solve_noalloc(mg_ctx *ctx, const mg_params *p, const mg_bc *bc, const double *rho, double *phi,
+                     double *hist, int *n_hist, void *stream);
+
 /* Short form of mg_solve (Sec. 2.3.7, Alg. 1, Alg. 2) with the defaults of mg_default_params:
  * FMG start, V(2,2) cycles, omega = 1.15, four_pi_g = 4 pi, FP64, dense layout, at most 50
  * cycles.  All six faces take bc_kind (MG_BC_*): FIXED faces hold b = 0; MULTIPOLE faces the

@@ -22,7 +22,7 @@ from ._abi import (MG_BC_FIXED, MG_BC_MULTIPOLE, MG_BC_PERIODIC, MG_BC_ZERO_GRAD
                    MG_LAYOUT_DENSE, MG_MODE_FMG, MG_MODE_MGI, MG_PREC_FP64, MG_PREC_MIXED, MG_NOT_CONVERGED,
                    MG_OK, MG_STALLED, MgError, STATUS_NAMES)
 
-__all__ = ["Context", "solve", "to_blocks", "from_blocks", "morton_order", "mg_solve", "mg_footprint_bytes", "params", "boundary", "level_bc",
+__all__ = ["Context", "solve", "to_blocks", "from_blocks", "morton_order", "mg_solve", "mg_solve_noalloc", "mg_footprint_bytes", "params", "boundary", "level_bc",
            "mg_solve_simple", "mg_op_fill", "mg_op_half_sweep", "mg_op_smooth", "mg_op_defect", "mg_op_restrict", "mg_op_prolong_add",
            "mg_op_prolong_fmg", "mg_op_coarsest", "mg_op_down", "mg_op_up", "mg_op_smooth_f32", "mg_op_down_f32",
            "mg_op_up_f32", "mg_op_sweep_input_norm", "mg_op_mixed_update", "mg_multipole_moments",
@@ -255,6 +255,18 @@ def mg_solve(ctx: Context, p: _abi.MgParams, bc: _abi.MgBC, rho, phi, stream=Non
     st = ctx._lib.mg_solve(ctx.handle, ctypes.byref(p), ctypes.byref(bc), _ptr(rho), _ptr(phi), hist,
                            ctypes.byref(nh), _stream(stream))
     ctx.check(st, "mg_solve")
+    return st, [hist[i] for i in range(nh.value)]
+
+
+def mg_solve_noalloc(ctx: Context, p: _abi.MgParams, bc: _abi.MgBC, rho, phi, stream=None):
+    """Raw ``mg_solve_noalloc`` (the solve in the library's static scratch, no allocation):
+    returns (status, hist list)."""
+    cap = max(p.max_cycles, p.fixed_cycles) + 1
+    hist = (ctypes.c_double * cap)()
+    nh = ctypes.c_int(0)
+    st = ctx._lib.mg_solve_noalloc(ctx.handle, ctypes.byref(p), ctypes.byref(bc), _ptr(rho), _ptr(phi), hist,
+                                   ctypes.byref(nh), _stream(stream))
+    ctx.check(st, "mg_solve_noalloc")
     return st, [hist[i] for i in range(nh.value)]
 
 

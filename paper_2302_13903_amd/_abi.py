@@ -108,6 +108,7 @@ def lib():
         "mg_server_run": (i, [_vp, ctypes.POINTER(MgRequest), i]),
         "mg_server_get_stats": (i, [_vp, ctypes.POINTER(MgServerStats)]),
         "mg_solve": (i, [_vp, ctypes.POINTER(MgParams), ctypes.POINTER(MgBC), _vp, _vp, _dp, _ip, _vp]),
+        "mg_solve_noalloc": (i, [_vp, ctypes.POINTER(MgParams), ctypes.POINTER(MgBC), _vp, _vp, _dp, _ip, _vp]),
         "mg_solve_simple": (i, [_vp, i, _vp, i, d, d, _vp, _dp, _ip, _vp]),
         "mg_last_timing": (i, [_vp, _dp, _dp, _dp, i, _ip]),
         "mg_set_kernel_timing": (i, [_vp, i]),

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -23,9 +24,45 @@
 
 using namespace mg;
 
+// ---- static device scratch of the allocation-free solve (mg_solve_noalloc)
+//
+// One array per device for the life of the process.  In host code `scratch` names a host-side
+// stand-in, not device memory: its device address is looked up once per device with
+// hipGetSymbolAddress (with that device current) and only that address is used.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (the caller has made it current); looked up once.
+char* static_scratch(int device, hipError_t* err) {
+  if (device < 0 || device >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_done[device]) {
+    void* ptr = nullptr;
+    g_scratch_err[device] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    g_scratch_ptr[device] = g_scratch_err[device] == hipSuccess ? static_cast<char*>(ptr) : nullptr;
+    g_scratch_done[device] = true;
+  }
+  *err = g_scratch_err[device];
+  return g_scratch_ptr[device];
+}
+}  // namespace
+
 struct mg_ctx {
   int device = 0;
   std::string err;
+  // device address of the static scratch on this context's device (allocation-free solve)
+  char* static_scratch = nullptr;
+  hipError_t static_scratch_err = hipSuccess;
   // device bytes this context may hold (workspace, operator scratch, reduction scratch);
   // 0 = no limit
   size_t hbm_budget = 0;
@@ -767,6 +804,9 @@ int mg_ctx_create(mg_ctx** out, int device, size_t hbm_budget) {
   c->tail64_top = tail_prepare(c->lds_per_block);
   blk_prepare<double>(c->lds_per_block);
   blk_prepare<float>(c->lds_per_block);
+  // the static scratch's device address, once per device with the device current (a failure
+  // is reported by mg_solve_noalloc, the only user)
+  c->static_scratch = static_scratch(device, &c->static_scratch_err);
   *out = c;
   return MG_OK;
 }
@@ -1145,6 +1185,33 @@ extern "C" int mg_solve(mg_ctx* c, const mg_params* p, const mg_bc* bc, const do
   mem.ws = c->ws;
   mem.part = c->part;
   mem.scal = c->scal;
+  return solve_impl(c, p, bc, rho, phi, hist, n_hist, reinterpret_cast<hipStream_t>(stream), y, mem);
+}
+
+extern "C" int mg_solve_noalloc(mg_ctx* c, const mg_params* p, const mg_bc* bc, const double* rho, double* phi,
+                                double* hist, int* n_hist, void* stream) {
+  if (!c) return MG_ERR_INVALID_ARG;
+  if (n_hist) *n_hist = 0;
+  int st = validate(c, p, bc);
+  if (st != MG_OK) return st;
+  if (!rho || !phi || !hist || !n_hist) return fail(c, MG_ERR_INVALID_ARG, "null rho/phi/hist/n_hist");
+  if (!c->static_scratch)
+    return fail(c, MG_ERR_DEVICE, std::string("static scratch address: ") + hipGetErrorString(c->static_scratch_err));
+  const Layout y = make_layout(p->n, p->precision, layout_lb(p), p->scheme == MG_SCHEME_FAS);
+  // the static scratch holds the device scalars, the reduction partials and the workspace
+  const size_t scal_bytes = align_up(sizeof(double) * kScal);
+  const size_t part_bytes = align_up(sizeof(double) * kMaxPartials * 32);
+  const size_t need = scal_bytes + part_bytes + y.total;
+  if (need > kStaticScratchBytes)
+    return fail(c, MG_ERR_OOM, "mg_solve_noalloc: this solve needs " + std::to_string(need) +
+                                   " bytes of scratch; the static scratch holds " +
+                                   std::to_string(kStaticScratchBytes) + " (every precision and layout up to n = 128)");
+  HIP_CHECK(c, hipSetDevice(c->device));
+  SolveMem mem;
+  mem.scal = reinterpret_cast<double*>(c->static_scratch);
+  mem.part = reinterpret_cast<double*>(c->static_scratch + scal_bytes);
+  mem.ws = c->static_scratch + scal_bytes + part_bytes;
+  mem.noalloc = true;
   return solve_impl(c, p, bc, rho, phi, hist, n_hist, reinterpret_cast<hipStream_t>(stream), y, mem);
 }
 
