@@ -151,7 +151,10 @@ int mg_autotune(mg_ctx *ctx, const mg_params *p, int reps);
  * z-marching passes, a power of two >= 64; smaller levels run one launch per operator) and
  * "tail fp64|fp32 l" (highest level, 1..4, solved by the single-workgroup LDS tail) and
  * "tb fp64|fp32 0|1" (1: large-level sweeps two per pass over HBM) and "blkz fp64|fp32 0|1"
- * (MeshBlock layout, 1: streaming passes across blocks on the large block levels).  Writes at most cap bytes (NUL-terminated) and returns the length
+ * (MeshBlock layout, 1: streaming passes across blocks on the large block levels) and
+ * "march fp64|fp32 0|1|2" (V(2,2) legs of the dense levels >= 256^3 as two streaming passes --
+ * down: two sweeps + restricted defect; up: prolongation + two sweeps + norm -- 0 off, 1 when
+ * every face is periodic (default), 2 always).  Writes at most cap bytes (NUL-terminated) and returns the length
  * needed including the NUL.  mg_tuning_set reads the same format (e.g. from a cache file)
  * and rejects schedules the device cannot run. */
 int mg_tuning_get(const mg_ctx *ctx, char *buf, int cap);
@@ -346,13 +349,15 @@ int mg_op_coarsest(mg_ctx *ctx, double h, const mg_level_bc *bc, double *u, cons
 
 /* Fused down step of a V-cycle level (Alg. 1 steps 1-3): `npre` smoothing sweeps of u,
  * then fc = restriction of the defect f - L u; uc = 0.  u, f: device n^3; fc, uc: (n/2)^3.
- * The defect runs fused into the last sweep or as its own pass as the context's schedule
- * says ("pass" lines of mg_tuning_set; default: its own pass). */
+ * The kernels follow the context's schedule as the solver does: with npre = 2 on n >= 128 and
+ * the "march" setting allowing it, one two-sweep streaming pass; otherwise the defect fused
+ * into the last sweep or as its own pass ("pass" lines of mg_tuning_set). */
 int mg_op_down(mg_ctx *ctx, int n, double h, double omega, int npre, const mg_level_bc *bc,
                double *u, const double *f, double *fc, double *uc, void *stream);
 
 /* Fused up step of a V-cycle level (Alg. 1 steps 5-7): u += trilinear(uc) with uc's ghosts
- * from bc_coarse, then `npost` smoothing sweeps with bc. */
+ * from bc_coarse, then `npost` smoothing sweeps with bc (with npost = 2 on n >= 128 and the
+ * "march" setting allowing it, in one two-sweep streaming pass). */
 int mg_op_up(mg_ctx *ctx, int n, double h, double omega, int npost, const mg_level_bc *bc,
              const mg_level_bc *bc_coarse, double *u, const double *f, const double *uc,
              void *stream);

@@ -20,6 +20,7 @@
 #include "mg_blocks.h"
 #include "mg_fused.h"
 #include "mg_launch.h"
+#include "mg_march.h"
 #include "mg_tblock.h"
 
 using namespace mg;
@@ -110,6 +111,10 @@ struct mg_ctx {
   // large-level smoothing: 1 = temporally blocked passes (two sweeps per pass over HBM),
   // 0 = one sweep per pass; -1 = the built-in default
   int tblock[2] = {-1, -1};
+  // V(2,2) legs as two-sweep streaming passes (down: two sweeps + restricted defect; up:
+  // prolongation + two sweeps [+ norm]): 0 = off, 1 = on levels whose faces are all periodic,
+  // 2 = on every level; -1 = the built-in default (1)
+  int march[2] = {-1, -1};
 };
 
 // refined-mesh solve (mg_amr.hip); part: device partials (kMaxPartials x 32 doubles), hpart:
@@ -347,12 +352,26 @@ struct Solver {
     return sizeof(T) == 8 ? 2 : 0;
   }
 
+  // Does level l run its V(2,2) legs as the two-sweep streaming passes (down: two sweeps and
+  // the restricted defect in one pass; up: prolongation, two sweeps and the norm in one)?
+  template <typename T>
+  bool march_on(const Hier<T>& H, int l, const LevelBC& bc) const {
+    const int mode = c->march[sizeof(T) == 8 ? 0 : 1] < 0 ? 1 : c->march[sizeof(T) == 8 ? 0 : 1];
+    if (mode == 0 || !use_fused || !H.u2[l] || l == H.T_top || Lb >= 0 || H.npre != 2 || H.npost != 2) return false;
+    if ((1 << l) < std::max(kMarchMinN, sizeof(T) == 8 ? fused_min_n64 : fused_min_n32) || tblock_on<T>()) return false;
+    if (mode == 1)
+      for (int f = 0; f < 6; ++f)
+        if (bc.kind[f] != BC_PERIODIC) return false;
+    return true;
+  }
+
   // FP64, dense: can the first pre-sweep of the finest level's V-cycle run as a head pass (a
-  // one-sweep streaming pass that also takes the residual norm of its input)?
+  // one-sweep streaming pass that also takes the residual norm of its input)?  Not when the
+  // finest level runs the two-sweep passes, whose up pass takes the norm of the cycle's result.
   bool head_possible(const Hier<double>& H) const {
     const int L = H.L;
     return use_fused && H.u2[L] && L != H.T_top && Lb < 0 && (1 << L) >= fused_min_n64 && !tblock_on<double>() &&
-           H.npre >= 1 && ((split_of<double>(L) & 1) || H.npre >= 2);
+           H.npre >= 1 && ((split_of<double>(L) & 1) || H.npre >= 2) && !march_on<double>(H, L, H.phys[L]);
   }
 
   // The head pass: first pre-sweep of the next V-cycle (u -> u2) and the residual norm of u
@@ -382,9 +401,10 @@ struct Solver {
     if (top_call && zero_start) {
       // only the one-sweep fused path starts with a plain sweep that can skip reading u;
       // elsewhere u is cleared first
-      const bool fused_first = use_fused && H.u2[l] && l != H.T_top &&
-                               (1 << l) >= (sizeof(T) == 8 ? fused_min_n64 : fused_min_n32) && !tblock_on<T>() &&
-                               H.npre >= 1 && !(H.npre == 1 && !(split_of<T>(l) & 1));
+      const bool fused_first = (use_fused && H.u2[l] && l != H.T_top &&
+                                (1 << l) >= (sizeof(T) == 8 ? fused_min_n64 : fused_min_n32) && !tblock_on<T>() &&
+                                H.npre >= 1 && !(H.npre == 1 && !(split_of<T>(l) & 1))) ||
+                               march_on<T>(H, l, bc);
       if (!fused_first) {
         launch_zero(H.u[l], cells(l) * sizeof(T), s);
         zero_start = false;
@@ -398,6 +418,26 @@ struct Solver {
     const double h = H.h[l];
     const bool timed = top_call && l == H.L && ktiming;
     const double cellsT = (double)cells(l) * sizeof(T);
+    if (march_on<T>(H, l, bc)) {
+      // V(2,2) in two streaming passes: down (two sweeps, restricted defect, coarse correction
+      // cleared), the coarse recursion, up (prolonged correction, two sweeps, and the norm of
+      // the result when asked); the result lands back in u[l] after the two ping-pongs
+      bool per = true;
+      for (int f = 0; f < 6; ++f) per = per && bc.kind[f] == BC_PERIODIC;
+      const bool zin = top_call && zero_start;
+      if (timed) kernel_begin();
+      march_down<T>(zin ? nullptr : H.u[l], H.u2[l], H.f[l], H.f[l - 1], H.u[l - 1], n, h, H.omega, bc, s);
+      // algorithmic bytes: u and f read, u written, coarse source and correction written
+      if (timed) kernel_end(march_name<T>(false, false, per), 3 * cellsT + cellsT / 4);
+      vcycle(H, l - 1, H.hom, false, false);
+      double* npart = want_norm && sizeof(T) == 8 ? part : nullptr;
+      if (timed) kernel_begin();
+      const int np = march_up<T>(H.u2[l], H.u[l], H.f[l], H.u[l - 1], H.hom, npart, n, h, H.omega, bc, s);
+      // algorithmic bytes: u, f and the coarse correction read, u written
+      if (timed) kernel_end(march_name<T>(true, npart != nullptr, per), 3 * cellsT + cellsT / 8);
+      if (npart) launch_sum_partials(part, np, scal + 2, s);
+      return npart != nullptr;
+    }
     if (use_fused && H.u2[l] && n >= (sizeof(T) == 8 ? fused_min_n64 : fused_min_n32) && tblock_on<T>()) {
       // temporally blocked: sweeps two at a time per pass; the restricted defect and the norm
       // as defect-only passes
@@ -621,19 +661,23 @@ struct Solver {
     }
   }
 
-  // Alg. 2: FMG over all levels with each level's physical description.
+  // Alg. 2: FMG over all levels with each level's physical description.  norm_top: the
+  // finest level's V-cycle may leave the sum of squared defects of its result in scal[2]
+  // (returns whether it did).
   template <typename T>
-  void fmg(Hier<T>& H) {
+  bool fmg(Hier<T>& H, bool norm_top = false) {
     tail(H, TAIL_FMG, H.phys[H.T_top]);
+    bool normed = false;
     for (int l = H.T_top + 1; l <= H.L; ++l) {
       if (Lb >= 0 && l > Lb) {
         blk_prolong<T>(H.u[l - 1], H.u[l], l - Lb, Lb, H.phys[l - 1], 1, s);
         vcycle_blk(H, l, H.phys[l]);
       } else {
         launch_prolong<T>(H.u[l - 1], H.u[l], 1 << (l - 1), H.phys[l - 1], 1, s);
-        vcycle(H, l, H.phys[l], false, false);
+        normed = vcycle(H, l, H.phys[l], false, norm_top && l == H.L);
       }
     }
+    return normed;
   }
 
   // ---- MeshBlock layout (Sec. 3.2): levels above Lb are block levels, Lb and below the root
@@ -1029,11 +1073,13 @@ int solve_impl(mg_ctx* c, const mg_params* p, const mg_bc* bc, const double* rho
   double* pbar[16] = {nullptr};
   if (fas)
     for (int l = 0; l < L; ++l) pbar[l] = reinterpret_cast<double*>(ws + y.pbar[l]);
+  bool fmg_normed = false;
   if (p->mode == MG_MODE_FMG) {
     if (fas) {
       S.fas_fmg(H64, pbar);
     } else if (!mixed) {
-      S.fmg(H64);
+      // the finest level's FMG V-cycle takes the norm of its result when its up pass can
+      fmg_normed = S.fmg(H64, S.march_on<double>(H64, L, phys[L]));
     } else {
       S.fmg(H32);
       launch_f32_to_f64(H32.u[L], phi, n3, s);
@@ -1044,7 +1090,7 @@ int solve_impl(mg_ctx* c, const mg_params* p, const mg_bc* bc, const double* rho
   // (of the FAS cycle 1 with the Full Approximation Scheme)
   const bool head_mode = !mixed && Lb < 0 && S.head_possible(H64);
   if (head_mode) S.head(H64, phys[L]);
-  else S.defect_norm(phi, f64L, mixed ? H32.f[L] : nullptr, p->n, p->dx, phys[L], scal + 2);
+  else if (!fmg_normed) S.defect_norm(phi, f64L, mixed ? H32.f[L] : nullptr, p->n, p->dx, phys[L], scal + 2);
   HIP_CHECK(c, hipEventRecord(c->ev_fmg, s));
   HIP_CHECK(c, hipMemcpyAsync(c->hscal, scal, sizeof(double) * 16, hipMemcpyDeviceToHost, s));
   HIP_CHECK(c, hipStreamSynchronize(s));
@@ -1410,6 +1456,7 @@ int mg_tuning_get(const mg_ctx* c, char* buf, int cap) {
     if (c->tail_top[q] > 0) o << "tail " << (q ? "fp32" : "fp64") << " " << c->tail_top[q] << "\n";
     if (c->tblock[q] >= 0) o << "tb " << (q ? "fp32" : "fp64") << " " << c->tblock[q] << "\n";
     if (c->blk_zmarch[q] >= 0) o << "blkz " << (q ? "fp32" : "fp64") << " " << c->blk_zmarch[q] << "\n";
+    if (c->march[q] >= 0) o << "march " << (q ? "fp32" : "fp64") << " " << c->march[q] << "\n";
   }
   const std::string t = o.str();
   if (buf && cap > 0) {
@@ -1430,11 +1477,12 @@ int mg_tuning_set(mg_ctx* c, const char* text) {
     if (line.empty()) continue;
     std::istringstream ls(line);
     std::string tag, prec;
-    if (line.rfind("tb ", 0) == 0 || line.rfind("blkz ", 0) == 0) {
+    if (line.rfind("tb ", 0) == 0 || line.rfind("blkz ", 0) == 0 || line.rfind("march ", 0) == 0) {
       int v;
-      if (!(ls >> tag >> prec >> v) || (prec != "fp64" && prec != "fp32") || (v != 0 && v != 1))
+      const int vmax = line.rfind("march ", 0) == 0 ? 2 : 1;
+      if (!(ls >> tag >> prec >> v) || (prec != "fp64" && prec != "fp32") || v < 0 || v > vmax)
         return fail(c, MG_ERR_INVALID_ARG, "bad tuning line: " + line);
-      add_misc.push_back({(tag == "tb" ? 4 : 6) + (prec == "fp64" ? 0 : 1), v});
+      add_misc.push_back({(tag == "tb" ? 4 : tag == "blkz" ? 6 : 8) + (prec == "fp64" ? 0 : 1), v});
       continue;
     }
     if (line.rfind("fusedmin ", 0) == 0 || line.rfind("tail ", 0) == 0) {
@@ -1473,7 +1521,8 @@ int mg_tuning_set(mg_ctx* c, const char* text) {
     if (kv.first < 2) c->fused_min_n[kv.first] = kv.second;
     else if (kv.first < 4) c->tail_top[kv.first - 2] = kv.second;
     else if (kv.first < 6) c->tblock[kv.first - 4] = kv.second;
-    else c->blk_zmarch[kv.first - 6] = kv.second;
+    else if (kv.first < 8) c->blk_zmarch[kv.first - 6] = kv.second;
+    else c->march[kv.first - 8] = kv.second;
   }
   return MG_OK;
 }
@@ -1544,6 +1593,19 @@ int op_smooth(mg_ctx* c, int n, double h, double omega, int sweeps, bool zero_in
   return op_epilogue(c);
 }
 
+// Do the operator entry points run a V(2,2) leg of this level as one two-sweep streaming pass
+// (the context's "march" setting, as in the solver; any level the passes support)?
+template <typename T>
+bool op_march(const mg_ctx* c, int n, int sweeps, const LevelBC& b) {
+  const int v = c->march[sizeof(T) == 8 ? 0 : 1];
+  const int mode = v < 0 ? 1 : v;
+  if (mode == 0 || sweeps != 2 || n < kMarchMinN) return false;
+  if (mode == 1)
+    for (int f = 0; f < 6; ++f)
+      if (b.kind[f] != BC_PERIODIC) return false;
+  return true;
+}
+
 // Down step (Alg. 1 steps 1-3) with the context's fusion schedule for this precision.
 template <typename T>
 int op_down(mg_ctx* c, int n, double h, double omega, int npre, const mg_level_bc* bc, T* u, const T* f, T* fc, T* uc,
@@ -1553,6 +1615,14 @@ int op_down(mg_ctx* c, int n, double h, double omega, int npre, const mg_level_b
   if (n < 2 || npre < 0 || npre > 4) return fail(c, MG_ERR_INVALID_ARG, "n >= 2, npre 0..4");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const LevelBC b = to_level_bc(bc);
+  if (op_march<T>(c, n, npre, b)) {
+    double* tmp = nullptr;
+    st = op_scratch(c, cells(ilog2(n)) * sizeof(T), &tmp);
+    if (st) return st;
+    march_down<T>(u, reinterpret_cast<T*>(tmp), f, fc, uc, n, h, omega, b, s);
+    HIP_CHECK(c, hipMemcpyAsync(u, tmp, cells(ilog2(n)) * sizeof(T), hipMemcpyDeviceToDevice, s));
+    return op_epilogue(c);
+  }
   if (fused_supported<T>(n) && npre > 0) {
     double* tmp = nullptr;
     st = op_scratch(c, cells(ilog2(n)) * sizeof(T), &tmp);
@@ -1587,6 +1657,14 @@ int op_up(mg_ctx* c, int n, double h, double omega, int npost, const mg_level_bc
   if (n < 2 || npost < 0 || npost > 4) return fail(c, MG_ERR_INVALID_ARG, "n >= 2, npost 0..4");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const LevelBC b = to_level_bc(bc), bcc = to_level_bc(bc_coarse);
+  if (op_march<T>(c, n, npost, b)) {
+    double* tmp = nullptr;
+    st = op_scratch(c, cells(ilog2(n)) * sizeof(T), &tmp);
+    if (st) return st;
+    (void)march_up<T>(u, reinterpret_cast<T*>(tmp), f, uc, bcc, nullptr, n, h, omega, b, s);
+    HIP_CHECK(c, hipMemcpyAsync(u, tmp, cells(ilog2(n)) * sizeof(T), hipMemcpyDeviceToDevice, s));
+    return op_epilogue(c);
+  }
   if (fused_supported<T>(n) && npost > 0) {
     double* tmp = nullptr;
     st = op_scratch(c, cells(ilog2(n)) * sizeof(T), &tmp);

@@ -1,0 +1,37 @@
+// mg_march.h -- two-sweep streaming passes of the large levels (internal; see mg_march.hip).
+//
+// Each pass reads u from `uin` and writes the result to `uout` (uin != uout): tiles overlap in
+// their halos, so the update cannot be in place.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "mg_common.h"
+
+namespace mg {
+
+// Smallest level the two-sweep passes run on (a z chunk must hold many planes).
+constexpr int kMarchMinN = 128;
+
+// Down step of a V-cycle level (Alg. 1 steps 1-3) in one pass: two smoothing sweeps of u, the
+// defect of the result restricted into fc, and the coarse correction uc0 cleared.
+// uin == nullptr: u is zero on input and is not read.
+template <typename T>
+void march_down(const T* uin, T* uout, const T* f, T* fc, T* uc0, int n, double h, double omega, const LevelBC& bc,
+                hipStream_t s);
+
+// Up step (Alg. 1 steps 5-7) in one pass: u += trilinear(ec) (ec's ghosts from bcc) as u is
+// loaded, then two smoothing sweeps.  part != nullptr: one partial sum of squared defects of
+// the result per workgroup into part (the convergence norm, Sec. 2.3.7); returns the number of
+// partials (0 without part).
+template <typename T>
+int march_up(const T* uin, T* uout, const T* f, const T* ec, const LevelBC& bcc, double* part, int n, double h,
+             double omega, const LevelBC& bc, hipStream_t s);
+
+// Names of the kernels as the profiler lists them (per: every face periodic).
+template <typename T>
+std::string march_name(bool up, bool norm, bool per);
+
+}  // namespace mg

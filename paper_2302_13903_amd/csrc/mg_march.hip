@@ -1,0 +1,619 @@
+// mg_march.hip -- two-sweep streaming passes of the large levels (the bandwidth path).
+//
+// One launch = the whole work of a V-cycle leg on one level, with u and f crossing HBM once:
+//   down (Alg. 1 steps 1-3): two red-black SOR sweeps (eqs. rbsor1-2), then the defect
+//        f - L u of the result (eq. defect) restricted to the coarse level (eq. restriction)
+//        and the coarse correction cleared;
+//   up   (Alg. 1 steps 5-7): u += trilinear prolongation of the coarse correction (eq.
+//        trilinear) as u is loaded, then two sweeps, optionally followed by the defect of the
+//        result summed as squares (the convergence norm of Sec. 2.3.7).
+//
+// Work layout.  A workgroup of W waves owns a tile of 64 x (8 W) cells in x-y and marches a
+// chunk of z planes.  Each half-wave holds a band of R = 4 rows, each lane the x-pair (2l, 2l+1)
+// of those rows.  At the step that loads plane P the stages run on older planes:
+//   red sweep 1 on P-1, black 1 on P-2, red 2 on P-3, black 2 on P-4, defect on P-4,
+// so every stage reads its z-neighbours in the colour state it needs.  u of six planes lives in
+// registers (a ring), f of plane P-1 in registers and of P-2..P-4 in per-thread LDS slots.
+//
+// The colour pattern is a compile-time constant: tile origins, halos and z-chunk starts are
+// even, chunks start at multiples of 6 and the ring has 6 planes, so the parity of the plane a
+// stage works on, and which cell of a lane's x-pair is red in each row, are template constants.
+// A stage then updates exactly one cell per row with no operand selection: two cross-lane moves
+// (DPP wave shifts) for the x-neighbour, in-lane rows or one LDS exchange of the band-edge rows
+// for y, ring planes for z.
+//
+// The defect stage needs the final state of both neighbouring planes.  Black cells of P-4 have
+// only red neighbours, final after red sweep 2; red cells of P-4 get their in-plane and lower
+// neighbours now and the upper one (black, final one step later) at the next step, so the ring
+// stays at six planes.  Tiles overlap by a halo of 6 cells (5 stages of radius 1, rounded up to
+// even) and are recomputed, so tiles are independent and the result goes to another array.
+// Boundary ghosts are evaluated on the fly (Sec. 2.3.6) for cells on non-periodic faces.
+#include "mg_march.h"
+
+#include <cstring>
+#include <type_traits>
+#include <utility>
+
+#include "mg_launch.h"
+
+namespace mg {
+
+namespace {
+
+constexpr int kLanes = 64;
+constexpr int kR = 4;          // rows per lane (a band)
+constexpr int kSL = 32;        // lanes per x segment (a half-wave)
+constexpr int kTX = 2 * kSL;   // tile width
+constexpr int kRing = 6;       // u planes held per lane
+constexpr int kFSlots = 3;     // f planes held in LDS per lane
+constexpr int kHalo = 6;       // tile overlap in x and y
+
+struct MarchArgs {
+  const void* uin;   // u on input (not read when zero_in)
+  void* uout;
+  const void* f;
+  const void* ec;    // up: coarse correction (n/2)^3
+  void* fc;          // down: restricted defect (n/2)^3
+  void* uc0;         // down: coarse correction to clear
+  double* part;      // norm: one partial sum per workgroup
+  LevelBC bc;        // this level
+  LevelBC bcc;       // up: coarse level (homogeneous)
+  int n, L, xo, yo, zc, tiles_x, tiles_y, ntiles;
+  int zero_in;
+  double h2, ih2, omega;
+};
+
+template <int N, typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl<N>(f, std::make_integer_sequence<int, N>{});
+}
+
+// Whole-wave shift by one lane through DPP: wave_shr:1 gives lane i the value of lane i-1,
+// wave_shl:1 the value of lane i+1 (lanes without a source keep their own value).
+constexpr int kDppWaveShr1 = 0x138;
+constexpr int kDppWaveShl1 = 0x130;
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+  const int i = __builtin_bit_cast(int, v);
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(i, i, CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = (int)(b & 0xffffffffLL), hi = (int)(b >> 32);
+  const int lo2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
+  const int hi2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((long long)hi2 << 32) | (long long)(unsigned)lo2);
+}
+template <typename T>
+__device__ __forceinline__ T from_left(T v) {   // value of lane - 1
+  return dpp_move<kDppWaveShr1>(v);
+}
+template <typename T>
+__device__ __forceinline__ T from_right(T v) {  // value of lane + 1
+  return dpp_move<kDppWaveShl1>(v);
+}
+
+template <typename T>
+__device__ __forceinline__ T ghost_of(const LevelBC& bc, int face, int n, int t1, int t2, T c) {
+  if (bc.kind[face] == BC_ZERO_GRADIENT) return c;
+  return (T)(2.0 * face_b(bc, face, n, t1, t2)) - c;
+}
+
+template <typename T>
+__device__ __forceinline__ T coarse_at(const T* __restrict__ e, int nc, int Lc, int X, int Y, int Z, const LevelBC& bcc) {
+  if ((unsigned)X < (unsigned)nc && (unsigned)Y < (unsigned)nc && (unsigned)Z < (unsigned)nc)
+    return e[cidx(Lc, X, Y, Z)];
+  return ghost_any(e, nc, Lc, X, Y, Z, bcc);
+}
+
+template <typename T>
+struct alignas(2 * sizeof(T)) Pair {
+  T a, b;
+};
+
+// Waves per workgroup: FP64 8 (tile 64 x 64, up to 256 registers per lane), FP32 16 (64 x 128).
+template <typename T>
+constexpr int cfg_W() {
+  return sizeof(T) == 8 ? 8 : 16;
+}
+
+// PER: every face of the level is periodic (the launcher checks), so no boundary code is
+// compiled in.
+template <typename T, int W, bool UP, bool NORM, bool PER>
+__global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
+  constexpr int R = kR, SL = kSL, NB = 2 * W, NT = kLanes * W;
+  constexpr bool DEF = !UP;                       // down: restricted defect
+  constexpr bool DSTAGE = DEF || NORM;            // a defect stage after the sweeps
+  constexpr int HZ = DSTAGE ? 5 : 4;              // planes marched before (and after) the chunk
+  __shared__ Pair<T> xch[2][NB][2][SL];
+  __shared__ Pair<T> fl[kFSlots][R][NT];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & (kLanes - 1);
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int seg = lane >> 5;
+  const int xl = lane & (SL - 1);
+  const int band = 2 * w + seg;
+  // XCD-aware order: consecutive block ids go to different XCDs, so give each XCD a
+  // contiguous run of tiles (neighbouring tiles then share that XCD's L2 for their halos)
+  const int nbk = gridDim.x, bid = blockIdx.x;
+  const int tile = (bid & 7) * (nbk >> 3) + (bid >> 3);
+  double acc = 0.0;
+  if (tile < A.ntiles) {
+    const int tx = tile % A.tiles_x;
+    const int ty = (tile / A.tiles_x) % A.tiles_y;
+    const int cz = tile / (A.tiles_x * A.tiles_y);
+    const int n = A.n, L = A.L, nm = n - 1;
+    const T* __restrict__ uin = reinterpret_cast<const T*>(A.uin);
+    T* __restrict__ uout = reinterpret_cast<T*>(A.uout);
+    const T* __restrict__ fin = reinterpret_cast<const T*>(A.f);
+    const bool px = PER || A.bc.kind[0] == BC_PERIODIC;
+    const bool py = PER || A.bc.kind[2] == BC_PERIODIC;
+    const bool pz = PER || A.bc.kind[4] == BC_PERIODIC;
+    const T h2 = (T)A.h2, ih2 = (T)A.ih2, omega = (T)A.omega;
+    const T inv6 = (T)(1.0 / 6.0);
+
+    const int xs = tx * A.xo;                    // first output column (even)
+    const int xa = xs - kHalo + 2 * xl;          // this lane's even column
+    const bool in_x = px || (xa >= 0 && xa < n);
+    const int xag = xa & nm;
+    const bool out_x = xa >= xs && xa < xs + A.xo && xa < n;
+    const bool bnd_xl = !px && xa == 0;          // cell a on the -x face
+    const bool bnd_xr = !px && xa + 1 == nm;     // cell b on the +x face
+
+    const int ys = ty * A.yo;                    // first output row (even)
+    int yv[R], ygv[R];
+    bool in_y[R], out_y[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int y = ys - kHalo + band * R + r;
+      yv[r] = y;
+      ygv[r] = y & nm;
+      in_y[r] = py || (y >= 0 && y < n);
+      out_y[r] = y >= ys && y < ys + A.yo && y < n;
+    }
+    const int z0 = cz * A.zc;                    // a multiple of 6
+    const int zend = min(z0 + A.zc, n);
+    const int zstart = z0 - HZ;
+    const int nsteps = (zend - z0) + 2 * HZ;
+    // does any cell of this wave touch a non-periodic face in x or y?
+    const int wy0 = ys - kHalo + w * 2 * R, wy1 = wy0 + 2 * R - 1;
+    const bool wave_bnd_xy =
+        !PER && ((!px && (xs - kHalo <= 0 || xs - kHalo + kTX - 1 >= nm)) || (!py && (wy0 <= 0 || wy1 >= nm)));
+
+    T u[kRing][R][2];
+    T pu[R][2], pf[R][2];      // prefetched u of plane P+1 and f of plane P
+    T fr[R][2];                // f of plane P-1
+    T dred[R];                 // red cells' partial defects of plane P-4 (completed next step)
+    T pend[R / 2], stash[R / 2];   // down: row-pair defect sums (black cells of P-4; even plane)
+    constexpr int NTAP = R / 2 + 2;
+    T pc[UP ? NTAP : 1][2];    // up: coarse rows Y0-1 .. Y0+2 on the two coarse planes of a fine plane
+#pragma unroll
+    for (int s = 0; s < kRing; ++s)
+#pragma unroll
+      for (int r = 0; r < R; ++r) u[s][r][0] = u[s][r][1] = (T)0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      fr[r][0] = fr[r][1] = (T)0;
+      dred[r] = (T)0;
+#pragma unroll
+      for (int q = 0; q < kFSlots; ++q) fl[q][r][tid] = Pair<T>{(T)0, (T)0};
+    }
+#pragma unroll
+    for (int j = 0; j < R / 2; ++j) pend[j] = stash[j] = (T)0;
+
+    // ---- loads of u on plane P (unless zero on input) and f on plane P-1 (the plane the red
+    // stage of the next step works on); up: the coarse taps of plane P
+    auto load_plane = [&](int P, bool first) __attribute__((always_inline)) {
+      const bool in_z = pz || (P >= 0 && P < n);
+      const bool in_zf = pz || (P - 1 >= 0 && P - 1 < n);
+      const int Pg = P & nm, Pfg = (P - 1) & nm;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (in_x && in_y[r] && in_z && !A.zero_in) {
+          const Pair<T> vu = *reinterpret_cast<const Pair<T>*>(uin + cidx(L, xag, ygv[r], Pg));
+          pu[r][0] = vu.a; pu[r][1] = vu.b;
+        } else {
+          pu[r][0] = pu[r][1] = (T)0;
+        }
+        if (in_x && in_y[r] && in_zf) {
+          const Pair<T> vf = *reinterpret_cast<const Pair<T>*>(fin + cidx(L, xag, ygv[r], Pfg));
+          pf[r][0] = vf.a; pf[r][1] = vf.b;
+        } else {
+          pf[r][0] = pf[r][1] = (T)0;
+        }
+      }
+      if constexpr (UP) {
+        // Trilinear prolongation (weights 1/4, 3/4 per axis) of the coarse correction: the
+        // lane's coarse column X, coarse rows Y0-1 .. Y0+2 (rows 2j, 2j+1 of the band take
+        // Y0+j-1 .. Y0+j+1) on the coarse planes (zlo, zlo+1) of fine plane P; the x-neighbour
+        // columns come from the lanes beside (an edge lane of a segment gets its own value
+        // back: wrong, but only in the outermost column of the tile, inside the halo).  Fine
+        // plane 2Z takes coarse planes (Z-1, Z), plane 2Z+1 (Z, Z+1): an even plane reuses
+        // the taps of the odd plane before it, an odd plane keeps its predecessor's upper plane
+        // as its lower one and loads one new plane.
+        const T* __restrict__ ec = reinterpret_cast<const T*>(A.ec);
+        const int nc = n >> 1, Lc = L - 1;
+        const int X = (px ? xag : xa) >> 1;
+        const int Y0 = (py ? ygv[0] : yv[0]) >> 1;
+        const int Pz = pz ? (P & nm) : P;
+        const int Z = Pz >> 1;
+        const int zlo = (Pz & 1) ? Z : Z - 1;
+        auto tap = [&](int i, int zz) __attribute__((always_inline)) {
+          int Y = Y0 - 1 + i;
+          if (py) Y &= nc - 1;
+          if (pz) zz &= nc - 1;
+          return coarse_at(ec, nc, Lc, X, Y, zz, A.bcc);
+        };
+        if (first || (P & 1)) {
+#pragma unroll
+          for (int i = 0; i < NTAP; ++i) {
+            pc[i][0] = first ? tap(i, zlo) : pc[i][1];
+            pc[i][1] = tap(i, zlo + 1);
+          }
+        }
+      }
+    };
+
+    // ---- add the prolonged correction fetched with plane P (parity PARP) to the prefetched u
+    auto prolong_apply = [&](int P, auto cPAR) __attribute__((always_inline)) {
+      if constexpr (UP) {
+        constexpr int PARP = decltype(cPAR)::value;
+        const bool in_z = pz || (P >= 0 && P < n);
+        const T wz0 = PARP ? (T)0.75 : (T)0.25, wz1 = PARP ? (T)0.25 : (T)0.75;
+        T czv[NTAP];
+#pragma unroll
+        for (int i = 0; i < NTAP; ++i) czv[i] = wz0 * pc[i][0] + wz1 * pc[i][1];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int j = r >> 1;
+          const T c = (r & 1) ? (T)0.75 * czv[j + 1] + (T)0.25 * czv[j + 2] : (T)0.25 * czv[j] + (T)0.75 * czv[j + 1];
+          const T cl = from_left(c), cr = from_right(c);
+          if (in_x && in_y[r] && in_z) {
+            pu[r][0] += (T)0.25 * cl + (T)0.75 * c;
+            pu[r][1] += (T)0.75 * c + (T)0.25 * cr;
+          }
+        }
+      }
+    };
+
+    int xbuf = 0;
+
+    // ---- one colour C (0 red, 1 black) of the RB-SOR update (eqs. rbsor1-2) on plane p of
+    // parity PAR held in uc, its z-neighbour planes in um (p-1) and up (p+1); f from the
+    // registers (FS < 0) or LDS slot FS
+    auto colour = [&](auto cC, auto cPAR, auto cFS, T (&um)[R][2], T (&uc)[R][2], T (&up)[R][2],
+                      int p) __attribute__((always_inline)) {
+      constexpr int C = decltype(cC)::value, PAR = decltype(cPAR)::value, FS = decltype(cFS)::value;
+      // the band-edge rows' cells of the other colour, for the bands below and above
+      constexpr int q0 = (PAR + C) & 1, qL = (R - 1 + PAR + C) & 1;
+      T* xt = reinterpret_cast<T*>(&xch[xbuf][0][0][0]);
+      xt[(band * 2 + 0) * SL + xl] = uc[0][q0 ^ 1];
+      xt[(band * 2 + 1) * SL + xl] = uc[R - 1][qL ^ 1];
+      __syncthreads();
+      const T below = xt[((band > 0 ? band - 1 : band) * 2 + 1) * SL + xl];
+      const T above = xt[((band < NB - 1 ? band + 1 : band) * 2 + 0) * SL + xl];
+      xbuf ^= 1;
+      const bool in_z = pz || (p >= 0 && p < n);
+      const bool bnd_z0 = !pz && p == 0, bnd_z1 = !pz && p == nm;
+      const bool bnd = !PER && (wave_bnd_xy || bnd_z0 || bnd_z1);
+      static_for<R>([&](auto rr) __attribute__((always_inline)) {
+        constexpr int r = decltype(rr)::value;
+        constexpr int q = (r + PAR + C) & 1;      // the cell of this colour in row r
+        const T c = uc[r][q];
+        T xm, xp, ym, yp;
+        if constexpr (q == 0) {
+          xm = from_left(uc[r][1]);
+          xp = uc[r][1];
+        } else {
+          xm = uc[r][0];
+          xp = from_right(uc[r][0]);
+        }
+        if constexpr (r > 0) ym = uc[r - 1][q]; else ym = below;
+        if constexpr (r < R - 1) yp = uc[r + 1][q]; else yp = above;
+        T zm = um[r][q], zp = up[r][q];
+        if (!PER && bnd && in_x && in_y[r] && in_z) {
+          // face-array coordinates in [0, n): wrapped on periodic axes, in range otherwise
+          const int xw = xag + q, yw = ygv[r], pw = p & nm;
+          if (q == 0 && bnd_xl) xm = ghost_of(A.bc, 0, n, yw, pw, c);
+          if (q == 1 && bnd_xr) xp = ghost_of(A.bc, 1, n, yw, pw, c);
+          if (!py && yv[r] == 0) ym = ghost_of(A.bc, 2, n, xw, pw, c);
+          if (!py && yv[r] == nm) yp = ghost_of(A.bc, 3, n, xw, pw, c);
+          if (bnd_z0) zm = ghost_of(A.bc, 4, n, xw, yw, c);
+          if (bnd_z1) zp = ghost_of(A.bc, 5, n, xw, yw, c);
+        }
+        T fv;
+        if constexpr (FS < 0) fv = fr[r][q];
+        else fv = q ? fl[FS][r][tid].b : fl[FS][r][tid].a;
+        const T nbs = ((((xm + xp) + ym) + yp) + zm) + zp;
+        uc[r][q] = c + omega * ((nbs - h2 * fv) * inv6 - c);
+      });
+    };
+
+    // ---- defect stage on plane p (parity PAR, final after black sweep 2, in uc; p-1 in um,
+    // p+1 in up, final in its red cells): completes the red cells of p-1 with the black cells
+    // of p above them, takes the black cells of p whole and the red cells of p without their
+    // upper neighbour; then the restriction (down) or the sum of squares (norm)
+    auto defect = [&](auto cPAR, auto cFS, T (&um)[R][2], T (&uc)[R][2], T (&up)[R][2], int p)
+                      __attribute__((always_inline)) {
+      constexpr int PAR = decltype(cPAR)::value, FS = decltype(cFS)::value;
+      Pair<T>* xq = &xch[xbuf][0][0][0];
+      xq[(band * 2 + 0) * SL + xl] = Pair<T>{uc[0][0], uc[0][1]};
+      xq[(band * 2 + 1) * SL + xl] = Pair<T>{uc[R - 1][0], uc[R - 1][1]};
+      __syncthreads();
+      const Pair<T> vb = xq[((band > 0 ? band - 1 : band) * 2 + 1) * SL + xl];
+      const Pair<T> va = xq[((band < NB - 1 ? band + 1 : band) * 2 + 0) * SL + xl];
+      xbuf ^= 1;
+      const T below[2] = {vb.a, vb.b}, above[2] = {va.a, va.b};
+      const bool in_z = pz || (p >= 0 && p < n);
+      const bool bnd_z0 = !pz && p == 0, bnd_z1 = !pz && p == nm;
+      const bool bnd = !PER && (wave_bnd_xy || bnd_z0 || bnd_z1);
+      // plane p-1: its red cells' upper neighbour is final now (unless p-1 is the top plane of
+      // a non-periodic axis, whose ghost was taken at once)
+      const bool top_prev = !pz && p - 1 == nm;
+      const bool out_prev = p - 1 >= z0 && p - 1 < zend;
+      const bool out_cur = p >= z0 && p < zend;
+      T dprev[R], dblk[R];
+      static_for<R>([&](auto rr) __attribute__((always_inline)) {
+        constexpr int r = decltype(rr)::value;
+        constexpr int qr_prev = (r + PAR + 1) & 1;   // red cell of row r on plane p-1 (parity PAR^1)
+        dprev[r] = top_prev ? dred[r] : dred[r] - ih2 * uc[r][qr_prev];
+      });
+      static_for<R>([&](auto rr) __attribute__((always_inline)) {
+        constexpr int r = decltype(rr)::value;
+        const Pair<T> fp = fl[FS][r][tid];
+        const T fpair[2] = {fp.a, fp.b};
+        // q = 0: the black cell, whole; q = 1: the red cell, without its upper neighbour
+        static_for<2>([&](auto qq) __attribute__((always_inline)) {
+          constexpr int black = decltype(qq)::value == 0;
+          constexpr int q = (r + PAR + (black ? 1 : 0)) & 1;
+          const T c = uc[r][q];
+          T xm, xp, ym, yp;
+          if constexpr (q == 0) {
+            xm = from_left(uc[r][1]);
+            xp = uc[r][1];
+          } else {
+            xm = uc[r][0];
+            xp = from_right(uc[r][0]);
+          }
+          if constexpr (r > 0) ym = uc[r - 1][q]; else ym = below[q];
+          if constexpr (r < R - 1) yp = uc[r + 1][q]; else yp = above[q];
+          T zm = um[r][q], zp = up[r][q];
+          if (!PER && bnd && in_x && in_y[r] && in_z) {
+            const int xw = xag + q, yw = ygv[r], pw = p & nm;
+            if (q == 0 && bnd_xl) xm = ghost_of(A.bc, 0, n, yw, pw, c);
+            if (q == 1 && bnd_xr) xp = ghost_of(A.bc, 1, n, yw, pw, c);
+            if (!py && yv[r] == 0) ym = ghost_of(A.bc, 2, n, xw, pw, c);
+            if (!py && yv[r] == nm) yp = ghost_of(A.bc, 3, n, xw, pw, c);
+            if (bnd_z0) zm = ghost_of(A.bc, 4, n, xw, yw, c);
+            if (bnd_z1) zp = ghost_of(A.bc, 5, n, xw, yw, c);
+          }
+          const T s5 = (((xm + xp) + ym) + yp) + zm;
+          if constexpr (black) {
+            dblk[r] = fpair[q] - ((s5 + zp) - (T)6 * c) * ih2;
+          } else {
+            // the upper neighbour of a red cell on the top plane of a non-periodic axis is its
+            // ghost (known now); elsewhere it is added at the next step
+            dred[r] = bnd_z1 ? fpair[q] - ((s5 + zp) - (T)6 * c) * ih2 : fpair[q] - (s5 - (T)6 * c) * ih2;
+          }
+        });
+      });
+      if constexpr (NORM) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if (out_x && out_y[r]) {
+            if (out_cur) acc += (double)dblk[r] * (double)dblk[r];
+            if (out_prev) acc += (double)dprev[r] * (double)dprev[r];
+          }
+        }
+      }
+      if constexpr (DEF) {
+        // plane p-1 is complete: its row-pair sums (black part from the previous step); the
+        // even plane of a coarse plane waits in stash, the odd one writes the coarse cell
+        constexpr int par_prev = PAR ^ 1;
+        T* __restrict__ fcp = reinterpret_cast<T*>(A.fc);
+        T* __restrict__ ucp = reinterpret_cast<T*>(A.uc0);
+#pragma unroll
+        for (int j = 0; j < R / 2; ++j) {
+          const T sprev = pend[j] + (dprev[2 * j] + dprev[2 * j + 1]);
+          if constexpr (par_prev == 0) {
+            stash[j] = sprev;
+          } else {
+            if (out_prev && out_x && out_y[2 * j]) {
+              const size_t ci = cidx(L - 1, xag >> 1, ygv[2 * j] >> 1, (p - 1) >> 1);
+              fcp[ci] = (stash[j] + sprev) * (T)0.125;
+              ucp[ci] = (T)0;
+            }
+          }
+          pend[j] = dblk[2 * j] + dblk[2 * j + 1];
+        }
+      }
+    };
+
+    load_plane(zstart, true);
+    prolong_apply(zstart, std::integral_constant<int, HZ & 1>{});
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      u[0][r][0] = pu[r][0]; u[0][r][1] = pu[r][1];
+      fr[r][0] = pf[r][0]; fr[r][1] = pf[r][1];
+    }
+    // one pipeline step: the plane in ring slot K is P = zstart + t, t = g + K with g a
+    // multiple of 6, so P - j sits in slot (K - j) mod 6, has parity (HZ + K + j) mod 2, and
+    // its f is in LDS slot (K - HZ - j) mod 3 (z0 is a multiple of 6)
+    auto step = [&](int g, auto kk) __attribute__((always_inline)) {
+      constexpr int K = decltype(kk)::value;
+      const int t = g + K;
+      if (t >= nsteps) return;
+      const int P = zstart + t;
+      if (t + 1 < nsteps) load_plane(P + 1, false);   // prefetch; consumed at the end of the step
+      constexpr int s0 = K, s1 = (K + 5) % 6, s2 = (K + 4) % 6, s3 = (K + 3) % 6, s4 = (K + 2) % 6,
+                    s5 = (K + 1) % 6;
+      using I0 = std::integral_constant<int, 0>;
+      using I1 = std::integral_constant<int, 1>;
+      using Par1 = std::integral_constant<int, (HZ + K + 1) & 1>;
+      using Par2 = std::integral_constant<int, (HZ + K + 2) & 1>;
+      using Par3 = std::integral_constant<int, (HZ + K + 3) & 1>;
+      using Par4 = std::integral_constant<int, (HZ + K + 4) & 1>;
+      using FsReg = std::integral_constant<int, -1>;
+      using Fs2 = std::integral_constant<int, ((K - HZ - 2) % 3 + 6) % 3>;
+      using Fs3 = std::integral_constant<int, ((K - HZ - 3) % 3 + 6) % 3>;
+      using Fs4 = std::integral_constant<int, ((K - HZ - 4) % 3 + 6) % 3>;
+      colour(I0{}, Par1{}, FsReg{}, u[s2], u[s1], u[s0], P - 1);   // red, sweep 1
+      colour(I1{}, Par2{}, Fs2{}, u[s3], u[s2], u[s1], P - 2);     // black, sweep 1
+      colour(I0{}, Par3{}, Fs3{}, u[s4], u[s3], u[s2], P - 3);     // red, sweep 2
+      colour(I1{}, Par4{}, Fs4{}, u[s5], u[s4], u[s3], P - 4);     // black, sweep 2
+      if constexpr (DSTAGE) defect(Par4{}, Fs4{}, u[s5], u[s4], u[s3], P - 4);
+      // plane P-4 is final: out
+      {
+        const int p = P - 4;
+        if (p >= z0 && p < zend && out_x) {
+          const int pg = p & nm;
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+            if (out_y[r]) {
+              typedef T ntv2 __attribute__((ext_vector_type(2)));
+              const ntv2 v = {u[s4][r][0], u[s4][r][1]};
+              __builtin_nontemporal_store(v, reinterpret_cast<ntv2*>(uout + cidx(L, xag, ygv[r], pg)));
+            }
+        }
+      }
+      if (t + 1 < nsteps) {
+        prolong_apply(P + 1, std::integral_constant<int, (HZ + K + 1) & 1>{});
+        // u(P+1) enters the ring in the slot of P-5; f(P-1) moves to the LDS slot of P-4 (done
+        // with), f(P) into the registers
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          u[s5][r][0] = pu[r][0]; u[s5][r][1] = pu[r][1];
+          fl[Fs4::value][r][tid] = Pair<T>{fr[r][0], fr[r][1]};
+          fr[r][0] = pf[r][0]; fr[r][1] = pf[r][1];
+        }
+      }
+    };
+    for (int g = 0; g < nsteps; g += kRing) {
+      step(g, std::integral_constant<int, 0>{});
+      step(g, std::integral_constant<int, 1>{});
+      step(g, std::integral_constant<int, 2>{});
+      step(g, std::integral_constant<int, 3>{});
+      step(g, std::integral_constant<int, 4>{});
+      step(g, std::integral_constant<int, 5>{});
+    }
+  }
+  if constexpr (NORM) {
+    // the exchange buffer is free once every wave has left the march
+    double* red = reinterpret_cast<double*>(&xch[0][0][0][0]);
+    acc = wave_sum(acc);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int q = 0; q < W; ++q) s += red[q];
+      A.part[blockIdx.x] = s;
+    }
+  }
+}
+
+constexpr int kCUs = 256;
+
+// Planes per workgroup: a multiple of 6 (the ring's period; chunks then start on planes whose
+// ring slot, parity and f slot are compile-time).  One workgroup per CU is resident (LDS), so
+// the grid runs in rounds of kCUs workgroups; the chunk minimises rounds x (planes marched,
+// 2 hz halo planes included).
+int march_zchunk(int n, int tiles_xy, int hz) {
+  int best = (n + 5) / 6 * 6;
+  long best_cost = -1;
+  for (int c = 1; c <= n / 6; ++c) {
+    int zc = (n + c - 1) / c;
+    zc = (zc + 5) / 6 * 6;
+    const long chunks = (n + zc - 1) / zc;
+    if ((long)tiles_xy * chunks > (long)kMaxPartials * 32 - 8) continue;   // partials buffer
+    const long rounds = ((long)tiles_xy * chunks + kCUs - 1) / kCUs;
+    const long cost = rounds * (zc + 2 * hz);
+    if (best_cost < 0 || cost < best_cost) best_cost = cost, best = zc;
+  }
+  return best;
+}
+
+template <typename T, bool UP, bool NORM>
+int launch_march(MarchArgs A, hipStream_t s) {
+  bool per = true;
+  for (int f = 0; f < 6; ++f) per = per && A.bc.kind[f] == BC_PERIODIC;
+  constexpr int W = cfg_W<T>();
+  constexpr int HZ = (!UP || NORM) ? 5 : 4;
+  A.L = ilog2(A.n);
+  A.xo = kTX - 2 * kHalo;
+  A.yo = kR * 2 * W - 2 * kHalo;
+  A.tiles_x = (A.n + A.xo - 1) / A.xo;
+  A.tiles_y = (A.n + A.yo - 1) / A.yo;
+  A.zc = march_zchunk(A.n, A.tiles_x * A.tiles_y, HZ);
+  const int chunks = (A.n + A.zc - 1) / A.zc;
+  A.ntiles = A.tiles_x * A.tiles_y * chunks;
+  const int grid = (A.ntiles + 7) / 8 * 8;
+  if (per) hipLaunchKernelGGL((k_march<T, W, UP, NORM, true>), dim3(grid), dim3(kLanes * W), 0, s, A);
+  else hipLaunchKernelGGL((k_march<T, W, UP, NORM, false>), dim3(grid), dim3(kLanes * W), 0, s, A);
+  return grid;
+}
+
+template <typename T>
+MarchArgs base_args(const T* uin, T* uout, const T* f, int n, double h, double omega, const LevelBC& bc) {
+  MarchArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.uin = uin;
+  A.uout = uout;
+  A.f = f;
+  A.bc = bc;
+  A.n = n;
+  A.h2 = h * h;
+  A.ih2 = 1.0 / (h * h);
+  A.omega = omega;
+  A.zero_in = uin == nullptr;
+  return A;
+}
+
+}  // namespace
+
+template <typename T>
+void march_down(const T* uin, T* uout, const T* f, T* fc, T* uc0, int n, double h, double omega, const LevelBC& bc,
+                hipStream_t s) {
+  MarchArgs A = base_args(uin, uout, f, n, h, omega, bc);
+  A.fc = fc;
+  A.uc0 = uc0;
+  launch_march<T, false, false>(A, s);
+}
+
+template <typename T>
+int march_up(const T* uin, T* uout, const T* f, const T* ec, const LevelBC& bcc, double* part, int n, double h,
+             double omega, const LevelBC& bc, hipStream_t s) {
+  MarchArgs A = base_args(uin, uout, f, n, h, omega, bc);
+  A.ec = ec;
+  A.bcc = bcc;
+  A.part = part;
+  if (part) return launch_march<T, true, true>(A, s);
+  launch_march<T, true, false>(A, s);
+  return 0;
+}
+
+template <typename T>
+std::string march_name(bool up, bool norm, bool per) {
+  return std::string("k_march<") + (sizeof(T) == 8 ? "double" : "float") + ", " + std::to_string(cfg_W<T>()) + ", " +
+         (up ? "true" : "false") + ", " + (up && norm ? "true" : "false") + ", " + (per ? "true" : "false") + ">";
+}
+
+template void march_down<double>(const double*, double*, const double*, double*, double*, int, double, double,
+                                 const LevelBC&, hipStream_t);
+template void march_down<float>(const float*, float*, const float*, float*, float*, int, double, double,
+                                const LevelBC&, hipStream_t);
+template int march_up<double>(const double*, double*, const double*, const double*, const LevelBC&, double*, int,
+                              double, double, const LevelBC&, hipStream_t);
+template int march_up<float>(const float*, float*, const float*, const float*, const LevelBC&, double*, int, double,
+                             double, const LevelBC&, hipStream_t);
+template std::string march_name<double>(bool, bool, bool);
+template std::string march_name<float>(bool, bool, bool);
+
+}  // namespace mg
