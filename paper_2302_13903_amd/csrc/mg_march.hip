@@ -8,7 +8,7 @@
 //        trilinear) as u is loaded, then two sweeps, optionally followed by the defect of the
 //        result summed as squares (the convergence norm of Sec. 2.3.7).
 //
-// Work layout.  A workgroup of W waves owns a tile of 64 x (8 W) cells in x-y and marches a
+// Work layout.  A workgroup of W = 8 waves owns a tile of 64 x 64 cells in x-y and marches a
 // chunk of z planes.  Each half-wave holds a band of R = 4 rows, each lane the x-pair (2l, 2l+1)
 // of those rows.  At the step that loads plane P the stages run on older planes:
 //   red sweep 1 on P-1, black 1 on P-2, red 2 on P-3, black 2 on P-4, defect on P-4,
@@ -117,10 +117,11 @@ struct alignas(2 * sizeof(T)) Pair {
   T a, b;
 };
 
-// Waves per workgroup: FP64 8 (tile 64 x 64, up to 256 registers per lane), FP32 16 (64 x 128).
+// Waves per workgroup: 8 (a 64 x 64 tile, 2 waves per SIMD with up to 256 registers per lane;
+// FP32 on 16 waves, a 64 x 128 tile, needs more than the 128 registers that leaves per lane).
 template <typename T>
 constexpr int cfg_W() {
-  return sizeof(T) == 8 ? 8 : 16;
+  return 8;
 }
 
 // PER: every face of the level is periodic (the launcher checks), so no boundary code is
@@ -249,7 +250,9 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
           int Y = Y0 - 1 + i;
           if (py) Y &= nc - 1;
           if (pz) zz &= nc - 1;
-          return coarse_at(ec, nc, Lc, X, Y, zz, A.bcc);
+          // every face periodic: the wrapped indices are in range (no ghost code compiled)
+          if constexpr (PER) return ec[cidx(Lc, X, Y, zz)];
+          else return coarse_at(ec, nc, Lc, X, Y, zz, A.bcc);
         };
         if (first || (P & 1)) {
 #pragma unroll
