@@ -27,7 +27,16 @@
 // neighbours now and the upper one (black, final one step later) at the next step, so the ring
 // stays at six planes.  Tiles overlap by a halo of 6 cells (5 stages of radius 1, rounded up to
 // even) and are recomputed, so tiles are independent and the result goes to another array.
-// Boundary ghosts are evaluated on the fly (Sec. 2.3.6) for cells on non-periodic faces.
+//
+// Non-periodic faces (Sec. 2.3.6): the cell just beyond a face is a ghost cell of the tile.
+// Before every stage it is set to kappa * (the adjacent active cell's current value) + beta,
+// with kappa = +1, beta = 0 for a zero-gradient face and kappa = -1, beta = 2 b for a fixed face,
+// so the stage itself needs no boundary code.  beta of an x or y face travels in the ghost
+// cell's own f slot (loaded with the plane); with 52-row output tiles and a halo of 6 the rows
+// beyond y = 0 and y = n-1 are always rows 1 and 2 of the same lane as their active neighbour.
+// The ghost planes beyond z = 0 and z = n-1 take beta from the face arrays (two planes per
+// level).  The coarse correction's taps (homogeneous conditions) are clamped to the domain with
+// the sign of each face's rule.
 #include "mg_march.h"
 
 #include <cstring>
@@ -99,17 +108,30 @@ __device__ __forceinline__ T from_right(T v) {  // value of lane + 1
   return dpp_move<kDppWaveShl1>(v);
 }
 
+// Ghost rule of a face as ghost = kappa * adjacent + beta: zero gradient kappa = 1, beta = 0;
+// fixed (and multipole) kappa = -1, beta = 2 b at the face point (t1, t2).
 template <typename T>
-__device__ __forceinline__ T ghost_of(const LevelBC& bc, int face, int n, int t1, int t2, T c) {
-  if (bc.kind[face] == BC_ZERO_GRADIENT) return c;
-  return (T)(2.0 * face_b(bc, face, n, t1, t2)) - c;
+__device__ __forceinline__ T kappa_of(const LevelBC& bc, int face) {
+  return bc.kind[face] == BC_ZERO_GRADIENT ? (T)1 : (T)-1;
+}
+template <typename T>
+__device__ __forceinline__ T beta_of(const LevelBC& bc, int face, int n, int t1, int t2) {
+  return bc.kind[face] == BC_ZERO_GRADIENT ? (T)0 : (T)(2.0 * face_b(bc, face, n, t1, t2));
 }
 
+// One index of a coarse tap under homogeneous conditions: inside, or clamped to the boundary
+// cell with the sign of that face's rule (periodic indices arrive wrapped).
 template <typename T>
-__device__ __forceinline__ T coarse_at(const T* __restrict__ e, int nc, int Lc, int X, int Y, int Z, const LevelBC& bcc) {
-  if ((unsigned)X < (unsigned)nc && (unsigned)Y < (unsigned)nc && (unsigned)Z < (unsigned)nc)
-    return e[cidx(Lc, X, Y, Z)];
-  return ghost_any(e, nc, Lc, X, Y, Z, bcc);
+__device__ __forceinline__ int clamp_tap(int v, int nc, const LevelBC& bcc, int lo_face, T& s) {
+  if (v < 0) {
+    s *= kappa_of<T>(bcc, lo_face);
+    return 0;
+  }
+  if (v >= nc) {
+    s *= kappa_of<T>(bcc, lo_face + 1);
+    return nc - 1;
+  }
+  return v;
 }
 
 template <typename T>
@@ -165,8 +187,9 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
     const bool in_x = px || (xa >= 0 && xa < n);
     const int xag = xa & nm;
     const bool out_x = xa >= xs && xa < xs + A.xo && xa < n;
-    const bool bnd_xl = !px && xa == 0;          // cell a on the -x face
-    const bool bnd_xr = !px && xa + 1 == nm;     // cell b on the +x face
+    // the lane whose odd cell is the ghost beyond x = 0, whose even cell is the ghost beyond n-1
+    const bool gx0 = !PER && !px && xa == -2;
+    const bool gx1 = !PER && !px && xa == n;
 
     const int ys = ty * A.yo;                    // first output row (even)
     int yv[R], ygv[R];
@@ -183,10 +206,16 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
     const int zend = min(z0 + A.zc, n);
     const int zstart = z0 - HZ;
     const int nsteps = (zend - z0) + 2 * HZ;
-    // does any cell of this wave touch a non-periodic face in x or y?
+    // rows 1 and 2 of this lane are the ghost row beyond y = 0 and its active neighbour, or the
+    // active row y = n-1 and the ghost beyond it
+    const bool gy0 = !PER && !py && yv[1] == -1;
+    const bool gy1 = !PER && !py && yv[2] == n;
+    // does any cell of this wave sit beside a ghost in x or y?
     const int wy0 = ys - kHalo + w * 2 * R, wy1 = wy0 + 2 * R - 1;
-    const bool wave_bnd_xy =
-        !PER && ((!px && (xs - kHalo <= 0 || xs - kHalo + kTX - 1 >= nm)) || (!py && (wy0 <= 0 || wy1 >= nm)));
+    const bool wave_x = !PER && !px && (xs - kHalo < 0 || xs - kHalo + kTX - 1 >= n);
+    const bool wave_y = !PER && !py && (wy0 < 0 || wy1 >= n);
+    const T kx0 = kappa_of<T>(A.bc, 0), kx1 = kappa_of<T>(A.bc, 1), ky0 = kappa_of<T>(A.bc, 2);
+    const T ky1 = kappa_of<T>(A.bc, 3), kz0 = kappa_of<T>(A.bc, 4), kz1 = kappa_of<T>(A.bc, 5);
 
     T u[kRing][R][2];
     T pu[R][2], pf[R][2];      // prefetched u of plane P+1 and f of plane P
@@ -229,6 +258,21 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
         } else {
           pf[r][0] = pf[r][1] = (T)0;
         }
+        if constexpr (!PER) {
+          // a ghost cell's f slot carries beta of its face at the ghost's transverse position
+          if (in_zf) {
+            if (gx0 && in_y[r]) pf[r][1] = beta_of<T>(A.bc, 0, n, ygv[r], Pfg);
+            if (gx1 && in_y[r]) pf[r][0] = beta_of<T>(A.bc, 1, n, ygv[r], Pfg);
+            if (r == 1 && gy0 && in_x) {
+              pf[1][0] = beta_of<T>(A.bc, 2, n, xag, Pfg);
+              pf[1][1] = beta_of<T>(A.bc, 2, n, xag + 1, Pfg);
+            }
+            if (r == 2 && gy1 && in_x) {
+              pf[2][0] = beta_of<T>(A.bc, 3, n, xag, Pfg);
+              pf[2][1] = beta_of<T>(A.bc, 3, n, xag + 1, Pfg);
+            }
+          }
+        }
       }
       if constexpr (UP) {
         // Trilinear prolongation (weights 1/4, 3/4 per axis) of the coarse correction: the
@@ -251,8 +295,15 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
           if (py) Y &= nc - 1;
           if (pz) zz &= nc - 1;
           // every face periodic: the wrapped indices are in range (no ghost code compiled)
-          if constexpr (PER) return ec[cidx(Lc, X, Y, zz)];
-          else return coarse_at(ec, nc, Lc, X, Y, zz, A.bcc);
+          if constexpr (PER) {
+            return ec[cidx(Lc, X, Y, zz)];
+          } else {
+            T sg = (T)1;
+            const int Xc = clamp_tap<T>(X, nc, A.bcc, 0, sg);
+            const int Yc = clamp_tap<T>(Y, nc, A.bcc, 2, sg);
+            const int Zc = clamp_tap<T>(zz, nc, A.bcc, 4, sg);
+            return sg * ec[cidx(Lc, Xc, Yc, Zc)];
+          }
         };
         if (first || (P & 1)) {
 #pragma unroll
@@ -288,12 +339,67 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
 
     int xbuf = 0;
 
+    // ---- ghost cells beside the active cells of colour COL (0 red, 1 black, 2 both) of plane p
+    // (parity PAR, in uc; the planes beside it in um, up; its f in registers when FS < 0, else
+    // in LDS slot FS) set from those cells' current values
+    auto refresh = [&](auto cCOL, auto cPAR, auto cFS, T (&um)[R][2], T (&uc)[R][2], T (&up)[R][2],
+                       int p) __attribute__((always_inline)) {
+      if constexpr (!PER) {
+        constexpr int COL = decltype(cCOL)::value, PAR = decltype(cPAR)::value, FS = decltype(cFS)::value;
+        auto fget = [&](int r, int e) __attribute__((always_inline)) -> T {
+          if constexpr (FS < 0) return fr[r][e];
+          else return e ? fl[FS][r][tid].b : fl[FS][r][tid].a;
+        };
+        // does cell e of row r have a colour being refreshed?
+        auto sel = [](int r, int e) constexpr { return COL == 2 || ((r + PAR + COL) & 1) == e; };
+        if (wave_x) {
+          static_for<R>([&](auto rr) __attribute__((always_inline)) {
+            constexpr int r = decltype(rr)::value;
+            if constexpr (sel(r, 0)) {   // x = 0 is an even column
+              const T v = from_right(uc[r][0]);
+              if (gx0) uc[r][1] = kx0 * v + fget(r, 1);
+            }
+            if constexpr (sel(r, 1)) {   // x = n-1 is an odd column
+              const T v = from_left(uc[r][1]);
+              if (gx1) uc[r][0] = kx1 * v + fget(r, 0);
+            }
+          });
+        }
+        if (wave_y) {
+          static_for<2>([&](auto ee) __attribute__((always_inline)) {
+            constexpr int e = decltype(ee)::value;
+            if constexpr (sel(2, e))
+              if (gy0) uc[1][e] = ky0 * uc[2][e] + fget(1, e);
+            if constexpr (sel(1, e))
+              if (gy1) uc[2][e] = ky1 * uc[1][e] + fget(2, e);
+          });
+        }
+        if (!pz && (p == 0 || p == nm)) {
+          // the ghost plane beyond z = 0 or z = n-1 (beta from the face arrays)
+          const bool lo = p == 0;
+          const T kz = lo ? kz0 : kz1;
+          static_for<R>([&](auto rr) __attribute__((always_inline)) {
+            constexpr int r = decltype(rr)::value;
+            static_for<2>([&](auto ee) __attribute__((always_inline)) {
+              constexpr int e = decltype(ee)::value;
+              if constexpr (sel(r, e)) {
+                const T g = kz * uc[r][e] + beta_of<T>(A.bc, lo ? 4 : 5, n, (xag + e) & nm, ygv[r]);
+                if (lo) um[r][e] = g;
+                else up[r][e] = g;
+              }
+            });
+          });
+        }
+      }
+    };
+
     // ---- one colour C (0 red, 1 black) of the RB-SOR update (eqs. rbsor1-2) on plane p of
     // parity PAR held in uc, its z-neighbour planes in um (p-1) and up (p+1); f from the
     // registers (FS < 0) or LDS slot FS
     auto colour = [&](auto cC, auto cPAR, auto cFS, T (&um)[R][2], T (&uc)[R][2], T (&up)[R][2],
                       int p) __attribute__((always_inline)) {
       constexpr int C = decltype(cC)::value, PAR = decltype(cPAR)::value, FS = decltype(cFS)::value;
+      refresh(cC, cPAR, cFS, um, uc, up, p);
       // the band-edge rows' cells of the other colour, for the bands below and above
       constexpr int q0 = (PAR + C) & 1, qL = (R - 1 + PAR + C) & 1;
       T* xt = reinterpret_cast<T*>(&xch[xbuf][0][0][0]);
@@ -303,9 +409,6 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
       const T below = xt[((band > 0 ? band - 1 : band) * 2 + 1) * SL + xl];
       const T above = xt[((band < NB - 1 ? band + 1 : band) * 2 + 0) * SL + xl];
       xbuf ^= 1;
-      const bool in_z = pz || (p >= 0 && p < n);
-      const bool bnd_z0 = !pz && p == 0, bnd_z1 = !pz && p == nm;
-      const bool bnd = !PER && (wave_bnd_xy || bnd_z0 || bnd_z1);
       static_for<R>([&](auto rr) __attribute__((always_inline)) {
         constexpr int r = decltype(rr)::value;
         constexpr int q = (r + PAR + C) & 1;      // the cell of this colour in row r
@@ -320,17 +423,7 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
         }
         if constexpr (r > 0) ym = uc[r - 1][q]; else ym = below;
         if constexpr (r < R - 1) yp = uc[r + 1][q]; else yp = above;
-        T zm = um[r][q], zp = up[r][q];
-        if (!PER && bnd && in_x && in_y[r] && in_z) {
-          // face-array coordinates in [0, n): wrapped on periodic axes, in range otherwise
-          const int xw = xag + q, yw = ygv[r], pw = p & nm;
-          if (q == 0 && bnd_xl) xm = ghost_of(A.bc, 0, n, yw, pw, c);
-          if (q == 1 && bnd_xr) xp = ghost_of(A.bc, 1, n, yw, pw, c);
-          if (!py && yv[r] == 0) ym = ghost_of(A.bc, 2, n, xw, pw, c);
-          if (!py && yv[r] == nm) yp = ghost_of(A.bc, 3, n, xw, pw, c);
-          if (bnd_z0) zm = ghost_of(A.bc, 4, n, xw, yw, c);
-          if (bnd_z1) zp = ghost_of(A.bc, 5, n, xw, yw, c);
-        }
+        const T zm = um[r][q], zp = up[r][q];
         T fv;
         if constexpr (FS < 0) fv = fr[r][q];
         else fv = q ? fl[FS][r][tid].b : fl[FS][r][tid].a;
@@ -346,6 +439,7 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
     auto defect = [&](auto cPAR, auto cFS, T (&um)[R][2], T (&uc)[R][2], T (&up)[R][2], int p)
                       __attribute__((always_inline)) {
       constexpr int PAR = decltype(cPAR)::value, FS = decltype(cFS)::value;
+      refresh(std::integral_constant<int, 2>{}, cPAR, cFS, um, uc, up, p);
       Pair<T>* xq = &xch[xbuf][0][0][0];
       xq[(band * 2 + 0) * SL + xl] = Pair<T>{uc[0][0], uc[0][1]};
       xq[(band * 2 + 1) * SL + xl] = Pair<T>{uc[R - 1][0], uc[R - 1][1]};
@@ -354,9 +448,7 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
       const Pair<T> va = xq[((band < NB - 1 ? band + 1 : band) * 2 + 0) * SL + xl];
       xbuf ^= 1;
       const T below[2] = {vb.a, vb.b}, above[2] = {va.a, va.b};
-      const bool in_z = pz || (p >= 0 && p < n);
-      const bool bnd_z0 = !pz && p == 0, bnd_z1 = !pz && p == nm;
-      const bool bnd = !PER && (wave_bnd_xy || bnd_z0 || bnd_z1);
+      const bool bnd_z1 = !PER && !pz && p == nm;
       // plane p-1: its red cells' upper neighbour is final now (unless p-1 is the top plane of
       // a non-periodic axis, whose ghost was taken at once)
       const bool top_prev = !pz && p - 1 == nm;
@@ -387,22 +479,13 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
           }
           if constexpr (r > 0) ym = uc[r - 1][q]; else ym = below[q];
           if constexpr (r < R - 1) yp = uc[r + 1][q]; else yp = above[q];
-          T zm = um[r][q], zp = up[r][q];
-          if (!PER && bnd && in_x && in_y[r] && in_z) {
-            const int xw = xag + q, yw = ygv[r], pw = p & nm;
-            if (q == 0 && bnd_xl) xm = ghost_of(A.bc, 0, n, yw, pw, c);
-            if (q == 1 && bnd_xr) xp = ghost_of(A.bc, 1, n, yw, pw, c);
-            if (!py && yv[r] == 0) ym = ghost_of(A.bc, 2, n, xw, pw, c);
-            if (!py && yv[r] == nm) yp = ghost_of(A.bc, 3, n, xw, pw, c);
-            if (bnd_z0) zm = ghost_of(A.bc, 4, n, xw, yw, c);
-            if (bnd_z1) zp = ghost_of(A.bc, 5, n, xw, yw, c);
-          }
+          const T zm = um[r][q], zp = up[r][q];
           const T s5 = (((xm + xp) + ym) + yp) + zm;
           if constexpr (black) {
             dblk[r] = fpair[q] - ((s5 + zp) - (T)6 * c) * ih2;
           } else {
-            // the upper neighbour of a red cell on the top plane of a non-periodic axis is its
-            // ghost (known now); elsewhere it is added at the next step
+            // the upper neighbour of a red cell on the top plane of a non-periodic axis is the
+            // ghost plane (set now); elsewhere it is added at the next step
             dred[r] = bnd_z1 ? fpair[q] - ((s5 + zp) - (T)6 * c) * ih2 : fpair[q] - (s5 - (T)6 * c) * ih2;
           }
         });
