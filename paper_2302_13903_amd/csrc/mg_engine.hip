@@ -21,6 +21,7 @@
 #include "mg_fused.h"
 #include "mg_launch.h"
 #include "mg_march.h"
+#include "mg_tile.h"
 #include "mg_tblock.h"
 
 using namespace mg;
@@ -115,6 +116,9 @@ struct mg_ctx {
   // prolongation + two sweeps [+ norm]): 0 = off, 1 = on levels whose faces are all periodic,
   // 2 = on every level; -1 = the built-in default (1)
   int march[2] = {-1, -1};
+  // V(2,2) legs of the levels 32^3 .. 128^3 (and the MeshBlock levels below the streaming
+  // passes) as one region-tile launch each: 1 = on (default), 0 = per-operator launches
+  int tile[2] = {-1, -1};
 };
 
 // refined-mesh solve (mg_amr.hip); part: device partials (kMaxPartials x 32 doubles), hpart:
@@ -189,7 +193,7 @@ Layout make_layout(int n, int precision, int Lb = -1, bool fas = false) {
     y.faces[l] = take(6 * face_sz(l) * 8);
     y.pbar[l] = (fas && l < y.L) ? take(cells(l) * 8) : (size_t)-1;
     y.u2[l] = (size_t)-1;
-    if ((1 << l) >= kFusedMinN || (Lb >= 0 && l > Lb)) y.u2[l] = take(cells(l) * (y.mixed ? 4 : 8));
+    if ((1 << l) >= kTileMinN || (Lb >= 0 && l > Lb)) y.u2[l] = take(cells(l) * (y.mixed ? 4 : 8));
   }
   y.total = off;
   return y;
@@ -365,6 +369,26 @@ struct Solver {
     return true;
   }
 
+  // May a MeshBlock level run the two-sweep streaming passes (the "march" setting for its faces)?
+  template <typename T>
+  bool march_blk_on(const Hier<T>& H, const LevelBC& bc) const {
+    const int mode = c->march[sizeof(T) == 8 ? 0 : 1] < 0 ? 1 : c->march[sizeof(T) == 8 ? 0 : 1];
+    if (mode == 0 || H.npre != 2 || H.npost != 2) return false;
+    if (mode == 1)
+      for (int f = 0; f < 6; ++f)
+        if (bc.kind[f] != BC_PERIODIC) return false;
+    return true;
+  }
+
+  // Does level l (side n) run its V(2,2) legs as region-tile launches (one per leg)?
+  template <typename T>
+  bool tile_on(const Hier<T>& H, int l) const {
+    const int v = c->tile[sizeof(T) == 8 ? 0 : 1];
+    const int n = 1 << l;
+    return (v < 0 || v == 1) && H.u2[l] && l != H.T_top && H.npre == 2 && H.npost == 2 && n >= kTileMinN &&
+           n <= kTileMaxN;
+  }
+
   // FP64, dense: can the first pre-sweep of the finest level's V-cycle run as a head pass (a
   // one-sweep streaming pass that also takes the residual norm of its input)?  Not when the
   // finest level runs the two-sweep passes, whose up pass takes the norm of the cycle's result.
@@ -435,6 +459,23 @@ struct Solver {
       const int np = march_up<T>(H.u2[l], H.u[l], H.f[l], H.u[l - 1], H.hom, npart, n, h, H.omega, bc, s);
       // algorithmic bytes: u, f and the coarse correction read, u written
       if (timed) kernel_end(march_name<T>(true, npart != nullptr, per), 3 * cellsT + cellsT / 8);
+      if (npart) launch_sum_partials(part, np, scal + 2, s);
+      return npart != nullptr;
+    }
+    if (n < (sizeof(T) == 8 ? fused_min_n64 : fused_min_n32) && tile_on<T>(H, l)) {
+      // a small level: each leg in one region-tile launch
+      if (top_call && zero_start) {
+        launch_zero(H.u[l], cells(l) * sizeof(T), s);
+        zero_start = false;
+      }
+      if (timed) kernel_begin();
+      tile_down<T>(H.u[l], H.u2[l], H.f[l], H.f[l - 1], H.u[l - 1], n, 0, 0, h, H.omega, bc, s);
+      if (timed) kernel_end(tile_name<T>(false, false), 3 * cellsT + cellsT / 4);
+      vcycle(H, l - 1, H.hom, false, false);
+      double* npart = want_norm && sizeof(T) == 8 ? part : nullptr;
+      if (timed) kernel_begin();
+      const int np = tile_up<T>(H.u2[l], H.u[l], H.f[l], H.u[l - 1], H.hom, npart, n, 0, 0, h, H.omega, bc, s);
+      if (timed) kernel_end(tile_name<T>(true, npart != nullptr), 3 * cellsT + cellsT / 8);
       if (npart) launch_sum_partials(part, np, scal + 2, s);
       return npart != nullptr;
     }
@@ -727,13 +768,38 @@ struct Solver {
     return (v < 0 ? true : v == 1) && (1 << l) >= (sizeof(T) == 8 ? fused_min_n64 : fused_min_n32);
   }
 
+  // Returns true when want_norm and the sum of squared defects of the result is in scal[2].
   template <typename T>
-  void vcycle_blk(Hier<T>& H, int l, const LevelBC& bc) {
+  bool vcycle_blk(Hier<T>& H, int l, const LevelBC& bc, bool want_norm = false) {
     if (l <= Lb) {
       vcycle(H, l, bc, false, false);
-      return;
+      return false;
     }
     const int Lm = l - Lb;
+    const int nl = 1 << l;
+    const bool big = blk_zmarch_on<T>(l) && nl >= kMarchMinN && march_blk_on<T>(H, bc);
+    if ((big || tile_on<T>(H, l)) && H.npre == 2 && H.npost == 2) {
+      // each leg of the block level in one launch over all blocks: the two-sweep streaming
+      // passes on the large levels, region tiles below
+      const bool timed = timed_top && l == H.L && ktiming;
+      const double cellsT = (double)cells(l) * sizeof(T);
+      bool per = true;
+      for (int f = 0; f < 6; ++f) per = per && bc.kind[f] == BC_PERIODIC;
+      if (timed) kernel_begin();
+      if (big) march_down<T>(H.u[l], H.u2[l], H.f[l], H.f[l - 1], H.u[l - 1], nl, H.h[l], H.omega, bc, s, Lm);
+      else tile_down<T>(H.u[l], H.u2[l], H.f[l], H.f[l - 1], H.u[l - 1], nl, Lm, Lb, H.h[l], H.omega, bc, s);
+      if (timed) kernel_end(big ? march_name<T>(false, false, per, true) : tile_name<T>(false, false), 3 * cellsT + cellsT / 4);
+      vcycle_blk(H, l - 1, H.hom);
+      double* npart = want_norm && sizeof(T) == 8 ? part : nullptr;
+      if (timed) kernel_begin();
+      const int np = big ? march_up<T>(H.u2[l], H.u[l], H.f[l], H.u[l - 1], H.hom, npart, nl, H.h[l], H.omega, bc, s, Lm)
+                         : tile_up<T>(H.u2[l], H.u[l], H.f[l], H.u[l - 1], H.hom, npart, nl, Lm, Lb, H.h[l], H.omega, bc, s);
+      if (timed)
+        kernel_end(big ? march_name<T>(true, npart != nullptr, per, true) : tile_name<T>(true, npart != nullptr),
+                   3 * cellsT + cellsT / 8);
+      if (npart) launch_sum_partials(part, np, scal + 2, s);
+      return npart != nullptr;
+    }
     if (blk_zmarch_on<T>(l) && H.npre > 0 && H.npost > 0) {
       // streaming passes across block boundaries: one sweep per pass, the restricted defect
       // as its own pass, the prolonged correction entering with the first post-sweep
@@ -755,7 +821,7 @@ struct Solver {
       pass(H.u[l - 1]);
       for (int it = 1; it < H.npost; ++it) pass(nullptr);
       if (cur != H.u[l]) (void)hipMemcpyAsync(H.u[l], cur, cells(l) * sizeof(T), hipMemcpyDeviceToDevice, s);
-      return;
+      return false;
     }
     T* cur = blk_sweeps(H, l, H.u[l], H.npre, bc);
     blk_defect_restrict<T>(cur, H.f[l], H.f[l - 1], H.u[l - 1], Lm, Lb, H.h[l], bc, s);
@@ -763,6 +829,7 @@ struct Solver {
     blk_prolong<T>(H.u[l - 1], cur, Lm, Lb, H.hom, 0, s);
     cur = blk_sweeps(H, l, cur, H.npost, bc);
     if (cur != H.u[l]) (void)hipMemcpyAsync(H.u[l], cur, cells(l) * sizeof(T), hipMemcpyDeviceToDevice, s);
+    return false;
   }
 
   // Source hierarchy f_{l-1} = restriction of f_l (Alg. 2 step 1) in either layout.
@@ -1079,7 +1146,8 @@ int solve_impl(mg_ctx* c, const mg_params* p, const mg_bc* bc, const double* rho
       S.fas_fmg(H64, pbar);
     } else if (!mixed) {
       // the finest level's FMG V-cycle takes the norm of its result when its up pass can
-      fmg_normed = S.fmg(H64, S.march_on<double>(H64, L, phys[L]));
+      fmg_normed = S.fmg(H64, S.march_on<double>(H64, L, phys[L]) ||
+                                  (p->n < S.fused_min_n64 && S.tile_on<double>(H64, L)));
     } else {
       S.fmg(H32);
       launch_f32_to_f64(H32.u[L], phi, n3, s);
@@ -1137,8 +1205,7 @@ int solve_impl(mg_ctx* c, const mg_params* p, const mg_bc* bc, const double* rho
         if (cyc + 1 < ncyc) S.head(H64, phys[L]);
         else S.defect_norm(phi, f64L, nullptr, p->n, p->dx, phys[L], scal + 2);
       } else if (!mixed && Lb >= 0) {
-        S.vcycle_blk(H64, L, phys[L]);
-        S.defect_norm(phi, f64L, nullptr, p->n, p->dx, phys[L], scal + 2);
+        if (!S.vcycle_blk(H64, L, phys[L], true)) S.defect_norm(phi, f64L, nullptr, p->n, p->dx, phys[L], scal + 2);
       } else if (mixed && Lb >= 0) {
         launch_zero(H32.u[L], n3 * sizeof(float), s);
         S.vcycle_blk(H32, L, hom);
@@ -1457,6 +1524,7 @@ int mg_tuning_get(const mg_ctx* c, char* buf, int cap) {
     if (c->tblock[q] >= 0) o << "tb " << (q ? "fp32" : "fp64") << " " << c->tblock[q] << "\n";
     if (c->blk_zmarch[q] >= 0) o << "blkz " << (q ? "fp32" : "fp64") << " " << c->blk_zmarch[q] << "\n";
     if (c->march[q] >= 0) o << "march " << (q ? "fp32" : "fp64") << " " << c->march[q] << "\n";
+    if (c->tile[q] >= 0) o << "tile " << (q ? "fp32" : "fp64") << " " << c->tile[q] << "\n";
   }
   const std::string t = o.str();
   if (buf && cap > 0) {
@@ -1477,12 +1545,13 @@ int mg_tuning_set(mg_ctx* c, const char* text) {
     if (line.empty()) continue;
     std::istringstream ls(line);
     std::string tag, prec;
-    if (line.rfind("tb ", 0) == 0 || line.rfind("blkz ", 0) == 0 || line.rfind("march ", 0) == 0) {
+    if (line.rfind("tb ", 0) == 0 || line.rfind("blkz ", 0) == 0 || line.rfind("march ", 0) == 0 ||
+        line.rfind("tile ", 0) == 0) {
       int v;
       const int vmax = line.rfind("march ", 0) == 0 ? 2 : 1;
       if (!(ls >> tag >> prec >> v) || (prec != "fp64" && prec != "fp32") || v < 0 || v > vmax)
         return fail(c, MG_ERR_INVALID_ARG, "bad tuning line: " + line);
-      add_misc.push_back({(tag == "tb" ? 4 : tag == "blkz" ? 6 : 8) + (prec == "fp64" ? 0 : 1), v});
+      add_misc.push_back({(tag == "tb" ? 4 : tag == "blkz" ? 6 : tag == "march" ? 8 : 10) + (prec == "fp64" ? 0 : 1), v});
       continue;
     }
     if (line.rfind("fusedmin ", 0) == 0 || line.rfind("tail ", 0) == 0) {
@@ -1522,7 +1591,8 @@ int mg_tuning_set(mg_ctx* c, const char* text) {
     else if (kv.first < 4) c->tail_top[kv.first - 2] = kv.second;
     else if (kv.first < 6) c->tblock[kv.first - 4] = kv.second;
     else if (kv.first < 8) c->blk_zmarch[kv.first - 6] = kv.second;
-    else c->march[kv.first - 8] = kv.second;
+    else if (kv.first < 10) c->march[kv.first - 8] = kv.second;
+    else c->tile[kv.first - 10] = kv.second;
   }
   return MG_OK;
 }
@@ -1606,6 +1676,23 @@ bool op_march(const mg_ctx* c, int n, int sweeps, const LevelBC& b) {
   return true;
 }
 
+// The region-tile and streaming up passes take the coarse correction's ghosts from the face
+// kinds alone (homogeneous conditions, no face values).
+bool hom_arrays_null(const LevelBC& b) {
+  for (int f = 0; f < 6; ++f)
+    if (b.b[f]) return false;
+  return true;
+}
+
+// Do the operator entry points run a V(2,2) leg of this level as one region-tile launch (the
+// context's "tile" setting, on the levels the solver uses them for: 32^3 .. 128^3, below the
+// streaming passes)?
+template <typename T>
+bool op_tile(const mg_ctx* c, int n, int sweeps) {
+  const int v = c->tile[sizeof(T) == 8 ? 0 : 1];
+  return (v < 0 || v == 1) && sweeps == 2 && n >= kTileMinN && n <= kTileMaxN && n < kFusedDefaultMinN;
+}
+
 // Down step (Alg. 1 steps 1-3) with the context's fusion schedule for this precision.
 template <typename T>
 int op_down(mg_ctx* c, int n, double h, double omega, int npre, const mg_level_bc* bc, T* u, const T* f, T* fc, T* uc,
@@ -1620,6 +1707,14 @@ int op_down(mg_ctx* c, int n, double h, double omega, int npre, const mg_level_b
     st = op_scratch(c, cells(ilog2(n)) * sizeof(T), &tmp);
     if (st) return st;
     march_down<T>(u, reinterpret_cast<T*>(tmp), f, fc, uc, n, h, omega, b, s);
+    HIP_CHECK(c, hipMemcpyAsync(u, tmp, cells(ilog2(n)) * sizeof(T), hipMemcpyDeviceToDevice, s));
+    return op_epilogue(c);
+  }
+  if (op_tile<T>(c, n, npre)) {
+    double* tmp = nullptr;
+    st = op_scratch(c, cells(ilog2(n)) * sizeof(T), &tmp);
+    if (st) return st;
+    tile_down<T>(u, reinterpret_cast<T*>(tmp), f, fc, uc, n, 0, 0, h, omega, b, s);
     HIP_CHECK(c, hipMemcpyAsync(u, tmp, cells(ilog2(n)) * sizeof(T), hipMemcpyDeviceToDevice, s));
     return op_epilogue(c);
   }
@@ -1657,11 +1752,19 @@ int op_up(mg_ctx* c, int n, double h, double omega, int npost, const mg_level_bc
   if (n < 2 || npost < 0 || npost > 4) return fail(c, MG_ERR_INVALID_ARG, "n >= 2, npost 0..4");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const LevelBC b = to_level_bc(bc), bcc = to_level_bc(bc_coarse);
-  if (op_march<T>(c, n, npost, b)) {
+  if (op_march<T>(c, n, npost, b) && hom_arrays_null(bcc)) {
     double* tmp = nullptr;
     st = op_scratch(c, cells(ilog2(n)) * sizeof(T), &tmp);
     if (st) return st;
     (void)march_up<T>(u, reinterpret_cast<T*>(tmp), f, uc, bcc, nullptr, n, h, omega, b, s);
+    HIP_CHECK(c, hipMemcpyAsync(u, tmp, cells(ilog2(n)) * sizeof(T), hipMemcpyDeviceToDevice, s));
+    return op_epilogue(c);
+  }
+  if (op_tile<T>(c, n, npost) && hom_arrays_null(bcc)) {
+    double* tmp = nullptr;
+    st = op_scratch(c, cells(ilog2(n)) * sizeof(T), &tmp);
+    if (st) return st;
+    (void)tile_up<T>(u, reinterpret_cast<T*>(tmp), f, uc, bcc, nullptr, n, 0, 0, h, omega, b, s);
     HIP_CHECK(c, hipMemcpyAsync(u, tmp, cells(ilog2(n)) * sizeof(T), hipMemcpyDeviceToDevice, s));
     return op_epilogue(c);
   }

@@ -18,9 +18,11 @@ constexpr int kMarchMinN = 128;
 // Down step of a V-cycle level (Alg. 1 steps 1-3) in one pass: two smoothing sweeps of u, the
 // defect of the result restricted into fc, and the coarse correction uc0 cleared.
 // uin == nullptr: u is zero on input and is not read.
+// Lm > 0: the level is in the MeshBlock layout with blocks of 2^Lm cells per side (the coarse
+// level below in the layout with blocks of 2^(Lm-1), or the dense root grid when Lm = 1).
 template <typename T>
 void march_down(const T* uin, T* uout, const T* f, T* fc, T* uc0, int n, double h, double omega, const LevelBC& bc,
-                hipStream_t s);
+                hipStream_t s, int Lm = 0);
 
 // Up step (Alg. 1 steps 5-7) in one pass: u += trilinear(ec) (ec's ghosts from bcc) as u is
 // loaded, then two smoothing sweeps.  part != nullptr: one partial sum of squared defects of
@@ -28,10 +30,11 @@ void march_down(const T* uin, T* uout, const T* f, T* fc, T* uc0, int n, double 
 // partials (0 without part).
 template <typename T>
 int march_up(const T* uin, T* uout, const T* f, const T* ec, const LevelBC& bcc, double* part, int n, double h,
-             double omega, const LevelBC& bc, hipStream_t s);
+             double omega, const LevelBC& bc, hipStream_t s, int Lm = 0);
 
-// Names of the kernels as the profiler lists them (per: every face periodic).
+// Names of the kernels as the profiler lists them (per: every face periodic; blk: MeshBlock
+// layout).
 template <typename T>
-std::string march_name(bool up, bool norm, bool per);
+std::string march_name(bool up, bool norm, bool per, bool blk = false);
 
 }  // namespace mg

@@ -1,4 +1,5 @@
-// mg_march.hip -- two-sweep streaming passes of the large levels (the bandwidth path).
+// mg_march.inl -- two-sweep streaming passes of the large levels (the bandwidth path); included
+// once per precision by mg_march_f64.hip and mg_march_f32.hip.
 //
 // One launch = the whole work of a V-cycle leg on one level, with u and f crossing HBM once:
 //   down (Alg. 1 steps 1-3): two red-black SOR sweeps (eqs. rbsor1-2), then the defect
@@ -69,6 +70,7 @@ struct MarchArgs {
   LevelBC bcc;       // up: coarse level (homogeneous)
   int n, L, xo, yo, zc, tiles_x, tiles_y, ntiles;
   int zero_in;
+  int Lm;            // BLK: log2 of the MeshBlock side on this level (the coarse level: Lm - 1)
   double h2, ih2, omega;
 };
 
@@ -147,8 +149,11 @@ constexpr int cfg_W() {
 }
 
 // PER: every face of the level is periodic (the launcher checks), so no boundary code is
-// compiled in.
-template <typename T, int W, bool UP, bool NORM, bool PER>
+// compiled in.  BLK: the level is in the MeshBlock layout (blocks of 2^A.Lm cells, Morton order);
+// the tile streams across block boundaries as across a dense array (an x-pair never straddles
+// two blocks), and the coarse level is in the layout below (blocks of 2^(A.Lm-1) cells, or the
+// dense root grid when that is one cell).
+template <typename T, int W, bool UP, bool NORM, bool PER, bool BLK>
 __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
   constexpr int R = kR, SL = kSL, NB = 2 * W, NT = kLanes * W;
   constexpr bool DEF = !UP;                       // down: restricted defect
@@ -176,6 +181,13 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
     const T* __restrict__ uin = reinterpret_cast<const T*>(A.uin);
     T* __restrict__ uout = reinterpret_cast<T*>(A.uout);
     const T* __restrict__ fin = reinterpret_cast<const T*>(A.f);
+    // storage index of cell (x, y, z) of this level and of the coarse level below
+    auto fidx = [&](int x, int y, int z) __attribute__((always_inline)) {
+      return BLK ? bidx(A.Lm, x, y, z) : cidx(L, x, y, z);
+    };
+    auto cdx = [&](int X, int Y, int Z) __attribute__((always_inline)) {
+      return BLK ? lidx(L - 1, A.Lm - 1, X, Y, Z) : cidx(L - 1, X, Y, Z);
+    };
     const bool px = PER || A.bc.kind[0] == BC_PERIODIC;
     const bool py = PER || A.bc.kind[2] == BC_PERIODIC;
     const bool pz = PER || A.bc.kind[4] == BC_PERIODIC;
@@ -247,13 +259,13 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if (in_x && in_y[r] && in_z && !A.zero_in) {
-          const Pair<T> vu = *reinterpret_cast<const Pair<T>*>(uin + cidx(L, xag, ygv[r], Pg));
+          const Pair<T> vu = *reinterpret_cast<const Pair<T>*>(uin + fidx(xag, ygv[r], Pg));
           pu[r][0] = vu.a; pu[r][1] = vu.b;
         } else {
           pu[r][0] = pu[r][1] = (T)0;
         }
         if (in_x && in_y[r] && in_zf) {
-          const Pair<T> vf = *reinterpret_cast<const Pair<T>*>(fin + cidx(L, xag, ygv[r], Pfg));
+          const Pair<T> vf = *reinterpret_cast<const Pair<T>*>(fin + fidx(xag, ygv[r], Pfg));
           pf[r][0] = vf.a; pf[r][1] = vf.b;
         } else {
           pf[r][0] = pf[r][1] = (T)0;
@@ -296,13 +308,13 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
           if (pz) zz &= nc - 1;
           // every face periodic: the wrapped indices are in range (no ghost code compiled)
           if constexpr (PER) {
-            return ec[cidx(Lc, X, Y, zz)];
+            return ec[cdx(X, Y, zz)];
           } else {
             T sg = (T)1;
             const int Xc = clamp_tap<T>(X, nc, A.bcc, 0, sg);
             const int Yc = clamp_tap<T>(Y, nc, A.bcc, 2, sg);
             const int Zc = clamp_tap<T>(zz, nc, A.bcc, 4, sg);
-            return sg * ec[cidx(Lc, Xc, Yc, Zc)];
+            return sg * ec[cdx(Xc, Yc, Zc)];
           }
         };
         if (first || (P & 1)) {
@@ -512,7 +524,7 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
             stash[j] = sprev;
           } else {
             if (out_prev && out_x && out_y[2 * j]) {
-              const size_t ci = cidx(L - 1, xag >> 1, ygv[2 * j] >> 1, (p - 1) >> 1);
+              const size_t ci = cdx(xag >> 1, ygv[2 * j] >> 1, (p - 1) >> 1);
               fcp[ci] = (stash[j] + sprev) * (T)0.125;
               ucp[ci] = (T)0;
             }
@@ -565,7 +577,7 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
             if (out_y[r]) {
               typedef T ntv2 __attribute__((ext_vector_type(2)));
               const ntv2 v = {u[s4][r][0], u[s4][r][1]};
-              __builtin_nontemporal_store(v, reinterpret_cast<ntv2*>(uout + cidx(L, xag, ygv[r], pg)));
+              __builtin_nontemporal_store(v, reinterpret_cast<ntv2*>(uout + fidx(xag, ygv[r], pg)));
             }
         }
       }
@@ -626,7 +638,7 @@ int march_zchunk(int n, int tiles_xy, int hz) {
   return best;
 }
 
-template <typename T, bool UP, bool NORM>
+template <typename T, bool UP, bool NORM, bool BLK>
 int launch_march(MarchArgs A, hipStream_t s) {
   bool per = true;
   for (int f = 0; f < 6; ++f) per = per && A.bc.kind[f] == BC_PERIODIC;
@@ -641,8 +653,8 @@ int launch_march(MarchArgs A, hipStream_t s) {
   const int chunks = (A.n + A.zc - 1) / A.zc;
   A.ntiles = A.tiles_x * A.tiles_y * chunks;
   const int grid = (A.ntiles + 7) / 8 * 8;
-  if (per) hipLaunchKernelGGL((k_march<T, W, UP, NORM, true>), dim3(grid), dim3(kLanes * W), 0, s, A);
-  else hipLaunchKernelGGL((k_march<T, W, UP, NORM, false>), dim3(grid), dim3(kLanes * W), 0, s, A);
+  if (per) hipLaunchKernelGGL((k_march<T, W, UP, NORM, true, BLK>), dim3(grid), dim3(kLanes * W), 0, s, A);
+  else hipLaunchKernelGGL((k_march<T, W, UP, NORM, false, BLK>), dim3(grid), dim3(kLanes * W), 0, s, A);
   return grid;
 }
 
@@ -666,40 +678,47 @@ MarchArgs base_args(const T* uin, T* uout, const T* f, int n, double h, double o
 
 template <typename T>
 void march_down(const T* uin, T* uout, const T* f, T* fc, T* uc0, int n, double h, double omega, const LevelBC& bc,
-                hipStream_t s) {
+                hipStream_t s, int Lm) {
   MarchArgs A = base_args(uin, uout, f, n, h, omega, bc);
   A.fc = fc;
   A.uc0 = uc0;
-  launch_march<T, false, false>(A, s);
+  A.Lm = Lm;
+  if (Lm > 0) launch_march<T, false, false, true>(A, s);
+  else launch_march<T, false, false, false>(A, s);
 }
 
 template <typename T>
 int march_up(const T* uin, T* uout, const T* f, const T* ec, const LevelBC& bcc, double* part, int n, double h,
-             double omega, const LevelBC& bc, hipStream_t s) {
+             double omega, const LevelBC& bc, hipStream_t s, int Lm) {
   MarchArgs A = base_args(uin, uout, f, n, h, omega, bc);
   A.ec = ec;
   A.bcc = bcc;
   A.part = part;
-  if (part) return launch_march<T, true, true>(A, s);
-  launch_march<T, true, false>(A, s);
+  A.Lm = Lm;
+  if (Lm > 0) {
+    if (part) return launch_march<T, true, true, true>(A, s);
+    launch_march<T, true, false, true>(A, s);
+    return 0;
+  }
+  if (part) return launch_march<T, true, true, false>(A, s);
+  launch_march<T, true, false, false>(A, s);
   return 0;
 }
 
 template <typename T>
-std::string march_name(bool up, bool norm, bool per) {
+std::string march_name(bool up, bool norm, bool per, bool blk) {
+  auto b = [](bool v) { return std::string(v ? "true" : "false"); };
   return std::string("k_march<") + (sizeof(T) == 8 ? "double" : "float") + ", " + std::to_string(cfg_W<T>()) + ", " +
-         (up ? "true" : "false") + ", " + (up && norm ? "true" : "false") + ", " + (per ? "true" : "false") + ">";
+         b(up) + ", " + b(up && norm) + ", " + b(per) + ", " + b(blk) + ">";
 }
 
-template void march_down<double>(const double*, double*, const double*, double*, double*, int, double, double,
-                                 const LevelBC&, hipStream_t);
-template void march_down<float>(const float*, float*, const float*, float*, float*, int, double, double,
-                                const LevelBC&, hipStream_t);
-template int march_up<double>(const double*, double*, const double*, const double*, const LevelBC&, double*, int,
-                              double, double, const LevelBC&, hipStream_t);
-template int march_up<float>(const float*, float*, const float*, const float*, const LevelBC&, double*, int, double,
-                             double, const LevelBC&, hipStream_t);
-template std::string march_name<double>(bool, bool, bool);
-template std::string march_name<float>(bool, bool, bool);
+#ifndef MG_MARCH_T
+#error "define MG_MARCH_T (the precision this translation unit instantiates)"
+#endif
+template void march_down<MG_MARCH_T>(const MG_MARCH_T*, MG_MARCH_T*, const MG_MARCH_T*, MG_MARCH_T*, MG_MARCH_T*, int,
+                                     double, double, const LevelBC&, hipStream_t, int);
+template int march_up<MG_MARCH_T>(const MG_MARCH_T*, MG_MARCH_T*, const MG_MARCH_T*, const MG_MARCH_T*, const LevelBC&,
+                                  double*, int, double, double, const LevelBC&, hipStream_t, int);
+template std::string march_name<MG_MARCH_T>(bool, bool, bool, bool);
 
 }  // namespace mg

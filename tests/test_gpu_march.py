@@ -1,4 +1,5 @@
-"""The two-sweep streaming passes (one pass per V(2,2) leg of a large level) against the oracle.
+"""The one-launch V(2,2) legs against the oracle: the two-sweep streaming passes of the large
+levels and the region-tile legs of the small ones (32^3 .. 128^3).
 
 Down pass: two sweeps, then the defect restricted to the coarse level (and the coarse
 correction cleared); up pass: the trilinear correction added as u is loaded, then two sweeps.
@@ -76,6 +77,9 @@ def scale_u(u, ref, f, h, bext):
 
 
 CASES = [(128, ks) for ks in range(len(KIND_SETS))] + [(256, 0), (512, 0), (512, 3)]
+# region-tile legs: 32^3 (one region per 16 x 16 x 8 block, wrapping halos), 64^3, and 128^3 with
+# the streaming passes off
+TILE_CASES = [(32, ks) for ks in range(len(KIND_SETS))] + [(64, 0), (64, 4), (128, 3)]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -179,3 +183,91 @@ def test_tolerance_stop_with_march(mg, n):
     torch.cuda.synchronize()
     assert st == rst == mg.MG_OK and len(hist) == len(rh), (hist, rh)
     assert rel(phi.cpu().numpy(), ref) < 1e-10
+
+
+def tile_ctx(mg, prec):
+    ctx = mg.Context(0)
+    ctx.set_tuning(f"march {prec} 0\n")
+    return ctx
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n,ks", TILE_CASES)
+def test_tile_down(mg, n, ks, prec):
+    kinds = KIND_SETS[ks]
+    f32 = prec == "fp32"
+    print(f"tile down n={n} kinds={kinds} {prec}", flush=True)
+    u, f, bext = make(n, 400 + n + ks, kinds, f32)
+    h = 1.0 / n
+    ref = oracle.smooth(oracle.smooth(u, f, h, OMEGA, kinds, bext), f, h, OMEGA, kinds, bext)
+    ref_fc = oracle.restrict(oracle.defect(ref, f, h, kinds, bext))
+    dt = torch.float32 if f32 else torch.float64
+    du = dev(u.astype(np.float32) if f32 else u)
+    df = dev(f.astype(np.float32) if f32 else f)
+    fc = torch.full((n // 2,) * 3, 7.0, dtype=dt, device="cuda:0")
+    uc = torch.full((n // 2,) * 3, 7.0, dtype=dt, device="cuda:0")
+    (mg.mg_op_down_f32 if f32 else mg.mg_op_down)(du, df, fc, uc, h, OMEGA, 2, kinds, dbext(bext),
+                                                  ctx=tile_ctx(mg, prec))
+    got, got_fc = host(du).astype(np.float64), host(fc).astype(np.float64)
+    s = scale_u(u, ref, f, h, bext)
+    ds = float(np.abs(f).max() + 12 * s / h ** 2)
+    bu, bf = (40 * EPS32 * s, 40 * EPS32 * ds) if f32 else (TOL64 * s, TOL64 * ds)
+    assert float(np.max(np.abs(got - ref))) <= bu, (np.max(np.abs(got - ref)), bu)
+    assert float(np.max(np.abs(got_fc - ref_fc))) <= bf, (np.max(np.abs(got_fc - ref_fc)), bf)
+    assert float(uc.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n,ks", TILE_CASES)
+def test_tile_up(mg, n, ks, prec):
+    kinds = KIND_SETS[ks]
+    hom = [k if k in (PERIODIC, ZERO_GRADIENT) else FIXED for k in kinds]
+    f32 = prec == "fp32"
+    print(f"tile up n={n} kinds={kinds} {prec}", flush=True)
+    u, f, bext = make(n, 500 + n + ks, kinds, f32)
+    h = 1.0 / n
+    rng = np.random.default_rng(600 + n + ks)
+    e = rng.standard_normal((n // 2,) * 3)
+    if f32:
+        e = e.astype(np.float32).astype(np.float64)
+    ref = oracle.prolong_add(e, u, hom)
+    ref = oracle.smooth(oracle.smooth(ref, f, h, OMEGA, kinds, bext), f, h, OMEGA, kinds, bext)
+    du = dev(u.astype(np.float32) if f32 else u)
+    df = dev(f.astype(np.float32) if f32 else f)
+    de = dev(e.astype(np.float32) if f32 else e)
+    (mg.mg_op_up_f32 if f32 else mg.mg_op_up)(du, df, de, h, OMEGA, 2, kinds, dbext(bext), kinds_coarse=hom,
+                                              ctx=tile_ctx(mg, prec))
+    got = host(du).astype(np.float64)
+    s = scale_u(u, ref, f, h, bext) + float(np.abs(e).max())
+    bound = 40 * EPS32 * s if f32 else TOL64 * s
+    assert float(np.max(np.abs(got - ref))) <= bound, (np.max(np.abs(got - ref)), bound)
+
+
+@pytest.mark.parametrize("n,kinds", [(32, "periodic"), (64, [FIXED] * 6), (128, [ZERO_GRADIENT] * 6),
+                                     (64, [FIXED, ZERO_GRADIENT, ZERO_GRADIENT, FIXED, PERIODIC, PERIODIC])])
+def test_solve_with_tiles_matches_oracle(mg, n, kinds):
+    """Whole FP64 solves with the region-tile legs on the levels 32^3 .. 128^3 (the default): phi
+    and the residual history (the finest up leg's norm) cycle by cycle against the oracle, and
+    against the per-operator launches."""
+    print(f"tile solve n={n} kinds={kinds}", flush=True)
+    gauge_free = kinds == "periodic" or kinds == [ZERO_GRADIENT] * 6
+    rho = wl.gaussian_clumps(n, 99, remove_mean=gauge_free)
+    faces = None
+    if not gauge_free:
+        rng = np.random.default_rng(7)
+        faces = [rng.standard_normal((n, n)) * 0.1 if k == FIXED else None for k in kinds]
+    ref, rh, _ = oracle.solve(rho, 1.0 / n, kinds, fixed_b=faces, fixed_cycles=5)
+    dfaces = None if faces is None else [None if b is None else dev(b) for b in faces]
+    out = {}
+    for mode in (1, 0):
+        ctx = mg.Context(0)
+        ctx.set_tuning(f"tile fp64 {mode}\n")
+        phi, hist, st = mg.solve(dev(rho), 1.0 / n, kinds, fixed_b=dfaces, fixed_cycles=5, ctx=ctx)
+        torch.cuda.synchronize()
+        assert st == mg.MG_OK
+        out[mode] = phi.cpu().numpy()
+        assert rel(out[mode], ref) < 1e-10, (mode, rel(out[mode], ref))
+        fl = floor_of(ref, rho, gauge_free)
+        for a, b in zip(hist, rh):
+            assert abs(a - b) <= 1e-6 * b + 10 * fl, (mode, hist, rh)
+    assert rel(out[1], out[0]) < 1e-12
