@@ -362,11 +362,19 @@ struct Solver {
   bool march_on(const Hier<T>& H, int l, const LevelBC& bc) const {
     const int mode = c->march[sizeof(T) == 8 ? 0 : 1] < 0 ? 1 : c->march[sizeof(T) == 8 ? 0 : 1];
     if (mode == 0 || !use_fused || !H.u2[l] || l == H.T_top || Lb >= 0 || H.npre != 2 || H.npost != 2) return false;
-    if ((1 << l) < std::max(kMarchMinN, sizeof(T) == 8 ? fused_min_n64 : fused_min_n32) || tblock_on<T>()) return false;
+    if ((1 << l) < march_min<T>() || tblock_on<T>()) return false;
     if (mode == 1)
       for (int f = 0; f < 6; ++f)
         if (bc.kind[f] != BC_PERIODIC) return false;
     return true;
+  }
+
+  // Smallest level side on which the two-sweep passes run: kMarchMinN, or the one-sweep
+  // passes' threshold when that was set larger.
+  template <typename T>
+  int march_min() const {
+    const int v = c->fused_min_n[sizeof(T) == 8 ? 0 : 1];
+    return v > 0 ? std::max(kMarchMinN, v) : kMarchMinN;
   }
 
   // May a MeshBlock level run the two-sweep streaming passes (the "march" setting for its faces)?
@@ -777,7 +785,8 @@ struct Solver {
     }
     const int Lm = l - Lb;
     const int nl = 1 << l;
-    const bool big = blk_zmarch_on<T>(l) && nl >= kMarchMinN && march_blk_on<T>(H, bc);
+    const int vz = c->blk_zmarch[sizeof(T) == 8 ? 0 : 1];
+    const bool big = vz != 0 && nl >= march_min<T>() && march_blk_on<T>(H, bc);
     if ((big || tile_on<T>(H, l)) && H.npre == 2 && H.npost == 2) {
       // each leg of the block level in one launch over all blocks: the two-sweep streaming
       // passes on the large levels, region tiles below
@@ -788,14 +797,15 @@ struct Solver {
       if (timed) kernel_begin();
       if (big) march_down<T>(H.u[l], H.u2[l], H.f[l], H.f[l - 1], H.u[l - 1], nl, H.h[l], H.omega, bc, s, Lm);
       else tile_down<T>(H.u[l], H.u2[l], H.f[l], H.f[l - 1], H.u[l - 1], nl, Lm, Lb, H.h[l], H.omega, bc, s);
-      if (timed) kernel_end(big ? march_name<T>(false, false, per, true) : tile_name<T>(false, false), 3 * cellsT + cellsT / 4);
+      if (timed) kernel_end(big ? march_name<T>(false, false, per, true) : tile_name<T>(false, false, true),
+                            3 * cellsT + cellsT / 4);
       vcycle_blk(H, l - 1, H.hom);
       double* npart = want_norm && sizeof(T) == 8 ? part : nullptr;
       if (timed) kernel_begin();
       const int np = big ? march_up<T>(H.u2[l], H.u[l], H.f[l], H.u[l - 1], H.hom, npart, nl, H.h[l], H.omega, bc, s, Lm)
                          : tile_up<T>(H.u2[l], H.u[l], H.f[l], H.u[l - 1], H.hom, npart, nl, Lm, Lb, H.h[l], H.omega, bc, s);
       if (timed)
-        kernel_end(big ? march_name<T>(true, npart != nullptr, per, true) : tile_name<T>(true, npart != nullptr),
+        kernel_end(big ? march_name<T>(true, npart != nullptr, per, true) : tile_name<T>(true, npart != nullptr, true),
                    3 * cellsT + cellsT / 8);
       if (npart) launch_sum_partials(part, np, scal + 2, s);
       return npart != nullptr;

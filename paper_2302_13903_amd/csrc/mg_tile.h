@@ -31,6 +31,6 @@ int tile_up(const T* uin, T* uout, const T* f, const T* ec, const LevelBC& bcc, 
             double h, double omega, const LevelBC& bc, hipStream_t s);
 
 template <typename T>
-std::string tile_name(bool up, bool norm);
+std::string tile_name(bool up, bool norm, bool blk = false);
 
 }  // namespace mg

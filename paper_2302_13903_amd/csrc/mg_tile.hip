@@ -23,6 +23,7 @@
 #include "mg_tile.h"
 
 #include <cstring>
+#include <type_traits>
 
 #include "mg_launch.h"
 
@@ -64,18 +65,21 @@ __device__ __forceinline__ T wall(const LevelBC& bc, int face, int n, int t1, in
   return (T)(2.0 * face_b(bc, face, n, t1, t2)) - uc;
 }
 
-// Storage index of cell (i, j, k) (in range) of this level and of the coarse level below.
+// Storage index of cell (i, j, k) (in range) of this level (BLK: MeshBlock layout) and of the
+// coarse level below.
+template <bool BLK>
 __device__ __forceinline__ size_t fine_at(const TileArgs& A, int i, int j, int k) {
-  return A.Lm > 0 ? bidx(A.Lm, i, j, k) : cidx(A.L, i, j, k);
+  return BLK ? bidx(A.Lm, i, j, k) : cidx(A.L, i, j, k);
 }
+template <bool BLK>
 __device__ __forceinline__ size_t coarse_idx(const TileArgs& A, int I, int J, int K) {
-  return A.Lm > 1 ? bidx(A.Lm - 1, I, J, K) : cidx(A.L - 1, I, J, K);
+  return BLK && A.Lm > 1 ? bidx(A.Lm - 1, I, J, K) : cidx(A.L - 1, I, J, K);
 }
 
 // Coarse correction at (I, J, K) under homogeneous conditions: periodic indices wrap; on the
 // other axes an index beyond the domain takes the boundary cell with the face's sign (+1 zero
 // gradient, -1 zero-fixed), axis by axis (edges and corners: the product of the signs).
-template <typename T>
+template <typename T, bool BLK>
 __device__ __forceinline__ T coarse_hom(const TileArgs& A, const T* __restrict__ ec, int I, int J, int K) {
   const int nc = A.n >> 1, ncm = nc - 1;
   T s = (T)1;
@@ -92,10 +96,10 @@ __device__ __forceinline__ T coarse_hom(const TileArgs& A, const T* __restrict__
     return v;
   };
   const int Ic = axis(I, 1, 0), Jc = axis(J, 2, 2), Kc = axis(K, 4, 4);
-  return s * ec[coarse_idx(A, Ic, Jc, Kc)];
+  return s * ec[coarse_idx<BLK>(A, Ic, Jc, Kc)];
 }
 
-template <typename T, bool UP, bool NORM>
+template <typename T, bool UP, bool NORM, bool BLK>
 __global__ void __launch_bounds__(kThreads) k_tile_leg(TileArgs A) {
   __shared__ T tile[TV];
   __shared__ T ctile[UP ? CV : 1];
@@ -120,14 +124,14 @@ __global__ void __launch_bounds__(kThreads) k_tile_leg(TileArgs A) {
   for (int q = tid; q < TV; q += kThreads) {
     const int tx = q % WX, ty = (q / WX) % WY, tz = q / (WX * WY);
     const int i = wrap(ox + tx - H, 1), j = wrap(oy + ty - H, 2), k = wrap(oz + tz - H, 4);
-    tile[q] = (i >= 0 && j >= 0 && k >= 0) ? uin[fine_at(A, i, j, k)] : (T)0;
+    tile[q] = (i >= 0 && j >= 0 && k >= 0) ? uin[fine_at<BLK>(A, i, j, k)] : (T)0;
   }
   if constexpr (UP) {
     const T* __restrict__ ec = reinterpret_cast<const T*>(A.ec);
     const int cx0 = (ox >> 1) - 4, cy0 = (oy >> 1) - 4, cz0 = (oz >> 1) - 4;
     for (int q = tid; q < CV; q += kThreads) {
       const int cx = q % CX, cy = (q / CX) % CY, cz = q / (CX * CY);
-      ctile[q] = coarse_hom(A, ec, cx0 + cx, cy0 + cy, cz0 + cz);
+      ctile[q] = coarse_hom<T, BLK>(A, ec, cx0 + cx, cy0 + cy, cz0 + cz);
     }
     __syncthreads();
     // trilinear prolongation (weights 1/4, 3/4 per axis; the even child is the lower one)
@@ -153,12 +157,13 @@ __global__ void __launch_bounds__(kThreads) k_tile_leg(TileArgs A) {
   }
   __syncthreads();
 
-  // ---- four colour passes (red, black, red, black) on the region plus a shrinking ring
-#pragma unroll 1
-  for (int pass = 0; pass < 4; ++pass) {
-    const int colour = pass & 1, ring = 4 - pass;
-    const int sx = DX + 2 * ring, sy = DY + 2 * ring, sz = DZ + 2 * ring, hx = sx >> 1;
-    const int cnt = hx * sy * sz;
+  // ---- four colour passes (red, black, red, black) on the region plus a shrinking ring (each
+  // pass's extents are compile-time, so the index arithmetic divides by constants)
+  auto pass_of = [&](auto cpass) __attribute__((always_inline)) {
+    constexpr int pass = decltype(cpass)::value;
+    constexpr int colour = pass & 1, ring = 4 - pass;
+    constexpr int sx = DX + 2 * ring, sy = DY + 2 * ring, sz = DZ + 2 * ring, hx = sx >> 1;
+    constexpr int cnt = hx * sy * sz;
     for (int q = tid; q < cnt; q += kThreads) {
       const int row = q / hx, xi = q - row * hx;
       const int ry2 = row % sy, rz2 = row / sy;
@@ -175,10 +180,14 @@ __global__ void __launch_bounds__(kThreads) k_tile_leg(TileArgs A) {
       const T zm = (!(per & 4) && k == 0) ? wall(A.bc, 4, n, i, j, uc) : tile[p - WX * WY];
       const T zp = (!(per & 4) && k == nm) ? wall(A.bc, 5, n, i, j, uc) : tile[p + WX * WY];
       const T nb = ((((xm + xp) + ym) + yp) + zm) + zp;
-      tile[p] = uc + omega * ((nb - h2 * fin[fine_at(A, i, j, k)]) * inv6 - uc);
+      tile[p] = uc + omega * ((nb - h2 * fin[fine_at<BLK>(A, i, j, k)]) * inv6 - uc);
     }
     __syncthreads();
-  }
+  };
+  pass_of(std::integral_constant<int, 0>{});
+  pass_of(std::integral_constant<int, 1>{});
+  pass_of(std::integral_constant<int, 2>{});
+  pass_of(std::integral_constant<int, 3>{});
 
   // defect of region cell (x, y, z) (region-local), from the final tile
   auto defect_at = [&](int x, int y, int z) __attribute__((always_inline)) {
@@ -192,7 +201,7 @@ __global__ void __launch_bounds__(kThreads) k_tile_leg(TileArgs A) {
     const T zm = (!(per & 4) && k == 0) ? wall(A.bc, 4, n, i, j, uc) : tile[p - WX * WY];
     const T zp = (!(per & 4) && k == nm) ? wall(A.bc, 5, n, i, j, uc) : tile[p + WX * WY];
     const T nb = ((((xm + xp) + ym) + yp) + zm) + zp;
-    return fin[fine_at(A, i, j, k)] - (nb - (T)6 * uc) * ih2;
+    return fin[fine_at<BLK>(A, i, j, k)] - (nb - (T)6 * uc) * ih2;
   };
 
   if constexpr (!UP) {
@@ -208,7 +217,7 @@ __global__ void __launch_bounds__(kThreads) k_tile_leg(TileArgs A) {
         for (int b = 0; b < 2; ++b)
 #pragma unroll
           for (int a = 0; a < 2; ++a) s += defect_at(2 * cx + a, 2 * cy + b, 2 * cz + c);
-      const size_t ci = coarse_idx(A, (ox >> 1) + cx, (oy >> 1) + cy, (oz >> 1) + cz);
+      const size_t ci = coarse_idx<BLK>(A, (ox >> 1) + cx, (oy >> 1) + cy, (oz >> 1) + cz);
       fc[ci] = s * (T)0.125;
       uc0[ci] = (T)0;
     }
@@ -217,7 +226,7 @@ __global__ void __launch_bounds__(kThreads) k_tile_leg(TileArgs A) {
   // ---- the region back to memory (and, for the norm, its defects)
   for (int q = tid; q < DX * DY * DZ; q += kThreads) {
     const int x = q % DX, y = (q / DX) % DY, z = q / (DX * DY);
-    uout[fine_at(A, ox + x, oy + y, oz + z)] = tile[((z + H) * WY + (y + H)) * WX + (x + H)];
+    uout[fine_at<BLK>(A, ox + x, oy + y, oz + z)] = tile[((z + H) * WY + (y + H)) * WX + (x + H)];
     if constexpr (UP && NORM) {
       const T d = defect_at(x, y, z);
       acc += (double)d * (double)d;
@@ -266,7 +275,8 @@ void tile_down(const T* uin, T* uout, const T* f, T* fc, T* uc0, int n, int Lm, 
   TileArgs A = base_args(uin, uout, f, n, Lm, h, omega, bc);
   A.fc = fc;
   A.uc0 = uc0;
-  hipLaunchKernelGGL((k_tile_leg<T, false, false>), dim3(regions(n)), dim3(kThreads), 0, s, A);
+  if (Lm > 0) hipLaunchKernelGGL((k_tile_leg<T, false, false, true>), dim3(regions(n)), dim3(kThreads), 0, s, A);
+  else hipLaunchKernelGGL((k_tile_leg<T, false, false, false>), dim3(regions(n)), dim3(kThreads), 0, s, A);
 }
 
 template <typename T>
@@ -278,17 +288,20 @@ int tile_up(const T* uin, T* uout, const T* f, const T* ec, const LevelBC& bcc, 
   A.bcc = bcc;
   A.part = part;
   if (part) {
-    hipLaunchKernelGGL((k_tile_leg<T, true, true>), dim3(regions(n)), dim3(kThreads), 0, s, A);
+    if (Lm > 0) hipLaunchKernelGGL((k_tile_leg<T, true, true, true>), dim3(regions(n)), dim3(kThreads), 0, s, A);
+    else hipLaunchKernelGGL((k_tile_leg<T, true, true, false>), dim3(regions(n)), dim3(kThreads), 0, s, A);
     return regions(n);
   }
-  hipLaunchKernelGGL((k_tile_leg<T, true, false>), dim3(regions(n)), dim3(kThreads), 0, s, A);
+  if (Lm > 0) hipLaunchKernelGGL((k_tile_leg<T, true, false, true>), dim3(regions(n)), dim3(kThreads), 0, s, A);
+  else hipLaunchKernelGGL((k_tile_leg<T, true, false, false>), dim3(regions(n)), dim3(kThreads), 0, s, A);
   return 0;
 }
 
 template <typename T>
-std::string tile_name(bool up, bool norm) {
-  return std::string("k_tile_leg<") + (sizeof(T) == 8 ? "double" : "float") + ", " + (up ? "true" : "false") + ", " +
-         (up && norm ? "true" : "false") + ">";
+std::string tile_name(bool up, bool norm, bool blk) {
+  auto b = [](bool v) { return std::string(v ? "true" : "false"); };
+  return std::string("k_tile_leg<") + (sizeof(T) == 8 ? "double" : "float") + ", " + b(up) + ", " + b(up && norm) + ", " +
+         b(blk) + ">";
 }
 
 template void tile_down<double>(const double*, double*, const double*, double*, double*, int, int, int, double, double,
@@ -299,7 +312,7 @@ template int tile_up<double>(const double*, double*, const double*, const double
                              int, double, double, const LevelBC&, hipStream_t);
 template int tile_up<float>(const float*, float*, const float*, const float*, const LevelBC&, double*, int, int, int,
                             double, double, const LevelBC&, hipStream_t);
-template std::string tile_name<double>(bool, bool);
-template std::string tile_name<float>(bool, bool);
+template std::string tile_name<double>(bool, bool, bool);
+template std::string tile_name<float>(bool, bool, bool);
 
 }  // namespace mg
