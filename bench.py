@@ -89,15 +89,18 @@ def measured_traffic(kernel: str, n: int):
     return None if entry is None else entry.get("bytes_per_launch")
 
 
-def run_solves(mg, ctx, rho, n, precision, steps, warmup, tol, scheme="cs"):
+def run_solves(mg, ctx, rho, n, precision, steps, warmup, tol, scheme="cs", bc="periodic", fixed_b=None,
+               label="C2"):
+    """`warmup` + `steps` solves; returns latencies, the V-cycle times of the timed solves (HIP
+    events in the library), their histories, kernel timings and the last phi."""
     import torch
     phi = torch.zeros_like(rho)
     lat, cyc, hists, kt = [], [], [], []
     for it in range(warmup + steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        phi, hist, st = mg.solve(rho, 1.0 / n, "periodic", tol=tol, precision=precision, phi=phi, ctx=ctx,
-                                 scheme=scheme)
+        phi, hist, st = mg.solve(rho, 1.0 / n, bc, fixed_b=fixed_b, lmax=4, tol=tol, precision=precision, phi=phi,
+                                 ctx=ctx, scheme=scheme)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         if st < 0 or hist[-1] > tol:
@@ -108,9 +111,17 @@ def run_solves(mg, ctx, rho, n, precision, steps, warmup, tol, scheme="cs"):
             cyc.extend(cms)
             hists.append(hist)
             kt.append(ctx.kernel_timing())
-        print(f"# {precision} {scheme} step {it - warmup:+d}: {1e3 * (t1 - t0):.2f} ms, cycles {len(hist) - 1}, "
-              f"r = {hist[-1]:.2e}", file=sys.stderr, flush=True)
-    return lat, cyc, hists, kt
+        print(f"# {label} {bc} {precision} {scheme} step {it - warmup:+d}: {1e3 * (t1 - t0):.2f} ms, "
+              f"cycles {len(hist) - 1}, r = {hist[-1]:.2e}", file=sys.stderr, flush=True)
+    return lat, cyc, hists, kt, phi
+
+
+def phi_error(phi, ref):
+    """Relative L2 and max-norm difference of two device fields."""
+    import torch
+    d = phi - ref
+    return {"rel_l2": float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(ref)),
+            "rel_max": float(d.abs().max() / ref.abs().max())}
 
 
 FUSED_BYTES_PER_DOF = 57.0   # fully fused V(2,2) cycle, FP64: 50 B per finest cell x 8/7 for all levels
@@ -125,21 +136,24 @@ def v_cycle_efficiency(n: int, t_v_ms: float):
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS}
 
 
-def v_cycle_counted(passes, cycles: int, n: int, t_v_ms: float):
-    """The V-cycle against HBM bytes counted by the profiler: the finest-level passes' FETCH +
-    WRITE bytes per launch (the committed counter summary) times their launches per cycle, times
-    8/7 for the coarser levels (each has an eighth of the cells of the one above); None without
-    a current counter summary for every pass."""
-    tot = 0.0
-    for q in passes:
-        t = measured_traffic(q["kernel"], n)
-        if t is None:
-            return None
-        tot += t * q["launches"]
-    per_cycle = tot / max(cycles, 1) * 8.0 / 7.0
+def v_cycle_counted(n: int, t_v_ms: float):
+    """The V-cycle against the HBM bytes the profiler counted for whole V-cycles: FETCH + WRITE
+    summed over every kernel dispatched from one finest-level down pass to the next (all levels,
+    the tail and the norm reduction), averaged over the cycles of the profiled FP64 solves (the
+    committed counter summary); None when it is missing or the kernel sources changed."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    vc = t.get("v_cycle", {}).get(str(n))
+    if t.get("source_hash") != kernel_source_hash() or vc is None:
+        return None
+    per_cycle = vc["bytes_per_cycle"]
     achieved = per_cycle / (t_v_ms * 1e-3) / 1e9
-    return {"bytes_per_cycle": per_cycle, "v_cycle_ms": t_v_ms, "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS}
+    return {"bytes_per_cycle": per_cycle, "cycles_counted": vc["cycles"], "v_cycle_ms": t_v_ms, "achieved": achieved,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "over_algorithmic": per_cycle / (FUSED_BYTES_PER_DOF * n ** 3)}
 
 
 def pass_table(kt):
@@ -159,24 +173,58 @@ def pass_table(kt):
     return passes
 
 
-def cpu_baseline(n: int, cycles: int = 3):
-    """The CPU oracle on a bounded sample: set-up plus `cycles` V(2,2) cycles from zero on the
-    same n^3 clump density; GDoF/s per V-cycle = n^3 / mean cycle time."""
+def cpu_baseline(n: int, cycles: int = 3, c3=None):
+    """The CPU oracle on bounded samples, V(2,2) cycles from zero after its set-up (FMG not
+    timed); GDoF/s per V-cycle = n^3 / mean cycle time.  The headline figure is configuration 2
+    (the same n^3 clump density as the GPU leg) on all the host threads the oracle's OpenMP
+    runtime gets; `rows` adds that configuration on one thread and configurations 1, 3
+    (`c3` = (rho, faces) of the sphere leg, fixed faces) and 4 (the 256^3 lognormal field as one
+    dense grid: the MeshBlock form is the same algorithm) on all threads."""
     import numpy as np
 
     import oracle
     import workloads as wl
+    nproc = oracle.num_threads()
+
+    def rate(rho, kinds, faces, k, threads):
+        oracle.set_threads(threads)
+        m = rho.shape[0]
+        st = oracle.State(rho, 1.0 / m, kinds, fixed_b=faces)
+        st.set_phi(np.zeros_like(rho))
+        t0 = time.perf_counter()
+        for _ in range(k):
+            st.vcycle()
+        dt = (time.perf_counter() - t0) / k
+        del st
+        return m ** 3 / dt / 1e9, dt
+
+    rows = []
+
+    def row(config, rho, kinds, faces, k, threads, what):
+        v, dt = rate(rho, kinds, faces, k, threads)
+        rows.append({"config": config, "threads": threads, "value": v, "unit": "GDoF/s per V-cycle",
+                     "sample": f"{what}, {k} V(2,2) cycles from zero, {dt * 1e3:.0f} ms per cycle"})
+        print(f"# cpu oracle {config} on {threads} threads: {v:.4f} GDoF/s per V-cycle", file=sys.stderr,
+              flush=True)
+        return v, dt
+
     rho = wl.gaussian_clumps(n, 2)
-    st = oracle.State(rho, 1.0 / n, "periodic")
-    st.set_phi(np.zeros_like(rho))
-    t0 = time.perf_counter()
-    for _ in range(cycles):
-        st.vcycle()
-    dt = (time.perf_counter() - t0) / cycles
-    return {"value": n ** 3 / dt / 1e9, "unit": "GDoF/s per V-cycle", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{n}^3 clump density, {cycles} V(2,2) cycles from zero (FMG not timed), "
-                      f"{dt * 1e3:.0f} ms per cycle"}
+    v, dt = row("C2", rho, "periodic", None, cycles, nproc, f"{n}^3 clump density")
+    out = {"value": v, "unit": "GDoF/s per V-cycle", "cores": nproc, "kind": "oracle",
+           "sample": f"{n}^3 clump density (the GPU leg's), {cycles} V(2,2) cycles from zero (FMG not timed), "
+                     f"{dt * 1e3:.0f} ms per cycle, oracle built -O3 -march=x86-64-v3 without contraction"}
+    row("C2", rho, "periodic", None, 1, 1, f"{n}^3 clump density")
+    del rho
+    row("C1", wl.sine_modes(32, 1)[0], "periodic", None, 20, nproc, "32^3 sine modes")
+    if c3 is not None:
+        row("C3", c3[0], "fixed", c3[1], 1, nproc, f"{c3[0].shape[0]}^3 uniform sphere, fixed faces")
+    r4 = wl.lognormal_grf(256, 2)
+    r4 -= r4.mean()
+    row("C4", r4, "periodic", None, 2, nproc, "256^3 lognormal field as one dense grid")
+    oracle.set_threads(nproc)
+    out["rows"] = rows
+    out["c5"] = "a request stream, not a solve: its CPU cost per solve follows from the C2 and C3 rows"
+    return out
 
 
 def gravity_leg(mg, ctx, rho, n: int, reps: int, with_cpu: bool):
@@ -222,6 +270,47 @@ def gravity_leg(mg, ctx, rho, n: int, reps: int, with_cpu: bool):
                                "kind": "oracle", "sample": f"{m}^3 random potential and density, g and rho g, "
                                                            f"{dt * 1e3:.0f} ms"}
     return out
+
+
+def c3_leg(mg, ctx, steps: int, seed: int = 3, n: int = 512):
+    """Configuration 3: the n^3 uniform sphere (radius 0.25, seeded centre offset, sub-cell
+    volume fractions on cut cells) with fixed faces (the analytic potential at the face centres)
+    and with multipole faces (l <= 4), FP64 and mixed precision to 1e-10.  Per face kind: the
+    V-cycle rate of each precision, phi against the analytic potential (the discretisation
+    error at this h) and the mixed phi against the FP64 phi of the same problem."""
+    import numpy as np
+    import torch
+
+    import workloads as wl
+    R = 0.25
+    t0 = time.perf_counter()
+    rho_h, centre = wl.uniform_sphere(n, seed, radius=R)
+    mass = 4.0 / 3.0 * math.pi * R ** 3
+    faces_h = wl.sphere_face_values(n, centre, R, mass)
+    x = wl.cell_centres(n)
+    phi_a = torch.from_numpy(wl.sphere_potential(x[None, None, :], x[None, :, None], x[:, None, None], centre, R,
+                                                 mass)).to("cuda:0")
+    rho = torch.from_numpy(rho_h).to("cuda:0")
+    faces = [torch.from_numpy(np.ascontiguousarray(b)).to("cuda:0") for b in faces_h]
+    print(f"# C3 input {n}^3 generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    out = {"workload": f"C3 uniform sphere {n}^3 (R = {R}, centre {[round(float(c), 4) for c in centre]}), "
+                       f"FMG + V(2,2) to relative residual 1e-10", "tol": 1e-10}
+    for kind in ("fixed", "multipole"):
+        res, phis = {}, {}
+        for prec in ("fp64", "mixed"):
+            lat, cyc, hists, _, phi = run_solves(mg, ctx, rho, n, prec, steps, 1, 1e-10, bc=kind,
+                                                 fixed_b=faces if kind == "fixed" else None, label="C3")
+            t_v = statistics.median(cyc)
+            phis[prec] = phi.clone()
+            res[prec] = {"value": n ** 3 / (t_v * 1e-3) / 1e9,
+                         "unit": "GDoF/s per V-cycle" if prec == "fp64" else "GDoF/s per outer cycle",
+                         "cycle_ms_median": t_v, "cycles_per_solve": len(hists[-1]) - 1,
+                         "solve_latency_ms": {"p50": pct(lat, 0.5), "p99": pct(lat, 0.99)},
+                         "error_vs_analytic": phi_error(phi, phi_a)}
+        res["mixed"]["error_vs_fp64"] = phi_error(phis["mixed"], phis["fp64"])
+        out[kind] = res
+        del phis
+    return out, (rho_h, faces_h)
 
 
 AMR_NB, AMR_NB_CELLS = 8, 16   # binary test: 128^3 root grid (8^3 blocks of 16^3), four nested levels
@@ -369,32 +458,46 @@ def batched_leg(steps: int, seed: int, n: int = 256, block_n: int = 16):
     return out
 
 
+SERVE_POOL = {64: 64, 128: 32, 256: 16, 512: 8}   # distinct densities per size
+
+
 def serving_leg(n_requests: int, workers: int, seed: int):
-    """Mixed-size request stream (sizes 64-512, periodic / fixed / multipole faces, Poisson
-    arrivals) through the native serving runtime: first all requests at once (saturated
-    throughput mu), then open-loop at 0.5 mu and 0.9 mu; FP64 and mixed precision."""
+    """Configuration 5: a Poisson-arrival stream of mixed-size requests (sizes 64-512 and
+    periodic / fixed / multipole faces, uniform) through the native serving runtime: first all
+    requests at once (saturated throughput mu), then open-loop at 0.9 mu (and 0.5 mu in FP64);
+    FP64 and mixed precision.  Each request's density is picked by its own seed from a pool of
+    distinct clump densities per size (two generated fields per size, each periodically shifted
+    by seeded offsets: the clump centres stay uniform), resident in HBM before the runs."""
+    import numpy as np
     import torch
 
     import workloads as wl
     from paper_2302_13903_amd import serving
     sizes = (64, 128, 256, 512)
-    pool = {n: [torch.from_numpy(wl.gaussian_clumps(n, seed + 17 * k + n, remove_mean=False)).to("cuda:0")
-                for k in range(2)] for n in sizes}
+    rng = np.random.default_rng(seed)
+    pool = {}
+    for n in sizes:
+        base = [torch.from_numpy(wl.gaussian_clumps(n, seed + 17 * k + n, remove_mean=False)).to("cuda:0")
+                for k in range(2)]
+        pool[n] = [torch.roll(base[k % 2], tuple(int(v) for v in rng.integers(0, n, 3)), dims=(0, 1, 2)).contiguous()
+                   for k in range(SERVE_POOL[n])]
+        del base
     srv = serving.Server(workers=workers)
     out = {"workers": workers, "requests": n_requests, "sizes": list(sizes),
-           "bcs": ["periodic", "fixed", "multipole"], "tol": 1e-10}
+           "bcs": ["periodic", "fixed", "multipole"], "tol": 1e-10,
+           "densities_per_size": {str(k): v for k, v in SERVE_POOL.items()}}
     for prec in ("fp64", "mixed"):
         def reqs(rate):
             tr = wl.serving_trace(n_requests, seed, rate if rate else 1.0, sizes=sizes)
-            return [serving.Request(rho=pool[t["n"]][t["seed"] % 2], bc=t["bc"], precision=prec,
+            return [serving.Request(rho=pool[t["n"]][t["seed"] % SERVE_POOL[t["n"]]], bc=t["bc"], precision=prec,
                                     arrival_ms=t["t"] if rate else 0.0) for t in tr]
-        srv.run([serving.Request(rho=pool[n][k % 2], bc="multipole", precision=prec)
+        srv.run([serving.Request(rho=pool[n][k], bc="multipole", precision=prec)
                  for n in sizes for k in range(workers)])  # warm-up: resident hierarchies
         res = {}
         sat = serving.summary(srv.run(reqs(None)))
         res["saturated"] = sat
         mu = sat["solves_per_s"] / 1e3  # requests per ms
-        for frac in (0.5, 0.9):
+        for frac in ((0.5, 0.9) if prec == "fp64" else (0.9,)):
             r = srv.run(reqs(frac * mu))
             bad = [q.status for q in r if q.status != 0]
             if bad:
@@ -407,6 +510,156 @@ def serving_leg(n_requests: int, workers: int, seed: int):
     return out
 
 
+# ---------------------------------------------------------------- profile summaries (no GPU)
+
+PROFILE_ARGS = "--steps 2 --warmup 1 --no-cpu-baseline --no-batched --serve-requests 0 --no-c3 --calibrate-copy"
+PROFILE_RUNS = {
+    "kernel_stats_c2_512.md": (
+        "Kernel time, C2 Gaussian clumps 512^3 periodic: FP64, FAS and mixed solves to 1e-10, gravity, refined mesh",
+        "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/p_trace -o run -- python3 bench.py "
+        + PROFILE_ARGS),
+    "kernel_stats_c4_blocks_256.md": (
+        "Kernel time, C4 lognormal 256^3 as 4096 MeshBlocks of 16^3 (autotune, dense FP64, blocks FP64 and mixed)",
+        "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/p_trace_c4 -o run -- python3 bench.py "
+        "--only batched --steps 2"),
+}
+COUNTER_CMDS = [f"rocprofv3 --pmc {c} --output-format csv -d gpurun_out/p_{c.split('_')[0].lower()} -o run -- "
+                f"python3 bench.py {PROFILE_ARGS}" for c in ("FETCH_SIZE", "WRITE_SIZE")]
+# kernels that run once per solve (set-up, FMG, gauge fix) or belong to another scheme: a span
+# between two finest-level down passes that holds one of them is not a plain V-cycle
+NOT_IN_CYCLE = ("k_source", "k_shift", "k_restrict<", "k_prolong<double, 1>", "k_fas", "k_mix", "k_copy_convert",
+                "k_grav")
+
+
+def _read_csv(path):
+    import csv
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def summarize_trace(trace_dir: str, out_name: str):
+    """profiles/<out_name>: per kernel and per (kernel, grid) call counts and mean durations from a
+    rocprofv3 kernel trace of this script."""
+    title, cmd = PROFILE_RUNS[out_name]
+    rows = _read_csv(os.path.join(trace_dir, "run_kernel_trace.csv"))
+    per, per_grid = {}, {}
+    for r in rows:
+        k = short_name(r["Kernel_Name"])
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
+        g = int(r.get("Grid_Size") or r.get("Grid_Size_X"))
+        for key, tab in ((k, per), ((k, g), per_grid)):
+            a = tab.setdefault(key, [0, 0.0])
+            a[0] += 1
+            a[1] += d
+    tot = sum(v[1] for v in per.values())
+    lines = [f"# {title} (rocprofv3 --kernel-trace --stats)", "",
+             "Command (from the repository root, after `cd /tmp && export TMPDIR=/tmp` and back):", "", "```", cmd,
+             "```", "", "Per kernel (all levels):", "", "| kernel | calls | avg us | total ms | % |",
+             "|---|---:|---:|---:|---:|"]
+    for k, (c, t) in sorted(per.items(), key=lambda x: -x[1][1])[:30]:
+        lines.append(f"| `{k}` | {c} | {t / c:.1f} | {t * 1e-3:.2f} | {100 * t / tot:.1f} |")
+    lines += ["", f"Total kernel time {tot * 1e-3:.1f} ms.", "",
+              "Per kernel and grid size (grid = threads launched; a kernel's largest grid is its finest level):", "",
+              "| kernel | grid | calls | avg us |", "|---|---:|---:|---:|"]
+    for (k, g), (c, t) in sorted(per_grid.items(), key=lambda x: -x[1][1])[:40]:
+        lines.append(f"| `{k}` | {g} | {c} | {t / c:.1f} |")
+    with open(os.path.join(ROOT, "profiles", out_name), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
+def summarize_counters(fetch_dir: str, write_dir: str, n: int):
+    """profiles/traffic.json and profiles/hbm_traffic_c2_<n>.md from the FETCH_SIZE and WRITE_SIZE
+    runs: bytes per launch of each kernel at its largest grid (its finest level), scaled by what
+    the counters read for the 1 GiB calibration copy, and the bytes of whole FP64 V-cycles (every
+    dispatch from one finest-level down pass to the next)."""
+    runs = {}
+    for ctr, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = [r for r in _read_csv(os.path.join(d, "run_counter_collection.csv")) if r["Counter_Name"] == ctr]
+        disp = {}
+        for r in rows:
+            key = int(r["Dispatch_Id"])
+            e = disp.setdefault(key, {"name": short_name(r["Kernel_Name"]), "grid": int(r["Grid_Size"]), "v": 0.0})
+            e["v"] += float(r["Counter_Value"])
+        runs[ctr] = [disp[k] for k in sorted(disp)]
+    gib = float(1 << 30)
+    scale = {}
+    for ctr in runs:
+        cal = max((e["v"] for e in runs[ctr] if e["name"].startswith("__amd_rocclr_copyBuffer")), default=None)
+        if not cal:
+            raise SystemExit(f"{ctr}: no calibration copy in the counter run (use --calibrate-copy)")
+        scale[ctr] = gib / (cal * 1024.0)
+    kernels = {}
+    for ctr, key in (("FETCH_SIZE", "read_bytes"), ("WRITE_SIZE", "write_bytes")):
+        top = {}
+        for e in runs[ctr]:
+            if e["name"].startswith("__amd"):
+                continue
+            t = top.get(e["name"])
+            if t is None or e["grid"] > t[0]:
+                top[e["name"]] = [e["grid"], [e["v"]]]
+            elif e["grid"] == t[0]:
+                t[1].append(e["v"])
+        for name, (g, vs) in top.items():
+            rec = kernels.setdefault(f"{name}@{n}", {"grid": g, "dispatches": len(vs)})
+            rec[key] = statistics.mean(vs) * 1024.0 * scale[ctr]
+    for rec in kernels.values():
+        rec["bytes_per_launch"] = rec.get("read_bytes", 0.0) + rec.get("write_bytes", 0.0)
+    # whole V-cycles: spans between consecutive dispatches of the FP64 finest-level down pass
+    cyc = {}
+    for ctr in runs:
+        ev = runs[ctr]
+        downs = [e for e in ev if e["name"].startswith("k_march<double") and ", false, false," in e["name"]
+                 and not e["name"].endswith("true>")]
+        if not downs:
+            raise SystemExit("no FP64 two-sweep down pass in the counter run")
+        gmax = max(e["grid"] for e in downs)
+        marks = [i for i, e in enumerate(ev) if e in downs and e["grid"] == gmax]
+        spans = []
+        for a, b in zip(marks, marks[1:]):
+            seg = ev[a:b]
+            if any(x in e["name"] for e in seg for x in NOT_IN_CYCLE):
+                continue
+            spans.append(sum(e["v"] for e in seg) * 1024.0 * scale[ctr])
+        cyc[ctr] = spans
+    nc = min(len(cyc["FETCH_SIZE"]), len(cyc["WRITE_SIZE"]))
+    if nc == 0:
+        raise SystemExit("no complete V-cycle in the counter runs")
+    rd, wr = statistics.mean(cyc["FETCH_SIZE"]), statistics.mean(cyc["WRITE_SIZE"])
+    out = {"source_hash": kernel_source_hash(), "fetch_scale": scale["FETCH_SIZE"], "write_scale": scale["WRITE_SIZE"],
+           "command": COUNTER_CMDS, "kernels": dict(sorted(kernels.items(), key=lambda x: -x[1]["bytes_per_launch"])),
+           "v_cycle": {str(n): {"bytes_per_cycle": rd + wr, "read_bytes": rd, "write_bytes": wr, "cycles": nc,
+                                "algorithmic_bytes": FUSED_BYTES_PER_DOF * n ** 3}}}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    lines = [f"# HBM traffic, C2 {n}^3 FP64 and mixed solves, FAS, gravity (rocprofv3 --pmc)", "",
+             "FETCH_SIZE and WRITE_SIZE (KiB per dispatch) from two separate runs of the same script:", "", "```"]
+    lines += COUNTER_CMDS + ["```", "",
+                             f"Calibration: the 1 GiB device-to-device copy that `--calibrate-copy` runs first "
+                             f"(`__amd_rocclr_copyBuffer`) gives bytes = FETCH_SIZE x 1024 x {scale['FETCH_SIZE']:.3f} "
+                             f"and WRITE_SIZE x 1024 x {scale['WRITE_SIZE']:.3f}.", "",
+                             f"Whole FP64 V-cycles ({nc} counted; every dispatch from one {n}^3 down pass to the "
+                             f"next: all levels, the tail, the norm reduction): read {rd / 1e9:.3f} GB + write "
+                             f"{wr / 1e9:.3f} GB = {(rd + wr) / 1e9:.3f} GB per cycle, "
+                             f"{(rd + wr) / (FUSED_BYTES_PER_DOF * n ** 3):.2f}x the {FUSED_BYTES_PER_DOF:.0f} B/DoF "
+                             f"a fully fused V(2,2) cycle moves ({FUSED_BYTES_PER_DOF * n ** 3 / 1e9:.2f} GB).", "",
+                             "Per kernel at its largest grid (its finest level):", "",
+                             "| kernel | grid | dispatches | read GB | write GB |", "|---|---:|---:|---:|---:|"]
+    for k, rec in list(out["kernels"].items())[:30]:
+        lines.append(f"| `{k.rsplit('@', 1)[0]}` | {rec['grid']} | {rec['dispatches']} | "
+                     f"{rec.get('read_bytes', 0.0) / 1e9:.3f} | {rec.get('write_bytes', 0.0) / 1e9:.3f} |")
+    with open(os.path.join(ROOT, "profiles", f"hbm_traffic_c2_{n}.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
+def summarize_profiles(trace_dir: str, fetch_dir: str, write_dir: str, n: int):
+    summarize_trace(trace_dir, "kernel_stats_c2_512.md")
+    summarize_counters(fetch_dir, write_dir, n)
+    c4 = os.path.join(os.path.dirname(os.path.abspath(trace_dir)), "p_trace_c4")
+    if os.path.isdir(c4):
+        summarize_trace(c4, "kernel_stats_c4_blocks_256.md")
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -417,16 +670,24 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=240,
+    ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests per serving run (0: skip the serving leg)")
     ap.add_argument("--serve-workers", type=int, default=4)
     ap.add_argument("--no-batched", action="store_true", help="skip the MeshBlock (4096 x 16^3) leg")
     ap.add_argument("--no-gravity", action="store_true", help="skip the g = -grad phi leg")
     ap.add_argument("--no-fas", action="store_true", help="skip the Full Approximation Scheme leg")
     ap.add_argument("--no-amr", action="store_true", help="skip the refined-mesh leg")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 512^3 sphere (fixed and multipole faces) leg")
+    ap.add_argument("--only", choices=("batched",),
+                    help="run only that leg and print its record (for profiling it alone)")
+    ap.add_argument("--summarize-profiles", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="write the profiles/ summaries from rocprofv3 output of this script (no GPU work)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device to device (reference for profiler byte counters)")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(*args.summarize_profiles, n=args.n)
+        return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
               file=sys.stderr)
@@ -437,6 +698,9 @@ def main() -> int:
     import paper_2302_13903_amd as mg
     import workloads as wl
 
+    if args.only == "batched":
+        print(json.dumps({"batched": batched_leg(args.steps, args.seed)}), flush=True)
+        return 0
     n = args.n
     t0 = time.perf_counter()
     rho_h = wl.gaussian_clumps(n, args.seed)
@@ -454,7 +718,8 @@ def main() -> int:
 
     ctx = mg.Context(0)
     ctx.set_kernel_timing(True)
-    lat, cyc, hists, kt = run_solves(mg, ctx, rho, n, "fp64", args.steps, args.warmup, args.tol)
+    lat, cyc, hists, kt, phi64 = run_solves(mg, ctx, rho, n, "fp64", args.steps, args.warmup, args.tol)
+    phi64 = phi64.clone()
     t_v = statistics.median(cyc)
     value = n ** 3 / (t_v * 1e-3) / 1e9
     passes = pass_table(kt)
@@ -463,10 +728,12 @@ def main() -> int:
     traffic = measured_traffic(dom["kernel"], n)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": None if achieved is None else achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "scope": "the dominant kernel (finest-level pass with the largest summed time); the whole V-cycle "
+                         "is in v_cycle_algorithmic and v_cycle_counted",
                 "kernel": dom["kernel"], "algorithmic_bytes_per_launch": dom["algorithmic_bytes_per_launch"],
                 "avg_launch_ms": dom["avg_launch_ms"], "launches": dom["launches"], "passes": passes,
                 "v_cycle_algorithmic": v_cycle_efficiency(n, t_v),
-                "v_cycle_counted": v_cycle_counted(passes, len(cyc), n, t_v)}
+                "v_cycle_counted": v_cycle_counted(n, t_v)}
 
     out = {
         "metric": "GDoF/s per V-cycle + % HBM roofline at 512^3; p50/p99 solve latency, mixed vs FP64",
@@ -492,8 +759,8 @@ def main() -> int:
         out["gravity"] = gravity_leg(mg, ctx, rho, n, 20, not args.no_cpu_baseline)
     if not args.no_fas:
         ctx.set_kernel_timing(True)
-        lat_f, cyc_f, hists_f, kt_f = run_solves(mg, ctx, rho, n, "fp64", max(2, args.steps // 2), 1, args.tol,
-                                                 scheme="fas")
+        lat_f, cyc_f, hists_f, kt_f, _ = run_solves(mg, ctx, rho, n, "fp64", max(2, args.steps // 2), 1, args.tol,
+                                                    scheme="fas")
         ctx.set_kernel_timing(False)
         tvf = statistics.median(cyc_f)
         pf = pass_table(kt_f)
@@ -508,18 +775,24 @@ def main() -> int:
     if not args.no_amr:
         out["amr"] = amr_leg(mg, 2, not args.no_cpu_baseline)
     if not args.no_mixed:
-        lat_m, cyc_m, hists_m, _ = run_solves(mg, ctx, rho, n, "mixed", args.steps, args.warmup, args.tol)
+        lat_m, cyc_m, hists_m, _, phim = run_solves(mg, ctx, rho, n, "mixed", args.steps, args.warmup, args.tol)
         tvm = statistics.median(cyc_m)
         out["mixed"] = {"value": n ** 3 / (tvm * 1e-3) / 1e9, "unit": "GDoF/s per outer cycle",
                         "ms_per_step": statistics.mean(lat_m), "cycles_per_solve": len(hists_m[-1]) - 1,
                         "cycle_ms_median": tvm,
-                        "solve_latency_ms": {"p50": pct(lat_m, 0.5), "p99": pct(lat_m, 0.99)}}
+                        "solve_latency_ms": {"p50": pct(lat_m, 0.5), "p99": pct(lat_m, 0.99)},
+                        "error_vs_fp64": phi_error(phim, phi64)}
+        del phim
+    del phi64
+    c3_inputs = None
+    if not args.no_c3:
+        out["c3"], c3_inputs = c3_leg(mg, ctx, max(2, args.steps // 2))
     if not args.no_batched:
         out["batched"] = batched_leg(args.steps, args.seed)
     if args.serve_requests > 0:
         out["serving"] = serving_leg(args.serve_requests, args.serve_workers, args.seed)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(n)
+        out["cpu_baseline"] = cpu_baseline(n, c3=c3_inputs)
     print(json.dumps(out), flush=True)
     return 0
 

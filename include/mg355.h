@@ -135,13 +135,15 @@ int mg_ctx_reserve(mg_ctx *ctx, const mg_params *p);
  * later solves use it.
  *   MG_LAYOUT_BLOCKS: the block sweep (threads per workgroup, blocks staged per workgroup,
  *     one or two sweeps fused per launch; every such schedule gives bitwise the same result)
- *     and, for block levels of at least 256 cells per side, whether the streaming z-marching
- *     passes that cross block boundaries replace the per-block halo-tile sweeps.
+ *     and, on the finest block level, whether the streaming passes that cross block
+ *     boundaries replace the per-block halo-tile sweeps (with V(2,2) from 128 cells per side:
+ *     the two-sweep down and up passes against four halo-tile sweeps; otherwise, from 256
+ *     cells per side, the one-sweep passes against one halo-tile sweep).
  *   MG_LAYOUT_DENSE (n >= 64): whether the restricted defect (and, on the FP64 finest level,
  *     the residual norm) is fused into the last smoothing pass or runs as its own streaming
  *     pass, and whether sweeps run one per pass or two per pass (temporally blocked).  The
  *     alternatives differ only in floating-point contraction (same expressions).
- * Allocates and frees its own scratch (3 n^3 arrays); synchronises its own stream. */
+ * Allocates and frees its own scratch (3.25 n^3 values); synchronises its own stream. */
 int mg_autotune(mg_ctx *ctx, const mg_params *p, int reps);
 
 /* The context's schedules as text, one line each: "blk fp64|fp32 Lm Lb threads G S"

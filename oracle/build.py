@@ -18,9 +18,12 @@ OUT = os.path.join(OUT_DIR, "liboracle.so")
 def build(verbose: bool = False) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
     tmp = OUT + ".tmp"
-    # -O2 without fast-math: IEEE FP64 semantics, no reassociation of the plain loops.
-    cmd = ["gcc", "-std=c11", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wno-unknown-pragmas",
-           SRC, "-o", tmp, "-lm"]
+    # -O3 without fast-math and without contraction: IEEE FP64 semantics, no reassociation of
+    # the plain loops and no fused multiply-adds, so every optimisation level gives the same
+    # bits.  x86-64-v3 (AVX2) rather than -march=native: the library may run on another host
+    # than the one that built it.
+    cmd = ["gcc", "-std=c11", "-O3", "-march=x86-64-v3", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+           "-Wall", "-Wno-unknown-pragmas", SRC, "-o", tmp, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

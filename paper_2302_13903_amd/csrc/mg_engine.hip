@@ -286,6 +286,14 @@ struct Hier {
   double omega = 1.15;
 };
 
+// Smallest level side on which the two-sweep passes run: kMarchMinN, or the one-sweep passes'
+// threshold ("fusedmin") when that was set larger.
+template <typename T>
+int march_min_n(const mg_ctx* c) {
+  const int v = c->fused_min_n[sizeof(T) == 8 ? 0 : 1];
+  return v > 0 ? std::max(kMarchMinN, v) : kMarchMinN;
+}
+
 struct Solver {
   mg_ctx* c;
   hipStream_t s;
@@ -369,12 +377,9 @@ struct Solver {
     return true;
   }
 
-  // Smallest level side on which the two-sweep passes run: kMarchMinN, or the one-sweep
-  // passes' threshold when that was set larger.
   template <typename T>
   int march_min() const {
-    const int v = c->fused_min_n[sizeof(T) == 8 ? 0 : 1];
-    return v > 0 ? std::max(kMarchMinN, v) : kMarchMinN;
+    return march_min_n<T>(c);
   }
 
   // May a MeshBlock level run the two-sweep streaming passes (the "march" setting for its faces)?
@@ -1364,18 +1369,21 @@ template <typename T>
 int autotune_blocks(mg_ctx* c, const mg_params* p, int Lb, int reps) {
   const int L = ilog2(p->n);
   const size_t cellsL = cells(L);
-  T* buf[3] = {nullptr, nullptr, nullptr};
-  if (over_budget(c, 3 * cellsL * sizeof(T), 0)) return fail(c, MG_ERR_OOM, "autotune scratch exceeds the HBM budget");
-  for (auto& b : buf)
-    if (hipMalloc((void**)&b, cellsL * sizeof(T)) != hipSuccess) {
+  // u (two), f, and the coarse source and correction of the finest block level
+  T* buf[4] = {nullptr, nullptr, nullptr, nullptr};
+  const size_t sz[4] = {cellsL, cellsL, cellsL, cellsL / 4};
+  if (over_budget(c, (3 * cellsL + cellsL / 4) * sizeof(T), 0))
+    return fail(c, MG_ERR_OOM, "autotune scratch exceeds the HBM budget");
+  for (int q = 0; q < 4; ++q)
+    if (hipMalloc((void**)&buf[q], sz[q] * sizeof(T)) != hipSuccess) {
       (void)hipGetLastError();
-      for (auto& q : buf)
-        if (q) (void)hipFree(q);
+      for (auto& b : buf)
+        if (b) (void)hipFree(b);
       return fail(c, MG_ERR_OOM, "autotune scratch allocation failed");
     }
   hipStream_t s = nullptr;
   HIP_CHECK(c, hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-  for (auto& b : buf) HIP_CHECK(c, hipMemsetAsync(b, 0, cellsL * sizeof(T), s));
+  for (int q = 0; q < 4; ++q) HIP_CHECK(c, hipMemsetAsync(buf[q], 0, sz[q] * sizeof(T), s));
   hipEvent_t e0, e1;
   HIP_CHECK(c, hipEventCreate(&e0));
   HIP_CHECK(c, hipEventCreate(&e1));
@@ -1403,7 +1411,23 @@ int autotune_blocks(mg_ctx* c, const mg_params* p, int Lb, int reps) {
           if (ms < best_ms) { best_ms = ms; best = t; }
         }
     c->blk_tune[(sizeof(T) == 8 ? 0 : 1000) + 100 * Lm + Lb] = best;
-    if (l == L && (1 << l) >= kFusedDefaultMinN) {
+    if (l == L && p->npre == 2 && p->npost == 2 && (1 << l) >= march_min_n<T>(c)) {
+      // V(2,2) on the finest block level: both legs as the two-sweep streaming passes across
+      // blocks against the four halo-tile sweeps alone (a lower bound on that schedule)
+      T* fc = buf[3];
+      T* uc = buf[3] + cellsL / 8;
+      LevelBC hom = bc;
+      (void)hipEventRecord(e0, s);
+      for (int r = 0; r < reps; ++r) {
+        march_down<T>(buf[0], buf[1], buf[2], fc, uc, 1 << l, h, p->omega, bc, s, Lm);
+        (void)march_up<T>(buf[1], buf[0], buf[2], uc, hom, nullptr, 1 << l, h, p->omega, bc, s, Lm);
+      }
+      (void)hipEventRecord(e1, s);
+      HIP_CHECK(c, hipEventSynchronize(e1));
+      HIP_CHECK(c, hipGetLastError());
+      const double t_m = elapsed(e0, e1) / reps;
+      c->blk_zmarch[sizeof(T) == 8 ? 0 : 1] = t_m < 4.0 * best_ms ? 1 : 0;
+    } else if (l == L && (1 << l) >= kFusedDefaultMinN) {
       // the finest block level: halo-tile sweeps against the streaming passes across blocks
       (void)hipEventRecord(e0, s);
       for (int r = 0; r < reps; ++r)

@@ -10,9 +10,9 @@
 namespace mg {
 
 // Smallest and largest level side the region-tile legs take (the level must hold whole
-// regions of 16 x 16 x 8 cells).
+// regions of 16 x 16 x 8 cells; above 128^3 the streaming passes move far fewer bytes).
 constexpr int kTileMinN = 32;
-constexpr int kTileMaxN = 256;
+constexpr int kTileMaxN = 128;
 
 // Down step of a V-cycle level (Alg. 1 steps 1-3) in one launch: two smoothing sweeps of u
 // (uin -> uout, distinct arrays), the defect restricted into fc and the coarse correction uc0
