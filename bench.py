@@ -567,7 +567,7 @@ def summarize_trace(trace_dir: str, out_name: str):
         fh.write("\n".join(lines) + "\n")
 
 
-def summarize_counters(fetch_dir: str, write_dir: str, n: int):
+def summarize_counters(fetch_dir: str, write_dir: str, n: int, out_dir: str = ""):
     """profiles/traffic.json and profiles/hbm_traffic_c2_<n>.md from the FETCH_SIZE and WRITE_SIZE
     runs: bytes per launch of each kernel at its largest grid (its finest level), scaled by what
     the counters read for the 1 GiB calibration copy, and the bytes of whole FP64 V-cycles (every
@@ -629,7 +629,8 @@ def summarize_counters(fetch_dir: str, write_dir: str, n: int):
            "command": COUNTER_CMDS, "kernels": dict(sorted(kernels.items(), key=lambda x: -x[1]["bytes_per_launch"])),
            "v_cycle": {str(n): {"bytes_per_cycle": rd + wr, "read_bytes": rd, "write_bytes": wr, "cycles": nc,
                                 "algorithmic_bytes": FUSED_BYTES_PER_DOF * n ** 3}}}
-    with open(TRAFFIC_FILE, "w") as fh:
+    out_dir = out_dir or os.path.join(ROOT, "profiles")
+    with open(os.path.join(out_dir, os.path.basename(TRAFFIC_FILE)), "w") as fh:
         json.dump(out, fh, indent=1)
         fh.write("\n")
     lines = [f"# HBM traffic, C2 {n}^3 FP64 and mixed solves, FAS, gravity (rocprofv3 --pmc)", "",
@@ -648,7 +649,7 @@ def summarize_counters(fetch_dir: str, write_dir: str, n: int):
     for k, rec in list(out["kernels"].items())[:30]:
         lines.append(f"| `{k.rsplit('@', 1)[0]}` | {rec['grid']} | {rec['dispatches']} | "
                      f"{rec.get('read_bytes', 0.0) / 1e9:.3f} | {rec.get('write_bytes', 0.0) / 1e9:.3f} |")
-    with open(os.path.join(ROOT, "profiles", f"hbm_traffic_c2_{n}.md"), "w") as fh:
+    with open(os.path.join(out_dir, f"hbm_traffic_c2_{n}.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
 
 

@@ -52,13 +52,55 @@ def test_traffic_lookup_and_staleness(tmp_path, monkeypatch):
 def test_v_cycle_counted(tmp_path, monkeypatch):
     f = tmp_path / "traffic.json"
     f.write_text(json.dumps({"source_hash": bench.kernel_source_hash(),
-                             "kernels": {"k_a@512": {"bytes_per_launch": 7e9}, "k_b@512": {"bytes_per_launch": 14e9}}}))
+                             "v_cycle": {"512": {"bytes_per_cycle": 32e9, "cycles": 5}}}))
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
-    passes = [{"kernel": "void mg::k_a(int)", "launches": 12}, {"kernel": "void mg::k_b(int)", "launches": 6}]
-    r = bench.v_cycle_counted(passes, 6, 512, 4.0)
-    # per cycle: (2 x 7 + 1 x 14) GB x 8/7 = 32 GB in 4 ms
+    r = bench.v_cycle_counted(512, 4.0)
     assert r["bytes_per_cycle"] == pytest.approx(32e9)
     assert r["achieved"] == pytest.approx(8000.0)
     assert r["frac"] == pytest.approx(1.0)
-    passes.append({"kernel": "void mg::k_c(int)", "launches": 6})
-    assert bench.v_cycle_counted(passes, 6, 512, 4.0) is None
+    assert r["over_algorithmic"] == pytest.approx(32e9 / (57.0 * 512 ** 3))
+    assert bench.v_cycle_counted(256, 4.0) is None
+    f.write_text(json.dumps({"source_hash": "0" * 16, "v_cycle": {"512": {"bytes_per_cycle": 32e9, "cycles": 5}}}))
+    assert bench.v_cycle_counted(512, 4.0) is None
+
+
+DOWN = "void mg::(anonymous namespace)::k_march<double, 8, false, false, true, false>(mg::(anonymous namespace)::MarchArgs)"
+UP = "void mg::(anonymous namespace)::k_march<double, 8, true, true, true, false>(mg::(anonymous namespace)::MarchArgs)"
+
+
+def _counter_csv(path, counter, rows):
+    import csv
+    path.mkdir()
+    with open(path / "run_counter_collection.csv", "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(["Dispatch_Id", "Grid_Size", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        for i, (name, grid, v) in enumerate(rows):
+            w.writerow([i + 1, grid, name, counter, v])
+
+
+def test_summarize_counters_sums_whole_cycles(tmp_path):
+    """Calibration from the 1 GiB copy; a V-cycle is every dispatch from one finest-level down
+    pass to the next (coarser down passes included); spans holding a once-per-solve kernel are
+    left out."""
+    seq = [("__amd_rocclr_copyBuffer", 131072, None), ("void mg::k_source(A)", 99, 7.0),
+           (DOWN, 1000, 100.0), (DOWN, 500, 50.0), ("void mg::k_tail<double, true>(A)", 10, 5.0), (UP, 1000, 200.0),
+           ("void mg::k_sum_partials(A)", 9, 1.0),
+           (DOWN, 1000, 100.0), (DOWN, 500, 50.0), ("void mg::k_tail<double, true>(A)", 10, 5.0), (UP, 1000, 200.0),
+           ("void mg::k_sum_partials(A)", 9, 1.0),
+           (DOWN, 1000, 100.0), ("void mg::k_shift(A)", 99, 3.0), ("void mg::k_source(A)", 99, 7.0),
+           (DOWN, 1000, 100.0)]
+    _counter_csv(tmp_path / "f", "FETCH_SIZE", [(k, g, 524288.0 if v is None else v) for k, g, v in seq])
+    _counter_csv(tmp_path / "w", "WRITE_SIZE", [(k, g, 1048576.0 if v is None else v / 2) for k, g, v in seq])
+    out = tmp_path / "out"
+    out.mkdir()
+    bench.summarize_counters(str(tmp_path / "f"), str(tmp_path / "w"), 512, str(out))
+    t = json.loads((out / "traffic.json").read_text())
+    assert t["fetch_scale"] == pytest.approx(2.0) and t["write_scale"] == pytest.approx(1.0)
+    vc = t["v_cycle"]["512"]
+    assert vc["cycles"] == 2
+    assert vc["read_bytes"] == pytest.approx(356.0 * 1024 * 2)
+    assert vc["write_bytes"] == pytest.approx(178.0 * 1024)
+    k = t["kernels"]["k_march<double, 8, false, false, true, false>@512"]
+    assert k["grid"] == 1000 and k["dispatches"] == 4
+    assert k["read_bytes"] == pytest.approx(100.0 * 1024 * 2)
+    assert (out / "hbm_traffic_c2_512.md").exists()
