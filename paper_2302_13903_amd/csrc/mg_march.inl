@@ -252,7 +252,7 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
 
     // ---- loads of u on plane P (unless zero on input) and f on plane P-1 (the plane the red
     // stage of the next step works on); up: the coarse taps of plane P
-    auto load_plane = [&](int P, bool first) __attribute__((always_inline)) {
+    auto load_plane = [&](int P) __attribute__((always_inline)) {
       const bool in_z = pz || (P >= 0 && P < n);
       const bool in_zf = pz || (P - 1 >= 0 && P - 1 < n);
       const int Pg = P & nm, Pfg = (P - 1) & nm;
@@ -292,9 +292,9 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
         // Y0+j-1 .. Y0+j+1) on the coarse planes (zlo, zlo+1) of fine plane P; the x-neighbour
         // columns come from the lanes beside (an edge lane of a segment gets its own value
         // back: wrong, but only in the outermost column of the tile, inside the halo).  Fine
-        // plane 2Z takes coarse planes (Z-1, Z), plane 2Z+1 (Z, Z+1): an even plane reuses
-        // the taps of the odd plane before it, an odd plane keeps its predecessor's upper plane
-        // as its lower one and loads one new plane.
+        // plane 2Z takes coarse planes (Z-1, Z), plane 2Z+1 (Z, Z+1).  Both planes are loaded
+        // for every fine plane (cache hits the second time): keeping the shared plane in
+        // registers instead makes the loads conditional and the march slower.
         const T* __restrict__ ec = reinterpret_cast<const T*>(A.ec);
         const int nc = n >> 1, Lc = L - 1;
         const int X = (px ? xag : xa) >> 1;
@@ -317,12 +317,10 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
             return sg * ec[cdx(Xc, Yc, Zc)];
           }
         };
-        if (first || (P & 1)) {
 #pragma unroll
-          for (int i = 0; i < NTAP; ++i) {
-            pc[i][0] = first ? tap(i, zlo) : pc[i][1];
-            pc[i][1] = tap(i, zlo + 1);
-          }
+        for (int i = 0; i < NTAP; ++i) {
+          pc[i][0] = tap(i, zlo);
+          pc[i][1] = tap(i, zlo + 1);
         }
       }
     };
@@ -534,7 +532,7 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
       }
     };
 
-    load_plane(zstart, true);
+    load_plane(zstart);
     prolong_apply(zstart, std::integral_constant<int, HZ & 1>{});
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -549,7 +547,7 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
       const int t = g + K;
       if (t >= nsteps) return;
       const int P = zstart + t;
-      if (t + 1 < nsteps) load_plane(P + 1, false);   // prefetch; consumed at the end of the step
+      if (t + 1 < nsteps) load_plane(P + 1);   // prefetch; consumed at the end of the step
       constexpr int s0 = K, s1 = (K + 5) % 6, s2 = (K + 4) % 6, s3 = (K + 3) % 6, s4 = (K + 2) % 6,
                     s5 = (K + 1) % 6;
       using I0 = std::integral_constant<int, 0>;
