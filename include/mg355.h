@@ -156,7 +156,7 @@ int mg_autotune(mg_ctx *ctx, const mg_params *p, int reps);
  * (MeshBlock layout, 1: streaming passes across blocks on the large block levels) and
  * "march fp64|fp32 0|1|2" (V(2,2) legs of the levels >= 128^3, or >= the fusedmin size when
  * that was set larger, as two streaming passes -- down: two sweeps + restricted defect; up:
- * prolongation + two sweeps + norm -- 0 off, 1 when every face is periodic (default), 2 always)
+ * prolongation + two sweeps + norm -- 0 off, 1 when every face is periodic, 2 always (default))
  * and "tile fp64|fp32 0|1" (1, the default: with V(2,2), each leg of the levels 32^3 .. 128^3
  * that the streaming passes do not take runs as one region-tile launch).  Writes at most cap bytes (NUL-terminated) and returns the length
  * needed including the NUL.  mg_tuning_set reads the same format (e.g. from a cache file)

@@ -114,7 +114,7 @@ struct mg_ctx {
   int tblock[2] = {-1, -1};
   // V(2,2) legs as two-sweep streaming passes (down: two sweeps + restricted defect; up:
   // prolongation + two sweeps [+ norm]): 0 = off, 1 = on levels whose faces are all periodic,
-  // 2 = on every level; -1 = the built-in default (1)
+  // 2 = on every level; -1 = the built-in default (2)
   int march[2] = {-1, -1};
   // V(2,2) legs of the levels 32^3 .. 128^3 (and the MeshBlock levels below the streaming
   // passes) as one region-tile launch each: 1 = on (default), 0 = per-operator launches
@@ -368,7 +368,7 @@ struct Solver {
   // the restricted defect in one pass; up: prolongation, two sweeps and the norm in one)?
   template <typename T>
   bool march_on(const Hier<T>& H, int l, const LevelBC& bc) const {
-    const int mode = c->march[sizeof(T) == 8 ? 0 : 1] < 0 ? 1 : c->march[sizeof(T) == 8 ? 0 : 1];
+    const int mode = c->march[sizeof(T) == 8 ? 0 : 1] < 0 ? 2 : c->march[sizeof(T) == 8 ? 0 : 1];
     if (mode == 0 || !use_fused || !H.u2[l] || l == H.T_top || Lb >= 0 || H.npre != 2 || H.npost != 2) return false;
     if ((1 << l) < march_min<T>() || tblock_on<T>()) return false;
     if (mode == 1)
@@ -385,7 +385,7 @@ struct Solver {
   // May a MeshBlock level run the two-sweep streaming passes (the "march" setting for its faces)?
   template <typename T>
   bool march_blk_on(const Hier<T>& H, const LevelBC& bc) const {
-    const int mode = c->march[sizeof(T) == 8 ? 0 : 1] < 0 ? 1 : c->march[sizeof(T) == 8 ? 0 : 1];
+    const int mode = c->march[sizeof(T) == 8 ? 0 : 1] < 0 ? 2 : c->march[sizeof(T) == 8 ? 0 : 1];
     if (mode == 0 || H.npre != 2 || H.npost != 2) return false;
     if (mode == 1)
       for (int f = 0; f < 6; ++f)
@@ -1702,7 +1702,7 @@ int op_smooth(mg_ctx* c, int n, double h, double omega, int sweeps, bool zero_in
 template <typename T>
 bool op_march(const mg_ctx* c, int n, int sweeps, const LevelBC& b) {
   const int v = c->march[sizeof(T) == 8 ? 0 : 1];
-  const int mode = v < 0 ? 1 : v;
+  const int mode = v < 0 ? 2 : v;
   if (mode == 0 || sweeps != 2 || n < kMarchMinN) return false;
   if (mode == 1)
     for (int f = 0; f < 6; ++f)

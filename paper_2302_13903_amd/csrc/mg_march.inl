@@ -29,15 +29,21 @@
 // stays at six planes.  Tiles overlap by a halo of 6 cells (5 stages of radius 1, rounded up to
 // even) and are recomputed, so tiles are independent and the result goes to another array.
 //
-// Non-periodic faces (Sec. 2.3.6): the cell just beyond a face is a ghost cell of the tile.
-// Before every stage it is set to kappa * (the adjacent active cell's current value) + beta,
-// with kappa = +1, beta = 0 for a zero-gradient face and kappa = -1, beta = 2 b for a fixed face,
-// so the stage itself needs no boundary code.  beta of an x or y face travels in the ghost
-// cell's own f slot (loaded with the plane); with 52-row output tiles and a halo of 6 the rows
-// beyond y = 0 and y = n-1 are always rows 1 and 2 of the same lane as their active neighbour.
-// The ghost planes beyond z = 0 and z = n-1 take beta from the face arrays (two planes per
-// level).  The coarse correction's taps (homogeneous conditions) are clamped to the domain with
-// the sign of each face's rule.
+// Non-periodic faces (Sec. 2.3.6): a ghost value is kappa * (the adjacent active cell's current
+// value) + beta, with kappa = +1, beta = 0 for a zero-gradient face and kappa = -1, beta = 2 b
+// for a fixed face.  beta enters only the stencil of that active cell, and there with the
+// weight of a neighbour, so it is folded into the cell's source as f - beta / h^2 when f is
+// loaded; what remains of the ghost is kappa times the cell's own current value:
+//   x: the lane holding x = 0 (x = n-1) takes kappa * c in place of its left (right) neighbour;
+//   y: with 52-row output tiles and a halo of 6 the rows beyond y = 0 and y = n-1 are always
+//      rows 1 and 2 of the same lane as their active neighbour; before each stage the ghost
+//      cells the stage reads are set to kappa times that neighbour (in-lane);
+//   z: the ring plane beyond z = 0 or z = n-1 is set the same way before a stage on the
+//      boundary plane.
+// Cells outside the domain are loaded from their periodic image (every address in range, no
+// predicated loads) and swept like the others; no active cell reads them.  The coarse
+// correction's taps (homogeneous conditions) are clamped to the domain with the sign of each
+// face's rule.
 #include "mg_march.h"
 
 #include <cstring>
@@ -121,21 +127,6 @@ __device__ __forceinline__ T beta_of(const LevelBC& bc, int face, int n, int t1,
   return bc.kind[face] == BC_ZERO_GRADIENT ? (T)0 : (T)(2.0 * face_b(bc, face, n, t1, t2));
 }
 
-// One index of a coarse tap under homogeneous conditions: inside, or clamped to the boundary
-// cell with the sign of that face's rule (periodic indices arrive wrapped).
-template <typename T>
-__device__ __forceinline__ int clamp_tap(int v, int nc, const LevelBC& bcc, int lo_face, T& s) {
-  if (v < 0) {
-    s *= kappa_of<T>(bcc, lo_face);
-    return 0;
-  }
-  if (v >= nc) {
-    s *= kappa_of<T>(bcc, lo_face + 1);
-    return nc - 1;
-  }
-  return v;
-}
-
 template <typename T>
 struct alignas(2 * sizeof(T)) Pair {
   T a, b;
@@ -161,6 +152,13 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
   constexpr int HZ = DSTAGE ? 5 : 4;              // planes marched before (and after) the chunk
   __shared__ Pair<T> xch[2][NB][2][SL];
   __shared__ Pair<T> fl[kFSlots][R][NT];
+  // walls with face values: -beta / h^2 of the wall cells of the plane being loaded, added to
+  // their f when that plane's f is taken up at the end of the step (x walls: per band, side
+  // and row; y walls: per side, column and cell)
+  __shared__ T fdx[PER ? 1 : NB][2][R];
+  __shared__ T fdy[2][PER ? 1 : SL][2];
+  // non-periodic: the red cells' partial defects carried to the next step (registers are short)
+  __shared__ T dredl[PER ? 1 : R][PER ? 1 : NT];
 
   const int tid = threadIdx.x;
   const int lane = tid & (kLanes - 1);
@@ -196,23 +194,24 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
 
     const int xs = tx * A.xo;                    // first output column (even)
     const int xa = xs - kHalo + 2 * xl;          // this lane's even column
-    const bool in_x = px || (xa >= 0 && xa < n);
     const int xag = xa & nm;
     const bool out_x = xa >= xs && xa < xs + A.xo && xa < n;
-    // the lane whose odd cell is the ghost beyond x = 0, whose even cell is the ghost beyond n-1
-    const bool gx0 = !PER && !px && xa == -2;
-    const bool gx1 = !PER && !px && xa == n;
+    // the lane whose even cell is x = 0, whose odd cell is x = n-1 (beside a wall)
+    const bool wx0 = !PER && !px && xa == 0;
+    [[maybe_unused]] const bool in_x = px || (xa >= 0 && xa < n);
+    const bool wx1 = !PER && !px && xa == n - 2;
 
     const int ys = ty * A.yo;                    // first output row (even)
     int yv[R], ygv[R];
-    bool in_y[R], out_y[R];
+    bool out_y[R];
+    [[maybe_unused]] bool in_y[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int y = ys - kHalo + band * R + r;
       yv[r] = y;
       ygv[r] = y & nm;
-      in_y[r] = py || (y >= 0 && y < n);
       out_y[r] = y >= ys && y < ys + A.yo && y < n;
+      in_y[r] = py || (y >= 0 && y < n);
     }
     const int z0 = cz * A.zc;                    // a multiple of 6
     const int zend = min(z0 + A.zc, n);
@@ -222,17 +221,29 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
     // active row y = n-1 and the ghost beyond it
     const bool gy0 = !PER && !py && yv[1] == -1;
     const bool gy1 = !PER && !py && yv[2] == n;
-    // does any cell of this wave sit beside a ghost in x or y?
+    // does any cell of this wave sit beside a wall in x or y?
     const int wy0 = ys - kHalo + w * 2 * R, wy1 = wy0 + 2 * R - 1;
     const bool wave_x = !PER && !px && (xs - kHalo < 0 || xs - kHalo + kTX - 1 >= n);
     const bool wave_y = !PER && !py && (wy0 < 0 || wy1 >= n);
+    // fold beta of the walls with face values into f (fixed and multipole faces)
+    const bool fold_x = wave_x && (A.bc.b[0] || A.bc.b[1]);
+    const bool fold_y = wave_y && (A.bc.b[2] || A.bc.b[3]);
     const T kx0 = kappa_of<T>(A.bc, 0), kx1 = kappa_of<T>(A.bc, 1), ky0 = kappa_of<T>(A.bc, 2);
     const T ky1 = kappa_of<T>(A.bc, 3), kz0 = kappa_of<T>(A.bc, 4), kz1 = kappa_of<T>(A.bc, 5);
+    // up: the coarse correction's rules (homogeneous conditions)
+    const T kcx0 = kappa_of<T>(A.bcc, 0), kcx1 = kappa_of<T>(A.bcc, 1), kcy0 = kappa_of<T>(A.bcc, 2);
+    const T kcy1 = kappa_of<T>(A.bcc, 3), kcz0 = kappa_of<T>(A.bcc, 4), kcz1 = kappa_of<T>(A.bcc, 5);
 
     T u[kRing][R][2];
     T pu[R][2], pf[R][2];      // prefetched u of plane P+1 and f of plane P
     T fr[R][2];                // f of plane P-1
-    T dred[R];                 // red cells' partial defects of plane P-4 (completed next step)
+    T dred[PER ? R : 1];       // red cells' partial defects of plane P-4 (completed next step)
+    // (non-periodic: in LDS)
+    auto dred_get = [&](int r) __attribute__((always_inline)) -> T { return PER ? dred[PER ? r : 0] : dredl[PER ? 0 : r][PER ? 0 : tid]; };
+    auto dred_set = [&](int r, T v) __attribute__((always_inline)) {
+      if constexpr (PER) dred[r] = v;
+      else dredl[r][tid] = v;
+    };
     T pend[R / 2], stash[R / 2];   // down: row-pair defect sums (black cells of P-4; even plane)
     constexpr int NTAP = R / 2 + 2;
     T pc[UP ? NTAP : 1][2];    // up: coarse rows Y0-1 .. Y0+2 on the two coarse planes of a fine plane
@@ -243,7 +254,7 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       fr[r][0] = fr[r][1] = (T)0;
-      dred[r] = (T)0;
+      dred_set(r, (T)0);
 #pragma unroll
       for (int q = 0; q < kFSlots; ++q) fl[q][r][tid] = Pair<T>{(T)0, (T)0};
     }
@@ -251,38 +262,99 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
     for (int j = 0; j < R / 2; ++j) pend[j] = stash[j] = (T)0;
 
     // ---- loads of u on plane P (unless zero on input) and f on plane P-1 (the plane the red
-    // stage of the next step works on); up: the coarse taps of plane P
+    // stage of the next step works on), beta of the walls folded into f; up: the coarse taps
+    // of plane P
     auto load_plane = [&](int P) __attribute__((always_inline)) {
-      const bool in_z = pz || (P >= 0 && P < n);
-      const bool in_zf = pz || (P - 1 >= 0 && P - 1 < n);
       const int Pg = P & nm, Pfg = (P - 1) & nm;
+      if constexpr (!PER) {
+        // beta of the x and y walls (fixed and multipole faces) for this plane's f: loaded
+        // before u and f, so waiting for them does not wait for the plane, and parked in LDS
+        // until the f it belongs to is taken up; every lane loads (from a valid address) and
+        // keeps its value or zero
+        if (fold_x || fold_y) {
+          const T bw = -(T)2 * ih2;   // f - beta / h^2 with beta = 2 b
+          const size_t row = (size_t)(Pfg + 1) * (size_t)(n + 2);
+          const double* bxa = A.bc.b[0] ? A.bc.b[0] : A.bc.b[1];
+          const double* bxb = A.bc.b[1] ? A.bc.b[1] : A.bc.b[0];
+          const double* bya = A.bc.b[2] ? A.bc.b[2] : A.bc.b[3];
+          const double* byb = A.bc.b[3] ? A.bc.b[3] : A.bc.b[2];
+          const bool hx = (wx0 && A.bc.b[0]) || (wx1 && A.bc.b[1]);
+          const bool hy = (gy0 && A.bc.b[2]) || (gy1 && A.bc.b[3]);
+          const double* bxp = wx1 ? bxb : bxa;
+          const double* byp = gy1 ? byb : bya;
+          T dx[R], dy[2];
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        if (in_x && in_y[r] && in_z && !A.zero_in) {
-          const Pair<T> vu = *reinterpret_cast<const Pair<T>*>(uin + fidx(xag, ygv[r], Pg));
-          pu[r][0] = vu.a; pu[r][1] = vu.b;
-        } else {
-          pu[r][0] = pu[r][1] = (T)0;
+          for (int r = 0; r < R; ++r) dx[r] = (T)0;
+          dy[0] = dy[1] = (T)0;
+          if (fold_x) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+              const double v = bxp[row + (size_t)(ygv[r] + 1)];
+              dx[r] = hx ? bw * (T)v : (T)0;
+            }
+          }
+          if (fold_y) {
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+              const double v = byp[row + (size_t)(((xag + e) & nm) + 1)];
+              dy[e] = hy ? bw * (T)v : (T)0;
+            }
+          }
+          if (wx0 || wx1) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) fdx[band][wx1 ? 1 : 0][r] = dx[r];
+          }
+          if (gy0 || gy1) {
+            fdy[gy1 ? 1 : 0][xl][0] = dy[0];
+            fdy[gy1 ? 1 : 0][xl][1] = dy[1];
+          }
         }
-        if (in_x && in_y[r] && in_zf) {
+      }
+      if constexpr (PER) {
+        // (the range tests are trivially true here; written out, they keep the compiler's
+        // register allocation of the periodic passes at its best)
+        const bool in_z = pz || (P >= 0 && P < n);
+        const bool in_zf = pz || (P - 1 >= 0 && P - 1 < n);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if (in_x && in_y[r] && in_z && !A.zero_in) {
+            const Pair<T> vu = *reinterpret_cast<const Pair<T>*>(uin + fidx(xag, ygv[r], Pg));
+            pu[r][0] = vu.a; pu[r][1] = vu.b;
+          } else {
+            pu[r][0] = pu[r][1] = (T)0;
+          }
+          if (in_x && in_y[r] && in_zf) {
+            const Pair<T> vf = *reinterpret_cast<const Pair<T>*>(fin + fidx(xag, ygv[r], Pfg));
+            pf[r][0] = vf.a; pf[r][1] = vf.b;
+          } else {
+            pf[r][0] = pf[r][1] = (T)0;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if (!A.zero_in) {
+            const Pair<T> vu = *reinterpret_cast<const Pair<T>*>(uin + fidx(xag, ygv[r], Pg));
+            pu[r][0] = vu.a; pu[r][1] = vu.b;
+          } else {
+            pu[r][0] = pu[r][1] = (T)0;
+          }
           const Pair<T> vf = *reinterpret_cast<const Pair<T>*>(fin + fidx(xag, ygv[r], Pfg));
           pf[r][0] = vf.a; pf[r][1] = vf.b;
-        } else {
-          pf[r][0] = pf[r][1] = (T)0;
         }
-        if constexpr (!PER) {
-          // a ghost cell's f slot carries beta of its face at the ghost's transverse position
-          if (in_zf) {
-            if (gx0 && in_y[r]) pf[r][1] = beta_of<T>(A.bc, 0, n, ygv[r], Pfg);
-            if (gx1 && in_y[r]) pf[r][0] = beta_of<T>(A.bc, 1, n, ygv[r], Pfg);
-            if (r == 1 && gy0 && in_x) {
-              pf[1][0] = beta_of<T>(A.bc, 2, n, xag, Pfg);
-              pf[1][1] = beta_of<T>(A.bc, 2, n, xag + 1, Pfg);
-            }
-            if (r == 2 && gy1 && in_x) {
-              pf[2][0] = beta_of<T>(A.bc, 3, n, xag, Pfg);
-              pf[2][1] = beta_of<T>(A.bc, 3, n, xag + 1, Pfg);
-            }
+      }
+      if constexpr (!PER) {
+        // the z walls: beta on the first and last plane of the level (two planes per pass;
+        // loaded and applied at once)
+        if (!pz && (Pfg == 0 || Pfg == nm)) {
+          const double* bz = Pfg == 0 ? A.bc.b[4] : A.bc.b[5];
+          if (bz) {
+            const T bw = -(T)2 * ih2;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+              for (int e = 0; e < 2; ++e)
+                pf[r][e] += bw * (T)bz[(size_t)(ygv[r] + 1) * (size_t)(n + 2) + (size_t)(((xag + e) & nm) + 1)];
           }
         }
       }
@@ -310,11 +382,13 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
           if constexpr (PER) {
             return ec[cdx(X, Y, zz)];
           } else {
-            T sg = (T)1;
-            const int Xc = clamp_tap<T>(X, nc, A.bcc, 0, sg);
-            const int Yc = clamp_tap<T>(Y, nc, A.bcc, 2, sg);
-            const int Zc = clamp_tap<T>(zz, nc, A.bcc, 4, sg);
-            return sg * ec[cdx(Xc, Yc, Zc)];
+            // clamped into the domain, with the sign of the wall's rule when clamped (min, max
+            // and selects: no branches around the load)
+            const int Xc = min(max(X, 0), nc - 1), Yc = min(max(Y, 0), nc - 1), Zc = min(max(zz, 0), nc - 1);
+            const T sx = X < 0 ? kcx0 : (X >= nc ? kcx1 : (T)1);
+            const T sy = Y < 0 ? kcy0 : (Y >= nc ? kcy1 : (T)1);
+            const T sz = zz < 0 ? kcz0 : (zz >= nc ? kcz1 : (T)1);
+            return (sx * sy) * (sz * ec[cdx(Xc, Yc, Zc)]);
           }
         };
 #pragma unroll
@@ -325,11 +399,32 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
       }
     };
 
+    // ---- the parked wall terms of the f just taken up into fr
+    auto fold_take = [&]() __attribute__((always_inline)) {
+      if constexpr (!PER) {
+        if (fold_x) {
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const T d0 = fdx[band][0][r], d1 = fdx[band][1][r];
+            fr[r][0] += wx0 ? d0 : (T)0;
+            fr[r][1] += wx1 ? d1 : (T)0;
+          }
+        }
+        if (fold_y) {
+#pragma unroll
+          for (int e = 0; e < 2; ++e) {
+            const T d0 = fdy[0][xl][e], d1 = fdy[1][xl][e];
+            fr[2][e] += gy0 ? d0 : (T)0;
+            fr[1][e] += gy1 ? d1 : (T)0;
+          }
+        }
+      }
+    };
+
     // ---- add the prolonged correction fetched with plane P (parity PARP) to the prefetched u
     auto prolong_apply = [&](int P, auto cPAR) __attribute__((always_inline)) {
       if constexpr (UP) {
         constexpr int PARP = decltype(cPAR)::value;
-        const bool in_z = pz || (P >= 0 && P < n);
         const T wz0 = PARP ? (T)0.75 : (T)0.25, wz1 = PARP ? (T)0.25 : (T)0.75;
         T czv[NTAP];
 #pragma unroll
@@ -339,64 +434,49 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
           const int j = r >> 1;
           const T c = (r & 1) ? (T)0.75 * czv[j + 1] + (T)0.25 * czv[j + 2] : (T)0.25 * czv[j] + (T)0.75 * czv[j + 1];
           const T cl = from_left(c), cr = from_right(c);
-          if (in_x && in_y[r] && in_z) {
-            pu[r][0] += (T)0.25 * cl + (T)0.75 * c;
-            pu[r][1] += (T)0.75 * c + (T)0.25 * cr;
-          }
+          pu[r][0] += (T)0.25 * cl + (T)0.75 * c;
+          pu[r][1] += (T)0.75 * c + (T)0.25 * cr;
         }
       }
     };
 
     int xbuf = 0;
 
-    // ---- ghost cells beside the active cells of colour COL (0 red, 1 black, 2 both) of plane p
-    // (parity PAR, in uc; the planes beside it in um, up; its f in registers when FS < 0, else
-    // in LDS slot FS) set from those cells' current values
-    auto refresh = [&](auto cCOL, auto cPAR, auto cFS, T (&um)[R][2], T (&uc)[R][2], T (&up)[R][2],
-                       int p) __attribute__((always_inline)) {
+    // ---- ghost cells read by the active cells of colour COL (0 red, 1 black, 2 both) of plane p
+    // (parity PAR, in uc; the planes beside it in um, up): y ghost rows and z ghost planes set
+    // to kappa times those cells' current values (x walls are taken in the stencil)
+    auto refresh = [&](auto cCOL, auto cPAR, T (&um)[R][2], T (&uc)[R][2], T (&up)[R][2], int p)
+                       __attribute__((always_inline)) {
       if constexpr (!PER) {
-        constexpr int COL = decltype(cCOL)::value, PAR = decltype(cPAR)::value, FS = decltype(cFS)::value;
-        auto fget = [&](int r, int e) __attribute__((always_inline)) -> T {
-          if constexpr (FS < 0) return fr[r][e];
-          else return e ? fl[FS][r][tid].b : fl[FS][r][tid].a;
-        };
+        constexpr int COL = decltype(cCOL)::value, PAR = decltype(cPAR)::value;
         // does cell e of row r have a colour being refreshed?
         auto sel = [](int r, int e) constexpr { return COL == 2 || ((r + PAR + COL) & 1) == e; };
-        if (wave_x) {
-          static_for<R>([&](auto rr) __attribute__((always_inline)) {
-            constexpr int r = decltype(rr)::value;
-            if constexpr (sel(r, 0)) {   // x = 0 is an even column
-              const T v = from_right(uc[r][0]);
-              if (gx0) uc[r][1] = kx0 * v + fget(r, 1);
-            }
-            if constexpr (sel(r, 1)) {   // x = n-1 is an odd column
-              const T v = from_left(uc[r][1]);
-              if (gx1) uc[r][0] = kx1 * v + fget(r, 0);
-            }
-          });
-        }
         if (wave_y) {
           static_for<2>([&](auto ee) __attribute__((always_inline)) {
             constexpr int e = decltype(ee)::value;
             if constexpr (sel(2, e))
-              if (gy0) uc[1][e] = ky0 * uc[2][e] + fget(1, e);
+              if (gy0) uc[1][e] = ky0 * uc[2][e];
             if constexpr (sel(1, e))
-              if (gy1) uc[2][e] = ky1 * uc[1][e] + fget(2, e);
+              if (gy1) uc[2][e] = ky1 * uc[1][e];
           });
         }
-        if (!pz && (p == 0 || p == nm)) {
-          // the ghost plane beyond z = 0 or z = n-1 (beta from the face arrays)
-          const bool lo = p == 0;
-          const T kz = lo ? kz0 : kz1;
+        // (two separate blocks: a store through a pointer chosen between the two ring planes
+        // would move the ring out of registers)
+        if (!pz && p == 0) {
           static_for<R>([&](auto rr) __attribute__((always_inline)) {
             constexpr int r = decltype(rr)::value;
             static_for<2>([&](auto ee) __attribute__((always_inline)) {
               constexpr int e = decltype(ee)::value;
-              if constexpr (sel(r, e)) {
-                const T g = kz * uc[r][e] + beta_of<T>(A.bc, lo ? 4 : 5, n, (xag + e) & nm, ygv[r]);
-                if (lo) um[r][e] = g;
-                else up[r][e] = g;
-              }
+              if constexpr (sel(r, e)) um[r][e] = kz0 * uc[r][e];
+            });
+          });
+        }
+        if (!pz && p == nm) {
+          static_for<R>([&](auto rr) __attribute__((always_inline)) {
+            constexpr int r = decltype(rr)::value;
+            static_for<2>([&](auto ee) __attribute__((always_inline)) {
+              constexpr int e = decltype(ee)::value;
+              if constexpr (sel(r, e)) up[r][e] = kz1 * uc[r][e];
             });
           });
         }
@@ -409,7 +489,7 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
     auto colour = [&](auto cC, auto cPAR, auto cFS, T (&um)[R][2], T (&uc)[R][2], T (&up)[R][2],
                       int p) __attribute__((always_inline)) {
       constexpr int C = decltype(cC)::value, PAR = decltype(cPAR)::value, FS = decltype(cFS)::value;
-      refresh(cC, cPAR, cFS, um, uc, up, p);
+      refresh(cC, cPAR, um, uc, up, p);
       // the band-edge rows' cells of the other colour, for the bands below and above
       constexpr int q0 = (PAR + C) & 1, qL = (R - 1 + PAR + C) & 1;
       T* xt = reinterpret_cast<T*>(&xch[xbuf][0][0][0]);
@@ -427,9 +507,11 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
         if constexpr (q == 0) {
           xm = from_left(uc[r][1]);
           xp = uc[r][1];
+          if constexpr (!PER) xm = wx0 ? kx0 * c : xm;
         } else {
           xm = uc[r][0];
           xp = from_right(uc[r][0]);
+          if constexpr (!PER) xp = wx1 ? kx1 * c : xp;
         }
         if constexpr (r > 0) ym = uc[r - 1][q]; else ym = below;
         if constexpr (r < R - 1) yp = uc[r + 1][q]; else yp = above;
@@ -449,7 +531,7 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
     auto defect = [&](auto cPAR, auto cFS, T (&um)[R][2], T (&uc)[R][2], T (&up)[R][2], int p)
                       __attribute__((always_inline)) {
       constexpr int PAR = decltype(cPAR)::value, FS = decltype(cFS)::value;
-      refresh(std::integral_constant<int, 2>{}, cPAR, cFS, um, uc, up, p);
+      refresh(std::integral_constant<int, 2>{}, cPAR, um, uc, up, p);
       Pair<T>* xq = &xch[xbuf][0][0][0];
       xq[(band * 2 + 0) * SL + xl] = Pair<T>{uc[0][0], uc[0][1]};
       xq[(band * 2 + 1) * SL + xl] = Pair<T>{uc[R - 1][0], uc[R - 1][1]};
@@ -468,7 +550,8 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
       static_for<R>([&](auto rr) __attribute__((always_inline)) {
         constexpr int r = decltype(rr)::value;
         constexpr int qr_prev = (r + PAR + 1) & 1;   // red cell of row r on plane p-1 (parity PAR^1)
-        dprev[r] = top_prev ? dred[r] : dred[r] - ih2 * uc[r][qr_prev];
+        const T dr = dred_get(r);
+        dprev[r] = top_prev ? dr : dr - ih2 * uc[r][qr_prev];
       });
       static_for<R>([&](auto rr) __attribute__((always_inline)) {
         constexpr int r = decltype(rr)::value;
@@ -483,9 +566,11 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
           if constexpr (q == 0) {
             xm = from_left(uc[r][1]);
             xp = uc[r][1];
+            if constexpr (!PER) xm = wx0 ? kx0 * c : xm;
           } else {
             xm = uc[r][0];
             xp = from_right(uc[r][0]);
+            if constexpr (!PER) xp = wx1 ? kx1 * c : xp;
           }
           if constexpr (r > 0) ym = uc[r - 1][q]; else ym = below[q];
           if constexpr (r < R - 1) yp = uc[r + 1][q]; else yp = above[q];
@@ -496,7 +581,7 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
           } else {
             // the upper neighbour of a red cell on the top plane of a non-periodic axis is the
             // ghost plane (set now); elsewhere it is added at the next step
-            dred[r] = bnd_z1 ? fpair[q] - ((s5 + zp) - (T)6 * c) * ih2 : fpair[q] - (s5 - (T)6 * c) * ih2;
+            dred_set(r, bnd_z1 ? fpair[q] - ((s5 + zp) - (T)6 * c) * ih2 : fpair[q] - (s5 - (T)6 * c) * ih2);
           }
         });
       });
@@ -538,6 +623,11 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
     for (int r = 0; r < R; ++r) {
       u[0][r][0] = pu[r][0]; u[0][r][1] = pu[r][1];
       fr[r][0] = pf[r][0]; fr[r][1] = pf[r][1];
+    }
+    if constexpr (!PER) {
+      if (fold_x || fold_y) {
+        fold_take();
+      }
     }
     // one pipeline step: the plane in ring slot K is P = zstart + t, t = g + K with g a
     // multiple of 6, so P - j sits in slot (K - j) mod 6, has parity (HZ + K + j) mod 2, and
@@ -588,6 +678,11 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
           u[s5][r][0] = pu[r][0]; u[s5][r][1] = pu[r][1];
           fl[Fs4::value][r][tid] = Pair<T>{fr[r][0], fr[r][1]};
           fr[r][0] = pf[r][0]; fr[r][1] = pf[r][1];
+        }
+        if constexpr (!PER) {
+          if (fold_x || fold_y) {
+            fold_take();
+          }
         }
       }
     };
