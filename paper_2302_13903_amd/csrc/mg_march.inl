@@ -132,6 +132,18 @@ struct alignas(2 * sizeof(T)) Pair {
   T a, b;
 };
 
+// MeshBlock storage index split into its x-y part and its z part (disjoint bits, so the index
+// is their sum): the x-y part is fixed per lane and row, the z part is uniform per plane.
+__device__ __forceinline__ unsigned blk_xy(int Lm, int i, int j) {
+  const int mm = (1 << Lm) - 1;
+  return ((spread3((unsigned)(i >> Lm)) | (spread3((unsigned)(j >> Lm)) << 1)) << (3 * Lm)) |
+         (unsigned)(((j & mm) << Lm) | (i & mm));
+}
+__device__ __forceinline__ unsigned blk_z(int Lm, int k) {
+  const int mm = (1 << Lm) - 1;
+  return ((spread3((unsigned)(k >> Lm)) << 2) << (3 * Lm)) | (unsigned)((k & mm) << (2 * Lm));
+}
+
 // Waves per workgroup: 8 (a 64 x 64 tile, 2 waves per SIMD with up to 256 registers per lane;
 // FP32 on 16 waves, a 64 x 128 tile, needs more than the 128 registers that leaves per lane).
 template <typename T>
@@ -179,10 +191,7 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
     const T* __restrict__ uin = reinterpret_cast<const T*>(A.uin);
     T* __restrict__ uout = reinterpret_cast<T*>(A.uout);
     const T* __restrict__ fin = reinterpret_cast<const T*>(A.f);
-    // storage index of cell (x, y, z) of this level and of the coarse level below
-    auto fidx = [&](int x, int y, int z) __attribute__((always_inline)) {
-      return BLK ? bidx(A.Lm, x, y, z) : cidx(L, x, y, z);
-    };
+    // storage index of cell (X, Y, Z) of the coarse level below
     auto cdx = [&](int X, int Y, int Z) __attribute__((always_inline)) {
       return BLK ? lidx(L - 1, A.Lm - 1, X, Y, Z) : cidx(L - 1, X, Y, Z);
     };
@@ -212,6 +221,35 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
       ygv[r] = y & nm;
       out_y[r] = y >= ys && y < ys + A.yo && y < n;
       in_y[r] = py || (y >= 0 && y < n);
+    }
+    // MeshBlock layout: the x-y part of each row's storage index (the z part is added per plane)
+    unsigned rxy[BLK ? R : 1];
+    if constexpr (BLK) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) rxy[r] = blk_xy(A.Lm, xag, ygv[r]);
+    }
+    // storage index of row r of this lane on plane z
+    auto fidr = [&](int r, int z) __attribute__((always_inline)) -> size_t {
+      if constexpr (BLK) return (size_t)(rxy[r] + blk_z(A.Lm, z));
+      else return cidx(L, xag, ygv[r], z);
+    };
+    // up, MeshBlock layout: the x-y part of the coarse taps' storage indices (rows Y0-1 ..
+    // Y0+2 of the lane's coarse column, wrapped or clamped as the taps take them); the coarse
+    // level is in blocks of 2^(Lm-1) cells, or the dense root grid when Lm = 1
+    constexpr int NTAP = R / 2 + 2;
+    unsigned cxy[BLK && UP ? NTAP : 1];
+    if constexpr (BLK && UP) {
+      const int nc = n >> 1, Lc = L - 1;
+      int X = (px ? xag : xa) >> 1;
+      if constexpr (!PER) X = min(max(X, 0), nc - 1);
+      const int Y0 = (py ? ygv[0] : yv[0]) >> 1;
+#pragma unroll
+      for (int i = 0; i < NTAP; ++i) {
+        int Y = Y0 - 1 + i;
+        if (py) Y &= nc - 1;
+        if constexpr (!PER) Y = min(max(Y, 0), nc - 1);
+        cxy[i] = A.Lm == 1 ? (unsigned)((Y << Lc) | X) : blk_xy(A.Lm - 1, X, Y);
+      }
     }
     const int z0 = cz * A.zc;                    // a multiple of 6
     const int zend = min(z0 + A.zc, n);
@@ -245,7 +283,6 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
       else dredl[r][tid] = v;
     };
     T pend[R / 2], stash[R / 2];   // down: row-pair defect sums (black cells of P-4; even plane)
-    constexpr int NTAP = R / 2 + 2;
     T pc[UP ? NTAP : 1][2];    // up: coarse rows Y0-1 .. Y0+2 on the two coarse planes of a fine plane
 #pragma unroll
     for (int s = 0; s < kRing; ++s)
@@ -318,13 +355,13 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           if (in_x && in_y[r] && in_z && !A.zero_in) {
-            const Pair<T> vu = *reinterpret_cast<const Pair<T>*>(uin + fidx(xag, ygv[r], Pg));
+            const Pair<T> vu = *reinterpret_cast<const Pair<T>*>(uin + fidr(r, Pg));
             pu[r][0] = vu.a; pu[r][1] = vu.b;
           } else {
             pu[r][0] = pu[r][1] = (T)0;
           }
           if (in_x && in_y[r] && in_zf) {
-            const Pair<T> vf = *reinterpret_cast<const Pair<T>*>(fin + fidx(xag, ygv[r], Pfg));
+            const Pair<T> vf = *reinterpret_cast<const Pair<T>*>(fin + fidr(r, Pfg));
             pf[r][0] = vf.a; pf[r][1] = vf.b;
           } else {
             pf[r][0] = pf[r][1] = (T)0;
@@ -334,12 +371,12 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           if (!A.zero_in) {
-            const Pair<T> vu = *reinterpret_cast<const Pair<T>*>(uin + fidx(xag, ygv[r], Pg));
+            const Pair<T> vu = *reinterpret_cast<const Pair<T>*>(uin + fidr(r, Pg));
             pu[r][0] = vu.a; pu[r][1] = vu.b;
           } else {
             pu[r][0] = pu[r][1] = (T)0;
           }
-          const Pair<T> vf = *reinterpret_cast<const Pair<T>*>(fin + fidx(xag, ygv[r], Pfg));
+          const Pair<T> vf = *reinterpret_cast<const Pair<T>*>(fin + fidr(r, Pfg));
           pf[r][0] = vf.a; pf[r][1] = vf.b;
         }
       }
@@ -379,7 +416,19 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
           if (py) Y &= nc - 1;
           if (pz) zz &= nc - 1;
           // every face periodic: the wrapped indices are in range (no ghost code compiled)
-          if constexpr (PER) {
+          if constexpr (BLK) {
+            // MeshBlock layout: the lane's x-y part plus the plane's z part
+            const int Zc = PER ? zz : min(max(zz, 0), nc - 1);
+            const size_t ci = (size_t)cxy[i] + (A.Lm == 1 ? ((size_t)Zc << (2 * Lc)) : (size_t)blk_z(A.Lm - 1, Zc));
+            if constexpr (PER) {
+              return ec[ci];
+            } else {
+              const T sx = X < 0 ? kcx0 : (X >= nc ? kcx1 : (T)1);
+              const T sy = Y < 0 ? kcy0 : (Y >= nc ? kcy1 : (T)1);
+              const T sz = zz < 0 ? kcz0 : (zz >= nc ? kcz1 : (T)1);
+              return (sx * sy) * (sz * ec[ci]);
+            }
+          } else if constexpr (PER) {
             return ec[cdx(X, Y, zz)];
           } else {
             // clamped into the domain, with the sign of the wall's rule when clamped (min, max
@@ -665,7 +714,7 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
             if (out_y[r]) {
               typedef T ntv2 __attribute__((ext_vector_type(2)));
               const ntv2 v = {u[s4][r][0], u[s4][r][1]};
-              __builtin_nontemporal_store(v, reinterpret_cast<ntv2*>(uout + fidx(xag, ygv[r], pg)));
+              __builtin_nontemporal_store(v, reinterpret_cast<ntv2*>(uout + fidr(r, pg)));
             }
         }
       }
