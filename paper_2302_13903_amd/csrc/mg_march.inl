@@ -90,30 +90,37 @@ __device__ __forceinline__ void static_for(F&& f) {
 }
 
 // Whole-wave shift by one lane through DPP: wave_shr:1 gives lane i the value of lane i-1,
-// wave_shl:1 the value of lane i+1 (lanes without a source keep their own value).
+// wave_shl:1 the value of lane i+1.  UNTIED: lanes without a source read zero (bound control),
+// which leaves the destination untied from the source (no copy before each move; used by the
+// all-periodic passes); otherwise they keep their own value (the non-periodic passes, whose
+// register allocation fares better with it).  Those lanes, and the edge lanes of each
+// half-wave, hold the outermost columns of a tile, inside its halo.
 constexpr int kDppWaveShr1 = 0x138;
 constexpr int kDppWaveShl1 = 0x130;
 
-template <int CTRL>
-__device__ __forceinline__ float dpp_move(float v) {
-  const int i = __builtin_bit_cast(int, v);
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(i, i, CTRL, 0xf, 0xf, false));
+template <int CTRL, bool UNTIED>
+__device__ __forceinline__ int dpp_move32(int v) {
+  if constexpr (UNTIED) return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, true);
+  else return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, false);
 }
-template <int CTRL>
+template <int CTRL, bool UNTIED>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __builtin_bit_cast(float, dpp_move32<CTRL, UNTIED>(__builtin_bit_cast(int, v)));
+}
+template <int CTRL, bool UNTIED>
 __device__ __forceinline__ double dpp_move(double v) {
   const long long b = __builtin_bit_cast(long long, v);
-  const int lo = (int)(b & 0xffffffffLL), hi = (int)(b >> 32);
-  const int lo2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
-  const int hi2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
+  const int lo2 = dpp_move32<CTRL, UNTIED>((int)(b & 0xffffffffLL));
+  const int hi2 = dpp_move32<CTRL, UNTIED>((int)(b >> 32));
   return __builtin_bit_cast(double, ((long long)hi2 << 32) | (long long)(unsigned)lo2);
 }
-template <typename T>
+template <bool UNTIED, typename T>
 __device__ __forceinline__ T from_left(T v) {   // value of lane - 1
-  return dpp_move<kDppWaveShr1>(v);
+  return dpp_move<kDppWaveShr1, UNTIED>(v);
 }
-template <typename T>
+template <bool UNTIED, typename T>
 __device__ __forceinline__ T from_right(T v) {  // value of lane + 1
-  return dpp_move<kDppWaveShl1>(v);
+  return dpp_move<kDppWaveShl1, UNTIED>(v);
 }
 
 // Ghost rule of a face as ghost = kappa * adjacent + beta: zero gradient kappa = 1, beta = 0;
@@ -237,8 +244,8 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
     // Y0+2 of the lane's coarse column, wrapped or clamped as the taps take them); the coarse
     // level is in blocks of 2^(Lm-1) cells, or the dense root grid when Lm = 1
     constexpr int NTAP = R / 2 + 2;
-    unsigned cxy[BLK && UP ? NTAP : 1];
-    if constexpr (BLK && UP) {
+    unsigned cxy[UP ? NTAP : 1];
+    if constexpr (UP) {
       const int nc = n >> 1, Lc = L - 1;
       int X = (px ? xag : xa) >> 1;
       if constexpr (!PER) X = min(max(X, 0), nc - 1);
@@ -248,7 +255,7 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
         int Y = Y0 - 1 + i;
         if (py) Y &= nc - 1;
         if constexpr (!PER) Y = min(max(Y, 0), nc - 1);
-        cxy[i] = A.Lm == 1 ? (unsigned)((Y << Lc) | X) : blk_xy(A.Lm - 1, X, Y);
+        cxy[i] = !BLK || A.Lm == 1 ? (unsigned)((Y << Lc) | X) : blk_xy(A.Lm - 1, X, Y);
       }
     }
     const int z0 = cz * A.zc;                    // a multiple of 6
@@ -399,8 +406,8 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
         // Trilinear prolongation (weights 1/4, 3/4 per axis) of the coarse correction: the
         // lane's coarse column X, coarse rows Y0-1 .. Y0+2 (rows 2j, 2j+1 of the band take
         // Y0+j-1 .. Y0+j+1) on the coarse planes (zlo, zlo+1) of fine plane P; the x-neighbour
-        // columns come from the lanes beside (an edge lane of a segment gets its own value
-        // back: wrong, but only in the outermost column of the tile, inside the halo).  Fine
+        // columns come from the lanes beside (an edge lane of a segment gets zero or another
+        // band's value: wrong, but only in the outermost column of the tile, inside the halo).  Fine
         // plane 2Z takes coarse planes (Z-1, Z), plane 2Z+1 (Z, Z+1).  Both planes are loaded
         // for every fine plane (cache hits the second time): keeping the shared plane in
         // registers instead makes the loads conditional and the march slower.
@@ -415,29 +422,19 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
           int Y = Y0 - 1 + i;
           if (py) Y &= nc - 1;
           if (pz) zz &= nc - 1;
-          // every face periodic: the wrapped indices are in range (no ghost code compiled)
-          if constexpr (BLK) {
-            // MeshBlock layout: the lane's x-y part plus the plane's z part
-            const int Zc = PER ? zz : min(max(zz, 0), nc - 1);
-            const size_t ci = (size_t)cxy[i] + (A.Lm == 1 ? ((size_t)Zc << (2 * Lc)) : (size_t)blk_z(A.Lm - 1, Zc));
-            if constexpr (PER) {
-              return ec[ci];
-            } else {
-              const T sx = X < 0 ? kcx0 : (X >= nc ? kcx1 : (T)1);
-              const T sy = Y < 0 ? kcy0 : (Y >= nc ? kcy1 : (T)1);
-              const T sz = zz < 0 ? kcz0 : (zz >= nc ? kcz1 : (T)1);
-              return (sx * sy) * (sz * ec[ci]);
-            }
-          } else if constexpr (PER) {
-            return ec[cdx(X, Y, zz)];
+          // the lane's x-y part (wrapped, or clamped into the domain) plus the plane's z part;
+          // every face periodic: the wrapped indices are in range (no ghost code compiled);
+          // otherwise the sign of the wall's rule when clamped (selects: no branches around
+          // the load)
+          const int Zc = PER ? zz : min(max(zz, 0), nc - 1);
+          const size_t ci = (size_t)cxy[i] + (!BLK || A.Lm == 1 ? ((size_t)Zc << (2 * Lc)) : (size_t)blk_z(A.Lm - 1, Zc));
+          if constexpr (PER) {
+            return ec[ci];
           } else {
-            // clamped into the domain, with the sign of the wall's rule when clamped (min, max
-            // and selects: no branches around the load)
-            const int Xc = min(max(X, 0), nc - 1), Yc = min(max(Y, 0), nc - 1), Zc = min(max(zz, 0), nc - 1);
             const T sx = X < 0 ? kcx0 : (X >= nc ? kcx1 : (T)1);
             const T sy = Y < 0 ? kcy0 : (Y >= nc ? kcy1 : (T)1);
             const T sz = zz < 0 ? kcz0 : (zz >= nc ? kcz1 : (T)1);
-            return (sx * sy) * (sz * ec[cdx(Xc, Yc, Zc)]);
+            return (sx * sy) * (sz * ec[ci]);
           }
         };
 #pragma unroll
@@ -482,7 +479,7 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
         for (int r = 0; r < R; ++r) {
           const int j = r >> 1;
           const T c = (r & 1) ? (T)0.75 * czv[j + 1] + (T)0.25 * czv[j + 2] : (T)0.25 * czv[j] + (T)0.75 * czv[j + 1];
-          const T cl = from_left(c), cr = from_right(c);
+          const T cl = from_left<PER>(c), cr = from_right<PER>(c);
           pu[r][0] += (T)0.25 * cl + (T)0.75 * c;
           pu[r][1] += (T)0.75 * c + (T)0.25 * cr;
         }
@@ -554,12 +551,12 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
         const T c = uc[r][q];
         T xm, xp, ym, yp;
         if constexpr (q == 0) {
-          xm = from_left(uc[r][1]);
+          xm = from_left<PER>(uc[r][1]);
           xp = uc[r][1];
           if constexpr (!PER) xm = wx0 ? kx0 * c : xm;
         } else {
           xm = uc[r][0];
-          xp = from_right(uc[r][0]);
+          xp = from_right<PER>(uc[r][0]);
           if constexpr (!PER) xp = wx1 ? kx1 * c : xp;
         }
         if constexpr (r > 0) ym = uc[r - 1][q]; else ym = below;
@@ -613,12 +610,12 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
           const T c = uc[r][q];
           T xm, xp, ym, yp;
           if constexpr (q == 0) {
-            xm = from_left(uc[r][1]);
+            xm = from_left<PER>(uc[r][1]);
             xp = uc[r][1];
             if constexpr (!PER) xm = wx0 ? kx0 * c : xm;
           } else {
             xm = uc[r][0];
-            xp = from_right(uc[r][0]);
+            xp = from_right<PER>(uc[r][0]);
             if constexpr (!PER) xp = wx1 ? kx1 * c : xp;
           }
           if constexpr (r > 0) ym = uc[r - 1][q]; else ym = below[q];
