@@ -314,28 +314,73 @@ constexpr int kTailThreads = 1024;
 // levels 0..l-1, sum of 8^q for q < l = (8^l - 1) / 7.
 __host__ __device__ __forceinline__ constexpr int level_offset(int l) { return ((1 << (3 * l)) - 1) / 7; }
 
-// PER: every face of every description the launch uses is periodic.  Ghosts are then the
+// KIND 1: every face of every description the launch uses is periodic.  Ghosts are then the
 // opposite cells, read by wrapping the index; this leaves the boundary code of the other kinds
 // out of the kernel image, which the tail's many short phases fetch cold otherwise (measured
-// 36 against 98 us for the tail from 16^3).  Same values, same order of operations.
-template <typename T, bool PER>
-__device__ __forceinline__ T lds_nb(const T* u, int n, int L, int i, int j, int k, T uc, const LevelBC& bc) {
-  if (PER) {
+// 36 against 98 us for the tail from 16^3).  KIND 2: no description carries face values (the
+// homogeneous conditions of a V-cycle's coarse levels): a wall's ghost is kappa times the
+// cell's own value, taken by a select after a wrapped (always in range) read, with no
+// boundary branches either.  KIND 0: the general ghost rules.  Same values, same order of
+// operations.
+// The walls of a description without face values: per face, the ghost's factor on the cell's
+// own value (0 for a periodic face: never used).
+template <typename T>
+struct WallRule {
+  T k[6];
+  __device__ __forceinline__ explicit WallRule(const LevelBC& bc) {
+#pragma unroll
+    for (int f = 0; f < 6; ++f)
+      k[f] = bc.kind[f] == BC_PERIODIC ? (T)0 : (bc.kind[f] == BC_ZERO_GRADIENT ? (T)1 : (T)-1);
+  }
+};
+
+template <typename T, int KIND>
+__device__ __forceinline__ T lds_nb(const T* u, int n, int L, int i, int j, int k, T uc, const LevelBC& bc,
+                                    const WallRule<T>& wr) {
+  if (KIND != 0) {
     const int m = n - 1;
-    return ((((u[cidx(L, (i - 1) & m, j, k)] + u[cidx(L, (i + 1) & m, j, k)]) + u[cidx(L, i, (j - 1) & m, k)]) +
-             u[cidx(L, i, (j + 1) & m, k)]) + u[cidx(L, i, j, (k - 1) & m)]) + u[cidx(L, i, j, (k + 1) & m)];
+    T xm = u[cidx(L, (i - 1) & m, j, k)], xp = u[cidx(L, (i + 1) & m, j, k)];
+    T ym = u[cidx(L, i, (j - 1) & m, k)], yp = u[cidx(L, i, (j + 1) & m, k)];
+    T zm = u[cidx(L, i, j, (k - 1) & m)], zp = u[cidx(L, i, j, (k + 1) & m)];
+    if (KIND == 2) {
+      if (i == 0 && wr.k[0] != (T)0) xm = wr.k[0] * uc;
+      if (i == m && wr.k[1] != (T)0) xp = wr.k[1] * uc;
+      if (j == 0 && wr.k[2] != (T)0) ym = wr.k[2] * uc;
+      if (j == m && wr.k[3] != (T)0) yp = wr.k[3] * uc;
+      if (k == 0 && wr.k[4] != (T)0) zm = wr.k[4] * uc;
+      if (k == m && wr.k[5] != (T)0) zp = wr.k[5] * uc;
+    }
+    return ((((xm + xp) + ym) + yp) + zm) + zp;
   }
   const size_t c = cidx(L, i, j, k);
   return neighbour_sum(u, n, L, i, j, k, c, uc, bc);
 }
 
+// KIND 2: a coarse index beyond a wall without values: wrapped (periodic) or clamped to the
+// boundary cell with the sign of the wall's rule.
+template <typename T>
+__device__ __forceinline__ int wall_tap(int c, int nc, int klo, int khi, T& s) {
+  if (c < 0) {
+    if (klo == BC_PERIODIC) return nc - 1;
+    if (klo != BC_ZERO_GRADIENT) s = -s;
+    return 0;
+  }
+  if (c >= nc) {
+    if (khi == BC_PERIODIC) return 0;
+    if (khi != BC_ZERO_GRADIENT) s = -s;
+    return nc - 1;
+  }
+  return c;
+}
+
 // One smoothing sweep on an LDS-resident level: work items enumerate only the cells of the
 // current colour (the x-pair index p picks the pair's cell of that colour), so no lane idles.
-template <typename T, bool PER>
+template <typename T, int KIND>
 __device__ __forceinline__ void tail_smooth(T* u, const T* f, int L, T h2, T omega, const LevelBC& bc) {
   const int n = 1 << L;
   const T inv6 = (T)(1.0 / 6.0);
   const int half = 1 << (3 * L - 1);
+  const WallRule<T> wr(bc);
 #pragma unroll 1
   for (int colour = 0; colour < 2; ++colour) {
 #pragma unroll 1
@@ -344,16 +389,17 @@ __device__ __forceinline__ void tail_smooth(T* u, const T* f, int L, T h2, T ome
       const int i = 2 * p + ((j + k + colour) & 1);
       const int c = (int)cidx(L, i, j, k);
       const T uc = u[c];
-      const T nb = lds_nb<T, PER>(u, n, L, i, j, k, uc, bc);
+      const T nb = lds_nb<T, KIND>(u, n, L, i, j, k, uc, bc, wr);
       u[c] = uc + omega * ((nb - h2 * f[c]) * inv6 - uc);
     }
     __syncthreads();
   }
 }
 
-template <typename T, bool PER>
+template <typename T, int KIND>
 __device__ __forceinline__ void tail_defect_restrict(const T* u, const T* f, T* fc, T* uc0, int L, T ih2, const LevelBC& bc) {
   const int n = 1 << L, Lc = L - 1, nc = n >> 1, nc3 = 1 << (3 * Lc);
+  const WallRule<T> wr(bc);
 #pragma unroll 1
   for (int C = threadIdx.x; C < nc3; C += blockDim.x) {
     const int I = C & (nc - 1), J = (C >> Lc) & (nc - 1), K = C >> (2 * Lc);
@@ -364,7 +410,7 @@ __device__ __forceinline__ void tail_defect_restrict(const T* u, const T* f, T* 
           const int i = 2 * I + a, j = 2 * J + b, k = 2 * K + c3;
           const int c = (int)cidx(L, i, j, k);
           const T ucv = u[c];
-          s += f[c] - (lds_nb<T, PER>(u, n, L, i, j, k, ucv, bc) - (T)6 * ucv) * ih2;
+          s += f[c] - (lds_nb<T, KIND>(u, n, L, i, j, k, ucv, bc, wr) - (T)6 * ucv) * ih2;
         }
     fc[C] = s * (T)0.125;
     uc0[C] = (T)0;
@@ -372,7 +418,7 @@ __device__ __forceinline__ void tail_defect_restrict(const T* u, const T* f, T* 
   __syncthreads();
 }
 
-template <typename T, int CUBIC, bool PER>
+template <typename T, int CUBIC, int KIND>
 __device__ __forceinline__ void tail_prolong(const T* uc, T* uf, int L, const LevelBC& bcc) {
   const int n = 1 << L, n3 = 1 << (3 * L), Lc = L - 1, nc = n >> 1;
 #pragma unroll 1
@@ -392,10 +438,17 @@ __device__ __forceinline__ void tail_prolong(const T* uc, T* uf, int L, const Le
         for (int ax = -1; ax <= 1; ++ax) {
           const T w = wx[ax + 1] * wy[by + 1] * wz[cz + 1];
           if (w == (T)0) continue;
-          if (PER)
+          if (KIND == 1) {
             s += w * uc[cidx(Lc, (I + ax) & (nc - 1), (J + by) & (nc - 1), (K + cz) & (nc - 1))];
-          else
+          } else if (KIND == 2) {
+            T sg = (T)1;
+            const int Ic = wall_tap<T>(I + ax, nc, bcc.kind[0], bcc.kind[1], sg);
+            const int Jc = wall_tap<T>(J + by, nc, bcc.kind[2], bcc.kind[3], sg);
+            const int Kc = wall_tap<T>(K + cz, nc, bcc.kind[4], bcc.kind[5], sg);
+            s += w * (sg * uc[cidx(Lc, Ic, Jc, Kc)]);
+          } else {
             s += w * (inner ? uc[cidx(Lc, I + ax, J + by, K + cz)] : ghost_any(uc, nc, Lc, I + ax, J + by, K + cz, bcc));
+          }
         }
     if (CUBIC) uf[c] = s;
     else uf[c] += s;
@@ -414,7 +467,7 @@ struct TailMeta {
 
 // V-cycle from level `topl` down to 0 and back, with bc_top on level topl and the
 // homogeneous description below.
-template <typename T, bool PER>
+template <typename T, int KIND>
 __device__ __forceinline__ void tail_vcycle(T* base, int total, int topl, const TailMeta& m, const LevelBC& bc_top, int npre,
                             int npost, T omega) {
 #pragma unroll 1
@@ -424,8 +477,8 @@ __device__ __forceinline__ void tail_vcycle(T* base, int total, int topl, const 
     T* f = base + total + level_offset(l);
     const T h2 = (T)m.h2[l];
 #pragma unroll 1
-    for (int it = 0; it < npre; ++it) tail_smooth<T, PER>(u, f, l, h2, omega, bc);
-    tail_defect_restrict<T, PER>(u, f, base + total + level_offset(l - 1), base + level_offset(l - 1), l, (T)(1.0 / m.h2[l]),
+    for (int it = 0; it < npre; ++it) tail_smooth<T, KIND>(u, f, l, h2, omega, bc);
+    tail_defect_restrict<T, KIND>(u, f, base + total + level_offset(l - 1), base + level_offset(l - 1), l, (T)(1.0 / m.h2[l]),
                          bc);
   }
   const LevelBC hom = m.hom;
@@ -435,13 +488,13 @@ __device__ __forceinline__ void tail_vcycle(T* base, int total, int topl, const 
   for (int l = 1; l <= topl; ++l) {
     const LevelBC bc = l == topl ? bc_top : hom;
     T* u = base + level_offset(l);
-    tail_prolong<T, 0, PER>(base + level_offset(l - 1), u, l, hom);
+    tail_prolong<T, 0, KIND>(base + level_offset(l - 1), u, l, hom);
 #pragma unroll 1
-    for (int it = 0; it < npost; ++it) tail_smooth<T, PER>(u, base + total + level_offset(l), l, (T)m.h2[l], omega, bc);
+    for (int it = 0; it < npost; ++it) tail_smooth<T, KIND>(u, base + total + level_offset(l), l, (T)m.h2[l], omega, bc);
   }
 }
 
-template <typename T, bool PER>
+template <typename T, int KIND>
 __global__ void __launch_bounds__(kTailThreads) k_tail(TailArgs a) {
   const T* const* fg = reinterpret_cast<const T* const*>(a.fg);
   T* ug = reinterpret_cast<T*>(a.ug);
@@ -489,10 +542,10 @@ __global__ void __launch_bounds__(kTailThreads) k_tail(TailArgs a) {
   for (int l = fmg ? 1 : top; l <= top; ++l) {
     if (fmg) {
       const LevelBC below = m.phys[l - 1];
-      tail_prolong<T, 1, PER>(base + level_offset(l - 1), base + level_offset(l), l, below);
+      tail_prolong<T, 1, KIND>(base + level_offset(l - 1), base + level_offset(l), l, below);
     }
     const LevelBC here = fmg ? m.phys[l] : m.top;
-    tail_vcycle<T, PER>(base, total, l, m, here, a.npre, a.npost, omega);
+    tail_vcycle<T, KIND>(base, total, l, m, here, a.npre, a.npost, omega);
   }
   const T* u = base + level_offset(top);
   for (int c = threadIdx.x; c < ntop; c += blockDim.x) ug[c] = u[c];
@@ -509,24 +562,37 @@ void launch_tail(const TailArgs& a, hipStream_t s) {
       if (q.kind[f] != BC_PERIODIC) return false;
     return true;
   };
-  bool per = periodic(b.hom) && ((b.mode & TAIL_FMG) != 0 || periodic(b.bc_top));
-  if (b.mode & TAIL_FMG)
-    for (int l = 0; l <= b.top; ++l) per = per && periodic(b.phys[l]);
+  // the wall form when no description carries face values
+  auto valueless = [](const LevelBC& q) {
+    for (int f = 0; f < 6; ++f)
+      if (q.kind[f] != BC_PERIODIC && q.kind[f] != BC_ZERO_GRADIENT && q.b[f]) return false;
+    return true;
+  };
+  const bool fmg = (b.mode & TAIL_FMG) != 0;
+  bool per = periodic(b.hom) && (fmg || periodic(b.bc_top));
+  bool walls = valueless(b.hom) && (fmg || valueless(b.bc_top));
+  if (fmg)
+    for (int l = 0; l <= b.top; ++l) {
+      per = per && periodic(b.phys[l]);
+      walls = walls && valueless(b.phys[l]);
+    }
   if (per)
-    hipLaunchKernelGGL((k_tail<T, true>), dim3(1), dim3(kTailThreads), lds, s, b);
+    hipLaunchKernelGGL((k_tail<T, 1>), dim3(1), dim3(kTailThreads), lds, s, b);
+  else if (walls)
+    hipLaunchKernelGGL((k_tail<T, 2>), dim3(1), dim3(kTailThreads), lds, s, b);
   else
-    hipLaunchKernelGGL((k_tail<T, false>), dim3(1), dim3(kTailThreads), lds, s, b);
+    hipLaunchKernelGGL((k_tail<T, 0>), dim3(1), dim3(kTailThreads), lds, s, b);
 }
 
 int tail_prepare(size_t lds_per_block) {
   const size_t need64 = tail_lds_bytes(4, sizeof(double));
   const size_t need32 = tail_lds_bytes(4, sizeof(float));
-  for (const void* k : {reinterpret_cast<const void*>(&k_tail<float, false>),
-                        reinterpret_cast<const void*>(&k_tail<float, true>)})
+  for (const void* k : {reinterpret_cast<const void*>(&k_tail<float, 0>), reinterpret_cast<const void*>(&k_tail<float, 1>),
+                        reinterpret_cast<const void*>(&k_tail<float, 2>)})
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need32);
   if (lds_per_block < need64) return 3;
-  for (const void* k : {reinterpret_cast<const void*>(&k_tail<double, false>),
-                        reinterpret_cast<const void*>(&k_tail<double, true>)})
+  for (const void* k : {reinterpret_cast<const void*>(&k_tail<double, 0>), reinterpret_cast<const void*>(&k_tail<double, 1>),
+                        reinterpret_cast<const void*>(&k_tail<double, 2>)})
     if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need64) != hipSuccess) {
       (void)hipGetLastError();
       return 3;
