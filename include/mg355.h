@@ -305,8 +305,9 @@ int mg_amr_patch_dims(const mg_amr_mesh *mesh, int lam, int dims[3]);
  *         when no face is fixed).
  *   hist  host, relative composite residual RMS(f - L phi)/RMS(f) (cell-volume weighted) of
  *         the initial guess and after each cycle; n_hist its length.
- * Allocates its workspace per call (device memory, freed before returning) and synchronises
- * `stream`. */
+ * The workspace is the context's: allocated on the first call, grown when a larger mesh needs
+ * more (within the context's HBM budget, else MG_ERR_OOM), kept for later calls and freed by
+ * mg_ctx_destroy.  Synchronises `stream`. */
 int mg_amr_solve(mg_ctx *ctx, const mg_params *p, const mg_amr_mesh *mesh, const mg_bc *bc,
                  const double *const *rho, double *const *phi, double *hist, int *n_hist,
                  void *stream);

@@ -1325,10 +1325,11 @@ int mg_amr_patch_dims(const mg_amr_mesh* m, int lam, int dims[3]) {
 
 }  // extern "C"
 
-// Solve on the refined mesh; memory is allocated per call (the refined path is not pooled).
+// Solve on the refined mesh.  The workspace is the caller's pool (*pool, *pool_cap bytes),
+// grown here when the mesh needs more (at most `room` bytes) and kept for the next call.
 int amr_solve_impl(int device, const mg_params* p, const mg_amr_mesh* m, const mg_bc* bc, const double* const* rho,
                    double* const* phi, double* hist, int* n_hist, void* stream, double* part, double* hpart,
-                   std::string* err) {
+                   double** pool, size_t* pool_cap, size_t room, std::string* err) {
   Plan pl;
   int st = amr_plan(m, pl, err);
   if (st != MG_OK) return st;
@@ -1403,11 +1404,24 @@ int amr_solve_impl(int device, const mg_params* p, const mg_amr_mesh* m, const m
   // multipole moments: per-block partials of every patch, then origin and Q_lm (32 values)
   const size_t mp_part = any_mp ? take((size_t)multipole_box_blocks() * (pl.Lam + 1) * 25) : 0;
   const size_t mp_scratch = any_mp ? take(32) : 0;
-  double* mem = nullptr;
-  if (hipMalloc(&mem, total * sizeof(double)) != hipSuccess) {
-    (void)hipGetLastError();
-    return fail_amr(err, MG_ERR_OOM, "refined-mesh workspace");
+  const size_t need = total * sizeof(double);
+  if (need > *pool_cap) {
+    if (need > room) return fail_amr(err, MG_ERR_OOM, "refined-mesh workspace exceeds the context's HBM budget");
+    if (*pool) {
+      // the old workspace may still be read by earlier work on any stream
+      (void)hipDeviceSynchronize();
+      (void)hipFree(*pool);
+      *pool = nullptr;
+      *pool_cap = 0;
+    }
+    if (hipMalloc(pool, need) != hipSuccess) {
+      (void)hipGetLastError();
+      *pool = nullptr;
+      return fail_amr(err, MG_ERR_OOM, "refined-mesh workspace");
+    }
+    *pool_cap = need;
   }
+  double* mem = *pool;
   (void)hipMemsetAsync(mem, 0, total * sizeof(double), s);
   for (int l = 0; l <= pl.Lam; ++l)
     for (int k = 0; k <= pl.K; ++k) {
@@ -1464,7 +1478,6 @@ int amr_solve_impl(int device, const mg_params* p, const mg_amr_mesh* m, const m
     if (launch_multipole_moments_boxes(boxes, pl.Lam + 1, bc->lmax, bc->use_origin, bc->origin, 0.5, mem + mp_part,
                                        mps, s) != MG_OK) {
       (void)hipStreamSynchronize(s);
-      (void)hipFree(mem);
       return fail_amr(err, MG_ERR_INVALID_ARG, "too many refinement levels for the multipole moments");
     }
     const double G = p->four_pi_g / (4.0 * M_PI);
@@ -1545,7 +1558,6 @@ int amr_solve_impl(int device, const mg_params* p, const mg_amr_mesh* m, const m
   }
   const hipError_t e1 = hipStreamSynchronize(s);
   const hipError_t e2 = hipGetLastError();
-  (void)hipFree(mem);
   if (e1 != hipSuccess || e2 != hipSuccess) return fail_amr(err, MG_ERR_DEVICE, hipGetErrorString(e1 != hipSuccess ? e1 : e2));
   return status;
 }

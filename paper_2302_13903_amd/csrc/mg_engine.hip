@@ -95,6 +95,9 @@ struct mg_ctx {
   // scratch of the operator entry points (ping-pong partner of a caller's array)
   void* op_scratch = nullptr;
   size_t op_scratch_cap = 0;
+  // workspace of the refined-mesh solve (grown on demand, kept across calls)
+  double* amr_ws = nullptr;
+  size_t amr_ws_cap = 0;
   // block-sweep schedules chosen by mg_autotune (or set), keyed by (precision, Lm, Lb)
   std::map<int, BlkTune> blk_tune;
   // MeshBlock layout: sweep the block levels of at least fused_min_n cells per side with the
@@ -122,10 +125,11 @@ struct mg_ctx {
 };
 
 // refined-mesh solve (mg_amr.hip); part: device partials (kMaxPartials x 32 doubles), hpart:
-// host partials (kMaxPartials x (MG_AMR_MAX_LEVELS + 1) doubles)
+// host partials (kMaxPartials x (MG_AMR_MAX_LEVELS + 1) doubles); *pool / *pool_cap: the
+// caller's workspace, grown (up to `room` bytes) when the mesh needs more
 int amr_solve_impl(int device, const mg_params* p, const mg_amr_mesh* m, const mg_bc* bc, const double* const* rho,
                    double* const* phi, double* hist, int* n_hist, void* stream, double* part, double* hpart,
-                   std::string* err);
+                   double** pool, size_t* pool_cap, size_t room, std::string* err);
 
 namespace {
 
@@ -247,7 +251,7 @@ constexpr size_t kFixedBytes = sizeof(double) * (kMaxPartials * 32 + kScal);
 // Would holding `bytes` more (beyond what the context holds now, less `freed`) exceed its budget?
 bool over_budget(const mg_ctx* c, size_t bytes, size_t freed) {
   if (c->hbm_budget == 0) return false;
-  const size_t held = kFixedBytes + c->ws_cap + c->op_scratch_cap - freed;
+  const size_t held = kFixedBytes + c->ws_cap + c->op_scratch_cap + c->amr_ws_cap - freed;
   return held + bytes > c->hbm_budget;
 }
 
@@ -943,6 +947,7 @@ void mg_ctx_destroy(mg_ctx* c) {
   (void)hipDeviceSynchronize();
   if (c->ws) (void)hipFree(c->ws);
   if (c->op_scratch) (void)hipFree(c->op_scratch);
+  if (c->amr_ws) (void)hipFree(c->amr_ws);
   if (c->part) (void)hipFree(c->part);
   if (c->scal) (void)hipFree(c->scal);
   if (c->hscal) (void)hipHostFree(c->hscal);
@@ -1983,7 +1988,14 @@ int mg_amr_solve(mg_ctx* c, const mg_params* p, const mg_amr_mesh* mesh, const m
   if (!c) return MG_ERR_INVALID_ARG;
   if (n_hist) *n_hist = 0;
   std::vector<double> hpart((size_t)kMaxPartials * (MG_AMR_MAX_LEVELS + 1));   // one row of partials per patch
-  return amr_solve_impl(c->device, p, mesh, bc, rho, phi, hist, n_hist, stream, c->part, hpart.data(), &c->err);
+  // what the budget leaves for the refined-mesh workspace (its current size included)
+  size_t room = SIZE_MAX;
+  if (c->hbm_budget) {
+    const size_t other = kFixedBytes + c->ws_cap + c->op_scratch_cap;
+    room = c->hbm_budget > other ? c->hbm_budget - other : 0;
+  }
+  return amr_solve_impl(c->device, p, mesh, bc, rho, phi, hist, n_hist, stream, c->part, hpart.data(), &c->amr_ws,
+                        &c->amr_ws_cap, room, &c->err);
 }
 
 int mg_gravity(mg_ctx* c, const mg_params* p, const mg_bc* bc, const double* phi, const double* rho, double* g,

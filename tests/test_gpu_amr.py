@@ -296,3 +296,30 @@ def test_binary_potential_multipole(mg):
         err.append(((phi[l].cpu().numpy() - ex) / ex)[m.patches[l][m.K].active()])
     e = np.concatenate(err)
     assert math.sqrt(np.mean(e * e)) < 1e-3
+
+
+def test_amr_workspace_kept_across_calls(mg):
+    """The refined-mesh workspace belongs to the context: a small mesh, a larger one (the
+    workspace grows) and the small one again on one context give bitwise the results of fresh
+    contexts; a budget below the workspace's size is refused with MG_ERR_OOM."""
+    def run(ctx, name):
+        NB, nb, boxes = MESHES[name]
+        m, rho, faces = case(NB, nb, boxes, KINDS["fixed"], 5)
+        mesh = mg.amr_mesh(NB, nb, boxes)
+        phi, hist, st = mg.amr_solve(mesh, [dev(r) for r in rho], KINDS["fixed"],
+                                     fixed_b=[None if f is None else dev(f) for f in faces], fixed_cycles=3, ctx=ctx)
+        torch.cuda.synchronize()
+        assert st == mg.MG_OK
+        return [p.cpu().numpy() for p in phi], hist
+
+    shared = mg.Context(0)
+    for name in ("one level", "larger", "one level"):
+        print(f"amr workspace: {name}", flush=True)
+        got, h = run(shared, name)
+        ref, hr = run(mg.Context(0), name)
+        assert h == hr
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b)
+    small = mg.Context(0, hbm_budget=1 << 20)
+    with pytest.raises(mg.MgError, match="OOM"):
+        run(small, "larger")
