@@ -95,6 +95,8 @@ struct mg_ctx {
   // scratch of the operator entry points (ping-pong partner of a caller's array)
   void* op_scratch = nullptr;
   size_t op_scratch_cap = 0;
+  // second stream and events for the split passes of levels with x or y walls
+  MarchAux aux;
   // workspace of the refined-mesh solve (grown on demand, kept across calls)
   double* amr_ws = nullptr;
   size_t amr_ws_cap = 0;
@@ -463,19 +465,17 @@ struct Solver {
       // V(2,2) in two streaming passes: down (two sweeps, restricted defect, coarse correction
       // cleared), the coarse recursion, up (prolonged correction, two sweeps, and the norm of
       // the result when asked); the result lands back in u[l] after the two ping-pongs
-      bool per = true;
-      for (int f = 0; f < 6; ++f) per = per && bc.kind[f] == BC_PERIODIC;
       const bool zin = top_call && zero_start;
       if (timed) kernel_begin();
-      march_down<T>(zin ? nullptr : H.u[l], H.u2[l], H.f[l], H.f[l - 1], H.u[l - 1], n, h, H.omega, bc, s);
+      march_down<T>(zin ? nullptr : H.u[l], H.u2[l], H.f[l], H.f[l - 1], H.u[l - 1], n, h, H.omega, bc, s, 0, &c->aux);
       // algorithmic bytes: u and f read, u written, coarse source and correction written
-      if (timed) kernel_end(march_name<T>(false, false, per), 3 * cellsT + cellsT / 4);
+      if (timed) kernel_end(march_name<T>(false, false, bc), 3 * cellsT + cellsT / 4);
       vcycle(H, l - 1, H.hom, false, false);
       double* npart = want_norm && sizeof(T) == 8 ? part : nullptr;
       if (timed) kernel_begin();
-      const int np = march_up<T>(H.u2[l], H.u[l], H.f[l], H.u[l - 1], H.hom, npart, n, h, H.omega, bc, s);
+      const int np = march_up<T>(H.u2[l], H.u[l], H.f[l], H.u[l - 1], H.hom, npart, n, h, H.omega, bc, s, 0, &c->aux);
       // algorithmic bytes: u, f and the coarse correction read, u written
-      if (timed) kernel_end(march_name<T>(true, npart != nullptr, per), 3 * cellsT + cellsT / 8);
+      if (timed) kernel_end(march_name<T>(true, npart != nullptr, bc), 3 * cellsT + cellsT / 8);
       if (npart) launch_sum_partials(part, np, scal + 2, s);
       return npart != nullptr;
     }
@@ -801,20 +801,19 @@ struct Solver {
       // passes on the large levels, region tiles below
       const bool timed = timed_top && l == H.L && ktiming;
       const double cellsT = (double)cells(l) * sizeof(T);
-      bool per = true;
-      for (int f = 0; f < 6; ++f) per = per && bc.kind[f] == BC_PERIODIC;
       if (timed) kernel_begin();
-      if (big) march_down<T>(H.u[l], H.u2[l], H.f[l], H.f[l - 1], H.u[l - 1], nl, H.h[l], H.omega, bc, s, Lm);
+      if (big) march_down<T>(H.u[l], H.u2[l], H.f[l], H.f[l - 1], H.u[l - 1], nl, H.h[l], H.omega, bc, s, Lm, &c->aux);
       else tile_down<T>(H.u[l], H.u2[l], H.f[l], H.f[l - 1], H.u[l - 1], nl, Lm, Lb, H.h[l], H.omega, bc, s);
-      if (timed) kernel_end(big ? march_name<T>(false, false, per, true) : tile_name<T>(false, false, true),
+      if (timed) kernel_end(big ? march_name<T>(false, false, bc, true) : tile_name<T>(false, false, true),
                             3 * cellsT + cellsT / 4);
       vcycle_blk(H, l - 1, H.hom);
       double* npart = want_norm && sizeof(T) == 8 ? part : nullptr;
       if (timed) kernel_begin();
-      const int np = big ? march_up<T>(H.u2[l], H.u[l], H.f[l], H.u[l - 1], H.hom, npart, nl, H.h[l], H.omega, bc, s, Lm)
+      const int np = big ? march_up<T>(H.u2[l], H.u[l], H.f[l], H.u[l - 1], H.hom, npart, nl, H.h[l], H.omega, bc, s, Lm,
+                                       &c->aux)
                          : tile_up<T>(H.u2[l], H.u[l], H.f[l], H.u[l - 1], H.hom, npart, nl, Lm, Lb, H.h[l], H.omega, bc, s);
       if (timed)
-        kernel_end(big ? march_name<T>(true, npart != nullptr, per, true) : tile_name<T>(true, npart != nullptr, true),
+        kernel_end(big ? march_name<T>(true, npart != nullptr, bc, true) : tile_name<T>(true, npart != nullptr, true),
                    3 * cellsT + cellsT / 8);
       if (npart) launch_sum_partials(part, np, scal + 2, s);
       return npart != nullptr;
@@ -937,6 +936,16 @@ int mg_ctx_create(mg_ctx** out, int device, size_t hbm_budget) {
   // the static scratch's device address, once per device with the device current (a failure
   // is reported by mg_solve_noalloc, the only user)
   c->static_scratch = static_scratch(device, &c->static_scratch_err);
+  // the second stream (default priority) and the fork / join events of the split passes of
+  // levels with x or y walls; without them those passes run as one launch
+  if (hipStreamCreateWithFlags(&c->aux.s2, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->aux.fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->aux.join, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    if (c->aux.s2) (void)hipStreamDestroy(c->aux.s2);
+    if (c->aux.fork) (void)hipEventDestroy(c->aux.fork);
+    c->aux = MarchAux{};
+  }
   *out = c;
   return MG_OK;
 }
@@ -952,6 +961,9 @@ void mg_ctx_destroy(mg_ctx* c) {
   if (c->scal) (void)hipFree(c->scal);
   if (c->hscal) (void)hipHostFree(c->hscal);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->aux.s2) (void)hipStreamDestroy(c->aux.s2);
+  if (c->aux.fork) (void)hipEventDestroy(c->aux.fork);
+  if (c->aux.join) (void)hipEventDestroy(c->aux.join);
   if (c->ev_setup) (void)hipEventDestroy(c->ev_setup);
   if (c->ev_fmg) (void)hipEventDestroy(c->ev_fmg);
   for (auto e : c->ev_cycle) (void)hipEventDestroy(e);

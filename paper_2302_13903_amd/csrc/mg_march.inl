@@ -46,6 +46,7 @@
 // face's rule.
 #include "mg_march.h"
 
+#include <algorithm>
 #include <cstring>
 #include <type_traits>
 #include <utility>
@@ -75,6 +76,7 @@ struct MarchArgs {
   LevelBC bc;        // this level
   LevelBC bcc;       // up: coarse level (homogeneous)
   int n, L, xo, yo, zc, tiles_x, tiles_y, ntiles;
+  int set;           // tiles of this launch: 0 all, 1 the interior ones, 2 the ring at the walls
   int zero_in;
   int Lm;            // BLK: log2 of the MeshBlock side on this level (the coarse level: Lm - 1)
   double h2, ih2, omega;
@@ -158,13 +160,16 @@ constexpr int cfg_W() {
   return 8;
 }
 
-// PER: every face of the level is periodic (the launcher checks), so no boundary code is
-// compiled in.  BLK: the level is in the MeshBlock layout (blocks of 2^A.Lm cells, Morton order);
+// WALLS: 0 = every face of the level is periodic (no boundary code compiled in); 1 = walls
+// only across z (x and y periodic, or a tile that reaches no x or y wall with its halo: no x/y
+// wall code compiled in); 2 = walls on any axis.  The launcher picks per tile.  BLK: the level is in the MeshBlock layout (blocks of 2^A.Lm cells, Morton order);
 // the tile streams across block boundaries as across a dense array (an x-pair never straddles
 // two blocks), and the coarse level is in the layout below (blocks of 2^(A.Lm-1) cells, or the
 // dense root grid when that is one cell).
-template <typename T, int W, bool UP, bool NORM, bool PER, bool BLK>
+template <typename T, int W, bool UP, bool NORM, int WALLS, bool BLK>
 __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
+  constexpr bool PER = WALLS == 0;                // every face periodic
+  constexpr bool XYW = WALLS == 2;                // x or y walls may be in reach
   constexpr int R = kR, SL = kSL, NB = 2 * W, NT = kLanes * W;
   constexpr bool DEF = !UP;                       // down: restricted defect
   constexpr bool DSTAGE = DEF || NORM;            // a defect stage after the sweeps
@@ -174,8 +179,8 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
   // walls with face values: -beta / h^2 of the wall cells of the plane being loaded, added to
   // their f when that plane's f is taken up at the end of the step (x walls: per band, side
   // and row; y walls: per side, column and cell)
-  __shared__ T fdx[PER ? 1 : NB][2][R];
-  __shared__ T fdy[2][PER ? 1 : SL][2];
+  __shared__ T fdx[XYW ? NB : 1][2][R];
+  __shared__ T fdy[2][XYW ? SL : 1][2];
   // non-periodic: the red cells' partial defects carried to the next step (registers are short)
   __shared__ T dredl[PER ? 1 : R][PER ? 1 : NT];
 
@@ -191,9 +196,34 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
   const int tile = (bid & 7) * (nbk >> 3) + (bid >> 3);
   double acc = 0.0;
   if (tile < A.ntiles) {
-    const int tx = tile % A.tiles_x;
-    const int ty = (tile / A.tiles_x) % A.tiles_y;
-    const int cz = tile / (A.tiles_x * A.tiles_y);
+    // tile coordinates and z-chunk: every tile; the interior rectangle [1, tiles_x - 1) x
+    // [1, tiles_y - 1); or the ring around it (bottom row, top row, then the two side columns)
+    int tx, ty, cz;
+    if (A.set == 0) {
+      tx = tile % A.tiles_x;
+      ty = (tile / A.tiles_x) % A.tiles_y;
+      cz = tile / (A.tiles_x * A.tiles_y);
+    } else if (A.set == 1) {
+      const int wi = A.tiles_x - 2, per = wi * (A.tiles_y - 2), t = tile % per;
+      cz = tile / per;
+      tx = 1 + t % wi;
+      ty = 1 + t / wi;
+    } else {
+      const int per = 2 * A.tiles_x + 2 * (A.tiles_y - 2);
+      int q = tile % per;
+      cz = tile / per;
+      if (q < A.tiles_x) {
+        tx = q;
+        ty = 0;
+      } else if (q < 2 * A.tiles_x) {
+        tx = q - A.tiles_x;
+        ty = A.tiles_y - 1;
+      } else {
+        q -= 2 * A.tiles_x;
+        tx = (q & 1) ? A.tiles_x - 1 : 0;
+        ty = 1 + (q >> 1);
+      }
+    }
     const int n = A.n, L = A.L, nm = n - 1;
     const T* __restrict__ uin = reinterpret_cast<const T*>(A.uin);
     T* __restrict__ uout = reinterpret_cast<T*>(A.uout);
@@ -202,8 +232,8 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
     auto cdx = [&](int X, int Y, int Z) __attribute__((always_inline)) {
       return BLK ? lidx(L - 1, A.Lm - 1, X, Y, Z) : cidx(L - 1, X, Y, Z);
     };
-    const bool px = PER || A.bc.kind[0] == BC_PERIODIC;
-    const bool py = PER || A.bc.kind[2] == BC_PERIODIC;
+    const bool px = !XYW || A.bc.kind[0] == BC_PERIODIC;
+    const bool py = !XYW || A.bc.kind[2] == BC_PERIODIC;
     const bool pz = PER || A.bc.kind[4] == BC_PERIODIC;
     const T h2 = (T)A.h2, ih2 = (T)A.ih2, omega = (T)A.omega;
     const T inv6 = (T)(1.0 / 6.0);
@@ -213,9 +243,9 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
     const int xag = xa & nm;
     const bool out_x = xa >= xs && xa < xs + A.xo && xa < n;
     // the lane whose even cell is x = 0, whose odd cell is x = n-1 (beside a wall)
-    const bool wx0 = !PER && !px && xa == 0;
+    const bool wx0 = XYW && !px && xa == 0;
     [[maybe_unused]] const bool in_x = px || (xa >= 0 && xa < n);
-    const bool wx1 = !PER && !px && xa == n - 2;
+    const bool wx1 = XYW && !px && xa == n - 2;
 
     const int ys = ty * A.yo;                    // first output row (even)
     int yv[R], ygv[R];
@@ -248,13 +278,13 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
     if constexpr (UP) {
       const int nc = n >> 1, Lc = L - 1;
       int X = (px ? xag : xa) >> 1;
-      if constexpr (!PER) X = min(max(X, 0), nc - 1);
+      if constexpr (XYW) X = min(max(X, 0), nc - 1);
       const int Y0 = (py ? ygv[0] : yv[0]) >> 1;
 #pragma unroll
       for (int i = 0; i < NTAP; ++i) {
         int Y = Y0 - 1 + i;
         if (py) Y &= nc - 1;
-        if constexpr (!PER) Y = min(max(Y, 0), nc - 1);
+        if constexpr (XYW) Y = min(max(Y, 0), nc - 1);
         cxy[i] = !BLK || A.Lm == 1 ? (unsigned)((Y << Lc) | X) : blk_xy(A.Lm - 1, X, Y);
       }
     }
@@ -264,12 +294,12 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
     const int nsteps = (zend - z0) + 2 * HZ;
     // rows 1 and 2 of this lane are the ghost row beyond y = 0 and its active neighbour, or the
     // active row y = n-1 and the ghost beyond it
-    const bool gy0 = !PER && !py && yv[1] == -1;
-    const bool gy1 = !PER && !py && yv[2] == n;
+    const bool gy0 = XYW && !py && yv[1] == -1;
+    const bool gy1 = XYW && !py && yv[2] == n;
     // does any cell of this wave sit beside a wall in x or y?
     const int wy0 = ys - kHalo + w * 2 * R, wy1 = wy0 + 2 * R - 1;
-    const bool wave_x = !PER && !px && (xs - kHalo < 0 || xs - kHalo + kTX - 1 >= n);
-    const bool wave_y = !PER && !py && (wy0 < 0 || wy1 >= n);
+    const bool wave_x = XYW && !px && (xs - kHalo < 0 || xs - kHalo + kTX - 1 >= n);
+    const bool wave_y = XYW && !py && (wy0 < 0 || wy1 >= n);
     // fold beta of the walls with face values into f (fixed and multipole faces)
     const bool fold_x = wave_x && (A.bc.b[0] || A.bc.b[1]);
     const bool fold_y = wave_y && (A.bc.b[2] || A.bc.b[3]);
@@ -310,7 +340,7 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
     // of plane P
     auto load_plane = [&](int P) __attribute__((always_inline)) {
       const int Pg = P & nm, Pfg = (P - 1) & nm;
-      if constexpr (!PER) {
+      if constexpr (XYW) {
         // beta of the x and y walls (fixed and multipole faces) for this plane's f: loaded
         // before u and f, so waiting for them does not wait for the plane, and parked in LDS
         // until the f it belongs to is taken up; every lane loads (from a valid address) and
@@ -447,7 +477,7 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
 
     // ---- the parked wall terms of the f just taken up into fr
     auto fold_take = [&]() __attribute__((always_inline)) {
-      if constexpr (!PER) {
+      if constexpr (XYW) {
         if (fold_x) {
 #pragma unroll
           for (int r = 0; r < R; ++r) {
@@ -553,11 +583,11 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
         if constexpr (q == 0) {
           xm = from_left<PER>(uc[r][1]);
           xp = uc[r][1];
-          if constexpr (!PER) xm = wx0 ? kx0 * c : xm;
+          if constexpr (XYW) xm = wx0 ? kx0 * c : xm;
         } else {
           xm = uc[r][0];
           xp = from_right<PER>(uc[r][0]);
-          if constexpr (!PER) xp = wx1 ? kx1 * c : xp;
+          if constexpr (XYW) xp = wx1 ? kx1 * c : xp;
         }
         if constexpr (r > 0) ym = uc[r - 1][q]; else ym = below;
         if constexpr (r < R - 1) yp = uc[r + 1][q]; else yp = above;
@@ -612,11 +642,11 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
           if constexpr (q == 0) {
             xm = from_left<PER>(uc[r][1]);
             xp = uc[r][1];
-            if constexpr (!PER) xm = wx0 ? kx0 * c : xm;
+            if constexpr (XYW) xm = wx0 ? kx0 * c : xm;
           } else {
             xm = uc[r][0];
             xp = from_right<PER>(uc[r][0]);
-            if constexpr (!PER) xp = wx1 ? kx1 * c : xp;
+            if constexpr (XYW) xp = wx1 ? kx1 * c : xp;
           }
           if constexpr (r > 0) ym = uc[r - 1][q]; else ym = below[q];
           if constexpr (r < R - 1) yp = uc[r + 1][q]; else yp = above[q];
@@ -670,7 +700,7 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
       u[0][r][0] = pu[r][0]; u[0][r][1] = pu[r][1];
       fr[r][0] = pf[r][0]; fr[r][1] = pf[r][1];
     }
-    if constexpr (!PER) {
+    if constexpr (XYW) {
       if (fold_x || fold_y) {
         fold_take();
       }
@@ -725,7 +755,7 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
           fl[Fs4::value][r][tid] = Pair<T>{fr[r][0], fr[r][1]};
           fr[r][0] = pf[r][0]; fr[r][1] = pf[r][1];
         }
-        if constexpr (!PER) {
+        if constexpr (XYW) {
           if (fold_x || fold_y) {
             fold_take();
           }
@@ -777,10 +807,35 @@ int march_zchunk(int n, int tiles_xy, int hz) {
   return best;
 }
 
+// Interior and wall tiles of a level with x or y walls: the chunk lengths of the two sets
+// (both launches resident together, in one round of kCUs workgroups) that balance the interior
+// march against the wall march, whose steps cost kWallCost times as much.
+constexpr double kWallCost = 1.3;
+
+bool march_split_plan(int n, int nint, int nring, int hz, int& zi, int& zr) {
+  double best = -1.0;
+  const long cap = (long)kMaxPartials * 32 - 8;
+  for (int ci = 1; ci <= (n + 5) / 6; ++ci) {
+    const int zci = ((n + ci - 1) / ci + 5) / 6 * 6;
+    const long ni = (long)nint * ((n + zci - 1) / zci);
+    for (int cr = 1; cr <= (n + 5) / 6; ++cr) {
+      const int zcr = ((n + cr - 1) / cr + 5) / 6 * 6;
+      const long nr = (long)nring * ((n + zcr - 1) / zcr);
+      const long tot = ((ni + 7) / 8 + (nr + 7) / 8) * 8;
+      if (tot > kCUs || tot > cap) continue;
+      const double t = std::max((double)(zci + 2 * hz), kWallCost * (zcr + 2 * hz));
+      if (best < 0 || t < best) best = t, zi = zci, zr = zcr;
+    }
+  }
+  return best > 0;
+}
+
 template <typename T, bool UP, bool NORM, bool BLK>
-int launch_march(MarchArgs A, hipStream_t s) {
+int launch_march(MarchArgs A, hipStream_t s, const MarchAux* aux) {
   bool per = true;
   for (int f = 0; f < 6; ++f) per = per && A.bc.kind[f] == BC_PERIODIC;
+  bool xyper = true;
+  for (int f = 0; f < 4; ++f) xyper = xyper && A.bc.kind[f] == BC_PERIODIC;
   constexpr int W = cfg_W<T>();
   constexpr int HZ = (!UP || NORM) ? 5 : 4;
   A.L = ilog2(A.n);
@@ -788,12 +843,42 @@ int launch_march(MarchArgs A, hipStream_t s) {
   A.yo = kR * 2 * W - 2 * kHalo;
   A.tiles_x = (A.n + A.xo - 1) / A.xo;
   A.tiles_y = (A.n + A.yo - 1) / A.yo;
+  A.set = 0;
+  int zi = 0, zr = 0;
+  if (sizeof(T) == 8 && !per && !xyper && aux && aux->s2 && A.tiles_x >= 3 && A.tiles_y >= 3 &&
+      march_split_plan(A.n, (A.tiles_x - 2) * (A.tiles_y - 2), 2 * A.tiles_x + 2 * (A.tiles_y - 2), HZ, zi, zr)) {
+    // FP64 with x or y walls: the interior tiles (their halos reach no x or y wall) march in
+    // the z-walls-only form on this stream, the ring of wall tiles in the full form on the
+    // second stream, concurrently (fork and join through events); the ring's partials follow
+    // the interior's.  (Measured at 512^3: down 1.18 -> 1.05 ms, up with the norm 1.54 ->
+    // 1.36 ms.  Less than the two forms' own rates promise: the two sets march at different z,
+    // so halo re-reads between them miss L2.  FP32, without spills in the full form, is
+    // slower split: 0.52 -> 0.57 ms.)
+    MarchArgs Ai = A, Ar = A;
+    Ai.set = 1;
+    Ai.zc = zi;
+    Ai.ntiles = (A.tiles_x - 2) * (A.tiles_y - 2) * ((A.n + zi - 1) / zi);
+    const int gi = (Ai.ntiles + 7) / 8 * 8;
+    Ar.set = 2;
+    Ar.zc = zr;
+    Ar.ntiles = (2 * A.tiles_x + 2 * (A.tiles_y - 2)) * ((A.n + zr - 1) / zr);
+    const int gr = (Ar.ntiles + 7) / 8 * 8;
+    if (A.part) Ar.part = A.part + gi;
+    (void)hipEventRecord(aux->fork, s);
+    (void)hipStreamWaitEvent(aux->s2, aux->fork, 0);
+    hipLaunchKernelGGL((k_march<T, W, UP, NORM, 2, BLK>), dim3(gr), dim3(kLanes * W), 0, aux->s2, Ar);
+    hipLaunchKernelGGL((k_march<T, W, UP, NORM, 1, BLK>), dim3(gi), dim3(kLanes * W), 0, s, Ai);
+    (void)hipEventRecord(aux->join, aux->s2);
+    (void)hipStreamWaitEvent(s, aux->join, 0);
+    return gi + gr;
+  }
   A.zc = march_zchunk(A.n, A.tiles_x * A.tiles_y, HZ);
   const int chunks = (A.n + A.zc - 1) / A.zc;
   A.ntiles = A.tiles_x * A.tiles_y * chunks;
   const int grid = (A.ntiles + 7) / 8 * 8;
-  if (per) hipLaunchKernelGGL((k_march<T, W, UP, NORM, true, BLK>), dim3(grid), dim3(kLanes * W), 0, s, A);
-  else hipLaunchKernelGGL((k_march<T, W, UP, NORM, false, BLK>), dim3(grid), dim3(kLanes * W), 0, s, A);
+  if (per) hipLaunchKernelGGL((k_march<T, W, UP, NORM, 0, BLK>), dim3(grid), dim3(kLanes * W), 0, s, A);
+  else if (xyper) hipLaunchKernelGGL((k_march<T, W, UP, NORM, 1, BLK>), dim3(grid), dim3(kLanes * W), 0, s, A);
+  else hipLaunchKernelGGL((k_march<T, W, UP, NORM, 2, BLK>), dim3(grid), dim3(kLanes * W), 0, s, A);
   return grid;
 }
 
@@ -817,47 +902,51 @@ MarchArgs base_args(const T* uin, T* uout, const T* f, int n, double h, double o
 
 template <typename T>
 void march_down(const T* uin, T* uout, const T* f, T* fc, T* uc0, int n, double h, double omega, const LevelBC& bc,
-                hipStream_t s, int Lm) {
+                hipStream_t s, int Lm, const MarchAux* aux) {
   MarchArgs A = base_args(uin, uout, f, n, h, omega, bc);
   A.fc = fc;
   A.uc0 = uc0;
   A.Lm = Lm;
-  if (Lm > 0) launch_march<T, false, false, true>(A, s);
-  else launch_march<T, false, false, false>(A, s);
+  if (Lm > 0) launch_march<T, false, false, true>(A, s, aux);
+  else launch_march<T, false, false, false>(A, s, aux);
 }
 
 template <typename T>
 int march_up(const T* uin, T* uout, const T* f, const T* ec, const LevelBC& bcc, double* part, int n, double h,
-             double omega, const LevelBC& bc, hipStream_t s, int Lm) {
+             double omega, const LevelBC& bc, hipStream_t s, int Lm, const MarchAux* aux) {
   MarchArgs A = base_args(uin, uout, f, n, h, omega, bc);
   A.ec = ec;
   A.bcc = bcc;
   A.part = part;
   A.Lm = Lm;
   if (Lm > 0) {
-    if (part) return launch_march<T, true, true, true>(A, s);
-    launch_march<T, true, false, true>(A, s);
+    if (part) return launch_march<T, true, true, true>(A, s, aux);
+    launch_march<T, true, false, true>(A, s, aux);
     return 0;
   }
-  if (part) return launch_march<T, true, true, false>(A, s);
-  launch_march<T, true, false, false>(A, s);
+  if (part) return launch_march<T, true, true, false>(A, s, aux);
+  launch_march<T, true, false, false>(A, s, aux);
   return 0;
 }
 
 template <typename T>
-std::string march_name(bool up, bool norm, bool per, bool blk) {
+std::string march_name(bool up, bool norm, const LevelBC& bc, bool blk) {
   auto b = [](bool v) { return std::string(v ? "true" : "false"); };
+  bool per = true, xyper = true;
+  for (int f = 0; f < 6; ++f) per = per && bc.kind[f] == BC_PERIODIC;
+  for (int f = 0; f < 4; ++f) xyper = xyper && bc.kind[f] == BC_PERIODIC;
+  const int walls = per ? 0 : (xyper ? 1 : 2);
   return std::string("k_march<") + (sizeof(T) == 8 ? "double" : "float") + ", " + std::to_string(cfg_W<T>()) + ", " +
-         b(up) + ", " + b(up && norm) + ", " + b(per) + ", " + b(blk) + ">";
+         b(up) + ", " + b(up && norm) + ", " + std::to_string(walls) + ", " + b(blk) + ">";
 }
 
 #ifndef MG_MARCH_T
 #error "define MG_MARCH_T (the precision this translation unit instantiates)"
 #endif
 template void march_down<MG_MARCH_T>(const MG_MARCH_T*, MG_MARCH_T*, const MG_MARCH_T*, MG_MARCH_T*, MG_MARCH_T*, int,
-                                     double, double, const LevelBC&, hipStream_t, int);
+                                     double, double, const LevelBC&, hipStream_t, int, const MarchAux*);
 template int march_up<MG_MARCH_T>(const MG_MARCH_T*, MG_MARCH_T*, const MG_MARCH_T*, const MG_MARCH_T*, const LevelBC&,
-                                  double*, int, double, double, const LevelBC&, hipStream_t, int);
-template std::string march_name<MG_MARCH_T>(bool, bool, bool, bool);
+                                  double*, int, double, double, const LevelBC&, hipStream_t, int, const MarchAux*);
+template std::string march_name<MG_MARCH_T>(bool, bool, const LevelBC&, bool);
 
 }  // namespace mg
