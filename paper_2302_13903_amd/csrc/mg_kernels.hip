@@ -334,14 +334,17 @@ struct WallRule {
   }
 };
 
+// LDS index of cell (i, j, k) of a level of 2^L cells per side (32-bit: LDS arrays are small)
+__device__ __forceinline__ int lds_idx(int L, int i, int j, int k) { return (k << (2 * L)) | (j << L) | i; }
+
 template <typename T, int KIND>
 __device__ __forceinline__ T lds_nb(const T* u, int n, int L, int i, int j, int k, T uc, const LevelBC& bc,
                                     const WallRule<T>& wr) {
   if (KIND != 0) {
     const int m = n - 1;
-    T xm = u[cidx(L, (i - 1) & m, j, k)], xp = u[cidx(L, (i + 1) & m, j, k)];
-    T ym = u[cidx(L, i, (j - 1) & m, k)], yp = u[cidx(L, i, (j + 1) & m, k)];
-    T zm = u[cidx(L, i, j, (k - 1) & m)], zp = u[cidx(L, i, j, (k + 1) & m)];
+    T xm = u[lds_idx(L, (i - 1) & m, j, k)], xp = u[lds_idx(L, (i + 1) & m, j, k)];
+    T ym = u[lds_idx(L, i, (j - 1) & m, k)], yp = u[lds_idx(L, i, (j + 1) & m, k)];
+    T zm = u[lds_idx(L, i, j, (k - 1) & m)], zp = u[lds_idx(L, i, j, (k + 1) & m)];
     if (KIND == 2) {
       if (i == 0 && wr.k[0] != (T)0) xm = wr.k[0] * uc;
       if (i == m && wr.k[1] != (T)0) xp = wr.k[1] * uc;
@@ -387,7 +390,7 @@ __device__ __forceinline__ void tail_smooth(T* u, const T* f, int L, T h2, T ome
     for (int t = threadIdx.x; t < half; t += blockDim.x) {
       const int p = t & ((n >> 1) - 1), j = (t >> (L - 1)) & (n - 1), k = t >> (2 * L - 1);
       const int i = 2 * p + ((j + k + colour) & 1);
-      const int c = (int)cidx(L, i, j, k);
+      const int c = lds_idx(L, i, j, k);
       const T uc = u[c];
       const T nb = lds_nb<T, KIND>(u, n, L, i, j, k, uc, bc, wr);
       u[c] = uc + omega * ((nb - h2 * f[c]) * inv6 - uc);
@@ -408,7 +411,7 @@ __device__ __forceinline__ void tail_defect_restrict(const T* u, const T* f, T* 
       for (int b = 0; b < 2; ++b)
         for (int a = 0; a < 2; ++a) {
           const int i = 2 * I + a, j = 2 * J + b, k = 2 * K + c3;
-          const int c = (int)cidx(L, i, j, k);
+          const int c = lds_idx(L, i, j, k);
           const T ucv = u[c];
           s += f[c] - (lds_nb<T, KIND>(u, n, L, i, j, k, ucv, bc, wr) - (T)6 * ucv) * ih2;
         }
@@ -439,13 +442,13 @@ __device__ __forceinline__ void tail_prolong(const T* uc, T* uf, int L, const Le
           const T w = wx[ax + 1] * wy[by + 1] * wz[cz + 1];
           if (w == (T)0) continue;
           if (KIND == 1) {
-            s += w * uc[cidx(Lc, (I + ax) & (nc - 1), (J + by) & (nc - 1), (K + cz) & (nc - 1))];
+            s += w * uc[lds_idx(Lc, (I + ax) & (nc - 1), (J + by) & (nc - 1), (K + cz) & (nc - 1))];
           } else if (KIND == 2) {
             T sg = (T)1;
             const int Ic = wall_tap<T>(I + ax, nc, bcc.kind[0], bcc.kind[1], sg);
             const int Jc = wall_tap<T>(J + by, nc, bcc.kind[2], bcc.kind[3], sg);
             const int Kc = wall_tap<T>(K + cz, nc, bcc.kind[4], bcc.kind[5], sg);
-            s += w * (sg * uc[cidx(Lc, Ic, Jc, Kc)]);
+            s += w * (sg * uc[lds_idx(Lc, Ic, Jc, Kc)]);
           } else {
             s += w * (inner ? uc[cidx(Lc, I + ax, J + by, K + cz)] : ghost_any(uc, nc, Lc, I + ax, J + by, K + cz, bcc));
           }
