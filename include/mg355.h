@@ -158,7 +158,10 @@ int mg_autotune(mg_ctx *ctx, const mg_params *p, int reps);
  * that was set larger, as two streaming passes -- down: two sweeps + restricted defect; up:
  * prolongation + two sweeps + norm -- 0 off, 1 when every face is periodic, 2 always (default))
  * and "tile fp64|fp32 0|1" (1, the default: with V(2,2), each leg of the levels 32^3 .. 128^3
- * that the streaming passes do not take runs as one region-tile launch).  Writes at most cap bytes (NUL-terminated) and returns the length
+ * that the streaming passes do not take runs as one region-tile launch) and "split fp64 0|1"
+ * (1, the default: an FP64 streaming pass of a level with x or y walls runs its interior tiles
+ * and its wall tiles as two launches on the context's second stream and the caller's, joined
+ * before the pass returns; 0: one launch; the serving runtime sets 0).  Writes at most cap bytes (NUL-terminated) and returns the length
  * needed including the NUL.  mg_tuning_set reads the same format (e.g. from a cache file)
  * and rejects schedules the device cannot run. */
 int mg_tuning_get(const mg_ctx *ctx, char *buf, int cap);

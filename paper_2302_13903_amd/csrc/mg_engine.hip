@@ -95,8 +95,10 @@ struct mg_ctx {
   // scratch of the operator entry points (ping-pong partner of a caller's array)
   void* op_scratch = nullptr;
   size_t op_scratch_cap = 0;
-  // second stream and events for the split passes of levels with x or y walls
+  // second stream and events for the split passes of levels with x or y walls, and whether the
+  // solver uses them ("split" setting: -1 = default (on), 0 = off, 1 = on)
   MarchAux aux;
+  int split = -1;
   // workspace of the refined-mesh solve (grown on demand, kept across calls)
   double* amr_ws = nullptr;
   size_t amr_ws_cap = 0;
@@ -388,6 +390,9 @@ struct Solver {
     return march_min_n<T>(c);
   }
 
+  // the second stream of the split passes (null: one launch per pass)
+  const MarchAux* aux_of() const { return c->split == 0 ? nullptr : &c->aux; }
+
   // May a MeshBlock level run the two-sweep streaming passes (the "march" setting for its faces)?
   template <typename T>
   bool march_blk_on(const Hier<T>& H, const LevelBC& bc) const {
@@ -467,13 +472,13 @@ struct Solver {
       // the result when asked); the result lands back in u[l] after the two ping-pongs
       const bool zin = top_call && zero_start;
       if (timed) kernel_begin();
-      march_down<T>(zin ? nullptr : H.u[l], H.u2[l], H.f[l], H.f[l - 1], H.u[l - 1], n, h, H.omega, bc, s, 0, &c->aux);
+      march_down<T>(zin ? nullptr : H.u[l], H.u2[l], H.f[l], H.f[l - 1], H.u[l - 1], n, h, H.omega, bc, s, 0, aux_of());
       // algorithmic bytes: u and f read, u written, coarse source and correction written
       if (timed) kernel_end(march_name<T>(false, false, bc), 3 * cellsT + cellsT / 4);
       vcycle(H, l - 1, H.hom, false, false);
       double* npart = want_norm && sizeof(T) == 8 ? part : nullptr;
       if (timed) kernel_begin();
-      const int np = march_up<T>(H.u2[l], H.u[l], H.f[l], H.u[l - 1], H.hom, npart, n, h, H.omega, bc, s, 0, &c->aux);
+      const int np = march_up<T>(H.u2[l], H.u[l], H.f[l], H.u[l - 1], H.hom, npart, n, h, H.omega, bc, s, 0, aux_of());
       // algorithmic bytes: u, f and the coarse correction read, u written
       if (timed) kernel_end(march_name<T>(true, npart != nullptr, bc), 3 * cellsT + cellsT / 8);
       if (npart) launch_sum_partials(part, np, scal + 2, s);
@@ -802,7 +807,7 @@ struct Solver {
       const bool timed = timed_top && l == H.L && ktiming;
       const double cellsT = (double)cells(l) * sizeof(T);
       if (timed) kernel_begin();
-      if (big) march_down<T>(H.u[l], H.u2[l], H.f[l], H.f[l - 1], H.u[l - 1], nl, H.h[l], H.omega, bc, s, Lm, &c->aux);
+      if (big) march_down<T>(H.u[l], H.u2[l], H.f[l], H.f[l - 1], H.u[l - 1], nl, H.h[l], H.omega, bc, s, Lm, aux_of());
       else tile_down<T>(H.u[l], H.u2[l], H.f[l], H.f[l - 1], H.u[l - 1], nl, Lm, Lb, H.h[l], H.omega, bc, s);
       if (timed) kernel_end(big ? march_name<T>(false, false, bc, true) : tile_name<T>(false, false, true),
                             3 * cellsT + cellsT / 4);
@@ -810,7 +815,7 @@ struct Solver {
       double* npart = want_norm && sizeof(T) == 8 ? part : nullptr;
       if (timed) kernel_begin();
       const int np = big ? march_up<T>(H.u2[l], H.u[l], H.f[l], H.u[l - 1], H.hom, npart, nl, H.h[l], H.omega, bc, s, Lm,
-                                       &c->aux)
+                                       aux_of())
                          : tile_up<T>(H.u2[l], H.u[l], H.f[l], H.u[l - 1], H.hom, npart, nl, Lm, Lb, H.h[l], H.omega, bc, s);
       if (timed)
         kernel_end(big ? march_name<T>(true, npart != nullptr, bc, true) : tile_name<T>(true, npart != nullptr, true),
@@ -1577,6 +1582,7 @@ int mg_tuning_get(const mg_ctx* c, char* buf, int cap) {
     if (c->march[q] >= 0) o << "march " << (q ? "fp32" : "fp64") << " " << c->march[q] << "\n";
     if (c->tile[q] >= 0) o << "tile " << (q ? "fp32" : "fp64") << " " << c->tile[q] << "\n";
   }
+  if (c->split >= 0) o << "split fp64 " << c->split << "\n";
   const std::string t = o.str();
   if (buf && cap > 0) {
     std::strncpy(buf, t.c_str(), (size_t)cap - 1);
@@ -1596,6 +1602,13 @@ int mg_tuning_set(mg_ctx* c, const char* text) {
     if (line.empty()) continue;
     std::istringstream ls(line);
     std::string tag, prec;
+    if (line.rfind("split ", 0) == 0) {
+      int v;
+      if (!(ls >> tag >> prec >> v) || prec != "fp64" || v < 0 || v > 1)
+        return fail(c, MG_ERR_INVALID_ARG, "bad tuning line: " + line);
+      add_misc.push_back({12, v});
+      continue;
+    }
     if (line.rfind("tb ", 0) == 0 || line.rfind("blkz ", 0) == 0 || line.rfind("march ", 0) == 0 ||
         line.rfind("tile ", 0) == 0) {
       int v;
@@ -1643,7 +1656,8 @@ int mg_tuning_set(mg_ctx* c, const char* text) {
     else if (kv.first < 6) c->tblock[kv.first - 4] = kv.second;
     else if (kv.first < 8) c->blk_zmarch[kv.first - 6] = kv.second;
     else if (kv.first < 10) c->march[kv.first - 8] = kv.second;
-    else c->tile[kv.first - 10] = kv.second;
+    else if (kv.first < 12) c->tile[kv.first - 10] = kv.second;
+    else c->split = kv.second;
   }
   return MG_OK;
 }

@@ -106,6 +106,10 @@ int materialise(mg_server* s, Entry* e) {
   const mg_params& p = e->params;
   int st = mg_ctx_create(&e->ctx, s->cfg.device, mg_footprint_bytes(&p));
   if (st != MG_OK) return st;
+  // one stream per worker: the split passes' second stream would share the device's few
+  // hardware queues with the other workers' streams (measured slower in the request mix)
+  st = mg_tuning_set(e->ctx, "split fp64 0\n");
+  if (st != MG_OK) return st;
   st = mg_ctx_reserve(e->ctx, &p);
   if (st != MG_OK) return st;
   if (hipMalloc((void**)&e->slot, (size_t)p.n * p.n * p.n * sizeof(double)) != hipSuccess) {

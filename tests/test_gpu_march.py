@@ -172,6 +172,31 @@ def test_solve_with_march_matches_oracle(mg, n, kinds):
     assert rel(out[2][0], out[0][0]) < 1e-12
 
 
+@pytest.mark.parametrize("n,kinds", [(256, [FIXED] * 6), (512, [ZERO_GRADIENT] * 6),
+                                     (256, [FIXED, FIXED, PERIODIC, PERIODIC, FIXED, FIXED])])
+def test_split_passes_are_bitwise_the_single_launch(mg, n, kinds):
+    """A level with x or y walls runs its interior tiles and its wall tiles as two concurrent
+    launches ("split fp64 1", the default) or as one ("split fp64 0"): the same arithmetic on
+    every cell, so bitwise the same phi.  The residual norms agree to rounding: the cells are
+    grouped into per-workgroup partial sums differently."""
+    print(f"split passes n={n} kinds={kinds}", flush=True)
+    rho = wl.gaussian_clumps(n, 31, remove_mean=False)
+    rng = np.random.default_rng(8)
+    faces = [dev(rng.standard_normal((n, n)) * 0.1) if k == FIXED else None for k in kinds]
+    out = []
+    for split in (1, 0):
+        ctx = mg.Context(0)
+        ctx.set_tuning(f"split fp64 {split}\n")
+        phi, hist, st = mg.solve(dev(rho), 1.0 / n, kinds, fixed_b=faces, fixed_cycles=3, ctx=ctx)
+        torch.cuda.synchronize()
+        assert st == mg.MG_OK
+        out.append((phi.cpu().numpy(), hist))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert len(out[0][1]) == len(out[1][1])
+    for a, b in zip(out[0][1], out[1][1]):
+        assert abs(a - b) <= 1e-13 * b, (out[0][1], out[1][1])
+
+
 @pytest.mark.parametrize("n", [256, 512])
 def test_tolerance_stop_with_march(mg, n):
     """Stopping by tolerance with the norm taken by the finest up pass: the same cycle count

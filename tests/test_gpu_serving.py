@@ -67,9 +67,13 @@ def test_alone_equals_in_mix_bitwise():
 
 
 def test_server_matches_direct_solve():
+    """A served solve equals a direct solve on a context with the server's settings (its
+    contexts run every pass as one launch: "split fp64 0"), bitwise, history included."""
     print("serving vs direct", flush=True)
     rho = clumps(128, 3, False)
-    phi_d, hist_d, st_d = mg.solve(rho, 1.0 / 128, "multipole", tol=1e-10)
+    ctx = mg.Context(0)
+    ctx.set_tuning("split fp64 0\n")
+    phi_d, hist_d, st_d = mg.solve(rho, 1.0 / 128, "multipole", tol=1e-10, ctx=ctx)
     phi_s = torch.zeros_like(rho)
     srv = serving.Server(workers=2)
     (r,) = srv.run([serving.Request(rho=rho, bc="multipole", phi=phi_s, want_hist=True)])
