@@ -63,7 +63,7 @@ def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2302_13903_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h")):
+        if name.endswith((".hip", ".h", ".inl")):
             with open(os.path.join(csrc, name), "rb") as fh:
                 h.update(fh.read())
     return h.hexdigest()[:16]
