@@ -660,18 +660,39 @@ struct Solver {
     return false;
   }
 
-  // done: pre-sweeps of the top level already run by the head pass (result in u2)
-  void fas_cycle(Hier<double>& H, double* const* pbar, int l, int done = 0) {
+  // done: pre-sweeps of the top level already run by the head pass (result in u2).  want_norm
+  // (top level): the two-sweep up pass may leave the sum of squared defects of the result in
+  // scal[2]; returns whether it did.
+  bool fas_cycle(Hier<double>& H, double* const* pbar, int l, int done = 0, bool want_norm = false) {
     if (l == 0) {
       // the single cell with its physical conditions, from the iterate phibar; when no face
       // fixes the zero point any value solves it and phibar is kept (zero correction)
       if (fixes_zero(H.phys[0])) launch_coarsest<double>(H.u[0], H.f[0], H.h[0], H.phys[0], s);
-      return;
+      return false;
     }
     const int n = 1 << l;
     const LevelBC& bc = H.phys[l];
     const bool timed = timed_top && l == H.L && ktiming;
     const double cellsT = (double)cells(l) * sizeof(double);
+    if (done == 0 && march_on<double>(H, l, bc)) {
+      // V(2,2) legs as the two-sweep passes: down (two sweeps, restricted defect, phibar, the
+      // coarse level started from it), steps 5-7 on the coarse level, up (the prolonged
+      // correction psi - phibar, two sweeps, and the norm of the result when asked)
+      if (timed) kernel_begin();
+      march_down_fas<double>(H.u[l], H.u2[l], H.f[l], H.f[l - 1], pbar[l - 1], H.u[l - 1], n, H.h[l], H.omega, bc, s);
+      // algorithmic bytes: u and f read, u written, three coarse arrays written
+      if (timed) kernel_end(march_fas_name<double>(bc), 3 * cellsT + 3 * cellsT / 8);
+      launch_fas_source(pbar[l - 1], H.f[l - 1], n / 2, H.h[l - 1], H.phys[l - 1], s);       // 5
+      fas_cycle(H, pbar, l - 1);                                                             // 6
+      launch_fas_correction(H.u[l - 1], pbar[l - 1], cells(l - 1), s);                       // 7
+      double* npart = want_norm ? part : nullptr;
+      if (timed) kernel_begin();
+      const int np = march_up<double>(H.u2[l], H.u[l], H.f[l], H.u[l - 1], H.hom, npart, n, H.h[l], H.omega, bc, s, 0,
+                                      aux_of());
+      if (timed) kernel_end(march_name<double>(true, npart != nullptr, bc), 3 * cellsT + cellsT / 8);
+      if (npart) launch_sum_partials(part, np, scal + 2, s);
+      return npart != nullptr;
+    }
     const bool streamed = use_fused && H.u2[l] && n >= fused_min_n64;
     // 1: the pre-sweeps; on streamed levels the last one carries steps 2-4 (fused below)
     const int pre = H.npre - done;
@@ -713,15 +734,19 @@ struct Solver {
     }
     cur = fas_sweeps(H, l, cur, post, bc);                                                   // 10
     if (cur != H.u[l]) (void)hipMemcpyAsync(H.u[l], cur, cells(l) * sizeof(double), hipMemcpyDeviceToDevice, s);
+    return false;
   }
 
   // Alg. 2 with FAS in place of the V-cycle.
-  void fas_fmg(Hier<double>& H, double* const* pbar) {
+  // Returns whether the finest level's cycle left the norm of its result in scal[2].
+  bool fas_fmg(Hier<double>& H, double* const* pbar) {
     launch_coarsest<double>(H.u[0], H.f[0], H.h[0], H.phys[0], s);
+    bool normed = false;
     for (int l = 1; l <= H.L; ++l) {
       launch_prolong<double>(H.u[l - 1], H.u[l], 1 << (l - 1), H.phys[l - 1], 1, s);
-      fas_cycle(H, pbar, l);
+      normed = fas_cycle(H, pbar, l, 0, l == H.L);
     }
+    return normed;
   }
 
   // Alg. 2: FMG over all levels with each level's physical description.  norm_top: the
@@ -1180,7 +1205,7 @@ int solve_impl(mg_ctx* c, const mg_params* p, const mg_bc* bc, const double* rho
   bool fmg_normed = false;
   if (p->mode == MG_MODE_FMG) {
     if (fas) {
-      S.fas_fmg(H64, pbar);
+      fmg_normed = S.fas_fmg(H64, pbar);
     } else if (!mixed) {
       // the finest level's FMG V-cycle takes the norm of its result when its up pass can
       fmg_normed = S.fmg(H64, S.march_on<double>(H64, L, phys[L]) ||
@@ -1228,11 +1253,12 @@ int solve_impl(mg_ctx* c, const mg_params* p, const mg_bc* bc, const double* rho
     for (int cyc = 0; cyc < ncyc; ++cyc) {
       S.timed_top = true;
       if (fas) {
-        // as below: the head pass of the next cycle measures this cycle's result
-        S.fas_cycle(H64, pbar, L, head_mode ? 1 : 0);
+        // as below: the head pass of the next cycle measures this cycle's result (or the
+        // two-sweep up pass does)
+        const bool normed = S.fas_cycle(H64, pbar, L, head_mode ? 1 : 0, !head_mode);
         S.head_done = false;
         if (head_mode && cyc + 1 < ncyc) S.head(H64, phys[L]);
-        else S.defect_norm(phi, f64L, nullptr, p->n, p->dx, phys[L], scal + 2);
+        else if (!normed) S.defect_norm(phi, f64L, nullptr, p->n, p->dx, phys[L], scal + 2);
       } else if (head_mode) {
         // the rest of this V-cycle (its first sweep ran in the head pass), then the head of the
         // next one, which measures this cycle's result; after the last allowed cycle the

@@ -39,6 +39,16 @@ template <typename T>
 int march_up(const T* uin, T* uout, const T* f, const T* ec, const LevelBC& bcc, double* part, int n, double h,
              double omega, const LevelBC& bc, hipStream_t s, int Lm = 0, const MarchAux* aux = nullptr);
 
+// Down step of a Full Approximation Scheme cycle (Alg. 3 steps 1-4) in one pass: two sweeps,
+// the defect of the result restricted into fc, the result itself restricted into pbar (phibar)
+// and the coarse level started from it (uc0 = phibar).
+template <typename T>
+void march_down_fas(const T* uin, T* uout, const T* f, T* fc, T* pbar, T* uc0, int n, double h, double omega,
+                    const LevelBC& bc, hipStream_t s);
+
+template <typename T>
+std::string march_fas_name(const LevelBC& bc);
+
 // Names of the kernels as the profiler lists them (the wall form follows bc's kinds; blk:
 // MeshBlock layout).
 template <typename T>

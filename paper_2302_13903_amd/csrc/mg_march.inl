@@ -71,7 +71,8 @@ struct MarchArgs {
   const void* f;
   const void* ec;    // up: coarse correction (n/2)^3
   void* fc;          // down: restricted defect (n/2)^3
-  void* uc0;         // down: coarse correction to clear
+  void* uc0;         // down: coarse correction to clear (FAS: to start from phibar)
+  void* pbar;        // FAS down: the restricted potential phibar
   double* part;      // norm: one partial sum per workgroup
   LevelBC bc;        // this level
   LevelBC bcc;       // up: coarse level (homogeneous)
@@ -166,8 +167,11 @@ constexpr int cfg_W() {
 // the tile streams across block boundaries as across a dense array (an x-pair never straddles
 // two blocks), and the coarse level is in the layout below (blocks of 2^(A.Lm-1) cells, or the
 // dense root grid when that is one cell).
-template <typename T, int W, bool UP, bool NORM, int WALLS, bool BLK>
-__global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
+// FAS (down only, Alg. 3 steps 2-4): the restriction also writes the restricted potential
+// phibar (mean of the 8 children of the pass's result) into A.pbar and starts the coarse level
+// from it (uc0 = phibar instead of 0).
+template <typename T, int W, bool UP, bool NORM, int WALLS, bool BLK, bool FAS>
+__device__ __forceinline__ void march_body(const MarchArgs& A) {
   constexpr bool PER = WALLS == 0;                // every face periodic
   constexpr bool XYW = WALLS == 2;                // x or y walls may be in reach
   constexpr int R = kR, SL = kSL, NB = 2 * W, NT = kLanes * W;
@@ -320,6 +324,7 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
       else dredl[r][tid] = v;
     };
     T pend[R / 2], stash[R / 2];   // down: row-pair defect sums (black cells of P-4; even plane)
+    T stash_u[FAS ? R / 2 : 1];      // FAS: row-pair sums of u on the even plane of a coarse plane
     T pc[UP ? NTAP : 1][2];    // up: coarse rows Y0-1 .. Y0+2 on the two coarse planes of a fine plane
 #pragma unroll
     for (int s = 0; s < kRing; ++s)
@@ -334,6 +339,10 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
     }
 #pragma unroll
     for (int j = 0; j < R / 2; ++j) pend[j] = stash[j] = (T)0;
+    if constexpr (FAS) {
+#pragma unroll
+      for (int j = 0; j < R / 2; ++j) stash_u[j] = (T)0;
+    }
 
     // ---- loads of u on plane P (unless zero on input) and f on plane P-1 (the plane the red
     // stage of the next step works on), beta of the walls folded into f; up: the coarse taps
@@ -679,13 +688,23 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
 #pragma unroll
         for (int j = 0; j < R / 2; ++j) {
           const T sprev = pend[j] + (dprev[2 * j] + dprev[2 * j + 1]);
+          // FAS: the final u of plane p-1 (um) over the same four cells
+          T suprev = (T)0;
+          if constexpr (FAS) suprev = (um[2 * j][0] + um[2 * j][1]) + (um[2 * j + 1][0] + um[2 * j + 1][1]);
           if constexpr (par_prev == 0) {
             stash[j] = sprev;
+            if constexpr (FAS) stash_u[j] = suprev;
           } else {
             if (out_prev && out_x && out_y[2 * j]) {
               const size_t ci = cdx(xag >> 1, ygv[2 * j] >> 1, (p - 1) >> 1);
               fcp[ci] = (stash[j] + sprev) * (T)0.125;
-              ucp[ci] = (T)0;
+              if constexpr (FAS) {
+                const T pb = (stash_u[j] + suprev) * (T)0.125;
+                reinterpret_cast<T*>(A.pbar)[ci] = pb;
+                ucp[ci] = pb;
+              } else {
+                ucp[ci] = (T)0;
+              }
             }
           }
           pend[j] = dblk[2 * j] + dblk[2 * j + 1];
@@ -786,6 +805,17 @@ __global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
   }
 }
 
+template <typename T, int W, bool UP, bool NORM, int WALLS, bool BLK>
+__global__ void __launch_bounds__(kLanes* W) k_march(MarchArgs A) {
+  march_body<T, W, UP, NORM, WALLS, BLK, false>(A);
+}
+
+// The down pass of a Full Approximation Scheme cycle (dense FP64 levels).
+template <typename T, int W, int WALLS>
+__global__ void __launch_bounds__(kLanes* W) k_march_fas(MarchArgs A) {
+  march_body<T, W, false, false, WALLS, false, true>(A);
+}
+
 constexpr int kCUs = 256;
 
 // Planes per workgroup: a multiple of 6 (the ring's period; chunks then start on planes whose
@@ -882,6 +912,27 @@ int launch_march(MarchArgs A, hipStream_t s, const MarchAux* aux) {
   return grid;
 }
 
+// The FAS down pass: one launch over every tile, the wall form chosen by the level's faces.
+template <typename T>
+void launch_march_fas(MarchArgs A, hipStream_t s) {
+  bool per = true, xyper = true;
+  for (int f = 0; f < 6; ++f) per = per && A.bc.kind[f] == BC_PERIODIC;
+  for (int f = 0; f < 4; ++f) xyper = xyper && A.bc.kind[f] == BC_PERIODIC;
+  constexpr int W = cfg_W<T>();
+  A.L = ilog2(A.n);
+  A.xo = kTX - 2 * kHalo;
+  A.yo = kR * 2 * W - 2 * kHalo;
+  A.tiles_x = (A.n + A.xo - 1) / A.xo;
+  A.tiles_y = (A.n + A.yo - 1) / A.yo;
+  A.set = 0;
+  A.zc = march_zchunk(A.n, A.tiles_x * A.tiles_y, 5);
+  A.ntiles = A.tiles_x * A.tiles_y * ((A.n + A.zc - 1) / A.zc);
+  const int grid = (A.ntiles + 7) / 8 * 8;
+  if (per) hipLaunchKernelGGL((k_march_fas<T, W, 0>), dim3(grid), dim3(kLanes * W), 0, s, A);
+  else if (xyper) hipLaunchKernelGGL((k_march_fas<T, W, 1>), dim3(grid), dim3(kLanes * W), 0, s, A);
+  else hipLaunchKernelGGL((k_march_fas<T, W, 2>), dim3(grid), dim3(kLanes * W), 0, s, A);
+}
+
 template <typename T>
 MarchArgs base_args(const T* uin, T* uout, const T* f, int n, double h, double omega, const LevelBC& bc) {
   MarchArgs A;
@@ -912,6 +963,16 @@ void march_down(const T* uin, T* uout, const T* f, T* fc, T* uc0, int n, double 
 }
 
 template <typename T>
+void march_down_fas(const T* uin, T* uout, const T* f, T* fc, T* pbar, T* uc0, int n, double h, double omega,
+                    const LevelBC& bc, hipStream_t s) {
+  MarchArgs A = base_args(uin, uout, f, n, h, omega, bc);
+  A.fc = fc;
+  A.pbar = pbar;
+  A.uc0 = uc0;
+  launch_march_fas<T>(A, s);
+}
+
+template <typename T>
 int march_up(const T* uin, T* uout, const T* f, const T* ec, const LevelBC& bcc, double* part, int n, double h,
              double omega, const LevelBC& bc, hipStream_t s, int Lm, const MarchAux* aux) {
   MarchArgs A = base_args(uin, uout, f, n, h, omega, bc);
@@ -927,6 +988,15 @@ int march_up(const T* uin, T* uout, const T* f, const T* ec, const LevelBC& bcc,
   if (part) return launch_march<T, true, true, false>(A, s, aux);
   launch_march<T, true, false, false>(A, s, aux);
   return 0;
+}
+
+template <typename T>
+std::string march_fas_name(const LevelBC& bc) {
+  bool per = true, xyper = true;
+  for (int f = 0; f < 6; ++f) per = per && bc.kind[f] == BC_PERIODIC;
+  for (int f = 0; f < 4; ++f) xyper = xyper && bc.kind[f] == BC_PERIODIC;
+  return std::string("k_march_fas<") + (sizeof(T) == 8 ? "double" : "float") + ", " + std::to_string(cfg_W<T>()) +
+         ", " + std::to_string(per ? 0 : (xyper ? 1 : 2)) + ">";
 }
 
 template <typename T>
@@ -948,5 +1018,8 @@ template void march_down<MG_MARCH_T>(const MG_MARCH_T*, MG_MARCH_T*, const MG_MA
 template int march_up<MG_MARCH_T>(const MG_MARCH_T*, MG_MARCH_T*, const MG_MARCH_T*, const MG_MARCH_T*, const LevelBC&,
                                   double*, int, double, double, const LevelBC&, hipStream_t, int, const MarchAux*);
 template std::string march_name<MG_MARCH_T>(bool, bool, const LevelBC&, bool);
+template std::string march_fas_name<MG_MARCH_T>(const LevelBC&);
+template void march_down_fas<MG_MARCH_T>(const MG_MARCH_T*, MG_MARCH_T*, const MG_MARCH_T*, MG_MARCH_T*, MG_MARCH_T*,
+                                         MG_MARCH_T*, int, double, double, const LevelBC&, hipStream_t);
 
 }  // namespace mg
