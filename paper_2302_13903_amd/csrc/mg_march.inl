@@ -347,7 +347,9 @@ __device__ __forceinline__ void march_body(const MarchArgs& A) {
     // ---- loads of u on plane P (unless zero on input) and f on plane P-1 (the plane the red
     // stage of the next step works on), beta of the walls folded into f; up: the coarse taps
     // of plane P
-    auto load_plane = [&](int P) __attribute__((always_inline)) {
+    // cTAPS (up): 0 load both coarse planes of P, 1 (P odd) keep the upper plane of P-1 as the
+    // lower one and load the upper, 2 (P even) keep the pair of P-1
+    auto load_plane = [&](int P, auto cTAPS) __attribute__((always_inline)) {
       const int Pg = P & nm, Pfg = (P - 1) & nm;
       if constexpr (XYW) {
         // beta of the x and y walls (fixed and multipole faces) for this plane's f: loaded
@@ -447,9 +449,11 @@ __device__ __forceinline__ void march_body(const MarchArgs& A) {
         // Y0+j-1 .. Y0+j+1) on the coarse planes (zlo, zlo+1) of fine plane P; the x-neighbour
         // columns come from the lanes beside (an edge lane of a segment gets zero or another
         // band's value: wrong, but only in the outermost column of the tile, inside the halo).  Fine
-        // plane 2Z takes coarse planes (Z-1, Z), plane 2Z+1 (Z, Z+1).  Both planes are loaded
-        // for every fine plane (cache hits the second time): keeping the shared plane in
-        // registers instead makes the loads conditional and the march slower.
+        // plane 2Z takes coarse planes (Z-1, Z), plane 2Z+1 (Z, Z+1), so the fine planes 2Z+1
+        // and 2Z+2 take the same pair (also where the planes wrap or are clamped): an odd plane
+        // loads one new coarse plane, an even one none (the parity is a template constant of
+        // each pipeline step).
+        constexpr int TAPS = decltype(cTAPS)::value;
         const T* __restrict__ ec = reinterpret_cast<const T*>(A.ec);
         const int nc = n >> 1, Lc = L - 1;
         const int X = (px ? xag : xa) >> 1;
@@ -476,10 +480,18 @@ __device__ __forceinline__ void march_body(const MarchArgs& A) {
             return (sx * sy) * (sz * ec[ci]);
           }
         };
+        if constexpr (TAPS == 0) {
 #pragma unroll
-        for (int i = 0; i < NTAP; ++i) {
-          pc[i][0] = tap(i, zlo);
-          pc[i][1] = tap(i, zlo + 1);
+          for (int i = 0; i < NTAP; ++i) {
+            pc[i][0] = tap(i, zlo);
+            pc[i][1] = tap(i, zlo + 1);
+          }
+        } else if constexpr (TAPS == 1) {
+#pragma unroll
+          for (int i = 0; i < NTAP; ++i) {
+            pc[i][0] = pc[i][1];
+            pc[i][1] = tap(i, zlo + 1);
+          }
         }
       }
     };
@@ -712,7 +724,7 @@ __device__ __forceinline__ void march_body(const MarchArgs& A) {
       }
     };
 
-    load_plane(zstart);
+    load_plane(zstart, std::integral_constant<int, 0>{});
     prolong_apply(zstart, std::integral_constant<int, HZ & 1>{});
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -732,7 +744,8 @@ __device__ __forceinline__ void march_body(const MarchArgs& A) {
       const int t = g + K;
       if (t >= nsteps) return;
       const int P = zstart + t;
-      if (t + 1 < nsteps) load_plane(P + 1);   // prefetch; consumed at the end of the step
+      // prefetch; consumed at the end of the step
+      if (t + 1 < nsteps) load_plane(P + 1, std::integral_constant<int, ((HZ + K + 1) & 1) ? 1 : 2>{});
       constexpr int s0 = K, s1 = (K + 5) % 6, s2 = (K + 4) % 6, s3 = (K + 3) % 6, s4 = (K + 2) % 6,
                     s5 = (K + 1) % 6;
       using I0 = std::integral_constant<int, 0>;

@@ -194,8 +194,10 @@ def test_split_passes_match_the_single_launch(mg, n, kinds):
         out.append((phi.cpu().numpy(), hist))
     assert rel(out[0][0], out[1][0]) < 1e-13
     assert len(out[0][1]) == len(out[1][1])
+    # norms of defects of two phi equal to rounding: equal up to the residual's round-off floor
+    fl = floor_of(out[1][0], rho, False)
     for a, b in zip(out[0][1], out[1][1]):
-        assert abs(a - b) <= 1e-12 * b, (out[0][1], out[1][1])
+        assert abs(a - b) <= 1e-12 * b + fl, (out[0][1], out[1][1], fl)
 
 
 @pytest.mark.parametrize("n", [256, 512])
