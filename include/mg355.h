@@ -161,7 +161,10 @@ int mg_autotune(mg_ctx *ctx, const mg_params *p, int reps);
  * that the streaming passes do not take runs as one region-tile launch) and "split fp64 0|1"
  * (1, the default: an FP64 streaming pass of a level with x or y walls runs its interior tiles
  * and its wall tiles as two launches on the context's second stream and the caller's, joined
- * before the pass returns; 0: one launch; the serving runtime sets 0).  Writes at most cap bytes (NUL-terminated) and returns the length
+ * before the pass returns; 0: one launch; the serving runtime sets 0) and "inner fp32 k"
+ * (precision MG_PREC_MIXED on grids above the LDS tail: k = 1..4 FP32 V-cycles per outer
+ * defect-correction step, each outer step then contracting the residual as k V-cycles do;
+ * unset: chosen per step, see mg_last_inner).  Writes at most cap bytes (NUL-terminated) and returns the length
  * needed including the NUL.  mg_tuning_set reads the same format (e.g. from a cache file)
  * and rejects schedules the device cannot run. */
 int mg_tuning_get(const mg_ctx *ctx, char *buf, int cap);
@@ -211,6 +214,16 @@ int mg_solve_simple(mg_ctx *ctx, int n, const double *rho, int bc_kind, double d
  * residual norm); *n = number of cycles (up to cap). */
 int mg_last_timing(const mg_ctx *ctx, double *setup_ms, double *fmg_ms, double *cycle_ms,
                    int cap, int *n);
+
+/* FP32 V-cycles the last mg_solve on this context ran inside its outer defect-correction
+ * steps (precision MG_PREC_MIXED; 0 for FP64).  Each outer step is one entry of the residual
+ * history and runs "inner fp32 k" V-cycles when that tuning line is set; otherwise, in a
+ * solve to a tolerance, as many as the residual contraction per V-cycle observed so far
+ * (taken 1.5 times as slow) says are still needed to reach it, at most 3 (one per step in a
+ * fixed-cycle solve).
+ *   inner_cycles  host int, output.
+ * Returns MG_ERR_INVALID_ARG for a null argument. */
+int mg_last_inner(const mg_ctx *ctx, int *inner_cycles);
 
 /* Kernel-level timing of the finest-level smoothing kernels of the V-cycles of the last
  * mg_solve, from HIP events recorded on the solve stream around each launch.  Enabled by

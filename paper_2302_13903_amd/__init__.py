@@ -97,6 +97,12 @@ class Context:
         self._lib.mg_last_timing(self.handle, ctypes.byref(setup), ctypes.byref(fmg), cyc, cap, ctypes.byref(n))
         return setup.value, fmg.value, [cyc[i] for i in range(min(n.value, cap))]
 
+    def last_inner(self) -> int:
+        """FP32 V-cycles of the last mixed-precision solve (see mg_last_inner)."""
+        k = ctypes.c_int()
+        self.check(self._lib.mg_last_inner(self.handle, ctypes.byref(k)), "mg_last_inner")
+        return k.value
+
     def set_kernel_timing(self, on: bool):
         self._lib.mg_set_kernel_timing(self.handle, 1 if on else 0)
 

@@ -111,6 +111,7 @@ def lib():
         "mg_solve_noalloc": (i, [_vp, ctypes.POINTER(MgParams), ctypes.POINTER(MgBC), _vp, _vp, _dp, _ip, _vp]),
         "mg_solve_simple": (i, [_vp, i, _vp, i, d, d, _vp, _dp, _ip, _vp]),
         "mg_last_timing": (i, [_vp, _dp, _dp, _dp, i, _ip]),
+        "mg_last_inner": (i, [_vp, _ip]),
         "mg_set_kernel_timing": (i, [_vp, i]),
         "mg_kernel_timing": (i, [_vp, i, _ip, _dp, _dp, ctypes.c_char_p, i]),
         "mg_multipole_moments": (i, [_vp, i, d, _vp, i, i, _dp, _dp, _dp, _vp]),

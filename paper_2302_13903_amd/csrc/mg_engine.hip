@@ -99,6 +99,10 @@ struct mg_ctx {
   // solver uses them ("split" setting: -1 = default (on), 0 = off, 1 = on)
   MarchAux aux;
   int split = -1;
+  // mixed precision: FP32 V-cycles per outer defect-correction step ("inner" setting; -1 =
+  // chosen per step by the solver), and how many the last solve ran
+  int inner = -1;
+  int last_inner = 0;
   // workspace of the refined-mesh solve (grown on demand, kept across calls)
   double* amr_ws = nullptr;
   size_t amr_ws_cap = 0;
@@ -1037,6 +1041,12 @@ int mg_kernel_timing(const mg_ctx* c, int index, int* launches, double* total_ms
   return MG_OK;
 }
 
+int mg_last_inner(const mg_ctx* c, int* inner_cycles) {
+  if (!c || !inner_cycles) return MG_ERR_INVALID_ARG;
+  *inner_cycles = c->last_inner;
+  return MG_OK;
+}
+
 int mg_last_timing(const mg_ctx* c, double* setup_ms, double* fmg_ms, double* cycle_ms, int cap, int* n) {
   if (!c) return MG_ERR_INVALID_ARG;
   if (setup_ms) *setup_ms = c->setup_ms;
@@ -1249,9 +1259,25 @@ int solve_impl(mg_ctx* c, const mg_params* p, const mg_bc* bc, const double* rho
   int slow = 0, done_cycles = 0;
   double* phi_cur = phi;     // mixed mode alternates phi with its ping-pong partner
   double* phi_oth = y.phi2 == (size_t)-1 ? nullptr : reinterpret_cast<double*>(ws + y.phi2);
+  // mixed: FP32 V-cycles per outer step -- the "inner" setting, else (to a tolerance) as many
+  // as the residual contraction per V-cycle seen so far says are still needed, at most 3 (one
+  // in fixed-cycle runs).  The contraction is taken 1.5 times as slow as seen (it slows as the
+  // iterate converges): one V-cycle too many costs less than another outer step with its FP64
+  // update pass.  The count of the whole solve is kept for mg_last_inner
+  c->last_inner = 0;
+  double rho_est = 0.1;
   if (p->fixed_cycles > 0 || r > p->tol) {
     for (int cyc = 0; cyc < ncyc; ++cyc) {
       S.timed_top = true;
+      int inner = 1;
+      if (mixed && !(Lb < 0 && L == H32.T_top)) {
+        if (c->inner > 0) {
+          inner = c->inner;
+        } else if (p->fixed_cycles <= 0 && r > p->tol) {
+          const double m = std::ceil(std::log(p->tol / r) / std::log(std::min(0.5, 1.5 * rho_est)));
+          inner = (int)std::min(3.0, std::max(1.0, m));
+        }
+      }
       if (fas) {
         // as below: the head pass of the next cycle measures this cycle's result (or the
         // two-sweep up pass does)
@@ -1271,7 +1297,7 @@ int solve_impl(mg_ctx* c, const mg_params* p, const mg_bc* bc, const double* rho
         if (!S.vcycle_blk(H64, L, phys[L], true)) S.defect_norm(phi, f64L, nullptr, p->n, p->dx, phys[L], scal + 2);
       } else if (mixed && Lb >= 0) {
         launch_zero(H32.u[L], n3 * sizeof(float), s);
-        S.vcycle_blk(H32, L, hom);
+        for (int k = 0; k < inner; ++k) S.vcycle_blk(H32, L, hom);
         launch_add_f32(phi, H32.u[L], n3, s);
         S.defect_norm(phi, f64L, H32.f[L], p->n, p->dx, phys[L], scal + 2);
       } else if (!mixed) {
@@ -1285,8 +1311,10 @@ int solve_impl(mg_ctx* c, const mg_params* p, const mg_bc* bc, const double* rho
           // the correction starts from zero: the first sweep does not read it (or the
           // V-cycle clears it when its first pass cannot skip the read)
           S.zero_start = true;
-          S.vcycle(H32, L, hom, true, false);
-          S.zero_start = false;
+          for (int k = 0; k < inner; ++k) {
+            S.vcycle(H32, L, hom, true, false);
+            S.zero_start = false;
+          }
         }
         if (phi_oth) {
           // phi += e and the FP64 defect (with its FP32 copy and norm) in one streaming pass
@@ -1305,6 +1333,10 @@ int solve_impl(mg_ctx* c, const mg_params* p, const mg_bc* bc, const double* rho
       const double rn = rel(c->hscal[2]);
       hist[nh++] = rn;
       ++done_cycles;
+      if (mixed) {
+        c->last_inner += inner;
+        if (r > 0 && rn > 0 && rn < r) rho_est = std::min(0.5, std::max(0.01, std::pow(rn / r, 1.0 / inner)));
+      }
       if (p->fixed_cycles > 0) { r = rn; continue; }
       slow = rn > 0.9 * r ? slow + 1 : 0;
       r = rn;
@@ -1609,6 +1641,7 @@ int mg_tuning_get(const mg_ctx* c, char* buf, int cap) {
     if (c->tile[q] >= 0) o << "tile " << (q ? "fp32" : "fp64") << " " << c->tile[q] << "\n";
   }
   if (c->split >= 0) o << "split fp64 " << c->split << "\n";
+  if (c->inner > 0) o << "inner fp32 " << c->inner << "\n";
   const std::string t = o.str();
   if (buf && cap > 0) {
     std::strncpy(buf, t.c_str(), (size_t)cap - 1);
@@ -1633,6 +1666,13 @@ int mg_tuning_set(mg_ctx* c, const char* text) {
       if (!(ls >> tag >> prec >> v) || prec != "fp64" || v < 0 || v > 1)
         return fail(c, MG_ERR_INVALID_ARG, "bad tuning line: " + line);
       add_misc.push_back({12, v});
+      continue;
+    }
+    if (line.rfind("inner ", 0) == 0) {
+      int v;
+      if (!(ls >> tag >> prec >> v) || prec != "fp32" || v < 1 || v > 4)
+        return fail(c, MG_ERR_INVALID_ARG, "bad tuning line: " + line);
+      add_misc.push_back({13, v});
       continue;
     }
     if (line.rfind("tb ", 0) == 0 || line.rfind("blkz ", 0) == 0 || line.rfind("march ", 0) == 0 ||
@@ -1683,7 +1723,8 @@ int mg_tuning_set(mg_ctx* c, const char* text) {
     else if (kv.first < 8) c->blk_zmarch[kv.first - 6] = kv.second;
     else if (kv.first < 10) c->march[kv.first - 8] = kv.second;
     else if (kv.first < 12) c->tile[kv.first - 10] = kv.second;
-    else c->split = kv.second;
+    else if (kv.first == 12) c->split = kv.second;
+    else c->inner = kv.second;
   }
   return MG_OK;
 }
