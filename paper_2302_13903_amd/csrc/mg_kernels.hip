@@ -433,6 +433,41 @@ __device__ __forceinline__ void tail_prolong(const T* uc, T* uf, int L, const Le
     if (CUBIC) { cub_w(i & 1, wx); cub_w(j & 1, wy); cub_w(k & 1, wz); }
     else { lin_w(i & 1, wx); lin_w(j & 1, wy); lin_w(k & 1, wz); }
     T s = (T)0;
+    if (!CUBIC && KIND != 0) {
+      // trilinear: on each axis the tap of weight zero is the third (even fine index) or the
+      // first (odd), so the two others are slots o, o+1 with o = the index's parity; each
+      // axis's two coarse indices (wrapped, or clamped with the wall's sign) are taken once,
+      // and the eight terms are summed in the order of the 27-tap loop below
+      const int ox = i & 1, oy = j & 1, oz = k & 1;
+      int xo[2], yo[2], zo[2];
+      T xs[2], ys[2], zs[2];
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        xs[d] = ys[d] = zs[d] = (T)1;
+        if (KIND == 1) {
+          xo[d] = (I - 1 + ox + d) & (nc - 1);
+          yo[d] = ((J - 1 + oy + d) & (nc - 1)) << Lc;
+          zo[d] = ((K - 1 + oz + d) & (nc - 1)) << (2 * Lc);
+        } else {
+          xo[d] = wall_tap<T>(I - 1 + ox + d, nc, bcc.kind[0], bcc.kind[1], xs[d]);
+          yo[d] = wall_tap<T>(J - 1 + oy + d, nc, bcc.kind[2], bcc.kind[3], ys[d]) << Lc;
+          zo[d] = wall_tap<T>(K - 1 + oz + d, nc, bcc.kind[4], bcc.kind[5], zs[d]) << (2 * Lc);
+        }
+      }
+#pragma unroll
+      for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+        for (int by = 0; by < 2; ++by)
+#pragma unroll
+          for (int ax = 0; ax < 2; ++ax) {
+            const T w = wx[ox + ax] * wy[oy + by] * wz[oz + cz];
+            const T v = uc[zo[cz] | yo[by] | xo[ax]];
+            if (KIND == 1) s += w * v;
+            else s += w * (((xs[ax] * ys[by]) * zs[cz]) * v);
+          }
+      uf[c] += s;
+      continue;
+    }
 #pragma unroll
     for (int cz = -1; cz <= 1; ++cz)
 #pragma unroll
