@@ -55,6 +55,7 @@ def _load():
                                  ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                  ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp, _dp, _ip]
     lib.oracle_set_scheme.argtypes = [vp, ctypes.c_int]
+    lib.oracle_set_coarse_rule.argtypes = [vp, ctypes.c_int]
     lib.oracle_state_create.restype = vp
     lib.oracle_state_create.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _ip,
                                         ctypes.POINTER(_dp), ctypes.c_int, ctypes.c_int, _dp,
@@ -188,6 +189,14 @@ class State:
         if getattr(self, "_s", None):
             self._lib.oracle_state_destroy(self._s)
             self._s = None
+
+    def set_coarse_rule(self, rule: str):
+        """Conditions of the coarse-level corrections: "homogeneous" (the default: each face's
+        homogeneous counterpart) or "literal" (Sec. 2.3.6 word for word: zero-fixed unless
+        periodic)."""
+        if rule not in ("homogeneous", "literal"):
+            raise ValueError(rule)
+        self._lib.oracle_set_coarse_rule(self._s, 1 if rule == "literal" else 0)
 
     def fmg(self):
         self._lib.oracle_fmg(self._s)

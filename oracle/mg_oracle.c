@@ -657,6 +657,17 @@ void oracle_fmg(ostate *s) { fmg(s); }
 /* scheme of the iterations: 0 = correction scheme (Alg. 1), 1 = FAS (Alg. 3) */
 void oracle_set_scheme(ostate *s, int fas) { s->fas = fas != 0; }
 
+/* Conditions of the corrections on the coarser levels: 0 = the homogeneous counterpart above
+ * (the reading the solver follows), 1 = Sec. 2.3.6 taken literally, zero-fixed on every face
+ * that is not periodic (zero-gradient faces too).  The literal rule is kept so that tests can
+ * show why it is not the one followed; no solve uses it by default. */
+void oracle_set_coarse_rule(ostate *s, int literal) {
+  s->hom = homogeneous(&s->phys[s->L]);
+  if (literal)
+    for (int f = 0; f < 6; ++f)
+      if (s->hom.kind[f] == OR_ZERO_GRADIENT) s->hom.kind[f] = OR_FIXED;
+}
+
 /* one V-cycle (or FAS iteration) on the finest level; returns the relative residual after it */
 double oracle_vcycle(ostate *s) {
   cycle(s, s->L);
