@@ -212,8 +212,20 @@ void launch_restrict(const Tin* uf, Tout* uc, int nc, hipStream_t s) {
 
 // cubic = 0: uf += trilinear(uc) (eq. trilinear, Alg. 1 steps 5-6);
 // cubic = 1: uf  = tricubic(uc)  (FMG prolongation, Alg. 2 step 3).
-// One work item per coarse cell: it gathers the 3x3x3 coarse neighbourhood once (ghost_any()
-// near faces) and writes its 8 children as four 2-cell row segments.
+// One work item per coarse cell: it gathers the 3x3x3 coarse neighbourhood once (through the
+// ghost rules only in the first and last rows and planes) and writes its 8 children as four
+// 2-cell row segments.
+// One-dimensional prolongation of the coarse values a, b, c at offsets -1, 0, +1 to the lower
+// (upper = 0) or upper child, with the weights of lin_w / cub_w (zero weights left out).
+template <typename T, int CUBIC>
+__device__ __forceinline__ T interp3(int upper, T a, T b, T c) {
+  if (CUBIC) {
+    return upper ? ((T)(-3.0 / 32.0) * a + (T)(30.0 / 32.0) * b) + (T)(5.0 / 32.0) * c
+                 : ((T)(5.0 / 32.0) * a + (T)(30.0 / 32.0) * b) + (T)(-3.0 / 32.0) * c;
+  }
+  return upper ? (T)0.75 * b + (T)0.25 * c : (T)0.25 * a + (T)0.75 * b;
+}
+
 template <typename T, int CUBIC>
 __global__ void __launch_bounds__(kBlock) k_prolong(const T* __restrict__ uc, T* __restrict__ uf, int Lc,
                                                      LevelBC bcc) {
@@ -223,48 +235,98 @@ __global__ void __launch_bounds__(kBlock) k_prolong(const T* __restrict__ uc, T*
   const int I = (int)(C & (size_t)(nc - 1));
   const int J = (int)((C >> Lc) & (size_t)(nc - 1));
   const int K = (int)(C >> (2 * Lc));
-  const bool inner = I > 0 && I < nc - 1 && J > 0 && J < nc - 1 && K > 0 && K < nc - 1;
-  T v[3][3][3];
+  // res[zc][yc][xc]: child (2I + xc, 2J + yc, 2K + zc), each the sum over the taps (cz, by, ax)
+  // in that order of (wx * wy * wz) * tap (the same terms in the same order in both branches)
+  T res[2][2][2];
+  if (J > 0 && J < nc - 1 && K > 0 && K < nc - 1) {
+    // rows inside in y and z (every row of the grid has its two x-boundary cells, so these
+    // must not leave the fast path): the 27 taps read directly, the x-neighbour beyond an x
+    // face given by that face's rule -- the wrapped cell, the cell itself (zero gradient) or
+    // 2b - u (a value b on the face) -- as the ghost rules give it; every weight a constant
+    const int Im = I > 0 ? I - 1 : nc - 1, Ip = I < nc - 1 ? I + 1 : 0;
+    const bool wlo = I == 0 && bcc.kind[0] != BC_PERIODIC, whi = I == nc - 1 && bcc.kind[1] != BC_PERIODIC;
+    T v[3][3][3];
 #pragma unroll
-  for (int cz = 0; cz < 3; ++cz)
+    for (int cz = 0; cz < 3; ++cz)
 #pragma unroll
-    for (int by = 0; by < 3; ++by)
+      for (int by = 0; by < 3; ++by) {
+        const int Jr = J + by - 1, Kr = K + cz - 1;
+        const size_t row = cidx(Lc, 0, Jr, Kr);
+        const T u0 = uc[row + (size_t)I];
+        T um = uc[row + (size_t)Im], up = uc[row + (size_t)Ip];
+        if (wlo) um = bcc.kind[0] == BC_ZERO_GRADIENT ? u0 : (T)(2.0 * face_b(bcc, 0, nc, Jr, Kr)) - u0;
+        if (whi) up = bcc.kind[1] == BC_ZERO_GRADIENT ? u0 : (T)(2.0 * face_b(bcc, 1, nc, Jr, Kr)) - u0;
+        v[cz][by][0] = um;
+        v[cz][by][1] = u0;
+        v[cz][by][2] = up;
+      }
+    // the weights are a product of one-dimensional ones: interpolate in x (nine rows), then in
+    // y (three planes), then in z -- 114 multiply-adds for the eight children instead of 216
+    T ex[3][3][2], ey[3][2][2];
 #pragma unroll
-      for (int ax = 0; ax < 3; ++ax)
-        v[cz][by][ax] = inner ? uc[cidx(Lc, I + ax - 1, J + by - 1, K + cz - 1)]
-                              : ghost_any(uc, nc, Lc, I + ax - 1, J + by - 1, K + cz - 1, bcc);
+    for (int cz = 0; cz < 3; ++cz)
+#pragma unroll
+      for (int by = 0; by < 3; ++by)
+#pragma unroll
+        for (int xc = 0; xc < 2; ++xc) ex[cz][by][xc] = interp3<T, CUBIC>(xc, v[cz][by][0], v[cz][by][1], v[cz][by][2]);
+#pragma unroll
+    for (int cz = 0; cz < 3; ++cz)
+#pragma unroll
+      for (int yc = 0; yc < 2; ++yc)
+#pragma unroll
+        for (int xc = 0; xc < 2; ++xc) ey[cz][yc][xc] = interp3<T, CUBIC>(yc, ex[cz][0][xc], ex[cz][1][xc], ex[cz][2][xc]);
+#pragma unroll
+    for (int zc = 0; zc < 2; ++zc)
+#pragma unroll
+      for (int yc = 0; yc < 2; ++yc)
+#pragma unroll
+        for (int xc = 0; xc < 2; ++xc) res[zc][yc][xc] = interp3<T, CUBIC>(zc, ey[0][yc][xc], ey[1][yc][xc], ey[2][yc][xc]);
+  } else {
+    // the first and last rows and planes: one tap at a time through the ghost rules (a loop,
+    // so the ghost code is in the kernel once), added to all eight children
+#pragma unroll
+    for (int zc = 0; zc < 2; ++zc)
+#pragma unroll
+      for (int yc = 0; yc < 2; ++yc)
+#pragma unroll
+        for (int xc = 0; xc < 2; ++xc) res[zc][yc][xc] = (T)0;
+#pragma unroll 1
+    for (int t = 0; t < 27; ++t) {
+      const int ax = t % 3, by = (t / 3) % 3, cz = t / 9;
+      const T val = ghost_any(uc, nc, Lc, I + ax - 1, J + by - 1, K + cz - 1, bcc);
+#pragma unroll
+      for (int zc = 0; zc < 2; ++zc)
+#pragma unroll
+        for (int yc = 0; yc < 2; ++yc)
+#pragma unroll
+          for (int xc = 0; xc < 2; ++xc) {
+            T wx[3], wy[3], wz[3];
+            if (CUBIC) { cub_w<T>(xc, wx); cub_w<T>(yc, wy); cub_w<T>(zc, wz); }
+            else { lin_w<T>(xc, wx); lin_w<T>(yc, wy); lin_w<T>(zc, wz); }
+            // the weights of this tap (selects: no runtime-indexed arrays)
+            const T a = ax == 0 ? wx[0] : (ax == 1 ? wx[1] : wx[2]);
+            const T b = by == 0 ? wy[0] : (by == 1 ? wy[1] : wy[2]);
+            const T c = cz == 0 ? wz[0] : (cz == 1 ? wz[1] : wz[2]);
+            if (!CUBIC && (a == (T)0 || b == (T)0 || c == (T)0)) continue;
+            res[zc][yc][xc] += (a * b * c) * val;
+          }
+    }
+  }
+  // the two x-children are adjacent (even index first): one vector access per child row; the
+  // FMG result is written past the caches (it is read again only by the next pass, and kept
+  // out of L2 it leaves room there for the coarse rows the neighbouring workgroups read:
+  // 455 -> 360 us at 512^3)
+  typedef T tv2 __attribute__((ext_vector_type(2)));
 #pragma unroll
   for (int zc = 0; zc < 2; ++zc)
 #pragma unroll
     for (int yc = 0; yc < 2; ++yc) {
-      T wz[3], wy[3];
-      if (CUBIC) { cub_w<T>(zc, wz); cub_w<T>(yc, wy); }
-      else { lin_w<T>(zc, wz); lin_w<T>(yc, wy); }
-      T out[2];
-#pragma unroll
-      for (int xc = 0; xc < 2; ++xc) {
-        T wx[3];
-        if (CUBIC) cub_w<T>(xc, wx);
-        else lin_w<T>(xc, wx);
-        T acc = (T)0;
-#pragma unroll
-        for (int cz = 0; cz < 3; ++cz)
-#pragma unroll
-          for (int by = 0; by < 3; ++by)
-#pragma unroll
-            for (int ax = 0; ax < 3; ++ax) {
-              if (!CUBIC && (wx[ax] == (T)0 || wy[by] == (T)0 || wz[cz] == (T)0)) continue;
-              acc += (wx[ax] * wy[by] * wz[cz]) * v[cz][by][ax];
-            }
-        out[xc] = acc;
-      }
-      const size_t f0 = cidx(L, 2 * I, 2 * J + yc, 2 * K + zc);
+      tv2* fp = reinterpret_cast<tv2*>(uf + cidx(L, 2 * I, 2 * J + yc, 2 * K + zc));
       if (CUBIC) {
-        uf[f0] = out[0];
-        uf[f0 + 1] = out[1];
+        __builtin_nontemporal_store(tv2{res[zc][yc][0], res[zc][yc][1]}, fp);
       } else {
-        uf[f0] += out[0];
-        uf[f0 + 1] += out[1];
+        const tv2 o = *fp;
+        *fp = tv2{o.x + res[zc][yc][0], o.y + res[zc][yc][1]};
       }
     }
 }
