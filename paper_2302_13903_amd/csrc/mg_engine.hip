@@ -697,6 +697,23 @@ struct Solver {
       if (npart) launch_sum_partials(part, np, scal + 2, s);
       return npart != nullptr;
     }
+    if (done == 0 && n < fused_min_n64 && tile_on<double>(H, l)) {
+      // a small level: each V(2,2) leg in one region-tile launch -- down (two sweeps,
+      // restricted defect, phibar, the coarse level started from it), steps 5-7 on the coarse
+      // level, up (the prolonged correction psi - phibar, two sweeps, the norm when asked)
+      if (timed) kernel_begin();
+      tile_down_fas<double>(H.u[l], H.u2[l], H.f[l], H.f[l - 1], pbar[l - 1], H.u[l - 1], n, H.h[l], H.omega, bc, s);
+      if (timed) kernel_end("k_tile_leg<double, false, false, false, true>", 3 * cellsT + 3 * cellsT / 8);
+      launch_fas_source(pbar[l - 1], H.f[l - 1], n / 2, H.h[l - 1], H.phys[l - 1], s);       // 5
+      fas_cycle(H, pbar, l - 1);                                                             // 6
+      launch_fas_correction(H.u[l - 1], pbar[l - 1], cells(l - 1), s);                       // 7
+      double* npart = want_norm ? part : nullptr;
+      if (timed) kernel_begin();
+      const int np = tile_up<double>(H.u2[l], H.u[l], H.f[l], H.u[l - 1], H.hom, npart, n, 0, 0, H.h[l], H.omega, bc, s);
+      if (timed) kernel_end(tile_name<double>(true, npart != nullptr), 3 * cellsT + cellsT / 8);
+      if (npart) launch_sum_partials(part, np, scal + 2, s);
+      return npart != nullptr;
+    }
     const bool streamed = use_fused && H.u2[l] && n >= fused_min_n64;
     // 1: the pre-sweeps; on streamed levels the last one carries steps 2-4 (fused below)
     const int pre = H.npre - done;

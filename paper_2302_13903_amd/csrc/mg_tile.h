@@ -23,6 +23,13 @@ template <typename T>
 void tile_down(const T* uin, T* uout, const T* f, T* fc, T* uc0, int n, int Lm, int Lb, double h, double omega,
                const LevelBC& bc, hipStream_t s);
 
+// The down step of a Full Approximation Scheme cycle (Alg. 3 steps 2-4; dense FP64 levels):
+// as tile_down, and phibar (the mean of the 8 children of the swept u) written to pbar and to
+// uc0, the coarse level's starting iterate.
+template <typename T>
+void tile_down_fas(const T* uin, T* uout, const T* f, T* fc, T* pbar, T* uc0, int n, double h, double omega,
+                   const LevelBC& bc, hipStream_t s);
+
 // Up step (Alg. 1 steps 5-7) in one launch: u += trilinear(ec) (ec's ghosts from the
 // homogeneous description bcc), then two sweeps (uin -> uout).  part != nullptr: one partial
 // sum of squared defects of the result per workgroup (returns their number, else 0).

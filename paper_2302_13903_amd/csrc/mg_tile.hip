@@ -45,7 +45,8 @@ struct TileArgs {
   const void* f;
   const void* ec;    // up: coarse correction
   void* fc;          // down: restricted defect
-  void* uc0;         // down: coarse correction to clear
+  void* uc0;         // down: coarse correction to clear (FAS: to start from phibar)
+  void* pbar;        // FAS down: the restricted potential phibar
   double* part;      // up with norm: one partial sum per workgroup
   LevelBC bc;        // this level
   LevelBC bcc;       // up: coarse level (homogeneous)
@@ -99,7 +100,9 @@ __device__ __forceinline__ T coarse_hom(const TileArgs& A, const T* __restrict__
   return s * ec[coarse_idx<BLK>(A, Ic, Jc, Kc)];
 }
 
-template <typename T, bool UP, bool NORM, bool BLK>
+// FAS (down, dense; Alg. 3 steps 2-4): the restriction also writes phibar, the mean of the 8
+// children of the swept u, into A.pbar and starts the coarse level from it (uc0 = phibar).
+template <typename T, bool UP, bool NORM, bool BLK, bool FAS = false>
 __global__ void __launch_bounds__(kThreads) k_tile_leg(TileArgs A) {
   __shared__ T tile[TV];
   __shared__ T ctile[UP ? CV : 1];
@@ -219,7 +222,20 @@ __global__ void __launch_bounds__(kThreads) k_tile_leg(TileArgs A) {
           for (int a = 0; a < 2; ++a) s += defect_at(2 * cx + a, 2 * cy + b, 2 * cz + c);
       const size_t ci = coarse_idx<BLK>(A, (ox >> 1) + cx, (oy >> 1) + cy, (oz >> 1) + cz);
       fc[ci] = s * (T)0.125;
-      uc0[ci] = (T)0;
+      if constexpr (FAS) {
+        T su = (T)0;
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) su += tile[((2 * cz + c + H) * WY + (2 * cy + b + H)) * WX + (2 * cx + a + H)];
+        const T pb = su * (T)0.125;
+        reinterpret_cast<T*>(A.pbar)[ci] = pb;
+        uc0[ci] = pb;
+      } else {
+        uc0[ci] = (T)0;
+      }
     }
   }
   double acc = 0.0;
@@ -280,6 +296,16 @@ void tile_down(const T* uin, T* uout, const T* f, T* fc, T* uc0, int n, int Lm, 
 }
 
 template <typename T>
+void tile_down_fas(const T* uin, T* uout, const T* f, T* fc, T* pbar, T* uc0, int n, double h, double omega,
+                   const LevelBC& bc, hipStream_t s) {
+  TileArgs A = base_args(uin, uout, f, n, 0, h, omega, bc);
+  A.fc = fc;
+  A.pbar = pbar;
+  A.uc0 = uc0;
+  hipLaunchKernelGGL((k_tile_leg<T, false, false, false, true>), dim3(regions(n)), dim3(kThreads), 0, s, A);
+}
+
+template <typename T>
 int tile_up(const T* uin, T* uout, const T* f, const T* ec, const LevelBC& bcc, double* part, int n, int Lm, int Lb,
             double h, double omega, const LevelBC& bc, hipStream_t s) {
   (void)Lb;
@@ -308,6 +334,8 @@ template void tile_down<double>(const double*, double*, const double*, double*, 
                                 const LevelBC&, hipStream_t);
 template void tile_down<float>(const float*, float*, const float*, float*, float*, int, int, int, double, double,
                                const LevelBC&, hipStream_t);
+template void tile_down_fas<double>(const double*, double*, const double*, double*, double*, double*, int, double,
+                                    double, const LevelBC&, hipStream_t);
 template int tile_up<double>(const double*, double*, const double*, const double*, const LevelBC&, double*, int, int,
                              int, double, double, const LevelBC&, hipStream_t);
 template int tile_up<float>(const float*, float*, const float*, const float*, const LevelBC&, double*, int, int, int,
