@@ -473,6 +473,11 @@ __device__ __forceinline__ void march_body(const MarchArgs& A) {
           const size_t ci = (size_t)cxy[i] + (!BLK || A.Lm == 1 ? ((size_t)Zc << (2 * Lc)) : (size_t)blk_z(A.Lm - 1, Zc));
           if constexpr (PER) {
             return ec[ci];
+          } else if constexpr (!XYW) {
+            // x and y taps wrapped into the domain: only a z wall's sign (the same value as
+            // the general form, whose x and y factors are 1 here)
+            const T sz = zz < 0 ? kcz0 : (zz >= nc ? kcz1 : (T)1);
+            return sz * ec[ci];
           } else {
             const T sx = X < 0 ? kcx0 : (X >= nc ? kcx1 : (T)1);
             const T sy = Y < 0 ? kcy0 : (Y >= nc ? kcy1 : (T)1);
