@@ -80,10 +80,15 @@ __device__ inline double nbsum(const double* __restrict__ u, const Dims& d, cons
   return ((((xm + xp) + ym) + yp) + zm) + zp;
 }
 
+// Cell (x, y, z) of work item t < cells(d).  32-bit arithmetic: amr_plan admits patches of
+// fewer than 2^31 cells only (a 64-bit division costs several times a 32-bit one, and the
+// small kernels and the single-workgroup stages decode an index per item and phase).
 __device__ inline void cell_of(size_t t, const Dims& d, int& x, int& y, int& z) {
-  x = (int)(t % d.n[0]);
-  y = (int)((t / d.n[0]) % d.n[1]);
-  z = (int)(t / ((size_t)d.n[0] * d.n[1]));
+  const unsigned tt = (unsigned)t, n0 = (unsigned)d.n[0], n1 = (unsigned)d.n[1];
+  const unsigned q = tt / n0;
+  x = (int)(tt - q * n0);
+  y = (int)(q % n1);
+  z = (int)(q / n1);
 }
 
 // ---- physical ghosts of the root patch (Sec. 2.3.6): filled axis by axis (x, then y over the
@@ -102,21 +107,22 @@ __device__ inline void fill_phys_body(double* __restrict__ u, const Dims& d, con
   const int n0 = d.n[0] + 2, n1 = d.n[1] + 2, n2 = d.n[2] + 2;
   const size_t f0 = (size_t)n1 * n2, f1 = (size_t)n0 * n2, f2 = (size_t)n0 * n1;
   int p[3];
+  // (32-bit decoding, as cell_of)
   if (t < 2 * f0) {
     p[0] = t < f0 ? -1 : d.n[0];
-    t %= f0;
-    p[1] = (int)(t % n1) - 1;
-    p[2] = (int)(t / n1) - 1;
+    const unsigned r = (unsigned)(t < f0 ? t : t - f0);
+    p[1] = (int)(r % (unsigned)n1) - 1;
+    p[2] = (int)(r / (unsigned)n1) - 1;
   } else if ((t -= 2 * f0) < 2 * f1) {
     p[1] = t < f1 ? -1 : d.n[1];
-    t %= f1;
-    p[0] = (int)(t % n0) - 1;
-    p[2] = (int)(t / n0) - 1;
+    const unsigned r = (unsigned)(t < f1 ? t : t - f1);
+    p[0] = (int)(r % (unsigned)n0) - 1;
+    p[2] = (int)(r / (unsigned)n0) - 1;
   } else if ((t -= 2 * f1) < 2 * f2) {
     p[2] = t < f2 ? -1 : d.n[2];
-    t %= f2;
-    p[0] = (int)(t % n0) - 1;
-    p[1] = (int)(t / n0) - 1;
+    const unsigned r = (unsigned)(t < f2 ? t : t - f2);
+    p[0] = (int)(r % (unsigned)n0) - 1;
+    p[1] = (int)(r / (unsigned)n0) - 1;
   } else {
     return;
   }
@@ -169,9 +175,10 @@ __device__ inline void cons_body(const Cons& A, int axis, size_t t) {
   const int t1a = axis == 0 ? 1 : 0, t2a = axis == 2 ? 1 : 2;
   const int nf1 = A.df.n[t1a], nf2 = A.df.n[t2a];
   if (t >= (size_t)2 * nf1 * nf2) return;
-  const int side = (int)(t / ((size_t)nf1 * nf2));
-  const int r = (int)(t % ((size_t)nf1 * nf2));
-  const int j1 = r % nf1, j2 = r / nf1;
+  const unsigned face = (unsigned)nf1 * (unsigned)nf2, tt = (unsigned)t;
+  const int side = tt >= face ? 1 : 0;
+  const unsigned r = side ? tt - face : tt;
+  const int j1 = (int)(r % (unsigned)nf1), j2 = (int)(r / (unsigned)nf1);
   const int J1 = A.lo[t1a] + (j1 >> 1), J2 = A.lo[t2a] + (j2 >> 1);
   const int cl = side ? A.hi[axis] : A.lo[axis] - 1;
   auto cidx = [&](int q1, int q2) {
@@ -1301,6 +1308,10 @@ static int amr_plan(const mg_amr_mesh* m, Plan& pl, std::string* err) {
           p.hole.hi[a] = pl.hi[lam][a] * c - p.o[a];
         }
     }
+  // the kernels decode cell indices in 32 bits (cell_of)
+  for (int lam = 0; lam <= pl.Lam; ++lam)
+    if (cells(pl.P[lam][pl.K].d) >= ((size_t)1 << 31))
+      return fail_amr(err, MG_ERR_UNSUPPORTED, "a refinement level's patch has 2^31 cells or more");
   pl.R.clear();
   for (int n = pl.NB / 2; n >= 1; n /= 2) {
     PatchL p;

@@ -89,3 +89,12 @@ def test_context_budget_below_fixed_scratch_is_refused():
     assert lib.mg_ctx_create(ctypes.byref(h), 0, 1024) == _abi.MG_ERR_OOM
     assert not h.value
     assert lib.mg_ctx_create(None, 0, 0) == _abi.MG_ERR_INVALID_ARG
+
+
+def test_amr_patch_size_limit():
+    """A refined mesh whose finest patch of a level holds 2^31 cells or more is refused at
+    plan time (the kernels decode cell indices in 32 bits); the plan needs no device."""
+    import paper_2302_13903_amd as mg
+    assert mg.amr_patch_dims(mg.amr_mesh(64, 16, []), 0) is not None      # 1024^3 root: admitted
+    with pytest.raises(mg.MgError, match="UNSUPPORTED"):
+        mg.amr_patch_dims(mg.amr_mesh(256, 64, []), 0)                     # 16384^3 root
