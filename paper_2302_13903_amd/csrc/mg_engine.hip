@@ -70,6 +70,7 @@ struct mg_ctx {
   size_t hbm_budget = 0;
   size_t lds_per_block = 65536;
   int tail64_top = 3;          // highest FP64 level held by the LDS coarse tail
+  bool tail_fas = false;       // the tail also runs FAS cycles (LDS for phibar beside u and f)
   char* ws = nullptr;
   size_t ws_cap = 0;
   double* part = nullptr;      // reduction partials
@@ -667,11 +668,47 @@ struct Solver {
   // done: pre-sweeps of the top level already run by the head pass (result in u2).  want_norm
   // (top level): the two-sweep up pass may leave the sum of squared defects of the result in
   // scal[2]; returns whether it did.
+  // Can the LDS tail run the FAS cycle from level l: its FAS form allowed, and no level's
+  // description (nor the corrections') carrying face values?
+  bool fas_tail_ok(const Hier<double>& H, int l) const {
+    if (!c->tail_fas) return false;
+    auto valueless = [](const LevelBC& q) {
+      for (int f = 0; f < 6; ++f)
+        if (q.kind[f] != BC_PERIODIC && q.kind[f] != BC_ZERO_GRADIENT && q.b[f]) return false;
+      return true;
+    };
+    if (!valueless(H.hom)) return false;
+    for (int q = 0; q <= l; ++q)
+      if (!valueless(H.phys[q])) return false;
+    return true;
+  }
+
   bool fas_cycle(Hier<double>& H, double* const* pbar, int l, int done = 0, bool want_norm = false) {
     if (l == 0) {
       // the single cell with its physical conditions, from the iterate phibar; when no face
       // fixes the zero point any value solves it and phibar is kept (zero correction)
       if (fixes_zero(H.phys[0])) launch_coarsest<double>(H.u[0], H.f[0], H.h[0], H.phys[0], s);
+      return false;
+    }
+    if (done == 0 && l <= H.T_top && fas_tail_ok(H, l)) {
+      // the whole FAS cycle from level l in one LDS-resident workgroup (levels <= 16^3 whose
+      // descriptions carry no face values)
+      TailArgs a;
+      std::memset(&a, 0, sizeof(a));
+      a.top = l;
+      a.mode = TAIL_FAS | TAIL_LOAD_U;
+      a.npre = H.npre;
+      a.npost = H.npost;
+      a.omega = H.omega;
+      for (int q = 0; q <= l; ++q) {
+        a.h[q] = H.h[q];
+        a.phys[q] = H.phys[q];
+        a.fg[q] = H.f[q];
+      }
+      a.bc_top = H.phys[l];
+      a.hom = H.hom;
+      a.ug = H.u[l];
+      launch_tail<double>(a, s);
       return false;
     }
     const int n = 1 << l;
@@ -982,6 +1019,7 @@ int mg_ctx_create(mg_ctx** out, int device, size_t hbm_budget) {
   }
   // the FP64 coarse tail keeps levels <= 16^3 in LDS when the device allows it per block
   c->tail64_top = tail_prepare(c->lds_per_block);
+  c->tail_fas = c->tail64_top == 4 && tail_fas_prepare(c->lds_per_block);
   blk_prepare<double>(c->lds_per_block);
   blk_prepare<float>(c->lds_per_block);
   // the static scratch's device address, once per device with the device current (a failure

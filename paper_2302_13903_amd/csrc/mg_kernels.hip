@@ -594,6 +594,94 @@ __device__ __forceinline__ void tail_vcycle(T* base, int total, int topl, const 
   }
 }
 
+// FAS (Alg. 3 steps 2-7) on an LDS-resident level: the restricted defect into the coarse
+// source, the restricted u (phibar) into the coarse level's phibar and starting iterate --
+// the same terms in the same order as the per-operator FAS restriction
+template <typename T, int KIND>
+__device__ __forceinline__ void tail_fas_restrict(const T* u, const T* f, T* fc, T* pbar, T* uc, int L, T ih2,
+                                                  const LevelBC& bc) {
+  const int n = 1 << L, Lc = L - 1, nc = n >> 1, nc3 = 1 << (3 * Lc);
+  const WallRule<T> wr(bc);
+#pragma unroll 1
+  for (int C = threadIdx.x; C < nc3; C += blockDim.x) {
+    const int I = C & (nc - 1), J = (C >> Lc) & (nc - 1), K = C >> (2 * Lc);
+    T sd = (T)0, su = (T)0;
+    for (int c3 = 0; c3 < 2; ++c3)
+      for (int b = 0; b < 2; ++b)
+        for (int a = 0; a < 2; ++a) {
+          const int i = 2 * I + a, j = 2 * J + b, k = 2 * K + c3;
+          const int c = lds_idx(L, i, j, k);
+          const T ucv = u[c];
+          sd += f[c] - (lds_nb<T, KIND>(u, n, L, i, j, k, ucv, bc, wr) - (T)6 * ucv) * ih2;
+          su += ucv;
+        }
+    fc[C] = sd * (T)0.125;
+    const T pb = su * (T)0.125;
+    pbar[C] = pb;
+    uc[C] = pb;
+  }
+  __syncthreads();
+}
+
+// f += L phibar on an LDS-resident level, phibar's ghosts from the level's physical description
+template <typename T, int KIND>
+__device__ __forceinline__ void tail_fas_source(const T* pbar, T* f, int L, T ih2, const LevelBC& bc) {
+  const int n = 1 << L, n3 = 1 << (3 * L);
+  const WallRule<T> wr(bc);
+#pragma unroll 1
+  for (int c = threadIdx.x; c < n3; c += blockDim.x) {
+    const int i = c & (n - 1), j = (c >> L) & (n - 1), k = c >> (2 * L);
+    const T pc = pbar[c];
+    f[c] = f[c] + (lds_nb<T, KIND>(pbar, n, L, i, j, k, pc, bc, wr) - (T)6 * pc) * ih2;
+  }
+  __syncthreads();
+}
+
+// One FAS cycle (Alg. 3) from level topl down to 0 and back, each level with its physical
+// description; phibar of each level at base + 2 total.  Only the forms without face values
+// (KIND 1, 2).  The single cell is solved when a face fixes the zero point (a zero-valued
+// fixed face) and otherwise keeps phibar (a zero correction), as in the per-operator cycle.
+template <typename T, int KIND>
+__device__ __forceinline__ void tail_fas_vcycle(T* base, int total, int topl, const TailMeta& m, int npre, int npost,
+                                                T omega) {
+  T* pbase = base + 2 * total;
+#pragma unroll 1
+  for (int l = topl; l >= 1; --l) {
+    const LevelBC bc = m.phys[l];
+    T* u = base + level_offset(l);
+    T* f = base + total + level_offset(l);
+#pragma unroll 1
+    for (int it = 0; it < npre; ++it) tail_smooth<T, KIND>(u, f, l, (T)m.h2[l], omega, bc);
+    tail_fas_restrict<T, KIND>(u, f, base + total + level_offset(l - 1), pbase + level_offset(l - 1),
+                               base + level_offset(l - 1), l, (T)(1.0 / m.h2[l]), bc);
+    const LevelBC bcc = m.phys[l - 1];
+    tail_fas_source<T, KIND>(pbase + level_offset(l - 1), base + total + level_offset(l - 1), l - 1,
+                             (T)(1.0 / m.h2[l - 1]), bcc);
+  }
+  if (threadIdx.x == 0) {
+    const LevelBC b0 = m.phys[0];
+    bool fixes = false;
+    for (int f = 0; f < 6; ++f) fixes = fixes || bc_has_value(b0.kind[f]);
+    if (fixes) base[0] = coarsest_value(base[total], (T)m.h2[0], b0);
+  }
+  __syncthreads();
+  const LevelBC hom = m.hom;
+#pragma unroll 1
+  for (int l = 1; l <= topl; ++l) {
+    // the coarse-grid correction psi - phibar, prolonged with the homogeneous conditions
+    T* uc = base + level_offset(l - 1);
+    const T* pc = pbase + level_offset(l - 1);
+    const int nc3 = 1 << (3 * (l - 1));
+    for (int c = threadIdx.x; c < nc3; c += blockDim.x) uc[c] = uc[c] - pc[c];
+    __syncthreads();
+    T* u = base + level_offset(l);
+    tail_prolong<T, 0, KIND>(uc, u, l, hom);
+    const LevelBC bc = m.phys[l];
+#pragma unroll 1
+    for (int it = 0; it < npost; ++it) tail_smooth<T, KIND>(u, base + total + level_offset(l), l, (T)m.h2[l], omega, bc);
+  }
+}
+
 template <typename T, int KIND>
 __global__ void __launch_bounds__(kTailThreads) k_tail(TailArgs a) {
   const T* const* fg = reinterpret_cast<const T* const*>(a.fg);
@@ -638,14 +726,18 @@ __global__ void __launch_bounds__(kTailThreads) k_tail(TailArgs a) {
   // with restricted defects, which FMG no longer needs: it proceeds upwards).  V-cycle mode:
   // the one V-cycle on level top.  One copy of the V-cycle code serves both (a small kernel
   // image keeps the instruction cache warm across the many short phases).
+  if ((a.mode & TAIL_FAS) != 0) {
+    if constexpr (KIND != 0) tail_fas_vcycle<T, KIND>(base, total, top, m, a.npre, a.npost, omega);
+  } else {
 #pragma unroll 1
-  for (int l = fmg ? 1 : top; l <= top; ++l) {
-    if (fmg) {
-      const LevelBC below = m.phys[l - 1];
-      tail_prolong<T, 1, KIND>(base + level_offset(l - 1), base + level_offset(l), l, below);
+    for (int l = fmg ? 1 : top; l <= top; ++l) {
+      if (fmg) {
+        const LevelBC below = m.phys[l - 1];
+        tail_prolong<T, 1, KIND>(base + level_offset(l - 1), base + level_offset(l), l, below);
+      }
+      const LevelBC here = fmg ? m.phys[l] : m.top;
+      tail_vcycle<T, KIND>(base, total, l, m, here, a.npre, a.npost, omega);
     }
-    const LevelBC here = fmg ? m.phys[l] : m.top;
-    tail_vcycle<T, KIND>(base, total, l, m, here, a.npre, a.npost, omega);
   }
   const T* u = base + level_offset(top);
   for (int c = threadIdx.x; c < ntop; c += blockDim.x) ug[c] = u[c];
@@ -655,7 +747,8 @@ template <typename T>
 void launch_tail(const TailArgs& a, hipStream_t s) {
   TailArgs b = a;
   b.total = level_offset(a.top + 1);
-  const size_t lds = 2 * (size_t)b.total * sizeof(T);
+  // FAS: phibar of every level beside u and f
+  const size_t lds = ((b.mode & TAIL_FAS) ? 3 : 2) * (size_t)b.total * sizeof(T);
   // the periodic form when every description this launch reads is periodic
   auto periodic = [](const LevelBC& q) {
     for (int f = 0; f < 6; ++f)
@@ -668,7 +761,8 @@ void launch_tail(const TailArgs& a, hipStream_t s) {
       if (q.kind[f] != BC_PERIODIC && q.kind[f] != BC_ZERO_GRADIENT && q.b[f]) return false;
     return true;
   };
-  const bool fmg = (b.mode & TAIL_FMG) != 0;
+  // FMG and FAS read every level's physical description
+  const bool fmg = (b.mode & (TAIL_FMG | TAIL_FAS)) != 0;
   bool per = periodic(b.hom) && (fmg || periodic(b.bc_top));
   bool walls = valueless(b.hom) && (fmg || valueless(b.bc_top));
   if (fmg)
@@ -684,6 +778,11 @@ void launch_tail(const TailArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((k_tail<T, 0>), dim3(1), dim3(kTailThreads), lds, s, b);
 }
 
+// the FAS form (forms 1 and 2 only) holds phibar beside u and f
+static size_t tail_fas_lds(int top) { return tail_lds_bytes(top, sizeof(double)) / 2 * 3; }
+
+bool tail_fas_prepare(size_t lds_per_block) { return lds_per_block >= tail_fas_lds(4); }
+
 int tail_prepare(size_t lds_per_block) {
   const size_t need64 = tail_lds_bytes(4, sizeof(double));
   const size_t need32 = tail_lds_bytes(4, sizeof(float));
@@ -691,14 +790,22 @@ int tail_prepare(size_t lds_per_block) {
                         reinterpret_cast<const void*>(&k_tail<float, 2>)})
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need32);
   if (lds_per_block < need64) return 3;
-  for (const void* k : {reinterpret_cast<const void*>(&k_tail<double, 0>), reinterpret_cast<const void*>(&k_tail<double, 1>),
-                        reinterpret_cast<const void*>(&k_tail<double, 2>)})
-    if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need64) != hipSuccess) {
+  // forms 1 and 2 also run the FAS cycle, with phibar beside u and f, where that fits
+  const size_t need_fas = tail_fas_lds(4);
+  const size_t need12 = lds_per_block >= need_fas ? need_fas : need64;
+  const void* k64[3] = {reinterpret_cast<const void*>(&k_tail<double, 0>),
+                        reinterpret_cast<const void*>(&k_tail<double, 1>),
+                        reinterpret_cast<const void*>(&k_tail<double, 2>)};
+  for (int q = 0; q < 3; ++q)
+    if (hipFuncSetAttribute(k64[q], hipFuncAttributeMaxDynamicSharedMemorySize, (int)(q == 0 ? need64 : need12)) !=
+        hipSuccess) {
       (void)hipGetLastError();
       return 3;
     }
   return 4;
 }
+
+
 
 size_t tail_lds_bytes(int top, size_t elem) {
   size_t total = 0;

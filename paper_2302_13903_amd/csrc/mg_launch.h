@@ -18,7 +18,7 @@ inline int ilog2(long long n) {
   return l;
 }
 
-enum : int { TAIL_FMG = 1, TAIL_LOAD_U = 2 };
+enum : int { TAIL_FMG = 1, TAIL_LOAD_U = 2, TAIL_FAS = 4 };
 
 // Arguments of the coarse-tail kernel (all levels <= 16^3 of one hierarchy in LDS).
 struct TailArgs {
@@ -52,6 +52,9 @@ void launch_coarsest(T* u, const T* f, double h, const LevelBC& bc, hipStream_t 
 template <typename T>
 void launch_tail(const TailArgs& a, hipStream_t s);
 size_t tail_lds_bytes(int top, size_t elem);
+// Allows the FP64 tail the LDS of its FAS form (u, f and phibar of levels 0..4); returns
+// whether it fits.
+bool tail_fas_prepare(size_t lds_per_block);
 // Allows the FP64 tail its dynamic LDS; returns the highest level it can hold (3 or 4).
 int tail_prepare(size_t lds_per_block);
 
