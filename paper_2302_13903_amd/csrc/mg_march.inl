@@ -7,7 +7,9 @@
 //        and the coarse correction cleared;
 //   up   (Alg. 1 steps 5-7): u += trilinear prolongation of the coarse correction (eq.
 //        trilinear) as u is loaded, then two sweeps, optionally followed by the defect of the
-//        result summed as squares (the convergence norm of Sec. 2.3.7).
+//        result summed as squares (the convergence norm of Sec. 2.3.7);
+//   FAS down (Alg. 3 steps 2-4, k_march_fas): the down leg with the swept u restricted beside
+//        the defect (phibar, also the coarse level's starting iterate).
 //
 // Work layout.  A workgroup of W = 8 waves owns a tile of 64 x 64 cells in x-y and marches a
 // chunk of z planes.  Each half-wave holds a band of R = 4 rows, each lane the x-pair (2l, 2l+1)
