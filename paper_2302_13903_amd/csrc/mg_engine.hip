@@ -1137,11 +1137,14 @@ int setup_faces(char* ws, double* part, double* scal, const Layout& y, const mg_
       double* e = fb + (size_t)f * face_sz(l);
       phys[l].kind[f] = k == MG_BC_MULTIPOLE ? MG_BC_FIXED : k;
       phys[l].b[f] = nullptr;
-      if (k == MG_BC_FIXED) {
+      if (k == MG_BC_FIXED && bc->fixed_b[f]) {
         if (l == L) launch_face_extend(bc->fixed_b[f], e, 1 << l, s);
         else launch_face_restrict(reinterpret_cast<double*>(ws + y.faces[l + 1]) + (size_t)f * face_sz(l + 1), e,
                                   1 << l, s);
         phys[l].b[f] = e;
+      } else if (k == MG_BC_FIXED) {
+        // no values: a zero-fixed face, described without an array (ghost = -u, as in the
+        // homogeneous descriptions), so the kernels' forms without face values apply
       } else if (k == MG_BC_MULTIPOLE) {
         mp_out[f] = e;
         phys[l].b[f] = e;

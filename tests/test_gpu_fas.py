@@ -154,3 +154,27 @@ def test_fas_tolerance_streamed(mg, name):
                            tol=1e-9, scheme="fas", ctx=ctx)
     assert st == mg.MG_OK and len(gh) == len(rh)
     assert rel(got.cpu().numpy(), ref) < 1e-10
+
+
+@pytest.mark.parametrize("mode", ["fmg", "mgi"])
+@pytest.mark.parametrize("n", [16, 64])
+@pytest.mark.parametrize("kinds", [[FIXED] * 6, [FIXED, ZERO_GRADIENT, ZERO_GRADIENT, FIXED, PERIODIC, PERIODIC]])
+def test_fas_zero_valued_fixed_faces(mg, n, kinds, mode):
+    """Fixed faces with zero values: no level's description carries face values, so the levels
+    <= 16^3 run the FAS cycle in the LDS tail (its wall form), whose single cell is then solved
+    (a fixed face fixes the zero point).  Against the oracle's FAS at equal cycle counts."""
+    print(f"fas zero-fixed n={n} kinds={kinds} {mode}", flush=True)
+    rng = np.random.default_rng(n + 7)
+    rho = wl.gaussian_clumps(n, 23, n_clumps=6, remove_mean=False)
+    phi0 = rng.uniform(-1, 1, (n, n, n)) if mode == "mgi" else None
+    ref, rh, _ = oracle.solve(rho, 1.0 / n, kinds, mode=mode, phi0=phi0, fixed_cycles=5, scheme="fas")
+    phi = dev(phi0) if phi0 is not None else None
+    got, gh, st = mg.solve(dev(rho), 1.0 / n, kinds, fixed_cycles=5, mode=mode, phi=phi, scheme="fas")
+    torch.cuda.synchronize()
+    assert st == mg.MG_OK
+    got = got.cpu().numpy()
+    assert rel(got, ref) < 1e-10
+    fl = floor_of(ref, rho, kinds)
+    assert len(gh) == len(rh) == 6
+    for a, b in zip(gh, rh):
+        assert abs(a - b) <= 1e-6 * b + 10 * fl, (gh, list(rh), fl)
