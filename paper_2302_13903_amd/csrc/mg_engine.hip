@@ -307,6 +307,9 @@ int march_min_n(const mg_ctx* c) {
   return v > 0 ? std::max(kMarchMinN, v) : kMarchMinN;
 }
 
+// Does a MeshBlock level of 2^l cells per side fit the two-sweep passes' 32-bit block index?
+inline bool blk_march_fits(int l) { return 3 * l < 32; }
+
 struct Solver {
   mg_ctx* c;
   hipStream_t s;
@@ -398,11 +401,13 @@ struct Solver {
   // the second stream of the split passes (null: one launch per pass)
   const MarchAux* aux_of() const { return c->split == 0 ? nullptr : &c->aux; }
 
-  // May a MeshBlock level run the two-sweep streaming passes (the "march" setting for its faces)?
+  // May MeshBlock level l run the two-sweep streaming passes (the "march" setting for its
+  // faces)?  Those passes index the block layout in 32 bits, so the level must hold fewer than
+  // 2^32 cells (every level up to 1024^3); larger ones take the block streaming sweeps.
   template <typename T>
-  bool march_blk_on(const Hier<T>& H, const LevelBC& bc) const {
+  bool march_blk_on(const Hier<T>& H, int l, const LevelBC& bc) const {
     const int mode = c->march[sizeof(T) == 8 ? 0 : 1] < 0 ? 2 : c->march[sizeof(T) == 8 ? 0 : 1];
-    if (mode == 0 || H.npre != 2 || H.npost != 2) return false;
+    if (mode == 0 || H.npre != 2 || H.npost != 2 || !blk_march_fits(l)) return false;
     if (mode == 1)
       for (int f = 0; f < 6; ++f)
         if (bc.kind[f] != BC_PERIODIC) return false;
@@ -883,7 +888,7 @@ struct Solver {
     const int Lm = l - Lb;
     const int nl = 1 << l;
     const int vz = c->blk_zmarch[sizeof(T) == 8 ? 0 : 1];
-    const bool big = vz != 0 && nl >= march_min<T>() && march_blk_on<T>(H, bc);
+    const bool big = vz != 0 && nl >= march_min<T>() && march_blk_on<T>(H, l, bc);
     if ((big || tile_on<T>(H, l)) && H.npre == 2 && H.npost == 2) {
       // each leg of the block level in one launch over all blocks: the two-sweep streaming
       // passes on the large levels, region tiles below
@@ -1549,7 +1554,7 @@ int autotune_blocks(mg_ctx* c, const mg_params* p, int Lb, int reps) {
           if (ms < best_ms) { best_ms = ms; best = t; }
         }
     c->blk_tune[(sizeof(T) == 8 ? 0 : 1000) + 100 * Lm + Lb] = best;
-    if (l == L && p->npre == 2 && p->npost == 2 && (1 << l) >= march_min_n<T>(c)) {
+    if (l == L && p->npre == 2 && p->npost == 2 && (1 << l) >= march_min_n<T>(c) && blk_march_fits(l)) {
       // V(2,2) on the finest block level: both legs as the two-sweep streaming passes across
       // blocks against the four halo-tile sweeps alone (a lower bound on that schedule)
       T* fc = buf[3];

@@ -145,7 +145,9 @@ struct alignas(2 * sizeof(T)) Pair {
 };
 
 // MeshBlock storage index split into its x-y part and its z part (disjoint bits, so the index
-// is their sum): the x-y part is fixed per lane and row, the z part is uniform per plane.
+// is their sum): the x-y part is fixed per lane and row, the z part is uniform per plane.  Both
+// are 32-bit (a 64-bit index costs these passes register spills): the launcher sends only
+// levels of fewer than 2^32 cells here.
 __device__ __forceinline__ unsigned blk_xy(int Lm, int i, int j) {
   const int mm = (1 << Lm) - 1;
   return ((spread3((unsigned)(i >> Lm)) | (spread3((unsigned)(j >> Lm)) << 1)) << (3 * Lm)) |

@@ -100,6 +100,29 @@ __device__ __forceinline__ T coarse_hom(const TileArgs& A, const T* __restrict__
   return s * ec[coarse_idx<BLK>(A, Ic, Jc, Kc)];
 }
 
+// One axis' share of coarse_hom, for the coordinate that is not 0 (the others must be 0, which
+// every layout maps to index part 0 with sign +1): the part of the storage index, with bit 31
+// set when the ghost rule negates the value.
+template <bool BLK>
+__device__ __forceinline__ unsigned coarse_part(const TileArgs& A, int I, int J, int K) {
+  const int ncm = (A.n >> 1) - 1;
+  bool neg = false;
+  auto axis = [&](int v, int pbit, int lo_face) __attribute__((always_inline)) {
+    if (A.per & pbit) return v & ncm;
+    if (v < 0) {
+      neg ^= A.bcc.kind[lo_face] != BC_ZERO_GRADIENT;
+      return 0;
+    }
+    if (v > ncm) {
+      neg ^= A.bcc.kind[lo_face + 1] != BC_ZERO_GRADIENT;
+      return ncm;
+    }
+    return v;
+  };
+  const int Ic = axis(I, 1, 0), Jc = axis(J, 2, 2), Kc = axis(K, 4, 4);
+  return (unsigned)coarse_idx<BLK>(A, Ic, Jc, Kc) | (neg ? 0x80000000u : 0u);
+}
+
 // FAS (down, dense; Alg. 3 steps 2-4): the restriction also writes phibar, the mean of the 8
 // children of the swept u, into A.pbar and starts the coarse level from it (uc0 = phibar).
 template <typename T, bool UP, bool NORM, bool BLK, bool FAS = false>
@@ -123,18 +146,58 @@ __global__ void __launch_bounds__(kThreads) k_tile_leg(TileArgs A) {
     return (unsigned)v < (unsigned)n ? v : -1;
   };
 
+  // MeshBlock layout: a storage index is the sum of an x part and a y-z part (disjoint bits of
+  // the block-major index), tabulated once for the staged extent, so each access costs two LDS
+  // reads instead of three bit spreads.  Entries of cells outside a non-periodic domain are
+  // never used.  Up: the same for the coarse cells under the tile, with the homogeneous ghost
+  // sign in bit 31 (the coarse level has at most 2^21 cells).
+  __shared__ unsigned ix_part[BLK ? WX : 1], iyz_part[BLK ? WY * WZ : 1];
+  __shared__ unsigned cx_part[BLK && UP ? CX : 1], cyz_part[BLK && UP ? CY * CZ : 1];
+  const int cx0 = (ox >> 1) - 4, cy0 = (oy >> 1) - 4, cz0 = (oz >> 1) - 4;
+  if constexpr (BLK) {
+    constexpr int NF = WX + WY * WZ, NC = UP ? CX + CY * CZ : 0;
+    for (int q = tid; q < NF + NC; q += kThreads) {
+      if (q < WX) {
+        const int i = wrap(ox + q - H, 1);
+        ix_part[q] = i < 0 ? 0u : (unsigned)fine_at<BLK>(A, i, 0, 0);
+      } else if (q < NF) {
+        const int r = q - WX, j = wrap(oy + r % WY - H, 2), k = wrap(oz + r / WY - H, 4);
+        iyz_part[r] = (j < 0 || k < 0) ? 0u : (unsigned)fine_at<BLK>(A, 0, j, k);
+      } else if constexpr (UP) {
+        const int r = q - NF;
+        if (r < CX) {
+          cx_part[r] = coarse_part<BLK>(A, cx0 + r, 0, 0);
+        } else {
+          const int t = r - CX;
+          cyz_part[t] = coarse_part<BLK>(A, 0, cy0 + t % CY, cz0 + t / CY);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // storage index of the staged cell (tx, ty, tz) (tile coordinates), in the domain at (i, j, k)
+  auto fat = [&](int tx, int ty, int tz, int i, int j, int k) __attribute__((always_inline)) -> size_t {
+    if constexpr (BLK) return (size_t)(ix_part[tx] + iyz_part[tz * WY + ty]);
+    else return cidx(A.L, i, j, k);
+  };
+
   // ---- stage u on the region and its halo
   for (int q = tid; q < TV; q += kThreads) {
     const int tx = q % WX, ty = (q / WX) % WY, tz = q / (WX * WY);
     const int i = wrap(ox + tx - H, 1), j = wrap(oy + ty - H, 2), k = wrap(oz + tz - H, 4);
-    tile[q] = (i >= 0 && j >= 0 && k >= 0) ? uin[fine_at<BLK>(A, i, j, k)] : (T)0;
+    tile[q] = (i >= 0 && j >= 0 && k >= 0) ? uin[fat(tx, ty, tz, i, j, k)] : (T)0;
   }
   if constexpr (UP) {
     const T* __restrict__ ec = reinterpret_cast<const T*>(A.ec);
-    const int cx0 = (ox >> 1) - 4, cy0 = (oy >> 1) - 4, cz0 = (oz >> 1) - 4;
     for (int q = tid; q < CV; q += kThreads) {
       const int cx = q % CX, cy = (q / CX) % CY, cz = q / (CX * CY);
-      ctile[q] = coarse_hom<T, BLK>(A, ec, cx0 + cx, cy0 + cy, cz0 + cz);
+      if constexpr (BLK) {
+        const unsigned a = cx_part[cx], b = cyz_part[cz * CY + cy];
+        const T v = ec[(a & 0x7fffffffu) + (b & 0x7fffffffu)];
+        ctile[q] = ((a ^ b) >> 31) ? -v : v;
+      } else {
+        ctile[q] = coarse_hom<T, BLK>(A, ec, cx0 + cx, cy0 + cy, cz0 + cz);
+      }
     }
     __syncthreads();
     // trilinear prolongation (weights 1/4, 3/4 per axis; the even child is the lower one)
@@ -183,7 +246,7 @@ __global__ void __launch_bounds__(kThreads) k_tile_leg(TileArgs A) {
       const T zm = (!(per & 4) && k == 0) ? wall(A.bc, 4, n, i, j, uc) : tile[p - WX * WY];
       const T zp = (!(per & 4) && k == nm) ? wall(A.bc, 5, n, i, j, uc) : tile[p + WX * WY];
       const T nb = ((((xm + xp) + ym) + yp) + zm) + zp;
-      tile[p] = uc + omega * ((nb - h2 * fin[fine_at<BLK>(A, i, j, k)]) * inv6 - uc);
+      tile[p] = uc + omega * ((nb - h2 * fin[fat(rx2 + H - ring, ry2 + H - ring, rz2 + H - ring, i, j, k)]) * inv6 - uc);
     }
     __syncthreads();
   };
@@ -204,7 +267,7 @@ __global__ void __launch_bounds__(kThreads) k_tile_leg(TileArgs A) {
     const T zm = (!(per & 4) && k == 0) ? wall(A.bc, 4, n, i, j, uc) : tile[p - WX * WY];
     const T zp = (!(per & 4) && k == nm) ? wall(A.bc, 5, n, i, j, uc) : tile[p + WX * WY];
     const T nb = ((((xm + xp) + ym) + yp) + zm) + zp;
-    return fin[fine_at<BLK>(A, i, j, k)] - (nb - (T)6 * uc) * ih2;
+    return fin[fat(x + H, y + H, z + H, i, j, k)] - (nb - (T)6 * uc) * ih2;
   };
 
   if constexpr (!UP) {
@@ -242,7 +305,7 @@ __global__ void __launch_bounds__(kThreads) k_tile_leg(TileArgs A) {
   // ---- the region back to memory (and, for the norm, its defects)
   for (int q = tid; q < DX * DY * DZ; q += kThreads) {
     const int x = q % DX, y = (q / DX) % DY, z = q / (DX * DY);
-    uout[fine_at<BLK>(A, ox + x, oy + y, oz + z)] = tile[((z + H) * WY + (y + H)) * WX + (x + H)];
+    uout[fat(x + H, y + H, z + H, ox + x, oy + y, oz + z)] = tile[((z + H) * WY + (y + H)) * WX + (x + H)];
     if constexpr (UP && NORM) {
       const T d = defect_at(x, y, z);
       acc += (double)d * (double)d;
