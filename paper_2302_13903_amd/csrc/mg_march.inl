@@ -847,9 +847,7 @@ constexpr int kCUs = 256;
 int march_zchunk(int n, int tiles_xy, int hz) {
   int best = (n + 5) / 6 * 6;
   long best_cost = -1;
-  for (int c = 1; c <= n / 6; ++c) {
-    int zc = (n + c - 1) / c;
-    zc = (zc + 5) / 6 * 6;
+  for (int zc = 6; zc <= (n + 5) / 6 * 6; zc += 6) {
     const long chunks = (n + zc - 1) / zc;
     if ((long)tiles_xy * chunks > (long)kMaxPartials * 32 - 8) continue;   // partials buffer
     const long rounds = ((long)tiles_xy * chunks + kCUs - 1) / kCUs;
