@@ -10,7 +10,7 @@
 namespace mg {
 
 // Smallest and largest level side the region-tile legs take (the level must hold whole
-// regions of 16 x 16 x 8 cells; above 128^3 the streaming passes move far fewer bytes).
+// regions of 8 x 8 x 4 cells or more; above 128^3 the streaming passes move far fewer bytes).
 constexpr int kTileMinN = 32;
 constexpr int kTileMaxN = 128;
 

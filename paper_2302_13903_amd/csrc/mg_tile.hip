@@ -10,9 +10,9 @@
 //   up   (Alg. 1 steps 5-7): u += trilinear prolongation of the coarse correction (eq.
 //        trilinear), two sweeps, optionally the sum of squared defects of the result
 //        (Sec. 2.3.7).
-// Each workgroup owns a region of 16 x 16 x 8 cells and stages it in LDS with a halo of 5 cells
-// (four colour passes of radius 1 and the defect); colour pass s updates the region plus a
-// ring of 4 - s cells, so every pass sees its neighbours exactly as a global sweep would, and
+// Each workgroup owns a region (16 x 16 x 8 cells on 128^3, smaller below) and stages it in
+// LDS with a halo of 5 cells (four colour passes of radius 1 and the defect); colour pass s
+// updates the region plus a ring of 4 - s cells, so every pass sees its neighbours exactly as a global sweep would, and
 // only the region is written back.  The rings are recomputed by the neighbouring regions,
 // never exchanged, so regions are independent.  The up leg first stages the coarse correction
 // under the tile (homogeneous ghosts: periodic wrap, or the boundary cell with the face's
@@ -32,12 +32,17 @@ namespace mg {
 namespace {
 
 constexpr int kThreads = 1024;
-constexpr int DX = 16, DY = 16, DZ = 8, H = 5;
-constexpr int WX = DX + 2 * H, WY = DY + 2 * H, WZ = DZ + 2 * H;   // staged tile 26 x 26 x 18
-constexpr int TV = WX * WY * WZ;
-// coarse cells under the tile: floor(x/2) - 1 .. floor(x/2) + 1 for every staged x
-constexpr int CX = DX / 2 + 8, CY = DY / 2 + 8, CZ = DZ / 2 + 8;   // 16 x 16 x 12
-constexpr int CV = CX * CY * CZ;
+constexpr int H = 5;   // staged halo: four colour passes of radius 1 and the defect
+
+// Region shapes (cells per workgroup, all even): 16 x 16 x 8 on the 128^3 levels; smaller
+// ones below, so that the few-microsecond legs of the 64^3 and 32^3 levels spread over more
+// CUs with less serial work per workgroup (16 x 16 x 4: 256 regions at 64^3; 8 x 8 x 4: 128
+// at 32^3).
+struct Shape {
+  int dx, dy, dz;
+};
+constexpr Shape kShapes[3] = {{16, 16, 8}, {16, 16, 4}, {8, 8, 4}};
+int shape_of(int n) { return n >= 128 ? 0 : n >= 64 ? 1 : 2; }
 
 struct TileArgs {
   const void* uin;
@@ -125,8 +130,14 @@ __device__ __forceinline__ unsigned coarse_part(const TileArgs& A, int I, int J,
 
 // FAS (down, dense; Alg. 3 steps 2-4): the restriction also writes phibar, the mean of the 8
 // children of the swept u, into A.pbar and starts the coarse level from it (uc0 = phibar).
-template <typename T, bool UP, bool NORM, bool BLK, bool FAS = false>
+template <typename T, bool UP, bool NORM, bool BLK, bool FAS, int SH>
 __global__ void __launch_bounds__(kThreads) k_tile_leg(TileArgs A) {
+  constexpr int DX = kShapes[SH].dx, DY = kShapes[SH].dy, DZ = kShapes[SH].dz;
+  constexpr int WX = DX + 2 * H, WY = DY + 2 * H, WZ = DZ + 2 * H;   // staged tile
+  constexpr int TV = WX * WY * WZ;
+  // coarse cells under the tile: floor(x/2) - 1 .. floor(x/2) + 1 for every staged x
+  constexpr int CX = DX / 2 + 8, CY = DY / 2 + 8, CZ = DZ / 2 + 8;
+  constexpr int CV = CX * CY * CZ;
   __shared__ T tile[TV];
   __shared__ T ctile[UP ? CV : 1];
   __shared__ double red[kThreads / 64];
@@ -335,15 +346,30 @@ TileArgs base_args(const T* uin, T* uout, const T* f, int n, int Lm, double h, d
   A.L = ilog2(n);
   A.Lm = Lm;
   A.per = (bc.kind[0] == BC_PERIODIC ? 1 : 0) | (bc.kind[2] == BC_PERIODIC ? 2 : 0) | (bc.kind[4] == BC_PERIODIC ? 4 : 0);
-  A.nrx = n / DX;
-  A.nry = n / DY;
+  const Shape sh = kShapes[shape_of(n)];
+  A.nrx = n / sh.dx;
+  A.nry = n / sh.dy;
   A.h2 = h * h;
   A.ih2 = 1.0 / (h * h);
   A.omega = omega;
   return A;
 }
 
-int regions(int n) { return (n / DX) * (n / DY) * (n / DZ); }
+int regions(int n) {
+  const Shape sh = kShapes[shape_of(n)];
+  return (n / sh.dx) * (n / sh.dy) * (n / sh.dz);
+}
+
+// One launch of the leg in the region shape of level side n.
+template <typename T, bool UP, bool NORM, bool BLK, bool FAS = false>
+void launch_leg(const TileArgs& A, hipStream_t s) {
+  const dim3 g(regions(A.n)), b(kThreads);
+  switch (shape_of(A.n)) {
+    case 0: hipLaunchKernelGGL((k_tile_leg<T, UP, NORM, BLK, FAS, 0>), g, b, 0, s, A); break;
+    case 1: hipLaunchKernelGGL((k_tile_leg<T, UP, NORM, BLK, FAS, 1>), g, b, 0, s, A); break;
+    default: hipLaunchKernelGGL((k_tile_leg<T, UP, NORM, BLK, FAS, 2>), g, b, 0, s, A); break;
+  }
+}
 
 }  // namespace
 
@@ -354,8 +380,8 @@ void tile_down(const T* uin, T* uout, const T* f, T* fc, T* uc0, int n, int Lm, 
   TileArgs A = base_args(uin, uout, f, n, Lm, h, omega, bc);
   A.fc = fc;
   A.uc0 = uc0;
-  if (Lm > 0) hipLaunchKernelGGL((k_tile_leg<T, false, false, true>), dim3(regions(n)), dim3(kThreads), 0, s, A);
-  else hipLaunchKernelGGL((k_tile_leg<T, false, false, false>), dim3(regions(n)), dim3(kThreads), 0, s, A);
+  if (Lm > 0) launch_leg<T, false, false, true>(A, s);
+  else launch_leg<T, false, false, false>(A, s);
 }
 
 template <typename T>
@@ -365,7 +391,7 @@ void tile_down_fas(const T* uin, T* uout, const T* f, T* fc, T* pbar, T* uc0, in
   A.fc = fc;
   A.pbar = pbar;
   A.uc0 = uc0;
-  hipLaunchKernelGGL((k_tile_leg<T, false, false, false, true>), dim3(regions(n)), dim3(kThreads), 0, s, A);
+  launch_leg<T, false, false, false, true>(A, s);
 }
 
 template <typename T>
@@ -377,12 +403,12 @@ int tile_up(const T* uin, T* uout, const T* f, const T* ec, const LevelBC& bcc, 
   A.bcc = bcc;
   A.part = part;
   if (part) {
-    if (Lm > 0) hipLaunchKernelGGL((k_tile_leg<T, true, true, true>), dim3(regions(n)), dim3(kThreads), 0, s, A);
-    else hipLaunchKernelGGL((k_tile_leg<T, true, true, false>), dim3(regions(n)), dim3(kThreads), 0, s, A);
+    if (Lm > 0) launch_leg<T, true, true, true>(A, s);
+    else launch_leg<T, true, true, false>(A, s);
     return regions(n);
   }
-  if (Lm > 0) hipLaunchKernelGGL((k_tile_leg<T, true, false, true>), dim3(regions(n)), dim3(kThreads), 0, s, A);
-  else hipLaunchKernelGGL((k_tile_leg<T, true, false, false>), dim3(regions(n)), dim3(kThreads), 0, s, A);
+  if (Lm > 0) launch_leg<T, true, false, true>(A, s);
+  else launch_leg<T, true, false, false>(A, s);
   return 0;
 }
 
