@@ -31,7 +31,6 @@ namespace mg {
 
 namespace {
 
-constexpr int kThreads = 1024;
 constexpr int H = 5;   // staged halo: four colour passes of radius 1 and the defect
 
 // Region shapes (cells per workgroup, all even): 16 x 16 x 8 on the 128^3 levels; smaller
@@ -39,9 +38,9 @@ constexpr int H = 5;   // staged halo: four colour passes of radius 1 and the de
 // CUs with less serial work per workgroup (16 x 16 x 4: 256 regions at 64^3; 8 x 8 x 4: 128
 // at 32^3).
 struct Shape {
-  int dx, dy, dz;
+  int dx, dy, dz, threads;
 };
-constexpr Shape kShapes[3] = {{16, 16, 8}, {16, 16, 4}, {8, 8, 4}};
+constexpr Shape kShapes[3] = {{16, 16, 8, 1024}, {16, 16, 4, 1024}, {8, 8, 4, 1024}};
 int shape_of(int n) { return n >= 128 ? 0 : n >= 64 ? 1 : 2; }
 
 struct TileArgs {
@@ -131,7 +130,8 @@ __device__ __forceinline__ unsigned coarse_part(const TileArgs& A, int I, int J,
 // FAS (down, dense; Alg. 3 steps 2-4): the restriction also writes phibar, the mean of the 8
 // children of the swept u, into A.pbar and starts the coarse level from it (uc0 = phibar).
 template <typename T, bool UP, bool NORM, bool BLK, bool FAS, int SH>
-__global__ void __launch_bounds__(kThreads) k_tile_leg(TileArgs A) {
+__global__ void __launch_bounds__(kShapes[SH].threads) k_tile_leg(TileArgs A) {
+  constexpr int kThreads = kShapes[SH].threads;
   constexpr int DX = kShapes[SH].dx, DY = kShapes[SH].dy, DZ = kShapes[SH].dz;
   constexpr int WX = DX + 2 * H, WY = DY + 2 * H, WZ = DZ + 2 * H;   // staged tile
   constexpr int TV = WX * WY * WZ;
@@ -363,7 +363,7 @@ int regions(int n) {
 // One launch of the leg in the region shape of level side n.
 template <typename T, bool UP, bool NORM, bool BLK, bool FAS = false>
 void launch_leg(const TileArgs& A, hipStream_t s) {
-  const dim3 g(regions(A.n)), b(kThreads);
+  const dim3 g(regions(A.n)), b(kShapes[shape_of(A.n)].threads);
   switch (shape_of(A.n)) {
     case 0: hipLaunchKernelGGL((k_tile_leg<T, UP, NORM, BLK, FAS, 0>), g, b, 0, s, A); break;
     case 1: hipLaunchKernelGGL((k_tile_leg<T, UP, NORM, BLK, FAS, 1>), g, b, 0, s, A); break;
