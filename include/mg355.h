@@ -226,8 +226,10 @@ int mg_last_timing(const mg_ctx *ctx, double *setup_ms, double *fmg_ms, double *
 int mg_last_inner(const mg_ctx *ctx, int *inner_cycles);
 
 /* Kernel-level timing of the finest-level smoothing kernels of the V-cycles of the last
- * mg_solve, from HIP events recorded on the solve stream around each launch.  Enabled by
- * mg_set_kernel_timing(ctx, 1); off by default (the events cost a little host time).
+ * mg_solve, from HIP events on the solve stream: a pass that is one kernel carries its events
+ * in its own dispatch (its start and end), a pass split over two streams has events recorded
+ * around both launches.  Enabled by mg_set_kernel_timing(ctx, 1); off by default (each timed
+ * dispatch costs the device a few microseconds between kernels).
  * Entry `index` (0-based, one per kernel name): launch count, summed duration (ms), the
  * algorithmic HBM bytes of one launch, and the kernel name (as the profiler lists it).
  * Returns MG_ERR_INVALID_ARG past the last entry. */

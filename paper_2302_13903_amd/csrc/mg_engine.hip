@@ -327,17 +327,39 @@ struct Solver {
   // vcycle)
   bool head_done = false;
 
-  void kernel_begin() {
+  // hook: the launcher that follows takes the launch-timing hook (one kernel timed by its own
+  // dispatch, no marker packets around it); otherwise events are recorded around the launcher
+  bool hooked = false;
+  void kernel_begin(bool hook = false) {
     hipEvent_t e;
     (void)hipEventCreate(&e);
-    (void)hipEventRecord(e, s);
+    if (hook) {
+      LaunchTiming& t = launch_timing();
+      t.e0 = e;
+      (void)hipEventCreate(&t.e1);
+      t.armed = true;
+      hooked = true;
+    } else {
+      (void)hipEventRecord(e, s);
+    }
     c->kev.push_back(e);
   }
   // algorithmic bytes of one launch are recorded with its name
   void kernel_end(const std::string& name, double bytes) {
     hipEvent_t e;
-    (void)hipEventCreate(&e);
-    (void)hipEventRecord(e, s);
+    if (hooked) {
+      LaunchTiming& t = launch_timing();
+      hooked = false;
+      e = t.e1;
+      if (t.armed) {   // the launcher did not take the hook: an empty interval here
+        t.armed = false;
+        (void)hipEventRecord(c->kev.back(), s);
+        (void)hipEventRecord(e, s);
+      }
+    } else {
+      (void)hipEventCreate(&e);
+      (void)hipEventRecord(e, s);
+    }
     c->kev.push_back(e);
     int id = -1;
     for (size_t q = 0; q < c->kstats.size(); ++q)
@@ -481,13 +503,13 @@ struct Solver {
       // cleared), the coarse recursion, up (prolonged correction, two sweeps, and the norm of
       // the result when asked); the result lands back in u[l] after the two ping-pongs
       const bool zin = top_call && zero_start;
-      if (timed) kernel_begin();
+      if (timed) kernel_begin(true);
       march_down<T>(zin ? nullptr : H.u[l], H.u2[l], H.f[l], H.f[l - 1], H.u[l - 1], n, h, H.omega, bc, s, 0, aux_of());
       // algorithmic bytes: u and f read, u written, coarse source and correction written
       if (timed) kernel_end(march_name<T>(false, false, bc), 3 * cellsT + cellsT / 4);
       vcycle(H, l - 1, H.hom, false, false);
       double* npart = want_norm && sizeof(T) == 8 ? part : nullptr;
-      if (timed) kernel_begin();
+      if (timed) kernel_begin(true);
       const int np = march_up<T>(H.u2[l], H.u[l], H.f[l], H.u[l - 1], H.hom, npart, n, h, H.omega, bc, s, 0, aux_of());
       // algorithmic bytes: u, f and the coarse correction read, u written
       if (timed) kernel_end(march_name<T>(true, npart != nullptr, bc), 3 * cellsT + cellsT / 8);
@@ -500,12 +522,12 @@ struct Solver {
         launch_zero(H.u[l], cells(l) * sizeof(T), s);
         zero_start = false;
       }
-      if (timed) kernel_begin();
+      if (timed) kernel_begin(true);
       tile_down<T>(H.u[l], H.u2[l], H.f[l], H.f[l - 1], H.u[l - 1], n, 0, 0, h, H.omega, bc, s);
       if (timed) kernel_end(tile_name<T>(false, false), 3 * cellsT + cellsT / 4);
       vcycle(H, l - 1, H.hom, false, false);
       double* npart = want_norm && sizeof(T) == 8 ? part : nullptr;
-      if (timed) kernel_begin();
+      if (timed) kernel_begin(true);
       const int np = tile_up<T>(H.u2[l], H.u[l], H.f[l], H.u[l - 1], H.hom, npart, n, 0, 0, h, H.omega, bc, s);
       if (timed) kernel_end(tile_name<T>(true, npart != nullptr), 3 * cellsT + cellsT / 8);
       if (npart) launch_sum_partials(part, np, scal + 2, s);
@@ -724,7 +746,7 @@ struct Solver {
       // V(2,2) legs as the two-sweep passes: down (two sweeps, restricted defect, phibar, the
       // coarse level started from it), steps 5-7 on the coarse level, up (the prolonged
       // correction psi - phibar, two sweeps, and the norm of the result when asked)
-      if (timed) kernel_begin();
+      if (timed) kernel_begin(true);
       march_down_fas<double>(H.u[l], H.u2[l], H.f[l], H.f[l - 1], pbar[l - 1], H.u[l - 1], n, H.h[l], H.omega, bc, s);
       // algorithmic bytes: u and f read, u written, three coarse arrays written
       if (timed) kernel_end(march_fas_name<double>(bc), 3 * cellsT + 3 * cellsT / 8);
@@ -732,7 +754,7 @@ struct Solver {
       fas_cycle(H, pbar, l - 1);                                                             // 6
       launch_fas_correction(H.u[l - 1], pbar[l - 1], cells(l - 1), s);                       // 7
       double* npart = want_norm ? part : nullptr;
-      if (timed) kernel_begin();
+      if (timed) kernel_begin(true);
       const int np = march_up<double>(H.u2[l], H.u[l], H.f[l], H.u[l - 1], H.hom, npart, n, H.h[l], H.omega, bc, s, 0,
                                       aux_of());
       if (timed) kernel_end(march_name<double>(true, npart != nullptr, bc), 3 * cellsT + cellsT / 8);
@@ -743,14 +765,14 @@ struct Solver {
       // a small level: each V(2,2) leg in one region-tile launch -- down (two sweeps,
       // restricted defect, phibar, the coarse level started from it), steps 5-7 on the coarse
       // level, up (the prolonged correction psi - phibar, two sweeps, the norm when asked)
-      if (timed) kernel_begin();
+      if (timed) kernel_begin(true);
       tile_down_fas<double>(H.u[l], H.u2[l], H.f[l], H.f[l - 1], pbar[l - 1], H.u[l - 1], n, H.h[l], H.omega, bc, s);
       if (timed) kernel_end("k_tile_leg<double, false, false, false, true>", 3 * cellsT + 3 * cellsT / 8);
       launch_fas_source(pbar[l - 1], H.f[l - 1], n / 2, H.h[l - 1], H.phys[l - 1], s);       // 5
       fas_cycle(H, pbar, l - 1);                                                             // 6
       launch_fas_correction(H.u[l - 1], pbar[l - 1], cells(l - 1), s);                       // 7
       double* npart = want_norm ? part : nullptr;
-      if (timed) kernel_begin();
+      if (timed) kernel_begin(true);
       const int np = tile_up<double>(H.u2[l], H.u[l], H.f[l], H.u[l - 1], H.hom, npart, n, 0, 0, H.h[l], H.omega, bc, s);
       if (timed) kernel_end(tile_name<double>(true, npart != nullptr), 3 * cellsT + cellsT / 8);
       if (npart) launch_sum_partials(part, np, scal + 2, s);
@@ -894,14 +916,14 @@ struct Solver {
       // passes on the large levels, region tiles below
       const bool timed = timed_top && l == H.L && ktiming;
       const double cellsT = (double)cells(l) * sizeof(T);
-      if (timed) kernel_begin();
+      if (timed) kernel_begin(true);
       if (big) march_down<T>(H.u[l], H.u2[l], H.f[l], H.f[l - 1], H.u[l - 1], nl, H.h[l], H.omega, bc, s, Lm, aux_of());
       else tile_down<T>(H.u[l], H.u2[l], H.f[l], H.f[l - 1], H.u[l - 1], nl, Lm, Lb, H.h[l], H.omega, bc, s);
       if (timed) kernel_end(big ? march_name<T>(false, false, bc, true) : tile_name<T>(false, false, true),
                             3 * cellsT + cellsT / 4);
       vcycle_blk(H, l - 1, H.hom);
       double* npart = want_norm && sizeof(T) == 8 ? part : nullptr;
-      if (timed) kernel_begin();
+      if (timed) kernel_begin(true);
       const int np = big ? march_up<T>(H.u2[l], H.u[l], H.f[l], H.u[l - 1], H.hom, npart, nl, H.h[l], H.omega, bc, s, Lm,
                                        aux_of())
                          : tile_up<T>(H.u2[l], H.u[l], H.f[l], H.u[l - 1], H.hom, npart, nl, Lm, Lb, H.h[l], H.omega, bc, s);

@@ -11,6 +11,11 @@
 
 namespace mg {
 
+LaunchTiming& launch_timing() {
+  static thread_local LaunchTiming t;
+  return t;
+}
+
 constexpr int kBlock = 256;
 
 static inline unsigned grid_for(size_t work, int per_thread = 1) {

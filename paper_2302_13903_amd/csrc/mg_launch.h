@@ -1,6 +1,7 @@
 // mg_launch.h -- host-side declarations of the kernel launchers (internal to the library).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -11,6 +12,28 @@
 namespace mg {
 
 constexpr int kMaxPartials = 2048;   // per-block partial sums of the two-stage reductions
+
+// Timing of the next launch (one per host thread).  The solver arms it with two created events
+// before a timed launcher that takes it; a single kernel then carries the events in its own
+// dispatch (start and end timestamps of that kernel, with no marker packet queued between it
+// and its neighbours), a launcher of several kernels records them around its launches.
+struct LaunchTiming {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  bool armed = false;
+};
+LaunchTiming& launch_timing();
+
+// One kernel launch, timed through the armed hook when there is one.
+template <typename K, typename... Args>
+void launch_maybe_timed(K kern, dim3 grid, dim3 block, unsigned lds, hipStream_t s, Args... args) {
+  LaunchTiming& t = launch_timing();
+  if (t.armed) {
+    t.armed = false;
+    hipExtLaunchKernelGGL(kern, grid, block, lds, s, t.e0, t.e1, 0u, args...);
+  } else {
+    hipLaunchKernelGGL(kern, grid, block, lds, s, args...);
+  }
+}
 
 inline int ilog2(long long n) {
   int l = 0;

@@ -914,21 +914,26 @@ int launch_march(MarchArgs A, hipStream_t s, const MarchAux* aux) {
     Ar.ntiles = (2 * A.tiles_x + 2 * (A.tiles_y - 2)) * ((A.n + zr - 1) / zr);
     const int gr = (Ar.ntiles + 7) / 8 * 8;
     if (A.part) Ar.part = A.part + gi;
+    LaunchTiming& lt = launch_timing();
+    const bool timed = lt.armed;
+    lt.armed = false;
+    if (timed) (void)hipEventRecord(lt.e0, s);
     (void)hipEventRecord(aux->fork, s);
     (void)hipStreamWaitEvent(aux->s2, aux->fork, 0);
     hipLaunchKernelGGL((k_march<T, W, UP, NORM, 2, BLK>), dim3(gr), dim3(kLanes * W), 0, aux->s2, Ar);
     hipLaunchKernelGGL((k_march<T, W, UP, NORM, 1, BLK>), dim3(gi), dim3(kLanes * W), 0, s, Ai);
     (void)hipEventRecord(aux->join, aux->s2);
     (void)hipStreamWaitEvent(s, aux->join, 0);
+    if (timed) (void)hipEventRecord(lt.e1, s);
     return gi + gr;
   }
   A.zc = march_zchunk(A.n, A.tiles_x * A.tiles_y, HZ);
   const int chunks = (A.n + A.zc - 1) / A.zc;
   A.ntiles = A.tiles_x * A.tiles_y * chunks;
   const int grid = (A.ntiles + 7) / 8 * 8;
-  if (per) hipLaunchKernelGGL((k_march<T, W, UP, NORM, 0, BLK>), dim3(grid), dim3(kLanes * W), 0, s, A);
-  else if (xyper) hipLaunchKernelGGL((k_march<T, W, UP, NORM, 1, BLK>), dim3(grid), dim3(kLanes * W), 0, s, A);
-  else hipLaunchKernelGGL((k_march<T, W, UP, NORM, 2, BLK>), dim3(grid), dim3(kLanes * W), 0, s, A);
+  if (per) launch_maybe_timed(k_march<T, W, UP, NORM, 0, BLK>, dim3(grid), dim3(kLanes * W), 0, s, A);
+  else if (xyper) launch_maybe_timed(k_march<T, W, UP, NORM, 1, BLK>, dim3(grid), dim3(kLanes * W), 0, s, A);
+  else launch_maybe_timed(k_march<T, W, UP, NORM, 2, BLK>, dim3(grid), dim3(kLanes * W), 0, s, A);
   return grid;
 }
 
@@ -948,9 +953,9 @@ void launch_march_fas(MarchArgs A, hipStream_t s) {
   A.zc = march_zchunk(A.n, A.tiles_x * A.tiles_y, 5);
   A.ntiles = A.tiles_x * A.tiles_y * ((A.n + A.zc - 1) / A.zc);
   const int grid = (A.ntiles + 7) / 8 * 8;
-  if (per) hipLaunchKernelGGL((k_march_fas<T, W, 0>), dim3(grid), dim3(kLanes * W), 0, s, A);
-  else if (xyper) hipLaunchKernelGGL((k_march_fas<T, W, 1>), dim3(grid), dim3(kLanes * W), 0, s, A);
-  else hipLaunchKernelGGL((k_march_fas<T, W, 2>), dim3(grid), dim3(kLanes * W), 0, s, A);
+  if (per) launch_maybe_timed(k_march_fas<T, W, 0>, dim3(grid), dim3(kLanes * W), 0, s, A);
+  else if (xyper) launch_maybe_timed(k_march_fas<T, W, 1>, dim3(grid), dim3(kLanes * W), 0, s, A);
+  else launch_maybe_timed(k_march_fas<T, W, 2>, dim3(grid), dim3(kLanes * W), 0, s, A);
 }
 
 template <typename T>

@@ -365,9 +365,9 @@ template <typename T, bool UP, bool NORM, bool BLK, bool FAS = false>
 void launch_leg(const TileArgs& A, hipStream_t s) {
   const dim3 g(regions(A.n)), b(kShapes[shape_of(A.n)].threads);
   switch (shape_of(A.n)) {
-    case 0: hipLaunchKernelGGL((k_tile_leg<T, UP, NORM, BLK, FAS, 0>), g, b, 0, s, A); break;
-    case 1: hipLaunchKernelGGL((k_tile_leg<T, UP, NORM, BLK, FAS, 1>), g, b, 0, s, A); break;
-    default: hipLaunchKernelGGL((k_tile_leg<T, UP, NORM, BLK, FAS, 2>), g, b, 0, s, A); break;
+    case 0: launch_maybe_timed(k_tile_leg<T, UP, NORM, BLK, FAS, 0>, g, b, 0, s, A); break;
+    case 1: launch_maybe_timed(k_tile_leg<T, UP, NORM, BLK, FAS, 1>, g, b, 0, s, A); break;
+    default: launch_maybe_timed(k_tile_leg<T, UP, NORM, BLK, FAS, 2>, g, b, 0, s, A); break;
   }
 }
 
