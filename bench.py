@@ -436,7 +436,6 @@ def batched_leg(steps: int, seed: int, n: int = 256, block_n: int = 16):
     for name, x, layout, prec in (("dense_fp64", rho, "dense", "fp64"), ("blocks_fp64", rho_b, "blocks", "fp64"),
                                   ("blocks_mixed", rho_b, "blocks", "mixed")):
         lat, cyc, inner = [], [], []
-        ctx.set_kernel_timing(name == "blocks_fp64")
         for it in range(steps + 1):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -462,6 +461,12 @@ def batched_leg(steps: int, seed: int, n: int = 256, block_n: int = 16):
             phi_d = mg.from_blocks(phi, n, block_n)
             rec["rel_diff_vs_dense"] = float(torch.linalg.norm(phi_d - phi_dense) / torch.linalg.norm(phi_dense))
         if name == "blocks_fp64":
+            # per-kernel times from one more solve with kernel timing on (the timed solves above
+            # run without it, as the dense one does: timing adds a few microseconds per pass)
+            ctx.set_kernel_timing(True)
+            mg.solve(x, 1.0 / n, "periodic", tol=1e-10, precision=prec, layout=layout, block_n=block_n, ctx=ctx)
+            torch.cuda.synchronize()
+            ctx.set_kernel_timing(False)
             rec["kernels"] = [{"kernel": k["name"], "launches": k["launches"],
                                "avg_launch_ms": k["total_ms"] / max(k["launches"], 1),
                                "achieved_GBs": k["bytes_per_launch"] * k["launches"] / (k["total_ms"] * 1e-3) / 1e9}
