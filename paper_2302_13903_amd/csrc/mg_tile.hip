@@ -12,8 +12,8 @@
 //        (Sec. 2.3.7).
 // Each workgroup owns a region (16 x 16 x 8 cells on 128^3, smaller below) and stages it in
 // LDS with a halo of 5 cells (four colour passes of radius 1 and the defect); colour pass s
-// updates the region plus a ring of 4 - s cells, so every pass sees its neighbours exactly as a global sweep would, and
-// only the region is written back.  The rings are recomputed by the neighbouring regions,
+// updates the region plus a ring of 4 - s cells, so every pass sees its neighbours exactly as
+// a global sweep would, and only the region is written back.  The rings are recomputed by the neighbouring regions,
 // never exchanged, so regions are independent.  The up leg first stages the coarse correction
 // under the tile (homogeneous ghosts: periodic wrap, or the boundary cell with the face's
 // sign) and adds its trilinear interpolant to every staged cell.  Boundary ghosts of the fine
