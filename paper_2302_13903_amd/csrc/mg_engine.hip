@@ -77,6 +77,12 @@ struct mg_ctx {
   double* scal = nullptr;      // device scalars: [0] sum rho, [1] sum f^2, [2] defect^2, [3] sum phi,
                                // [8..13] sum b^2 per face, [16..47] multipole scratch
   double* hscal = nullptr;     // pinned host mirror of scal
+  // the stopping test's squared norm as the device publishes it after each cycle (coherent
+  // pinned memory: [0] the value's bits, [1] the publishing launch's sequence number); pub_ok
+  // turns false if a publication ever fails to arrive (blocking copies from then on)
+  unsigned long long* hpub = nullptr;
+  unsigned long long pub_seq = 0;
+  bool pub_ok = true;
   // timing of the last solve
   hipEvent_t ev0 = nullptr, ev_setup = nullptr, ev_fmg = nullptr;
   std::vector<hipEvent_t> ev_cycle;
@@ -1039,6 +1045,7 @@ int mg_ctx_create(mg_ctx** out, int device, size_t hbm_budget) {
   if (hipMalloc((void**)&c->part, sizeof(double) * kMaxPartials * 32) != hipSuccess ||
       hipMalloc((void**)&c->scal, sizeof(double) * kScal) != hipSuccess ||
       hipHostMalloc((void**)&c->hscal, sizeof(double) * kScal, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->hpub, 2 * sizeof(unsigned long long), hipHostMallocCoherent) != hipSuccess ||
       hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev_setup) != hipSuccess ||
       hipEventCreate(&c->ev_fmg) != hipSuccess) {
     mg_ctx_destroy(c);
@@ -1076,6 +1083,7 @@ void mg_ctx_destroy(mg_ctx* c) {
   if (c->part) (void)hipFree(c->part);
   if (c->scal) (void)hipFree(c->scal);
   if (c->hscal) (void)hipHostFree(c->hscal);
+  if (c->hpub) (void)hipHostFree(c->hpub);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->aux.s2) (void)hipStreamDestroy(c->aux.s2);
   if (c->aux.fork) (void)hipEventDestroy(c->aux.fork);
@@ -1205,6 +1213,42 @@ struct SolveMem {
   double* scal = nullptr;
   bool noalloc = false;
 };
+
+// The squared defect norm *dnorm (device) of the cycle just queued on s, for the host's
+// stopping test (Sec. 2.3.7).  A one-lane kernel publishes it with a sequence number into
+// coherent pinned memory and the host spins on the number: waking from a stream
+// synchronisation costs tens of microseconds per cycle.  The spin polls the stream every 256
+// rounds, so a failed launch ends it with an error; if the stream has finished and the number
+// has not arrived, the value is read by a blocking copy and publishing is given up for good.
+int read_norm(mg_ctx* c, const double* dnorm, hipStream_t s, double* out) {
+  if (c->pub_ok) {
+    const unsigned long long want = ++c->pub_seq;
+    launch_publish(dnorm, c->hpub, want, s);
+    HIP_CHECK(c, hipGetLastError());
+    for (unsigned spin = 1;; ++spin) {
+      if (__atomic_load_n(c->hpub + 1, __ATOMIC_ACQUIRE) == want) {
+        *out = __builtin_bit_cast(double, __atomic_load_n(c->hpub, __ATOMIC_RELAXED));
+        return MG_OK;
+      }
+      if ((spin & 255u) == 0) {
+        const hipError_t q = hipStreamQuery(s);
+        if (q == hipErrorNotReady) continue;
+        HIP_CHECK(c, q);
+        if (__atomic_load_n(c->hpub + 1, __ATOMIC_ACQUIRE) == want) {
+          *out = __builtin_bit_cast(double, __atomic_load_n(c->hpub, __ATOMIC_RELAXED));
+          return MG_OK;
+        }
+        c->pub_ok = false;
+        break;
+      }
+      __builtin_ia32_pause();
+    }
+  }
+  HIP_CHECK(c, hipMemcpyAsync(c->hscal + 2, dnorm, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(c, hipStreamSynchronize(s));
+  *out = c->hscal[2];
+  return MG_OK;
+}
 
 int solve_impl(mg_ctx* c, const mg_params* p, const mg_bc* bc, const double* rho, double* phi, double* hist,
                int* n_hist, hipStream_t s, const Layout& y, const SolveMem& mem) {
@@ -1413,9 +1457,9 @@ int solve_impl(mg_ctx* c, const mg_params* p, const mg_bc* bc, const double* rho
         }
       }
       if (cyc_timed) HIP_CHECK(c, hipEventRecord(c->ev_cycle[cyc], s));
-      HIP_CHECK(c, hipMemcpyAsync(c->hscal + 2, scal + 2, sizeof(double), hipMemcpyDeviceToHost, s));
-      HIP_CHECK(c, hipStreamSynchronize(s));
-      const double rn = rel(c->hscal[2]);
+      double d2 = 0.0;
+      if (const int st = read_norm(c, scal + 2, s, &d2); st != MG_OK) return st;
+      const double rn = rel(d2);
       hist[nh++] = rn;
       ++done_cycles;
       if (mixed) {

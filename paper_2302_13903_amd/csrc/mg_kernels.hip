@@ -900,6 +900,20 @@ int reduce_blocks(size_t n3) {
   return (int)(b < 1 ? 1 : b);
 }
 
+// One device scalar copied into coherent pinned host memory (dst[0]), then the sequence number
+// `seq` stored beside it (dst[1]) with system-scope release, so that a host that sees the number
+// also sees the value.  Vector stores from one lane.
+__global__ void k_publish(const double* __restrict__ src, unsigned long long* dst, unsigned long long seq) {
+  if (threadIdx.x != 0) return;
+  __hip_atomic_store(dst, __builtin_bit_cast(unsigned long long, src[0]), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(dst + 1, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+void launch_publish(const double* src, unsigned long long* dst_host, unsigned long long seq, hipStream_t s) {
+  hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, src, dst_host, seq);
+}
+
 void launch_sum_partials(const double* part, int np, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBlock), 0, s, part, np, 1, out, 1);
 }
