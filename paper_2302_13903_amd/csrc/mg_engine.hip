@@ -1220,10 +1220,13 @@ struct SolveMem {
 // synchronisation costs tens of microseconds per cycle.  The spin polls the stream every 256
 // rounds, so a failed launch ends it with an error; if the stream has finished and the number
 // has not arrived, the value is read by a blocking copy and publishing is given up for good.
-int read_norm(mg_ctx* c, const double* dnorm, hipStream_t s, double* out) {
+// done != nullptr: the event that ends the cycle's timing, taken from the publishing kernel's
+// own dispatch (an event recorded between kernels would idle the device for microseconds; at
+// the publication it costs nothing the host's reply does not already).
+int read_norm(mg_ctx* c, const double* dnorm, hipStream_t s, double* out, hipEvent_t done) {
   if (c->pub_ok) {
     const unsigned long long want = ++c->pub_seq;
-    launch_publish(dnorm, c->hpub, want, s);
+    launch_publish(dnorm, c->hpub, want, s, done);
     HIP_CHECK(c, hipGetLastError());
     for (unsigned spin = 1;; ++spin) {
       if (__atomic_load_n(c->hpub + 1, __ATOMIC_ACQUIRE) == want) {
@@ -1244,6 +1247,7 @@ int read_norm(mg_ctx* c, const double* dnorm, hipStream_t s, double* out) {
       __builtin_ia32_pause();
     }
   }
+  if (done) HIP_CHECK(c, hipEventRecord(done, s));
   HIP_CHECK(c, hipMemcpyAsync(c->hscal + 2, dnorm, sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_CHECK(c, hipStreamSynchronize(s));
   *out = c->hscal[2];
@@ -1456,9 +1460,9 @@ int solve_impl(mg_ctx* c, const mg_params* p, const mg_bc* bc, const double* rho
           S.defect_norm(phi, f64L, H32.f[L], p->n, p->dx, phys[L], scal + 2);
         }
       }
-      if (cyc_timed) HIP_CHECK(c, hipEventRecord(c->ev_cycle[cyc], s));
       double d2 = 0.0;
-      if (const int st = read_norm(c, scal + 2, s, &d2); st != MG_OK) return st;
+      if (const int st = read_norm(c, scal + 2, s, &d2, cyc_timed ? c->ev_cycle[cyc] : nullptr); st != MG_OK)
+        return st;
       const double rn = rel(d2);
       hist[nh++] = rn;
       ++done_cycles;

@@ -910,8 +910,10 @@ __global__ void k_publish(const double* __restrict__ src, unsigned long long* ds
   __hip_atomic_store(dst + 1, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-void launch_publish(const double* src, unsigned long long* dst_host, unsigned long long seq, hipStream_t s) {
-  hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, src, dst_host, seq);
+void launch_publish(const double* src, unsigned long long* dst_host, unsigned long long seq, hipStream_t s,
+                    hipEvent_t done) {
+  if (done) hipExtLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, nullptr, done, 0u, src, dst_host, seq);
+  else hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, src, dst_host, seq);
 }
 
 void launch_sum_partials(const double* part, int np, double* out, hipStream_t s) {

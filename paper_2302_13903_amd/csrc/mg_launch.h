@@ -99,8 +99,10 @@ int reduce_blocks(size_t n3);
 // what: 0 = sum x, 1 = sum x^2, 2 = count of non-finite values; result in out[0] (device)
 void launch_sum(const double* x, size_t n3, int what, double* part, double* out, hipStream_t s);
 // out[0] = sum of part[0..np) in index order (second stage of a deterministic reduction)
-// Publish *src (device) to dst_host[0] and then seq to dst_host[1] (coherent pinned memory).
-void launch_publish(const double* src, unsigned long long* dst_host, unsigned long long seq, hipStream_t s);
+// Publish *src (device) to dst_host[0] and then seq to dst_host[1] (coherent pinned memory);
+// done != nullptr: that event takes the end of the publishing kernel (from its own dispatch).
+void launch_publish(const double* src, unsigned long long* dst_host, unsigned long long seq, hipStream_t s,
+                    hipEvent_t done);
 void launch_sum_partials(const double* part, int np, double* out, hipStream_t s);
 void launch_defect_norm(const double* u, const double* f, float* r32, int n, double h, const LevelBC& bc,
                         double* part, double* out, hipStream_t s);
