@@ -361,3 +361,50 @@ def test_mixed_two_sweep_passes_reach_fp64(mg, kinds):
     assert st == mg.MG_OK and hist[-1] <= 1e-11, (st, hist)
     assert len(hist) <= len(rh11) + 1, (hist, rh11)
     assert rel(phi.cpu().numpy(), ref) < 1e-10
+
+
+@pytest.mark.parametrize("n,kinds,layout,extra", [
+    (64, "periodic", "dense", {}),                      # region-tile legs
+    (128, "periodic", "dense", {}),                     # two-sweep passes
+    (128, [FIXED] * 6, "dense", {}),                    # split passes (interior and wall ring)
+    (128, [PERIODIC, PERIODIC, FIXED, FIXED, ZERO_GRADIENT, ZERO_GRADIENT], "dense", {}),
+    (128, "periodic", "blocks", {}),                    # MeshBlock layout
+    (128, "periodic", "dense", {"scheme": "fas"}),
+    (128, [FIXED] * 6, "dense", {"precision": "mixed"}),
+])
+def test_history_is_the_defect_rms_of_phi(mg, n, kinds, layout, extra):
+    """Each history entry the device reports (the norm it publishes to the host after a cycle)
+    is RMS(f - L phi)/RMS(f) of the phi it returns (Sec. 2.3.7), recomputed on the host with the
+    matrix-free ghost rules of oracle.exact: for k = 0..4 cycles after FMG, hist[k] of a k-cycle
+    run matches it to 1e-9 relative plus 1 % of the round-off floor (a gauge-free phi is shifted
+    to zero mean after the last cycle, which moves its residual by round-off), and every run's
+    history is a prefix of the next one's to the same bound."""
+    print(f"history pin n={n} kinds={kinds} layout={layout} {extra}", flush=True)
+    gauge_free = kinds == "periodic"
+    kk = [PERIODIC] * 6 if gauge_free else kinds
+    rho = wl.gaussian_clumps(n, 7, remove_mean=False)
+    rng = np.random.default_rng(2)
+    faces = [rng.standard_normal((n, n)) * 0.1 if k == FIXED else None for k in kk]
+    dfaces = None if gauge_free else [None if b is None else dev(b) for b in faces]
+    f = 4 * math.pi * rho
+    if gauge_free:
+        f = f - f.mean()
+    x = mg.to_blocks(dev(rho), 16) if layout == "blocks" else dev(rho)
+    ctx = mg.Context(0)
+    prev = None
+    for k in range(5):
+        cyc = {"max_cycles": 0} if k == 0 else {"fixed_cycles": k}
+        phi, hist, st = mg.solve(x, 1.0 / n, kinds, fixed_b=dfaces, layout=layout, block_n=16, ctx=ctx, **cyc,
+                                 **extra)
+        torch.cuda.synchronize()
+        assert st >= 0, (k, st, hist)
+        assert len(hist) == k + 1, (k, hist)
+        p = (mg.from_blocks(phi, n, 16) if layout == "blocks" else phi).cpu().numpy()
+        r = ex.rel_residual(p, f, 1.0 / n, kk, None if gauge_free else faces)
+        floor = residual_floor(p, rho, gauge_free)
+        assert hist[-1] > 1e3 * floor or k == 4, (k, hist, floor)
+        assert abs(hist[-1] - r) <= 1e-9 * r + 1e-2 * floor, (k, hist[-1], r, floor)
+        if prev is not None:
+            for a, b in zip(hist[:-1], prev):
+                assert abs(a - b) <= 1e-9 * b + 1e-2 * floor, (hist, prev)
+        prev = list(hist)
