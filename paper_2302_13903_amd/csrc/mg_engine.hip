@@ -88,8 +88,9 @@ struct mg_ctx {
   std::vector<hipEvent_t> ev_cycle;
   double setup_ms = 0, fmg_ms = 0;
   std::vector<double> cycle_ms;
-  // kernel timing of the finest-level smoothing kernels: events around each launch, then
-  // per kernel name the launch count, summed duration and algorithmic bytes per launch
+  // kernel timing of the finest-level smoothing kernels: an event pair per launch (from the
+  // kernel's own dispatch, or recorded around a split pass), then per kernel name the launch
+  // count, summed duration and algorithmic bytes per launch
   int ktiming = 0;
   std::vector<hipEvent_t> kev;
   std::vector<int> kev_id;
