@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -334,6 +335,72 @@ struct Solver {
   // vcycle)
   bool head_done = false;
 
+  // the first leg of the next top-level V-cycle has already been queued (down_ahead): the
+  // next top-level vcycle / vcycle_blk skips it
+  bool down_done = false;
+
+  // The down leg of dense level l of a V(2,2) cycle in one launch: the two-sweep pass
+  // (march) or the region-tile leg.  It reads u and f and writes only u2 and the coarse
+  // level's source and correction.  zin: u is zero and not read.
+  template <typename T>
+  void down_leg(Hier<T>& H, int l, const LevelBC& bc, bool march, bool zin, bool timed) {
+    const int n = 1 << l;
+    const double cellsT = (double)cells(l) * sizeof(T);
+    if (timed) kernel_begin(true);
+    if (march) {
+      march_down<T>(zin ? nullptr : H.u[l], H.u2[l], H.f[l], H.f[l - 1], H.u[l - 1], n, H.h[l], H.omega, bc, s, 0,
+                    aux_of());
+      // algorithmic bytes: u and f read, u written, coarse source and correction written
+      if (timed) kernel_end(march_name<T>(false, false, bc), 3 * cellsT + cellsT / 4);
+    } else {
+      tile_down<T>(H.u[l], H.u2[l], H.f[l], H.f[l - 1], H.u[l - 1], n, 0, 0, H.h[l], H.omega, bc, s);
+      if (timed) kernel_end(tile_name<T>(false, false), 3 * cellsT + cellsT / 4);
+    }
+  }
+  // The same for MeshBlock level l (big: the two-sweep pass across blocks).
+  template <typename T>
+  void blk_down_leg(Hier<T>& H, int l, const LevelBC& bc, bool big, bool timed) {
+    const int nl = 1 << l, Lm = l - Lb;
+    const double cellsT = (double)cells(l) * sizeof(T);
+    if (timed) kernel_begin(true);
+    if (big) march_down<T>(H.u[l], H.u2[l], H.f[l], H.f[l - 1], H.u[l - 1], nl, H.h[l], H.omega, bc, s, Lm, aux_of());
+    else tile_down<T>(H.u[l], H.u2[l], H.f[l], H.f[l - 1], H.u[l - 1], nl, Lm, Lb, H.h[l], H.omega, bc, s);
+    if (timed) kernel_end(big ? march_name<T>(false, false, bc, true) : tile_name<T>(false, false, true),
+                          3 * cellsT + cellsT / 4);
+  }
+
+  // Queues the next top-level V-cycle's first leg now, before the host has read this cycle's
+  // norm (the solve loop decides when): FP64 correction-scheme cycles whose finest-level down
+  // leg is one of the single launches above, under the same conditions vcycle / vcycle_blk
+  // apply.  If the solve stops after all, nothing that leg wrote is read.  Returns whether it
+  // queued the leg (then down_done is set).
+  bool down_ahead(Hier<double>& H, const LevelBC& bc) {
+    const int L = H.L;
+    const bool timed = timed_top && ktiming;
+    if (H.npre != 2 || H.npost != 2 || L == H.T_top) return false;
+    if (Lb < 0) {
+      if (march_on<double>(H, L, bc)) down_leg<double>(H, L, bc, true, false, timed);
+      else if ((1 << L) < fused_min_n64 && tile_on<double>(H, L)) down_leg<double>(H, L, bc, false, false, timed);
+      else return false;
+    } else {
+      if (L <= Lb) return false;
+      const bool big = c->blk_zmarch[0] != 0 && (1 << L) >= march_min<double>() && march_blk_on<double>(H, L, bc);
+      if (!big && !tile_on<double>(H, L)) return false;
+      blk_down_leg<double>(H, L, bc, big, timed);
+    }
+    down_done = true;
+    return true;
+  }
+  // The timing record of a leg queued ahead and then not used (the last two events).
+  void drop_ahead_timing() {
+    if (!(timed_top && ktiming) || c->kev.size() < 2 || c->kev_id.empty()) return;
+    for (int q = 0; q < 2; ++q) {
+      (void)hipEventDestroy(c->kev.back());
+      c->kev.pop_back();
+    }
+    c->kev_id.pop_back();
+  }
+
   // hook: the launcher that follows takes the launch-timing hook (one kernel timed by its own
   // dispatch, no marker packets around it); otherwise events are recorded around the launcher
   bool hooked = false;
@@ -510,10 +577,8 @@ struct Solver {
       // cleared), the coarse recursion, up (prolonged correction, two sweeps, and the norm of
       // the result when asked); the result lands back in u[l] after the two ping-pongs
       const bool zin = top_call && zero_start;
-      if (timed) kernel_begin(true);
-      march_down<T>(zin ? nullptr : H.u[l], H.u2[l], H.f[l], H.f[l - 1], H.u[l - 1], n, h, H.omega, bc, s, 0, aux_of());
-      // algorithmic bytes: u and f read, u written, coarse source and correction written
-      if (timed) kernel_end(march_name<T>(false, false, bc), 3 * cellsT + cellsT / 4);
+      if (top_call && down_done) down_done = false;   // queued ahead of the stopping test
+      else down_leg<T>(H, l, bc, true, zin, timed);
       vcycle(H, l - 1, H.hom, false, false);
       double* npart = want_norm && sizeof(T) == 8 ? part : nullptr;
       if (timed) kernel_begin(true);
@@ -529,9 +594,8 @@ struct Solver {
         launch_zero(H.u[l], cells(l) * sizeof(T), s);
         zero_start = false;
       }
-      if (timed) kernel_begin(true);
-      tile_down<T>(H.u[l], H.u2[l], H.f[l], H.f[l - 1], H.u[l - 1], n, 0, 0, h, H.omega, bc, s);
-      if (timed) kernel_end(tile_name<T>(false, false), 3 * cellsT + cellsT / 4);
+      if (top_call && down_done) down_done = false;   // queued ahead of the stopping test
+      else down_leg<T>(H, l, bc, false, false, timed);
       vcycle(H, l - 1, H.hom, false, false);
       double* npart = want_norm && sizeof(T) == 8 ? part : nullptr;
       if (timed) kernel_begin(true);
@@ -923,11 +987,8 @@ struct Solver {
       // passes on the large levels, region tiles below
       const bool timed = timed_top && l == H.L && ktiming;
       const double cellsT = (double)cells(l) * sizeof(T);
-      if (timed) kernel_begin(true);
-      if (big) march_down<T>(H.u[l], H.u2[l], H.f[l], H.f[l - 1], H.u[l - 1], nl, H.h[l], H.omega, bc, s, Lm, aux_of());
-      else tile_down<T>(H.u[l], H.u2[l], H.f[l], H.f[l - 1], H.u[l - 1], nl, Lm, Lb, H.h[l], H.omega, bc, s);
-      if (timed) kernel_end(big ? march_name<T>(false, false, bc, true) : tile_name<T>(false, false, true),
-                            3 * cellsT + cellsT / 4);
+      if (l == H.L && down_done) down_done = false;   // queued ahead of the stopping test
+      else blk_down_leg<T>(H, l, bc, big, timed);
       vcycle_blk(H, l - 1, H.hom);
       double* npart = want_norm && sizeof(T) == 8 ? part : nullptr;
       if (timed) kernel_begin(true);
@@ -1216,25 +1277,41 @@ struct SolveMem {
 };
 
 // The squared defect norm *dnorm (device) of the cycle just queued on s, for the host's
-// stopping test (Sec. 2.3.7).  A one-lane kernel publishes it with a sequence number into
-// coherent pinned memory and the host spins on the number: waking from a stream
-// synchronisation costs tens of microseconds per cycle.  The spin polls the stream every 256
-// rounds, so a failed launch ends it with an error; if the stream has finished and the number
-// has not arrived, the value is read by a blocking copy and publishing is given up for good.
-// done != nullptr: the event that ends the cycle's timing, taken from the publishing kernel's
-// own dispatch (an event recorded between kernels would idle the device for microseconds; at
-// the publication it costs nothing the host's reply does not already).
-int read_norm(mg_ctx* c, const double* dnorm, hipStream_t s, double* out, hipEvent_t done) {
+// stopping test (Sec. 2.3.7), in two steps so that more work can be queued between them.
+// post_norm: a one-lane kernel publishes the value with a sequence number (returned) into
+// coherent pinned memory; done != nullptr: that event, which ends the cycle's timing, is taken
+// from the publishing kernel's own dispatch (an event recorded between kernels would idle the
+// device for microseconds; at the publication it costs nothing the host's reply does not
+// already).  await_norm: the host spins on the number (waking from a stream synchronisation
+// costs tens of microseconds per cycle), polling the stream after 20 ms and every 20 ms from
+// then on, so that a failed launch ends the wait with an error; if the stream has finished and the number has not
+// arrived, the value is read by a blocking copy and publishing is given up for good (then
+// post_norm queues a copy and returns 0).
+unsigned long long post_norm(mg_ctx* c, const double* dnorm, hipStream_t s, hipEvent_t done) {
   if (c->pub_ok) {
     const unsigned long long want = ++c->pub_seq;
     launch_publish(dnorm, c->hpub, want, s, done);
-    HIP_CHECK(c, hipGetLastError());
+    return want;
+  }
+  if (done) (void)hipEventRecord(done, s);
+  (void)hipMemcpyAsync(c->hscal + 2, dnorm, sizeof(double), hipMemcpyDeviceToHost, s);
+  return 0;
+}
+
+int await_norm(mg_ctx* c, const double* dnorm, hipStream_t s, unsigned long long want, double* out) {
+  HIP_CHECK(c, hipGetLastError());
+  if (want != 0) {
+    // the stream is polled only once the wait has lasted kPollMs, then every kPollMs: a query
+    // queues a marker behind the last command, which idles the device for microseconds
+    constexpr double kPollMs = 20.0;
+    auto t_next = std::chrono::steady_clock::now() + std::chrono::duration<double, std::milli>(kPollMs);
     for (unsigned spin = 1;; ++spin) {
       if (__atomic_load_n(c->hpub + 1, __ATOMIC_ACQUIRE) == want) {
         *out = __builtin_bit_cast(double, __atomic_load_n(c->hpub, __ATOMIC_RELAXED));
         return MG_OK;
       }
-      if ((spin & 255u) == 0) {
+      if ((spin & 1023u) == 0 && std::chrono::steady_clock::now() >= t_next) {
+        t_next = std::chrono::steady_clock::now() + std::chrono::duration<double, std::milli>(kPollMs);
         const hipError_t q = hipStreamQuery(s);
         if (q == hipErrorNotReady) continue;
         HIP_CHECK(c, q);
@@ -1243,13 +1320,12 @@ int read_norm(mg_ctx* c, const double* dnorm, hipStream_t s, double* out, hipEve
           return MG_OK;
         }
         c->pub_ok = false;
+        HIP_CHECK(c, hipMemcpyAsync(c->hscal + 2, dnorm, sizeof(double), hipMemcpyDeviceToHost, s));
         break;
       }
       __builtin_ia32_pause();
     }
   }
-  if (done) HIP_CHECK(c, hipEventRecord(done, s));
-  HIP_CHECK(c, hipMemcpyAsync(c->hscal + 2, dnorm, sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_CHECK(c, hipStreamSynchronize(s));
   *out = c->hscal[2];
   return MG_OK;
@@ -1400,6 +1476,10 @@ int solve_impl(mg_ctx* c, const mg_params* p, const mg_bc* bc, const double* rho
   // update pass.  The count of the whole solve is kept for mg_last_inner
   c->last_inner = 0;
   double rho_est = 0.1;
+  // first legs queued ahead of the stopping test: FP64 correction-scheme cycles (not in head
+  // mode, whose head pass already overlaps the test); rho_seen = the last cycle's contraction
+  const bool ahead_ok = !mixed && !fas && !head_mode;
+  double rho_seen = 0.1;
   if (p->fixed_cycles > 0 || r > p->tol) {
     for (int cyc = 0; cyc < ncyc; ++cyc) {
       S.timed_top = true;
@@ -1461,10 +1541,17 @@ int solve_impl(mg_ctx* c, const mg_params* p, const mg_bc* bc, const double* rho
           S.defect_norm(phi, f64L, H32.f[L], p->n, p->dx, phys[L], scal + 2);
         }
       }
+      const unsigned long long want = post_norm(c, scal + 2, s, cyc_timed ? c->ev_cycle[cyc] : nullptr);
+      // the next cycle's first leg is queued before this cycle's norm is read when that leg
+      // reads u only and another cycle will run: always with a fixed cycle count, and when the
+      // tolerance is still at least 4x past what this cycle reaches at the contraction seen so
+      // far (had the solve stopped after all, that leg's results go unused)
+      if (ahead_ok && cyc + 1 < ncyc && (p->fixed_cycles > 0 || 0.25 * rho_seen * r > p->tol))
+        (void)S.down_ahead(H64, phys[L]);
       double d2 = 0.0;
-      if (const int st = read_norm(c, scal + 2, s, &d2, cyc_timed ? c->ev_cycle[cyc] : nullptr); st != MG_OK)
-        return st;
+      if (const int st = await_norm(c, scal + 2, s, want, &d2); st != MG_OK) return st;
       const double rn = rel(d2);
+      if (r > 0 && rn > 0) rho_seen = std::min(1.0, rn / r);
       hist[nh++] = rn;
       ++done_cycles;
       if (mixed) {
@@ -1479,6 +1566,10 @@ int solve_impl(mg_ctx* c, const mg_params* p, const mg_bc* bc, const double* rho
     }
   } else {
     status = MG_OK;
+  }
+  if (S.down_done) {   // a leg queued ahead of a test that then stopped the solve: unused
+    S.down_done = false;
+    S.drop_ahead_timing();
   }
   *n_hist = nh;
   if (phi_cur != phi) HIP_CHECK(c, hipMemcpyAsync(phi, phi_cur, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
