@@ -177,7 +177,10 @@ int mg_tuning_set(mg_ctx *ctx, const char *text);
  *   hist  host, capacity max(max_cycles, fixed_cycles) + 1: the relative residual after
  *         the FMG sweep (or of the initial guess) and after each V-cycle.
  *   n_hist host: number of entries written.
- * Synchronises `stream` once per cycle (the stopping test runs on the host). */
+ * Waits once per cycle for the stopping test, which runs on the host: the device publishes the
+ * cycle's norm to pinned host memory and the calling thread spins until it arrives (one CPU
+ * core stays busy during the solve); the next cycle's first pass may already be queued on
+ * `stream` by then.  Returns after synchronising `stream`. */
 int mg_solve(mg_ctx *ctx, const mg_params *p, const mg_bc *bc, const double *rho, double *phi,
              double *hist, int *n_hist, void *stream);
 
