@@ -1362,15 +1362,9 @@ int solve_impl(mg_ctx* c, const mg_params* p, const mg_bc* bc, const double* rho
   // ---- source (eq. poisson, f = 4 pi G rho; mean removed when gauge-free, Sec. 2.3.6)
   double* f64L = reinterpret_cast<double*>(ws + y.f64L);
   float* f32L = mixed ? reinterpret_cast<float*>(ws + y.f32[L]) : nullptr;
-  double shift = 0.0;
+  // (gauge-free: the source kernel reads the sum of rho from scal[0] and shifts by the mean)
   launch_sum(rho, n3, 0, part, scal + 0, s);
-  if (gauge_free) {
-    // the shift needs the mean on the host; this is the one extra synchronisation of set-up
-    HIP_CHECK(c, hipMemcpyAsync(c->hscal, scal, sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_CHECK(c, hipStreamSynchronize(s));
-    shift = -p->four_pi_g * (c->hscal[0] / (double)n3);
-  }
-  launch_source(rho, f64L, f32L, n3, p->four_pi_g, shift, part, scal + 1, s);
+  launch_source(rho, f64L, f32L, n3, p->four_pi_g, gauge_free ? scal + 0 : nullptr, part, scal + 1, s);
 
   LevelBC phys[16], hom;
   setup_faces(ws, part, scal, y, p, bc, rho, s, phys, &hom);

@@ -957,13 +957,16 @@ void launch_defect_norm(const double* u, const double* f, float* r32, int n, dou
   hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBlock), 0, s, part, nb, 1, out, 1);
 }
 
-// f = a * rho + c (the source 4 pi G rho, mean-shifted when gauge-free), in FP64, plus the
+// f = a * rho + c (the source 4 pi G rho, mean-shifted when gauge-free: c = -a * mean(rho),
+// read from the device so that the host need not wait for the sum), in FP64, plus the
 // FP32 copy when f32 != nullptr, and one partial sum of f^2 per block (fixed grid and tree,
 // so the sum is reproducible).
 __global__ void __launch_bounds__(kBlock) k_source(const double* __restrict__ rho, double* __restrict__ f,
-                                                    float* __restrict__ f32, size_t n3, double a, double c,
-                                                    double* __restrict__ part) {
+                                                    float* __restrict__ f32, size_t n3, double a,
+                                                    const double* __restrict__ rho_sum, double* __restrict__ part) {
   __shared__ double red[kBlock / 64];
+  // gauge-free: c = -a * mean(rho), from the sum the previous launch left in device memory
+  const double c = rho_sum ? -a * (rho_sum[0] / (double)n3) : 0.0;
   double acc = 0.0;
   for (size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x; t < n3; t += (size_t)gridDim.x * kBlock) {
     const double v = a * rho[t] + c;
@@ -975,10 +978,10 @@ __global__ void __launch_bounds__(kBlock) k_source(const double* __restrict__ rh
   if (threadIdx.x == 0) part[blockIdx.x] = r;
 }
 
-void launch_source(const double* rho, double* f, float* f32, size_t n3, double a, double c, double* part,
-                   double* sumsq, hipStream_t s) {
+void launch_source(const double* rho, double* f, float* f32, size_t n3, double a, const double* rho_sum,
+                   double* part, double* sumsq, hipStream_t s) {
   const int nb = reduce_blocks(n3);
-  hipLaunchKernelGGL(k_source, dim3(nb), dim3(kBlock), 0, s, rho, f, f32, n3, a, c, part);
+  hipLaunchKernelGGL(k_source, dim3(nb), dim3(kBlock), 0, s, rho, f, f32, n3, a, rho_sum, part);
   hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBlock), 0, s, part, nb, 1, sumsq, 1);
 }
 

@@ -88,9 +88,10 @@ void launch_fas_restrict(const double* u, const double* f, double* fc, double* p
 void launch_fas_source(const double* pbar, double* f, int n, double h, const LevelBC& bc, hipStream_t s);
 void launch_fas_correction(double* u, const double* pbar, size_t n3, hipStream_t s);
 
-// f = a rho + c (and its FP32 copy when f32 != nullptr); sumsq[0] = sum of f^2 (device)
-void launch_source(const double* rho, double* f, float* f32, size_t n3, double a, double c, double* part,
-                   double* sumsq, hipStream_t s);
+// f = a rho + c (and its FP32 copy when f32 != nullptr); sumsq[0] = sum of f^2 (device).
+// c = -a * rho_sum[0] / n3 when rho_sum (device) is given (the gauge-free source), else 0.
+void launch_source(const double* rho, double* f, float* f32, size_t n3, double a, const double* rho_sum,
+                   double* part, double* sumsq, hipStream_t s);
 void launch_sub_mean(double* u, size_t n3, const double* sum_dev, hipStream_t s);
 void launch_f32_to_f64(const float* a, double* b, size_t n3, hipStream_t s);
 void launch_add_f32(double* phi, const float* e, size_t n3, hipStream_t s);
